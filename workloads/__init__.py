@@ -1,0 +1,210 @@
+"""Seeded synthetic workloads for the implicit-Euler PD step and its adjoint.
+
+This module holds scene descriptions and seeded random draws only: voxel
+masks, material fields, boundary-node lists, actuation sequences, loss
+vectors and request traces.  It performs none of the method's arithmetic
+(no shape functions, no masses, no projections, no solves), so the CPU
+oracle and the HIP path can both read it without sharing any of the method.
+
+The paper's meshes (cantilever, quadruped, contact scenes; Sec. Evaluation
+and Applications) are not available, so voxel boxes of the stated sizes and
+shapes stand in for them.  Every array is drawn from
+``numpy.random.default_rng(seed)``.
+
+Conventions
+-----------
+* A scene is a set of cubic voxels with integer corner coordinates
+  ``(i, j, k)``; a node exists wherever a voxel corner exists.  Public node
+  order is lexicographic over present grid nodes with ``i`` fastest, then
+  ``j``, then ``k``.
+* The rest position of grid node ``(i, j, k)`` is ``origin + dx * (i, j, k)``;
+  ``z`` is up and gravity points along ``-z`` (the paper puts gravity along
+  the negative z axis in its supplemental experiment details).
+* Loss vectors are node-major (x0, y0, z0, x1, ...) over all nodes.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, asdict
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Scene",
+    "box_cells",
+    "cantilever",
+    "legged_body",
+    "dropped_block",
+    "served_requests",
+    "loss_vector",
+    "actuation_sequence",
+    "present_nodes",
+    "config",
+    "CONFIG_NAMES",
+]
+
+
+@dataclass
+class Scene:
+    """One simulated body and its physical constants (SI units)."""
+
+    name: str
+    cells: np.ndarray                 # [E, 3] int32 voxel indices
+    youngs: np.ndarray                # [E] float64, Pa
+    fixed_nodes: np.ndarray           # [F, 3] int32 grid coordinates held at rest
+    dx: float = 0.01                  # voxel edge, m
+    rho: float = 1e3                  # density, kg/m^3
+    nu: float = 0.45                  # Poisson ratio
+    h: float = 0.01                   # time step, s
+    gravity: tuple = (0.0, 0.0, -9.81)
+    origin: tuple = (0.0, 0.0, 0.0)
+    contact_k: float = 0.0            # ground penalty stiffness, N/m (0 = off)
+    friction_mu: float = 0.0          # Coulomb coefficient of the explicit friction
+    friction_eps: float = 1e-3        # velocity regulariser of the friction, m/s
+    muscle_k: float = 0.0             # fibre stiffness per unit volume, Pa (0 = off)
+    fiber: tuple = (1.0, 0.0, 0.0)    # unit fibre direction
+    steps: int = 10
+    loss_seed: int = 0
+    act_seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_elements(self) -> int:
+        return int(self.cells.shape[0])
+
+    def physics(self) -> dict:
+        d = asdict(self)
+        for key in ("cells", "youngs", "fixed_nodes", "extra", "name"):
+            d.pop(key)
+        return d
+
+
+def box_cells(nx: int, ny: int, nz: int) -> np.ndarray:
+    """All voxels of an nx x ny x nz box, in lexicographic order (i fastest)."""
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.int32)
+
+
+def present_nodes(cells: np.ndarray) -> np.ndarray:
+    """Grid coordinates of all voxel corners, unique, lexicographic (i fastest).
+
+    This is set bookkeeping on integer coordinates (which corners exist), not
+    part of the discretisation.
+    """
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    corners = np.array([[a & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], dtype=np.int64)
+    allc = (cells[:, None, :] + corners[None, :, :]).reshape(-1, 3)
+    uniq = np.unique(allc[:, ::-1], axis=0)
+    return uniq[:, ::-1].astype(np.int32)
+
+
+def _face_nodes(cells: np.ndarray, axis: int, value: int) -> np.ndarray:
+    nodes = present_nodes(cells)
+    return nodes[nodes[:, axis] == value]
+
+
+def cantilever(nx: int, ny: int, nz: int, *, youngs="const", steps: int = 10,
+               seed: int = 0, name: Optional[str] = None) -> Scene:
+    """Hex beam along +x with the x = 0 face held (the paper's Cantilever layout).
+
+    ``youngs="const"`` gives E = 1e6 Pa everywhere; ``"loguniform"`` draws
+    log10(E_e) ~ U(5, 7) per element from ``default_rng(seed)``.
+    """
+    cells = box_cells(nx, ny, nz)
+    E = cells.shape[0]
+    if youngs == "const":
+        ym = np.full(E, 1e6)
+    elif youngs == "loguniform":
+        ym = 10.0 ** np.random.default_rng(seed).uniform(5.0, 7.0, size=E)
+    else:
+        ym = np.asarray(youngs, dtype=np.float64).reshape(E)
+    return Scene(name=name or f"cantilever_{nx}x{ny}x{nz}", cells=cells, youngs=ym,
+                 fixed_nodes=_face_nodes(cells, 0, 0), steps=steps)
+
+
+def legged_body(nx: int = 20, ny: int = 10, nz: int = 6, *, steps: int = 200,
+                leg_height: int = 3) -> Scene:
+    """Quadruped-like voxel body: a slab on four corner legs, feet on z = 0.
+
+    A cell (i, j, k) is present iff k >= leg_height, or it lies in one of the
+    four corner leg columns (i < 4 or i >= nx - 4) and (j < 3 or j >= ny - 3).
+    Muscles run along +x in every element; the feet touch a penalty ground.
+    """
+    allc = box_cells(nx, ny, nz)
+    i, j, k = allc[:, 0], allc[:, 1], allc[:, 2]
+    leg = ((i < 4) | (i >= nx - 4)) & ((j < 3) | (j >= ny - 3))
+    cells = allc[(k >= leg_height) | leg]
+    E = cells.shape[0]
+    nu = 0.45
+    mu = 1e6 / (2.0 * (1.0 + nu))
+    return Scene(name=f"legged_{nx}x{ny}x{nz}", cells=cells, youngs=np.full(E, 1e6),
+                 fixed_nodes=np.zeros((0, 3), np.int32), h=5e-3, steps=steps,
+                 contact_k=1e4, friction_mu=0.5, muscle_k=2.0 * mu)
+
+
+def dropped_block(nx: int = 64, ny: int = 32, nz: int = 32, *, steps: int = 200,
+                  drop: float = 0.02) -> Scene:
+    """Free hex block released ``drop`` metres above a frictionless penalty ground."""
+    cells = box_cells(nx, ny, nz)
+    E = cells.shape[0]
+    return Scene(name=f"block_{nx}x{ny}x{nz}", cells=cells, youngs=np.full(E, 1e6),
+                 fixed_nodes=np.zeros((0, 3), np.int32), origin=(0.0, 0.0, drop),
+                 steps=steps, contact_k=1e4)
+
+
+def loss_vector(n_nodes: int, seed: int = 0) -> np.ndarray:
+    """Weights of the loss dot(c, x_T): N(0, 1) draws, node-major over all nodes."""
+    return np.random.default_rng(seed).standard_normal(3 * n_nodes)
+
+
+def actuation_sequence(steps: int, n_elements: int, seed: int = 0) -> np.ndarray:
+    """Per-step, per-element muscle actuation u[t, e] ~ U[0, 1]."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, size=(steps, n_elements))
+
+
+def served_requests(n_requests: int = 64, lo: int = 4, hi: int = 24, steps: int = 50,
+                    rate: float = 10.0, seed: int = 0) -> list:
+    """Request trace for the rollout server: cube cantilevers of random size.
+
+    Sizes n ~ U{lo..hi} (cubes of n^3 cells), Poisson arrivals with the given
+    rate (requests per second; ``inf`` puts every arrival at t = 0).  The loss
+    seed of request r is r.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(lo, hi + 1, size=n_requests)
+    if np.isinf(rate):
+        arrivals = np.zeros(n_requests)
+    else:
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+        arrivals -= arrivals[0]
+    reqs = []
+    for r in range(n_requests):
+        n = int(sizes[r])
+        sc = cantilever(n, n, n, steps=steps, name=f"req{r}_{n}^3")
+        sc.loss_seed = r
+        reqs.append({"id": r, "scene": sc, "arrival": float(arrivals[r])})
+    return reqs
+
+
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+
+
+def config(name: str) -> Scene:
+    """The five benchmark scenes.
+
+    c1: 4x4x4 cantilever, E = 1e6, 10 steps.
+    c2: 16x8x8 cantilever, log-uniform E in [1e5, 1e7], 100 steps.
+    c3: legged 20x10x6 body, muscles, penalty ground + friction, h = 5 ms, 200 steps.
+    c5: 64x32x32 block dropped 2 cm onto a penalty ground, 200 steps.
+    (c4 is a request trace, see ``served_requests``.)
+    """
+    if name == "c1":
+        return cantilever(4, 4, 4, steps=10, name="c1_cantilever_4x4x4")
+    if name == "c2":
+        return cantilever(16, 8, 8, youngs="loguniform", steps=100, seed=0,
+                          name="c2_cantilever_16x8x8")
+    if name == "c3":
+        return legged_body()
+    if name == "c5":
+        return dropped_block()
+    raise KeyError(name)
