@@ -1,0 +1,202 @@
+/*
+ * diffpd.h -- C ABI of the MI355X (gfx950) implementation of the implicit-Euler
+ * Projective Dynamics time step on hexahedral voxel meshes and its adjoint
+ * (Du et al., "DiffPD: Differentiable Projective Dynamics").
+ *
+ * Every entry point returns a dpd_status; nothing throws across the ABI.
+ * Arguments are plain host or device pointers and sizes.  A "stream" argument
+ * is a hipStream_t passed as void* (NULL = the default stream).
+ *
+ * Layouts
+ *   - State vectors (x, v, gradients) are device arrays of doubles in SoA
+ *     layout [3][N]: x[c * N + n] is coordinate c of node n.
+ *   - Node order ("public order") is lexicographic over present grid nodes,
+ *     i fastest, then j, then k.  Node (i, j, k) rests at
+ *     origin + dx * (i, j, k).
+ *   - Element e is the voxel cells_ijk[3e .. 3e+2]; per-element arrays
+ *     (Young's moduli, actuation, their gradients) follow that order.
+ *
+ * Ownership
+ *   - The mesh handle owns all internal device memory (connectivity, the
+ *     factor, workspaces, per-quadrature-point caches).
+ *   - The caller owns every state and gradient buffer; they must stay valid
+ *     until the work enqueued on the stream completes.
+ *   - One handle is used by at most one stream at a time (its workspaces are
+ *     shared by all calls on it).  Distinct handles are independent.
+ *
+ * Errors
+ *   - Negative codes are hard errors: outputs are undefined; the handle stays
+ *     usable unless the code is DPD_EHIP.  dpd_last_error() gives a message.
+ *   - DPD_NOT_CONVERGED is soft: outputs hold the last iterate; see stats.
+ */
+#ifndef DIFFPD_H
+#define DIFFPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dpd_mesh dpd_mesh;
+
+typedef enum {
+  DPD_OK = 0,
+  DPD_NOT_CONVERGED = 1,   /* iteration cap reached; outputs = last iterate          */
+  DPD_EINVAL = -1,         /* invalid argument or mesh description                     */
+  DPD_ENOTSPD = -2,        /* non-positive pivot while factorizing A                   */
+  DPD_ENOMEM = -3,         /* device or host allocation failed                         */
+  DPD_EHIP = -4,           /* a HIP runtime call failed                                 */
+  DPD_ESTATE = -5,         /* call not valid in the handle's state (e.g. no factor)    */
+  DPD_ENONFINITE = -6,     /* NaN or Inf met in a residual                             */
+  DPD_ECURVATURE = -7      /* adjoint CG met non-positive curvature and no fallback    */
+} dpd_status;
+
+/* Precision of the iteration (fwd/bwd local steps and triangular sweeps).   */
+enum { DPD_FP64 = 0, DPD_MIXED = 1 };
+/* Adjoint solver.                                                          */
+enum { DPD_BWD_FIXED_POINT = 0, DPD_BWD_PCG = 1 };
+
+typedef struct {
+  /* physics (SI units) */
+  double dx;               /* voxel edge length, m                               */
+  double rho;              /* density, kg/m^3                                    */
+  double nu;               /* Poisson ratio, 0 <= nu < 0.5                       */
+  double h;                /* time step, s                                       */
+  double gravity[3];       /* m/s^2                                              */
+  double origin[3];        /* rest position of grid node (0,0,0), m              */
+  double contact_k;        /* ground penalty stiffness per node, N/m; 0 = off    */
+  double friction_mu;      /* explicit Coulomb friction coefficient; 0 = off     */
+  double friction_eps;     /* friction velocity regulariser, m/s                 */
+  double muscle_k;         /* fibre stiffness per volume, Pa; 0 = no muscles     */
+  double fiber[3];         /* unit fibre direction, same for every element       */
+  /* forward iteration (Alg. 1) */
+  int32_t fwd_max_iter;    /* maximum number of global solves per step           */
+  int32_t fwd_fixed_iters; /* 1: perform exactly fwd_max_iter solves              */
+  double fwd_rel_tol;      /* stop when |grad g| <= tol |grad g(x^0)|            */
+  double fwd_abs_tol_rel;  /* ... or |grad g| <= this * |M y / h^2| (free DoFs)   */
+  /* backward iteration (Alg. 2 or CG) */
+  int32_t bwd_max_iter;
+  int32_t bwd_solver;      /* DPD_BWD_FIXED_POINT or DPD_BWD_PCG                   */
+  double bwd_rel_tol;      /* stop when |xbar - H z| <= tol |xbar|               */
+  int32_t precision;       /* DPD_FP64 or DPD_MIXED                                */
+  int32_t check_every;     /* host convergence check period (iterations), >= 1   */
+} dpd_options;
+
+typedef struct {
+  int32_t fwd_iters;       /* global solves performed in the last forward step   */
+  int32_t bwd_iters;       /* adjoint iterations in the last backward step       */
+  int32_t converged;       /* 1 if the last call met its tolerance                */
+  int32_t fallbacks;       /* CG -> fixed-point fallbacks in the last backward    */
+  int32_t inverted_qps;    /* quadrature points with det F <= 0 (last local pass) */
+  int32_t reserved;
+  double fwd_rel_res;      /* final |grad g| / |grad g(x^0)|                      */
+  double bwd_rel_res;      /* final |xbar - H z| / |xbar|                          */
+  double ms_total;         /* wall time of the call when stats were requested     */
+} dpd_stats;
+
+typedef struct {
+  int64_t n_nodes, n_elements, n_free, n_fixed, n_contact;
+  int64_t n_supernodes, n_levels;
+  int64_t factor_nnz;      /* stored entries of the factor panels (packed count)  */
+  int64_t factor_bytes;    /* device bytes of the FP64 panels                     */
+  int64_t device_bytes;    /* all device memory owned by the handle               */
+} dpd_mesh_info;
+
+/* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
+ * no contact, friction or muscles, fwd 100 iterations / 1e-10 / 1e-12,
+ * bwd CG 5000 iterations / 1e-10, FP64, check_every 8. */
+dpd_status dpd_default_options(dpd_options* opt);
+
+/* Build a mesh from voxels (Sec. Background: FEM nodes, lumped mass; supp.
+ * Sec. Energy Definitions: energies integrated at Gauss points).
+ *   cells_ijk   host, [n_cells][3] int32 voxel indices, unique
+ *   youngs      host, [n_cells] Young's moduli in Pa (> 0)
+ *   fixed_ijk   host, [n_fixed][3] grid nodes held at rest (Dirichlet), or NULL
+ *   opt         host options (copied)
+ *   out         receives the handle; NULL on failure
+ * Assembles A = M/h^2 + sum_c w_c G_c^T G_c (eq:pd_global) over free nodes,
+ * orders it by geometric nested dissection and performs the symbolic
+ * analysis.  No numeric factorization yet (dpd_factorize).  DPD_EINVAL on bad
+ * input (duplicate voxels, fixed nodes not on the mesh, nu out of range, ...). */
+dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
+                           const int32_t* fixed_ijk, int64_t n_fixed,
+                           const dpd_options* opt, dpd_mesh** out);
+
+void dpd_destroy_mesh(dpd_mesh* mesh);
+
+dpd_status dpd_get_info(const dpd_mesh* mesh, dpd_mesh_info* info);
+
+/* Host copies: node grid coordinates [N][3] int32; rest positions [3][N];
+ * contact-candidate node indices [n_contact] int32 (nodes of minimal rest
+ * height when contact_k > 0). */
+dpd_status dpd_node_ijk(const dpd_mesh* mesh, int32_t* ijk_host);
+dpd_status dpd_rest_positions(const dpd_mesh* mesh, double* X_host);
+dpd_status dpd_contact_nodes(const dpd_mesh* mesh, int32_t* nodes_host);
+
+/* Replace the options used by later step calls (physics fields must not
+ * change: dx, rho, nu, h, contact, muscles are fixed at creation; changing
+ * them returns DPD_EINVAL).  Iteration controls and precision may change. */
+dpd_status dpd_set_options(dpd_mesh* mesh, const dpd_options* opt);
+
+/* Replace the per-element Young's moduli (device or host pointer as flagged,
+ * [n_elements] Pa).  Marks the factor stale: the next step needs
+ * dpd_factorize again (DPD_ESTATE otherwise). */
+dpd_status dpd_set_youngs(dpd_mesh* mesh, const double* youngs, int32_t on_device, void* stream);
+
+/* Numeric Cholesky factorization of A, computed once per material
+ * (Sec. Background: the factorization of the constant matrix A can be
+ * precomputed).  Builds the FP64 panels (and FP32 copies when precision is
+ * DPD_MIXED) and uploads them.  Synchronizes the stream.  DPD_ENOTSPD on a
+ * non-positive pivot. */
+dpd_status dpd_factorize(dpd_mesh* mesh, void* stream);
+
+/* One implicit-Euler step (eq:time_integration) by Alg. 1:
+ *   y = x + h v + h^2 M^{-1} (M g + f_friction(x, v)); x^0 = y (Dirichlet nodes
+ *   at rest); repeat local projections and a global solve with A.
+ *   x, v        device [3][N], read-only
+ *   act         device [n_elements] muscle actuation (1 = rest length), or NULL
+ *   x_next      device [3][N], overwritten; must not alias x or v
+ *   v_next      device [3][N], overwritten: (x_next - x) / h
+ *   stats       host or NULL; non-NULL synchronizes the stream
+ * Asynchronous except for the periodic convergence checks (every
+ * opt.check_every iterations the host waits for a 4-byte flag). */
+dpd_status dpd_forward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
+                            const double* act, double* x_next, double* v_next, dpd_stats* stats);
+
+/* Adjoint of one step (eq:adjoint, eq:chain_rule; Alg. 2 or its CG
+ * acceleration).  Given dL/dx_next and dL/dv_next, returns dL/dx, dL/dv and
+ * parameter gradients.
+ *   x, v, act, x_next   as passed to / returned by dpd_forward_step
+ *   gx_next, gv_next    device [3][N]
+ *   gx, gv              device [3][N], overwritten; must not alias the inputs
+ *   g_youngs            device [n_elements], ACCUMULATED (+=), or NULL
+ *   g_act               device [n_elements], overwritten, or NULL
+ *   stats               host or NULL */
+dpd_status dpd_backward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
+                             const double* act, const double* x_next, const double* gx_next,
+                             const double* gv_next, double* gx, double* gv, double* g_youngs,
+                             double* g_act, dpd_stats* stats);
+
+/* Building blocks, exposed for kernel-level tests and custom solvers.  All
+ * device [3][N] arrays; fixed-node rows of outputs are zero.
+ *   dpd_apply_inverse:  out = A^{-1} b on free nodes (eq:pd_global's matrix)
+ *   dpd_gradient:       out = grad g(x) = A x - b(x) for the given y (eq:energy_grad)
+ *   dpd_hessian_apply:  out = (A - dA(x)) p (eq:matrix_split)
+ *   dpd_rotations:      R_out device [9][8 n_elements]: closest rotation at each
+ *                       Gauss point q = 8e + (qx + 2 qy + 4 qz), row-major 3x3 */
+dpd_status dpd_apply_inverse(dpd_mesh* mesh, void* stream, int32_t precision, const double* b,
+                             double* out);
+dpd_status dpd_gradient(dpd_mesh* mesh, void* stream, const double* x, const double* y,
+                        const double* act, double* out);
+dpd_status dpd_hessian_apply(dpd_mesh* mesh, void* stream, const double* x, const double* act,
+                             const double* p, double* out);
+dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* R_out);
+
+const char* dpd_status_string(dpd_status s);
+const char* dpd_last_error(const dpd_mesh* mesh);   /* thread-local if mesh is NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFPD_H */

@@ -25,6 +25,7 @@ body, static equilibrium, and agreement with Newton on small meshes.
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse.linalg as spla
 
 
 def _initial_guess(model, y):
@@ -75,7 +76,9 @@ def pd_step(model, x_i, v_i, act=None, **kw):
 
 
 def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=60):
-    """Minimise g(x) for fixed y with dense Newton steps and backtracking.
+    """Minimise g(x) for fixed y with Newton steps and backtracking.
+
+    Dense solves up to 1500 free DoFs, sparse LU beyond.
 
     Stops when |grad g| <= tol_rel |M y / h^2| or when the gradient norm has
     stopped decreasing for three iterations (round-off floor reached).
@@ -97,8 +100,11 @@ def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=60):
             stall += 1
             if stall >= 3:
                 break
-        H = model.hessian(x, act)[free][:, free].toarray()
-        dx = -np.linalg.solve(H, gr)
+        H = model.hessian(x, act)[free][:, free]
+        if H.shape[0] <= 1500:
+            dx = -np.linalg.solve(H.toarray(), gr)
+        else:
+            dx = -spla.spsolve(H.tocsc(), gr)
         g0 = model.g(x, y, act)
         ng0 = np.linalg.norm(gr)
         t = 1.0

@@ -1,0 +1,114 @@
+"""ctypes binding of libdiffpd.so (the C ABI declared in include/diffpd.h).
+
+Argument marshalling only: every step of the simulation runs inside the
+library's HIP kernels.  The library is built in-tree by ``_build.py``; if it
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiffpd.so")
+
+DPD_OK, DPD_NOT_CONVERGED = 0, 1
+DPD_FP64, DPD_MIXED = 0, 1
+DPD_BWD_FIXED_POINT, DPD_BWD_PCG = 0, 1
+
+STATUS_NAMES = {0: "DPD_OK", 1: "DPD_NOT_CONVERGED", -1: "DPD_EINVAL", -2: "DPD_ENOTSPD",
+                -3: "DPD_ENOMEM", -4: "DPD_EHIP", -5: "DPD_ESTATE", -6: "DPD_ENONFINITE",
+                -7: "DPD_ECURVATURE"}
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("dx", C.c_double), ("rho", C.c_double), ("nu", C.c_double), ("h", C.c_double),
+        ("gravity", C.c_double * 3), ("origin", C.c_double * 3),
+        ("contact_k", C.c_double), ("friction_mu", C.c_double), ("friction_eps", C.c_double),
+        ("muscle_k", C.c_double), ("fiber", C.c_double * 3),
+        ("fwd_max_iter", C.c_int32), ("fwd_fixed_iters", C.c_int32),
+        ("fwd_rel_tol", C.c_double), ("fwd_abs_tol_rel", C.c_double),
+        ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
+        ("precision", C.c_int32), ("check_every", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("fwd_iters", C.c_int32), ("bwd_iters", C.c_int32), ("converged", C.c_int32),
+        ("fallbacks", C.c_int32), ("inverted_qps", C.c_int32), ("reserved", C.c_int32),
+        ("fwd_rel_res", C.c_double), ("bwd_rel_res", C.c_double), ("ms_total", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
+        "factor_nnz", "factor_bytes", "device_bytes")]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+
+# name -> (restype, argtypes); the CPU tests check this list against the header
+PROTOTYPES = {
+    "dpd_default_options": (C.c_int, [C.POINTER(Options)]),
+    "dpd_create_mesh": (C.c_int, [_I32, C.c_int64, _D, _I32, C.c_int64, C.POINTER(Options),
+                                  C.POINTER(_P)]),
+    "dpd_destroy_mesh": (None, [_P]),
+    "dpd_get_info": (C.c_int, [_P, C.POINTER(MeshInfo)]),
+    "dpd_node_ijk": (C.c_int, [_P, _I32]),
+    "dpd_rest_positions": (C.c_int, [_P, _D]),
+    "dpd_contact_nodes": (C.c_int, [_P, _I32]),
+    "dpd_set_options": (C.c_int, [_P, C.POINTER(Options)]),
+    "dpd_set_youngs": (C.c_int, [_P, _P, C.c_int32, _P]),
+    "dpd_factorize": (C.c_int, [_P, _P]),
+    "dpd_forward_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.POINTER(Stats)]),
+    "dpd_backward_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    C.POINTER(Stats)]),
+    "dpd_apply_inverse": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "dpd_gradient": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dpd_hessian_apply": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dpd_rotations": (C.c_int, [_P, _P, _P, _P]),
+    "dpd_status_string": (C.c_char_p, [C.c_int]),
+    "dpd_last_error": (C.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libdiffpd.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DiffPDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code: int, handle=None) -> int:
+    """Raise on hard errors (negative codes); return soft codes."""
+    if code < 0:
+        lib = load()
+        msg = lib.dpd_last_error(handle)
+        raise DiffPDError(code, msg.decode() if msg else "")
+    return code

@@ -1,0 +1,633 @@
+// C ABI of the diffpd library: mesh handles, factorization and the step
+// drivers for the forward PD iteration (Alg. 1) and its adjoint (Alg. 2 and
+// the conjugate-gradient acceleration).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/diffpd.h"
+#include "device.hpp"
+#include "internal.hpp"
+
+using namespace dpd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int32_t kLeafMax = 64;
+constexpr int32_t kSepMax = 1024;
+constexpr int64_t kLdsBudget = 48 * 1024;
+
+}  // namespace
+
+struct dpd_mesh {
+  dpd_options opt{};
+  HostMesh hm;
+  Csr A;
+  Symbolic S;
+  LevelPlan plan;
+  DevMesh dm{};
+  DevSolve ds{};
+  bool factored = false;
+  bool have_fp32 = false;
+  std::string err;
+  int64_t device_bytes = 0;
+  std::vector<void*> allocs;
+  // device buffers
+  SweepTask* d_fwd = nullptr;
+  SweepTask* d_bwd = nullptr;
+  double* w_e = nullptr;
+  double* panel64 = nullptr;
+  float* panel32 = nullptr;
+  double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
+  double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr;
+  IterState* st = nullptr;
+  IterState* h_st = nullptr;  // pinned host mirror
+};
+
+namespace {
+
+dpd_status fail(dpd_mesh* m, dpd_status code, const std::string& msg) {
+  if (m) m->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHECK(m, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((m), DPD_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+dpd_status dev_alloc(dpd_mesh* m, T** out, int64_t count) {
+  *out = nullptr;
+  if (count <= 0) count = 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, (size_t)count * sizeof(T)) != hipSuccess)
+    return fail(m, DPD_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  m->allocs.push_back(p);
+  m->device_bytes += count * (int64_t)sizeof(T);
+  *out = (T*)p;
+  return DPD_OK;
+}
+
+template <typename T>
+dpd_status upload(dpd_mesh* m, T** out, const std::vector<T>& v) {
+  dpd_status s = dev_alloc(m, out, (int64_t)v.size());
+  if (s != DPD_OK) return s;
+  if (!v.empty()) HIPCHECK(m, hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DPD_OK;
+}
+
+void free_dev(dpd_mesh* m, void* p) {
+  if (!p) return;
+  auto it = std::find(m->allocs.begin(), m->allocs.end(), p);
+  if (it != m->allocs.end()) m->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// A^{-1} b on free nodes, out[perm] = alpha x (+ out when accumulate).
+void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, double alpha,
+           int accumulate, const IterState* st) {
+  const LevelPlan& P = m->plan;
+  const int32_t L = m->S.n_levels;
+  for (int32_t l = 0; l < L; ++l) {
+    const int n = P.fwd_off[l + 1] - P.fwd_off[l];
+    if (n) launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
+  }
+  for (int32_t l = L - 1; l >= 0; --l) {
+    const int n = P.bwd_off[l + 1] - P.bwd_off[l];
+    const bool lds = (int64_t)3 * P.bwd_rows[l] * (int64_t)sizeof(double) <= kLdsBudget;
+    if (n)
+      launch_sweep_bwd(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], lds, fp32, out, m->dm.N,
+                       alpha, accumulate, st);
+  }
+}
+
+dpd_status read_state(dpd_mesh* m, hipStream_t s) {
+  HIPCHECK(m, hipMemcpyAsync(m->h_st, m->st, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  return DPD_OK;
+}
+
+void fill_devmesh(dpd_mesh* m) {
+  const dpd_options& o = m->opt;
+  DevMesh& d = m->dm;
+  d.N = (int32_t)m->hm.n_nodes;
+  d.E = (int32_t)m->hm.n_elems;
+  d.nf = (int32_t)m->hm.n_free;
+  d.h = o.h;
+  d.dx = o.dx;
+  d.nu = o.nu;
+  d.Vq = o.dx * o.dx * o.dx / 8.0;
+  for (int k = 0; k < 3; ++k) {
+    d.g[k] = o.gravity[k];
+    d.fiber[k] = o.fiber[k];
+  }
+  d.contact_k = o.contact_k;
+  d.friction_mu = o.friction_mu;
+  d.friction_eps = o.friction_eps;
+  d.muscle_k = o.muscle_k;
+}
+
+std::vector<double> corotated_weights(const HostMesh& hm, const dpd_options& o) {
+  std::vector<double> w(hm.n_elems);
+  const double Vq = o.dx * o.dx * o.dx / 8.0;
+  for (int64_t e = 0; e < hm.n_elems; ++e) w[e] = 2.0 * hm.youngs[e] / (2.0 * (1.0 + o.nu)) * Vq;
+  return w;
+}
+
+dpd_status check_ready(dpd_mesh* m) {
+  if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
+  if (!m->factored) return fail(m, DPD_ESTATE, "mesh is not factorized (call dpd_factorize)");
+  return DPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dpd_status dpd_default_options(dpd_options* o) {
+  if (!o) return fail(nullptr, DPD_EINVAL, "null options");
+  std::memset(o, 0, sizeof(*o));
+  o->dx = 0.01;
+  o->rho = 1e3;
+  o->nu = 0.45;
+  o->h = 0.01;
+  o->gravity[2] = -9.81;
+  o->friction_eps = 1e-3;
+  o->fiber[0] = 1.0;
+  o->fwd_max_iter = 100;
+  o->fwd_fixed_iters = 0;
+  o->fwd_rel_tol = 1e-10;
+  o->fwd_abs_tol_rel = 1e-12;
+  o->bwd_max_iter = 5000;
+  o->bwd_solver = DPD_BWD_PCG;
+  o->bwd_rel_tol = 1e-10;
+  o->precision = DPD_FP64;
+  o->check_every = 8;
+  return DPD_OK;
+}
+
+dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
+                           const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options* opt,
+                           dpd_mesh** out) {
+  if (!out) return fail(nullptr, DPD_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!opt) return fail(nullptr, DPD_EINVAL, "null options");
+  if (n_fixed > 0 && !fixed_ijk) return fail(nullptr, DPD_EINVAL, "null fixed-node list");
+  dpd_mesh* m = new (std::nothrow) dpd_mesh();
+  if (!m) return fail(nullptr, DPD_ENOMEM, "host allocation failed");
+  m->opt = *opt;
+  if (m->opt.check_every < 1) m->opt.check_every = 1;
+  std::string e = build_mesh(cells_ijk, n_cells, youngs, fixed_ijk, n_fixed, m->opt, m->hm);
+  if (!e.empty()) {
+    delete m;
+    return fail(nullptr, DPD_EINVAL, e);
+  }
+  assemble_As(m->hm, m->opt, m->A);
+  analyse(m->hm, m->A, kLeafMax, kSepMax, m->S);
+  build_plan(m->S, m->plan);
+  fill_devmesh(m);
+
+  const HostMesh& hm = m->hm;
+  const int64_t N = hm.n_nodes, E = hm.n_elems, nf = hm.n_free;
+  std::vector<int32_t> conn_soa(8 * E);
+  for (int64_t el = 0; el < E; ++el)
+    for (int a = 0; a < 8; ++a) conn_soa[a * E + el] = hm.conn[8 * el + a];
+  std::vector<int32_t> perm_pub(nf);
+  for (int64_t i = 0; i < nf; ++i) perm_pub[i] = hm.free_nodes[m->S.perm[i]];
+  std::vector<int32_t> col0, ncols, nrows;
+  std::vector<int64_t> roff, poff, uoff;
+  for (auto& s : m->S.sn) {
+    col0.push_back(s.col0);
+    ncols.push_back(s.ncols);
+    nrows.push_back(s.nrows);
+    roff.push_back(s.rows_off);
+    poff.push_back(s.panel_off);
+    uoff.push_back(s.u_off);
+  }
+  dpd_status st = DPD_OK;
+  double *X, *mass;
+  int32_t *conn, *inc, *pp, *c0, *nc, *nr, *rows, *cptr, *cidx;
+  int64_t *ro, *po, *uo;
+  uint8_t *fixed, *contact;
+#define UP(ptr, vec)                       \
+  if ((st = upload(m, &ptr, vec)) != DPD_OK) { \
+    dpd_destroy_mesh(m);                   \
+    return st;                             \
+  }
+  UP(X, hm.X);
+  UP(mass, hm.mass);
+  UP(conn, conn_soa);
+  UP(inc, hm.node_inc);
+  UP(fixed, hm.fixed);
+  UP(contact, hm.is_contact);
+  UP(m->w_e, corotated_weights(hm, m->opt));
+  UP(pp, perm_pub);
+  UP(c0, col0);
+  UP(nc, ncols);
+  UP(nr, nrows);
+  UP(ro, roff);
+  UP(po, poff);
+  UP(uo, uoff);
+  UP(rows, m->S.rows);
+  UP(cptr, m->S.cptr);
+  UP(cidx, m->S.cidx);
+  UP(m->d_fwd, m->plan.fwd);
+  UP(m->d_bwd, m->plan.bwd);
+#undef UP
+  DevMesh& d = m->dm;
+  d.X = X;
+  d.mass = mass;
+  d.conn = conn;
+  d.node_inc = inc;
+  d.fixed = fixed;
+  d.contact = contact;
+  d.w_e = m->w_e;
+  DevSolve& ds = m->ds;
+  ds.nf = (int32_t)nf;
+  ds.perm_pub = pp;
+  ds.sn_col0 = c0;
+  ds.sn_ncols = nc;
+  ds.sn_nrows = nr;
+  ds.sn_rows_off = ro;
+  ds.sn_panel_off = po;
+  ds.sn_u_off = uo;
+  ds.rows = rows;
+  ds.cptr = cptr;
+  ds.cidx = cidx;
+#define AL(ptr, count)                                   \
+  if ((st = dev_alloc(m, &ptr, (count))) != DPD_OK) {    \
+    dpd_destroy_mesh(m);                                 \
+    return st;                                           \
+  }
+  AL(ds.y_int, 3 * nf);
+  AL(ds.x_int, 3 * nf);
+  AL(ds.U, 3 * m->S.u_size);
+  AL(m->fe, 3 * 8 * E);
+  AL(m->r, 3 * N);
+  AL(m->y, 3 * N);
+  AL(m->partials, std::max<int64_t>(N, 8 * E) / kBlock + 16);
+  AL(m->cache, (int64_t)kAdjCacheRows * 8 * E);
+  AL(m->z, 3 * N);
+  AL(m->p, 3 * N);
+  AL(m->q, 3 * N);
+  AL(m->s, 3 * N);
+  AL(m->xbar, 3 * N);
+  AL(m->st, 1);
+#undef AL
+  if (hipHostMalloc((void**)&m->h_st, sizeof(IterState), hipHostMallocDefault) != hipSuccess) {
+    dpd_destroy_mesh(m);
+    return fail(nullptr, DPD_ENOMEM, "pinned host allocation failed");
+  }
+  std::memset(m->h_st, 0, sizeof(IterState));
+  // zero the scratch vectors whose fixed-node rows are read
+  for (double* v : {m->z, m->p, m->q, m->s, m->xbar, m->r})
+    if (hipMemset(v, 0, 3 * N * sizeof(double)) != hipSuccess) {
+      dpd_destroy_mesh(m);
+      return fail(nullptr, DPD_EHIP, "hipMemset failed");
+    }
+  if (hipMemset(m->st, 0, sizeof(IterState)) != hipSuccess) {
+    dpd_destroy_mesh(m);
+    return fail(nullptr, DPD_EHIP, "hipMemset failed");
+  }
+  *out = m;
+  return DPD_OK;
+}
+
+void dpd_destroy_mesh(dpd_mesh* m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : m->allocs) (void)hipFree(p);
+  if (m->h_st) (void)hipHostFree(m->h_st);
+  delete m;
+}
+
+dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
+  if (!m || !info) return fail(nullptr, DPD_EINVAL, "null argument");
+  info->n_nodes = m->hm.n_nodes;
+  info->n_elements = m->hm.n_elems;
+  info->n_free = m->hm.n_free;
+  info->n_fixed = m->hm.n_nodes - m->hm.n_free;
+  info->n_contact = (int64_t)m->hm.contact.size();
+  info->n_supernodes = (int64_t)m->S.sn.size();
+  info->n_levels = m->S.n_levels;
+  info->factor_nnz = m->S.packed_nnz;
+  info->factor_bytes = m->S.panel_size * (int64_t)sizeof(double);
+  info->device_bytes = m->device_bytes;
+  return DPD_OK;
+}
+
+dpd_status dpd_node_ijk(const dpd_mesh* m, int32_t* ijk) {
+  if (!m || !ijk) return fail(nullptr, DPD_EINVAL, "null argument");
+  std::memcpy(ijk, m->hm.node_ijk.data(), m->hm.node_ijk.size() * sizeof(int32_t));
+  return DPD_OK;
+}
+
+dpd_status dpd_rest_positions(const dpd_mesh* m, double* X) {
+  if (!m || !X) return fail(nullptr, DPD_EINVAL, "null argument");
+  std::memcpy(X, m->hm.X.data(), m->hm.X.size() * sizeof(double));
+  return DPD_OK;
+}
+
+dpd_status dpd_contact_nodes(const dpd_mesh* m, int32_t* nodes) {
+  if (!m || (!nodes && !m->hm.contact.empty())) return fail(nullptr, DPD_EINVAL, "null argument");
+  if (!m->hm.contact.empty())
+    std::memcpy(nodes, m->hm.contact.data(), m->hm.contact.size() * sizeof(int32_t));
+  return DPD_OK;
+}
+
+dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
+  if (!m || !o) return fail(nullptr, DPD_EINVAL, "null argument");
+  const dpd_options& c = m->opt;
+  bool same = c.dx == o->dx && c.rho == o->rho && c.nu == o->nu && c.h == o->h &&
+              c.contact_k == o->contact_k && c.muscle_k == o->muscle_k &&
+              c.friction_mu == o->friction_mu && c.friction_eps == o->friction_eps;
+  for (int k = 0; k < 3; ++k)
+    same = same && c.gravity[k] == o->gravity[k] && c.origin[k] == o->origin[k] && c.fiber[k] == o->fiber[k];
+  if (!same) return fail(m, DPD_EINVAL, "physics options are fixed at mesh creation");
+  const bool need32 = o->precision == DPD_MIXED && !m->have_fp32;
+  m->opt = *o;
+  if (m->opt.check_every < 1) m->opt.check_every = 1;
+  if (need32 && m->factored) {
+    if (dev_alloc(m, &m->panel32, m->S.panel_size) != DPD_OK) return DPD_ENOMEM;
+    std::vector<double> tmp(m->S.panel_size);
+    HIPCHECK(m, hipMemcpy(tmp.data(), m->panel64, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<float> f(tmp.begin(), tmp.end());
+    HIPCHECK(m, hipMemcpy(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    m->ds.panel32 = m->panel32;
+    m->have_fp32 = true;
+  }
+  return DPD_OK;
+}
+
+dpd_status dpd_set_youngs(dpd_mesh* m, const double* youngs, int32_t on_device, void* stream) {
+  if (!m || !youngs) return fail(nullptr, DPD_EINVAL, "null argument");
+  std::vector<double> ym(m->hm.n_elems);
+  if (on_device) {
+    HIPCHECK(m, hipMemcpyAsync(ym.data(), youngs, ym.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               (hipStream_t)stream));
+    HIPCHECK(m, hipStreamSynchronize((hipStream_t)stream));
+  } else {
+    std::memcpy(ym.data(), youngs, ym.size() * sizeof(double));
+  }
+  for (double v : ym)
+    if (!(v > 0) || !std::isfinite(v)) return fail(m, DPD_EINVAL, "Young's moduli must be positive");
+  m->hm.youngs = ym;
+  std::vector<double> w = corotated_weights(m->hm, m->opt);
+  HIPCHECK(m, hipMemcpy(m->w_e, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  assemble_As(m->hm, m->opt, m->A);
+  m->factored = false;
+  return DPD_OK;
+}
+
+dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
+  if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
+  std::vector<double> panels;
+  std::string e;
+  if (!factor_panels(m->S, m->A, panels, e)) return fail(m, DPD_ENOTSPD, e);
+  hipStream_t s = (hipStream_t)stream;
+  if (!m->panel64) {
+    dpd_status st = dev_alloc(m, &m->panel64, m->S.panel_size);
+    if (st != DPD_OK) return st;
+  }
+  HIPCHECK(m, hipMemcpyAsync(m->panel64, panels.data(), panels.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+  m->ds.panel64 = m->panel64;
+  if (m->opt.precision == DPD_MIXED || m->have_fp32) {
+    if (!m->panel32) {
+      dpd_status st = dev_alloc(m, &m->panel32, m->S.panel_size);
+      if (st != DPD_OK) return st;
+    }
+    std::vector<float> f(panels.begin(), panels.end());
+    HIPCHECK(m, hipMemcpyAsync(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+    m->ds.panel32 = m->panel32;
+    m->have_fp32 = true;
+  }
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->factored = true;
+  return DPD_OK;
+}
+
+dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const double* v,
+                            const double* act, double* xn, double* vn, dpd_stats* stats) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!x || !v || !xn || !vn) return fail(m, DPD_EINVAL, "null state pointer");
+  if (xn == x || xn == v || vn == x || vn == v || xn == vn)
+    return fail(m, DPD_EINVAL, "outputs must not alias inputs");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const dpd_options& o = m->opt;
+  const bool fp32 = o.precision == DPD_MIXED;
+  if (fp32 && !m->have_fp32) return fail(m, DPD_ESTATE, "mixed precision needs FP32 panels (refactorize)");
+  const int max_it = std::max(0, o.fwd_max_iter);
+  launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol);
+  launch_prologue(m->dm, s, x, v, m->y, xn, m->st, m->partials, o.fwd_abs_tol_rel);
+  for (int k = 0;; ++k) {
+    launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, k, max_it,
+                         o.fwd_fixed_iters);
+    if (k >= max_it) break;
+    solve(m, s, fp32, m->r, xn, -1.0, 1, m->st);
+    if (!o.fwd_fixed_iters && (k + 1) % o.check_every == 0) {
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (m->h_st->done) break;
+    }
+  }
+  launch_velocity(m->dm, s, x, xn, vn);
+  HIPCHECK(m, hipGetLastError());
+  if ((rc = read_state(m, s)) != DPD_OK) return rc;
+  const IterState& h = *m->h_st;
+  if (stats) {
+    stats->fwd_iters = h.iter;
+    stats->converged = h.converged;
+    stats->inverted_qps = h.inverted;
+    stats->fwd_rel_res = h.r0sq > 0 ? std::sqrt(h.rsq / h.r0sq) : 0.0;
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (h.nonfinite) return fail(m, DPD_ENONFINITE, "non-finite residual in the forward iteration");
+  if (!o.fwd_fixed_iters && !h.converged) return DPD_NOT_CONVERGED;
+  return DPD_OK;
+}
+
+namespace {
+
+// Alg. 2 in correction form: z <- z - A^{-1}((A - dA) z - xbar), from the current z.
+dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, int max_it) {
+  dpd_status rc;
+  const dpd_options& o = m->opt;
+  for (int k = 0;; ++k) {
+    launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
+    launch_node_hvp(m->dm, s, m->z, m->fe, xn, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
+    if (k >= max_it) break;
+    solve(m, s, fp32, m->r, m->z, -1.0, 1, m->st);
+    if ((k + 1) % o.check_every == 0) {
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (m->h_st->done) break;
+    }
+  }
+  return DPD_OK;
+}
+
+// Conjugate gradients on (A - dA) z = xbar preconditioned by A^{-1}.
+dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, int max_it) {
+  dpd_status rc;
+  const dpd_options& o = m->opt;
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  launch_fill(s, n3, m->z, 0.0);
+  launch_lincomb(s, n3, m->r, 1.0, m->xbar, 0.0, nullptr);
+  launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
+  solve(m, s, fp32, m->r, m->s, 1.0, 0, nullptr);
+  launch_dot(m->dm, s, m->r, m->s, m->st, m->partials, 1);
+  launch_lincomb(s, n3, m->p, 1.0, m->s, 0.0, nullptr);
+  for (int k = 1; k <= max_it; ++k) {
+    launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, m->st);
+    launch_node_hvp(m->dm, s, m->p, m->fe, xn, nullptr, m->q, m->st, m->partials, 2, k, max_it);
+    launch_cg_update(m->dm, s, m->z, m->r, m->p, m->q, m->st, m->partials, k, max_it);
+    solve(m, s, fp32, m->r, m->s, 1.0, 0, m->st);
+    launch_dot(m->dm, s, m->r, m->s, m->st, m->partials, 2);
+    launch_cg_direction(m->dm, s, m->p, m->s, m->st);
+    if (k % o.check_every == 0) {
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (m->h_st->done) break;
+    }
+  }
+  return DPD_OK;
+}
+
+}  // namespace
+
+dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const double* v,
+                             const double* act, const double* xn, const double* gx_next,
+                             const double* gv_next, double* gx, double* gv, double* g_youngs,
+                             double* g_act, dpd_stats* stats) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!x || !v || !xn || !gx_next || !gv_next || !gx || !gv)
+    return fail(m, DPD_EINVAL, "null state pointer");
+  if (gx == gx_next || gx == gv_next || gv == gx_next || gv == gv_next || gx == gv)
+    return fail(m, DPD_EINVAL, "outputs must not alias inputs");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const dpd_options& o = m->opt;
+  const bool fp32 = o.precision == DPD_MIXED;
+  if (fp32 && !m->have_fp32) return fail(m, DPD_ESTATE, "mixed precision needs FP32 panels (refactorize)");
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  const int max_it = std::max(0, o.bwd_max_iter);
+  launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol);
+  // xbar = dL/dx_{i+1} + dL/dv_{i+1} / h  (v_{i+1} = (x_{i+1} - x_i)/h)
+  launch_lincomb(s, n3, m->xbar, 1.0, gx_next, 1.0 / o.h, gv_next);
+  launch_zero_fixed(m->dm, s, m->xbar);
+  launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
+  int fallbacks = 0;
+  if (o.bwd_solver == DPD_BWD_PCG) {
+    if ((rc = conjugate_gradient(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+    if ((rc = read_state(m, s)) != DPD_OK) return rc;
+    if (m->h_st->curvature) {
+      // the paper's safeguard when the quasi-Newton step is not a descent:
+      // continue with the plain fixed-point iteration from the current z
+      fallbacks = 1;
+      launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol);
+      launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
+      if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+    }
+  } else {
+    launch_fill(s, n3, m->z, 0.0);
+    launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
+    if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+  }
+  launch_adj_epilogue(m->dm, s, x, v, m->z, gv_next, gx, gv);
+  if (g_youngs || g_act) launch_grad_params(m->dm, s, xn, m->z, m->cache, g_youngs, g_act);
+  HIPCHECK(m, hipGetLastError());
+  if ((rc = read_state(m, s)) != DPD_OK) return rc;
+  const IterState& h = *m->h_st;
+  if (stats) {
+    stats->bwd_iters = h.iter;
+    stats->converged = h.converged;
+    stats->fallbacks = fallbacks;
+    stats->inverted_qps = h.inverted;
+    stats->bwd_rel_res = h.nb2 > 0 ? std::sqrt(h.rsq / h.nb2) : 0.0;
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (h.nonfinite) return fail(m, DPD_ENONFINITE, "non-finite residual in the adjoint iteration");
+  if (h.curvature) return fail(m, DPD_ECURVATURE, "non-positive curvature in the adjoint iteration");
+  if (!h.converged) return DPD_NOT_CONVERGED;
+  return DPD_OK;
+}
+
+dpd_status dpd_apply_inverse(dpd_mesh* m, void* stream, int32_t precision, const double* b, double* out) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!b || !out || b == out) return fail(m, DPD_EINVAL, "bad vector arguments");
+  const bool fp32 = precision == DPD_MIXED;
+  if (fp32 && !m->have_fp32) return fail(m, DPD_ESTATE, "no FP32 panels");
+  hipStream_t s = (hipStream_t)stream;
+  solve(m, s, fp32, b, out, 1.0, 0, nullptr);
+  launch_zero_fixed(m->dm, s, out);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+dpd_status dpd_gradient(dpd_mesh* m, void* stream, const double* x, const double* y, const double* act,
+                        double* out) {
+  if (!m || !x || !y || !out) return fail(m, DPD_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  launch_reset(s, m->st, 0.0);
+  launch_elem_forces(m->dm, s, x, act, m->fe, nullptr, nullptr);
+  launch_node_residual(m->dm, s, x, y, m->fe, out, m->st, m->partials, 0, 0, 1);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+dpd_status dpd_hessian_apply(dpd_mesh* m, void* stream, const double* x, const double* act,
+                             const double* p, double* out) {
+  if (!m || !x || !p || !out) return fail(m, DPD_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  launch_adj_cache(m->dm, s, x, act, m->cache, nullptr);
+  launch_elem_hvp(m->dm, s, p, m->cache, m->fe, nullptr);
+  launch_node_hvp(m->dm, s, p, m->fe, x, nullptr, out, nullptr, nullptr, 0, 0, 0);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_out) {
+  if (!m || !x || !R_out) return fail(m, DPD_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  launch_elem_forces(m->dm, s, x, nullptr, m->fe, R_out, nullptr);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+const char* dpd_status_string(dpd_status s) {
+  switch (s) {
+    case DPD_OK: return "ok";
+    case DPD_NOT_CONVERGED: return "not converged";
+    case DPD_EINVAL: return "invalid argument";
+    case DPD_ENOTSPD: return "matrix not positive definite";
+    case DPD_ENOMEM: return "out of memory";
+    case DPD_EHIP: return "HIP runtime error";
+    case DPD_ESTATE: return "invalid state";
+    case DPD_ENONFINITE: return "non-finite value";
+    case DPD_ECURVATURE: return "non-positive curvature";
+  }
+  return "unknown status";
+}
+
+const char* dpd_last_error(const dpd_mesh* m) {
+  if (m) return m->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

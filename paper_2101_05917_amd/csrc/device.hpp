@@ -1,0 +1,100 @@
+// Device-side data of one mesh and the kernel launchers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace dpd {
+
+// Scalars the iteration kernels exchange without host round trips.  One per
+// handle; reductions finalize into it with a last-block-done pattern.
+struct IterState {
+  double r0sq, rsq, atolsq, tolsq;   // forward / fixed-point residual norms
+  double nb2;                        // |xbar|^2 (adjoint)
+  double rs, pq, alpha, beta;        // conjugate-gradient scalars
+  double acc;                        // scratch accumulator
+  int32_t iter, done, converged, nonfinite, curvature, inverted;
+  uint32_t counter;                  // last-block-done ticket
+  int32_t pad;
+};
+
+struct DevSolve {
+  int32_t nf;                 // free nodes
+  const int32_t* perm_pub;    // [nf] internal index -> public node id
+  const int32_t* sn_col0;
+  const int32_t* sn_ncols;
+  const int32_t* sn_nrows;
+  const int64_t* sn_rows_off;
+  const int64_t* sn_panel_off;
+  const int64_t* sn_u_off;
+  const int32_t* rows;        // concatenated R_s (internal)
+  const int32_t* cptr;        // [nf + 1]
+  const int32_t* cidx;        // positions into U
+  const double* panel64;
+  const float* panel32;
+  double* y_int;              // [3][nf]
+  double* x_int;              // [3][nf]
+  double* U;                  // [u_size][3]
+};
+
+struct DevMesh {
+  int32_t N, E, nf;
+  double h, dx, nu, Vq;
+  double g[3];
+  double contact_k, friction_mu, friction_eps;
+  double muscle_k, fiber[3];
+  const double* X;            // [3][N]
+  const double* mass;         // [N]
+  const int32_t* conn;        // [8][E]
+  const int32_t* node_inc;    // [8][N], 8e + a or -1
+  const uint8_t* fixed;       // [N]
+  const uint8_t* contact;     // [N]
+  const double* w_e;          // [E] corotated weight per Gauss point, 2 mu_e V_q
+};
+
+constexpr int kElemsPerBlock = kBlock / 8;
+
+}  // namespace dpd
+
+namespace dpd {
+// kernel launchers (kernels.hip)
+void launch_lincomb(hipStream_t s, int64_t n, double* out, double a, const double* x, double b,
+                    const double* y);
+void launch_fill(hipStream_t s, int64_t n, double* out, double v);
+void launch_reset(hipStream_t s, IterState* st, double tolsq);
+void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
+                     double* xn, IterState* st, double* partials, double abs_tol_rel);
+void launch_elem_forces(const DevMesh& M, hipStream_t s, const double* x, const double* act,
+                        double* fe, double* R_out, IterState* st);
+void launch_node_residual(const DevMesh& M, hipStream_t s, const double* x, const double* y,
+                          const double* fe, double* r, IterState* st, double* partials, int k,
+                          int max_iter, int fixed_iters);
+void launch_velocity(const DevMesh& M, hipStream_t s, const double* x, const double* xn, double* vn);
+void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v);
+void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                      int lds_cols, bool fp32, const double* b, int N, const IterState* st);
+void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                      int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
+                      int accumulate, const IterState* st);
+void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
+                      double* cache, IterState* st);
+void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
+                     double* fe, const IterState* st);
+void launch_node_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* fe,
+                     const double* xk, const double* rhs, double* out, IterState* st,
+                     double* partials, int mode, int k, int max_iter);
+void launch_dot(const DevMesh& M, hipStream_t s, const double* a, const double* b, IterState* st,
+                double* partials, int what);
+void launch_cg_update(const DevMesh& M, hipStream_t s, double* z, double* r, const double* p,
+                      const double* q, IterState* st, double* partials, int k, int max_iter);
+void launch_cg_direction(const DevMesh& M, hipStream_t s, double* p, const double* sv,
+                         const IterState* st);
+void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
+                         const double* z, const double* gv_next, double* gx, double* gv);
+void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
+                        const double* cache, double* g_youngs, double* g_act);
+constexpr int kAdjCacheRows = 19;
+}  // namespace dpd

@@ -1,0 +1,354 @@
+// Ordering, symbolic analysis and numeric factorization of the scalar node
+// matrix A_s, and construction of the panels the GPU triangular sweeps read.
+//
+// The paper factorizes the constant matrix A once and back-substitutes in
+// every global step of the forward (Alg. 1) and backward (Alg. 2) iterations
+// (Sec. Background, Projective Dynamics; Sec. Differentiable Projective
+// Dynamics).  Here:
+//   * nested dissection on the voxel grid (a grid plane separates the two
+//     halves because hex neighbours differ by at most one in each index);
+//   * one supernode per dissection leaf and per separator (split into chunks
+//     of at most sep_max columns), ordered children before parents;
+//   * multifrontal Cholesky with dense fronts;
+//   * per supernode s the panel [inv(L_ss); -L_Rs inv(L_ss)], so that both
+//     sweeps become dense matrix-vector products with no intra-block
+//     dependency chain:
+//        forward   y_s = inv(L_ss) b~_s,   b_R -= (L_Rs inv(L_ss)) b~_s
+//        backward  x_s = inv(L_ss)^T y_s - (L_Rs inv(L_ss))^T x_R
+//     where b~_s is b_s minus the updates of s's descendants.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include <omp.h>
+
+#include "internal.hpp"
+
+namespace dpd {
+
+namespace {
+
+struct NdCtx {
+  const HostMesh* m;
+  int32_t leaf_max, sep_max;
+  std::vector<std::vector<int32_t>> groups;  // emitted supernode node lists (free indices)
+};
+
+void sort_lex(const HostMesh& m, std::vector<int32_t>& v) {
+  std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+    const int32_t* pa = &m.node_ijk[3 * (int64_t)m.free_nodes[a]];
+    const int32_t* pb = &m.node_ijk[3 * (int64_t)m.free_nodes[b]];
+    if (pa[2] != pb[2]) return pa[2] < pb[2];
+    if (pa[1] != pb[1]) return pa[1] < pb[1];
+    return pa[0] < pb[0];
+  });
+}
+
+void emit(NdCtx& c, std::vector<int32_t>& nodes, int32_t chunk) {
+  sort_lex(*c.m, nodes);
+  const int64_t n = (int64_t)nodes.size();
+  const int64_t pieces = (n + chunk - 1) / chunk;
+  for (int64_t p = 0; p < pieces; ++p) {
+    int64_t b = n * p / pieces, e = n * (p + 1) / pieces;
+    c.groups.emplace_back(nodes.begin() + b, nodes.begin() + e);
+  }
+}
+
+void nd(NdCtx& c, std::vector<int32_t>& nodes) {
+  if (nodes.empty()) return;
+  const HostMesh& m = *c.m;
+  if ((int64_t)nodes.size() <= c.leaf_max) {
+    emit(c, nodes, c.sep_max);
+    return;
+  }
+  int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  for (int32_t f : nodes) {
+    const int32_t* p = &m.node_ijk[3 * (int64_t)m.free_nodes[f]];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], p[k]);
+      hi[k] = std::max(hi[k], p[k]);
+    }
+  }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+  if (hi[ax] - lo[ax] < 2) {
+    emit(c, nodes, c.sep_max);
+    return;
+  }
+  const int32_t mid = lo[ax] + (hi[ax] - lo[ax]) / 2;
+  std::vector<int32_t> left, right, sep;
+  for (int32_t f : nodes) {
+    int32_t v = m.node_ijk[3 * (int64_t)m.free_nodes[f] + ax];
+    (v < mid ? left : (v > mid ? right : sep)).push_back(f);
+  }
+  std::vector<int32_t>().swap(nodes);
+  nd(c, left);
+  nd(c, right);
+  if (!sep.empty()) emit(c, sep, c.sep_max);
+}
+
+}  // namespace
+
+void analyse(const HostMesh& m, const Csr& A, int32_t leaf_max, int32_t sep_max, Symbolic& S) {
+  const int32_t n = A.n;
+  NdCtx c{&m, leaf_max, sep_max, {}};
+  std::vector<int32_t> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  nd(c, all);
+
+  S.n = n;
+  S.perm.clear();
+  S.perm.reserve(n);
+  S.sn.clear();
+  for (auto& g : c.groups) {
+    Supernode s;
+    s.col0 = (int32_t)S.perm.size();
+    s.ncols = (int32_t)g.size();
+    S.sn.push_back(s);
+    S.perm.insert(S.perm.end(), g.begin(), g.end());
+  }
+  S.iperm.assign(n, -1);
+  for (int32_t i = 0; i < n; ++i) S.iperm[S.perm[i]] = i;
+  const int32_t ns = (int32_t)S.sn.size();
+  S.snode_of.assign(n, -1);
+  for (int32_t s = 0; s < ns; ++s)
+    for (int32_t j = 0; j < S.sn[s].ncols; ++j) S.snode_of[S.sn[s].col0 + j] = s;
+
+  S.children.assign(ns, {});
+  S.rows.clear();
+  std::vector<int32_t> mark(n, -1), buf;
+  int64_t panel = 0, u = 0, packed = 0;
+  S.n_levels = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    Supernode& sn = S.sn[s];
+    const int32_t end = sn.col0 + sn.ncols;
+    buf.clear();
+    for (int32_t j = sn.col0; j < end; ++j) {
+      const int32_t f = S.perm[j];
+      for (int64_t k = A.ptr[f]; k < A.ptr[f + 1]; ++k) {
+        const int32_t i = S.iperm[A.col[k]];
+        if (i >= end && mark[i] != s) {
+          mark[i] = s;
+          buf.push_back(i);
+        }
+      }
+    }
+    int32_t lvl = 0;
+    for (int32_t ch : S.children[s]) {
+      const Supernode& cs = S.sn[ch];
+      lvl = std::max(lvl, cs.level + 1);
+      for (int32_t p = 0; p < cs.nrows; ++p) {
+        const int32_t i = S.rows[cs.rows_off + p];
+        if (i >= end && mark[i] != s) {
+          mark[i] = s;
+          buf.push_back(i);
+        }
+      }
+    }
+    std::sort(buf.begin(), buf.end());
+    sn.level = lvl;
+    S.n_levels = std::max(S.n_levels, lvl + 1);
+    sn.nrows = (int32_t)buf.size();
+    sn.rows_off = (int64_t)S.rows.size();
+    S.rows.insert(S.rows.end(), buf.begin(), buf.end());
+    sn.parent = buf.empty() ? -1 : S.snode_of[buf[0]];
+    if (sn.parent >= 0) S.children[sn.parent].push_back(s);
+    sn.panel_off = panel;
+    panel += (int64_t)(sn.ncols + sn.nrows) * sn.ncols;
+    sn.u_off = u;
+    u += sn.nrows;
+    packed += (int64_t)sn.ncols * (sn.ncols + 1) / 2 + (int64_t)sn.nrows * sn.ncols;
+  }
+  S.panel_size = panel;
+  S.u_size = u;
+  S.packed_nnz = packed;
+
+  // forward-update contributions to every internal row, in supernode order
+  S.cptr.assign(n + 1, 0);
+  for (int32_t s = 0; s < ns; ++s)
+    for (int32_t p = 0; p < S.sn[s].nrows; ++p) S.cptr[S.rows[S.sn[s].rows_off + p] + 1]++;
+  for (int32_t i = 0; i < n; ++i) S.cptr[i + 1] += S.cptr[i];
+  S.cidx.assign(S.cptr[n], 0);
+  std::vector<int32_t> fill(S.cptr.begin(), S.cptr.end() - 1);
+  for (int32_t s = 0; s < ns; ++s)
+    for (int32_t p = 0; p < S.sn[s].nrows; ++p) {
+      const int32_t i = S.rows[S.sn[s].rows_off + p];
+      S.cidx[fill[i]++] = (int32_t)(S.sn[s].u_off + p);
+    }
+}
+
+namespace {
+
+// Left-looking Cholesky of the ncols leading columns of an ld x ld front
+// (column-major): produces L_ss in rows [0, n) and L_Rs in rows [n, ld).
+bool panel_cholesky(double* F, int32_t n, int32_t ld) {
+  for (int32_t j = 0; j < n; ++j) {
+    double* cj = F + (int64_t)j * ld;
+    for (int32_t k = 0; k < j; ++k) {
+      const double* ck = F + (int64_t)k * ld;
+      const double a = ck[j];
+      if (a == 0.0) continue;
+      for (int32_t i = j; i < ld; ++i) cj[i] -= ck[i] * a;
+    }
+    const double d = cj[j];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    const double s = std::sqrt(d);
+    cj[j] = s;
+    const double inv = 1.0 / s;
+    for (int32_t i = j + 1; i < ld; ++i) cj[i] *= inv;
+  }
+  return true;
+}
+
+// U (r x r, lower, column-major) = F22 - L21 L21^T where F22 and L21 live in
+// the front F (ld = n + r).
+void schur_update(const double* F, int32_t n, int32_t ld, double* U) {
+  const int32_t r = ld - n;
+  for (int32_t j = 0; j < r; ++j)
+    for (int32_t i = j; i < r; ++i) U[(int64_t)j * r + i] = F[(int64_t)(n + j) * ld + n + i];
+  const int64_t work = (int64_t)r * r * n;
+#pragma omp parallel for schedule(dynamic, 4) if (work > (1 << 22))
+  for (int32_t j0 = 0; j0 < r; j0 += 4) {
+    const int32_t jn = std::min(4, r - j0);
+    for (int32_t k = 0; k < n; ++k) {
+      const double* lk = F + (int64_t)k * ld + n;  // L21[:, k]
+      double a[4] = {0, 0, 0, 0};
+      for (int32_t t = 0; t < jn; ++t) a[t] = lk[j0 + t];
+      if (jn == 4) {
+        double* u0 = U + (int64_t)(j0 + 0) * r;
+        double* u1 = U + (int64_t)(j0 + 1) * r;
+        double* u2 = U + (int64_t)(j0 + 2) * r;
+        double* u3 = U + (int64_t)(j0 + 3) * r;
+        for (int32_t t = 0; t < 4; ++t) {
+          double* ut = U + (int64_t)(j0 + t) * r;
+          for (int32_t i = j0 + t; i < j0 + 4; ++i) ut[i] -= lk[i] * a[t];
+        }
+        for (int32_t i = j0 + 4; i < r; ++i) {
+          const double l = lk[i];
+          u0[i] -= l * a[0];
+          u1[i] -= l * a[1];
+          u2[i] -= l * a[2];
+          u3[i] -= l * a[3];
+        }
+      } else {
+        for (int32_t t = 0; t < jn; ++t) {
+          double* ut = U + (int64_t)(j0 + t) * r;
+          for (int32_t i = j0 + t; i < r; ++i) ut[i] -= lk[i] * a[t];
+        }
+      }
+    }
+  }
+}
+
+// Panel [inv(L11); -L21 inv(L11)] (ld x n, column-major) from the factored front.
+// The lower block is stored negated so both sweeps only add.
+void make_panel(const double* F, int32_t n, int32_t ld, double* P) {
+  // inverse of the lower-triangular L11, column by column
+  std::vector<double> T((int64_t)n * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 8) if ((int64_t)n * n * n > (1 << 21))
+  for (int32_t j = 0; j < n; ++j) {
+    double* t = T.data() + (int64_t)j * n;
+    t[j] = 1.0;
+    for (int32_t k = j; k < n; ++k) {
+      const double* lk = F + (int64_t)k * ld;
+      t[k] /= lk[k];
+      const double tk = t[k];
+      if (tk == 0.0) continue;
+      for (int32_t i = k + 1; i < n; ++i) t[i] -= lk[i] * tk;
+    }
+  }
+  const int32_t r = ld - n;
+#pragma omp parallel for schedule(dynamic, 4) if ((int64_t)r * n * n > (1 << 21))
+  for (int32_t j = 0; j < n; ++j) {
+    double* pc = P + (int64_t)j * ld;
+    const double* t = T.data() + (int64_t)j * n;
+    for (int32_t i = 0; i < n; ++i) pc[i] = t[i];
+    double* w = pc + n;
+    for (int32_t i = 0; i < r; ++i) w[i] = 0.0;
+    for (int32_t k = j; k < n; ++k) {
+      const double tk = t[k];
+      if (tk == 0.0) continue;
+      const double* l = F + (int64_t)k * ld + n;
+      for (int32_t i = 0; i < r; ++i) w[i] -= l[i] * tk;
+    }
+  }
+}
+
+}  // namespace
+
+bool factor_panels(const Symbolic& S, const Csr& A, std::vector<double>& panels, std::string& err) {
+  const int32_t n = S.n, ns = (int32_t)S.sn.size();
+  panels.assign(S.panel_size, 0.0);
+  std::vector<int32_t> loc(n, -1);
+  std::vector<std::vector<double>> upd(ns);
+  std::vector<double> F;
+  for (int32_t s = 0; s < ns; ++s) {
+    const Supernode& sn = S.sn[s];
+    const int32_t nc = sn.ncols, nr = sn.nrows, ld = nc + nr;
+    for (int32_t j = 0; j < nc; ++j) loc[sn.col0 + j] = j;
+    for (int32_t p = 0; p < nr; ++p) loc[S.rows[sn.rows_off + p]] = nc + p;
+    F.assign((int64_t)ld * ld, 0.0);
+    const int32_t end = sn.col0 + nc;
+    for (int32_t j = sn.col0; j < end; ++j) {
+      const int32_t f = S.perm[j];
+      const int32_t lj = loc[j];
+      for (int64_t k = A.ptr[f]; k < A.ptr[f + 1]; ++k) {
+        const int32_t i = S.iperm[A.col[k]];
+        if (i < j) continue;
+        F[(int64_t)lj * ld + loc[i]] += A.val[k];
+      }
+    }
+    for (int32_t ch : S.children[s]) {
+      const Supernode& cs = S.sn[ch];
+      const int32_t r = cs.nrows;
+      const double* U = upd[ch].data();
+      const int32_t* R = &S.rows[cs.rows_off];
+      for (int32_t q = 0; q < r; ++q) {
+        const int64_t lq = (int64_t)loc[R[q]] * ld;
+        for (int32_t p = q; p < r; ++p) F[lq + loc[R[p]]] += U[(int64_t)q * r + p];
+      }
+      std::vector<double>().swap(upd[ch]);
+    }
+    if (!panel_cholesky(F.data(), nc, ld)) {
+      err = "non-positive pivot in supernode " + std::to_string(s);
+      return false;
+    }
+    if (nr > 0) {
+      upd[s].assign((int64_t)nr * nr, 0.0);
+      schur_update(F.data(), nc, ld, upd[s].data());
+    }
+    make_panel(F.data(), nc, ld, panels.data() + sn.panel_off);
+  }
+  return true;
+}
+
+void build_plan(const Symbolic& S, LevelPlan& P) {
+  const int32_t L = S.n_levels;
+  std::vector<std::vector<int32_t>> by_level(L);
+  for (int32_t s = 0; s < (int32_t)S.sn.size(); ++s) by_level[S.sn[s].level].push_back(s);
+  P.fwd.clear();
+  P.bwd.clear();
+  P.fwd_off.assign(L + 1, 0);
+  P.bwd_off.assign(L + 1, 0);
+  P.fwd_cols.assign(L, 0);
+  P.bwd_rows.assign(L, 0);
+  for (int32_t l = 0; l < L; ++l) {
+    P.fwd_off[l] = (int32_t)P.fwd.size();
+    P.bwd_off[l] = (int32_t)P.bwd.size();
+    for (int32_t s : by_level[l]) {
+      const Supernode& sn = S.sn[s];
+      const int32_t ld = sn.ncols + sn.nrows;
+      for (int32_t f = 0; f < ld; f += kBlock) P.fwd.push_back({s, f, std::min(kBlock, ld - f), 0});
+      for (int32_t f = 0; f < sn.ncols; f += kColsPerTask)
+        P.bwd.push_back({s, f, std::min(kColsPerTask, sn.ncols - f), 0});
+      P.fwd_cols[l] = std::max(P.fwd_cols[l], sn.ncols);
+      P.bwd_rows[l] = std::max(P.bwd_rows[l], ld);
+    }
+  }
+  P.fwd_off[L] = (int32_t)P.fwd.size();
+  P.bwd_off[L] = (int32_t)P.bwd.size();
+}
+
+}  // namespace dpd

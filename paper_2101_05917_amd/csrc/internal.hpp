@@ -1,0 +1,100 @@
+// Internal host-side structures of the diffpd library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/diffpd.h"
+
+namespace dpd {
+
+// Dimensionless trilinear shape-function gradients dN_a/dxi_j at the 2x2x2
+// Gauss points (xi = +-1/sqrt(3)); q = qx + 2qy + 4qz, a = ax + 2ay + 4az.
+// Physical gradients are these times 2/dx.
+void reference_gradients(double Bxi[8][3][8]);
+
+// Voxel mesh on the host: public node numbering, connectivity, mass, the
+// Dirichlet and contact sets, and the scalar node matrix A_s (free nodes).
+struct HostMesh {
+  int64_t n_nodes = 0, n_elems = 0, n_free = 0;
+  std::vector<int32_t> node_ijk;     // [N][3]
+  std::vector<int32_t> conn;         // [E][8] public node ids
+  std::vector<double> mass;          // [N]
+  std::vector<double> youngs;        // [E]
+  std::vector<uint8_t> fixed;        // [N]
+  std::vector<int32_t> free_index;   // [N] -> index among free nodes, or -1
+  std::vector<int32_t> free_nodes;   // [n_free] public ids
+  std::vector<int32_t> contact;      // public ids of contact candidates
+  std::vector<uint8_t> is_contact;   // [N]
+  std::vector<double> X;             // [3][N] rest positions
+  // node -> incident (element, local corner) pairs, 8e + a, -1 padded: [8][N]
+  std::vector<int32_t> node_inc;
+  int32_t grid_min[3] = {0, 0, 0}, grid_max[3] = {0, 0, 0};
+};
+
+// Sparse symmetric matrix over free nodes in free-index order, full pattern
+// (both triangles), CSR with sorted columns.
+struct Csr {
+  int32_t n = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+std::string build_mesh(const int32_t* cells, int64_t n_cells, const double* youngs,
+                       const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options& o,
+                       HostMesh& m);
+void assemble_As(const HostMesh& m, const dpd_options& o, Csr& A);
+
+// Supernode of the nested-dissection factor.  Its panel is an ld x ncols
+// column-major block, ld = ncols + nrows: rows [0, ncols) hold the inverse of
+// the diagonal Cholesky block (lower triangular), rows [ncols, ld) hold
+// W = L_{R,s} L_ss^{-1} for the rows R_s below the block.
+struct Supernode {
+  int32_t col0 = 0, ncols = 0, nrows = 0, parent = -1, level = 0;
+  int64_t rows_off = 0;   // into Symbolic::rows
+  int64_t panel_off = 0;  // into the panel array (elements)
+  int64_t u_off = 0;      // into the forward-update buffer (positions)
+};
+
+struct Symbolic {
+  int32_t n = 0;                       // free nodes
+  std::vector<int32_t> perm;           // internal -> free index
+  std::vector<int32_t> iperm;          // free index -> internal
+  std::vector<Supernode> sn;
+  std::vector<int32_t> rows;           // concatenated R_s (internal indices, ascending)
+  std::vector<int32_t> snode_of;       // internal column -> supernode
+  std::vector<std::vector<int32_t>> children;
+  int32_t n_levels = 0;
+  std::vector<int32_t> cptr, cidx;     // forward-update contributions per internal row
+  int64_t panel_size = 0, u_size = 0, packed_nnz = 0;
+};
+
+// Task of a triangular-sweep level: supernode s, first row/column, count.
+struct SweepTask {
+  int32_t sn, first, count, pad;
+};
+
+constexpr int kBlock = 256;          // threads per workgroup of every kernel
+constexpr int kColsPerTask = 16;     // backward-sweep columns per workgroup
+
+// Level schedule of the sweeps: supernodes of equal tree level are
+// independent.  Forward tasks cover 256 panel rows, backward tasks 16 columns.
+struct LevelPlan {
+  std::vector<int32_t> fwd_off, bwd_off;   // task ranges per level (size L + 1)
+  std::vector<int32_t> fwd_cols, bwd_rows; // dynamic LDS extents per level
+  std::vector<SweepTask> fwd, bwd;
+};
+
+// Geometric nested dissection of the free nodes on the voxel grid, then the
+// supernodal symbolic analysis (row structures, tree, levels, contributions).
+void analyse(const HostMesh& m, const Csr& A, int32_t leaf_max, int32_t sep_max, Symbolic& S);
+
+// Multifrontal numeric Cholesky of A (permuted to internal order) and the
+// panel construction.  Returns false (with message) on a non-positive pivot.
+bool factor_panels(const Symbolic& S, const Csr& A, std::vector<double>& panels, std::string& err);
+
+void build_plan(const Symbolic& S, LevelPlan& P);
+
+}  // namespace dpd

@@ -1,0 +1,1109 @@
+// HIP kernels (gfx950) of the PD step and its adjoint.
+//
+//  * Local step (Alg. 1, eq:pd_energy_single): one thread per Gauss point,
+//    eight lanes per hex element.  The element's eight node positions are
+//    staged in LDS, each lane forms its deformation gradient F_q, projects it
+//    onto SO(3) (closest rotation, supplemental Sec. Energy Definitions) and
+//    the lanes of an element exchange their stresses through LDS to produce
+//    the eight nodal force vectors of the element.  No atomics: element
+//    forces go to an element-major buffer and a node-centric kernel gathers
+//    the (at most eight) contributions of each node in a fixed order.
+//  * Residual: grad g(x) = M (x - y)/h^2 + sum_c w_c G_c^T (G_c x - p_c)
+//    (eq:energy_grad), whose norm drives the stopping test; the global step
+//    is then x <- x - A^{-1} grad g(x), the correction form of Alg. 1.
+//  * Adjoint local step (eq:matrix_split): dA p through the differential of
+//    the polar decomposition at cached rotations.
+//  * Global step: level-scheduled supernodal sweeps over precomputed panels
+//    [inv(L_ss); -L_Rs inv(L_ss)] (dense matrix-vector products per level).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.hpp"
+
+namespace dpd {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; valid in thread 0.
+__device__ inline double block_sum(double v, double* ws) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ws[i];
+  __syncthreads();
+  return t;
+}
+
+// Grid-wide sum with a deterministic order: each block publishes its partial,
+// the last block to arrive sums the partials in block order.  Returns true in
+// thread 0 of the last block, with the total in *total.
+__device__ inline bool grid_sum(double v, double* partials, IterState* st, double* total) {
+  __shared__ double ws[kBlock / 64];
+  __shared__ int last;
+  const double bs = block_sum(v, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t =
+        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // keep the order fixed: strided partial sums, then the block tree
+  s = block_sum(s, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = s;
+  }
+  return threadIdx.x == 0;
+}
+
+// dN_a/dX_j at Gauss point q of a cubic voxel: (1/8) s_aj prod_{k != j}(1 +- g) * 2/dx,
+// the factor being 1 + g when bits k of a and q agree and 1 - g otherwise.
+struct GradTable {
+  double c2, c1, c0;  // magnitudes for two, one, zero agreeing axes
+};
+
+__device__ inline double bgrad(int q, int j, int a, const GradTable& T) {
+  const int x = ~(a ^ q);
+  const int agree = ((x >> ((j + 1) % 3)) & 1) + ((x >> ((j + 2) % 3)) & 1);
+  const double mag = agree == 2 ? T.c2 : (agree == 1 ? T.c1 : T.c0);
+  return ((a >> j) & 1) ? mag : -mag;
+}
+
+__device__ inline GradTable grad_table(double dx) {
+  const double g = 0.57735026918962576451;  // 1/sqrt(3)
+  const double s = 2.0 / dx / 8.0;
+  return {s * (1.0 + g) * (1.0 + g), s * (1.0 + g) * (1.0 - g), s * (1.0 - g) * (1.0 - g)};
+}
+
+// Closest rotation to F (row-major 3x3), i.e. argmax over SO(3) of tr(R^T F).
+// With R = R(quat) this is the largest-eigenvalue eigenvector of a symmetric
+// 4x4 matrix (Davenport's q-method); the eigenproblem is solved by cyclic
+// Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition).
+__device__ inline void jrot(double (&B)[4][4], double (&V)[4][4], int p, int q) {
+  const double apq = B[p][q];
+  if (fabs(apq) <= 1e-300) return;
+  const double tau = (B[q][q] - B[p][p]) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k == p || k == q) continue;
+    const double bkp = B[k][p], bkq = B[k][q];
+    B[k][p] = B[p][k] = c * bkp - s * bkq;
+    B[k][q] = B[q][k] = s * bkp + c * bkq;
+  }
+  B[p][p] -= t * apq;
+  B[q][q] += t * apq;
+  B[p][q] = B[q][p] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double vkp = V[k][p], vkq = V[k][q];
+    V[k][p] = c * vkp - s * vkq;
+    V[k][q] = s * vkp + c * vkq;
+  }
+}
+
+__device__ inline void closest_rotation(const double F[9], double R[9]) {
+  double B[4][4], V[4][4];
+  B[0][0] = F[0] + F[4] + F[8];
+  B[1][1] = F[0] - F[4] - F[8];
+  B[2][2] = -F[0] + F[4] - F[8];
+  B[3][3] = -F[0] - F[4] + F[8];
+  B[0][1] = B[1][0] = F[7] - F[5];
+  B[0][2] = B[2][0] = F[2] - F[6];
+  B[0][3] = B[3][0] = F[3] - F[1];
+  B[1][2] = B[2][1] = F[1] + F[3];
+  B[1][3] = B[3][1] = F[2] + F[6];
+  B[2][3] = B[3][2] = F[5] + F[7];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  double nrm = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) nrm += B[i][j] * B[i][j];
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    const double off = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[0][3] * B[0][3] +
+                       B[1][2] * B[1][2] + B[1][3] * B[1][3] + B[2][3] * B[2][3];
+    if (off <= 1e-34 * nrm) break;
+    jrot(B, V, 0, 1);
+    jrot(B, V, 0, 2);
+    jrot(B, V, 0, 3);
+    jrot(B, V, 1, 2);
+    jrot(B, V, 1, 3);
+    jrot(B, V, 2, 3);
+  }
+  int k = 0;
+  double best = B[0][0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (B[i][i] > best) {
+      best = B[i][i];
+      k = i;
+    }
+  double w = 1.0, x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i == k) {
+      w = V[0][i];
+      x = V[1][i];
+      y = V[2][i];
+      z = V[3][i];
+    }
+  const double s = 2.0 / (w * w + x * x + y * y + z * z);
+  R[0] = 1.0 - s * (y * y + z * z);
+  R[1] = s * (x * y - w * z);
+  R[2] = s * (x * z + w * y);
+  R[3] = s * (x * y + w * z);
+  R[4] = 1.0 - s * (x * x + z * z);
+  R[5] = s * (y * z - w * x);
+  R[6] = s * (x * z - w * y);
+  R[7] = s * (y * z + w * x);
+  R[8] = 1.0 - s * (x * x + y * y);
+}
+
+__device__ inline double det3(const double F[9]) {
+  return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+         F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// Differential of the closest rotation: dR = R [w]_x with
+// (tr(S) I - S) w = axial(R^T dF - dF^T R), S = R^T F (symmetric).  Returns the
+// inverse of K = tr(S) I - S as 6 entries (xx, yy, zz, xy, xz, yz); a singular K
+// (sigma_i + sigma_j = 0) yields zeros and is reported through the flag.
+__device__ inline bool rotation_kinv(const double F[9], const double R[9], double Ki[6]) {
+  double S[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = R[i] * F[j] + R[3 + i] * F[3 + j] + R[6 + i] * F[6 + j];
+  const double sxy = 0.5 * (S[1] + S[3]), sxz = 0.5 * (S[2] + S[6]), syz = 0.5 * (S[5] + S[7]);
+  const double tr = S[0] + S[4] + S[8];
+  const double kxx = tr - S[0], kyy = tr - S[4], kzz = tr - S[8];
+  const double kxy = -sxy, kxz = -sxz, kyz = -syz;
+  const double cxx = kyy * kzz - kyz * kyz, cyy = kxx * kzz - kxz * kxz, czz = kxx * kyy - kxy * kxy;
+  const double cxy = kxz * kyz - kxy * kzz, cxz = kxy * kyz - kxz * kyy, cyz = kxy * kxz - kxx * kyz;
+  const double det = kxx * cxx + kxy * cxy + kxz * cxz;
+  const double scale = fabs(tr) + 1e-300;
+  if (!(fabs(det) > 1e-12 * scale * scale * scale)) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Ki[i] = 0.0;
+    return false;
+  }
+  const double id = 1.0 / det;
+  Ki[0] = cxx * id;
+  Ki[1] = cyy * id;
+  Ki[2] = czz * id;
+  Ki[3] = cxy * id;
+  Ki[4] = cxz * id;
+  Ki[5] = cyz * id;
+  return true;
+}
+
+__device__ inline void rotation_apply_diff(const double R[9], const double Ki[6], const double dF[9],
+                                           double dR[9]) {
+  // M = R^T dF; a = axial(M - M^T) = (M21 - M12, M02 - M20, M10 - M01)
+  double M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = R[i] * dF[j] + R[3 + i] * dF[3 + j] + R[6 + i] * dF[6 + j];
+  const double a0 = M[7] - M[5], a1 = M[2] - M[6], a2 = M[3] - M[1];
+  const double w0 = Ki[0] * a0 + Ki[3] * a1 + Ki[4] * a2;
+  const double w1 = Ki[3] * a0 + Ki[1] * a1 + Ki[5] * a2;
+  const double w2 = Ki[4] * a0 + Ki[5] * a1 + Ki[2] * a2;
+  // R [w]_x, [w]_x = [[0,-w2,w1],[w2,0,-w0],[-w1,w0,0]]
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r0 = R[3 * i], r1 = R[3 * i + 1], r2 = R[3 * i + 2];
+    dR[3 * i + 0] = r1 * w2 - r2 * w1;
+    dR[3 * i + 1] = -r0 * w2 + r2 * w0;
+    dR[3 * i + 2] = r0 * w1 - r1 * w0;
+  }
+}
+
+// Element tile: 32 elements x 8 Gauss points per 256-thread block.
+struct ElemTile {
+  double xs[kElemsPerBlock][8][3];
+  double Ps[kElemsPerBlock][8][9];
+};
+
+__device__ inline void gather_nodes(const DevMesh& M, const double* __restrict__ x, ElemTile& T,
+                                    int le, int a, int e, bool valid) {
+  if (valid) {
+    const int n = M.conn[(int64_t)a * M.E + e];
+    T.xs[le][a][0] = x[n];
+    T.xs[le][a][1] = x[(int64_t)M.N + n];
+    T.xs[le][a][2] = x[2 * (int64_t)M.N + n];
+  }
+}
+
+__device__ inline void deformation_gradient(const ElemTile& T, int le, int q, const GradTable& G,
+                                            double F[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F[i] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double b0 = bgrad(q, 0, a, G), b1 = bgrad(q, 1, a, G), b2 = bgrad(q, 2, a, G);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double xi = T.xs[le][a][i];
+      F[3 * i + 0] += xi * b0;
+      F[3 * i + 1] += xi * b1;
+      F[3 * i + 2] += xi * b2;
+    }
+  }
+}
+
+// f_a = sum_q P_q gradN_a(xi_q), written to fe[c][8e + a]
+__device__ inline void element_forces_out(const DevMesh& M, const ElemTile& T, int le, int a,
+                                          int e, bool valid, const GradTable& G, double* fe) {
+  if (!valid) return;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double b0 = bgrad(q, 0, a, G), b1 = bgrad(q, 1, a, G), b2 = bgrad(q, 2, a, G);
+    const double* P = T.Ps[le][q];
+    f0 += P[0] * b0 + P[1] * b1 + P[2] * b2;
+    f1 += P[3] * b0 + P[4] * b1 + P[5] * b2;
+    f2 += P[6] * b0 + P[7] * b1 + P[8] * b2;
+  }
+  const int64_t E8 = 8 * (int64_t)M.E, idx = 8 * (int64_t)e + a;
+  fe[idx] = f0;
+  fe[E8 + idx] = f1;
+  fe[2 * E8 + idx] = f2;
+}
+
+// ------------------------------------------------------------------ forward local step
+
+__global__ void __launch_bounds__(kBlock) k_elem_forces(DevMesh M, const double* __restrict__ x,
+                                                        const double* __restrict__ act,
+                                                        double* __restrict__ fe,
+                                                        double* __restrict__ R_out,
+                                                        IterState* st) {
+  if (st && st->done) return;
+  __shared__ ElemTile T;
+  const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int e = blockIdx.x * kElemsPerBlock + le;
+  const bool valid = e < M.E;
+  const GradTable G = grad_table(M.dx);
+  gather_nodes(M, x, T, le, q, e, valid);
+  __syncthreads();
+  if (valid) {
+    double F[9], R[9];
+    deformation_gradient(T, le, q, G, F);
+    closest_rotation(F, R);
+    if (st && det3(F) <= 0.0) atomicAdd(&st->inverted, 1);
+    const double w = M.w_e[e];
+    double* P = T.Ps[le][q];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[i] = w * (F[i] - R[i]);
+    if (R_out) {
+      const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R_out[i * Q + qi] = R[i];
+    }
+    if (M.muscle_k > 0.0) {
+      // fibre projection onto |p| = r (supplemental, muscle fibers)
+      const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
+      const double f0 = F[0] * m0 + F[1] * m1 + F[2] * m2;
+      const double f1 = F[3] * m0 + F[4] * m1 + F[5] * m2;
+      const double f2 = F[6] * m0 + F[7] * m1 + F[8] * m2;
+      const double r = act ? act[e] : 1.0;
+      const double nf = sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+      double p0, p1, p2;
+      if (nf > 0.0) {
+        p0 = r * f0 / nf;
+        p1 = r * f1 / nf;
+        p2 = r * f2 / nf;
+      } else {
+        p0 = r * m0;
+        p1 = r * m1;
+        p2 = r * m2;
+      }
+      const double wm = M.muscle_k * M.Vq;
+      const double d0 = wm * (f0 - p0), d1 = wm * (f1 - p1), d2 = wm * (f2 - p2);
+      P[0] += d0 * m0; P[1] += d0 * m1; P[2] += d0 * m2;
+      P[3] += d1 * m0; P[4] += d1 * m1; P[5] += d1 * m2;
+      P[6] += d2 * m0; P[7] += d2 * m1; P[8] += d2 * m2;
+    }
+  }
+  __syncthreads();
+  element_forces_out(M, T, le, q, e, valid, G, fe);
+}
+
+// Sum the element forces of every node (fixed order) and form the residual.
+__device__ inline void node_force(const DevMesh& M, const double* __restrict__ fe, int n,
+                                  double& f0, double& f1, double& f2) {
+  const int64_t E8 = 8 * (int64_t)M.E;
+  f0 = f1 = f2 = 0.0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int p = M.node_inc[(int64_t)s * M.N + n];
+    if (p >= 0) {
+      f0 += fe[p];
+      f1 += fe[E8 + p];
+      f2 += fe[2 * E8 + p];
+    }
+  }
+}
+
+// r = M (x - y)/h^2 + sum w G^T (G x - p) + ground term; |r|^2 -> stopping test.
+__global__ void __launch_bounds__(kBlock) k_node_residual(DevMesh M, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ fe,
+                                                          double* __restrict__ r, IterState* st,
+                                                          double* partials, int k, int max_iter,
+                                                          int fixed_iters) {
+  if (st->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N) {
+    const int64_t N = M.N;
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    if (!M.fixed[n]) {
+      node_force(M, fe, n, r0, r1, r2);
+      const double c = M.mass[n] / (M.h * M.h);
+      r0 += c * (x[n] - y[n]);
+      r1 += c * (x[N + n] - y[N + n]);
+      r2 += c * (x[2 * N + n] - y[2 * N + n]);
+      if (M.contact[n]) {
+        const double z = x[2 * N + n];
+        if (z < 0.0) r2 += M.contact_k * z;
+      }
+      acc = r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    r[n] = r0;
+    r[N + n] = r1;
+    r[2 * N + n] = r2;
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    st->rsq = tot;
+    st->iter = k;
+    if (k == 0) st->r0sq = tot;
+    if (!isfinite(tot)) {
+      st->nonfinite = 1;
+      st->done = 1;
+    } else if (!fixed_iters && (tot <= st->tolsq * st->r0sq || tot <= st->atolsq)) {
+      st->converged = 1;
+      st->done = 1;
+    }
+    if (k >= max_iter) st->done = 1;
+  }
+}
+
+__global__ void k_reset_state(IterState* st, double tolsq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->r0sq = st->rsq = st->atolsq = 0.0;
+    st->tolsq = tolsq;
+    st->nb2 = st->rs = st->pq = st->alpha = st->beta = st->acc = 0.0;
+    st->iter = st->done = st->converged = st->nonfinite = st->curvature = st->inverted = 0;
+    st->counter = 0u;
+  }
+}
+
+// y = x + h v + h^2 (g + f_fric / m); x^0 = y with Dirichlet nodes at rest.
+// The explicit friction acts on ground-contact nodes below the ground.
+__global__ void __launch_bounds__(kBlock) k_prologue(DevMesh M, const double* __restrict__ x,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ y, double* __restrict__ xn,
+                                                     IterState* st, double* partials,
+                                                     double abs_tol_rel) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N) {
+    const int64_t N = M.N;
+    double ft0 = 0.0, ft1 = 0.0;
+    if (M.contact[n] && M.friction_mu > 0.0) {
+      const double z = x[2 * N + n];
+      const double fn = M.contact_k * fmax(0.0, -z);
+      const double v0 = v[n], v1 = v[N + n];
+      const double s = sqrt(v0 * v0 + v1 * v1 + M.friction_eps * M.friction_eps);
+      ft0 = -M.friction_mu * fn * v0 / s;
+      ft1 = -M.friction_mu * fn * v1 / s;
+    }
+    const double h = M.h, m = M.mass[n];
+    const double y0 = x[n] + h * v[n] + h * h * (M.g[0] + ft0 / m);
+    const double y1 = x[N + n] + h * v[N + n] + h * h * (M.g[1] + ft1 / m);
+    const double y2 = x[2 * N + n] + h * v[2 * N + n] + h * h * M.g[2];
+    y[n] = y0;
+    y[N + n] = y1;
+    y[2 * N + n] = y2;
+    if (M.fixed[n]) {
+      xn[n] = M.X[n];
+      xn[N + n] = M.X[N + n];
+      xn[2 * N + n] = M.X[2 * N + n];
+    } else {
+      xn[n] = y0;
+      xn[N + n] = y1;
+      xn[2 * N + n] = y2;
+      const double c = m / (h * h);
+      acc = c * c * (y0 * y0 + y1 * y1 + y2 * y2);
+    }
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) st->atolsq = abs_tol_rel * abs_tol_rel * tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_velocity(int N, double inv_h, const double* __restrict__ x,
+                                                     const double* __restrict__ xn,
+                                                     double* __restrict__ vn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * (int64_t)N) vn[i] = (xn[i] - x[i]) * inv_h;
+}
+
+// ------------------------------------------------------------------ triangular sweeps
+
+// Forward sweep of one level: for each task (supernode s, rows [first, first+count)),
+// b~_s = b_s + (updates of s's descendants), then rows < ncols give y_s = inv(L_ss) b~_s
+// and the remaining rows give the update -L_Rs inv(L_ss) b~_s for s's ancestors.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                      const T* __restrict__ panel,
+                                                      const double* __restrict__ b, int N,
+                                                      const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double bs[];
+  const SweepTask t = tasks[blockIdx.x];
+  const int s = t.sn;
+  const int col0 = S.sn_col0[s], nc = S.sn_ncols[s], nr = S.sn_nrows[s], ld = nc + nr;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int j = col0 + c;
+    const int node = S.perm_pub[j];
+    double v0 = b[node], v1 = b[(int64_t)N + node], v2 = b[2 * (int64_t)N + node];
+    for (int k = S.cptr[j]; k < S.cptr[j + 1]; ++k) {
+      const int64_t pos = 3 * (int64_t)S.cidx[k];
+      v0 += S.U[pos];
+      v1 += S.U[pos + 1];
+      v2 += S.U[pos + 2];
+    }
+    bs[c] = v0;
+    bs[nc + c] = v1;
+    bs[2 * nc + c] = v2;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x >= t.count) return;
+  const int r = t.first + threadIdx.x;
+  const T* P = panel + S.sn_panel_off[s] + r;
+  const int cend = r < nc ? r + 1 : nc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int c = 0;
+  for (; c + 4 <= cend; c += 4) {
+    const double p0 = (double)P[(int64_t)(c + 0) * ld], p1 = (double)P[(int64_t)(c + 1) * ld];
+    const double p2 = (double)P[(int64_t)(c + 2) * ld], p3 = (double)P[(int64_t)(c + 3) * ld];
+    a0 += p0 * bs[c] + p1 * bs[c + 1] + p2 * bs[c + 2] + p3 * bs[c + 3];
+    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 1] + p2 * bs[nc + c + 2] + p3 * bs[nc + c + 3];
+    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 1] + p2 * bs[2 * nc + c + 2] +
+          p3 * bs[2 * nc + c + 3];
+  }
+  for (; c < cend; ++c) {
+    const double p = (double)P[(int64_t)c * ld];
+    a0 += p * bs[c];
+    a1 += p * bs[nc + c];
+    a2 += p * bs[2 * nc + c];
+  }
+  if (r < nc) {
+    const int j = col0 + r;
+    S.y_int[j] = a0;
+    S.y_int[(int64_t)S.nf + j] = a1;
+    S.y_int[2 * (int64_t)S.nf + j] = a2;
+  } else {
+    const int64_t pos = 3 * (S.sn_u_off[s] + (r - nc));
+    S.U[pos] = a0;
+    S.U[pos + 1] = a1;
+    S.U[pos + 2] = a2;
+  }
+}
+
+// Backward sweep of one level: for each task (supernode s, columns [first, first+count)),
+// x_s = inv(L_ss)^T y_s + (-L_Rs inv(L_ss))^T x_R, one wave per column.
+// out[perm] = alpha x (+ out if accumulate).
+template <typename T, bool kLds>
+__global__ void __launch_bounds__(kBlock) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                      const T* __restrict__ panel,
+                                                      double* __restrict__ out, int N, double alpha,
+                                                      int accumulate, const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double vs[];
+  const SweepTask t = tasks[blockIdx.x];
+  const int s = t.sn;
+  const int col0 = S.sn_col0[s], nc = S.sn_ncols[s], nr = S.sn_nrows[s], ld = nc + nr;
+  const int64_t nf = S.nf;
+  const int* rows = S.rows + S.sn_rows_off[s];
+  if (kLds) {
+    for (int r = threadIdx.x; r < ld; r += blockDim.x) {
+      const double* src = S.y_int;
+      int j = col0 + r;
+      if (r >= nc) {
+        src = S.x_int;
+        j = rows[r - nc];
+      }
+      vs[r] = src[j];
+      vs[ld + r] = src[nf + j];
+      vs[2 * ld + r] = src[2 * nf + j];
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const T* Pb = panel + S.sn_panel_off[s];
+  for (int cc = wid; cc < t.count; cc += nw) {
+    const int c = t.first + cc;
+    const T* P = Pb + (int64_t)c * ld;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int r = c + lane; r < ld; r += 64) {
+      const double p = (double)P[r];
+      double v0, v1, v2;
+      if (kLds) {
+        v0 = vs[r];
+        v1 = vs[ld + r];
+        v2 = vs[2 * ld + r];
+      } else {
+        const double* src = S.y_int;
+        int j = col0 + r;
+        if (r >= nc) {
+          src = S.x_int;
+          j = rows[r - nc];
+        }
+        v0 = src[j];
+        v1 = src[nf + j];
+        v2 = src[2 * nf + j];
+      }
+      a0 += p * v0;
+      a1 += p * v1;
+      a2 += p * v2;
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      const int j = col0 + c;
+      S.x_int[j] = a0;
+      S.x_int[nf + j] = a1;
+      S.x_int[2 * nf + j] = a2;
+      const int node = S.perm_pub[j];
+      if (accumulate) {
+        out[node] += alpha * a0;
+        out[(int64_t)N + node] += alpha * a1;
+        out[2 * (int64_t)N + node] += alpha * a2;
+      } else {
+        out[node] = alpha * a0;
+        out[(int64_t)N + node] = alpha * a1;
+        out[2 * (int64_t)N + node] = alpha * a2;
+      }
+    }
+  }
+}
+
+// Zero the fixed-node rows of a [3][N] vector (outputs of a solve are defined
+// on free nodes only).
+__global__ void k_zero_fixed(DevMesh M, double* v) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < M.N && M.fixed[n]) {
+    v[n] = 0.0;
+    v[(int64_t)M.N + n] = 0.0;
+    v[2 * (int64_t)M.N + n] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// Per Gauss point at x_{i+1}: R (9), inv(tr(S) I - S) (6), and for muscles the unit
+// fibre image n (3) and r/|f| (1): cache layout [19][Q].
+constexpr int kCacheRows = 19;
+
+__global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* __restrict__ x,
+                                                      const double* __restrict__ act,
+                                                      double* __restrict__ cache, IterState* st) {
+  __shared__ ElemTile T;
+  const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int e = blockIdx.x * kElemsPerBlock + le;
+  const bool valid = e < M.E;
+  const GradTable G = grad_table(M.dx);
+  gather_nodes(M, x, T, le, q, e, valid);
+  __syncthreads();
+  if (!valid) return;
+  double F[9], R[9], Ki[6];
+  deformation_gradient(T, le, q, G, F);
+  closest_rotation(F, R);
+  const bool ok = rotation_kinv(F, R, Ki);
+  if (st && (!ok || det3(F) <= 0.0)) atomicAdd(&st->inverted, 1);
+  const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cache[i * Q + qi] = R[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) cache[(9 + i) * Q + qi] = Ki[i];
+  if (M.muscle_k > 0.0) {
+    const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
+    const double f0 = F[0] * m0 + F[1] * m1 + F[2] * m2;
+    const double f1 = F[3] * m0 + F[4] * m1 + F[5] * m2;
+    const double f2 = F[6] * m0 + F[7] * m1 + F[8] * m2;
+    const double nf = sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+    const double r = act ? act[e] : 1.0;
+    if (nf > 0.0) {
+      cache[15 * Q + qi] = f0 / nf;
+      cache[16 * Q + qi] = f1 / nf;
+      cache[17 * Q + qi] = f2 / nf;
+      cache[18 * Q + qi] = r / nf;
+    } else {
+      cache[15 * Q + qi] = m0;
+      cache[16 * Q + qi] = m1;
+      cache[17 * Q + qi] = m2;
+      cache[18 * Q + qi] = 0.0;
+    }
+  }
+}
+
+// Element part of (A - dA) p: stress w (dF - dR[dF]) (+ muscle (I - dp/df) term).
+__global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
+                                                     const double* __restrict__ cache,
+                                                     double* __restrict__ fe, const IterState* st) {
+  if (st && st->done) return;
+  __shared__ ElemTile T;
+  const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int e = blockIdx.x * kElemsPerBlock + le;
+  const bool valid = e < M.E;
+  const GradTable G = grad_table(M.dx);
+  gather_nodes(M, p, T, le, q, e, valid);
+  __syncthreads();
+  if (valid) {
+    const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+    double dF[9], R[9], Ki[6], dR[9];
+    deformation_gradient(T, le, q, G, dF);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = cache[i * Q + qi];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Ki[i] = cache[(9 + i) * Q + qi];
+    rotation_apply_diff(R, Ki, dF, dR);
+    const double w = M.w_e[e];
+    double* P = T.Ps[le][q];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[i] = w * (dF[i] - dR[i]);
+    if (M.muscle_k > 0.0) {
+      const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
+      const double d0 = dF[0] * m0 + dF[1] * m1 + dF[2] * m2;
+      const double d1 = dF[3] * m0 + dF[4] * m1 + dF[5] * m2;
+      const double d2 = dF[6] * m0 + dF[7] * m1 + dF[8] * m2;
+      const double n0 = cache[15 * Q + qi], n1 = cache[16 * Q + qi], n2 = cache[17 * Q + qi];
+      const double sc = cache[18 * Q + qi];
+      const double nd = n0 * d0 + n1 * d1 + n2 * d2;
+      const double wm = M.muscle_k * M.Vq;
+      // (I - (r/|f|)(I - n n^T)) df
+      const double g0 = wm * (d0 - sc * (d0 - n0 * nd));
+      const double g1 = wm * (d1 - sc * (d1 - n1 * nd));
+      const double g2 = wm * (d2 - sc * (d2 - n2 * nd));
+      P[0] += g0 * m0; P[1] += g0 * m1; P[2] += g0 * m2;
+      P[3] += g1 * m0; P[4] += g1 * m1; P[5] += g1 * m2;
+      P[6] += g2 * m0; P[7] += g2 * m1; P[8] += g2 * m2;
+    }
+  }
+  __syncthreads();
+  element_forces_out(M, T, le, q, e, valid, G, fe);
+}
+
+// out = (A - dA) p (- rhs if given); mode 0: plain; mode 1: out = H p - rhs and
+// |out|^2 / nb2 drives the fixed-point stopping test; mode 2: p . out -> CG alpha.
+__global__ void __launch_bounds__(kBlock) k_node_hvp(DevMesh M, const double* __restrict__ p,
+                                                     const double* __restrict__ fe,
+                                                     const double* __restrict__ xk,
+                                                     const double* __restrict__ rhs,
+                                                     double* __restrict__ out, IterState* st,
+                                                     double* partials, int mode, int k, int max_iter) {
+  if (st && st->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N) {
+    const int64_t N = M.N;
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (!M.fixed[n]) {
+      node_force(M, fe, n, o0, o1, o2);
+      const double c = M.mass[n] / (M.h * M.h);
+      const double p0 = p[n], p1 = p[N + n], p2 = p[2 * N + n];
+      o0 += c * p0;
+      o1 += c * p1;
+      o2 += c * p2;
+      if (M.contact[n] && xk[2 * N + n] < 0.0) o2 += M.contact_k * p2;
+      if (rhs) {
+        o0 -= rhs[n];
+        o1 -= rhs[N + n];
+        o2 -= rhs[2 * N + n];
+      }
+      acc = (mode == 2) ? (p0 * o0 + p1 * o1 + p2 * o2) : (o0 * o0 + o1 * o1 + o2 * o2);
+    }
+    out[n] = o0;
+    out[N + n] = o1;
+    out[2 * N + n] = o2;
+  }
+  if (mode == 0) return;
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    if (mode == 1) {
+      st->rsq = tot;
+      st->iter = k;
+      if (!isfinite(tot)) {
+        st->nonfinite = 1;
+        st->done = 1;
+      } else if (tot <= st->tolsq * st->nb2) {
+        st->converged = 1;
+        st->done = 1;
+      }
+      if (k >= max_iter) st->done = 1;
+    } else {
+      st->pq = tot;
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        st->curvature = 1;
+        st->done = 1;
+      } else {
+        st->alpha = st->rs / tot;
+      }
+    }
+  }
+}
+
+// Dot product / squared norm over free nodes into st (what: 0 -> nb2 (and rsq),
+// 1 -> rs (initial), 2 -> beta = new/old rs, rs = new).
+__global__ void __launch_bounds__(kBlock) k_dot(DevMesh M, const double* __restrict__ a,
+                                                const double* __restrict__ b, IterState* st,
+                                                double* partials, int what) {
+  if (what == 2 && st->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N && !M.fixed[n]) {
+    const int64_t N = M.N;
+    acc = a[n] * b[n] + a[N + n] * b[N + n] + a[2 * N + n] * b[2 * N + n];
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    if (what == 0) {
+      st->nb2 = tot;
+      st->rsq = tot;
+      if (!(tot > 0.0)) {
+        st->converged = 1;
+        st->done = 1;
+      }
+    } else if (what == 1) {
+      st->rs = tot;
+    } else {
+      st->beta = tot / st->rs;
+      st->rs = tot;
+    }
+  }
+}
+
+// z += alpha p; r -= alpha q; |r|^2 -> stopping test.
+__global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh M, double* __restrict__ z,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q, IterState* st,
+                                                      double* partials, int k, int max_iter) {
+  if (st->done) return;
+  const double alpha = st->alpha;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N && !M.fixed[n]) {
+    const int64_t N = M.N;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * N + n;
+      z[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      acc += ri * ri;
+    }
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    st->rsq = tot;
+    st->iter = k;
+    if (!isfinite(tot)) {
+      st->nonfinite = 1;
+      st->done = 1;
+    } else if (tot <= st->tolsq * st->nb2) {
+      st->converged = 1;
+      st->done = 1;
+    }
+    if (k >= max_iter) st->done = 1;
+  }
+}
+
+// p = s + beta p
+__global__ void __launch_bounds__(kBlock) k_cg_direction(DevMesh M, double* __restrict__ p,
+                                                         const double* __restrict__ s,
+                                                         const IterState* st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < M.N && !M.fixed[n]) {
+    const int64_t N = M.N;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c * N + n] = s[c * N + n] + beta * p[c * N + n];
+  }
+}
+
+// Backward epilogue: dL/dy = M z/h^2 (eq:chain_rule); through
+// y = x + h v + h^2 M^{-1}(M g + f_fric(x, v)) and v_{i+1} = (x_{i+1} - x)/h.
+// dL/df_fric = h^2 M^{-1} dL/dy = z.
+__global__ void __launch_bounds__(kBlock) k_adj_epilogue(DevMesh M, const double* __restrict__ x,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ z,
+                                                         const double* __restrict__ gv_next,
+                                                         double* __restrict__ gx,
+                                                         double* __restrict__ gv) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= M.N) return;
+  const int64_t N = M.N;
+  const double h = M.h;
+  const bool fixed = M.fixed[n];
+  const double c = fixed ? 0.0 : M.mass[n] / (h * h);
+  double dy[3], ox[3], ov[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dy[k] = fixed ? 0.0 : c * z[k * N + n];
+    ox[k] = dy[k] - gv_next[k * N + n] / h;
+    ov[k] = h * dy[k];
+  }
+  if (!fixed && M.contact[n] && M.friction_mu > 0.0) {
+    const double zz = x[2 * N + n];
+    const double k = M.contact_k, mu = M.friction_mu;
+    const double fn = k * fmax(0.0, -zz);
+    const double dfn = zz < 0.0 ? -k : 0.0;
+    const double v0 = v[n], v1 = v[N + n];
+    const double s2 = v0 * v0 + v1 * v1 + M.friction_eps * M.friction_eps;
+    const double s = sqrt(s2);
+    const double w0 = z[n], w1 = z[N + n];
+    ox[2] += -mu * dfn * (w0 * v0 + w1 * v1) / s;
+    const double a = -mu * fn / s, b = mu * fn / (s * s2);
+    const double vw = v0 * w0 + v1 * w1;
+    ov[0] += a * w0 + b * v0 * vw;
+    ov[1] += a * w1 + b * v1 * vw;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gx[k * N + n] = ox[k];
+    gv[k * N + n] = ov[k];
+  }
+}
+
+// dL/dE_e += -V_q/(1+nu) sum_q <G_q z, F_q - R_q>;  dL/dr_e = sum_q w_m <G_m,q z, n_q>.
+__global__ void __launch_bounds__(kBlock) k_grad_params(DevMesh M, const double* __restrict__ xn,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ cache,
+                                                        double* __restrict__ g_youngs,
+                                                        double* __restrict__ g_act) {
+  __shared__ ElemTile T;
+  __shared__ double Zs[kElemsPerBlock][8][3];
+  __shared__ double red[kElemsPerBlock][8][2];
+  const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int e = blockIdx.x * kElemsPerBlock + le;
+  const bool valid = e < M.E;
+  const GradTable G = grad_table(M.dx);
+  gather_nodes(M, xn, T, le, q, e, valid);
+  if (valid) {
+    const int nd = M.conn[(int64_t)q * M.E + e];
+    Zs[le][q][0] = z[nd];
+    Zs[le][q][1] = z[(int64_t)M.N + nd];
+    Zs[le][q][2] = z[2 * (int64_t)M.N + nd];
+  }
+  __syncthreads();
+  double ge = 0.0, ga = 0.0;
+  if (valid) {
+    const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+    double F[9], dF[9];
+    deformation_gradient(T, le, q, G, F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dF[i] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const double b0 = bgrad(q, 0, a, G), b1 = bgrad(q, 1, a, G), b2 = bgrad(q, 2, a, G);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double zi = Zs[le][a][i];
+        dF[3 * i + 0] += zi * b0;
+        dF[3 * i + 1] += zi * b1;
+        dF[3 * i + 2] += zi * b2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ge += dF[i] * (F[i] - cache[i * Q + qi]);
+    ge *= -M.Vq / (1.0 + M.nu);
+    if (M.muscle_k > 0.0) {
+      const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
+      const double d0 = dF[0] * m0 + dF[1] * m1 + dF[2] * m2;
+      const double d1 = dF[3] * m0 + dF[4] * m1 + dF[5] * m2;
+      const double d2 = dF[6] * m0 + dF[7] * m1 + dF[8] * m2;
+      ga = M.muscle_k * M.Vq *
+           (d0 * cache[15 * Q + qi] + d1 * cache[16 * Q + qi] + d2 * cache[17 * Q + qi]);
+    }
+    red[le][q][0] = ge;
+    red[le][q][1] = ga;
+  }
+  __syncthreads();
+  if (valid && q == 0) {
+    double se = 0.0, sa = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      se += red[le][k][0];
+      sa += red[le][k][1];
+    }
+    if (g_youngs) g_youngs[e] += se;
+    if (g_act) g_act[e] = sa;
+  }
+}
+
+// out = a x + b y over 3N entries (y may be null: out = a x)
+__global__ void __launch_bounds__(kBlock) k_lincomb(int64_t n, double* __restrict__ out, double a,
+                                                    const double* __restrict__ x, double b,
+                                                    const double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(int64_t n, double* __restrict__ out, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+void launch_lincomb(hipStream_t s, int64_t n, double* out, double a, const double* x, double b,
+                    const double* y) {
+  hipLaunchKernelGGL(k_lincomb, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, out, a, x, b, y);
+}
+
+void launch_fill(hipStream_t s, int64_t n, double* out, double v) {
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, out, v);
+}
+
+void launch_reset(hipStream_t s, IterState* st, double tolsq) {
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st, tolsq);
+}
+
+void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
+                     double* xn, IterState* st, double* partials, double abs_tol_rel) {
+  hipLaunchKernelGGL(k_prologue, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x, v, y, xn, st,
+                     partials, abs_tol_rel);
+}
+
+void launch_elem_forces(const DevMesh& M, hipStream_t s, const double* x, const double* act,
+                        double* fe, double* R_out, IterState* st) {
+  const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
+  hipLaunchKernelGGL(k_elem_forces, dim3(nb), dim3(kBlock), 0, s, M, x, act, fe, R_out, st);
+}
+
+void launch_node_residual(const DevMesh& M, hipStream_t s, const double* x, const double* y,
+                          const double* fe, double* r, IterState* st, double* partials, int k,
+                          int max_iter, int fixed_iters) {
+  hipLaunchKernelGGL(k_node_residual, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x, y, fe, r, st,
+                     partials, k, max_iter, fixed_iters);
+}
+
+void launch_velocity(const DevMesh& M, hipStream_t s, const double* x, const double* xn, double* vn) {
+  hipLaunchKernelGGL(k_velocity, dim3(blocks_for(3 * (int64_t)M.N)), dim3(kBlock), 0, s, M.N,
+                     1.0 / M.h, x, xn, vn);
+}
+
+void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v) {
+  hipLaunchKernelGGL(k_zero_fixed, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, v);
+}
+
+void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                      int lds_cols, bool fp32, const double* b, int N, const IterState* st) {
+  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32,
+                       b, N, st);
+  else
+    hipLaunchKernelGGL(k_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+                       S.panel64, b, N, st);
+}
+
+void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                      int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
+                      int accumulate, const IterState* st) {
+  const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
+  if (fp32) {
+    if (use_lds)
+      hipLaunchKernelGGL((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+                         S.panel32, out, N, alpha, accumulate, st);
+    else
+      hipLaunchKernelGGL((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
+                         S.panel32, out, N, alpha, accumulate, st);
+  } else {
+    if (use_lds)
+      hipLaunchKernelGGL((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+                         S.panel64, out, N, alpha, accumulate, st);
+    else
+      hipLaunchKernelGGL((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
+                         S.panel64, out, N, alpha, accumulate, st);
+  }
+}
+
+void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
+                      double* cache, IterState* st) {
+  const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
+  hipLaunchKernelGGL(k_adj_cache, dim3(nb), dim3(kBlock), 0, s, M, x, act, cache, st);
+}
+
+void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
+                     double* fe, const IterState* st) {
+  const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
+  hipLaunchKernelGGL(k_elem_hvp, dim3(nb), dim3(kBlock), 0, s, M, p, cache, fe, st);
+}
+
+void launch_node_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* fe,
+                     const double* xk, const double* rhs, double* out, IterState* st,
+                     double* partials, int mode, int k, int max_iter) {
+  hipLaunchKernelGGL(k_node_hvp, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, p, fe, xk, rhs, out,
+                     st, partials, mode, k, max_iter);
+}
+
+void launch_dot(const DevMesh& M, hipStream_t s, const double* a, const double* b, IterState* st,
+                double* partials, int what) {
+  hipLaunchKernelGGL(k_dot, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, a, b, st, partials, what);
+}
+
+void launch_cg_update(const DevMesh& M, hipStream_t s, double* z, double* r, const double* p,
+                      const double* q, IterState* st, double* partials, int k, int max_iter) {
+  hipLaunchKernelGGL(k_cg_update, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, z, r, p, q, st,
+                     partials, k, max_iter);
+}
+
+void launch_cg_direction(const DevMesh& M, hipStream_t s, double* p, const double* sv,
+                         const IterState* st) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, p, sv, st);
+}
+
+void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
+                         const double* z, const double* gv_next, double* gx, double* gv) {
+  hipLaunchKernelGGL(k_adj_epilogue, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x, v, z, gv_next,
+                     gx, gv);
+}
+
+void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
+                        const double* cache, double* g_youngs, double* g_act) {
+  const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
+  hipLaunchKernelGGL(k_grad_params, dim3(nb), dim3(kBlock), 0, s, M, xn, z, cache, g_youngs, g_act);
+}
+
+}  // namespace dpd

@@ -1,0 +1,231 @@
+"""Python handle of a simulated voxel body on the GPU.
+
+Thin marshalling over the C ABI: tensors provide device memory and the
+current HIP stream; every computation happens in libdiffpd's kernels.
+State tensors are float64 with shape [3, N] (SoA, public node order).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import warnings
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PHYSICS_KEYS = ("dx", "rho", "nu", "h", "contact_k", "friction_mu", "friction_eps", "muscle_k")
+
+
+def make_options(physics: Optional[dict] = None, **iteration) -> L.Options:
+    lib = L.load()
+    o = L.Options()
+    L.check(lib.dpd_default_options(C.byref(o)))
+    physics = physics or {}
+    for k in PHYSICS_KEYS:
+        if k in physics:
+            setattr(o, k, float(physics[k]))
+    for k in ("gravity", "origin", "fiber"):
+        if k in physics:
+            arr = getattr(o, k)
+            for i, val in enumerate(physics[k]):
+                arr[i] = float(val)
+    for k, val in iteration.items():
+        if k == "precision" and isinstance(val, str):
+            val = {"fp64": L.DPD_FP64, "mixed": L.DPD_MIXED}[val]
+        if k == "bwd_solver" and isinstance(val, str):
+            val = {"fixed_point": L.DPD_BWD_FIXED_POINT, "pcg": L.DPD_BWD_PCG}[val]
+        setattr(o, k, val)
+    return o
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Mesh:
+    """A voxel body: mesh, factor and workspaces live in the library handle."""
+
+    def __init__(self, cells, youngs, fixed_nodes=None, physics: Optional[dict] = None,
+                 device="cuda:0", factorize=True, **iteration):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+        youngs = np.ascontiguousarray(np.asarray(youngs, dtype=np.float64).reshape(-1))
+        fixed = (np.zeros((0, 3), np.int32) if fixed_nodes is None
+                 else np.ascontiguousarray(np.asarray(fixed_nodes, dtype=np.int32).reshape(-1, 3)))
+        self.options = make_options(physics, **iteration)
+        self.physics = dict(physics or {})
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_create_mesh(
+                cells.ctypes.data_as(L._I32), cells.shape[0],
+                youngs.ctypes.data_as(L._D),
+                fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
+                C.byref(self.options), C.byref(h)))
+        self.handle = h
+        info = L.MeshInfo()
+        L.check(self.lib.dpd_get_info(self.handle, C.byref(info)), self.handle)
+        self.info = {k: getattr(info, k) for k, _ in info._fields_}
+        self.n_nodes = info.n_nodes
+        self.n_elements = info.n_elements
+        self.youngs = youngs.copy()
+        if factorize:
+            self.factorize()
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda:0", **iteration):
+        return cls(scene.cells, scene.youngs, scene.fixed_nodes, scene.physics(), device=device,
+                   **iteration)
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.dpd_destroy_mesh(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ setup
+    def factorize(self):
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_factorize(self.handle, _stream(self.device)), self.handle)
+
+    def set_options(self, **iteration):
+        for k, val in iteration.items():
+            if k == "precision" and isinstance(val, str):
+                val = {"fp64": L.DPD_FP64, "mixed": L.DPD_MIXED}[val]
+            if k == "bwd_solver" and isinstance(val, str):
+                val = {"fixed_point": L.DPD_BWD_FIXED_POINT, "pcg": L.DPD_BWD_PCG}[val]
+            setattr(self.options, k, val)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_set_options(self.handle, C.byref(self.options)), self.handle)
+
+    def set_youngs(self, youngs, refactorize=True):
+        ym = np.ascontiguousarray(np.asarray(youngs, dtype=np.float64).reshape(-1))
+        L.check(self.lib.dpd_set_youngs(self.handle, ym.ctypes.data_as(C.c_void_p), 0, None),
+                self.handle)
+        self.youngs = ym.copy()
+        if refactorize:
+            self.factorize()
+
+    def node_ijk(self) -> np.ndarray:
+        out = np.zeros((self.n_nodes, 3), np.int32)
+        L.check(self.lib.dpd_node_ijk(self.handle, out.ctypes.data_as(L._I32)), self.handle)
+        return out
+
+    def rest_positions(self) -> torch.Tensor:
+        out = np.zeros((3, self.n_nodes), np.float64)
+        L.check(self.lib.dpd_rest_positions(self.handle, out.ctypes.data_as(L._D)), self.handle)
+        return torch.from_numpy(out).to(self.device)
+
+    def contact_nodes(self) -> np.ndarray:
+        out = np.zeros(max(1, self.info["n_contact"]), np.int32)
+        L.check(self.lib.dpd_contact_nodes(self.handle, out.ctypes.data_as(L._I32)), self.handle)
+        return out[: self.info["n_contact"]]
+
+    def zeros_state(self) -> torch.Tensor:
+        return torch.zeros(3, self.n_nodes, dtype=torch.float64, device=self.device)
+
+    def _check_state(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if (t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous()
+                    or tuple(t.shape) != (3, self.n_nodes)):
+                raise ValueError(f"expected contiguous float64 [3, {self.n_nodes}] on {self.device}")
+
+    def _check_elem(self, t):
+        if t is None:
+            return
+        if (t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous()
+                or t.numel() != self.n_elements):
+            raise ValueError(f"expected contiguous float64 [{self.n_elements}] on {self.device}")
+
+    # ------------------------------------------------------------------ steps
+    def forward_step(self, x, v, act=None, out=None, strict=False):
+        """One implicit-Euler PD step.  Returns (x_next, v_next, stats dict)."""
+        self._check_state(x, v)
+        self._check_elem(act)
+        xn, vn = out if out is not None else (torch.empty_like(x), torch.empty_like(v))
+        st = L.Stats()
+        with torch.cuda.device(self.device):
+            code = L.check(self.lib.dpd_forward_step(self.handle, _stream(self.device), _ptr(x),
+                                                     _ptr(v), _ptr(act), _ptr(xn), _ptr(vn),
+                                                     C.byref(st)), self.handle)
+        stats = st.as_dict()
+        if code == L.DPD_NOT_CONVERGED:
+            if strict:
+                raise L.DiffPDError(code, f"forward step not converged: {stats}")
+            warnings.warn(f"forward PD step not converged: {stats}", RuntimeWarning, stacklevel=2)
+        return xn, vn, stats
+
+    def backward_step(self, x, v, act, x_next, gx_next, gv_next, g_youngs=None, want_act=False,
+                      strict=False):
+        """Adjoint of one step.  Returns (gx, gv, g_act or None, stats dict).
+
+        ``g_youngs`` (float64 [E] on the device) is accumulated in place."""
+        self._check_state(x, v, x_next, gx_next, gv_next)
+        self._check_elem(act)
+        self._check_elem(g_youngs)
+        gx = torch.empty_like(gx_next)
+        gv = torch.empty_like(gv_next)
+        g_act = (torch.empty(self.n_elements, dtype=torch.float64, device=self.device)
+                 if want_act else None)
+        st = L.Stats()
+        with torch.cuda.device(self.device):
+            code = L.check(self.lib.dpd_backward_step(
+                self.handle, _stream(self.device), _ptr(x), _ptr(v), _ptr(act), _ptr(x_next),
+                _ptr(gx_next), _ptr(gv_next), _ptr(gx), _ptr(gv), _ptr(g_youngs), _ptr(g_act),
+                C.byref(st)), self.handle)
+        stats = st.as_dict()
+        if code == L.DPD_NOT_CONVERGED:
+            if strict:
+                raise L.DiffPDError(code, f"adjoint not converged: {stats}")
+            warnings.warn(f"adjoint iteration not converged: {stats}", RuntimeWarning, stacklevel=2)
+        return gx, gv, g_act, stats
+
+    # ------------------------------------------------------------------ building blocks
+    def apply_inverse(self, b, precision="fp64"):
+        self._check_state(b)
+        out = torch.empty_like(b)
+        prec = {"fp64": L.DPD_FP64, "mixed": L.DPD_MIXED}[precision]
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_apply_inverse(self.handle, _stream(self.device), prec, _ptr(b),
+                                               _ptr(out)), self.handle)
+        return out
+
+    def gradient(self, x, y, act=None):
+        self._check_state(x, y)
+        out = torch.empty_like(x)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_gradient(self.handle, _stream(self.device), _ptr(x), _ptr(y),
+                                          _ptr(act), _ptr(out)), self.handle)
+        return out
+
+    def hessian_apply(self, x, p, act=None):
+        self._check_state(x, p)
+        out = torch.empty_like(p)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_hessian_apply(self.handle, _stream(self.device), _ptr(x),
+                                               _ptr(act), _ptr(p), _ptr(out)), self.handle)
+        return out
+
+    def rotations(self, x):
+        self._check_state(x)
+        out = torch.empty(9, 8 * self.n_elements, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_rotations(self.handle, _stream(self.device), _ptr(x), _ptr(out)),
+                    self.handle)
+        return out

@@ -1,0 +1,145 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import forward as of, adjoint as oa, projections as op
+from parity_helpers import soa, to_dev, elem_dev, pair, rel, robot_scene, ragged_scene
+
+pytestmark = pytest.mark.gpu
+
+SCENES = {
+    "c1": lambda: W.config("c1"),
+    "c2": lambda: W.config("c2"),
+    "robot": robot_scene,
+    "ragged": ragged_scene,
+}
+
+
+def converged_state(o, x, v, act=None):
+    """The implicit-Euler solution for the start state: Newton on g to round-off."""
+    xr, info = of.newton_solve(o, o.y_of(x, v), act)
+    return xr
+
+
+def _perturbed(o, scale=2e-3, seed=0):
+    rng = np.random.default_rng(seed)
+    x = o.X + scale * rng.standard_normal(3 * o.N)
+    x[o.fixed] = o.X[o.fixed]
+    v = 0.05 * rng.standard_normal(3 * o.N)
+    v[o.fixed] = 0.0
+    return x, v
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_mesh_numbering_and_rest_positions(name):
+    sc = SCENES[name]()
+    g, o = pair(sc)
+    print(name, g.info, flush=True)
+    assert np.array_equal(g.node_ijk(), o.mesh.node_ijk)
+    assert np.abs(soa(g.rest_positions()) - o.X).max() == 0.0
+    if len(o.contact_nodes):
+        assert np.array_equal(np.sort(g.contact_nodes()), o.contact_nodes)
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_apply_inverse(name):
+    sc = SCENES[name]()
+    g, o = pair(sc)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(3 * o.N)
+    x = soa(g.apply_inverse(to_dev(b, o.N)))
+    ref = np.zeros(3 * o.N)
+    ref[o.free] = o.solve_A(b[o.free])
+    assert rel(x, ref) <= 1e-12
+    assert np.all(x[o.fixed] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["c1", "robot", "ragged"])
+def test_rotations(name):
+    sc = SCENES[name]()
+    g, o = pair(sc)
+    x, _ = _perturbed(o, scale=3e-3)
+    R = g.rotations(to_dev(x, o.N)).cpu().numpy()          # [9, Q]
+    Rref = op.closest_rotation(o.deformation_gradients(x)).reshape(o.Q, 9).T
+    assert np.abs(R - Rref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_gradient_and_hessian(name):
+    sc = SCENES[name]()
+    g, o = pair(sc)
+    x, v = _perturbed(o, seed=2)
+    y = o.y_of(x, v)
+    act = None
+    if o.Gm is not None:
+        act = np.random.default_rng(3).uniform(0, 1, o.E)
+    a_dev = None if act is None else elem_dev(act)
+    r = soa(g.gradient(to_dev(x, o.N), to_dev(y, o.N), a_dev))
+    ref = o.grad_g(x, y, act)
+    ref[o.fixed] = 0.0
+    assert rel(r, ref) <= 1e-11
+    p = np.random.default_rng(4).standard_normal(3 * o.N)
+    p[o.fixed] = 0.0
+    hp = soa(g.hessian_apply(to_dev(x, o.N), to_dev(p, o.N), a_dev))
+    ref = o.hessian(x, act) @ p
+    ref[o.fixed] = 0.0
+    assert rel(hp, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged"])
+def test_forward_fixed_iterations(name):
+    """Same algorithm, same number of global solves (100)."""
+    sc = SCENES[name]()
+    g, o = pair(sc, fwd_max_iter=100, fwd_fixed_iters=1)
+    x, v = _perturbed(o, seed=5)
+    xn, vn, st = g.forward_step(to_dev(x, o.N), to_dev(v, o.N))
+    assert st["fwd_iters"] == 100
+    xr, vr, info = of.pd_step(o, x, v, max_iter=100, fixed_iters=True)
+    assert info["iters"] == 100
+    assert rel(soa(xn), xr) <= 1e-12
+    assert np.linalg.norm(soa(xn) - xr) <= 1e-9 * np.linalg.norm(xr - x)
+    assert rel(soa(vn), vr) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "robot"])
+def test_forward_converged(name):
+    sc = SCENES[name]()
+    g, o = pair(sc, fwd_max_iter=100000, fwd_rel_tol=1e-13, check_every=64)
+    x, v = o.X.copy(), np.zeros(3 * o.N)
+    act = None
+    if o.Gm is not None:
+        act = np.random.default_rng(6).uniform(0, 1, o.E)
+        v[0::3] = 0.05
+    xn, vn, st = g.forward_step(to_dev(x, o.N), to_dev(v, o.N),
+                                None if act is None else elem_dev(act))
+    print(name, st, flush=True)
+    assert st["converged"] == 1
+    xr = converged_state(o, x, v, act)
+    assert np.linalg.norm(soa(xn) - xr) <= 1e-9 * np.linalg.norm(xr - x)
+
+
+@pytest.mark.parametrize("solver", ["pcg", "fixed_point"])
+@pytest.mark.parametrize("name", ["c1", "robot", "ragged"])
+def test_backward_step(name, solver):
+    sc = SCENES[name]()
+    g, o = pair(sc, bwd_solver=solver, bwd_max_iter=100000, bwd_rel_tol=1e-13, check_every=64)
+    x, v = _perturbed(o, seed=7)
+    act = None if o.Gm is None else np.random.default_rng(8).uniform(0, 1, o.E)
+    a_dev = None if act is None else elem_dev(act)
+    xr = converged_state(o, x, v, act)
+    rng = np.random.default_rng(9)
+    gxn, gvn = rng.standard_normal(3 * o.N), rng.standard_normal(3 * o.N)
+    gE = torch.zeros(o.E, dtype=torch.float64, device="cuda:0")
+    gx, gv, ga, st = g.backward_step(to_dev(x, o.N), to_dev(v, o.N), a_dev, to_dev(xr, o.N),
+                                     to_dev(gxn, o.N), to_dev(gvn, o.N), g_youngs=gE,
+                                     want_act=act is not None)
+    print(name, solver, st, flush=True)
+    assert st["converged"] == 1
+    rx, rv, rE, ra, _ = oa.backward_step(o, x, v, act, xr, gxn, gvn, solver="direct")
+    assert rel(soa(gx), rx) <= 1e-8
+    assert rel(soa(gv), rv) <= 1e-8
+    assert rel(gE.cpu().numpy(), rE) <= 1e-8
+    if act is not None:
+        assert rel(ga.cpu().numpy(), ra) <= 1e-8
