@@ -1,0 +1,167 @@
+"""Benchmark: DoF-steps/s of the PD forward step plus its adjoint on one MI355X.
+
+One benchmark step is one whole rollout of the workload: T implicit-Euler
+steps forward (PD local projections + global solves with the factor of A)
+followed by T adjoint steps back to the initial state, giving dL/dx0, dL/dv0
+and dL/dE for L = c . x_T (c ~ N(0, 1), seed 0).  Inputs are synthetic and
+already resident in HBM when timing starts; the factorization is done before
+the timed region (once per material, as in the method).
+
+The default workload is the 16x8x8-cell cantilever with log-uniform
+per-element Young's moduli (1377 nodes, 100 steps).  The gradient of the
+timed rollout is compared with the oracle's stored reference
+(tests/golden/<name>_rollout_reference.npz) and the relative error reported.
+
+  python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+import workloads as W  # noqa: E402
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed rollouts")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--fwd-solver", default="newton_pcg", choices=["newton_pcg", "pd"])
+    ap.add_argument("--bwd-solver", default="pcg", choices=["pcg", "fixed_point"])
+    ap.add_argument("--fwd-tol", type=float, default=1e-10)
+    ap.add_argument("--bwd-tol", type=float, default=1e-10)
+    ap.add_argument("--rollout-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def rollout(mesh, X, c_dev, T, torch):
+    """Forward T steps, then the adjoint back to step 0.  Returns gradients."""
+    x = X.clone()
+    v = torch.zeros_like(X)
+    xs, vs = [x], [v]
+    fwd_iters = bwd_iters = 0
+    for _ in range(T):
+        x, v, st = mesh.forward_step(x, v)
+        xs.append(x)
+        vs.append(v)
+        fwd_iters += st["fwd_iters"]
+    gx, gv = c_dev.clone(), torch.zeros_like(X)
+    gE = torch.zeros(mesh.n_elements, dtype=torch.float64, device=X.device)
+    for t in range(T - 1, -1, -1):
+        gx, gv, _, st = mesh.backward_step(xs[t], vs[t], None, xs[t + 1], gx, gv, g_youngs=gE)
+        bwd_iters += st["bwd_iters"]
+    return xs[-1], gx, gv, gE, fwd_iters, bwd_iters
+
+
+def cpu_baseline(scene, T_budget_s):
+    """The oracle on the host: Newton (sparse LU) forward + direct adjoint, a
+    prefix of the rollout bounded to about ``T_budget_s`` seconds."""
+    import threadpoolctl  # noqa: F401  (present in the image)
+    from oracle import model as om, forward as of, adjoint as oa
+    m = om.Model(scene)
+    x, v = m.X.copy(), np.zeros(3 * m.N)
+    t0 = time.perf_counter()
+    xs, vs = [x], [v]
+    steps = 0
+    while True:
+        xn, _ = of.newton_solve(m, m.y_of(x, v))
+        vn = (xn - x) / m.h
+        xs.append(xn)
+        vs.append(vn)
+        x, v = xn, vn
+        steps += 1
+        if time.perf_counter() - t0 > 0.8 * T_budget_s or steps >= scene.steps:
+            break
+    c = W.loss_vector(m.N, scene.loss_seed)
+    gx, gv = c.copy(), np.zeros(3 * m.N)
+    for t in range(steps - 1, -1, -1):
+        gx, gv, _, _, _ = oa.backward_step(m, xs[t], vs[t], None, xs[t + 1], gx, gv, solver="direct")
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {"value": 3 * m.N * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {steps} of {scene.steps} steps, Newton (sparse LU) forward + direct "
+                      f"adjoint, {dt:.1f} s wall, numpy/scipy on {cores} host cores"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the workload does not shard across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2101_05917_amd.mesh import Mesh
+
+    scene = W.config(args.config)
+    T = args.rollout_steps or scene.steps
+    mesh = Mesh.from_scene(scene, fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol,
+                           fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
+                           bwd_max_iter=200000, precision=args.precision, check_every=16)
+    X = mesh.rest_positions()
+    N = mesh.n_nodes
+    c = W.loss_vector(N, scene.loss_seed)
+    c_dev = torch.from_numpy(np.ascontiguousarray(c.reshape(N, 3).T)).to(X.device)
+
+    for _ in range(args.warmup):
+        rollout(mesh, X, c_dev, T, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xT, gx, gv, gE, fi, bi = rollout(mesh, X, c_dev, T, torch)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    value = 3 * N * T / dt
+
+    # accuracy against the oracle's reference gradient
+    err = None
+    ref_path = os.path.join(HERE, "tests", "golden", f"{args.config}_rollout_reference.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        if int(ref["steps"]) == T:
+            gx_np = gx.cpu().numpy().T.reshape(-1)
+            gE_np = gE.cpu().numpy()
+            err = {"g_x0": float(np.linalg.norm(gx_np - ref["g_x0"]) / np.linalg.norm(ref["g_x0"])),
+                   "g_youngs": float(np.linalg.norm(gE_np - ref["g_youngs"]) /
+                                     np.linalg.norm(ref["g_youngs"]))}
+
+    out = {
+        "metric": "DoF-steps/s fwd+adjoint at 1e-6 rel grad error",
+        "value": value,
+        "unit": "DoF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{scene.name}: {len(scene.cells)} hex, {N} nodes, {3 * N} DoFs, "
+                               f"{T} steps fwd+adjoint, loss dot(N(0,1) seed 0, x_T)",
+                   "fwd_solver": args.fwd_solver, "bwd_solver": args.bwd_solver,
+                   "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol},
+        "fwd_iters_per_step": fi / T,
+        "bwd_iters_per_step": bi / T,
+        "grad_rel_err_vs_oracle": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -56,6 +56,11 @@ typedef enum {
 enum { DPD_FP64 = 0, DPD_MIXED = 1 };
 /* Adjoint solver.                                                          */
 enum { DPD_BWD_FIXED_POINT = 0, DPD_BWD_PCG = 1 };
+/* Forward solver: Alg. 1 (local/global PD), or Newton steps whose linear
+ * systems (A - dA) d = -grad g are solved by conjugate gradients
+ * preconditioned with the same factor of A.  Both stop on the same test and
+ * converge to the same implicit-Euler state.                                */
+enum { DPD_FWD_PD = 0, DPD_FWD_NEWTON_PCG = 1 };
 
 typedef struct {
   /* physics (SI units) */
@@ -75,6 +80,9 @@ typedef struct {
   int32_t fwd_fixed_iters; /* 1: perform exactly fwd_max_iter solves              */
   double fwd_rel_tol;      /* stop when |grad g| <= tol |grad g(x^0)|            */
   double fwd_abs_tol_rel;  /* ... or |grad g| <= this * |M y / h^2| (free DoFs)   */
+  int32_t fwd_solver;      /* DPD_FWD_PD or DPD_FWD_NEWTON_PCG                     */
+  int32_t fwd_inner_max_iter; /* CG iterations per Newton step                    */
+  double fwd_inner_tol;    /* CG relative tolerance per Newton step               */
   /* backward iteration (Alg. 2 or CG) */
   int32_t bwd_max_iter;
   int32_t bwd_solver;      /* DPD_BWD_FIXED_POINT or DPD_BWD_PCG                   */
@@ -85,11 +93,11 @@ typedef struct {
 
 typedef struct {
   int32_t fwd_iters;       /* global solves performed in the last forward step   */
+  int32_t fwd_outer;       /* Newton steps (DPD_FWD_NEWTON_PCG), else fwd_iters   */
   int32_t bwd_iters;       /* adjoint iterations in the last backward step       */
   int32_t converged;       /* 1 if the last call met its tolerance                */
   int32_t fallbacks;       /* CG -> fixed-point fallbacks in the last backward    */
   int32_t inverted_qps;    /* quadrature points with det F <= 0 (last local pass) */
-  int32_t reserved;
   double fwd_rel_res;      /* final |grad g| / |grad g(x^0)|                      */
   double bwd_rel_res;      /* final |xbar - H z| / |xbar|                          */
   double ms_total;         /* wall time of the call when stats were requested     */
@@ -104,7 +112,8 @@ typedef struct {
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
- * no contact, friction or muscles, fwd 100 iterations / 1e-10 / 1e-12,
+ * no contact, friction or muscles, fwd PD 100 iterations / 1e-10 / 1e-12
+ * (Newton-CG inner loop: 200 iterations / 1e-2),
  * bwd CG 5000 iterations / 1e-10, FP64, check_every 8. */
 dpd_status dpd_default_options(dpd_options* opt);
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdiffpd.so")
 DPD_OK, DPD_NOT_CONVERGED = 0, 1
 DPD_FP64, DPD_MIXED = 0, 1
 DPD_BWD_FIXED_POINT, DPD_BWD_PCG = 0, 1
+DPD_FWD_PD, DPD_FWD_NEWTON_PCG = 0, 1
 
 STATUS_NAMES = {0: "DPD_OK", 1: "DPD_NOT_CONVERGED", -1: "DPD_EINVAL", -2: "DPD_ENOTSPD",
                 -3: "DPD_ENOMEM", -4: "DPD_EHIP", -5: "DPD_ESTATE", -6: "DPD_ENONFINITE",
@@ -29,6 +30,7 @@ class Options(C.Structure):
         ("muscle_k", C.c_double), ("fiber", C.c_double * 3),
         ("fwd_max_iter", C.c_int32), ("fwd_fixed_iters", C.c_int32),
         ("fwd_rel_tol", C.c_double), ("fwd_abs_tol_rel", C.c_double),
+        ("fwd_solver", C.c_int32), ("fwd_inner_max_iter", C.c_int32), ("fwd_inner_tol", C.c_double),
         ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
         ("precision", C.c_int32), ("check_every", C.c_int32),
     ]
@@ -36,13 +38,13 @@ class Options(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [
-        ("fwd_iters", C.c_int32), ("bwd_iters", C.c_int32), ("converged", C.c_int32),
-        ("fallbacks", C.c_int32), ("inverted_qps", C.c_int32), ("reserved", C.c_int32),
+        ("fwd_iters", C.c_int32), ("fwd_outer", C.c_int32), ("bwd_iters", C.c_int32),
+        ("converged", C.c_int32), ("fallbacks", C.c_int32), ("inverted_qps", C.c_int32),
         ("fwd_rel_res", C.c_double), ("bwd_rel_res", C.c_double), ("ms_total", C.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class MeshInfo(C.Structure):

@@ -47,9 +47,9 @@ struct dpd_mesh {
   double* panel64 = nullptr;
   float* panel32 = nullptr;
   double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
-  double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr;
-  IterState* st = nullptr;
-  IterState* h_st = nullptr;  // pinned host mirror
+  double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
+  IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
+  IterState* h_st = nullptr;   // pinned host mirror [2]
 };
 
 namespace {
@@ -114,7 +114,7 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
 }
 
 dpd_status read_state(dpd_mesh* m, hipStream_t s) {
-  HIPCHECK(m, hipMemcpyAsync(m->h_st, m->st, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipMemcpyAsync(m->h_st, m->st, 2 * sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIPCHECK(m, hipStreamSynchronize(s));
   return DPD_OK;
 }
@@ -154,6 +154,11 @@ dpd_status check_ready(dpd_mesh* m) {
 
 }  // namespace
 
+namespace {
+dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs,
+                              double* z, const double* xk, bool fp32, int max_it, int check_every);
+}  // namespace
+
 extern "C" {
 
 dpd_status dpd_default_options(dpd_options* o) {
@@ -170,6 +175,9 @@ dpd_status dpd_default_options(dpd_options* o) {
   o->fwd_fixed_iters = 0;
   o->fwd_rel_tol = 1e-10;
   o->fwd_abs_tol_rel = 1e-12;
+  o->fwd_solver = DPD_FWD_PD;
+  o->fwd_inner_max_iter = 200;
+  o->fwd_inner_tol = 1e-2;
   o->bwd_max_iter = 5000;
   o->bwd_solver = DPD_BWD_PCG;
   o->bwd_rel_tol = 1e-10;
@@ -284,20 +292,21 @@ dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const doub
   AL(m->q, 3 * N);
   AL(m->s, 3 * N);
   AL(m->xbar, 3 * N);
-  AL(m->st, 1);
+  AL(m->cg_r, 3 * N);
+  AL(m->st, 2);
 #undef AL
-  if (hipHostMalloc((void**)&m->h_st, sizeof(IterState), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&m->h_st, 2 * sizeof(IterState), hipHostMallocDefault) != hipSuccess) {
     dpd_destroy_mesh(m);
     return fail(nullptr, DPD_ENOMEM, "pinned host allocation failed");
   }
-  std::memset(m->h_st, 0, sizeof(IterState));
+  std::memset(m->h_st, 0, 2 * sizeof(IterState));
   // zero the scratch vectors whose fixed-node rows are read
-  for (double* v : {m->z, m->p, m->q, m->s, m->xbar, m->r})
+  for (double* v : {m->z, m->p, m->q, m->s, m->xbar, m->r, m->cg_r})
     if (hipMemset(v, 0, 3 * N * sizeof(double)) != hipSuccess) {
       dpd_destroy_mesh(m);
       return fail(nullptr, DPD_EHIP, "hipMemset failed");
     }
-  if (hipMemset(m->st, 0, sizeof(IterState)) != hipSuccess) {
+  if (hipMemset(m->st, 0, 2 * sizeof(IterState)) != hipSuccess) {
     dpd_destroy_mesh(m);
     return fail(nullptr, DPD_EHIP, "hipMemset failed");
   }
@@ -435,7 +444,39 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
   const int max_it = std::max(0, o.fwd_max_iter);
   launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol);
   launch_prologue(m->dm, s, x, v, m->y, xn, m->st, m->partials, o.fwd_abs_tol_rel);
-  for (int k = 0;; ++k) {
+  int solves = -1, outer = 0;
+  if (o.fwd_solver == DPD_FWD_NEWTON_PCG && !o.fwd_fixed_iters) {
+    // Newton on g: (A - dA(x)) d = -grad g(x) by A-preconditioned CG to a
+    // relative tolerance; the same stopping test as Alg. 1 on grad g.
+    IterState* inner = m->st + 1;
+    const int64_t n3 = 3 * (int64_t)m->dm.N;
+    const int never = 0x3fffffff;
+    solves = 0;
+    launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, 0, never, 0);
+    for (outer = 0;; ++outer) {
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (m->h_st[0].done || solves >= max_it) break;
+      launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
+      launch_reset(s, inner, o.fwd_inner_tol * o.fwd_inner_tol);
+      launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
+      const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
+      if ((rc = conjugate_gradient(m, s, inner, m->xbar, m->z, xn, fp32, inner_max, o.check_every)) !=
+          DPD_OK)
+        return rc;
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      solves += 1 + std::max(0, m->h_st[1].iter);
+      if (m->h_st[1].curvature) {
+        // not a descent direction: take one plain PD step instead
+        solve(m, s, fp32, m->r, xn, -1.0, 1, nullptr);
+      } else {
+        launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
+      }
+      launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+      launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
+    }
+  }
+  for (int k = 0; solves < 0; ++k) {
     launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
     launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, k, max_it,
                          o.fwd_fixed_iters);
@@ -451,7 +492,8 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
   if ((rc = read_state(m, s)) != DPD_OK) return rc;
   const IterState& h = *m->h_st;
   if (stats) {
-    stats->fwd_iters = h.iter;
+    stats->fwd_iters = solves < 0 ? h.iter : solves;
+    stats->fwd_outer = solves < 0 ? h.iter : outer;
     stats->converged = h.converged;
     stats->inverted_qps = h.inverted;
     stats->fwd_rel_res = h.r0sq > 0 ? std::sqrt(h.rsq / h.r0sq) : 0.0;
@@ -481,27 +523,29 @@ dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, 
   return DPD_OK;
 }
 
-// Conjugate gradients on (A - dA) z = xbar preconditioned by A^{-1}.
-dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, int max_it) {
+// Conjugate gradients on (A - dA(xk)) z = rhs preconditioned by A^{-1}, from
+// z = 0, with its scalars in *st (stopping test |r| <= sqrt(st->tolsq) |rhs|).
+// Uses m->cg_r, p, q, s as work vectors; the cached rotations must be at xk.
+dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs,
+                              double* z, const double* xk, bool fp32, int max_it, int check_every) {
   dpd_status rc;
-  const dpd_options& o = m->opt;
   const int64_t n3 = 3 * (int64_t)m->dm.N;
-  launch_fill(s, n3, m->z, 0.0);
-  launch_lincomb(s, n3, m->r, 1.0, m->xbar, 0.0, nullptr);
-  launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
-  solve(m, s, fp32, m->r, m->s, 1.0, 0, nullptr);
-  launch_dot(m->dm, s, m->r, m->s, m->st, m->partials, 1);
+  launch_fill(s, n3, z, 0.0);
+  launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
+  launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
+  solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, nullptr);
+  launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 1);
   launch_lincomb(s, n3, m->p, 1.0, m->s, 0.0, nullptr);
   for (int k = 1; k <= max_it; ++k) {
-    launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, m->st);
-    launch_node_hvp(m->dm, s, m->p, m->fe, xn, nullptr, m->q, m->st, m->partials, 2, k, max_it);
-    launch_cg_update(m->dm, s, m->z, m->r, m->p, m->q, m->st, m->partials, k, max_it);
-    solve(m, s, fp32, m->r, m->s, 1.0, 0, m->st);
-    launch_dot(m->dm, s, m->r, m->s, m->st, m->partials, 2);
-    launch_cg_direction(m->dm, s, m->p, m->s, m->st);
-    if (k % o.check_every == 0) {
+    launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, st);
+    launch_node_hvp(m->dm, s, m->p, m->fe, xk, nullptr, m->q, st, m->partials, 2, k, max_it);
+    launch_cg_update(m->dm, s, z, m->cg_r, m->p, m->q, st, m->partials, k, max_it);
+    solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st);
+    launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 2);
+    launch_cg_direction(m->dm, s, m->p, m->s, st);
+    if (k % check_every == 0) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      if (m->h_st->done) break;
+      if (st == m->st ? m->h_st[0].done : m->h_st[1].done) break;
     }
   }
   return DPD_OK;
@@ -533,7 +577,9 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
   int fallbacks = 0;
   if (o.bwd_solver == DPD_BWD_PCG) {
-    if ((rc = conjugate_gradient(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+    if ((rc = conjugate_gradient(m, s, m->st, m->xbar, m->z, xn, fp32, max_it, o.check_every)) !=
+        DPD_OK)
+      return rc;
     if ((rc = read_state(m, s)) != DPD_OK) return rc;
     if (m->h_st->curvature) {
       // the paper's safeguard when the quasi-Newton step is not a descent:

@@ -970,9 +970,9 @@ __global__ void __launch_bounds__(kBlock) k_grad_params(DevMesh M, const double*
 }
 
 // out = a x + b y over 3N entries (y may be null: out = a x)
-__global__ void __launch_bounds__(kBlock) k_lincomb(int64_t n, double* __restrict__ out, double a,
-                                                    const double* __restrict__ x, double b,
-                                                    const double* __restrict__ y) {
+__global__ void __launch_bounds__(kBlock) k_lincomb(int64_t n, double* out, double a,
+                                                    const double* x, double b,
+                                                    const double* y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }

@@ -36,6 +36,8 @@ def make_options(physics: Optional[dict] = None, **iteration) -> L.Options:
             val = {"fp64": L.DPD_FP64, "mixed": L.DPD_MIXED}[val]
         if k == "bwd_solver" and isinstance(val, str):
             val = {"fixed_point": L.DPD_BWD_FIXED_POINT, "pcg": L.DPD_BWD_PCG}[val]
+        if k == "fwd_solver" and isinstance(val, str):
+            val = {"pd": L.DPD_FWD_PD, "newton_pcg": L.DPD_FWD_NEWTON_PCG}[val]
         setattr(o, k, val)
     return o
 
@@ -108,6 +110,8 @@ class Mesh:
                 val = {"fp64": L.DPD_FP64, "mixed": L.DPD_MIXED}[val]
             if k == "bwd_solver" and isinstance(val, str):
                 val = {"fixed_point": L.DPD_BWD_FIXED_POINT, "pcg": L.DPD_BWD_PCG}[val]
+            if k == "fwd_solver" and isinstance(val, str):
+                val = {"pd": L.DPD_FWD_PD, "newton_pcg": L.DPD_FWD_NEWTON_PCG}[val]
             setattr(self.options, k, val)
         with torch.cuda.device(self.device):
             L.check(self.lib.dpd_set_options(self.handle, C.byref(self.options)), self.handle)

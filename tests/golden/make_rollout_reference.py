@@ -1,0 +1,52 @@
+"""Write the oracle's reference rollout gradient of a benchmark scene.
+
+Calls only the oracle: each forward step is solved to round-off by Newton's
+method on g (the implicit-Euler solution, eq:time_integration), each backward
+step by a direct solve of the adjoint system (eq:adjoint).  The loss is
+dot(c, x_T) with c ~ N(0, 1) (seed 0), node-major.
+
+usage: python tests/golden/make_rollout_reference.py c2 [steps]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import model as om, forward as of, adjoint as oa  # noqa: E402
+
+
+def main():
+    name = sys.argv[1]
+    sc = W.config(name)
+    steps = int(sys.argv[2]) if len(sys.argv) > 2 else sc.steps
+    m = om.Model(sc)
+    x, v = m.X.copy(), np.zeros(3 * m.N)
+    xs, vs = [x], [v]
+    t0 = time.time()
+    for t in range(steps):
+        xn, info = of.newton_solve(m, m.y_of(x, v))
+        vn = (xn - x) / m.h
+        xs.append(xn)
+        vs.append(vn)
+        x, v = xn, vn
+        print(f"forward {t} newton iters {info['iters']} |grad| {info['grad']:.2e} "
+              f"{time.time() - t0:.0f}s", flush=True)
+    c = W.loss_vector(m.N, sc.loss_seed)
+    gx, gv = c.copy(), np.zeros(3 * m.N)
+    gE = np.zeros(m.E)
+    for t in range(steps - 1, -1, -1):
+        gx, gv, ge, _, _ = oa.backward_step(m, xs[t], vs[t], None, xs[t + 1], gx, gv, solver="direct")
+        gE += ge
+    out = os.path.join(HERE, f"{name}_rollout_reference.npz")
+    np.savez_compressed(out, steps=steps, loss=float(c @ xs[-1]), x_T=xs[-1], g_x0=gx, g_v0=gv,
+                        g_youngs=gE)
+    print("wrote", out, f"{time.time() - t0:.0f}s")
+
+
+if __name__ == "__main__":
+    main()

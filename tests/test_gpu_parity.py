@@ -103,10 +103,11 @@ def test_forward_fixed_iterations(name):
     assert rel(soa(vn), vr) <= 1e-9
 
 
+@pytest.mark.parametrize("solver", ["pd", "newton_pcg"])
 @pytest.mark.parametrize("name", ["c1", "c2", "robot"])
-def test_forward_converged(name):
+def test_forward_converged(name, solver):
     sc = SCENES[name]()
-    g, o = pair(sc, fwd_max_iter=100000, fwd_rel_tol=1e-13, check_every=64)
+    g, o = pair(sc, fwd_solver=solver, fwd_max_iter=100000, fwd_rel_tol=1e-13, check_every=64)
     x, v = o.X.copy(), np.zeros(3 * o.N)
     act = None
     if o.Gm is not None:
