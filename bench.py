@@ -30,6 +30,12 @@ sys.path.insert(0, HERE)
 import workloads as W  # noqa: E402
 
 
+KERNEL_NAMES = {"sweep_fwd": "k_sweep_fwd (forward triangular sweep, one tree level per launch)",
+                "sweep_bwd": "k_sweep_bwd (backward triangular sweep, one tree level per launch)",
+                "elem_hvp": "k_elem_hvp (adjoint local step dA p)",
+                "elem_forces": "k_elem_forces (forward local step)"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,11 +45,13 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--fwd-solver", default="newton_pcg", choices=["newton_pcg", "pd"])
     ap.add_argument("--bwd-solver", default="pcg", choices=["pcg", "fixed_point"])
-    ap.add_argument("--fwd-tol", type=float, default=1e-10)
-    ap.add_argument("--bwd-tol", type=float, default=1e-10)
+    ap.add_argument("--fwd-tol", type=float, default=1e-7)
+    ap.add_argument("--bwd-tol", type=float, default=1e-7)
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--roofline-kernel", default="sweep_fwd",
+                    choices=["sweep_fwd", "sweep_bwd", "elem_hvp", "elem_forces"])
     return ap.parse_args()
 
 
@@ -118,12 +126,22 @@ def main():
     for _ in range(args.warmup):
         rollout(mesh, X, c_dev, T, torch)
     torch.cuda.synchronize()
+    mesh.profile_start(args.roofline_kernel)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         xT, gx, gv, gE, fi, bi = rollout(mesh, X, c_dev, T, torch)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    prof = mesh.profile_read()
     value = 3 * N * T / dt
+    avg_ms = prof["total_ms"] / max(1, prof["launches"])
+    bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": achieved / 8000.0, "traffic": None,
+                "kernel": KERNEL_NAMES[args.roofline_kernel],
+                "launches": prof["launches"], "avg_us": avg_ms * 1e3,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
 
     # accuracy against the oracle's reference gradient
     err = None
@@ -157,6 +175,7 @@ def main():
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,
         "grad_rel_err_vs_oracle": err,
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)

@@ -202,6 +202,26 @@ dpd_status dpd_hessian_apply(dpd_mesh* mesh, void* stream, const double* x, cons
                              const double* p, double* out);
 dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* R_out);
 
+/* Kernel timing for roofline measurement.  After dpd_profile_start(mesh, k),
+ * every launch of kernel class k made by calls on this handle is bracketed by
+ * HIP events recorded on the launch stream, and the algorithmic bytes and
+ * flops of that launch (what the method must move or compute, from the factor
+ * structure and the mesh) are added up.  dpd_profile_read synchronizes the
+ * stream, returns the totals since the start and stops timing.  One launch
+ * in every 16 of the class is timed (two event records each), so the totals
+ * describe that sample; launches that exit early because their iteration had
+ * already converged are not counted.  Class DPD_PROF_OFF disables timing. */
+enum { DPD_PROF_OFF = 0, DPD_PROF_SWEEP_FWD = 1, DPD_PROF_SWEEP_BWD = 2, DPD_PROF_ELEM_HVP = 3,
+       DPD_PROF_ELEM_FORCES = 4 };
+typedef struct {
+  int64_t launches;
+  double total_ms;         /* summed event-measured durations                    */
+  double bytes;            /* summed algorithmic bytes                           */
+  double flops;            /* summed algorithmic floating-point operations       */
+} dpd_kernel_profile;
+dpd_status dpd_profile_start(dpd_mesh* mesh, int32_t kernel_class);
+dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* out);
+
 const char* dpd_status_string(dpd_status s);
 const char* dpd_last_error(const dpd_mesh* mesh);   /* thread-local if mesh is NULL */
 

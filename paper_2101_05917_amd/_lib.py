@@ -53,6 +53,13 @@ class MeshInfo(C.Structure):
         "factor_nnz", "factor_bytes", "device_bytes")]
 
 
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
+DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4}
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 _I32 = C.POINTER(C.c_int32)
@@ -77,6 +84,8 @@ PROTOTYPES = {
     "dpd_gradient": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "dpd_hessian_apply": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "dpd_rotations": (C.c_int, [_P, _P, _P, _P]),
+    "dpd_profile_start": (C.c_int, [_P, C.c_int32]),
+    "dpd_profile_read": (C.c_int, [_P, _P, C.POINTER(KernelProfile)]),
     "dpd_status_string": (C.c_char_p, [C.c_int]),
     "dpd_last_error": (C.c_char_p, [_P]),
 }

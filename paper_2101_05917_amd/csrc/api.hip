@@ -24,8 +24,16 @@ thread_local std::string g_last_error;
 constexpr int32_t kLeafMax = 64;
 constexpr int32_t kSepMax = 1024;
 constexpr int64_t kLdsBudget = 48 * 1024;
+constexpr int64_t kProfStride = 16;
 
 }  // namespace
+
+struct TimedLaunch {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  double bytes, flops;
+  int st_idx, k;
+  bool strict;
+};
 
 struct dpd_mesh {
   dpd_options opt{};
@@ -50,6 +58,12 @@ struct dpd_mesh {
   double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
   IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   IterState* h_st = nullptr;   // pinned host mirror [2]
+  // kernel timing (dpd_profile_start / dpd_profile_read)
+  int32_t prof_class = DPD_PROF_OFF;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  std::vector<TimedLaunch> ev_pending;
+  int64_t prof_launches = 0, prof_seen = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
 };
 
 namespace {
@@ -95,28 +109,109 @@ void free_dev(dpd_mesh* m, void* p) {
   (void)hipFree(p);
 }
 
+// Bracket one launch of kernel class cls with events when it is being timed.
+// A launch inside an iteration is tagged with its iteration k and the state
+// (0 outer, 1 inner) that gates it; kernels enqueued after the iteration
+// converged exit at once, and such launches are dropped when harvested.
+struct ProfScope {
+  dpd_mesh* m;
+  hipStream_t s;
+  bool on;
+  TimedLaunch t{};
+  ProfScope(dpd_mesh* mm, hipStream_t ss, int32_t cls, double bytes, double flops, int st_idx = -1,
+            int k = 0, bool strict = true)
+      : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF) {
+    if (!on) return;
+    // time one launch in every kProfStride to keep the event overhead small
+    on = (m->prof_seen++ % kProfStride) == 0;
+    if (!on) return;
+    if (m->ev_free.empty()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        on = false;
+        return;
+      }
+      m->ev_free.push_back({a, b});
+    }
+    t.ev = m->ev_free.back();
+    m->ev_free.pop_back();
+    t.bytes = bytes;
+    t.flops = flops;
+    t.st_idx = st_idx;
+    t.k = k;
+    t.strict = strict;
+    (void)hipEventRecord(t.ev.first, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(t.ev.second, s);
+    m->ev_pending.push_back(t);
+  }
+};
+
+// Accumulate the timed launches that did their work (after a stream sync,
+// with the iteration states freshly read into h_st).
+void prof_harvest(dpd_mesh* m) {
+  for (auto& t : m->ev_pending) {
+    bool live = true;
+    if (t.st_idx >= 0) {
+      const IterState& h = m->h_st[t.st_idx];
+      live = !h.done || (t.strict ? t.k < h.iter : t.k <= h.iter);
+    }
+    if (live) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.ev.first, t.ev.second) == hipSuccess) m->prof_ms += ms;
+      m->prof_launches += 1;
+      m->prof_bytes += t.bytes;
+      m->prof_flops += t.flops;
+    }
+    m->ev_free.push_back(t.ev);
+  }
+  m->ev_pending.clear();
+}
+
 // A^{-1} b on free nodes, out[perm] = alpha x (+ out when accumulate).
 void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, double alpha,
-           int accumulate, const IterState* st) {
+           int accumulate, const IterState* st, int k = 0) {
+  const int st_idx = st == nullptr ? -1 : (st == m->st ? 0 : 1);
   const LevelPlan& P = m->plan;
   const int32_t L = m->S.n_levels;
   for (int32_t l = 0; l < L; ++l) {
     const int n = P.fwd_off[l + 1] - P.fwd_off[l];
-    if (n) launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
+    if (!n) continue;
+    const double scale = fp32 ? 0.5 : 1.0;
+    ProfScope ps(m, s, DPD_PROF_SWEEP_FWD, P.fwd_bytes[l] * scale, P.fwd_flops[l], st_idx, k);
+    launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
   }
   for (int32_t l = L - 1; l >= 0; --l) {
     const int n = P.bwd_off[l + 1] - P.bwd_off[l];
     const bool lds = (int64_t)3 * P.bwd_rows[l] * (int64_t)sizeof(double) <= kLdsBudget;
-    if (n)
-      launch_sweep_bwd(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], lds, fp32, out, m->dm.N,
-                       alpha, accumulate, st);
+    if (!n) continue;
+    ProfScope ps(m, s, DPD_PROF_SWEEP_BWD, P.bwd_bytes[l] * (fp32 ? 0.5 : 1.0), P.bwd_flops[l],
+                 st_idx, k);
+    launch_sweep_bwd(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], lds, fp32, out, m->dm.N,
+                     alpha, accumulate, st);
   }
 }
 
 dpd_status read_state(dpd_mesh* m, hipStream_t s) {
   HIPCHECK(m, hipMemcpyAsync(m->h_st, m->st, 2 * sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIPCHECK(m, hipStreamSynchronize(s));
+  prof_harvest(m);
   return DPD_OK;
+}
+
+// Per-launch algorithmic work of the element kernels: node gather (24 B per
+// node), per-Gauss-point cache (15 doubles read by the adjoint kernel),
+// element forces written (24 doubles), connectivity and weights.
+double elem_hvp_bytes(const dpd_mesh* m) {
+  const double E = m->dm.E, N = m->dm.N;
+  return 24.0 * N + E * (8 * 15 * 8.0 + 24 * 8.0 + 32.0 + 8.0);
+}
+double elem_hvp_flops(const dpd_mesh* m) { return 411.0 * 8.0 * m->dm.E; }
+double elem_forces_bytes(const dpd_mesh* m) {
+  const double E = m->dm.E, N = m->dm.N;
+  return 24.0 * N + E * (24 * 8.0 + 32.0 + 8.0);
 }
 
 void fill_devmesh(dpd_mesh* m) {
@@ -318,6 +413,14 @@ void dpd_destroy_mesh(dpd_mesh* m) {
   if (!m) return;
   (void)hipDeviceSynchronize();
   for (void* p : m->allocs) (void)hipFree(p);
+  for (auto& e : m->ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : m->ev_pending) {
+    (void)hipEventDestroy(e.ev.first);
+    (void)hipEventDestroy(e.ev.second);
+  }
   if (m->h_st) (void)hipHostFree(m->h_st);
   delete m;
 }
@@ -452,7 +555,10 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
     const int64_t n3 = 3 * (int64_t)m->dm.N;
     const int never = 0x3fffffff;
     solves = 0;
-    launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    {
+      ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
+      launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    }
     launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, 0, never, 0);
     for (outer = 0;; ++outer) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
@@ -472,16 +578,22 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       } else {
         launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
       }
+      {
+      ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
       launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    }
       launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
     }
   }
   for (int k = 0; solves < 0; ++k) {
-    launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    {
+      ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0, 0, k, false);
+      launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+    }
     launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, k, max_it,
                          o.fwd_fixed_iters);
     if (k >= max_it) break;
-    solve(m, s, fp32, m->r, xn, -1.0, 1, m->st);
+    solve(m, s, fp32, m->r, xn, -1.0, 1, m->st, k);
     if (!o.fwd_fixed_iters && (k + 1) % o.check_every == 0) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
       if (m->h_st->done) break;
@@ -511,10 +623,13 @@ dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, 
   dpd_status rc;
   const dpd_options& o = m->opt;
   for (int k = 0;; ++k) {
-    launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
+    {
+      ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), 0, k, false);
+      launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
+    }
     launch_node_hvp(m->dm, s, m->z, m->fe, xn, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
     if (k >= max_it) break;
-    solve(m, s, fp32, m->r, m->z, -1.0, 1, m->st);
+    solve(m, s, fp32, m->r, m->z, -1.0, 1, m->st, k);
     if ((k + 1) % o.check_every == 0) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
       if (m->h_st->done) break;
@@ -537,10 +652,14 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 1);
   launch_lincomb(s, n3, m->p, 1.0, m->s, 0.0, nullptr);
   for (int k = 1; k <= max_it; ++k) {
-    launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, st);
+    {
+      ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m),
+                   st == m->st ? 0 : 1, k, false);
+      launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, st);
+    }
     launch_node_hvp(m->dm, s, m->p, m->fe, xk, nullptr, m->q, st, m->partials, 2, k, max_it);
     launch_cg_update(m->dm, s, z, m->cg_r, m->p, m->q, st, m->partials, k, max_it);
-    solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st);
+    solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st, k);
     launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 2);
     launch_cg_direction(m->dm, s, m->p, m->s, st);
     if (k % check_every == 0) {
@@ -653,6 +772,29 @@ dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_o
   hipStream_t s = (hipStream_t)stream;
   launch_elem_forces(m->dm, s, x, nullptr, m->fe, R_out, nullptr);
   HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
+  if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_ELEM_FORCES)
+    return fail(m, DPD_EINVAL, "unknown kernel class");
+  m->prof_class = kernel_class;
+  m->prof_launches = 0;
+  m->prof_seen = 0;
+  m->prof_ms = m->prof_bytes = m->prof_flops = 0.0;
+  return DPD_OK;
+}
+
+dpd_status dpd_profile_read(dpd_mesh* m, void* stream, dpd_kernel_profile* out) {
+  if (!m || !out) return fail(m, DPD_EINVAL, "null argument");
+  HIPCHECK(m, hipStreamSynchronize((hipStream_t)stream));
+  prof_harvest(m);
+  out->launches = m->prof_launches;
+  out->total_ms = m->prof_ms;
+  out->bytes = m->prof_bytes;
+  out->flops = m->prof_flops;
+  m->prof_class = DPD_PROF_OFF;
   return DPD_OK;
 }
 

@@ -347,6 +347,23 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
       P.bwd_rows[l] = std::max(P.bwd_rows[l], ld);
     }
   }
+  P.fwd_bytes.assign(L, 0.0);
+  P.bwd_bytes.assign(L, 0.0);
+  P.fwd_flops.assign(L, 0.0);
+  P.bwd_flops.assign(L, 0.0);
+  for (int32_t l = 0; l < L; ++l)
+    for (int32_t s : by_level[l]) {
+      const Supernode& sn = S.sn[s];
+      const double nc = sn.ncols, nr = sn.nrows, nnz = nc * (nc + 1) / 2 + nr * nc;
+      double contribs = 0;
+      for (int32_t j = sn.col0; j < sn.col0 + sn.ncols; ++j) contribs += S.cptr[j + 1] - S.cptr[j];
+      // forward: panel, b_s and incoming updates read, y_s and outgoing updates written
+      P.fwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + contribs) + 24.0 * (nc + nr) + 4.0 * contribs;
+      // backward: panel, y_s and x_R read, x_s written (internal and public copies)
+      P.bwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + nr) + 4.0 * nr + 48.0 * nc;
+      P.fwd_flops[l] += 6.0 * nnz;
+      P.bwd_flops[l] += 6.0 * nnz;
+    }
   P.fwd_off[L] = (int32_t)P.fwd.size();
   P.bwd_off[L] = (int32_t)P.bwd.size();
 }

@@ -85,6 +85,10 @@ struct LevelPlan {
   std::vector<int32_t> fwd_off, bwd_off;   // task ranges per level (size L + 1)
   std::vector<int32_t> fwd_cols, bwd_rows; // dynamic LDS extents per level
   std::vector<SweepTask> fwd, bwd;
+  // algorithmic traffic of one launch per level: panel entries read (packed
+  // lower triangle of the diagonal block plus the off-diagonal block) and the
+  // right-hand-side, update and solution vectors read and written once
+  std::vector<double> fwd_bytes, bwd_bytes, fwd_flops, bwd_flops;
 };
 
 // Geometric nested dissection of the free nodes on the voxel grid, then the

@@ -233,3 +233,15 @@ class Mesh:
             L.check(self.lib.dpd_rotations(self.handle, _stream(self.device), _ptr(x), _ptr(out)),
                     self.handle)
         return out
+
+    # ------------------------------------------------------------------ timing
+    def profile_start(self, kernel_class: str):
+        """Time every launch of one kernel class with HIP events (see dpd_profile_start)."""
+        L.check(self.lib.dpd_profile_start(self.handle, L.DPD_PROF[kernel_class]), self.handle)
+
+    def profile_read(self) -> dict:
+        out = L.KernelProfile()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_profile_read(self.handle, _stream(self.device), C.byref(out)),
+                    self.handle)
+        return {k: getattr(out, k) for k, _ in out._fields_}

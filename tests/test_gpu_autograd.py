@@ -1,0 +1,102 @@
+"""Rollouts through torch.autograd (PDStep) against the oracle, checkpointing,
+and central finite differences of the GPU path itself."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import model as om, rollout as orr
+from parity_helpers import to_dev, elem_dev, robot_scene, rel
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(fwd_solver="newton_pcg", fwd_rel_tol=1e-13, fwd_max_iter=100000, bwd_rel_tol=1e-13,
+             bwd_max_iter=100000, check_every=32)
+
+
+def gpu_loss_and_grads(mesh, sc, x0, v0, acts, cx, checkpoint_every=1):
+    from paper_2101_05917_amd.autograd import rollout
+    N = mesh.n_nodes
+    x = to_dev(x0, N).requires_grad_(True)
+    v = to_dev(v0, N).requires_grad_(True)
+    E = elem_dev(sc.youngs).requires_grad_(True)
+    a = None if acts is None else elem_dev(acts).requires_grad_(True)
+    a_list = None if a is None else [a[t] for t in range(a.shape[0])]
+    xT, vT = rollout(mesh, x, v, sc.steps, a_list, E, checkpoint_every=checkpoint_every)
+    L = (to_dev(cx, N) * xT).sum()
+    L.backward()
+    return (L.item(), x.grad.cpu().numpy().T.reshape(-1), v.grad.cpu().numpy().T.reshape(-1),
+            E.grad.cpu().numpy(), None if a is None else a.grad.cpu().numpy())
+
+
+def test_rollout_gradients_match_oracle_c1():
+    from paper_2101_05917_amd.mesh import Mesh
+    sc = W.config("c1")
+    mesh = Mesh.from_scene(sc, **TIGHT)
+    m = om.Model(sc)
+    x0, v0 = m.X.copy(), np.zeros(3 * m.N)
+    cx = W.loss_vector(m.N, 0)
+    Lg, gx, gv, gE, _ = gpu_loss_and_grads(mesh, sc, x0, v0, None, cx)
+    Lo, g = orr.loss_and_grad(m, x0, v0, None, cx, pd_kw={"max_iter": 20000, "tol": 1e-14})
+    assert abs(Lg - Lo) <= 1e-12 * abs(Lo)
+    assert rel(gx, g["x0"]) <= 1e-8
+    assert rel(gv, g["v0"]) <= 1e-8
+    assert rel(gE, g["youngs"]) <= 1e-8
+
+
+def test_checkpointed_gradients_equal_stored():
+    from paper_2101_05917_amd.mesh import Mesh
+    sc = W.config("c1")
+    mesh = Mesh.from_scene(sc, **TIGHT)
+    X = mesh.rest_positions().cpu().numpy().T.reshape(-1)
+    cx = W.loss_vector(mesh.n_nodes, 0)
+    ref = gpu_loss_and_grads(mesh, sc, X, np.zeros_like(X), None, cx, checkpoint_every=1)
+    for K in (3, 10):
+        got = gpu_loss_and_grads(mesh, sc, X, np.zeros_like(X), None, cx, checkpoint_every=K)
+        assert got[0] == ref[0]
+        for a, b in zip(got[1:4], ref[1:4]):
+            assert np.array_equal(a, b)
+
+
+def test_robot_actuation_gradients_match_oracle():
+    from paper_2101_05917_amd.mesh import Mesh
+    sc = robot_scene(steps=4)
+    mesh = Mesh.from_scene(sc, **TIGHT)
+    m = om.Model(sc)
+    acts = W.actuation_sequence(sc.steps, m.E, seed=0)
+    x0, v0 = m.X.copy(), np.zeros(3 * m.N)
+    v0[0::3] = 0.1
+    cx = W.loss_vector(m.N, 1)
+    Lg, gx, gv, gE, ga = gpu_loss_and_grads(mesh, sc, x0, v0, acts, cx, checkpoint_every=2)
+    Lo, g = orr.loss_and_grad(m, x0, v0, acts, cx, pd_kw={"max_iter": 20000, "tol": 1e-14})
+    assert abs(Lg - Lo) <= 1e-10 * abs(Lo)
+    assert rel(ga, g["act"]) <= 1e-7
+    assert rel(gx, g["x0"]) <= 1e-7
+    assert rel(gv, g["v0"]) <= 1e-7
+
+
+def test_gpu_gradient_against_its_own_finite_differences():
+    """Central differences in log E of the GPU forward alone (eps 1e-6)."""
+    from paper_2101_05917_amd.mesh import Mesh
+    sc = W.cantilever(6, 3, 3, youngs="loguniform", steps=5, seed=2)
+    mesh = Mesh.from_scene(sc, **TIGHT)
+    X = mesh.rest_positions().cpu().numpy().T.reshape(-1)
+    cx = W.loss_vector(mesh.n_nodes, 0)
+    L0, gx, gv, gE, _ = gpu_loss_and_grads(mesh, sc, X, np.zeros_like(X), None, cx)
+    E0 = sc.youngs.copy()
+    rng = np.random.default_rng(1)
+    for e in rng.choice(len(E0), 3, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            E = E0.copy()
+            E[e] *= np.exp(sgn * 1e-6)
+            mesh.set_youngs(E)
+            xs = to_dev(X, mesh.n_nodes)
+            vs = torch.zeros_like(xs)
+            for _ in range(sc.steps):
+                xs, vs, _ = mesh.forward_step(xs, vs)
+            vals.append(float((to_dev(cx, mesh.n_nodes) * xs).sum()))
+        mesh.set_youngs(E0)
+        fd = (vals[0] - vals[1]) / 2e-6
+        an = gE[e] * E0[e]
+        assert abs(fd - an) <= 1e-5 * np.abs(gE * E0).max() + 1e-4 * abs(an)

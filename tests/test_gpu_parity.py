@@ -144,3 +144,58 @@ def test_backward_step(name, solver):
     assert rel(gE.cpu().numpy(), rE) <= 1e-8
     if act is not None:
         assert rel(ga.cpu().numpy(), ra) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["c2", "robot"])
+def test_mixed_precision_forward_and_backward(name):
+    """FP32 panels inside FP64 residual corrections: same converged state."""
+    sc = SCENES[name]()
+    g, o = pair(sc, precision="mixed", fwd_solver="newton_pcg", fwd_max_iter=100000,
+                fwd_rel_tol=1e-12, bwd_rel_tol=1e-12, bwd_max_iter=100000, check_every=32)
+    x, v = _perturbed(o, seed=11)
+    act = None if o.Gm is None else np.random.default_rng(12).uniform(0, 1, o.E)
+    a_dev = None if act is None else elem_dev(act)
+    xn, vn, st = g.forward_step(to_dev(x, o.N), to_dev(v, o.N), a_dev)
+    print(name, "mixed fwd", st, flush=True)
+    xr = converged_state(o, x, v, act)
+    err_x = np.linalg.norm(soa(xn) - xr) / np.linalg.norm(xr - x)
+    assert err_x <= 1e-5
+    gxn = np.random.default_rng(13).standard_normal(3 * o.N)
+    gE = torch.zeros(o.E, dtype=torch.float64, device="cuda:0")
+    gx, gv, ga, bst = g.backward_step(to_dev(x, o.N), to_dev(v, o.N), a_dev, to_dev(xr, o.N),
+                                      to_dev(gxn, o.N), to_dev(np.zeros(3 * o.N), o.N), g_youngs=gE)
+    print(name, "mixed bwd", bst, flush=True)
+    rx, rv, rE, ra, _ = oa.backward_step(o, x, v, act, xr, gxn, np.zeros(3 * o.N), solver="direct")
+    assert rel(soa(gx), rx) <= 1e-6
+    assert rel(gE.cpu().numpy(), rE) <= 1e-6
+    # mixed-precision solve alone: FP32 panels, error at single-precision level
+    b = np.random.default_rng(14).standard_normal(3 * o.N)
+    xs = soa(g.apply_inverse(to_dev(b, o.N), precision="mixed"))
+    ref = np.zeros(3 * o.N)
+    ref[o.free] = o.solve_A(b[o.free])
+    assert 1e-12 < rel(xs, ref) <= 1e-4
+
+
+def test_rest_state_converges_immediately():
+    """Zero residual at x^0: the stopping test's absolute floor ends the step."""
+    sc = W.config("c1")
+    sc.gravity = (0.0, 0.0, 0.0)
+    g, o = pair(sc, fwd_solver="newton_pcg")
+    X = g.rest_positions()
+    xn, vn, st = g.forward_step(X, torch.zeros_like(X))
+    assert st["converged"] == 1 and st["fwd_iters"] == 0
+    assert torch.equal(xn, X) and float(vn.abs().max()) == 0.0
+
+
+def test_single_voxel_free_fall_is_exact():
+    sc = W.dropped_block(1, 1, 1, steps=1)
+    sc.contact_k = 0.0
+    g, o = pair(sc)
+    X = g.rest_positions()
+    v = torch.zeros_like(X)
+    v[0] = 0.3
+    xn, vn, st = g.forward_step(X, v)
+    expect = X.clone()
+    expect[0] += 0.01 * 0.3
+    expect[2] += 1e-4 * -9.81
+    assert float((xn - expect).abs().max()) <= 1e-15
