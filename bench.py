@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--requests", type=int, default=64, help="c4: number of requests")
+    ap.add_argument("--max-cube", type=int, default=24, help="c4: largest cube side (cells)")
+    ap.add_argument("--rate", type=float, default=float("inf"), help="c4: Poisson arrival rate")
+    ap.add_argument("--slots", type=int, default=8, help="c4: resident requests")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
     ap.add_argument("--roofline-kernel", default="sweep_fwd",
                     choices=["sweep_fwd", "sweep_bwd", "elem_hvp", "elem_forces"])
     return ap.parse_args()
@@ -104,8 +109,60 @@ def cpu_baseline(scene, T_budget_s):
                       f"adjoint, {dt:.1f} s wall, numpy/scipy on {cores} host cores"}
 
 
+def serve_bench(args):
+    """Served batch: rollout requests of cube cantilevers with Poisson arrivals."""
+    import torch  # noqa: F401
+    from paper_2101_05917_amd.serve import Server
+    reqs = W.served_requests(n_requests=args.requests, lo=4, hi=args.max_cube, steps=50,
+                             rate=args.rate, seed=0)
+    srv = Server(int(args.hbm_budget_gb * (1 << 30)), max_slots=args.slots)
+    solve = dict(fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol, fwd_max_iter=200000,
+                 bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol, bwd_max_iter=200000,
+                 precision=args.precision, check_every=16)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        wait = r["arrival"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        sc = r["scene"]
+        N = len(W.present_nodes(sc.cells))
+        tickets.append(srv.submit(sc, W.loss_vector(N, sc.loss_seed), **solve))
+    srv.drain()
+    wall = time.perf_counter() - t0
+    res = [srv.poll(t, gradients=False) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in res if r.state == "done"]
+    lat = np.array([r.latency for r in ok])
+    dof_steps = sum(3 * r.n_nodes * 50 for r in ok)
+    first = min(r.t_submit for r in res)
+    last = max(r.t_done for r in res)
+    return {
+        "metric": "p99 rollout latency (served batch)",
+        "value": float(np.percentile(lat, 99)), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": wall * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} cube-cantilever rollout requests, n ~ U{{4..{args.max_cube}}}"
+                               f" cells per side, 50 steps fwd+adjoint each, Poisson rate {args.rate}/s",
+                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb},
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "dof_steps_per_s": dof_steps / (last - first),
+        "completed": len(ok), "failed": len(res) - len(ok),
+        "peak_hbm_bytes": st["peak_bytes"], "peak_resident_requests": st["peak_active"],
+    }
+
+
 def main():
     args = parse()
+    if args.config == "c4":
+        if args.gpus != 1:
+            print("bench.py runs on exactly one GPU", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(serve_bench(args)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the workload does not shard across GPUs in this build)", file=sys.stderr)

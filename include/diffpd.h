@@ -107,7 +107,7 @@ typedef struct {
   int64_t n_nodes, n_elements, n_free, n_fixed, n_contact;
   int64_t n_supernodes, n_levels;
   int64_t factor_nnz;      /* stored entries of the factor panels (packed count)  */
-  int64_t factor_bytes;    /* device bytes of the FP64 panels                     */
+  int64_t factor_bytes;    /* device bytes of the FP64 panels (both layouts)      */
   int64_t device_bytes;    /* all device memory owned by the handle               */
 } dpd_mesh_info;
 
@@ -132,6 +132,7 @@ dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const doub
                            const int32_t* fixed_ijk, int64_t n_fixed,
                            const dpd_options* opt, dpd_mesh** out);
 
+/* Waits for the device to finish outstanding work, then frees the handle. */
 void dpd_destroy_mesh(dpd_mesh* mesh);
 
 dpd_status dpd_get_info(const dpd_mesh* mesh, dpd_mesh_info* info);
@@ -221,6 +222,61 @@ typedef struct {
 } dpd_kernel_profile;
 dpd_status dpd_profile_start(dpd_mesh* mesh, int32_t kernel_class);
 dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* out);
+
+/* ------------------------------------------------------------------------
+ * Rollout server with continuous batching.
+ *
+ * A request is a whole differentiable rollout: build the mesh, factorize A,
+ * run T forward steps from rest, evaluate L = c . x_T and run the T adjoint
+ * steps back to the initial state.  The server keeps up to max_slots requests
+ * resident on the device at once, each with its own factor, states and HIP
+ * stream (all streams at default priority), so their kernels overlap on the
+ * GPU.  A queued request is admitted as soon as a slot is free and its device
+ * footprint (factor panels, mesh buffers, the T + 1 stored states) fits in
+ * what remains of hbm_budget_bytes; requests arriving while others run join
+ * as slots and memory free up.  Results are independent of what else runs
+ * (every kernel is deterministic), bitwise.
+ * ------------------------------------------------------------------------ */
+typedef struct dpd_server dpd_server;
+
+typedef struct {
+  const int32_t* cells_ijk;  /* host [n_cells][3]                             */
+  int64_t n_cells;
+  const double* youngs;      /* host [n_cells]                                */
+  const int32_t* fixed_ijk;  /* host [n_fixed][3] or NULL                     */
+  int64_t n_fixed;
+  const double* loss_x;      /* host [3][N] weights c of L = c . x_T           */
+  int64_t n_nodes;           /* N of the mesh the cells define (checked)      */
+  int32_t steps;             /* T >= 1                                         */
+  int32_t pad;
+  dpd_options opt;           /* physics and solver settings of this request    */
+} dpd_request;               /* everything is copied by dpd_server_submit      */
+
+enum { DPD_REQ_QUEUED = 0, DPD_REQ_RUNNING = 1, DPD_REQ_DONE = 2, DPD_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;             /* DPD_REQ_*                                      */
+  int32_t status;            /* dpd_status of the request (soft or hard)       */
+  double loss;               /* c . x_T                                        */
+  double t_submit, t_admit, t_done;  /* seconds since dpd_server_create        */
+  int64_t n_nodes, n_elements, footprint_bytes;
+  int64_t fwd_iters, bwd_iters;      /* summed over the T steps                */
+} dpd_result;
+
+/* max_slots >= 1 requests resident at once within hbm_budget_bytes of device
+ * memory, on the device current at creation. */
+dpd_status dpd_server_create(int64_t hbm_budget_bytes, int32_t max_slots, dpd_server** out);
+/* Queue a request (copied); returns its ticket.  Never blocks on the GPU. */
+dpd_status dpd_server_submit(dpd_server* srv, const dpd_request* req, int64_t* ticket);
+/* Result of a ticket; the gradient outputs (host, or NULL) are filled once the
+ * request is done: g_x0, g_v0 [3][N], g_youngs [n_cells]. */
+dpd_status dpd_server_poll(dpd_server* srv, int64_t ticket, dpd_result* out, double* g_x0,
+                           double* g_v0, double* g_youngs);
+/* Block until every submitted request has finished. */
+dpd_status dpd_server_drain(dpd_server* srv);
+/* Peak device bytes admitted at once and peak number of resident requests. */
+dpd_status dpd_server_stats(dpd_server* srv, int64_t* peak_bytes, int32_t* peak_active);
+void dpd_server_destroy(dpd_server* srv);   /* drains first */
 
 const char* dpd_status_string(dpd_status s);
 const char* dpd_last_error(const dpd_mesh* mesh);   /* thread-local if mesh is NULL */

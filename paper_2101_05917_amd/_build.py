@@ -8,11 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiffpd.so")
-SOURCES = ["host_mesh.cpp", "factor.cpp", "kernels.hip", "api.hip"]
+SOURCES = ["host_mesh.cpp", "factor.cpp", "kernels.hip", "api.hip", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
+    "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-pthread",
     "--offload-arch=gfx950",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

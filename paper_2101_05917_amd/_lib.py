@@ -58,6 +58,20 @@ class KernelProfile(C.Structure):
                 ("flops", C.c_double)]
 
 
+class Request(C.Structure):
+    _fields_ = [("cells_ijk", C.POINTER(C.c_int32)), ("n_cells", C.c_int64),
+                ("youngs", C.POINTER(C.c_double)), ("fixed_ijk", C.POINTER(C.c_int32)),
+                ("n_fixed", C.c_int64), ("loss_x", C.POINTER(C.c_double)), ("n_nodes", C.c_int64),
+                ("steps", C.c_int32), ("pad", C.c_int32), ("opt", Options)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("loss", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("n_nodes", C.c_int64), ("n_elements", C.c_int64), ("footprint_bytes", C.c_int64),
+                ("fwd_iters", C.c_int64), ("bwd_iters", C.c_int64)]
+
+
 DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4}
 
 _P = C.c_void_p
@@ -86,6 +100,12 @@ PROTOTYPES = {
     "dpd_rotations": (C.c_int, [_P, _P, _P, _P]),
     "dpd_profile_start": (C.c_int, [_P, C.c_int32]),
     "dpd_profile_read": (C.c_int, [_P, _P, C.POINTER(KernelProfile)]),
+    "dpd_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(_P)]),
+    "dpd_server_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_int64)]),
+    "dpd_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(Result), _P, _P, _P]),
+    "dpd_server_drain": (C.c_int, [_P]),
+    "dpd_server_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "dpd_server_destroy": (None, [_P]),
     "dpd_status_string": (C.c_char_p, [C.c_int]),
     "dpd_last_error": (C.c_char_p, [_P]),
 }

@@ -54,6 +54,8 @@ struct dpd_mesh {
   double* w_e = nullptr;
   double* panel64 = nullptr;
   float* panel32 = nullptr;
+  double* panelT64 = nullptr;
+  float* panelT32 = nullptr;
   double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
   double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
   IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
@@ -181,7 +183,10 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
     if (!n) continue;
     const double scale = fp32 ? 0.5 : 1.0;
     ProfScope ps(m, s, DPD_PROF_SWEEP_FWD, P.fwd_bytes[l] * scale, P.fwd_flops[l], st_idx, k);
-    launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
+    if (P.fwd_wide[l])
+      launch_sweep_fwd_wide(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
+    else
+      launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
   }
   for (int32_t l = L - 1; l >= 0; --l) {
     const int n = P.bwd_off[l + 1] - P.bwd_off[l];
@@ -241,6 +246,27 @@ std::vector<double> corotated_weights(const HostMesh& hm, const dpd_options& o) 
   return w;
 }
 
+// FP32 copies (column-major and row-major) of the FP64 panels.
+dpd_status make_fp32_panels(dpd_mesh* m, const std::vector<double>& panels, hipStream_t s) {
+  if (!m->panel32) {
+    dpd_status st = dev_alloc(m, &m->panel32, m->S.panel_size);
+    if (st != DPD_OK) return st;
+  }
+  if (!m->panelT32) {
+    dpd_status st = dev_alloc(m, &m->panelT32, m->S.panel_size);
+    if (st != DPD_OK) return st;
+  }
+  const std::vector<float> f(panels.begin(), panels.end());
+  const std::vector<float> ft = transpose_panels<float>(m->S, panels);
+  HIPCHECK(m, hipMemcpyAsync(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHECK(m, hipMemcpyAsync(m->panelT32, ft.data(), ft.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->ds.panel32 = m->panel32;
+  m->ds.panelT32 = m->panelT32;
+  m->have_fp32 = true;
+  return DPD_OK;
+}
+
 dpd_status check_ready(dpd_mesh* m) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
   if (!m->factored) return fail(m, DPD_ESTATE, "mesh is not factorized (call dpd_factorize)");
@@ -284,6 +310,21 @@ dpd_status dpd_default_options(dpd_options* o) {
 dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
                            const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options* opt,
                            dpd_mesh** out) {
+  dpd_status st = dpd::create_host(cells_ijk, n_cells, youngs, fixed_ijk, n_fixed, opt, out);
+  if (st != DPD_OK) return st;
+  st = dpd::upload_device(*out);
+  if (st != DPD_OK) *out = nullptr;
+  return st;
+}
+
+}  // extern "C"
+
+namespace dpd {
+
+// Host stage of mesh creation: validation, numbering, A_s, ordering, plan.
+dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
+                       const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options* opt,
+                       dpd_mesh** out) {
   if (!out) return fail(nullptr, DPD_EINVAL, "null output handle");
   *out = nullptr;
   if (!opt) return fail(nullptr, DPD_EINVAL, "null options");
@@ -301,7 +342,29 @@ dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const doub
   analyse(m->hm, m->A, kLeafMax, kSepMax, m->S);
   build_plan(m->S, m->plan);
   fill_devmesh(m);
+  *out = m;
+  return DPD_OK;
+}
 
+// Device bytes the handle will own once uploaded and factorized.
+int64_t footprint_bytes(const dpd_mesh* m) {
+  const int64_t N = m->hm.n_nodes, E = m->hm.n_elems, nf = m->hm.n_free;
+  const Symbolic& S = m->S;
+  int64_t b = 0;
+  b += 8 * (3 * N + N + E);                                  // X, mass, weights
+  b += 4 * (8 * E + 8 * N + nf) + 2 * N;                     // conn, incidence, perm, flags
+  b += (int64_t)S.sn.size() * (3 * 4 + 3 * 8) + 4 * (int64_t)S.rows.size();
+  b += 4 * ((int64_t)S.cptr.size() + (int64_t)S.cidx.size());
+  b += 16 * (int64_t)(m->plan.fwd.size() + m->plan.bwd.size());
+  b += 8 * (6 * nf + 3 * S.u_size + 24 * E + 8 * 3 * N);    // sweep vectors, fe, work vectors
+  b += 8 * ((int64_t)kAdjCacheRows * 8 * E + std::max<int64_t>(N, 8 * E) / kBlock + 16);
+  b += 2 * 8 * S.panel_size;                                 // FP64 panels, both layouts
+  if (m->opt.precision == DPD_MIXED) b += 2 * 4 * S.panel_size;  // FP32 copies
+  return b;
+}
+
+// Device stage: allocate and upload everything; frees the handle on failure.
+dpd_status upload_device(dpd_mesh* m) {
   const HostMesh& hm = m->hm;
   const int64_t N = hm.n_nodes, E = hm.n_elems, nf = hm.n_free;
   std::vector<int32_t> conn_soa(8 * E);
@@ -405,13 +468,26 @@ dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const doub
     dpd_destroy_mesh(m);
     return fail(nullptr, DPD_EHIP, "hipMemset failed");
   }
-  *out = m;
   return DPD_OK;
 }
+
+}  // namespace dpd
+
+extern "C" {
 
 void dpd_destroy_mesh(dpd_mesh* m) {
   if (!m) return;
   (void)hipDeviceSynchronize();
+  dpd::destroy_synced(m);
+}
+
+}  // extern "C"
+
+namespace dpd {
+
+// Free a handle whose streams the caller has already synchronized.
+void destroy_synced(dpd_mesh* m) {
+  if (!m) return;
   for (void* p : m->allocs) (void)hipFree(p);
   for (auto& e : m->ev_free) {
     (void)hipEventDestroy(e.first);
@@ -425,6 +501,10 @@ void dpd_destroy_mesh(dpd_mesh* m) {
   delete m;
 }
 
+}  // namespace dpd
+
+extern "C" {
+
 dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   if (!m || !info) return fail(nullptr, DPD_EINVAL, "null argument");
   info->n_nodes = m->hm.n_nodes;
@@ -435,7 +515,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->n_supernodes = (int64_t)m->S.sn.size();
   info->n_levels = m->S.n_levels;
   info->factor_nnz = m->S.packed_nnz;
-  info->factor_bytes = m->S.panel_size * (int64_t)sizeof(double);
+  info->factor_bytes = 2 * m->S.panel_size * (int64_t)sizeof(double);
   info->device_bytes = m->device_bytes;
   return DPD_OK;
 }
@@ -472,13 +552,10 @@ dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
   m->opt = *o;
   if (m->opt.check_every < 1) m->opt.check_every = 1;
   if (need32 && m->factored) {
-    if (dev_alloc(m, &m->panel32, m->S.panel_size) != DPD_OK) return DPD_ENOMEM;
     std::vector<double> tmp(m->S.panel_size);
     HIPCHECK(m, hipMemcpy(tmp.data(), m->panel64, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<float> f(tmp.begin(), tmp.end());
-    HIPCHECK(m, hipMemcpy(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-    m->ds.panel32 = m->panel32;
-    m->have_fp32 = true;
+    dpd_status st = make_fp32_panels(m, tmp, nullptr);
+    if (st != DPD_OK) return st;
   }
   return DPD_OK;
 }
@@ -513,19 +590,20 @@ dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
     dpd_status st = dev_alloc(m, &m->panel64, m->S.panel_size);
     if (st != DPD_OK) return st;
   }
+  if (!m->panelT64) {
+    dpd_status st = dev_alloc(m, &m->panelT64, m->S.panel_size);
+    if (st != DPD_OK) return st;
+  }
   HIPCHECK(m, hipMemcpyAsync(m->panel64, panels.data(), panels.size() * sizeof(double),
                              hipMemcpyHostToDevice, s));
+  const std::vector<double> pt = transpose_panels<double>(m->S, panels);
+  HIPCHECK(m, hipMemcpyAsync(m->panelT64, pt.data(), pt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
   m->ds.panel64 = m->panel64;
+  m->ds.panelT64 = m->panelT64;
   if (m->opt.precision == DPD_MIXED || m->have_fp32) {
-    if (!m->panel32) {
-      dpd_status st = dev_alloc(m, &m->panel32, m->S.panel_size);
-      if (st != DPD_OK) return st;
-    }
-    std::vector<float> f(panels.begin(), panels.end());
-    HIPCHECK(m, hipMemcpyAsync(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    HIPCHECK(m, hipStreamSynchronize(s));
-    m->ds.panel32 = m->panel32;
-    m->have_fp32 = true;
+    dpd_status st = make_fp32_panels(m, panels, s);
+    if (st != DPD_OK) return st;
   }
   HIPCHECK(m, hipStreamSynchronize(s));
   m->factored = true;

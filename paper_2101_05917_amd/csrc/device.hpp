@@ -33,8 +33,10 @@ struct DevSolve {
   const int32_t* rows;        // concatenated R_s (internal)
   const int32_t* cptr;        // [nf + 1]
   const int32_t* cidx;        // positions into U
-  const double* panel64;
+  const double* panel64;       // column-major panels (backward, narrow forward)
   const float* panel32;
+  const double* panelT64;      // row-major copies (wide forward)
+  const float* panelT32;
   double* y_int;              // [3][nf]
   double* x_int;              // [3][nf]
   double* U;                  // [u_size][3]
@@ -76,6 +78,8 @@ void launch_velocity(const DevMesh& M, hipStream_t s, const double* x, const dou
 void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v);
 void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                       int lds_cols, bool fp32, const double* b, int N, const IterState* st);
+void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                           int lds_cols, bool fp32, const double* b, int N, const IterState* st);
 void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                       int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
                       int accumulate, const IterState* st);

@@ -334,15 +334,31 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
   P.bwd_off.assign(L + 1, 0);
   P.fwd_cols.assign(L, 0);
   P.bwd_rows.assign(L, 0);
+  P.fwd_wide.assign(L, 0);
+  const int64_t target = 2048;  // workgroups wanted per level
   for (int32_t l = 0; l < L; ++l) {
     P.fwd_off[l] = (int32_t)P.fwd.size();
     P.bwd_off[l] = (int32_t)P.bwd.size();
+    int64_t rows = 0, cols = 0;
+    int32_t max_nc = 0;
+    for (int32_t s : by_level[l]) {
+      rows += S.sn[s].ncols + S.sn[s].nrows;
+      cols += S.sn[s].ncols;
+      max_nc = std::max(max_nc, S.sn[s].ncols);
+    }
+    const bool wide = max_nc > 64;
+    P.fwd_wide[l] = wide ? 1 : 0;
+    // wide forward: rows per task in [4, 64]; backward: columns per task in {4, 8, 12, 16}
+    int32_t rpt = (int32_t)std::min<int64_t>(64, std::max<int64_t>(4, (rows + target - 1) / target));
+    rpt = (rpt + 3) / 4 * 4;
+    int32_t cpt = (int32_t)std::min<int64_t>(kColsPerTask, std::max<int64_t>(4, (cols + target - 1) / target));
+    cpt = (cpt + 3) / 4 * 4;
     for (int32_t s : by_level[l]) {
       const Supernode& sn = S.sn[s];
       const int32_t ld = sn.ncols + sn.nrows;
-      for (int32_t f = 0; f < ld; f += kBlock) P.fwd.push_back({s, f, std::min(kBlock, ld - f), 0});
-      for (int32_t f = 0; f < sn.ncols; f += kColsPerTask)
-        P.bwd.push_back({s, f, std::min(kColsPerTask, sn.ncols - f), 0});
+      const int32_t fstep = wide ? rpt : kBlock;
+      for (int32_t f = 0; f < ld; f += fstep) P.fwd.push_back({s, f, std::min(fstep, ld - f), 0});
+      for (int32_t f = 0; f < sn.ncols; f += cpt) P.bwd.push_back({s, f, std::min(cpt, sn.ncols - f), 0});
       P.fwd_cols[l] = std::max(P.fwd_cols[l], sn.ncols);
       P.bwd_rows[l] = std::max(P.bwd_rows[l], ld);
     }

@@ -80,10 +80,13 @@ constexpr int kBlock = 256;          // threads per workgroup of every kernel
 constexpr int kColsPerTask = 16;     // backward-sweep columns per workgroup
 
 // Level schedule of the sweeps: supernodes of equal tree level are
-// independent.  Forward tasks cover 256 panel rows, backward tasks 16 columns.
+// independent.  Levels whose blocks have more than 64 columns use the
+// wave-per-row forward kernel; task sizes shrink on levels with little work
+// so that every level offers many workgroups.
 struct LevelPlan {
   std::vector<int32_t> fwd_off, bwd_off;   // task ranges per level (size L + 1)
   std::vector<int32_t> fwd_cols, bwd_rows; // dynamic LDS extents per level
+  std::vector<uint8_t> fwd_wide;           // 1: wave-per-row forward kernel (row-major panel)
   std::vector<SweepTask> fwd, bwd;
   // algorithmic traffic of one launch per level: panel entries read (packed
   // lower triangle of the diagonal block plus the off-diagonal block) and the
@@ -100,5 +103,27 @@ void analyse(const HostMesh& m, const Csr& A, int32_t leaf_max, int32_t sep_max,
 bool factor_panels(const Symbolic& S, const Csr& A, std::vector<double>& panels, std::string& err);
 
 void build_plan(const Symbolic& S, LevelPlan& P);
+
+// Row-major copy of every panel (same offsets): element (r, c) of supernode s
+// at panel_off + r * ncols + c.
+template <typename T>
+std::vector<T> transpose_panels(const Symbolic& S, const std::vector<double>& panels) {
+  std::vector<T> out(panels.size());
+  for (const Supernode& sn : S.sn) {
+    const int64_t ld = sn.ncols + sn.nrows;
+    for (int64_t c = 0; c < sn.ncols; ++c)
+      for (int64_t r = 0; r < ld; ++r)
+        out[sn.panel_off + r * sn.ncols + c] = (T)panels[sn.panel_off + c * ld + r];
+  }
+  return out;
+}
+
+// Two-stage mesh creation (api.hip), used by dpd_create_mesh and the server.
+dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
+                       const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options* opt,
+                       dpd_mesh** out);
+int64_t footprint_bytes(const dpd_mesh* m);
+dpd_status upload_device(dpd_mesh* m);
+void destroy_synced(dpd_mesh* m);
 
 }  // namespace dpd

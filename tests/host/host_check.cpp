@@ -8,6 +8,7 @@
 // Python tests can compare them with the oracle.
 //
 // usage: host_check <input.bin> <output.bin>
+#include <algorithm>
 #include <cassert>
 #include <cstdio>
 #include <cstdlib>
@@ -94,6 +95,7 @@ int main(int argc, char** argv) {
   }
   std::vector<int32_t> perm_pub(nf);
   for (int64_t i = 0; i < nf; ++i) perm_pub[i] = m.free_nodes[S.perm[i]];
+  const std::vector<double> panelT = transpose_panels<double>(S, panel);
 
   std::vector<double> X((size_t)nrhs * 3 * N, 0.0);
   for (int64_t rhs = 0; rhs < nrhs; ++rhs) {
@@ -126,9 +128,12 @@ int main(int argc, char** argv) {
           const int cend = r < nc_ ? r + 1 : nc_;
           double a[3] = {0, 0, 0};
           for (int c = 0; c < cend; ++c) {
-            const int64_t pi = sn.panel_off + r + (int64_t)c * ld;
+            // narrow kernel reads the column-major panel, wide kernel the row-major copy
+            const int64_t pi = P.fwd_wide[l] ? sn.panel_off + (int64_t)r * nc_ + c
+                                             : sn.panel_off + r + (int64_t)c * ld;
             CHECK(pi >= 0 && pi < S.panel_size);
-            for (int q = 0; q < 3; ++q) a[q] += panel[pi] * bs[q * nc_ + c];
+            const double pv = P.fwd_wide[l] ? panelT[pi] : panel[pi];
+            for (int q = 0; q < 3; ++q) a[q] += pv * bs[q * nc_ + c];
           }
           if (r < nc_) {
             for (int q = 0; q < 3; ++q) y_int[q * nf + sn.col0 + r] = a[q];
@@ -146,10 +151,13 @@ int main(int argc, char** argv) {
         const Supernode& sn = S.sn[t.sn];
         const int nc_ = sn.ncols, ld = sn.ncols + sn.nrows;
         CHECK(ld <= P.bwd_rows[l]);
+        const int nw = kBlock / 64, cpw = (t.count + nw - 1) / nw;
+        CHECK(cpw <= 4);
         for (int cc = 0; cc < t.count; ++cc) {
           const int c = t.first + cc;
+          const int cw = t.first + (cc / cpw) * cpw;   // first column of the owning wave
           double a[3] = {0, 0, 0};
-          for (int r = c; r < ld; ++r) {
+          for (int r = cw; r < ld; ++r) {
             const int64_t pi = sn.panel_off + (int64_t)c * ld + r;
             CHECK(pi >= 0 && pi < S.panel_size);
             int j;
@@ -173,6 +181,20 @@ int main(int argc, char** argv) {
       }
   }
 
+  if (std::getenv("HOST_CHECK_LEVELS")) {
+    for (int32_t l = 0; l < S.n_levels; ++l) {
+      int nsn = 0, maxld = 0, maxnc = 0;
+      for (auto& sn : S.sn)
+        if (sn.level == l) {
+          nsn++;
+          maxld = std::max(maxld, sn.ncols + sn.nrows);
+          maxnc = std::max(maxnc, sn.ncols);
+        }
+      std::fprintf(stderr, "level %2d supernodes %5d fwd_tasks %6d bwd_tasks %6d max_nc %5d max_ld %5d fwd_MB %8.2f\n",
+                   l, nsn, P.fwd_off[l + 1] - P.fwd_off[l], P.bwd_off[l + 1] - P.bwd_off[l], maxnc, maxld,
+                   P.fwd_bytes[l] / 1e6);
+    }
+  }
   FILE* f = std::fopen(argv[2], "wb");
   int64_t hdr[8] = {N, nf, (int64_t)A.col.size(), (int64_t)S.sn.size(), S.n_levels, S.packed_nnz,
                     (int64_t)P.fwd.size(), (int64_t)P.bwd.size()};

@@ -33,7 +33,8 @@ def test_every_declared_symbol_is_exported_and_bound():
 def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sz.c"
     fields = {"dpd_options": L.Options, "dpd_stats": L.Stats, "dpd_mesh_info": L.MeshInfo,
-              "dpd_kernel_profile": L.KernelProfile}
+              "dpd_kernel_profile": L.KernelProfile, "dpd_request": L.Request,
+              "dpd_result": L.Result}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, cls in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

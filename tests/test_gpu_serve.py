@@ -1,0 +1,121 @@
+"""Rollout server: each result is the same alone and in the mix; admission by HBM budget."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SOLVE = dict(fwd_solver="newton_pcg", fwd_rel_tol=1e-9, fwd_max_iter=100000, bwd_rel_tol=1e-9,
+             bwd_max_iter=100000)
+
+
+def _requests():
+    out = []
+    for r, n in enumerate((2, 5, 3, 4, 2, 3)):
+        sc = W.cantilever(n + 1, n, n, youngs="loguniform", steps=4, seed=r, name=f"r{r}")
+        N = len(W.present_nodes(sc.cells))
+        out.append((sc, W.loss_vector(N, r)))
+    return out
+
+
+def _run(server, reqs):
+    tickets = [server.submit(sc, c, **SOLVE) for sc, c in reqs]
+    server.drain()
+    return [server.poll(t) for t in tickets]
+
+
+def test_alone_equals_in_mix_bitwise():
+    from paper_2101_05917_amd.serve import Server
+    reqs = _requests()
+    alone = []
+    for sc, c in reqs:
+        s = Server(8 << 30, max_slots=1)
+        alone += _run(s, [(sc, c)])
+        s.close()
+    s = Server(8 << 30, max_slots=4)
+    mix = _run(s, reqs)
+    stats = s.stats()
+    s.close()
+    print("mix stats", stats, flush=True)
+    assert stats["peak_active"] >= 2
+    for a, b in zip(alone, mix):
+        assert a.state == "done" and b.state == "done", (a, b)
+        assert a.loss == b.loss
+        assert np.array_equal(a.g_x0, b.g_x0)
+        assert np.array_equal(a.g_v0, b.g_v0)
+        assert np.array_equal(a.g_youngs, b.g_youngs)
+
+
+def test_server_matches_direct_rollout():
+    from paper_2101_05917_amd.serve import Server
+    from paper_2101_05917_amd.mesh import Mesh
+    sc, c = _requests()[1]
+    s = Server(8 << 30, max_slots=2)
+    res = _run(s, [(sc, c)])[0]
+    s.close()
+    mesh = Mesh.from_scene(sc, **SOLVE)
+    X = mesh.rest_positions()
+    x, v = X.clone(), torch.zeros_like(X)
+    xs, vs = [x], [v]
+    for _ in range(sc.steps):
+        x, v, _ = mesh.forward_step(x, v)
+        xs.append(x)
+        vs.append(v)
+    N = mesh.n_nodes
+    cd = torch.from_numpy(np.ascontiguousarray(c.reshape(N, 3).T)).cuda()
+    L = float((cd * xs[-1]).sum())
+    gx, gv = cd.clone(), torch.zeros_like(X)
+    gE = torch.zeros(mesh.n_elements, dtype=torch.float64, device="cuda:0")
+    for t in range(sc.steps - 1, -1, -1):
+        gx, gv, _, _ = mesh.backward_step(xs[t], vs[t], None, xs[t + 1], gx, gv, g_youngs=gE)
+    assert abs(L - res.loss) <= 1e-13 * abs(L)
+    assert np.allclose(res.g_x0, gx.cpu().numpy(), rtol=0, atol=1e-12 * np.abs(res.g_x0).max())
+    assert np.allclose(res.g_youngs, gE.cpu().numpy(), rtol=0,
+                       atol=1e-12 * np.abs(res.g_youngs).max())
+
+
+def test_admission_respects_budget_and_rejects_oversized():
+    from paper_2101_05917_amd.serve import Server
+    reqs = _requests()
+    probe = Server(8 << 30, max_slots=1)
+    fps = [r.footprint_bytes for r in _run(probe, reqs)]
+    probe.close()
+    budget = int(1.2 * max(fps))
+    s = Server(budget, max_slots=6)
+    res = _run(s, reqs)
+    st = s.stats()
+    assert all(r.state == "done" for r in res)
+    assert st["peak_bytes"] <= budget
+    # the budget holds the largest request plus a few small ones at most
+    assert st["peak_active"] < len(reqs)
+    big = W.cantilever(8, 8, 8, steps=2)
+    N = len(W.present_nodes(big.cells))
+    t = s.submit(big, W.loss_vector(N, 0), **SOLVE)
+    s.drain()
+    r = s.poll(t)
+    assert r.state == "failed" and r.status == -3
+    s.close()
+
+
+def test_requests_join_while_others_run():
+    from paper_2101_05917_amd.serve import Server
+    import time
+    reqs = _requests()
+    s = Server(8 << 30, max_slots=3)
+    long_sc = W.cantilever(8, 4, 4, youngs="loguniform", steps=40, seed=9, name="long")
+    N = len(W.present_nodes(long_sc.cells))
+    first = [s.submit(long_sc, W.loss_vector(N, 9), **SOLVE)]
+    t0 = time.time()
+    while s.poll(first[0], gradients=False).state == "queued" and time.time() - t0 < 60:
+        time.sleep(0.002)
+    later = [s.submit(sc, c, **SOLVE) for sc, c in reqs]
+    s.drain()
+    res = [s.poll(t) for t in first + later]
+    st = s.stats()
+    s.close()
+    assert all(r.state == "done" for r in res)
+    # requests submitted while the long one ran were admitted and finished before it
+    assert min(r.t_admit for r in res[1:]) < res[0].t_done
+    assert st["peak_active"] >= 2
