@@ -30,8 +30,12 @@ sys.path.insert(0, HERE)
 import workloads as W  # noqa: E402
 
 
-KERNEL_NAMES = {"sweep_fwd": "k_sweep_fwd (forward triangular sweep, one tree level per launch)",
+KERNEL_NAMES = {"solve": "global step A^{-1} b: k_solve_small (every level of both sweeps in one "
+                         "workgroup) for small factors, else the per-level k_sweep_* launches",
+                "sweep_fwd": "k_sweep_fwd (forward triangular sweep, one tree level per launch)",
                 "sweep_bwd": "k_sweep_bwd (backward triangular sweep, one tree level per launch)",
+                "sweep_fwd_wide": "k_sweep_gather + k_sweep_fwd_wide (forward sweep level with wide blocks)",
+                "sweep_bwd_narrow": "k_sweep_bwd_narrow (backward sweep level of many small blocks)",
                 "elem_hvp": "k_elem_hvp (adjoint local step dA p)",
                 "elem_forces": "k_elem_forces (forward local step)"}
 
@@ -50,33 +54,62 @@ def parse():
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--checkpoint-every", type=int, default=0,
+                    help="keep every K-th state and recompute segments (default: 20 for c3, else 1)")
+    ap.add_argument("--check-checkpointing", action="store_true",
+                    help="also run the rollout storing every state and compare the gradients")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run one plain device copy of this many bytes (counter scaling)")
     ap.add_argument("--requests", type=int, default=64, help="c4: number of requests")
     ap.add_argument("--max-cube", type=int, default=24, help="c4: largest cube side (cells)")
-    ap.add_argument("--rate", type=float, default=float("inf"), help="c4: Poisson arrival rate")
+    ap.add_argument("--rate", type=float, default=1.1,
+                    help="c4: Poisson arrival rate, requests/s (inf: all at t = 0)")
     ap.add_argument("--slots", type=int, default=8, help="c4: resident requests")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
-    ap.add_argument("--roofline-kernel", default="sweep_fwd",
-                    choices=["sweep_fwd", "sweep_bwd", "elem_hvp", "elem_forces"])
+    ap.add_argument("--roofline-kernel", default=None,
+                    choices=["solve", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
+                             "elem_hvp", "elem_forces"])
     return ap.parse_args()
 
 
-def rollout(mesh, X, c_dev, T, torch):
-    """Forward T steps, then the adjoint back to step 0.  Returns gradients."""
+def rollout(mesh, X, c_dev, T, torch, acts=None, checkpoint_every=1):
+    """Forward T steps, then the adjoint back to step 0.  Returns gradients.
+
+    With checkpoint_every = K > 1 only every K-th state is kept in the forward
+    pass and each segment's states are recomputed before its adjoint steps."""
+    K = max(1, checkpoint_every)
     x = X.clone()
     v = torch.zeros_like(X)
-    xs, vs = [x], [v]
+    ck = {0: (x, v)}
     fwd_iters = bwd_iters = 0
-    for _ in range(T):
-        x, v, st = mesh.forward_step(x, v)
-        xs.append(x)
-        vs.append(v)
+    for t in range(T):
+        x, v, st = mesh.forward_step(x, v, None if acts is None else acts[t])
         fwd_iters += st["fwd_iters"]
+        if K == 1 or (t + 1) % K == 0 or t + 1 == T:
+            ck[t + 1] = (x, v)
+    xT = x
     gx, gv = c_dev.clone(), torch.zeros_like(X)
     gE = torch.zeros(mesh.n_elements, dtype=torch.float64, device=X.device)
-    for t in range(T - 1, -1, -1):
-        gx, gv, _, st = mesh.backward_step(xs[t], vs[t], None, xs[t + 1], gx, gv, g_youngs=gE)
-        bwd_iters += st["bwd_iters"]
-    return xs[-1], gx, gv, gE, fwd_iters, bwd_iters
+    g_act = [] if acts is not None else None
+    for s0 in reversed(range(0, T, K)):
+        s1 = min(s0 + K, T)
+        xs, vs = [ck[s0][0]], [ck[s0][1]]
+        for t in range(s0, s1 - 1):              # recompute the segment's inner states
+            xn, vn, _ = mesh.forward_step(xs[-1], vs[-1], None if acts is None else acts[t])
+            xs.append(xn)
+            vs.append(vn)
+        xs.append(ck[s1][0])
+        vs.append(ck[s1][1])
+        for t in range(s1 - 1, s0 - 1, -1):
+            a = None if acts is None else acts[t]
+            gx, gv, ga, st = mesh.backward_step(xs[t - s0], vs[t - s0], a, xs[t - s0 + 1], gx, gv,
+                                                g_youngs=gE, want_act=acts is not None)
+            bwd_iters += st["bwd_iters"]
+            if g_act is not None:
+                g_act.append(ga)
+    if g_act is not None:
+        g_act = torch.stack(g_act[::-1])
+    return xT, gx, gv, gE, g_act, fwd_iters, bwd_iters
 
 
 def cpu_baseline(scene, T_budget_s):
@@ -155,9 +188,50 @@ def serve_bench(args):
     }
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2101_05917_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str, precision: str):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in
+    profiles/traffic.json (each scaled by the plain-copy calibration), or None
+    if none was taken for this kernel or the kernel sources changed since."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload, {}).get(f"{kernel}/{precision}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+
+
+def copy_calibration(nbytes: int):
+    """A plain device copy of nbytes (read nbytes, write nbytes), for scaling
+    the FETCH_SIZE / WRITE_SIZE hardware counters to bytes."""
+    import torch
+    n = nbytes // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8}), flush=True)
+
+
 def main():
     args = parse()
-    if args.config == "c4":
+    if args.roofline_kernel is None:
+        # the kernel with the largest share of GPU time in the rocprofv3 summary of each workload
+        args.roofline_kernel = {"c5": "sweep_fwd_wide"}.get(args.config, "sweep_bwd")
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.config == "c4":  # served batch
         if args.gpus != 1:
             print("bench.py runs on exactly one GPU", file=sys.stderr)
             sys.exit(2)
@@ -180,13 +254,18 @@ def main():
     c = W.loss_vector(N, scene.loss_seed)
     c_dev = torch.from_numpy(np.ascontiguousarray(c.reshape(N, 3).T)).to(X.device)
 
+    acts = None
+    if scene.muscle_k > 0:
+        a = W.actuation_sequence(T, mesh.n_elements, seed=scene.act_seed)
+        acts = torch.from_numpy(np.ascontiguousarray(a)).to(X.device)
+    K = args.checkpoint_every if args.checkpoint_every else (20 if args.config == "c3" else 1)
     for _ in range(args.warmup):
-        rollout(mesh, X, c_dev, T, torch)
+        rollout(mesh, X, c_dev, T, torch, acts, K)
     torch.cuda.synchronize()
     mesh.profile_start(args.roofline_kernel)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        xT, gx, gv, gE, fi, bi = rollout(mesh, X, c_dev, T, torch)
+        xT, gx, gv, gE, g_act, fi, bi = rollout(mesh, X, c_dev, T, torch, acts, K)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     prof = mesh.profile_read()
@@ -195,7 +274,8 @@ def main():
     bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": None,
+                "frac": achieved / 8000.0,
+                "traffic": measured_traffic(scene.name, args.roofline_kernel, args.precision),
                 "kernel": KERNEL_NAMES[args.roofline_kernel],
                 "launches": prof["launches"], "avg_us": avg_ms * 1e3,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
@@ -211,6 +291,13 @@ def main():
             err = {"g_x0": float(np.linalg.norm(gx_np - ref["g_x0"]) / np.linalg.norm(ref["g_x0"])),
                    "g_youngs": float(np.linalg.norm(gE_np - ref["g_youngs"]) /
                                      np.linalg.norm(ref["g_youngs"]))}
+
+    ckpt_check = None
+    if args.check_checkpointing and K > 1:
+        _, gx1, gv1, gE1, ga1, _, _ = rollout(mesh, X, c_dev, T, torch, acts, 1)
+        ckpt_check = {"checkpoint_every": K,
+                      "bitwise_equal_to_stored": bool(torch.equal(gx, gx1) and torch.equal(gE, gE1) and
+                                                      (g_act is None or torch.equal(g_act, ga1)))}
 
     out = {
         "metric": "DoF-steps/s fwd+adjoint at 1e-6 rel grad error",
@@ -232,6 +319,7 @@ def main():
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,
         "grad_rel_err_vs_oracle": err,
+        "checkpointing": {"checkpoint_every": K, "check": ckpt_check},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

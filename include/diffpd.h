@@ -212,8 +212,16 @@ dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* 
  * in every 16 of the class is timed (two event records each), so the totals
  * describe that sample; launches that exit early because their iteration had
  * already converged are not counted.  Class DPD_PROF_OFF disables timing. */
-enum { DPD_PROF_OFF = 0, DPD_PROF_SWEEP_FWD = 1, DPD_PROF_SWEEP_BWD = 2, DPD_PROF_ELEM_HVP = 3,
-       DPD_PROF_ELEM_FORCES = 4 };
+enum {
+  DPD_PROF_OFF = 0,
+  DPD_PROF_SWEEP_FWD = 1,        /* k_sweep_fwd: forward level, blocks of <= 64 columns     */
+  DPD_PROF_SWEEP_BWD = 2,        /* k_sweep_bwd: backward level, column tasks               */
+  DPD_PROF_ELEM_HVP = 3,         /* k_elem_hvp: adjoint local step                          */
+  DPD_PROF_ELEM_FORCES = 4,      /* k_elem_forces: forward local step                       */
+  DPD_PROF_SOLVE = 5,            /* a whole A^{-1} b, all of its launches                   */
+  DPD_PROF_SWEEP_FWD_WIDE = 6,   /* k_sweep_fwd_wide: forward level, wide blocks            */
+  DPD_PROF_SWEEP_BWD_NARROW = 7  /* k_sweep_bwd_narrow: backward level of many small blocks */
+};
 typedef struct {
   int64_t launches;
   double total_ms;         /* summed event-measured durations                    */

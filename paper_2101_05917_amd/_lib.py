@@ -72,7 +72,8 @@ class Result(C.Structure):
                 ("fwd_iters", C.c_int64), ("bwd_iters", C.c_int64)]
 
 
-DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4}
+DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4, "solve": 5,
+            "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7}
 
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)

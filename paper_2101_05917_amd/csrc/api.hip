@@ -22,8 +22,8 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int32_t kLeafMax = 64;
-constexpr int32_t kSepMax = 1024;
-constexpr int64_t kLdsBudget = 48 * 1024;
+constexpr int32_t kSepMax = 2048;
+constexpr int64_t kLdsBudget = 60 * 1024;
 constexpr int64_t kProfStride = 16;
 
 }  // namespace
@@ -51,6 +51,8 @@ struct dpd_mesh {
   // device buffers
   SweepTask* d_fwd = nullptr;
   SweepTask* d_bwd = nullptr;
+  int32_t* d_gather = nullptr;
+  double solve_bytes = 0.0, solve_flops = 0.0;   // algorithmic work of one A^{-1} b
   double* w_e = nullptr;
   double* panel64 = nullptr;
   float* panel32 = nullptr;
@@ -176,15 +178,19 @@ void prof_harvest(dpd_mesh* m) {
 void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, double alpha,
            int accumulate, const IterState* st, int k = 0) {
   const int st_idx = st == nullptr ? -1 : (st == m->st ? 0 : 1);
+  const double scale = fp32 ? 0.5 : 1.0;
+  ProfScope whole(m, s, DPD_PROF_SOLVE, m->solve_bytes * scale, m->solve_flops, st_idx, k);
+
   const LevelPlan& P = m->plan;
   const int32_t L = m->S.n_levels;
   for (int32_t l = 0; l < L; ++l) {
     const int n = P.fwd_off[l + 1] - P.fwd_off[l];
     if (!n) continue;
-    const double scale = fp32 ? 0.5 : 1.0;
-    ProfScope ps(m, s, DPD_PROF_SWEEP_FWD, P.fwd_bytes[l] * scale, P.fwd_flops[l], st_idx, k);
+    ProfScope ps(m, s, P.fwd_wide[l] ? DPD_PROF_SWEEP_FWD_WIDE : DPD_PROF_SWEEP_FWD,
+                 P.fwd_bytes[l] * scale, P.fwd_flops[l], st_idx, k);
     if (P.fwd_wide[l])
-      launch_sweep_fwd_wide(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
+      launch_sweep_fwd_wide(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N,
+                            m->d_gather + P.gather_off[l], P.gather_off[l + 1] - P.gather_off[l], st);
     else
       launch_sweep_fwd(m->ds, s, m->d_fwd + P.fwd_off[l], n, P.fwd_cols[l], fp32, b, m->dm.N, st);
   }
@@ -192,10 +198,14 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
     const int n = P.bwd_off[l + 1] - P.bwd_off[l];
     const bool lds = (int64_t)3 * P.bwd_rows[l] * (int64_t)sizeof(double) <= kLdsBudget;
     if (!n) continue;
-    ProfScope ps(m, s, DPD_PROF_SWEEP_BWD, P.bwd_bytes[l] * (fp32 ? 0.5 : 1.0), P.bwd_flops[l],
-                 st_idx, k);
-    launch_sweep_bwd(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], lds, fp32, out, m->dm.N,
-                     alpha, accumulate, st);
+    ProfScope ps(m, s, P.bwd_narrow[l] ? DPD_PROF_SWEEP_BWD_NARROW : DPD_PROF_SWEEP_BWD,
+                 P.bwd_bytes[l] * (fp32 ? 0.5 : 1.0), P.bwd_flops[l], st_idx, k);
+    if (P.bwd_narrow[l])
+      launch_sweep_bwd_narrow(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], fp32, out, m->dm.N,
+                              alpha, accumulate, st);
+    else
+      launch_sweep_bwd(m->ds, s, m->d_bwd + P.bwd_off[l], n, P.bwd_rows[l], lds, fp32, out, m->dm.N,
+                       alpha, accumulate, st);
   }
 }
 
@@ -356,7 +366,8 @@ int64_t footprint_bytes(const dpd_mesh* m) {
   b += (int64_t)S.sn.size() * (3 * 4 + 3 * 8) + 4 * (int64_t)S.rows.size();
   b += 4 * ((int64_t)S.cptr.size() + (int64_t)S.cidx.size());
   b += 16 * (int64_t)(m->plan.fwd.size() + m->plan.bwd.size());
-  b += 8 * (6 * nf + 3 * S.u_size + 24 * E + 8 * 3 * N);    // sweep vectors, fe, work vectors
+  b += 8 * (9 * nf + 3 * S.u_size + 24 * E + 8 * 3 * N);    // sweep vectors, fe, work vectors
+  b += 4 * (int64_t)m->plan.gather_cols.size();
   b += 8 * ((int64_t)kAdjCacheRows * 8 * E + std::max<int64_t>(N, 8 * E) / kBlock + 16);
   b += 2 * 8 * S.panel_size;                                 // FP64 panels, both layouts
   if (m->opt.precision == DPD_MIXED) b += 2 * 4 * S.panel_size;  // FP32 copies
@@ -372,20 +383,9 @@ dpd_status upload_device(dpd_mesh* m) {
     for (int a = 0; a < 8; ++a) conn_soa[a * E + el] = hm.conn[8 * el + a];
   std::vector<int32_t> perm_pub(nf);
   for (int64_t i = 0; i < nf; ++i) perm_pub[i] = hm.free_nodes[m->S.perm[i]];
-  std::vector<int32_t> col0, ncols, nrows;
-  std::vector<int64_t> roff, poff, uoff;
-  for (auto& s : m->S.sn) {
-    col0.push_back(s.col0);
-    ncols.push_back(s.ncols);
-    nrows.push_back(s.nrows);
-    roff.push_back(s.rows_off);
-    poff.push_back(s.panel_off);
-    uoff.push_back(s.u_off);
-  }
   dpd_status st = DPD_OK;
   double *X, *mass;
-  int32_t *conn, *inc, *pp, *c0, *nc, *nr, *rows, *cptr, *cidx;
-  int64_t *ro, *po, *uo;
+  int32_t *conn, *inc, *pp, *rows, *cptr, *cidx;
   uint8_t *fixed, *contact;
 #define UP(ptr, vec)                       \
   if ((st = upload(m, &ptr, vec)) != DPD_OK) { \
@@ -400,17 +400,16 @@ dpd_status upload_device(dpd_mesh* m) {
   UP(contact, hm.is_contact);
   UP(m->w_e, corotated_weights(hm, m->opt));
   UP(pp, perm_pub);
-  UP(c0, col0);
-  UP(nc, ncols);
-  UP(nr, nrows);
-  UP(ro, roff);
-  UP(po, poff);
-  UP(uo, uoff);
   UP(rows, m->S.rows);
   UP(cptr, m->S.cptr);
   UP(cidx, m->S.cidx);
   UP(m->d_fwd, m->plan.fwd);
   UP(m->d_bwd, m->plan.bwd);
+  UP(m->d_gather, m->plan.gather_cols);
+  for (int32_t l = 0; l < m->S.n_levels; ++l) {
+    m->solve_bytes += m->plan.fwd_bytes[l] + m->plan.bwd_bytes[l];
+    m->solve_flops += m->plan.fwd_flops[l] + m->plan.bwd_flops[l];
+  }
 #undef UP
   DevMesh& d = m->dm;
   d.X = X;
@@ -423,12 +422,6 @@ dpd_status upload_device(dpd_mesh* m) {
   DevSolve& ds = m->ds;
   ds.nf = (int32_t)nf;
   ds.perm_pub = pp;
-  ds.sn_col0 = c0;
-  ds.sn_ncols = nc;
-  ds.sn_nrows = nr;
-  ds.sn_rows_off = ro;
-  ds.sn_panel_off = po;
-  ds.sn_u_off = uo;
   ds.rows = rows;
   ds.cptr = cptr;
   ds.cidx = cidx;
@@ -440,6 +433,7 @@ dpd_status upload_device(dpd_mesh* m) {
   AL(ds.y_int, 3 * nf);
   AL(ds.x_int, 3 * nf);
   AL(ds.U, 3 * m->S.u_size);
+  AL(ds.bt, 3 * nf);
   AL(m->fe, 3 * 8 * E);
   AL(m->r, 3 * N);
   AL(m->y, 3 * N);
@@ -855,7 +849,7 @@ dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_o
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_ELEM_FORCES)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_SWEEP_BWD_NARROW)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   m->prof_class = kernel_class;
   m->prof_launches = 0;

@@ -24,12 +24,6 @@ struct IterState {
 struct DevSolve {
   int32_t nf;                 // free nodes
   const int32_t* perm_pub;    // [nf] internal index -> public node id
-  const int32_t* sn_col0;
-  const int32_t* sn_ncols;
-  const int32_t* sn_nrows;
-  const int64_t* sn_rows_off;
-  const int64_t* sn_panel_off;
-  const int64_t* sn_u_off;
   const int32_t* rows;        // concatenated R_s (internal)
   const int32_t* cptr;        // [nf + 1]
   const int32_t* cidx;        // positions into U
@@ -40,6 +34,7 @@ struct DevSolve {
   double* y_int;              // [3][nf]
   double* x_int;              // [3][nf]
   double* U;                  // [u_size][3]
+  double* bt;                 // [3][nf] gathered right-hand sides of pre-gathered levels
 };
 
 struct DevMesh {
@@ -58,6 +53,7 @@ struct DevMesh {
 };
 
 constexpr int kElemsPerBlock = kBlock / 8;
+
 
 }  // namespace dpd
 
@@ -79,7 +75,11 @@ void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v);
 void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                       int lds_cols, bool fp32, const double* b, int N, const IterState* st);
 void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
-                           int lds_cols, bool fp32, const double* b, int N, const IterState* st);
+                           int lds_cols, bool fp32, const double* b, int N, const int32_t* gather_cols,
+                           int n_gather, const IterState* st);
+void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                             int lds_rows, bool fp32, double* out, int N, double alpha, int accumulate,
+                             const IterState* st);
 void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                       int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
                       int accumulate, const IterState* st);

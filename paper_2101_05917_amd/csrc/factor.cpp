@@ -324,6 +324,20 @@ bool factor_panels(const Symbolic& S, const Csr& A, std::vector<double>& panels,
   return true;
 }
 
+static SweepTask make_task(const Supernode& sn, int32_t s, int32_t first, int32_t count) {
+  SweepTask t{};
+  t.sn = s;
+  t.first = first;
+  t.count = count;
+  t.col0 = sn.col0;
+  t.ncols = sn.ncols;
+  t.nrows = sn.nrows;
+  t.panel_off = sn.panel_off;
+  t.rows_off = sn.rows_off;
+  t.u_off = sn.u_off;
+  return t;
+}
+
 void build_plan(const Symbolic& S, LevelPlan& P) {
   const int32_t L = S.n_levels;
   std::vector<std::vector<int32_t>> by_level(L);
@@ -335,6 +349,7 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
   P.fwd_cols.assign(L, 0);
   P.bwd_rows.assign(L, 0);
   P.fwd_wide.assign(L, 0);
+  P.bwd_narrow.assign(L, 0);
   const int64_t target = 2048;  // workgroups wanted per level
   for (int32_t l = 0; l < L; ++l) {
     P.fwd_off[l] = (int32_t)P.fwd.size();
@@ -348,6 +363,11 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     }
     const bool wide = max_nc > 64;
     P.fwd_wide[l] = wide ? 1 : 0;
+    int32_t max_ld = 0;
+    for (int32_t s : by_level[l]) max_ld = std::max(max_ld, S.sn[s].ncols + S.sn[s].nrows);
+    // many small supernodes: one backward task each (LDS holds 3 x ld doubles)
+    const bool narrow_b = !wide && (int64_t)by_level[l].size() >= 256 && max_ld <= 2048;
+    P.bwd_narrow[l] = narrow_b ? 1 : 0;
     // wide forward: rows per task in [4, 64]; backward: columns per task in {4, 8, 12, 16}
     int32_t rpt = (int32_t)std::min<int64_t>(64, std::max<int64_t>(4, (rows + target - 1) / target));
     rpt = (rpt + 3) / 4 * 4;
@@ -357,12 +377,27 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
       const Supernode& sn = S.sn[s];
       const int32_t ld = sn.ncols + sn.nrows;
       const int32_t fstep = wide ? rpt : kBlock;
-      for (int32_t f = 0; f < ld; f += fstep) P.fwd.push_back({s, f, std::min(fstep, ld - f), 0});
-      for (int32_t f = 0; f < sn.ncols; f += cpt) P.bwd.push_back({s, f, std::min(cpt, sn.ncols - f), 0});
+      for (int32_t f = 0; f < ld; f += fstep) P.fwd.push_back(make_task(sn, s, f, std::min(fstep, ld - f)));
+      if (narrow_b)
+        P.bwd.push_back(make_task(sn, s, 0, sn.ncols));
+      else
+        for (int32_t f = 0; f < sn.ncols; f += cpt) P.bwd.push_back(make_task(sn, s, f, std::min(cpt, sn.ncols - f)));
       P.fwd_cols[l] = std::max(P.fwd_cols[l], sn.ncols);
       P.bwd_rows[l] = std::max(P.bwd_rows[l], ld);
     }
   }
+  // pre-gather on wide levels whose supernodes are split into several tasks
+  P.gather_off.assign(L + 1, 0);
+  P.gather_cols.clear();
+  for (int32_t l = 0; l < L; ++l) {
+    P.gather_off[l] = (int32_t)P.gather_cols.size();
+    const int32_t ntask = P.fwd_off[l + 1] - P.fwd_off[l];
+    const int32_t nsn = (int32_t)by_level[l].size();
+    if (P.fwd_wide[l] && ntask >= 4 * nsn)
+      for (int32_t s : by_level[l])
+        for (int32_t c = 0; c < S.sn[s].ncols; ++c) P.gather_cols.push_back(S.sn[s].col0 + c);
+  }
+  P.gather_off[L] = (int32_t)P.gather_cols.size();
   P.fwd_bytes.assign(L, 0.0);
   P.bwd_bytes.assign(L, 0.0);
   P.fwd_flops.assign(L, 0.0);
@@ -374,6 +409,8 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
       double contribs = 0;
       for (int32_t j = sn.col0; j < sn.col0 + sn.ncols; ++j) contribs += S.cptr[j + 1] - S.cptr[j];
       // forward: panel, b_s and incoming updates read, y_s and outgoing updates written
+      // (pre-gathered levels read the gathered b~_s instead: the gather pass
+      // is timed with its level)
       P.fwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + contribs) + 24.0 * (nc + nr) + 4.0 * contribs;
       // backward: panel, y_s and x_R read, x_s written (internal and public copies)
       P.bwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + nr) + 4.0 * nr + 48.0 * nc;

@@ -71,9 +71,12 @@ struct Symbolic {
   int64_t panel_size = 0, u_size = 0, packed_nnz = 0;
 };
 
-// Task of a triangular-sweep level: supernode s, first row/column, count.
+// Task of a triangular-sweep level: supernode s, first row/column, count, and
+// a copy of the supernode's fields so a kernel reads them in one load.
 struct SweepTask {
-  int32_t sn, first, count, pad;
+  int32_t sn, first, count, col0;
+  int32_t ncols, nrows, pad0, pad1;
+  int64_t panel_off, rows_off, u_off, pad2;
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of every kernel
@@ -87,6 +90,11 @@ struct LevelPlan {
   std::vector<int32_t> fwd_off, bwd_off;   // task ranges per level (size L + 1)
   std::vector<int32_t> fwd_cols, bwd_rows; // dynamic LDS extents per level
   std::vector<uint8_t> fwd_wide;           // 1: wave-per-row forward kernel (row-major panel)
+  std::vector<uint8_t> bwd_narrow;         // 1: one task per supernode, lanes over columns
+  // levels whose supernodes span many tasks gather their right-hand sides once
+  // in a separate pass: the internal columns of those supernodes per level
+  std::vector<int32_t> gather_off;         // size L + 1 (empty range: gather inside the tasks)
+  std::vector<int32_t> gather_cols;
   std::vector<SweepTask> fwd, bwd;
   // algorithmic traffic of one launch per level: panel entries read (packed
   // lower triangle of the diagonal block plus the off-diagonal block) and the

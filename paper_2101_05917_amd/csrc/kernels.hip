@@ -472,229 +472,6 @@ __global__ void __launch_bounds__(kBlock) k_velocity(int N, double inv_h, const 
   if (i < 3 * (int64_t)N) vn[i] = (xn[i] - x[i]) * inv_h;
 }
 
-// ------------------------------------------------------------------ triangular sweeps
-
-// Forward sweep of one level: for each task (supernode s, rows [first, first+count)),
-// b~_s = b_s + (updates of s's descendants), then rows < ncols give y_s = inv(L_ss) b~_s
-// and the remaining rows give the update -L_Rs inv(L_ss) b~_s for s's ancestors.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTask* __restrict__ tasks,
-                                                      const T* __restrict__ panel,
-                                                      const double* __restrict__ b, int N,
-                                                      const IterState* st) {
-  if (st && st->done) return;
-  extern __shared__ double bs[];
-  const SweepTask t = tasks[blockIdx.x];
-  const int s = t.sn;
-  const int col0 = S.sn_col0[s], nc = S.sn_ncols[s], nr = S.sn_nrows[s], ld = nc + nr;
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    const int j = col0 + c;
-    const int node = S.perm_pub[j];
-    double v0 = b[node], v1 = b[(int64_t)N + node], v2 = b[2 * (int64_t)N + node];
-    for (int k = S.cptr[j]; k < S.cptr[j + 1]; ++k) {
-      const int64_t pos = 3 * (int64_t)S.cidx[k];
-      v0 += S.U[pos];
-      v1 += S.U[pos + 1];
-      v2 += S.U[pos + 2];
-    }
-    bs[c] = v0;
-    bs[nc + c] = v1;
-    bs[2 * nc + c] = v2;
-  }
-  __syncthreads();
-  if ((int)threadIdx.x >= t.count) return;
-  const int r = t.first + threadIdx.x;
-  const T* P = panel + S.sn_panel_off[s] + r;
-  const int cend = r < nc ? r + 1 : nc;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  int c = 0;
-  for (; c + 4 <= cend; c += 4) {
-    const double p0 = (double)P[(int64_t)(c + 0) * ld], p1 = (double)P[(int64_t)(c + 1) * ld];
-    const double p2 = (double)P[(int64_t)(c + 2) * ld], p3 = (double)P[(int64_t)(c + 3) * ld];
-    a0 += p0 * bs[c] + p1 * bs[c + 1] + p2 * bs[c + 2] + p3 * bs[c + 3];
-    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 1] + p2 * bs[nc + c + 2] + p3 * bs[nc + c + 3];
-    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 1] + p2 * bs[2 * nc + c + 2] +
-          p3 * bs[2 * nc + c + 3];
-  }
-  for (; c < cend; ++c) {
-    const double p = (double)P[(int64_t)c * ld];
-    a0 += p * bs[c];
-    a1 += p * bs[nc + c];
-    a2 += p * bs[2 * nc + c];
-  }
-  if (r < nc) {
-    const int j = col0 + r;
-    S.y_int[j] = a0;
-    S.y_int[(int64_t)S.nf + j] = a1;
-    S.y_int[2 * (int64_t)S.nf + j] = a2;
-  } else {
-    const int64_t pos = 3 * (S.sn_u_off[s] + (r - nc));
-    S.U[pos] = a0;
-    S.U[pos + 1] = a1;
-    S.U[pos + 2] = a2;
-  }
-}
-
-// Forward sweep of one level for supernodes with wide blocks: the panel is
-// read from its row-major copy, one wave per row (lanes over the contiguous
-// columns, then a wave reduction), so long rows stream with full memory-level
-// parallelism instead of one column at a time per thread.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
-                                                           const T* __restrict__ panelT,
-                                                           const double* __restrict__ b, int N,
-                                                           const IterState* st) {
-  if (st && st->done) return;
-  extern __shared__ double bs[];
-  const SweepTask t = tasks[blockIdx.x];
-  const int s = t.sn;
-  const int col0 = S.sn_col0[s], nc = S.sn_ncols[s];
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    const int j = col0 + c;
-    const int node = S.perm_pub[j];
-    double v0 = b[node], v1 = b[(int64_t)N + node], v2 = b[2 * (int64_t)N + node];
-    for (int k = S.cptr[j]; k < S.cptr[j + 1]; ++k) {
-      const int64_t pos = 3 * (int64_t)S.cidx[k];
-      v0 += S.U[pos];
-      v1 += S.U[pos + 1];
-      v2 += S.U[pos + 2];
-    }
-    bs[c] = v0;
-    bs[nc + c] = v1;
-    bs[2 * nc + c] = v2;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const T* Pb = panelT + S.sn_panel_off[s];
-  for (int rr = wid; rr < t.count; rr += nw) {
-    const int r = t.first + rr;
-    const T* row = Pb + (int64_t)r * nc;
-    const int cend = r < nc ? r + 1 : nc;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    int c = lane;
-    for (; c + 192 < cend; c += 256) {
-      const double p0 = (double)row[c], p1 = (double)row[c + 64];
-      const double p2 = (double)row[c + 128], p3 = (double)row[c + 192];
-      a0 += p0 * bs[c] + p1 * bs[c + 64] + p2 * bs[c + 128] + p3 * bs[c + 192];
-      a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 64] + p2 * bs[nc + c + 128] + p3 * bs[nc + c + 192];
-      a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 64] + p2 * bs[2 * nc + c + 128] +
-            p3 * bs[2 * nc + c + 192];
-    }
-    for (; c < cend; c += 64) {
-      const double p = (double)row[c];
-      a0 += p * bs[c];
-      a1 += p * bs[nc + c];
-      a2 += p * bs[2 * nc + c];
-    }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    a2 = wave_sum(a2);
-    if (lane == 0) {
-      if (r < nc) {
-        const int j = col0 + r;
-        S.y_int[j] = a0;
-        S.y_int[(int64_t)S.nf + j] = a1;
-        S.y_int[2 * (int64_t)S.nf + j] = a2;
-      } else {
-        const int64_t pos = 3 * (S.sn_u_off[s] + (r - nc));
-        S.U[pos] = a0;
-        S.U[pos + 1] = a1;
-        S.U[pos + 2] = a2;
-      }
-    }
-  }
-}
-
-// Backward sweep of one level: for each task (supernode s, columns [first, first+count)),
-// x_s = inv(L_ss)^T y_s + (-L_Rs inv(L_ss))^T x_R, one wave per column.
-// out[perm] = alpha x (+ out if accumulate).
-template <typename T, bool kLds>
-__global__ void __launch_bounds__(kBlock) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
-                                                      const T* __restrict__ panel,
-                                                      double* __restrict__ out, int N, double alpha,
-                                                      int accumulate, const IterState* st) {
-  if (st && st->done) return;
-  extern __shared__ double vs[];
-  const SweepTask t = tasks[blockIdx.x];
-  const int s = t.sn;
-  const int col0 = S.sn_col0[s], nc = S.sn_ncols[s], nr = S.sn_nrows[s], ld = nc + nr;
-  const int64_t nf = S.nf;
-  const int* rows = S.rows + S.sn_rows_off[s];
-  if (kLds) {
-    for (int r = threadIdx.x; r < ld; r += blockDim.x) {
-      const double* src = S.y_int;
-      int j = col0 + r;
-      if (r >= nc) {
-        src = S.x_int;
-        j = rows[r - nc];
-      }
-      vs[r] = src[j];
-      vs[ld + r] = src[nf + j];
-      vs[2 * ld + r] = src[2 * nf + j];
-    }
-    __syncthreads();
-  }
-  // wave w owns columns [cw, cw + cpw) of the task (cpw <= 4)
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int cpw = (t.count + nw - 1) / nw;
-  const int cw = t.first + wid * cpw;
-  const int nown = min(cpw, t.first + t.count - cw);
-  if (nown <= 0) return;
-  const T* Pb = panel + S.sn_panel_off[s] + (int64_t)cw * ld;
-  double acc[4][3];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-  for (int r = cw + lane; r < ld; r += 64) {
-    double v0, v1, v2;
-    if (kLds) {
-      v0 = vs[r];
-      v1 = vs[ld + r];
-      v2 = vs[2 * ld + r];
-    } else {
-      const double* src = S.y_int;
-      int j = col0 + r;
-      if (r >= nc) {
-        src = S.x_int;
-        j = rows[r - nc];
-      }
-      v0 = src[j];
-      v1 = src[nf + j];
-      v2 = src[2 * nf + j];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < nown) {
-        // rows above a column's diagonal hold explicit zeros in the panel
-        const double p = (double)Pb[(int64_t)q * ld + r];
-        acc[q][0] += p * v0;
-        acc[q][1] += p * v1;
-        acc[q][2] += p * v2;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q >= nown) break;
-    const double a0 = wave_sum(acc[q][0]), a1 = wave_sum(acc[q][1]), a2 = wave_sum(acc[q][2]);
-    if (lane == 0) {
-      const int j = col0 + cw + q;
-      S.x_int[j] = a0;
-      S.x_int[nf + j] = a1;
-      S.x_int[2 * nf + j] = a2;
-      const int node = S.perm_pub[j];
-      if (accumulate) {
-        out[node] += alpha * a0;
-        out[(int64_t)N + node] += alpha * a1;
-        out[2 * (int64_t)N + node] += alpha * a2;
-      } else {
-        out[node] = alpha * a0;
-        out[(int64_t)N + node] = alpha * a1;
-        out[2 * (int64_t)N + node] = alpha * a2;
-      }
-    }
-  }
-}
-
 // Zero the fixed-node rows of a [3][N] vector (outputs of a solve are defined
 // on free nodes only).
 __global__ void k_zero_fixed(DevMesh M, double* v) {
@@ -1108,48 +885,9 @@ void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v) {
   hipLaunchKernelGGL(k_zero_fixed, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, v);
 }
 
-void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
-                      int lds_cols, bool fp32, const double* b, int N, const IterState* st) {
-  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
-  if (fp32)
-    hipLaunchKernelGGL(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32,
-                       b, N, st);
-  else
-    hipLaunchKernelGGL(k_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                       S.panel64, b, N, st);
-}
 
-void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
-                           int lds_cols, bool fp32, const double* b, int N, const IterState* st) {
-  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
-  if (fp32)
-    hipLaunchKernelGGL(k_sweep_fwd_wide<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                       S.panelT32, b, N, st);
-  else
-    hipLaunchKernelGGL(k_sweep_fwd_wide<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                       S.panelT64, b, N, st);
-}
 
-void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
-                      int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
-                      int accumulate, const IterState* st) {
-  const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
-  if (fp32) {
-    if (use_lds)
-      hipLaunchKernelGGL((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                         S.panel32, out, N, alpha, accumulate, st);
-    else
-      hipLaunchKernelGGL((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
-                         S.panel32, out, N, alpha, accumulate, st);
-  } else {
-    if (use_lds)
-      hipLaunchKernelGGL((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                         S.panel64, out, N, alpha, accumulate, st);
-    else
-      hipLaunchKernelGGL((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
-                         S.panel64, out, N, alpha, accumulate, st);
-  }
-}
+
 
 void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
                       double* cache, IterState* st) {

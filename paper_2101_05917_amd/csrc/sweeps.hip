@@ -1,0 +1,424 @@
+// Level-scheduled supernodal triangular sweeps (gfx950): the global step
+// x = A^{-1} b of Alg. 1 and Alg. 2 with the factor of A computed once.
+//
+// Every supernode s stores the panel P_s = [inv(L_ss); -L_Rs inv(L_ss)]
+// (ncols + nrows rows, ncols columns) in column-major order, plus a row-major
+// copy.  A level of the elimination tree is a set of independent dense
+// matrix-vector products with three right-hand sides (x, y, z):
+//   forward   y_s = inv(L_ss) b~_s and the updates -L_Rs inv(L_ss) b~_s of
+//             s's ancestors, b~_s = b_s + (updates of s's descendants);
+//   backward  x_s = P_s^T [y_s; x_R].
+// Updates are gathered by their consumer in a fixed order (no atomics).
+//
+// Each kernel launch processes one level; a task (256 threads) is one block
+// of rows or columns of one supernode.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace dpd {
+
+namespace {
+
+constexpr int kGroup = 256;  // threads per task
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// b~ for the task's supernode into bs[3][nc]: pre-gathered (bt) or gathered here.
+__device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const double* __restrict__ b,
+                                 int N, bool pre, int tid, double* bs) {
+  const int nc = t.ncols;
+  for (int c = tid; c < nc; c += kGroup) {
+    const int j = t.col0 + c;
+    double v0, v1, v2;
+    if (pre) {
+      v0 = S.bt[j];
+      v1 = S.bt[(int64_t)S.nf + j];
+      v2 = S.bt[2 * (int64_t)S.nf + j];
+    } else {
+      const int node = S.perm_pub[j];
+      v0 = b[node];
+      v1 = b[(int64_t)N + node];
+      v2 = b[2 * (int64_t)N + node];
+      for (int k = S.cptr[j]; k < S.cptr[j + 1]; ++k) {
+        const int64_t pos = 3 * (int64_t)S.cidx[k];
+        v0 += S.U[pos];
+        v1 += S.U[pos + 1];
+        v2 += S.U[pos + 2];
+      }
+    }
+    bs[c] = v0;
+    bs[nc + c] = v1;
+    bs[2 * nc + c] = v2;
+  }
+}
+
+__device__ inline void store_fwd_row(const DevSolve& S, const SweepTask& t, int r, double a0, double a1,
+                                     double a2) {
+  if (r < t.ncols) {
+    const int j = t.col0 + r;
+    S.y_int[j] = a0;
+    S.y_int[(int64_t)S.nf + j] = a1;
+    S.y_int[2 * (int64_t)S.nf + j] = a2;
+  } else {
+    const int64_t pos = 3 * (t.u_off + (r - t.ncols));
+    S.U[pos] = a0;
+    S.U[pos + 1] = a1;
+    S.U[pos + 2] = a2;
+  }
+}
+
+// v[3][ld] = [y_s; x_R] for the backward task.
+__device__ inline void stage_solution(const DevSolve& S, const SweepTask& t, int tid, double* vs) {
+  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  const int64_t nf = S.nf;
+  const int* rows = S.rows + t.rows_off;
+  for (int r = tid; r < ld; r += kGroup) {
+    const double* src = S.y_int;
+    int j = t.col0 + r;
+    if (r >= nc) {
+      src = S.x_int;
+      j = rows[r - nc];
+    }
+    vs[r] = src[j];
+    vs[ld + r] = src[nf + j];
+    vs[2 * ld + r] = src[2 * nf + j];
+  }
+}
+
+__device__ inline void store_bwd_col(const DevSolve& S, const SweepTask& t, int c, double x0, double x1,
+                                     double x2, double* __restrict__ out, int N, double alpha,
+                                     int accumulate) {
+  const int j = t.col0 + c;
+  const int64_t nf = S.nf;
+  S.x_int[j] = x0;
+  S.x_int[nf + j] = x1;
+  S.x_int[2 * nf + j] = x2;
+  const int node = S.perm_pub[j];
+  if (accumulate) {
+    out[node] += alpha * x0;
+    out[(int64_t)N + node] += alpha * x1;
+    out[2 * (int64_t)N + node] += alpha * x2;
+  } else {
+    out[node] = alpha * x0;
+    out[(int64_t)N + node] = alpha * x1;
+    out[2 * (int64_t)N + node] = alpha * x2;
+  }
+}
+
+// Forward task, blocks of at most 64 columns: lane per panel row, columns in
+// sequence (column-major panel, coalesced across lanes).
+template <typename T>
+__device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
+                                       const double* __restrict__ b, int N, bool active, int tid,
+                                       double* bs) {
+  __syncthreads();
+  if (active) stage_rhs(S, t, b, N, false, tid, bs);
+  __syncthreads();
+  if (!active || tid >= t.count) return;
+  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  const int r = t.first + tid;
+  const T* P = panel + t.panel_off + r;
+  const int cend = r < nc ? r + 1 : nc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int c = 0;
+  for (; c + 4 <= cend; c += 4) {
+    const double p0 = (double)P[(int64_t)(c + 0) * ld], p1 = (double)P[(int64_t)(c + 1) * ld];
+    const double p2 = (double)P[(int64_t)(c + 2) * ld], p3 = (double)P[(int64_t)(c + 3) * ld];
+    a0 += p0 * bs[c] + p1 * bs[c + 1] + p2 * bs[c + 2] + p3 * bs[c + 3];
+    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 1] + p2 * bs[nc + c + 2] + p3 * bs[nc + c + 3];
+    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 1] + p2 * bs[2 * nc + c + 2] + p3 * bs[2 * nc + c + 3];
+  }
+  for (; c < cend; ++c) {
+    const double p = (double)P[(int64_t)c * ld];
+    a0 += p * bs[c];
+    a1 += p * bs[nc + c];
+    a2 += p * bs[2 * nc + c];
+  }
+  store_fwd_row(S, t, r, a0, a1, a2);
+}
+
+// Forward task, wide blocks: wave per panel row on the row-major copy.
+template <typename T>
+__device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
+                                     const double* __restrict__ b, int N, bool pre, bool active, int tid,
+                                     double* bs) {
+  __syncthreads();
+  if (active) stage_rhs(S, t, b, N, pre, tid, bs);
+  __syncthreads();
+  if (!active) return;
+  const int nc = t.ncols;
+  const int lane = tid & 63, wid = tid >> 6;
+  const T* Pb = panelT + t.panel_off;
+  for (int rr = wid; rr < t.count; rr += kGroup / 64) {
+    const int r = t.first + rr;
+    const T* row = Pb + (int64_t)r * nc;
+    const int cend = r < nc ? r + 1 : nc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    int c = lane;
+    for (; c + 192 < cend; c += 256) {
+      const double p0 = (double)row[c], p1 = (double)row[c + 64];
+      const double p2 = (double)row[c + 128], p3 = (double)row[c + 192];
+      a0 += p0 * bs[c] + p1 * bs[c + 64] + p2 * bs[c + 128] + p3 * bs[c + 192];
+      a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 64] + p2 * bs[nc + c + 128] + p3 * bs[nc + c + 192];
+      a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 64] + p2 * bs[2 * nc + c + 128] +
+            p3 * bs[2 * nc + c + 192];
+    }
+    for (; c < cend; c += 64) {
+      const double p = (double)row[c];
+      a0 += p * bs[c];
+      a1 += p * bs[nc + c];
+      a2 += p * bs[2 * nc + c];
+    }
+    a0 = wsum(a0);
+    a1 = wsum(a1);
+    a2 = wsum(a2);
+    if (lane == 0) store_fwd_row(S, t, r, a0, a1, a2);
+  }
+}
+
+// Backward task: each wave owns up to four adjacent columns and walks their
+// rows (column-major panel); v from LDS (kLds) or from global memory.
+template <typename T, bool kLds>
+__device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
+                                     double* __restrict__ out, int N, double alpha, int accumulate,
+                                     bool active, int tid, double* vs) {
+  __syncthreads();
+  if (kLds && active) stage_solution(S, t, tid, vs);
+  __syncthreads();
+  if (!active) return;
+  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  const int64_t nf = S.nf;
+  const int* rows = S.rows + t.rows_off;
+  const int lane = tid & 63, wid = tid >> 6, nw = kGroup / 64;
+  const int cpw = (t.count + nw - 1) / nw;
+  const int cw = t.first + wid * cpw;
+  const int nown = min(cpw, t.first + t.count - cw);
+  if (nown <= 0) return;
+  const T* Pb = panel + t.panel_off + (int64_t)cw * ld;
+  double acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+  for (int r = cw + lane; r < ld; r += 64) {
+    double v0, v1, v2;
+    if (kLds) {
+      v0 = vs[r];
+      v1 = vs[ld + r];
+      v2 = vs[2 * ld + r];
+    } else {
+      const double* src = S.y_int;
+      int j = t.col0 + r;
+      if (r >= nc) {
+        src = S.x_int;
+        j = rows[r - nc];
+      }
+      v0 = src[j];
+      v1 = src[nf + j];
+      v2 = src[2 * nf + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < nown) {
+        // rows above a column's diagonal hold explicit zeros in the panel
+        const double p = (double)Pb[(int64_t)q * ld + r];
+        acc[q][0] += p * v0;
+        acc[q][1] += p * v1;
+        acc[q][2] += p * v2;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q >= nown) break;
+    const double a0 = wsum(acc[q][0]), a1 = wsum(acc[q][1]), a2 = wsum(acc[q][2]);
+    if (lane == 0) store_bwd_col(S, t, cw + q, a0, a1, a2, out, N, alpha, accumulate);
+  }
+}
+
+// Backward task of a small supernode (at most 64 columns): lanes over its
+// columns on the row-major copy, rows split four ways, combined through LDS.
+// vs holds 3 ld doubles followed by 4 x 64 x 3 reduction slots.
+template <typename T>
+__device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
+                                       double* __restrict__ out, int N, double alpha, int accumulate,
+                                       bool active, int tid, double* vs) {
+  __syncthreads();
+  if (active) stage_solution(S, t, tid, vs);
+  __syncthreads();
+  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  double* red = vs + 3 * ld;
+  const int c = tid & 63, part = tid >> 6;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (active && c < nc) {
+    const T* Pc = panelT + t.panel_off + c;
+    // first row >= c (rows above the diagonal are zeros) in this part's residue class
+    int r = c + ((part - c) & 3);
+    for (; r + 12 < ld; r += 16) {
+      const double p0 = (double)Pc[(int64_t)r * nc], p1 = (double)Pc[(int64_t)(r + 4) * nc];
+      const double p2 = (double)Pc[(int64_t)(r + 8) * nc], p3 = (double)Pc[(int64_t)(r + 12) * nc];
+      a0 += p0 * vs[r] + p1 * vs[r + 4] + p2 * vs[r + 8] + p3 * vs[r + 12];
+      a1 += p0 * vs[ld + r] + p1 * vs[ld + r + 4] + p2 * vs[ld + r + 8] + p3 * vs[ld + r + 12];
+      a2 += p0 * vs[2 * ld + r] + p1 * vs[2 * ld + r + 4] + p2 * vs[2 * ld + r + 8] + p3 * vs[2 * ld + r + 12];
+    }
+    for (; r < ld; r += 4) {
+      const double p = (double)Pc[(int64_t)r * nc];
+      a0 += p * vs[r];
+      a1 += p * vs[ld + r];
+      a2 += p * vs[2 * ld + r];
+    }
+  }
+  if (active) {
+    red[(part * 64 + c) * 3 + 0] = a0;
+    red[(part * 64 + c) * 3 + 1] = a1;
+    red[(part * 64 + c) * 3 + 2] = a2;
+  }
+  __syncthreads();
+  if (active && part == 0 && c < nc) {
+    double x[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      x[q] = red[(0 * 64 + c) * 3 + q] + red[(1 * 64 + c) * 3 + q] + red[(2 * 64 + c) * 3 + q] +
+             red[(3 * 64 + c) * 3 + q];
+    store_bwd_col(S, t, c, x[0], x[1], x[2], out, N, alpha, accumulate);
+  }
+}
+
+// ---------------------------------------------------------------- per-level kernels
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                      const T* __restrict__ panel, const double* __restrict__ b,
+                                                      int N, const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double lds[];
+  fwd_narrow_task<T>(S, tasks[blockIdx.x], panel, b, N, true, threadIdx.x, lds);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                           const T* __restrict__ panelT,
+                                                           const double* __restrict__ b, int N, int pre,
+                                                           const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double lds[];
+  fwd_wide_task<T>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
+}
+
+// Right-hand sides of one level with the descendants' updates added, once per
+// column: bt[j] = b[perm j] + sum of the updates of row j (wave per column).
+__global__ void __launch_bounds__(kBlock) k_sweep_gather(DevSolve S, const int32_t* __restrict__ cols,
+                                                         int ncols, const double* __restrict__ b, int N,
+                                                         const IterState* st) {
+  if (st && st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= ncols) return;
+  const int j = cols[w];
+  const int k0 = S.cptr[j], k1 = S.cptr[j + 1];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int k = k0 + lane; k < k1; k += 64) {
+    const int64_t pos = 3 * (int64_t)S.cidx[k];
+    v0 += S.U[pos];
+    v1 += S.U[pos + 1];
+    v2 += S.U[pos + 2];
+  }
+  v0 = wsum(v0);
+  v1 = wsum(v1);
+  v2 = wsum(v2);
+  if (lane == 0) {
+    const int node = S.perm_pub[j];
+    S.bt[j] = b[node] + v0;
+    S.bt[(int64_t)S.nf + j] = b[(int64_t)N + node] + v1;
+    S.bt[2 * (int64_t)S.nf + j] = b[2 * (int64_t)N + node] + v2;
+  }
+}
+
+template <typename T, bool kLds>
+__global__ void __launch_bounds__(kBlock) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                      const T* __restrict__ panel, double* __restrict__ out,
+                                                      int N, double alpha, int accumulate, const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double lds[];
+  bwd_cols_task<T, kLds>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true, threadIdx.x, lds);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sweep_bwd_narrow(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                             const T* __restrict__ panelT,
+                                                             double* __restrict__ out, int N, double alpha,
+                                                             int accumulate, const IterState* st) {
+  if (st && st->done) return;
+  extern __shared__ double lds[];
+  bwd_narrow_task<T>(S, tasks[blockIdx.x], panelT, out, N, alpha, accumulate, true, threadIdx.x, lds);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks, int lds_cols,
+                      bool fp32, const double* b, int N, const IterState* st) {
+  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32, b, N, st);
+  else
+    hipLaunchKernelGGL(k_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel64, b, N, st);
+}
+
+void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                           int lds_cols, bool fp32, const double* b, int N, const int32_t* gather_cols,
+                           int n_gather, const IterState* st) {
+  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
+  const int pre = gather_cols != nullptr && n_gather > 0;
+  if (pre) {
+    const int waves = kBlock / 64;
+    hipLaunchKernelGGL(k_sweep_gather, dim3((n_gather + waves - 1) / waves), dim3(kBlock), 0, s, S,
+                       gather_cols, n_gather, b, N, st);
+  }
+  if (fp32)
+    hipLaunchKernelGGL(k_sweep_fwd_wide<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
+                       b, N, pre, st);
+  else
+    hipLaunchKernelGGL(k_sweep_fwd_wide<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
+                       b, N, pre, st);
+}
+
+void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks, int lds_rows,
+                      bool use_lds, bool fp32, double* out, int N, double alpha, int accumulate,
+                      const IterState* st) {
+  const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
+  if (fp32) {
+    if (use_lds)
+      hipLaunchKernelGGL((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+                         S.panel32, out, N, alpha, accumulate, st);
+    else
+      hipLaunchKernelGGL((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks, S.panel32,
+                         out, N, alpha, accumulate, st);
+  } else {
+    if (use_lds)
+      hipLaunchKernelGGL((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+                         S.panel64, out, N, alpha, accumulate, st);
+    else
+      hipLaunchKernelGGL((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
+                         S.panel64, out, N, alpha, accumulate, st);
+  }
+}
+
+void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
+                             int lds_rows, bool fp32, double* out, int N, double alpha, int accumulate,
+                             const IterState* st) {
+  const size_t lds = ((size_t)3 * lds_rows + 4 * 64 * 3) * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
+                       out, N, alpha, accumulate, st);
+  else
+    hipLaunchKernelGGL(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
+                       out, N, alpha, accumulate, st);
+}
+
+
+}  // namespace dpd

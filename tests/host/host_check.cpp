@@ -89,10 +89,21 @@ int main(int argc, char** argv) {
     const Supernode& sn = S.sn[t.sn];
     CHECK(t.first >= 0 && t.count > 0 && t.count <= kBlock && t.first + t.count <= sn.ncols + sn.nrows);
   }
-  for (const SweepTask& t : P.bwd) {
-    const Supernode& sn = S.sn[t.sn];
-    CHECK(t.first >= 0 && t.count > 0 && t.count <= kColsPerTask && t.first + t.count <= sn.ncols);
-  }
+  for (int32_t l = 0; l < S.n_levels; ++l)
+    for (int32_t ti = P.bwd_off[l]; ti < P.bwd_off[l + 1]; ++ti) {
+      const SweepTask& t = P.bwd[ti];
+      const Supernode& sn = S.sn[t.sn];
+      CHECK(sn.level == l);
+      CHECK(t.first >= 0 && t.count > 0 && t.first + t.count <= sn.ncols);
+      CHECK(P.bwd_narrow[l] ? t.count <= 64 : t.count <= kColsPerTask);
+    }
+  CHECK((int32_t)P.gather_off.size() == S.n_levels + 1);
+  for (int32_t l = 0; l < S.n_levels; ++l)
+    for (int32_t g = P.gather_off[l]; g < P.gather_off[l + 1]; ++g) {
+      const int32_t j = P.gather_cols[g];
+      CHECK(j >= 0 && j < nf && S.sn[S.snode_of[j]].level == l && P.fwd_wide[l]);
+      CHECK(S.cptr[j] <= S.cptr[j + 1] && S.cptr[j + 1] <= (int32_t)S.cidx.size());
+    }
   std::vector<int32_t> perm_pub(nf);
   for (int64_t i = 0; i < nf; ++i) perm_pub[i] = m.free_nodes[S.perm[i]];
   const std::vector<double> panelT = transpose_panels<double>(S, panel);
@@ -151,14 +162,15 @@ int main(int argc, char** argv) {
         const Supernode& sn = S.sn[t.sn];
         const int nc_ = sn.ncols, ld = sn.ncols + sn.nrows;
         CHECK(ld <= P.bwd_rows[l]);
-        const int nw = kBlock / 64, cpw = (t.count + nw - 1) / nw;
-        CHECK(cpw <= 4);
+        const int nw = kBlock / 64, cpw = P.bwd_narrow[l] ? 1 : (t.count + nw - 1) / nw;
+        CHECK(P.bwd_narrow[l] ? (t.first == 0 && t.count == nc_ && nc_ <= 64 && ld <= 2048) : cpw <= 4);
         for (int cc = 0; cc < t.count; ++cc) {
           const int c = t.first + cc;
-          const int cw = t.first + (cc / cpw) * cpw;   // first column of the owning wave
+          const int cw = P.bwd_narrow[l] ? c : t.first + (cc / cpw) * cpw;   // first row read
           double a[3] = {0, 0, 0};
           for (int r = cw; r < ld; ++r) {
-            const int64_t pi = sn.panel_off + (int64_t)c * ld + r;
+            const int64_t pi = P.bwd_narrow[l] ? sn.panel_off + (int64_t)r * nc_ + c
+                                               : sn.panel_off + (int64_t)c * ld + r;
             CHECK(pi >= 0 && pi < S.panel_size);
             int j;
             const double* src;
@@ -171,7 +183,8 @@ int main(int argc, char** argv) {
               src = x_int.data();
             }
             CHECK(j >= 0 && j < nf);
-            for (int q = 0; q < 3; ++q) a[q] += panel[pi] * src[q * nf + j];
+            const double pv = P.bwd_narrow[l] ? panelT[pi] : panel[pi];
+            for (int q = 0; q < 3; ++q) a[q] += pv * src[q * nf + j];
           }
           const int j = sn.col0 + c;
           for (int q = 0; q < 3; ++q) x_int[q * nf + j] = a[q];

@@ -28,7 +28,7 @@ def driver(tmp_path_factory):
     return out
 
 
-def run_driver(driver, sc, rhs, leaf_max=64, sep_max=1024):
+def run_driver(driver, sc, rhs, leaf_max=64, sep_max=2048):
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
@@ -78,7 +78,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("leaf,sep", [(64, 1024), (8, 16)])
+@pytest.mark.parametrize("leaf,sep", [(64, 2048), (8, 16)])
 def test_host_mesh_matrix_and_solve(driver, name, leaf, sep):
     sc = CASES[name]()
     o = om.Model(sc)
@@ -110,3 +110,23 @@ def test_host_mesh_matrix_and_solve(driver, name, leaf, sep):
         got = out["x"][k].T.reshape(-1)
         assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
         assert np.all(got[o.fixed] == 0.0)
+
+
+@pytest.mark.slow
+def test_host_solve_large_block_residual(driver):
+    """A block large enough for the many-leaf kernels (>= 256 leaf supernodes):
+    replayed sweeps solve A_s x = b to round-off (checked with the driver's A_s)."""
+    sc = W.dropped_block(48, 24, 24, steps=1)
+    N = len(W.present_nodes(sc.cells))
+    rhs = np.random.default_rng(3).standard_normal((1, 3, N))
+    out = run_driver(driver, sc, rhs)
+    ptr, col, val = out["A"]
+    nf = out["nf"]
+    import scipy.sparse as sp
+    rows = np.repeat(np.arange(nf), np.diff(ptr))
+    A = sp.csr_matrix((val, (rows, col)), shape=(nf, nf))
+    fn = out["free_nodes"]
+    for c in range(3):
+        x = out["x"][0, c, fn]
+        b = rhs[0, c, fn]
+        assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
