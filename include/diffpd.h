@@ -89,6 +89,8 @@ typedef struct {
   double bwd_rel_tol;      /* stop when |xbar - H z| <= tol |xbar|               */
   int32_t precision;       /* DPD_FP64 or DPD_MIXED                                */
   int32_t check_every;     /* host convergence check period (iterations), >= 1   */
+  int32_t use_graphs;      /* 1: run conjugate-gradient iterations as HIP graphs  */
+  int32_t pad;
 } dpd_options;
 
 typedef struct {
@@ -109,12 +111,13 @@ typedef struct {
   int64_t factor_nnz;      /* stored entries of the factor panels (packed count)  */
   int64_t factor_bytes;    /* device bytes of the FP64 panels (both layouts)      */
   int64_t device_bytes;    /* all device memory owned by the handle               */
+  int64_t leaf_nodes;      /* dissection leaf size chosen for the factor          */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
  * no contact, friction or muscles, fwd PD 100 iterations / 1e-10 / 1e-12
  * (Newton-CG inner loop: 200 iterations / 1e-2),
- * bwd CG 5000 iterations / 1e-10, FP64, check_every 8. */
+ * bwd CG 5000 iterations / 1e-10, FP64, check_every 8, HIP graphs on. */
 dpd_status dpd_default_options(dpd_options* opt);
 
 /* Build a mesh from voxels (Sec. Background: FEM nodes, lumped mass; supp.
@@ -125,8 +128,8 @@ dpd_status dpd_default_options(dpd_options* opt);
  *   opt         host options (copied)
  *   out         receives the handle; NULL on failure
  * Assembles A = M/h^2 + sum_c w_c G_c^T G_c (eq:pd_global) over free nodes,
- * orders it by geometric nested dissection and performs the symbolic
- * analysis.  No numeric factorization yet (dpd_factorize).  DPD_EINVAL on bad
+ * orders it by geometric nested dissection (leaf size chosen by an estimate of
+ * the solve time) and performs the symbolic analysis.  No numeric factorization yet (dpd_factorize).  DPD_EINVAL on bad
  * input (duplicate voxels, fixed nodes not on the mesh, nu out of range, ...). */
 dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
                            const int32_t* fixed_ijk, int64_t n_fixed,

@@ -32,7 +32,8 @@ class Options(C.Structure):
         ("fwd_rel_tol", C.c_double), ("fwd_abs_tol_rel", C.c_double),
         ("fwd_solver", C.c_int32), ("fwd_inner_max_iter", C.c_int32), ("fwd_inner_tol", C.c_double),
         ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
-        ("precision", C.c_int32), ("check_every", C.c_int32),
+        ("precision", C.c_int32), ("check_every", C.c_int32), ("use_graphs", C.c_int32),
+        ("pad", C.c_int32),
     ]
 
 
@@ -50,7 +51,7 @@ class Stats(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
-        "factor_nnz", "factor_bytes", "device_bytes")]
+        "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes")]
 
 
 class KernelProfile(C.Structure):

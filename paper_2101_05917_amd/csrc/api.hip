@@ -21,10 +21,12 @@ namespace {
 
 thread_local std::string g_last_error;
 
-constexpr int32_t kLeafMax = 64;
+constexpr double kLaunchSeconds = 4e-6;      // measured time of a small dependent launch
+constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of the sweeps
 constexpr int32_t kSepMax = 2048;
 constexpr int64_t kLdsBudget = 60 * 1024;
 constexpr int64_t kProfStride = 16;
+constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
 
 }  // namespace
 
@@ -53,6 +55,11 @@ struct dpd_mesh {
   SweepTask* d_bwd = nullptr;
   int32_t* d_gather = nullptr;
   double solve_bytes = 0.0, solve_flops = 0.0;   // algorithmic work of one A^{-1} b
+  int32_t leaf_max = 0;                           // chosen dissection leaf size
+  uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
+  hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
+  bool capturing = false;
+  hipStream_t capture_stream = nullptr;
   double* w_e = nullptr;
   double* panel64 = nullptr;
   float* panel32 = nullptr;
@@ -60,6 +67,7 @@ struct dpd_mesh {
   float* panelT32 = nullptr;
   double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
   double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
+  double* xbar_w = nullptr;   // H s of the conjugate-gradient iteration
   IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   IterState* h_st = nullptr;   // pinned host mirror [2]
   // kernel timing (dpd_profile_start / dpd_profile_read)
@@ -120,11 +128,12 @@ void free_dev(dpd_mesh* m, void* p) {
 struct ProfScope {
   dpd_mesh* m;
   hipStream_t s;
-  bool on;
+  bool on, around;
   TimedLaunch t{};
   ProfScope(dpd_mesh* mm, hipStream_t ss, int32_t cls, double bytes, double flops, int st_idx = -1,
             int k = 0, bool strict = true)
-      : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF) {
+      : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF && !mm->capturing),
+        around(cls == DPD_PROF_SOLVE) {
     if (!on) return;
     // time one launch in every kProfStride to keep the event overhead small
     on = (m->prof_seen++ % kProfStride) == 0;
@@ -144,12 +153,25 @@ struct ProfScope {
     t.st_idx = st_idx;
     t.k = k;
     t.strict = strict;
-    (void)hipEventRecord(t.ev.first, s);
+    if (around) {
+      (void)hipEventRecord(t.ev.first, s);  // several launches: bracket them in the stream
+    } else {
+      g_launch_events = {t.ev.first, t.ev.second, false};  // one kernel: timed at its dispatch
+    }
   }
   ~ProfScope() {
     if (!on) return;
-    (void)hipEventRecord(t.ev.second, s);
-    m->ev_pending.push_back(t);
+    bool timed = true;
+    if (around) {
+      (void)hipEventRecord(t.ev.second, s);
+    } else {
+      timed = g_launch_events.used;
+      g_launch_events = {};
+    }
+    if (timed)
+      m->ev_pending.push_back(t);
+    else
+      m->ev_free.push_back(t.ev);
   }
 };
 
@@ -286,8 +308,8 @@ dpd_status check_ready(dpd_mesh* m) {
 }  // namespace
 
 namespace {
-dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs,
-                              double* z, const double* xk, bool fp32, int max_it, int check_every);
+dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
+                              int max_it, int check_every);
 }  // namespace
 
 extern "C" {
@@ -314,6 +336,7 @@ dpd_status dpd_default_options(dpd_options* o) {
   o->bwd_rel_tol = 1e-10;
   o->precision = DPD_FP64;
   o->check_every = 8;
+  o->use_graphs = 1;
   return DPD_OK;
 }
 
@@ -349,8 +372,29 @@ dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* 
     return fail(nullptr, DPD_EINVAL, e);
   }
   assemble_As(m->hm, m->opt, m->A);
-  analyse(m->hm, m->A, kLeafMax, kSepMax, m->S);
-  build_plan(m->S, m->plan);
+  // Partition: among candidate leaf sizes pick the one with the smallest
+  // estimated solve time, launches x kLaunchSeconds + factor bytes / kSweepBandwidth.
+  // Small meshes end up with few levels (one dense supernode when every free
+  // node fits in one block); large meshes keep the deep dissection tree.
+  double best = 1e300;
+  std::vector<int32_t> leaves = {64, 128, 256, 512};
+  if (m->hm.n_free <= kSepMax) leaves.push_back((int32_t)m->hm.n_free);
+  for (int32_t leaf : leaves) {
+    Symbolic S;
+    analyse(m->hm, m->A, leaf, kSepMax, S);
+    LevelPlan P;
+    build_plan(S, P);
+    double launches = 0.0;
+    for (int32_t l = 0; l < S.n_levels; ++l)
+      launches += 2.0 + (P.gather_off[l + 1] > P.gather_off[l] ? 1.0 : 0.0);
+    const double est = launches * kLaunchSeconds + 2.0 * 8.0 * (double)S.packed_nnz / kSweepBandwidth;
+    if (est < best) {
+      best = est;
+      m->S = std::move(S);
+      m->plan = std::move(P);
+      m->leaf_max = leaf;
+    }
+  }
   fill_devmesh(m);
   *out = m;
   return DPD_OK;
@@ -366,9 +410,9 @@ int64_t footprint_bytes(const dpd_mesh* m) {
   b += (int64_t)S.sn.size() * (3 * 4 + 3 * 8) + 4 * (int64_t)S.rows.size();
   b += 4 * ((int64_t)S.cptr.size() + (int64_t)S.cidx.size());
   b += 16 * (int64_t)(m->plan.fwd.size() + m->plan.bwd.size());
-  b += 8 * (9 * nf + 3 * S.u_size + 24 * E + 8 * 3 * N);    // sweep vectors, fe, work vectors
+  b += 8 * (9 * nf + 3 * S.u_size + 24 * E + 9 * 3 * N);    // sweep vectors, fe, work vectors
   b += 4 * (int64_t)m->plan.gather_cols.size();
-  b += 8 * ((int64_t)kAdjCacheRows * 8 * E + std::max<int64_t>(N, 8 * E) / kBlock + 16);
+  b += 8 * ((int64_t)kAdjCacheRows * 8 * E + 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
   b += 2 * 8 * S.panel_size;                                 // FP64 panels, both layouts
   if (m->opt.precision == DPD_MIXED) b += 2 * 4 * S.panel_size;  // FP32 copies
   return b;
@@ -437,7 +481,7 @@ dpd_status upload_device(dpd_mesh* m) {
   AL(m->fe, 3 * 8 * E);
   AL(m->r, 3 * N);
   AL(m->y, 3 * N);
-  AL(m->partials, std::max<int64_t>(N, 8 * E) / kBlock + 16);
+  AL(m->partials, 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
   AL(m->cache, (int64_t)kAdjCacheRows * 8 * E);
   AL(m->z, 3 * N);
   AL(m->p, 3 * N);
@@ -445,6 +489,9 @@ dpd_status upload_device(dpd_mesh* m) {
   AL(m->s, 3 * N);
   AL(m->xbar, 3 * N);
   AL(m->cg_r, 3 * N);
+  AL(m->xbar_w, 3 * N);
+  AL(m->cmask, N);
+  m->dm.cmask = m->cmask;
   AL(m->st, 2);
 #undef AL
   if (hipHostMalloc((void**)&m->h_st, 2 * sizeof(IterState), hipHostMallocDefault) != hipSuccess) {
@@ -453,7 +500,7 @@ dpd_status upload_device(dpd_mesh* m) {
   }
   std::memset(m->h_st, 0, 2 * sizeof(IterState));
   // zero the scratch vectors whose fixed-node rows are read
-  for (double* v : {m->z, m->p, m->q, m->s, m->xbar, m->r, m->cg_r})
+  for (double* v : {m->z, m->p, m->q, m->s, m->xbar, m->r, m->cg_r, m->xbar_w})
     if (hipMemset(v, 0, 3 * N * sizeof(double)) != hipSuccess) {
       dpd_destroy_mesh(m);
       return fail(nullptr, DPD_EHIP, "hipMemset failed");
@@ -482,6 +529,10 @@ namespace dpd {
 // Free a handle whose streams the caller has already synchronized.
 void destroy_synced(dpd_mesh* m) {
   if (!m) return;
+  for (auto& row : m->cg_exec)
+    for (auto& ex : row)
+      if (ex) (void)hipGraphExecDestroy(ex);
+  if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
   for (void* p : m->allocs) (void)hipFree(p);
   for (auto& e : m->ev_free) {
     (void)hipEventDestroy(e.first);
@@ -511,6 +562,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->factor_nnz = m->S.packed_nnz;
   info->factor_bytes = 2 * m->S.panel_size * (int64_t)sizeof(double);
   info->device_bytes = m->device_bytes;
+  info->leaf_nodes = m->leaf_max;
   return DPD_OK;
 }
 
@@ -617,7 +669,7 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
   const bool fp32 = o.precision == DPD_MIXED;
   if (fp32 && !m->have_fp32) return fail(m, DPD_ESTATE, "mixed precision needs FP32 panels (refactorize)");
   const int max_it = std::max(0, o.fwd_max_iter);
-  launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol);
+  launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol, std::max(0, o.fwd_max_iter));
   launch_prologue(m->dm, s, x, v, m->y, xn, m->st, m->partials, o.fwd_abs_tol_rel);
   int solves = -1, outer = 0;
   if (o.fwd_solver == DPD_FWD_NEWTON_PCG && !o.fwd_fixed_iters) {
@@ -636,14 +688,14 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
       if (m->h_st[0].done || solves >= max_it) break;
       launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
-      launch_reset(s, inner, o.fwd_inner_tol * o.fwd_inner_tol);
-      launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
       const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
-      if ((rc = conjugate_gradient(m, s, inner, m->xbar, m->z, xn, fp32, inner_max, o.check_every)) !=
+      launch_reset(s, inner, o.fwd_inner_tol * o.fwd_inner_tol, inner_max);
+      launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
+      if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
           DPD_OK)
         return rc;
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      solves += 1 + std::max(0, m->h_st[1].iter);
+      solves += std::max(1, m->h_st[1].iter);
       if (m->h_st[1].curvature) {
         // not a descent direction: take one plain PD step instead
         solve(m, s, fp32, m->r, xn, -1.0, 1, nullptr);
@@ -699,7 +751,7 @@ dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, 
       ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), 0, k, false);
       launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
     }
-    launch_node_hvp(m->dm, s, m->z, m->fe, xn, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
+    launch_node_hvp(m->dm, s, m->z, m->fe, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
     if (k >= max_it) break;
     solve(m, s, fp32, m->r, m->z, -1.0, 1, m->st, k);
     if ((k + 1) % o.check_every == 0) {
@@ -713,31 +765,72 @@ dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, 
 // Conjugate gradients on (A - dA(xk)) z = rhs preconditioned by A^{-1}, from
 // z = 0, with its scalars in *st (stopping test |r| <= sqrt(st->tolsq) |rhs|).
 // Uses m->cg_r, p, q, s as work vectors; the cached rotations must be at xk.
-dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs,
-                              double* z, const double* xk, bool fp32, int max_it, int check_every) {
+// One conjugate-gradient iteration (Chronopoulos-Gear): s = M^{-1} r, w = H s,
+// the fused inner products, then the vector updates.  Every argument is a
+// buffer of the handle, so the sequence can be captured once and replayed.
+void cg_iteration(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32, int k) {
+  const int st_idx = st == m->st ? 0 : 1;
+  solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st, k);
+  {
+    ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), st_idx, k);
+    launch_elem_hvp(m->dm, s, m->s, m->cache, m->fe, st);
+  }
+  launch_cg_hvp_dots(m->dm, s, m->s, m->fe, m->cg_r, m->xbar_w, st, m->partials);
+  launch_cg_step(m->dm, s, m->z, m->cg_r, m->p, m->q, m->s, m->xbar_w, st, m->partials);
+}
+
+// Graph of kGraphIters iterations on state st (captured on first use).
+hipGraphExec_t cg_graph(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32) {
+  hipGraphExec_t& ex = m->cg_exec[st == m->st ? 0 : 1][fp32 ? 1 : 0];
+  if (ex) return ex;
+  // capture on a private stream (the caller's may be the null stream); nothing
+  // executes during capture, and the graph is then launched on the caller's stream
+  if (!m->capture_stream &&
+      hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return nullptr;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  m->capturing = true;
+  for (int i = 0; i < kGraphIters; ++i) cg_iteration(m, m->capture_stream, st, fp32, 0);
+  m->capturing = false;
+  if (hipStreamEndCapture(m->capture_stream, &g) != hipSuccess || !g) return nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+  (void)hipGraphDestroy(g);
+  return ex;
+}
+
+// Conjugate gradients on (A - dA) z = rhs preconditioned by A^{-1}, from
+// z = m->z = 0, with its scalars in *st (stop when |r| <= sqrt(tolsq) |rhs| or
+// after st->max_iter iterations).  The cached rotations and the contact mask
+// must describe the linearisation point.  Iterations run as captured graphs of
+// kGraphIters, except that while a kernel class is being timed one chunk in
+// kProfStride runs as direct launches (timed live).
+dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
+                              int max_it, int check_every) {
   dpd_status rc;
   const int64_t n3 = 3 * (int64_t)m->dm.N;
-  launch_fill(s, n3, z, 0.0);
+  const int st_idx = st == m->st ? 0 : 1;
+  launch_fill(s, n3, m->z, 0.0);
+  launch_fill(s, n3, m->p, 0.0);
+  launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
-  solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, nullptr);
-  launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 1);
-  launch_lincomb(s, n3, m->p, 1.0, m->s, 0.0, nullptr);
-  for (int k = 1; k <= max_it; ++k) {
-    {
-      ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m),
-                   st == m->st ? 0 : 1, k, false);
-      launch_elem_hvp(m->dm, s, m->p, m->cache, m->fe, st);
+  const int chunk = std::max(kGraphIters, check_every / kGraphIters * kGraphIters);
+  int chunks = 0;
+  for (int k = 0; k < max_it;) {
+    const bool direct = !m->opt.use_graphs || (m->prof_class != DPD_PROF_OFF && chunks % kProfStride == 0);
+    hipGraphExec_t ex = direct ? nullptr : cg_graph(m, s, st, fp32);
+    for (int i = 0; i < chunk && k < max_it; i += kGraphIters) {
+      if (ex) {
+        HIPCHECK(m, hipGraphLaunch(ex, s));
+        k += kGraphIters;
+      } else {
+        for (int j = 0; j < kGraphIters; ++j, ++k) cg_iteration(m, s, st, fp32, k);
+      }
     }
-    launch_node_hvp(m->dm, s, m->p, m->fe, xk, nullptr, m->q, st, m->partials, 2, k, max_it);
-    launch_cg_update(m->dm, s, z, m->cg_r, m->p, m->q, st, m->partials, k, max_it);
-    solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st, k);
-    launch_dot(m->dm, s, m->cg_r, m->s, st, m->partials, 2);
-    launch_cg_direction(m->dm, s, m->p, m->s, st);
-    if (k % check_every == 0) {
-      if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      if (st == m->st ? m->h_st[0].done : m->h_st[1].done) break;
-    }
+    chunks += 1;
+    if ((rc = read_state(m, s)) != DPD_OK) return rc;
+    if (m->h_st[st_idx].done) break;
   }
   return DPD_OK;
 }
@@ -761,14 +854,14 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   if (fp32 && !m->have_fp32) return fail(m, DPD_ESTATE, "mixed precision needs FP32 panels (refactorize)");
   const int64_t n3 = 3 * (int64_t)m->dm.N;
   const int max_it = std::max(0, o.bwd_max_iter);
-  launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol);
+  launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
   // xbar = dL/dx_{i+1} + dL/dv_{i+1} / h  (v_{i+1} = (x_{i+1} - x_i)/h)
   launch_lincomb(s, n3, m->xbar, 1.0, gx_next, 1.0 / o.h, gv_next);
   launch_zero_fixed(m->dm, s, m->xbar);
   launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
   int fallbacks = 0;
   if (o.bwd_solver == DPD_BWD_PCG) {
-    if ((rc = conjugate_gradient(m, s, m->st, m->xbar, m->z, xn, fp32, max_it, o.check_every)) !=
+    if ((rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every)) !=
         DPD_OK)
       return rc;
     if ((rc = read_state(m, s)) != DPD_OK) return rc;
@@ -776,7 +869,7 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       // the paper's safeguard when the quasi-Newton step is not a descent:
       // continue with the plain fixed-point iteration from the current z
       fallbacks = 1;
-      launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol);
+      launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
       launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
       if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
     }
@@ -821,7 +914,7 @@ dpd_status dpd_gradient(dpd_mesh* m, void* stream, const double* x, const double
                         double* out) {
   if (!m || !x || !y || !out) return fail(m, DPD_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  launch_reset(s, m->st, 0.0);
+  launch_reset(s, m->st, 0.0, 0);
   launch_elem_forces(m->dm, s, x, act, m->fe, nullptr, nullptr);
   launch_node_residual(m->dm, s, x, y, m->fe, out, m->st, m->partials, 0, 0, 1);
   HIPCHECK(m, hipGetLastError());
@@ -834,7 +927,7 @@ dpd_status dpd_hessian_apply(dpd_mesh* m, void* stream, const double* x, const d
   hipStream_t s = (hipStream_t)stream;
   launch_adj_cache(m->dm, s, x, act, m->cache, nullptr);
   launch_elem_hvp(m->dm, s, p, m->cache, m->fe, nullptr);
-  launch_node_hvp(m->dm, s, p, m->fe, x, nullptr, out, nullptr, nullptr, 0, 0, 0);
+  launch_node_hvp(m->dm, s, p, m->fe, nullptr, out, nullptr, nullptr, 0, 0, 0);
   HIPCHECK(m, hipGetLastError());
   return DPD_OK;
 }

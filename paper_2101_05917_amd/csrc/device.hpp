@@ -1,6 +1,7 @@
 // Device-side data of one mesh and the kernel launchers (internal).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,7 +19,7 @@ struct IterState {
   double acc;                        // scratch accumulator
   int32_t iter, done, converged, nonfinite, curvature, inverted;
   uint32_t counter;                  // last-block-done ticket
-  int32_t pad;
+  int32_t max_iter;                  // iteration cap of the conjugate-gradient loop
 };
 
 struct DevSolve {
@@ -50,9 +51,31 @@ struct DevMesh {
   const uint8_t* fixed;       // [N]
   const uint8_t* contact;     // [N]
   const double* w_e;          // [E] corotated weight per Gauss point, 2 mu_e V_q
+  uint8_t* cmask;             // [N] ground contact active at the linearisation point
 };
 
 constexpr int kElemsPerBlock = kBlock / 8;
+
+// Kernel timing: when start/stop events are set, the next launch made with
+// DPD_LAUNCH records them at its own dispatch start and completion
+// (hipExtLaunchKernelGGL), so the measured time is the kernel's alone.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool used = false;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+#define DPD_LAUNCH(kernel, grid, block, shmem, stream, ...)                                        \
+  do {                                                                                             \
+    if (::dpd::g_launch_events.start) {                                                            \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ::dpd::g_launch_events.start,      \
+                            ::dpd::g_launch_events.stop, 0, __VA_ARGS__);                          \
+      ::dpd::g_launch_events.start = nullptr;                                                      \
+      ::dpd::g_launch_events.used = true;                                                          \
+    } else {                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                         \
+    }                                                                                              \
+  } while (0)
 
 
 }  // namespace dpd
@@ -62,7 +85,7 @@ namespace dpd {
 void launch_lincomb(hipStream_t s, int64_t n, double* out, double a, const double* x, double b,
                     const double* y);
 void launch_fill(hipStream_t s, int64_t n, double* out, double v);
-void launch_reset(hipStream_t s, IterState* st, double tolsq);
+void launch_reset(hipStream_t s, IterState* st, double tolsq, int max_iter);
 void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
                      double* xn, IterState* st, double* partials, double abs_tol_rel);
 void launch_elem_forces(const DevMesh& M, hipStream_t s, const double* x, const double* act,
@@ -88,14 +111,14 @@ void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const do
 void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
                      double* fe, const IterState* st);
 void launch_node_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* fe,
-                     const double* xk, const double* rhs, double* out, IterState* st,
-                     double* partials, int mode, int k, int max_iter);
+                     const double* rhs, double* out, IterState* st, double* partials, int mode, int k,
+                     int max_iter);
 void launch_dot(const DevMesh& M, hipStream_t s, const double* a, const double* b, IterState* st,
                 double* partials, int what);
-void launch_cg_update(const DevMesh& M, hipStream_t s, double* z, double* r, const double* p,
-                      const double* q, IterState* st, double* partials, int k, int max_iter);
-void launch_cg_direction(const DevMesh& M, hipStream_t s, double* p, const double* sv,
-                         const IterState* st);
+void launch_cg_hvp_dots(const DevMesh& M, hipStream_t s, const double* sv, const double* fe,
+                        const double* r, double* w, IterState* st, double* partials);
+void launch_cg_step(const DevMesh& M, hipStream_t s, double* z, double* r, double* p, double* q,
+                    const double* sv, const double* w, IterState* st, double* partials);
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
                          const double* z, const double* gv_next, double* gx, double* gv);
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,

@@ -393,7 +393,11 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     P.gather_off[l] = (int32_t)P.gather_cols.size();
     const int32_t ntask = P.fwd_off[l + 1] - P.fwd_off[l];
     const int32_t nsn = (int32_t)by_level[l].size();
-    if (P.fwd_wide[l] && ntask >= 4 * nsn)
+    int32_t max_nc = 0;
+    for (int32_t s : by_level[l]) max_nc = std::max(max_nc, S.sn[s].ncols);
+    int64_t contribs = 0;
+    for (int32_t s : by_level[l]) contribs += S.cptr[S.sn[s].col0 + S.sn[s].ncols] - S.cptr[S.sn[s].col0];
+    if (P.fwd_wide[l] && ntask >= 4 * nsn && max_nc >= 256 && contribs > 0)
       for (int32_t s : by_level[l])
         for (int32_t c = 0; c < S.sn[s].ncols; ++c) P.gather_cols.push_back(S.sn[s].col0 + c);
   }

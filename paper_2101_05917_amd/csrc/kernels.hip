@@ -23,6 +23,8 @@
 
 namespace dpd {
 
+thread_local LaunchEvents g_launch_events;
+
 // ------------------------------------------------------------------ helpers
 
 __device__ inline double wave_sum(double v) {
@@ -412,8 +414,9 @@ __global__ void __launch_bounds__(kBlock) k_node_residual(DevMesh M, const doubl
   }
 }
 
-__global__ void k_reset_state(IterState* st, double tolsq) {
+__global__ void k_reset_state(IterState* st, double tolsq, int max_iter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->max_iter = max_iter;
     st->r0sq = st->rsq = st->atolsq = 0.0;
     st->tolsq = tolsq;
     st->nb2 = st->rs = st->pq = st->alpha = st->beta = st->acc = 0.0;
@@ -531,6 +534,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
   }
 }
 
+// Ground contact active at the linearisation point x (height below zero): the
+// contact term of A - dA is k on the vertical coordinate there, zero elsewhere.
+__global__ void __launch_bounds__(kBlock) k_contact_mask(DevMesh M, const double* __restrict__ x) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < M.N) M.cmask[n] = (M.contact[n] && x[2 * (int64_t)M.N + n] < 0.0) ? 1 : 0;
+}
+
 // Element part of (A - dA) p: stress w (dF - dR[dF]) (+ muscle (I - dp/df) term).
 __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
                                                      const double* __restrict__ cache,
@@ -579,10 +589,9 @@ __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __
 }
 
 // out = (A - dA) p (- rhs if given); mode 0: plain; mode 1: out = H p - rhs and
-// |out|^2 / nb2 drives the fixed-point stopping test; mode 2: p . out -> CG alpha.
+// |out|^2 / nb2 drives the fixed-point stopping test.
 __global__ void __launch_bounds__(kBlock) k_node_hvp(DevMesh M, const double* __restrict__ p,
                                                      const double* __restrict__ fe,
-                                                     const double* __restrict__ xk,
                                                      const double* __restrict__ rhs,
                                                      double* __restrict__ out, IterState* st,
                                                      double* partials, int mode, int k, int max_iter) {
@@ -599,95 +608,19 @@ __global__ void __launch_bounds__(kBlock) k_node_hvp(DevMesh M, const double* __
       o0 += c * p0;
       o1 += c * p1;
       o2 += c * p2;
-      if (M.contact[n] && xk[2 * N + n] < 0.0) o2 += M.contact_k * p2;
+      if (M.cmask[n]) o2 += M.contact_k * p2;
       if (rhs) {
         o0 -= rhs[n];
         o1 -= rhs[N + n];
         o2 -= rhs[2 * N + n];
       }
-      acc = (mode == 2) ? (p0 * o0 + p1 * o1 + p2 * o2) : (o0 * o0 + o1 * o1 + o2 * o2);
+      acc = o0 * o0 + o1 * o1 + o2 * o2;
     }
     out[n] = o0;
     out[N + n] = o1;
     out[2 * N + n] = o2;
   }
   if (mode == 0) return;
-  double tot;
-  if (grid_sum(acc, partials, st, &tot)) {
-    if (mode == 1) {
-      st->rsq = tot;
-      st->iter = k;
-      if (!isfinite(tot)) {
-        st->nonfinite = 1;
-        st->done = 1;
-      } else if (tot <= st->tolsq * st->nb2) {
-        st->converged = 1;
-        st->done = 1;
-      }
-      if (k >= max_iter) st->done = 1;
-    } else {
-      st->pq = tot;
-      if (!(tot > 0.0) || !isfinite(tot)) {
-        st->curvature = 1;
-        st->done = 1;
-      } else {
-        st->alpha = st->rs / tot;
-      }
-    }
-  }
-}
-
-// Dot product / squared norm over free nodes into st (what: 0 -> nb2 (and rsq),
-// 1 -> rs (initial), 2 -> beta = new/old rs, rs = new).
-__global__ void __launch_bounds__(kBlock) k_dot(DevMesh M, const double* __restrict__ a,
-                                                const double* __restrict__ b, IterState* st,
-                                                double* partials, int what) {
-  if (what == 2 && st->done) return;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  if (n < M.N && !M.fixed[n]) {
-    const int64_t N = M.N;
-    acc = a[n] * b[n] + a[N + n] * b[N + n] + a[2 * N + n] * b[2 * N + n];
-  }
-  double tot;
-  if (grid_sum(acc, partials, st, &tot)) {
-    if (what == 0) {
-      st->nb2 = tot;
-      st->rsq = tot;
-      if (!(tot > 0.0)) {
-        st->converged = 1;
-        st->done = 1;
-      }
-    } else if (what == 1) {
-      st->rs = tot;
-    } else {
-      st->beta = tot / st->rs;
-      st->rs = tot;
-    }
-  }
-}
-
-// z += alpha p; r -= alpha q; |r|^2 -> stopping test.
-__global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh M, double* __restrict__ z,
-                                                      double* __restrict__ r,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ q, IterState* st,
-                                                      double* partials, int k, int max_iter) {
-  if (st->done) return;
-  const double alpha = st->alpha;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  if (n < M.N && !M.fixed[n]) {
-    const int64_t N = M.N;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t i = c * N + n;
-      z[i] += alpha * p[i];
-      const double ri = r[i] - alpha * q[i];
-      r[i] = ri;
-      acc += ri * ri;
-    }
-  }
   double tot;
   if (grid_sum(acc, partials, st, &tot)) {
     st->rsq = tot;
@@ -703,17 +636,143 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh M, double* __restr
   }
 }
 
-// p = s + beta p
-__global__ void __launch_bounds__(kBlock) k_cg_direction(DevMesh M, double* __restrict__ p,
-                                                         const double* __restrict__ s,
-                                                         const IterState* st) {
-  if (st->done) return;
-  const double beta = st->beta;
+// |a|^2 over free nodes into st->nb2 (and rsq); a zero norm ends the iteration.
+__global__ void __launch_bounds__(kBlock) k_dot(DevMesh M, const double* __restrict__ a,
+                                                const double* __restrict__ b, IterState* st,
+                                                double* partials, int what) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N && !M.fixed[n]) {
+    const int64_t N = M.N;
+    acc = a[n] * b[n] + a[N + n] * b[N + n] + a[2 * N + n] * b[2 * N + n];
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    st->nb2 = tot;
+    st->rsq = tot;
+    if (!(tot > 0.0)) {
+      st->converged = 1;
+      st->done = 1;
+    }
+  }
+}
+
+// Two grid sums at once (same fixed order as grid_sum).
+__device__ inline bool grid_sum2(double a, double b, double* partials, IterState* st, double* ta,
+                                 double* tb) {
+  __shared__ double ws[kBlock / 64];
+  __shared__ int last;
+  const double ba = block_sum(a, ws);
+  const double bb = block_sum(b, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partials[2 * blockIdx.x], ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&partials[2 * blockIdx.x + 1], bb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t =
+        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  double sa = 0.0, sb = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+    sa += __hip_atomic_load(&partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sb += __hip_atomic_load(&partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  sa = block_sum(sa, ws);
+  sb = block_sum(sb, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *ta = sa;
+    *tb = sb;
+  }
+  return threadIdx.x == 0;
+}
+
+// Conjugate gradients in the Chronopoulos-Gear arrangement, which needs one
+// grid reduction per iteration: with s = M^{-1} r and w = H s,
+//   gamma = r.s, delta = w.s, beta = gamma/gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old)   (= gamma / p^T H p),
+//   p = s + beta p, q = w + beta q, z += alpha p, r -= alpha q.
+// This kernel forms w = H s (node part) and both inner products.
+__global__ void __launch_bounds__(kBlock) k_cg_hvp_dots(DevMesh M, const double* __restrict__ sv,
+                                                        const double* __restrict__ fe,
+                                                        const double* __restrict__ r,
+                                                        double* __restrict__ w, IterState* st,
+                                                        double* partials) {
+  if (st->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double rs = 0.0, ws_ = 0.0;
+  if (n < M.N) {
+    const int64_t N = M.N;
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (!M.fixed[n]) {
+      node_force(M, fe, n, o0, o1, o2);
+      const double c = M.mass[n] / (M.h * M.h);
+      const double s0 = sv[n], s1 = sv[N + n], s2 = sv[2 * N + n];
+      o0 += c * s0;
+      o1 += c * s1;
+      o2 += c * s2;
+      if (M.cmask[n]) o2 += M.contact_k * s2;
+      rs = r[n] * s0 + r[N + n] * s1 + r[2 * N + n] * s2;
+      ws_ = o0 * s0 + o1 * s1 + o2 * s2;
+    }
+    w[n] = o0;
+    w[N + n] = o1;
+    w[2 * N + n] = o2;
+  }
+  double gamma, delta;
+  if (grid_sum2(rs, ws_, partials, st, &gamma, &delta)) {
+    const bool first = st->iter == 0;
+    const double beta = first ? 0.0 : gamma / st->rs;
+    const double den = first ? delta : delta - beta * gamma / st->alpha;
+    if (!(den > 0.0) || !isfinite(den) || !isfinite(gamma)) {
+      st->curvature = 1;
+      st->done = 1;
+    } else {
+      st->beta = beta;
+      st->alpha = gamma / den;
+      st->rs = gamma;
+    }
+  }
+}
+
+// p = s + beta p; q = w + beta q; z += alpha p; r -= alpha q; |r|^2 -> stopping test.
+__global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restrict__ z, double* __restrict__ r,
+                                                    double* __restrict__ p, double* __restrict__ q,
+                                                    const double* __restrict__ sv,
+                                                    const double* __restrict__ w, IterState* st,
+                                                    double* partials) {
+  if (st->done) return;
+  const double alpha = st->alpha, beta = st->beta;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
   if (n < M.N && !M.fixed[n]) {
     const int64_t N = M.N;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[c * N + n] = s[c * N + n] + beta * p[c * N + n];
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * N + n;
+      const double pi = sv[i] + beta * p[i];
+      const double qi = w[i] + beta * q[i];
+      p[i] = pi;
+      q[i] = qi;
+      z[i] += alpha * pi;
+      const double ri = r[i] - alpha * qi;
+      r[i] = ri;
+      acc += ri * ri;
+    }
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    st->rsq = tot;
+    st->iter += 1;
+    if (!isfinite(tot)) {
+      st->nonfinite = 1;
+      st->done = 1;
+    } else if (tot <= st->tolsq * st->nb2) {
+      st->converged = 1;
+      st->done = 1;
+    }
+    if (st->iter >= st->max_iter) st->done = 1;
   }
 }
 
@@ -853,8 +912,8 @@ void launch_fill(hipStream_t s, int64_t n, double* out, double v) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, out, v);
 }
 
-void launch_reset(hipStream_t s, IterState* st, double tolsq) {
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st, tolsq);
+void launch_reset(hipStream_t s, IterState* st, double tolsq, int max_iter) {
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st, tolsq, max_iter);
 }
 
 void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
@@ -866,7 +925,7 @@ void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const dou
 void launch_elem_forces(const DevMesh& M, hipStream_t s, const double* x, const double* act,
                         double* fe, double* R_out, IterState* st) {
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
-  hipLaunchKernelGGL(k_elem_forces, dim3(nb), dim3(kBlock), 0, s, M, x, act, fe, R_out, st);
+  DPD_LAUNCH(k_elem_forces, dim3(nb), dim3(kBlock), 0, s, M, x, act, fe, R_out, st);
 }
 
 void launch_node_residual(const DevMesh& M, hipStream_t s, const double* x, const double* y,
@@ -893,18 +952,19 @@ void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const do
                       double* cache, IterState* st) {
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
   hipLaunchKernelGGL(k_adj_cache, dim3(nb), dim3(kBlock), 0, s, M, x, act, cache, st);
+  hipLaunchKernelGGL(k_contact_mask, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x);
 }
 
 void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
                      double* fe, const IterState* st) {
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
-  hipLaunchKernelGGL(k_elem_hvp, dim3(nb), dim3(kBlock), 0, s, M, p, cache, fe, st);
+  DPD_LAUNCH(k_elem_hvp, dim3(nb), dim3(kBlock), 0, s, M, p, cache, fe, st);
 }
 
 void launch_node_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* fe,
-                     const double* xk, const double* rhs, double* out, IterState* st,
-                     double* partials, int mode, int k, int max_iter) {
-  hipLaunchKernelGGL(k_node_hvp, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, p, fe, xk, rhs, out,
+                     const double* rhs, double* out, IterState* st, double* partials, int mode, int k,
+                     int max_iter) {
+  hipLaunchKernelGGL(k_node_hvp, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, p, fe, rhs, out,
                      st, partials, mode, k, max_iter);
 }
 
@@ -913,16 +973,19 @@ void launch_dot(const DevMesh& M, hipStream_t s, const double* a, const double* 
   hipLaunchKernelGGL(k_dot, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, a, b, st, partials, what);
 }
 
-void launch_cg_update(const DevMesh& M, hipStream_t s, double* z, double* r, const double* p,
-                      const double* q, IterState* st, double* partials, int k, int max_iter) {
-  hipLaunchKernelGGL(k_cg_update, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, z, r, p, q, st,
-                     partials, k, max_iter);
+
+void launch_cg_hvp_dots(const DevMesh& M, hipStream_t s, const double* sv, const double* fe,
+                        const double* r, double* w, IterState* st, double* partials) {
+  hipLaunchKernelGGL(k_cg_hvp_dots, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, sv, fe, r, w, st,
+                     partials);
 }
 
-void launch_cg_direction(const DevMesh& M, hipStream_t s, double* p, const double* sv,
-                         const IterState* st) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, p, sv, st);
+void launch_cg_step(const DevMesh& M, hipStream_t s, double* z, double* r, double* p, double* q,
+                    const double* sv, const double* w, IterState* st, double* partials) {
+  hipLaunchKernelGGL(k_cg_step, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, z, r, p, q, sv, w, st,
+                     partials);
 }
+
 
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
                          const double* z, const double* gv_next, double* gx, double* gv) {

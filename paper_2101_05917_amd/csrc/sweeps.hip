@@ -364,9 +364,9 @@ void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
                       bool fp32, const double* b, int N, const IterState* st) {
   const size_t lds = (size_t)3 * lds_cols * sizeof(double);
   if (fp32)
-    hipLaunchKernelGGL(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32, b, N, st);
+    DPD_LAUNCH(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32, b, N, st);
   else
-    hipLaunchKernelGGL(k_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel64, b, N, st);
+    DPD_LAUNCH(k_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel64, b, N, st);
 }
 
 void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
@@ -380,10 +380,10 @@ void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* ta
                        gather_cols, n_gather, b, N, st);
   }
   if (fp32)
-    hipLaunchKernelGGL(k_sweep_fwd_wide<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
+    DPD_LAUNCH(k_sweep_fwd_wide<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
                        b, N, pre, st);
   else
-    hipLaunchKernelGGL(k_sweep_fwd_wide<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
+    DPD_LAUNCH(k_sweep_fwd_wide<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
                        b, N, pre, st);
 }
 
@@ -393,17 +393,17 @@ void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
   const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
   if (fp32) {
     if (use_lds)
-      hipLaunchKernelGGL((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+      DPD_LAUNCH((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
                          S.panel32, out, N, alpha, accumulate, st);
     else
-      hipLaunchKernelGGL((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks, S.panel32,
+      DPD_LAUNCH((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks, S.panel32,
                          out, N, alpha, accumulate, st);
   } else {
     if (use_lds)
-      hipLaunchKernelGGL((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
+      DPD_LAUNCH((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
                          S.panel64, out, N, alpha, accumulate, st);
     else
-      hipLaunchKernelGGL((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
+      DPD_LAUNCH((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
                          S.panel64, out, N, alpha, accumulate, st);
   }
 }
@@ -413,10 +413,10 @@ void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* 
                              const IterState* st) {
   const size_t lds = ((size_t)3 * lds_rows + 4 * 64 * 3) * sizeof(double);
   if (fp32)
-    hipLaunchKernelGGL(k_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
+    DPD_LAUNCH(k_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
                        out, N, alpha, accumulate, st);
   else
-    hipLaunchKernelGGL(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
+    DPD_LAUNCH(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
                        out, N, alpha, accumulate, st);
 }
 

@@ -199,3 +199,26 @@ def test_single_voxel_free_fall_is_exact():
     expect[0] += 0.01 * 0.3
     expect[2] += 1e-4 * -9.81
     assert float((xn - expect).abs().max()) <= 1e-15
+
+
+@pytest.mark.parametrize("name", ["c1", "robot"])
+def test_graph_replay_equals_direct_launches(name):
+    """Captured conjugate-gradient iterations give bitwise the result of direct
+    launches, over many replays with eager work and syncs in between."""
+    sc = SCENES[name]()
+    g1, o = pair(sc, fwd_solver="newton_pcg", use_graphs=1, fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
+                 fwd_max_iter=100000, bwd_max_iter=100000)
+    g0, _ = pair(sc, fwd_solver="newton_pcg", use_graphs=0, fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
+                 fwd_max_iter=100000, bwd_max_iter=100000)
+    act = None if o.Gm is None else elem_dev(np.random.default_rng(3).uniform(0, 1, o.E))
+    for seed in range(3):
+        x, v = _perturbed(o, seed=20 + seed)
+        xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+        a1 = g1.forward_step(xd, vd, act)
+        a0 = g0.forward_step(xd, vd, act)
+        assert torch.equal(a1[0], a0[0]) and a1[2]["fwd_iters"] == a0[2]["fwd_iters"]
+        gxn = to_dev(np.random.default_rng(seed).standard_normal(3 * o.N), o.N)
+        b1 = g1.backward_step(xd, vd, act, a1[0], gxn, torch.zeros_like(gxn))
+        b0 = g0.backward_step(xd, vd, act, a0[0], gxn, torch.zeros_like(gxn))
+        assert torch.equal(b1[0], b0[0]) and torch.equal(b1[1], b0[1])
+        torch.cuda.synchronize()

@@ -78,7 +78,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("leaf,sep", [(64, 2048), (8, 16)])
+@pytest.mark.parametrize("leaf,sep", [(64, 2048), (8, 16), (4096, 2048)])
 def test_host_mesh_matrix_and_solve(driver, name, leaf, sep):
     sc = CASES[name]()
     o = om.Model(sc)
