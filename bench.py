@@ -30,8 +30,9 @@ sys.path.insert(0, HERE)
 import workloads as W  # noqa: E402
 
 
-KERNEL_NAMES = {"solve": "global step A^{-1} b: k_solve_small (every level of both sweeps in one "
-                         "workgroup) for small factors, else the per-level k_sweep_* launches",
+KERNEL_NAMES = {"solve": "global step A^{-1} b: the per-level k_sweep_* launches of both sweeps",
+                "cg_dense": "k_cg_dense (a whole preconditioned conjugate-gradient solve in one "
+                            "cooperative launch, dense A^{-1})",
                 "sweep_fwd": "k_sweep_fwd (forward triangular sweep, one tree level per launch)",
                 "sweep_bwd": "k_sweep_bwd (backward triangular sweep, one tree level per launch)",
                 "sweep_fwd_wide": "k_sweep_gather + k_sweep_fwd_wide (forward sweep level with wide blocks)",
@@ -67,7 +68,7 @@ def parse():
     ap.add_argument("--slots", type=int, default=8, help="c4: resident requests")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
     ap.add_argument("--roofline-kernel", default=None,
-                    choices=["solve", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
+                    choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
                              "elem_hvp", "elem_forces"])
     return ap.parse_args()
 

@@ -90,7 +90,9 @@ typedef struct {
   int32_t precision;       /* DPD_FP64 or DPD_MIXED                                */
   int32_t check_every;     /* host convergence check period (iterations), >= 1   */
   int32_t use_graphs;      /* 1: run conjugate-gradient iterations as HIP graphs  */
-  int32_t pad;
+  int32_t fused_cg;        /* 1: meshes of at most 2048 free nodes keep A^{-1}
+                              dense and run each conjugate-gradient solve in one
+                              cooperative launch (same method and tolerances)  */
 } dpd_options;
 
 typedef struct {
@@ -112,6 +114,8 @@ typedef struct {
   int64_t factor_bytes;    /* device bytes of the FP64 panels (both layouts)      */
   int64_t device_bytes;    /* all device memory owned by the handle               */
   int64_t leaf_nodes;      /* dissection leaf size chosen for the factor          */
+  int64_t fused_blocks;    /* workgroups of the fused dense conjugate-gradient
+                              launch; 0 when solves use the multi-launch path    */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
@@ -223,7 +227,8 @@ enum {
   DPD_PROF_ELEM_FORCES = 4,      /* k_elem_forces: forward local step                       */
   DPD_PROF_SOLVE = 5,            /* a whole A^{-1} b, all of its launches                   */
   DPD_PROF_SWEEP_FWD_WIDE = 6,   /* k_sweep_fwd_wide: forward level, wide blocks            */
-  DPD_PROF_SWEEP_BWD_NARROW = 7  /* k_sweep_bwd_narrow: backward level of many small blocks */
+  DPD_PROF_SWEEP_BWD_NARROW = 7, /* k_sweep_bwd_narrow: backward level of many small blocks */
+  DPD_PROF_CG_DENSE = 8          /* k_cg_dense: a whole fused conjugate-gradient solve      */
 };
 typedef struct {
   int64_t launches;

@@ -26,6 +26,8 @@ constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of t
 constexpr int32_t kSepMax = 2048;
 constexpr int64_t kLdsBudget = 60 * 1024;
 constexpr int64_t kProfStride = 16;
+constexpr int kHoldPeriods = 8;         // about 25 us of s_sleep ahead of one timed kernel
+constexpr int kHoldPeriodsAround = 40;  // about 130 us ahead of a timed multi-launch solve
 constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
 
 }  // namespace
@@ -35,6 +37,10 @@ struct TimedLaunch {
   double bytes, flops;
   int st_idx, k;
   bool strict;
+  // a launch that iterates on the device: bytes and flops per iteration,
+  // multiplied at harvest by the iteration count of state iter_state
+  int iter_state = -1;
+  double iter_bytes = 0.0, iter_flops = 0.0;
 };
 
 struct dpd_mesh {
@@ -58,6 +64,12 @@ struct dpd_mesh {
   int32_t leaf_max = 0;                           // chosen dissection leaf size
   uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
   hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
+  // fused dense conjugate gradients (meshes with few free nodes)
+  DenseCG dcg{};
+  int dense_blocks = 0;                           // workgroups of its launch; 0: not available
+  bool dense_alloc = false;
+  double* ainv64 = nullptr;
+  float* ainv32 = nullptr;
   bool capturing = false;
   hipStream_t capture_stream = nullptr;
   double* w_e = nullptr;
@@ -133,14 +145,18 @@ struct ProfScope {
   ProfScope(dpd_mesh* mm, hipStream_t ss, int32_t cls, double bytes, double flops, int st_idx = -1,
             int k = 0, bool strict = true)
       : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF && !mm->capturing),
-        around(cls == DPD_PROF_SOLVE) {
+        around(cls == DPD_PROF_SOLVE || cls == DPD_PROF_CG_DENSE) {
     if (!on) return;
     // time one launch in every kProfStride to keep the event overhead small
     on = (m->prof_seen++ % kProfStride) == 0;
     if (!on) return;
     if (m->ev_free.empty()) {
       hipEvent_t a = nullptr, b = nullptr;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      // timing-only events: no system-scope fence (cache writeback and
+      // invalidate) when they are recorded, which would lengthen the kernel
+      // they bracket; they are read after a stream synchronisation
+      const unsigned fl = hipEventDisableSystemFence;
+      if (hipEventCreateWithFlags(&a, fl) != hipSuccess || hipEventCreateWithFlags(&b, fl) != hipSuccess) {
         on = false;
         return;
       }
@@ -153,6 +169,10 @@ struct ProfScope {
     t.st_idx = st_idx;
     t.k = k;
     t.strict = strict;
+    // Hold the stream while the timed launch and its events are enqueued, so
+    // the GPU reaches them back to back and the host's enqueue time between
+    // the start event and the kernel is not counted.
+    launch_hold(s, m->prof_class == DPD_PROF_SOLVE ? kHoldPeriodsAround : kHoldPeriods);
     if (around) {
       (void)hipEventRecord(t.ev.first, s);  // several launches: bracket them in the stream
     } else {
@@ -190,6 +210,11 @@ void prof_harvest(dpd_mesh* m) {
       m->prof_launches += 1;
       m->prof_bytes += t.bytes;
       m->prof_flops += t.flops;
+      if (t.iter_state >= 0) {
+        const double it = m->h_st[t.iter_state].iter;
+        m->prof_bytes += it * t.iter_bytes;
+        m->prof_flops += it * t.iter_flops;
+      }
     }
     m->ev_free.push_back(t.ev);
   }
@@ -305,6 +330,116 @@ dpd_status check_ready(dpd_mesh* m) {
   return DPD_OK;
 }
 
+// FP32 copy of the dense inverse for mixed precision.
+dpd_status dense_fp32(dpd_mesh* m, hipStream_t s) {
+  if (!m->dense_blocks) return DPD_OK;
+  const int64_t n = m->hm.n_free;
+  if (!m->ainv32) {
+    dpd_status st = dev_alloc(m, &m->ainv32, n * n);
+    if (st != DPD_OK) return st;
+    m->dcg.ainv32 = m->ainv32;
+  }
+  launch_to_fp32(s, n * n, m->ainv64, m->ainv32);
+  HIPCHECK(m, hipGetLastError());
+  HIPCHECK(m, hipStreamSynchronize(s));
+  return DPD_OK;
+}
+
+// Fused dense conjugate gradients for meshes of at most kSepMax free nodes:
+// the workgroup partition (R consecutive internal rows per workgroup, the hex
+// elements touching them, the incidence codes of each row in the fixed order
+// of the node-incidence table), the iteration vectors, and A^{-1} itself,
+// formed column by column by the factor's own sweeps on unit right-hand sides
+// (three per solve).  Leaves dense_blocks = 0 when the path is off or the
+// launch would not fit on the device.
+dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
+  const int n = (int)m->hm.n_free, N = (int)m->hm.n_nodes;
+  m->dense_blocks = 0;
+  if (!m->opt.fused_cg || n < 1 || n > kSepMax) return DPD_OK;
+  int G = 0;
+  if (!m->dense_alloc) {
+    int dev = 0, cus = 0;
+    HIPCHECK(m, hipGetDevice(&dev));
+    HIPCHECK(m, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int R = std::max(2, std::min(kDenseMaxRows, (n + std::max(1, cus) - 1) / std::max(1, cus)));
+    G = (n + R - 1) / R;
+    const HostMesh& hm = m->hm;
+    std::vector<int32_t> perm(n), inv(N, -1);
+    for (int i = 0; i < n; ++i) {
+      perm[i] = hm.free_nodes[m->S.perm[i]];
+      inv[perm[i]] = i;
+    }
+    std::vector<int32_t> eoff(G + 1, 0), elems, row_inc((size_t)8 * n, -1);
+    int max_e = 0;
+    for (int b = 0; b < G; ++b) {
+      const int j0 = b * R, j1 = std::min(n, j0 + R);
+      std::vector<int32_t> list;
+      for (int j = j0; j < j1; ++j)
+        for (int a = 0; a < 8; ++a) {
+          const int32_t code = hm.node_inc[(size_t)a * N + perm[j]];
+          if (code >= 0) list.push_back(code / 8);
+        }
+      std::sort(list.begin(), list.end());
+      list.erase(std::unique(list.begin(), list.end()), list.end());
+      for (int j = j0; j < j1; ++j)
+        for (int a = 0; a < 8; ++a) {
+          const int32_t code = hm.node_inc[(size_t)a * N + perm[j]];
+          if (code < 0) continue;
+          const int slot = (int)(std::lower_bound(list.begin(), list.end(), code / 8) - list.begin());
+          row_inc[(size_t)8 * j + a] = slot * 8 + code % 8;
+        }
+      elems.insert(elems.end(), list.begin(), list.end());
+      eoff[b + 1] = (int32_t)elems.size();
+      max_e = std::max(max_e, (int)list.size());
+    }
+    if (max_e > kDenseElems || cg_dense_max_blocks(n, max_e, false) < G ||
+        cg_dense_max_blocks(n, max_e, true) < G)
+      return DPD_OK;  // does not fit as one resident grid: keep the multi-launch path
+    DenseCG& d = m->dcg;
+    d.n = n;
+    d.rows = R;
+    d.max_elems = max_e;
+    int32_t *dinv, *deoff, *delems, *drinc;
+    double *r, *q, *p, *sv, *w, *z, *part;
+    uint32_t* bar;
+    dpd_status st;
+    if ((st = upload(m, &dinv, inv)) != DPD_OK || (st = upload(m, &deoff, eoff)) != DPD_OK ||
+        (st = upload(m, &delems, elems)) != DPD_OK || (st = upload(m, &drinc, row_inc)) != DPD_OK ||
+        (st = dev_alloc(m, &r, 6 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &q, 6 * (int64_t)n)) != DPD_OK ||
+        (st = dev_alloc(m, &p, 3 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &sv, 3 * (int64_t)n)) != DPD_OK ||
+        (st = dev_alloc(m, &w, 3 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &z, 3 * (int64_t)n)) != DPD_OK ||
+        (st = dev_alloc(m, &part, 4 * (int64_t)G)) != DPD_OK || (st = dev_alloc(m, &bar, kDenseBarWords)) != DPD_OK ||
+        (st = dev_alloc(m, &m->ainv64, (int64_t)n * n)) != DPD_OK)
+      return st;
+    d.perm = m->ds.perm_pub;
+    d.inv = dinv;
+    d.blk_eoff = deoff;
+    d.blk_elems = delems;
+    d.row_inc = drinc;
+    d.r = r;
+    d.q = q;
+    d.p = p;
+    d.s = sv;
+    d.w = w;
+    d.z = z;
+    d.part = part;
+    d.bar = bar;
+    d.ainv64 = m->ainv64;
+    m->dense_alloc = true;
+  }
+  G = (n + m->dcg.rows - 1) / m->dcg.rows;
+  for (int j0 = 0; j0 < n; j0 += 3) {
+    launch_unit_rhs(s, N, n, m->ds.perm_pub, j0, m->r);
+    solve(m, s, false, m->r, m->y, 1.0, 0, nullptr);
+    launch_collect_rows(s, N, n, m->ds.perm_pub, j0, m->y, m->ainv64);
+  }
+  HIPCHECK(m, hipGetLastError());
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->dense_blocks = G;
+  if (m->have_fp32) return dense_fp32(m, s);
+  return DPD_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -337,6 +472,7 @@ dpd_status dpd_default_options(dpd_options* o) {
   o->precision = DPD_FP64;
   o->check_every = 8;
   o->use_graphs = 1;
+  o->fused_cg = 1;
   return DPD_OK;
 }
 
@@ -415,6 +551,10 @@ int64_t footprint_bytes(const dpd_mesh* m) {
   b += 8 * ((int64_t)kAdjCacheRows * 8 * E + 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
   b += 2 * 8 * S.panel_size;                                 // FP64 panels, both layouts
   if (m->opt.precision == DPD_MIXED) b += 2 * 4 * S.panel_size;  // FP32 copies
+  if (m->opt.fused_cg && nf >= 1 && nf <= kSepMax) {             // dense inverse and its vectors
+    b += nf * nf * (m->opt.precision == DPD_MIXED ? 12 : 8);
+    b += 8 * 24 * nf + 4 * (9 * nf + N + 8 * E) + 8 * nf;
+  }
   return b;
 }
 
@@ -563,6 +703,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->factor_bytes = 2 * m->S.panel_size * (int64_t)sizeof(double);
   info->device_bytes = m->device_bytes;
   info->leaf_nodes = m->leaf_max;
+  info->fused_blocks = m->opt.fused_cg ? m->dense_blocks : 0;
   return DPD_OK;
 }
 
@@ -602,6 +743,7 @@ dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
     HIPCHECK(m, hipMemcpy(tmp.data(), m->panel64, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
     dpd_status st = make_fp32_panels(m, tmp, nullptr);
     if (st != DPD_OK) return st;
+    if ((st = dense_fp32(m, nullptr)) != DPD_OK) return st;
   }
   return DPD_OK;
 }
@@ -652,6 +794,10 @@ dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
     if (st != DPD_OK) return st;
   }
   HIPCHECK(m, hipStreamSynchronize(s));
+  {
+    dpd_status st = setup_dense(m, s);
+    if (st != DPD_OK) return st;
+  }
   m->factored = true;
   return DPD_OK;
 }
@@ -805,8 +951,46 @@ hipGraphExec_t cg_graph(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32) {
 // must describe the linearisation point.  Iterations run as captured graphs of
 // kGraphIters, except that while a kernel class is being timed one chunk in
 // kProfStride runs as direct launches (timed live).
+// Algorithmic traffic of the fused solver: one product with A^{-1} (n^2
+// entries and the 3n-vectors r in, s out) and, per iteration, that product,
+// the rotation cache of every Gauss point (15 doubles, 19 with muscles), the
+// connectivity and weights, and the 3n-vectors r, q, w, s, p, z each read and
+// written once.
+double dense_matvec_bytes(const dpd_mesh* m, bool fp32) {
+  const double n = (double)m->hm.n_free;
+  return n * n * (fp32 ? 4.0 : 8.0) + 2.0 * 3.0 * n * 8.0;
+}
+
+double dense_iter_bytes(const dpd_mesh* m, bool fp32) {
+  const double n = (double)m->hm.n_free, E = (double)m->hm.n_elems;
+  const double rows = m->opt.muscle_k > 0.0 ? 19.0 : 15.0;
+  return n * n * (fp32 ? 4.0 : 8.0) + rows * 8.0 * E * 8.0 + 8.0 * E * 4.0 + E * 8.0 + 12.0 * 3.0 * n * 8.0;
+}
+
+dpd_status cg_dense(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32) {
+  const int st_idx = st == m->st ? 0 : 1;
+  if (fp32 && !m->ainv32) return fail(m, DPD_ESTATE, "no FP32 copy of the dense inverse");
+  launch_fill(s, 3 * (int64_t)m->dm.N, m->z, 0.0);
+  {
+    const double n = (double)m->hm.n_free;
+    ProfScope ps(m, s, DPD_PROF_CG_DENSE, dense_matvec_bytes(m, fp32), 6.0 * n * n);
+    if (ps.on) {
+      ps.t.iter_state = st_idx;
+      ps.t.iter_bytes = dense_iter_bytes(m, fp32);
+      ps.t.iter_flops = 6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems;
+    }
+    HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, m->z, st));
+  }
+  dpd_status rc = read_state(m, s);
+  if (rc != DPD_OK) return rc;
+  if (m->h_st[st_idx].aborted)
+    return fail(m, DPD_EHIP, "fused conjugate-gradient solver: grid barrier timed out");
+  return DPD_OK;
+}
+
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
                               int max_it, int check_every) {
+  if (m->dense_blocks > 0 && m->opt.fused_cg) return cg_dense(m, s, st, rhs, fp32);
   dpd_status rc;
   const int64_t n3 = 3 * (int64_t)m->dm.N;
   const int st_idx = st == m->st ? 0 : 1;
@@ -942,7 +1126,7 @@ dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_o
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_SWEEP_BWD_NARROW)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CG_DENSE)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   m->prof_class = kernel_class;
   m->prof_launches = 0;

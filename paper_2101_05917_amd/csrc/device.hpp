@@ -20,6 +20,7 @@ struct IterState {
   int32_t iter, done, converged, nonfinite, curvature, inverted;
   uint32_t counter;                  // last-block-done ticket
   int32_t max_iter;                  // iteration cap of the conjugate-gradient loop
+  int32_t aborted;                   // the fused solver's grid barrier timed out
 };
 
 struct DevSolve {
@@ -56,6 +57,37 @@ struct DevMesh {
 
 constexpr int kElemsPerBlock = kBlock / 8;
 
+// Dense form of the preconditioned conjugate-gradient solve for meshes with
+// few free nodes: A^{-1} kept as an explicit n x n matrix (internal order) and
+// the whole iteration in one cooperative launch.  Workgroup b owns the rows
+// [b R, b R + R) of every internal-order vector and the hex elements that touch
+// them (computed redundantly where workgroups share an element).
+constexpr int kDenseMaxRows = 8;                // rows per workgroup (R)
+constexpr int kDenseBlock = 512;                // threads per workgroup
+constexpr int kDenseElems = kDenseBlock / 8;    // elements evaluated at once, one per 8 lanes
+static_assert(8 * kDenseMaxRows <= kDenseElems, "a workgroup's rows touch at most 8 R elements");
+constexpr int kDenseBarWords = 64 * 9;          // barrier counters (top, abort, 8 groups)
+struct DenseCG {
+  int32_t n, rows;            // free nodes; rows per workgroup R
+  int32_t max_elems;          // largest element list of a workgroup
+  int32_t pad;
+  const int32_t* perm;        // [n] internal row -> public node
+  const int32_t* inv;         // [N] public node -> internal row, -1 when fixed
+  const double* ainv64;       // [n][n] A^{-1} (symmetric; row j = column j)
+  const float* ainv32;
+  const int32_t* blk_eoff;    // [G + 1] element-list ranges
+  const int32_t* blk_elems;   // concatenated element lists
+  const int32_t* row_inc;     // [n][8] list slot * 8 + corner per incidence, -1 padded
+  double* r;                  // [2][3][n] residuals r_k (k even, odd)
+  double* q;                  // [2][3][n] H p_k (k even, odd)
+  double* p;                  // [3][n]
+  double* s;                  // [3][n] A^{-1} r_k
+  double* w;                  // [3][n] H s_k
+  double* z;                  // [3][n] solution
+  double* part;               // [G][4] per-workgroup partial sums
+  uint32_t* bar;              // [kDenseBarWords] barrier counters and abort flag
+};
+
 // Kernel timing: when start/stop events are set, the next launch made with
 // DPD_LAUNCH records them at its own dispatch start and completion
 // (hipExtLaunchKernelGGL), so the measured time is the kernel's alone.
@@ -85,6 +117,7 @@ namespace dpd {
 void launch_lincomb(hipStream_t s, int64_t n, double* out, double a, const double* x, double b,
                     const double* y);
 void launch_fill(hipStream_t s, int64_t n, double* out, double v);
+void launch_hold(hipStream_t s, int periods);
 void launch_reset(hipStream_t s, IterState* st, double tolsq, int max_iter);
 void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
                      double* xn, IterState* st, double* partials, double abs_tol_rel);
@@ -124,4 +157,13 @@ void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
                         const double* cache, double* g_youngs, double* g_act);
 constexpr int kAdjCacheRows = 19;
+// fused dense solver (cg_dense.hip)
+size_t cg_dense_lds_bytes(int n, int max_elems);
+int cg_dense_max_blocks(int n, int max_elems, bool fp32);
+hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
+                           const double* cache, const double* rhs, double* z_out, IterState* st);
+void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, double* b);
+void launch_collect_rows(hipStream_t s, int N, int n, const int32_t* perm, int j0, const double* x,
+                         double* ainv);
+void launch_to_fp32(hipStream_t s, int64_t count, const double* in, float* out);
 }  // namespace dpd

@@ -1,0 +1,356 @@
+// Device-side building blocks shared by the kernels of the PD step, its
+// adjoint and the fused dense conjugate-gradient solver (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.hpp"
+
+namespace dpd {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; valid in thread 0.
+__device__ inline double block_sum(double v, double* ws) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ws[i];
+  __syncthreads();
+  return t;
+}
+
+// Grid-wide sum with a deterministic order: each block publishes its partial,
+// the last block to arrive sums the partials in block order.  Returns true in
+// thread 0 of the last block, with the total in *total.
+__device__ inline bool grid_sum(double v, double* partials, IterState* st, double* total) {
+  __shared__ double ws[kBlock / 64];
+  __shared__ int last;
+  const double bs = block_sum(v, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t =
+        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // keep the order fixed: strided partial sums, then the block tree
+  s = block_sum(s, ws);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *total = s;
+  }
+  return threadIdx.x == 0;
+}
+
+// dN_a/dX_j at Gauss point q of a cubic voxel: (1/8) s_aj prod_{k != j}(1 +- g) * 2/dx,
+// the factor being 1 + g when bits k of a and q agree and 1 - g otherwise.
+struct GradTable {
+  double c2, c1, c0;  // magnitudes for two, one, zero agreeing axes
+};
+
+__device__ inline double bgrad(int q, int j, int a, const GradTable& T) {
+  const int x = ~(a ^ q);
+  const int agree = ((x >> ((j + 1) % 3)) & 1) + ((x >> ((j + 2) % 3)) & 1);
+  const double mag = agree == 2 ? T.c2 : (agree == 1 ? T.c1 : T.c0);
+  return ((a >> j) & 1) ? mag : -mag;
+}
+
+__device__ inline GradTable grad_table(double dx) {
+  const double g = 0.57735026918962576451;  // 1/sqrt(3)
+  const double s = 2.0 / dx / 8.0;
+  return {s * (1.0 + g) * (1.0 + g), s * (1.0 + g) * (1.0 - g), s * (1.0 - g) * (1.0 - g)};
+}
+
+// Closest rotation to F (row-major 3x3), i.e. argmax over SO(3) of tr(R^T F).
+// With R = R(quat) this is the largest-eigenvalue eigenvector of a symmetric
+// 4x4 matrix (Davenport's q-method); the eigenproblem is solved by cyclic
+// Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition).
+__device__ inline void jrot(double (&B)[4][4], double (&V)[4][4], int p, int q) {
+  const double apq = B[p][q];
+  if (fabs(apq) <= 1e-300) return;
+  const double tau = (B[q][q] - B[p][p]) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k == p || k == q) continue;
+    const double bkp = B[k][p], bkq = B[k][q];
+    B[k][p] = B[p][k] = c * bkp - s * bkq;
+    B[k][q] = B[q][k] = s * bkp + c * bkq;
+  }
+  B[p][p] -= t * apq;
+  B[q][q] += t * apq;
+  B[p][q] = B[q][p] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double vkp = V[k][p], vkq = V[k][q];
+    V[k][p] = c * vkp - s * vkq;
+    V[k][q] = s * vkp + c * vkq;
+  }
+}
+
+__device__ inline void closest_rotation(const double F[9], double R[9]) {
+  double B[4][4], V[4][4];
+  B[0][0] = F[0] + F[4] + F[8];
+  B[1][1] = F[0] - F[4] - F[8];
+  B[2][2] = -F[0] + F[4] - F[8];
+  B[3][3] = -F[0] - F[4] + F[8];
+  B[0][1] = B[1][0] = F[7] - F[5];
+  B[0][2] = B[2][0] = F[2] - F[6];
+  B[0][3] = B[3][0] = F[3] - F[1];
+  B[1][2] = B[2][1] = F[1] + F[3];
+  B[1][3] = B[3][1] = F[2] + F[6];
+  B[2][3] = B[3][2] = F[5] + F[7];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  double nrm = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) nrm += B[i][j] * B[i][j];
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    const double off = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[0][3] * B[0][3] +
+                       B[1][2] * B[1][2] + B[1][3] * B[1][3] + B[2][3] * B[2][3];
+    if (off <= 1e-34 * nrm) break;
+    jrot(B, V, 0, 1);
+    jrot(B, V, 0, 2);
+    jrot(B, V, 0, 3);
+    jrot(B, V, 1, 2);
+    jrot(B, V, 1, 3);
+    jrot(B, V, 2, 3);
+  }
+  int k = 0;
+  double best = B[0][0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (B[i][i] > best) {
+      best = B[i][i];
+      k = i;
+    }
+  double w = 1.0, x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i == k) {
+      w = V[0][i];
+      x = V[1][i];
+      y = V[2][i];
+      z = V[3][i];
+    }
+  const double s = 2.0 / (w * w + x * x + y * y + z * z);
+  R[0] = 1.0 - s * (y * y + z * z);
+  R[1] = s * (x * y - w * z);
+  R[2] = s * (x * z + w * y);
+  R[3] = s * (x * y + w * z);
+  R[4] = 1.0 - s * (x * x + z * z);
+  R[5] = s * (y * z - w * x);
+  R[6] = s * (x * z - w * y);
+  R[7] = s * (y * z + w * x);
+  R[8] = 1.0 - s * (x * x + y * y);
+}
+
+__device__ inline double det3(const double F[9]) {
+  return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+         F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// Differential of the closest rotation: dR = R [w]_x with
+// (tr(S) I - S) w = axial(R^T dF - dF^T R), S = R^T F (symmetric).  Returns the
+// inverse of K = tr(S) I - S as 6 entries (xx, yy, zz, xy, xz, yz); a singular K
+// (sigma_i + sigma_j = 0) yields zeros and is reported through the flag.
+__device__ inline bool rotation_kinv(const double F[9], const double R[9], double Ki[6]) {
+  double S[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = R[i] * F[j] + R[3 + i] * F[3 + j] + R[6 + i] * F[6 + j];
+  const double sxy = 0.5 * (S[1] + S[3]), sxz = 0.5 * (S[2] + S[6]), syz = 0.5 * (S[5] + S[7]);
+  const double tr = S[0] + S[4] + S[8];
+  const double kxx = tr - S[0], kyy = tr - S[4], kzz = tr - S[8];
+  const double kxy = -sxy, kxz = -sxz, kyz = -syz;
+  const double cxx = kyy * kzz - kyz * kyz, cyy = kxx * kzz - kxz * kxz, czz = kxx * kyy - kxy * kxy;
+  const double cxy = kxz * kyz - kxy * kzz, cxz = kxy * kyz - kxz * kyy, cyz = kxy * kxz - kxx * kyz;
+  const double det = kxx * cxx + kxy * cxy + kxz * cxz;
+  const double scale = fabs(tr) + 1e-300;
+  if (!(fabs(det) > 1e-12 * scale * scale * scale)) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Ki[i] = 0.0;
+    return false;
+  }
+  const double id = 1.0 / det;
+  Ki[0] = cxx * id;
+  Ki[1] = cyy * id;
+  Ki[2] = czz * id;
+  Ki[3] = cxy * id;
+  Ki[4] = cxz * id;
+  Ki[5] = cyz * id;
+  return true;
+}
+
+__device__ inline void rotation_apply_diff(const double R[9], const double Ki[6], const double dF[9],
+                                           double dR[9]) {
+  // M = R^T dF; a = axial(M - M^T) = (M21 - M12, M02 - M20, M10 - M01)
+  double M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = R[i] * dF[j] + R[3 + i] * dF[3 + j] + R[6 + i] * dF[6 + j];
+  const double a0 = M[7] - M[5], a1 = M[2] - M[6], a2 = M[3] - M[1];
+  const double w0 = Ki[0] * a0 + Ki[3] * a1 + Ki[4] * a2;
+  const double w1 = Ki[3] * a0 + Ki[1] * a1 + Ki[5] * a2;
+  const double w2 = Ki[4] * a0 + Ki[5] * a1 + Ki[2] * a2;
+  // R [w]_x, [w]_x = [[0,-w2,w1],[w2,0,-w0],[-w1,w0,0]]
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double r0 = R[3 * i], r1 = R[3 * i + 1], r2 = R[3 * i + 2];
+    dR[3 * i + 0] = r1 * w2 - r2 * w1;
+    dR[3 * i + 1] = -r0 * w2 + r2 * w0;
+    dR[3 * i + 2] = r0 * w1 - r1 * w0;
+  }
+}
+
+// Element tile: 32 elements x 8 Gauss points per 256-thread block.
+template <int kE>
+struct ElemTileT {
+  double xs[kE][8][3];
+  double Ps[kE][8][9];
+};
+using ElemTile = ElemTileT<kElemsPerBlock>;
+
+__device__ inline void gather_nodes(const DevMesh& M, const double* __restrict__ x, ElemTile& T,
+                                    int le, int a, int e, bool valid) {
+  if (valid) {
+    const int n = M.conn[(int64_t)a * M.E + e];
+    T.xs[le][a][0] = x[n];
+    T.xs[le][a][1] = x[(int64_t)M.N + n];
+    T.xs[le][a][2] = x[2 * (int64_t)M.N + n];
+  }
+}
+
+template <class Tile>
+__device__ inline void deformation_gradient(const Tile& T, int le, int q, const GradTable& G,
+                                            double F[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F[i] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const double b0 = bgrad(q, 0, a, G), b1 = bgrad(q, 1, a, G), b2 = bgrad(q, 2, a, G);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double xi = T.xs[le][a][i];
+      F[3 * i + 0] += xi * b0;
+      F[3 * i + 1] += xi * b1;
+      F[3 * i + 2] += xi * b2;
+    }
+  }
+}
+
+// f_a = sum_q P_q gradN_a(xi_q), written to fe[c][8e + a]
+template <class Tile>
+__device__ inline void corner_force(const Tile& T, int le, int a, const GradTable& G, double& f0,
+                                    double& f1, double& f2) {
+  f0 = f1 = f2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double b0 = bgrad(q, 0, a, G), b1 = bgrad(q, 1, a, G), b2 = bgrad(q, 2, a, G);
+    const double* P = T.Ps[le][q];
+    f0 += P[0] * b0 + P[1] * b1 + P[2] * b2;
+    f1 += P[3] * b0 + P[4] * b1 + P[5] * b2;
+    f2 += P[6] * b0 + P[7] * b1 + P[8] * b2;
+  }
+}
+
+__device__ inline void element_forces_out(const DevMesh& M, const ElemTile& T, int le, int a,
+                                          int e, bool valid, const GradTable& G, double* fe) {
+  if (!valid) return;
+  double f0, f1, f2;
+  corner_force(T, le, a, G, f0, f1, f2);
+  const int64_t E8 = 8 * (int64_t)M.E, idx = 8 * (int64_t)e + a;
+  fe[idx] = f0;
+  fe[E8 + idx] = f1;
+  fe[2 * E8 + idx] = f2;
+}
+
+
+// Stress differential of the adjoint local step at Gauss point q of an element
+// (eq:matrix_split): w (dF - dR[dF]) with dR from the cached rotation and
+// inv(tr(S) I - S), plus the muscle term (I - (r/|f|)(I - n n^T)) df m^T.
+// dF is formed from the direction staged in T.xs; the result goes to T.Ps.
+// cq holds the Gauss point's cache entries: R (9), inv(tr(S) I - S) (6) and,
+// with muscles, the unit fibre image n (3) and r/|f| (1).
+__device__ inline void hvp_stress_from_dF(const DevMesh& M, double* P, const double dF[9], double w,
+                                          const double* cq) {
+  double dR[9];
+  rotation_apply_diff(cq, cq + 9, dF, dR);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P[i] = w * (dF[i] - dR[i]);
+  if (M.muscle_k > 0.0) {
+    const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
+    const double d0 = dF[0] * m0 + dF[1] * m1 + dF[2] * m2;
+    const double d1 = dF[3] * m0 + dF[4] * m1 + dF[5] * m2;
+    const double d2 = dF[6] * m0 + dF[7] * m1 + dF[8] * m2;
+    const double n0 = cq[15], n1 = cq[16], n2 = cq[17], sc = cq[18];
+    const double nd = n0 * d0 + n1 * d1 + n2 * d2;
+    const double wm = M.muscle_k * M.Vq;
+    const double g0 = wm * (d0 - sc * (d0 - n0 * nd));
+    const double g1 = wm * (d1 - sc * (d1 - n1 * nd));
+    const double g2 = wm * (d2 - sc * (d2 - n2 * nd));
+    P[0] += g0 * m0; P[1] += g0 * m1; P[2] += g0 * m2;
+    P[3] += g1 * m0; P[4] += g1 * m1; P[5] += g1 * m2;
+    P[6] += g2 * m0; P[7] += g2 * m1; P[8] += g2 * m2;
+  }
+}
+
+// Cache entries of Gauss point q of element e (layout [19][8E]).
+__device__ inline void load_gauss_cache(const DevMesh& M, const double* __restrict__ cache, int e, int q,
+                                        double cq[19]) {
+  const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+  const int rows = M.muscle_k > 0.0 ? 19 : 15;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) cq[i] = i < rows ? cache[i * Q + qi] : 0.0;
+}
+
+__device__ inline void hvp_stress(const DevMesh& M, ElemTile& T, int le, int q, int e, const GradTable& G,
+                                  const double* __restrict__ cache) {
+  double cq[19], dF[9];
+  load_gauss_cache(M, cache, e, q, cq);
+  deformation_gradient(T, le, q, G, dF);
+  hvp_stress_from_dF(M, T.Ps[le][q], dF, M.w_e[e], cq);
+}
+
+// Sum the element forces of every node (fixed order) and form the residual.
+__device__ inline void node_force(const DevMesh& M, const double* __restrict__ fe, int n,
+                                  double& f0, double& f1, double& f2) {
+  const int64_t E8 = 8 * (int64_t)M.E;
+  f0 = f1 = f2 = 0.0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int p = M.node_inc[(int64_t)s * M.N + n];
+    if (p >= 0) {
+      f0 += fe[p];
+      f1 += fe[E8 + p];
+      f2 += fe[2 * E8 + p];
+    }
+  }
+}
+
+}  // namespace dpd

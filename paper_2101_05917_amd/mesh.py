@@ -73,11 +73,9 @@ class Mesh:
                 fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
                 C.byref(self.options), C.byref(h)))
         self.handle = h
-        info = L.MeshInfo()
-        L.check(self.lib.dpd_get_info(self.handle, C.byref(info)), self.handle)
-        self.info = {k: getattr(info, k) for k, _ in info._fields_}
-        self.n_nodes = info.n_nodes
-        self.n_elements = info.n_elements
+        self._read_info()
+        self.n_nodes = self.info["n_nodes"]
+        self.n_elements = self.info["n_elements"]
         self.youngs = youngs.copy()
         if factorize:
             self.factorize()
@@ -100,9 +98,15 @@ class Mesh:
             pass
 
     # ------------------------------------------------------------------ setup
+    def _read_info(self):
+        info = L.MeshInfo()
+        L.check(self.lib.dpd_get_info(self.handle, C.byref(info)), self.handle)
+        self.info = {k: getattr(info, k) for k, _ in info._fields_}
+
     def factorize(self):
         with torch.cuda.device(self.device):
             L.check(self.lib.dpd_factorize(self.handle, _stream(self.device)), self.handle)
+        self._read_info()
 
     def set_options(self, **iteration):
         for k, val in iteration.items():

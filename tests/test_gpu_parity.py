@@ -206,10 +206,10 @@ def test_graph_replay_equals_direct_launches(name):
     """Captured conjugate-gradient iterations give bitwise the result of direct
     launches, over many replays with eager work and syncs in between."""
     sc = SCENES[name]()
-    g1, o = pair(sc, fwd_solver="newton_pcg", use_graphs=1, fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
-                 fwd_max_iter=100000, bwd_max_iter=100000)
-    g0, _ = pair(sc, fwd_solver="newton_pcg", use_graphs=0, fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
-                 fwd_max_iter=100000, bwd_max_iter=100000)
+    g1, o = pair(sc, fwd_solver="newton_pcg", use_graphs=1, fused_cg=0, fwd_rel_tol=1e-12,
+                 bwd_rel_tol=1e-12, fwd_max_iter=100000, bwd_max_iter=100000)
+    g0, _ = pair(sc, fwd_solver="newton_pcg", use_graphs=0, fused_cg=0, fwd_rel_tol=1e-12,
+                 bwd_rel_tol=1e-12, fwd_max_iter=100000, bwd_max_iter=100000)
     act = None if o.Gm is None else elem_dev(np.random.default_rng(3).uniform(0, 1, o.E))
     for seed in range(3):
         x, v = _perturbed(o, seed=20 + seed)
@@ -222,3 +222,70 @@ def test_graph_replay_equals_direct_launches(name):
         b0 = g0.backward_step(xd, vd, act, a0[0], gxn, torch.zeros_like(gxn))
         assert torch.equal(b1[0], b0[0]) and torch.equal(b1[1], b0[1])
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["c1", "c2", "robot", "ragged"])
+def test_fused_dense_cg_matches_multilaunch_and_oracle(name, precision):
+    """The one-launch dense solver and the level-scheduled multi-launch solver
+    run the same preconditioned iteration: same converged states, both at the
+    oracle's, and the same iteration counts up to rounding."""
+    sc = SCENES[name]()
+    kw = dict(precision=precision, fwd_solver="newton_pcg", fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
+              fwd_max_iter=100000, bwd_max_iter=100000, check_every=16)
+    g1, o = pair(sc, fused_cg=1, **kw)
+    g0, _ = pair(sc, fused_cg=0, **kw)
+    print(name, precision, g1.info, flush=True)
+    assert g1.info["fused_blocks"] > 0 and g0.info["fused_blocks"] == 0
+    x, v = _perturbed(o, seed=31)
+    act = None if o.Gm is None else np.random.default_rng(32).uniform(0, 1, o.E)
+    a_dev = None if act is None else elem_dev(act)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    x1, _, s1 = g1.forward_step(xd, vd, a_dev)
+    x0, _, s0 = g0.forward_step(xd, vd, a_dev)
+    print("fwd", s1, s0, flush=True)
+    assert s1["converged"] == 1 and s0["converged"] == 1
+    xr = converged_state(o, x, v, act)
+    tol_x = 1e-9 if precision == "fp64" else 1e-5
+    for xn in (x1, x0):
+        assert np.linalg.norm(soa(xn) - xr) <= tol_x * np.linalg.norm(xr - x)
+    rng = np.random.default_rng(33)
+    gxn, gvn = rng.standard_normal(3 * o.N), rng.standard_normal(3 * o.N)
+    gE1 = torch.zeros(o.E, dtype=torch.float64, device="cuda:0")
+    gE0 = torch.zeros_like(gE1)
+    xrd = to_dev(xr, o.N)
+    b1 = g1.backward_step(xd, vd, a_dev, xrd, to_dev(gxn, o.N), to_dev(gvn, o.N), g_youngs=gE1,
+                          want_act=act is not None)
+    b0 = g0.backward_step(xd, vd, a_dev, xrd, to_dev(gxn, o.N), to_dev(gvn, o.N), g_youngs=gE0,
+                          want_act=act is not None)
+    print("bwd", b1[3], b0[3], flush=True)
+    assert b1[3]["converged"] == 1 and b0[3]["converged"] == 1
+    assert abs(b1[3]["bwd_iters"] - b0[3]["bwd_iters"]) <= 2
+    rx, rv, rE, ra, _ = oa.backward_step(o, x, v, act, xr, gxn, gvn, solver="direct")
+    tol_g = 1e-8 if precision == "fp64" else 1e-6
+    for gx, gE in ((b1[0], gE1), (b0[0], gE0)):
+        assert rel(soa(gx), rx) <= tol_g
+        assert rel(gE.cpu().numpy(), rE) <= tol_g
+    assert rel(soa(b1[0]), soa(b0[0])) <= (1e-10 if precision == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("name", ["c1", "robot"])
+def test_fused_dense_cg_iteration_cap(name):
+    """With the iteration cap reached, both solvers stop after exactly that many
+    updates, report no convergence and agree on the partial solution."""
+    sc = SCENES[name]()
+    kw = dict(bwd_rel_tol=1e-14, bwd_max_iter=3, check_every=1)
+    g1, o = pair(sc, fused_cg=1, **kw)
+    g0, _ = pair(sc, fused_cg=0, **kw)
+    assert g1.info["fused_blocks"] > 0
+    x, v = _perturbed(o, seed=41)
+    act = None if o.Gm is None else elem_dev(np.random.default_rng(42).uniform(0, 1, o.E))
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    gxn = to_dev(np.random.default_rng(43).standard_normal(3 * o.N), o.N)
+    zero = torch.zeros_like(gxn)
+    r1 = g1.backward_step(xd, vd, act, xd, gxn, zero)
+    r0 = g0.backward_step(xd, vd, act, xd, gxn, zero)
+    print(r1[3], r0[3], flush=True)
+    assert r1[3]["bwd_iters"] == 3 and r0[3]["bwd_iters"] == 3
+    assert r1[3]["converged"] == 0 and r0[3]["converged"] == 0
+    assert rel(soa(r1[0]), soa(r0[0])) <= 1e-11
