@@ -392,13 +392,18 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
       eoff[b + 1] = (int32_t)elems.size();
       max_e = std::max(max_e, (int)list.size());
     }
-    if (max_e > kDenseElems || cg_dense_max_blocks(n, max_e, false) < G ||
-        cg_dense_max_blocks(n, max_e, true) < G)
+    // r and q kept in every workgroup's LDS when they fit, else exchanged in memory
+    int vec = -1;
+    for (int v : {1, 0})
+      if (vec < 0 && cg_dense_max_blocks(n, v != 0, false) >= G && cg_dense_max_blocks(n, v != 0, true) >= G)
+        vec = v;
+    if (max_e > kDenseElems || vec < 0)
       return DPD_OK;  // does not fit as one resident grid: keep the multi-launch path
     DenseCG& d = m->dcg;
     d.n = n;
     d.rows = R;
     d.max_elems = max_e;
+    d.vec_lds = vec;
     int32_t *dinv, *deoff, *delems, *drinc;
     double *r, *q, *p, *sv, *w, *z, *part;
     uint32_t* bar;

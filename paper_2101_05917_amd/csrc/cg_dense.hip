@@ -134,62 +134,93 @@ __device__ inline double block_all(double v, double* ws, double* bc) {
   return out;
 }
 
-// s[rows j0..j0+R) = A^{-1}[rows] r, r staged in LDS (rv, [3][n]).  Every lane
-// walks its columns (c = lane, lane + kDenseBlock, ...) for all R rows at once;
-// the 3R sums are then reduced over the workgroup and stored device-coherently
-// and in the owner's LDS copy.
+// s[rows j0..j0+R) = A^{-1}[rows] r, r staged in LDS (rv, [3][n]): one wave
+// per row (R <= 8 waves), lanes over the columns with eight loads of the row
+// in flight per lane, then three wave sums.  The result is stored
+// device-coherently and in the owner's LDS copy.
 template <typename T>
 __device__ __forceinline__ void dense_rows(const T* __restrict__ ainv, int n, const double* rv, int j0, int R,
-                                           double* __restrict__ s_glob, double* own_s, double* red) {
-  double acc[kDenseMaxRows][3];
-#pragma unroll
-  for (int i = 0; i < kDenseMaxRows; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
-  for (int c = threadIdx.x; c < n; c += kDenseBlock) {
-    T av[kDenseMaxRows];
-#pragma unroll
-    for (int i = 0; i < kDenseMaxRows; ++i) av[i] = i < R ? ainv[(int64_t)(j0 + i) * n + c] : (T)0;
-    const double r0 = rv[c], r1 = rv[n + c], r2 = rv[2 * n + c];
-#pragma unroll
-    for (int i = 0; i < kDenseMaxRows; ++i) {
-      acc[i][0] += (double)av[i] * r0;
-      acc[i][1] += (double)av[i] * r1;
-      acc[i][2] += (double)av[i] * r2;
-    }
-  }
+                                           double* __restrict__ s_glob, double* own_s) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = wid; i < R; i += kDenseBlock / 64) {
+    const T* row = ainv + (int64_t)(j0 + i) * n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    int c = lane;
+    for (; c + 7 * 64 < n; c += 8 * 64) {
+      double p[8];
 #pragma unroll
-  for (int i = 0; i < kDenseMaxRows; ++i) {
-    if (i < R) {
+      for (int u = 0; u < 8; ++u) p[u] = (double)row[c + 64 * u];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double v = wave_sum(acc[i][c]);
-        if (lane == 0) red[(wid * kDenseMaxRows + i) * 3 + c] = v;
+      for (int u = 0; u < 8; ++u) {
+        const int cu = c + 64 * u;
+        a0 += p[u] * rv[cu];
+        a1 += p[u] * rv[n + cu];
+        a2 += p[u] * rv[2 * n + cu];
       }
     }
-  }
-  __syncthreads();
-  if (threadIdx.x < 3 * R) {
-    const int i = threadIdx.x / 3, c = threadIdx.x % 3;
-    double v = 0.0;
-    for (int w = 0; w < kDenseBlock / 64; ++w) v += red[(w * kDenseMaxRows + i) * 3 + c];
-    st_dev(&s_glob[c * n + j0 + i], v);
-    own_s[c * kDenseMaxRows + i] = v;
+    for (; c < n; c += 64) {
+      const double pc = (double)row[c];
+      a0 += pc * rv[c];
+      a1 += pc * rv[n + c];
+      a2 += pc * rv[2 * n + c];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      const int j = j0 + i;
+      st_dev(&s_glob[j], a0);
+      st_dev(&s_glob[n + j], a1);
+      st_dev(&s_glob[2 * n + j], a2);
+      own_s[i] = a0;
+      own_s[kDenseMaxRows + i] = a1;
+      own_s[2 * kDenseMaxRows + i] = a2;
+    }
   }
   __syncthreads();
 }
 
-template <typename T>
+// Two sums over the workgroup in one pass, returned to every lane.
+__device__ inline void block_all2(double& a, double& b, double* ws2, double* bc2) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    ws2[2 * wid] = a;
+    ws2[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      ta += ws2[2 * w];
+      tb += ws2[2 * w + 1];
+    }
+    bc2[0] = ta;
+    bc2[1] = tb;
+  }
+  __syncthreads();
+  a = bc2[0];
+  b = bc2[1];
+  __syncthreads();
+}
+
+template <typename T, bool kVecLds>
 __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, const T* __restrict__ ainv,
                                                           const double* __restrict__ cache,
                                                           const double* __restrict__ rhs,
                                                           double* __restrict__ z_out, IterState* st) {
   extern __shared__ double lds[];
-  double* rv = lds;                       // [3][n] r of the current phase 1
-  double* fl = lds + 3 * D.n;             // [kDenseElems][8][3] corner forces
+  // r_k of every row in LDS ([3][n]); with kVecLds also q_k of every row, so
+  // that r and q never go through device memory (every workgroup forms the
+  // same values from the same inputs), else they are exchanged through D.r, D.q
+  double* rv = lds;
+  double* ql = lds + 3 * D.n;
+  double* fl = lds + (kVecLds ? 6 : 3) * D.n;   // [kDenseElems][8][3] corner forces
   __shared__ ElemTileT<kDenseElems> Tl;
   __shared__ double ws[kDenseBlock / 64];
   __shared__ double bc;
-  __shared__ double red[(kDenseBlock / 64) * kDenseMaxRows * 3];
+  __shared__ double ws2[2 * (kDenseBlock / 64)], bc2[2];
   // the workgroup's own rows: r_k, s_k, p, z (owner-private), node data
   __shared__ double own_r[3 * kDenseMaxRows], own_s[3 * kDenseMaxRows];
   __shared__ double own_p[3 * kDenseMaxRows], own_z[3 * kDenseMaxRows];
@@ -238,14 +269,18 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     rv[n + i] = rhs[(int64_t)N + node];
     rv[2 * n + i] = rhs[2 * (int64_t)N + node];
   }
+  if (kVecLds)
+    for (int i = tid; i < 3 * n; i += kDenseBlock) ql[i] = 0.0;
   __syncthreads();
   double acc = 0.0;
   if (tid < 3 * R) {
     const int c = tid / R, i = tid % R, j = j0 + i;
     const double v = rv[c * n + j];
-    st_dev(&D.r[c * n + j], v);
-    st_dev(&D.q[c * n + j], 0.0);
-    st_dev(&D.q[3 * n + c * n + j], 0.0);
+    if (!kVecLds) {
+      st_dev(&D.r[c * n + j], v);
+      st_dev(&D.q[c * n + j], 0.0);
+      st_dev(&D.q[3 * n + c * n + j], 0.0);
+    }
     own_r[c * MR + i] = v;
     own_p[c * MR + i] = 0.0;
     own_z[c * MR + i] = 0.0;
@@ -253,7 +288,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   }
   acc = block_sum(acc, ws);
   if (tid == 0) st_dev(&D.part[4 * b + 2], acc);
-  dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s, red);
+  dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s);
   alive = grid_barrier(D.bar, round);
 
   double nb2 = 0.0, rsq = 0.0, rs_old = 0.0, alpha_old = 0.0, alpha = 0.0, beta = 0.0;
@@ -341,8 +376,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       gam = own_r[tid] * s0 + own_r[MR + tid] * s1 + own_r[2 * MR + tid] * s2;
       del = o0 * s0 + o1 * s1 + o2 * s2;
     }
-    gam = block_sum(gam, ws);
-    del = block_sum(del, ws);
+    block_all2(gam, del, ws2, bc2);
     if (tid == 0) {
       st_dev(&D.part[4 * b + 0], gam);
       st_dev(&D.part[4 * b + 1], del);
@@ -366,12 +400,12 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       wv[u] = qv[u] = rr[u] = 0.0;
       if (i < 3 * n) {
         wv[u] = ld_dev(&D.w[i]);
-        qv[u] = ld_dev(&qprev[i]);
-        rr[u] = ld_dev(&rk[i]);
+        qv[u] = kVecLds ? ql[i] : ld_dev(&qprev[i]);
+        rr[u] = kVecLds ? rv[i] : ld_dev(&rk[i]);
       }
     }
-    const double gamma = block_all(pg, ws, &bc);
-    const double delta = block_all(pd, ws, &bc);
+    double gamma = pg, delta = pd;
+    block_all2(gamma, delta, ws2, bc2);
     beta = k == 0 ? 0.0 : gamma / rs_old;
     const double den = k == 0 ? delta : delta - beta * gamma / alpha_old;
     if (!(den > 0.0) || !isfinite(den) || !isfinite(gamma)) {
@@ -390,8 +424,8 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
           wv[u] = qv[u] = rr[u] = 0.0;
           if (i < 3 * n) {
             wv[u] = ld_dev(&D.w[i]);
-            qv[u] = ld_dev(&qprev[i]);
-            rr[u] = ld_dev(&rk[i]);
+            qv[u] = kVecLds ? ql[i] : ld_dev(&qprev[i]);
+            rr[u] = kVecLds ? rv[i] : ld_dev(&rk[i]);
           }
         }
       }
@@ -402,11 +436,14 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
           const double qi = wv[u] + beta * qv[u];
           const double ri = rr[u] - alpha * qi;
           rv[i] = ri;
+          if (kVecLds) ql[i] = qi;
           const int c = i / n, j = i - c * n;
           if (j >= j0 && j < j1) {
             const int o = c * MR + (j - j0);
-            st_dev(&qcur[i], qi);
-            st_dev(&rnext[i], ri);
+            if (!kVecLds) {
+              st_dev(&qcur[i], qi);
+              st_dev(&rnext[i], ri);
+            }
             own_r[o] = ri;
             const double pi = own_s[o] + beta * own_p[o];
             own_p[o] = pi;
@@ -419,7 +456,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     racc = block_sum(racc, ws);
     if (tid == 0) st_dev(&D.part[4 * b + 2], racc);
     __syncthreads();
-    dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s, red);
+    dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s);
     if (!(alive = grid_barrier(D.bar, round))) break;
   }
 
@@ -474,30 +511,40 @@ __global__ void __launch_bounds__(kBlock) k_to_fp32(int64_t count, const double*
 
 }  // namespace
 
-size_t cg_dense_lds_bytes(int n, int max_elems) {
-  (void)max_elems;  // the corner-force table spans the full element tile
-  return ((size_t)3 * n + (size_t)24 * kDenseElems) * sizeof(double);
+size_t cg_dense_lds_bytes(int n, bool vec_lds) {
+  return ((size_t)(vec_lds ? 6 : 3) * n + (size_t)24 * kDenseElems) * sizeof(double);
 }
 
-int cg_dense_max_blocks(int n, int max_elems, bool fp32) {
+namespace {
+const void* dense_kernel(bool fp32, bool vec_lds) {
+  if (fp32) return vec_lds ? (const void*)k_cg_dense<float, true> : (const void*)k_cg_dense<float, false>;
+  return vec_lds ? (const void*)k_cg_dense<double, true> : (const void*)k_cg_dense<double, false>;
+}
+}  // namespace
+
+int cg_dense_max_blocks(int n, bool vec_lds, bool fp32) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t lds = cg_dense_lds_bytes(n, max_elems);
-  const void* fn = fp32 ? (const void*)k_cg_dense<float> : (const void*)k_cg_dense<double>;
+  const size_t lds = cg_dense_lds_bytes(n, vec_lds);
+  const void* fn = dense_kernel(fp32, vec_lds);
   if (lds > 48 * 1024 &&
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
     return 0;
-  hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_dense<float>, kDenseBlock, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_dense<double>, kDenseBlock, lds);
-  if (e != hipSuccess) return 0;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kDenseBlock, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
   return per_cu * cus;
 }
 
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double* z_out, IterState* st) {
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar);
-  const size_t lds = cg_dense_lds_bytes(D.n, D.max_elems);
+  const bool vec = D.vec_lds != 0;
+  const size_t lds = cg_dense_lds_bytes(D.n, vec);
   DevMesh m = M;
   DenseCG d = D;
   IterState* stp = st;
@@ -507,12 +554,12 @@ hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, in
   if (fp32) {
     const float* a = D.ainv32;
     void* args[] = {&m, &d, &a, &cp, &rp, &zp, &stp};
-    return hipLaunchCooperativeKernel((const void*)k_cg_dense<float>, dim3(blocks), dim3(kDenseBlock), args,
+    return hipLaunchCooperativeKernel(dense_kernel(true, vec), dim3(blocks), dim3(kDenseBlock), args,
                                       (unsigned)lds, s);
   }
   const double* a = D.ainv64;
   void* args[] = {&m, &d, &a, &cp, &rp, &zp, &stp};
-  return hipLaunchCooperativeKernel((const void*)k_cg_dense<double>, dim3(blocks), dim3(kDenseBlock), args,
+  return hipLaunchCooperativeKernel(dense_kernel(false, vec), dim3(blocks), dim3(kDenseBlock), args,
                                     (unsigned)lds, s);
 }
 

@@ -70,7 +70,7 @@ constexpr int kDenseBarWords = 64 * 9;          // barrier counters (top, abort,
 struct DenseCG {
   int32_t n, rows;            // free nodes; rows per workgroup R
   int32_t max_elems;          // largest element list of a workgroup
-  int32_t pad;
+  int32_t vec_lds;            // 1: r and q of every row live in each workgroup's LDS
   const int32_t* perm;        // [n] internal row -> public node
   const int32_t* inv;         // [N] public node -> internal row, -1 when fixed
   const double* ainv64;       // [n][n] A^{-1} (symmetric; row j = column j)
@@ -158,8 +158,8 @@ void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const
                         const double* cache, double* g_youngs, double* g_act);
 constexpr int kAdjCacheRows = 19;
 // fused dense solver (cg_dense.hip)
-size_t cg_dense_lds_bytes(int n, int max_elems);
-int cg_dense_max_blocks(int n, int max_elems, bool fp32);
+size_t cg_dense_lds_bytes(int n, bool vec_lds);
+int cg_dense_max_blocks(int n, bool vec_lds, bool fp32);
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double* z_out, IterState* st);
 void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, double* b);

@@ -224,13 +224,19 @@ def test_graph_replay_equals_direct_launches(name):
         torch.cuda.synchronize()
 
 
+def wide_beam():
+    """2016 free nodes: the largest dense size, where r and q no longer fit in
+    LDS next to the element tile and go through device memory."""
+    return W.cantilever(14, 11, 11, youngs="loguniform", seed=5)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["c1", "c2", "robot", "ragged"])
+@pytest.mark.parametrize("name", ["c1", "c2", "robot", "ragged", "wide"])
 def test_fused_dense_cg_matches_multilaunch_and_oracle(name, precision):
     """The one-launch dense solver and the level-scheduled multi-launch solver
     run the same preconditioned iteration: same converged states, both at the
     oracle's, and the same iteration counts up to rounding."""
-    sc = SCENES[name]()
+    sc = wide_beam() if name == "wide" else SCENES[name]()
     kw = dict(precision=precision, fwd_solver="newton_pcg", fwd_rel_tol=1e-12, bwd_rel_tol=1e-12,
               fwd_max_iter=100000, bwd_max_iter=100000, check_every=16)
     g1, o = pair(sc, fused_cg=1, **kw)
