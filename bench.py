@@ -198,17 +198,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str, precision: str):
+def measured_traffic(workload: str, kernel: str, precision: str, iters_per_launch: float):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in
     profiles/traffic.json (each scaled by the plain-copy calibration), or None
-    if none was taken for this kernel or the kernel sources changed since."""
+    if none was taken for this kernel or the kernel sources changed since.
+    For the fused solver, whose launches run a varying number of iterations,
+    the record holds bytes per iteration, scaled here by the timed launches'
+    mean iteration count."""
     path = os.path.join(HERE, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload, {}).get(f"{kernel}/{precision}")
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+    per = rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+    return per * iters_per_launch if rec.get("per") == "iteration" else per
 
 
 def copy_calibration(nbytes: int):
@@ -226,9 +230,6 @@ def copy_calibration(nbytes: int):
 
 def main():
     args = parse()
-    if args.roofline_kernel is None:
-        # the kernel with the largest share of GPU time in the rocprofv3 summary of each workload
-        args.roofline_kernel = {"c5": "sweep_fwd_wide"}.get(args.config, "sweep_bwd")
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -250,6 +251,11 @@ def main():
     mesh = Mesh.from_scene(scene, fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol,
                            fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
                            bwd_max_iter=200000, precision=args.precision, check_every=16)
+    if args.roofline_kernel is None:
+        # the kernel with the largest share of GPU time in the rocprofv3 summary of the workload:
+        # the fused conjugate-gradient launch where the mesh is small enough for it, else the
+        # forward sweep level with wide blocks
+        args.roofline_kernel = "cg_dense" if mesh.info["fused_blocks"] > 0 else "sweep_fwd_wide"
     X = mesh.rest_positions()
     N = mesh.n_nodes
     c = W.loss_vector(N, scene.loss_seed)
@@ -276,10 +282,13 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0,
-                "traffic": measured_traffic(scene.name, args.roofline_kernel, args.precision),
+                "traffic": measured_traffic(scene.name, args.roofline_kernel, args.precision,
+                                            prof["iterations"] / max(1, prof["launches"])),
                 "kernel": KERNEL_NAMES[args.roofline_kernel],
                 "launches": prof["launches"], "avg_us": avg_ms * 1e3,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
+    if prof["iterations"]:
+        roofline["iterations_per_launch"] = prof["iterations"] / max(1, prof["launches"])
 
     # accuracy against the oracle's reference gradient
     err = None
@@ -316,7 +325,8 @@ def main():
         "config": {"workload": f"{scene.name}: {len(scene.cells)} hex, {N} nodes, {3 * N} DoFs, "
                                f"{T} steps fwd+adjoint, loss dot(N(0,1) seed 0, x_T)",
                    "fwd_solver": args.fwd_solver, "bwd_solver": args.bwd_solver,
-                   "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol},
+                   "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol,
+                   "precision": args.precision, "fused_cg_workgroups": mesh.info["fused_blocks"]},
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,
         "grad_rel_err_vs_oracle": err,

@@ -92,7 +92,10 @@ typedef struct {
   int32_t use_graphs;      /* 1: run conjugate-gradient iterations as HIP graphs  */
   int32_t fused_cg;        /* 1: meshes of at most 2048 free nodes keep A^{-1}
                               dense and run each conjugate-gradient solve in one
-                              cooperative launch (same method and tolerances)  */
+                              cooperative launch (same method and tolerances);
+                              0: off; 2 + m: only with LDS placement m (bit 0:
+                              r and q, bit 1: the workgroup's rows of A^{-1}),
+                              off when m does not fit; read at factorization  */
 } dpd_options;
 
 typedef struct {
@@ -116,6 +119,8 @@ typedef struct {
   int64_t leaf_nodes;      /* dissection leaf size chosen for the factor          */
   int64_t fused_blocks;    /* workgroups of the fused dense conjugate-gradient
                               launch; 0 when solves use the multi-launch path    */
+  int64_t fused_lds;       /* its LDS placement, FP64 | FP32 << 2 (bits as in
+                              dpd_options.fused_cg)                              */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
@@ -218,7 +223,9 @@ dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* 
  * stream, returns the totals since the start and stops timing.  One launch
  * in every 16 of the class is timed (two event records each), so the totals
  * describe that sample; launches that exit early because their iteration had
- * already converged are not counted.  Class DPD_PROF_OFF disables timing. */
+ * already converged are not counted.  Launches of DPD_PROF_CG_DENSE (each a
+ * whole solve of varying length) are all timed.  Class DPD_PROF_OFF disables
+ * timing. */
 enum {
   DPD_PROF_OFF = 0,
   DPD_PROF_SWEEP_FWD = 1,        /* k_sweep_fwd: forward level, blocks of <= 64 columns     */
@@ -235,6 +242,8 @@ typedef struct {
   double total_ms;         /* summed event-measured durations                    */
   double bytes;            /* summed algorithmic bytes                           */
   double flops;            /* summed algorithmic floating-point operations       */
+  int64_t iterations;      /* device-side iterations of the timed launches (class
+                              DPD_PROF_CG_DENSE), else 0                         */
 } dpd_kernel_profile;
 dpd_status dpd_profile_start(dpd_mesh* mesh, int32_t kernel_class);
 dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* out);

@@ -51,12 +51,12 @@ class Stats(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
-        "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks")]
+        "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds")]
 
 
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
-                ("flops", C.c_double)]
+                ("flops", C.c_double), ("iterations", C.c_int64)]
 
 
 class Request(C.Structure):

@@ -86,7 +86,7 @@ struct dpd_mesh {
   int32_t prof_class = DPD_PROF_OFF;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   std::vector<TimedLaunch> ev_pending;
-  int64_t prof_launches = 0, prof_seen = 0;
+  int64_t prof_launches = 0, prof_seen = 0, prof_iters = 0;
   double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
 };
 
@@ -147,8 +147,13 @@ struct ProfScope {
       : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF && !mm->capturing),
         around(cls == DPD_PROF_SOLVE || cls == DPD_PROF_CG_DENSE) {
     if (!on) return;
-    // time one launch in every kProfStride to keep the event overhead small
-    on = (m->prof_seen++ % kProfStride) == 0;
+    // Short kernels: time one launch in every kProfStride, behind a bounded
+    // stream hold (below).  The fused solver's launches run for hundreds of
+    // microseconds and their work differs from launch to launch (the number of
+    // iterations), so every one of them is timed, without a hold: the host's
+    // enqueue delay is then a few percent of a launch.
+    const bool every = cls == DPD_PROF_CG_DENSE;
+    on = every || (m->prof_seen++ % kProfStride) == 0;
     if (!on) return;
     if (m->ev_free.empty()) {
       hipEvent_t a = nullptr, b = nullptr;
@@ -172,7 +177,7 @@ struct ProfScope {
     // Hold the stream while the timed launch and its events are enqueued, so
     // the GPU reaches them back to back and the host's enqueue time between
     // the start event and the kernel is not counted.
-    launch_hold(s, m->prof_class == DPD_PROF_SOLVE ? kHoldPeriodsAround : kHoldPeriods);
+    if (!every) launch_hold(s, cls == DPD_PROF_SOLVE ? kHoldPeriodsAround : kHoldPeriods);
     if (around) {
       (void)hipEventRecord(t.ev.first, s);  // several launches: bracket them in the stream
     } else {
@@ -212,6 +217,7 @@ void prof_harvest(dpd_mesh* m) {
       m->prof_flops += t.flops;
       if (t.iter_state >= 0) {
         const double it = m->h_st[t.iter_state].iter;
+        m->prof_iters += m->h_st[t.iter_state].iter;
         m->prof_bytes += it * t.iter_bytes;
         m->prof_flops += it * t.iter_flops;
       }
@@ -392,18 +398,26 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
       eoff[b + 1] = (int32_t)elems.size();
       max_e = std::max(max_e, (int)list.size());
     }
-    // r and q kept in every workgroup's LDS when they fit, else exchanged in memory
-    int vec = -1;
-    for (int v : {1, 0})
-      if (vec < 0 && cg_dense_max_blocks(n, v != 0, false) >= G && cg_dense_max_blocks(n, v != 0, true) >= G)
-        vec = v;
-    if (max_e > kDenseElems || vec < 0)
+    // What lives in LDS, per precision of A^{-1}, in order of preference: the
+    // full r and q and the workgroup's rows of A^{-1}; r and q alone; the rows
+    // alone; neither.  The first that fits with one workgroup per CU wins
+    // (r and q in LDS remove two device-coherent vector reads per iteration,
+    // the rows in LDS only shorten the dense product's load latency).
+    // (fused_cg = 2 + m asks for placement m only.)
+    int mode[2] = {-1, -1};
+    for (int p = 0; p < 2; ++p)
+      for (int md : {kDenseVecLds | kDenseAinvLds, kDenseVecLds, kDenseAinvLds, 0})
+        if (mode[p] < 0 && (m->opt.fused_cg < 2 || md == m->opt.fused_cg - 2) &&
+            cg_dense_max_blocks(n, R, md, p == 1) >= G)
+          mode[p] = md;
+    if (max_e > kDenseElems || mode[0] < 0 || mode[1] < 0)
       return DPD_OK;  // does not fit as one resident grid: keep the multi-launch path
     DenseCG& d = m->dcg;
     d.n = n;
     d.rows = R;
     d.max_elems = max_e;
-    d.vec_lds = vec;
+    d.mode64 = mode[0];
+    d.mode32 = mode[1];
     int32_t *dinv, *deoff, *delems, *drinc;
     double *r, *q, *p, *sv, *w, *z, *part;
     uint32_t* bar;
@@ -450,6 +464,9 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
 namespace {
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
                               int max_it, int check_every);
+dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
+                          bool fp32, bool pd_fallback);
+dpd_status check_aborted(dpd_mesh* m, int st_idx);
 }  // namespace
 
 extern "C" {
@@ -709,6 +726,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->device_bytes = m->device_bytes;
   info->leaf_nodes = m->leaf_max;
   info->fused_blocks = m->opt.fused_cg ? m->dense_blocks : 0;
+  info->fused_lds = info->fused_blocks ? m->dcg.mode64 | (m->dcg.mode32 << 2) : 0;
   return DPD_OK;
 }
 
@@ -835,12 +853,34 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
     }
     launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, 0, never, 0);
+    // With the fused solver a Newton step needs one synchronisation: its
+    // solve, the update x += z (z = the PD step after a curvature failure)
+    // and the next residual are enqueued together, and the solve's iteration
+    // count is read with the residual's convergence flag.
+    const bool fused = m->dense_blocks > 0 && o.fused_cg;
+    bool pending = false;
     for (outer = 0;; ++outer) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (pending) {
+        if ((rc = check_aborted(m, 1)) != DPD_OK) return rc;
+        solves += std::max(1, m->h_st[1].iter);
+        pending = false;
+      }
       if (m->h_st[0].done || solves >= max_it) break;
       launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
       const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
       launch_reset(s, inner, o.fwd_inner_tol * o.fwd_inner_tol, inner_max);
+      if (fused) {
+        if ((rc = cg_dense_async(m, s, inner, m->r, -1.0, fp32, true)) != DPD_OK) return rc;
+        pending = true;
+        launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
+        {
+          ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
+          launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+        }
+        launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
+        continue;
+      }
       launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
       if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
           DPD_OK)
@@ -972,10 +1012,15 @@ double dense_iter_bytes(const dpd_mesh* m, bool fp32) {
   return n * n * (fp32 ? 4.0 : 8.0) + rows * 8.0 * E * 8.0 + 8.0 * E * 4.0 + E * 8.0 + 12.0 * 3.0 * n * 8.0;
 }
 
-dpd_status cg_dense(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32) {
+// One fused solve on state st (reset beforehand with its tolerance and cap)
+// for the right-hand side rhs_scale * rhs, into m->z (fixed rows stay zero).
+// Asynchronous: the caller reads the state (iterations, curvature, abort) at
+// its next synchronisation.  With pd_fallback a non-positive curvature leaves
+// z = A^{-1} rhs, the plain PD step.
+dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
+                          bool fp32, bool pd_fallback) {
   const int st_idx = st == m->st ? 0 : 1;
   if (fp32 && !m->ainv32) return fail(m, DPD_ESTATE, "no FP32 copy of the dense inverse");
-  launch_fill(s, 3 * (int64_t)m->dm.N, m->z, 0.0);
   {
     const double n = (double)m->hm.n_free;
     ProfScope ps(m, s, DPD_PROF_CG_DENSE, dense_matvec_bytes(m, fp32), 6.0 * n * n);
@@ -984,13 +1029,25 @@ dpd_status cg_dense(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs
       ps.t.iter_bytes = dense_iter_bytes(m, fp32);
       ps.t.iter_flops = 6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems;
     }
-    HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, m->z, st));
+    HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, rhs_scale,
+                                pd_fallback ? 1 : 0, m->z, st));
   }
-  dpd_status rc = read_state(m, s);
-  if (rc != DPD_OK) return rc;
+  return DPD_OK;
+}
+
+dpd_status check_aborted(dpd_mesh* m, int st_idx) {
   if (m->h_st[st_idx].aborted)
     return fail(m, DPD_EHIP, "fused conjugate-gradient solver: grid barrier timed out");
   return DPD_OK;
+}
+
+dpd_status cg_dense(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32) {
+  const int st_idx = st == m->st ? 0 : 1;
+  dpd_status rc = cg_dense_async(m, s, st, rhs, 1.0, fp32, false);
+  if (rc != DPD_OK) return rc;
+  rc = read_state(m, s);
+  if (rc != DPD_OK) return rc;
+  return check_aborted(m, st_idx);
 }
 
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
@@ -1136,6 +1193,7 @@ dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   m->prof_class = kernel_class;
   m->prof_launches = 0;
   m->prof_seen = 0;
+  m->prof_iters = 0;
   m->prof_ms = m->prof_bytes = m->prof_flops = 0.0;
   return DPD_OK;
 }
@@ -1145,6 +1203,7 @@ dpd_status dpd_profile_read(dpd_mesh* m, void* stream, dpd_kernel_profile* out) 
   HIPCHECK(m, hipStreamSynchronize((hipStream_t)stream));
   prof_harvest(m);
   out->launches = m->prof_launches;
+  out->iterations = m->prof_iters;
   out->total_ms = m->prof_ms;
   out->bytes = m->prof_bytes;
   out->flops = m->prof_flops;

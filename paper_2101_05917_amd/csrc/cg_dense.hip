@@ -134,16 +134,17 @@ __device__ inline double block_all(double v, double* ws, double* bc) {
   return out;
 }
 
-// s[rows j0..j0+R) = A^{-1}[rows] r, r staged in LDS (rv, [3][n]): one wave
-// per row (R <= 8 waves), lanes over the columns with eight loads of the row
-// in flight per lane, then three wave sums.  The result is stored
+// s[rows j0..j0+R) = A^{-1}[rows] r, r staged in LDS (rv, [3][n]); `rows`
+// points at the workgroup's R rows of A^{-1} (in LDS or in device memory).
+// One wave per row (R <= 8 waves), lanes over the columns with eight loads of
+// the row in flight per lane, then three wave sums.  The result is stored
 // device-coherently and in the owner's LDS copy.
 template <typename T>
-__device__ __forceinline__ void dense_rows(const T* __restrict__ ainv, int n, const double* rv, int j0, int R,
+__device__ __forceinline__ void dense_rows(const T* __restrict__ rows, int n, const double* rv, int j0, int R,
                                            double* __restrict__ s_glob, double* own_s) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int i = wid; i < R; i += kDenseBlock / 64) {
-    const T* row = ainv + (int64_t)(j0 + i) * n;
+    const T* row = rows + (int64_t)i * n;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     int c = lane;
     for (; c + 7 * 64 < n; c += 8 * 64) {
@@ -205,24 +206,30 @@ __device__ inline void block_all2(double& a, double& b, double* ws2, double* bc2
   __syncthreads();
 }
 
-template <typename T, bool kVecLds>
+template <typename T, bool kVecLds, bool kAinvLds>
 __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, const T* __restrict__ ainv,
                                                           const double* __restrict__ cache,
-                                                          const double* __restrict__ rhs,
-                                                          double* __restrict__ z_out, IterState* st) {
+                                                          const double* __restrict__ rhs, double rhs_scale,
+                                                          int pd_fallback, double* __restrict__ z_out,
+                                                          IterState* st) {
   extern __shared__ double lds[];
   // r_k of every row in LDS ([3][n]); with kVecLds also q_k of every row, so
   // that r and q never go through device memory (every workgroup forms the
   // same values from the same inputs), else they are exchanged through D.r, D.q
+  // With kAinvLds the workgroup's R rows of A^{-1} are copied to LDS once per
+  // launch (after the vectors).
   double* rv = lds;
   double* ql = lds + 3 * D.n;
-  double* fl = lds + (kVecLds ? 6 : 3) * D.n;   // [kDenseElems][8][3] corner forces
+  T* arows = reinterpret_cast<T*>(lds + (kVecLds ? 6 : 3) * D.n);
   __shared__ ElemTileT<kDenseElems> Tl;
+  // corner forces [kDenseElems][8][3] share storage with the tile's node
+  // values, which are dead once the stresses are formed
+  double* fl = &Tl.xs[0][0][0];
   __shared__ double ws[kDenseBlock / 64];
   __shared__ double bc;
   __shared__ double ws2[2 * (kDenseBlock / 64)], bc2[2];
   // the workgroup's own rows: r_k, s_k, p, z (owner-private), node data
-  __shared__ double own_r[3 * kDenseMaxRows], own_s[3 * kDenseMaxRows];
+  __shared__ double own_r[3 * kDenseMaxRows], own_s[3 * kDenseMaxRows], own_s0[3 * kDenseMaxRows];
   __shared__ double own_p[3 * kDenseMaxRows], own_z[3 * kDenseMaxRows];
   __shared__ double row_c[kDenseMaxRows], row_k[kDenseMaxRows];
   __shared__ int row_node[kDenseMaxRows], row_inc[kDenseMaxRows][8];
@@ -265,12 +272,15 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   // ---- phase 1 (k = 0): r_0 = rhs on the free rows, p = q = z = 0, s_0 = A^{-1} r_0
   for (int i = tid; i < n; i += kDenseBlock) {
     const int node = D.perm[i];
-    rv[i] = rhs[node];
-    rv[n + i] = rhs[(int64_t)N + node];
-    rv[2 * n + i] = rhs[2 * (int64_t)N + node];
+    rv[i] = rhs_scale * rhs[node];
+    rv[n + i] = rhs_scale * rhs[(int64_t)N + node];
+    rv[2 * n + i] = rhs_scale * rhs[2 * (int64_t)N + node];
   }
   if (kVecLds)
     for (int i = tid; i < 3 * n; i += kDenseBlock) ql[i] = 0.0;
+  if (kAinvLds)
+    for (int i = tid; i < R * n; i += kDenseBlock) arows[i] = ainv[(int64_t)j0 * n + i];
+  const T* my_rows = kAinvLds ? arows : ainv + (int64_t)j0 * n;
   __syncthreads();
   double acc = 0.0;
   if (tid < 3 * R) {
@@ -288,7 +298,8 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   }
   acc = block_sum(acc, ws);
   if (tid == 0) st_dev(&D.part[4 * b + 2], acc);
-  dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s);
+  dense_rows<T>(my_rows, n, rv, j0, R, D.s, own_s);
+  if (tid < 3 * MR) own_s0[tid] = own_s[tid];
   alive = grid_barrier(D.bar, round);
 
   double nb2 = 0.0, rsq = 0.0, rs_old = 0.0, alpha_old = 0.0, alpha = 0.0, beta = 0.0;
@@ -410,6 +421,9 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     const double den = k == 0 ? delta : delta - beta * gamma / alpha_old;
     if (!(den > 0.0) || !isfinite(den) || !isfinite(gamma)) {
       curvature = 1;
+      // the forward Newton step falls back to one plain PD step, A^{-1} rhs = s_0
+      if (pd_fallback && tid < 3 * MR) own_z[tid] = own_s0[tid];
+      __syncthreads();
       break;
     }
     alpha = gamma / den;
@@ -456,7 +470,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     racc = block_sum(racc, ws);
     if (tid == 0) st_dev(&D.part[4 * b + 2], racc);
     __syncthreads();
-    dense_rows<T>(ainv, n, rv, j0, R, D.s, own_s);
+    dense_rows<T>(my_rows, n, rv, j0, R, D.s, own_s);
     if (!(alive = grid_barrier(D.bar, round))) break;
   }
 
@@ -511,23 +525,33 @@ __global__ void __launch_bounds__(kBlock) k_to_fp32(int64_t count, const double*
 
 }  // namespace
 
-size_t cg_dense_lds_bytes(int n, bool vec_lds) {
-  return ((size_t)(vec_lds ? 6 : 3) * n + (size_t)24 * kDenseElems) * sizeof(double);
+size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32) {
+  size_t b = (size_t)((mode & kDenseVecLds) ? 6 : 3) * n * sizeof(double);
+  if (mode & kDenseAinvLds) b += (size_t)rows * n * (fp32 ? sizeof(float) : sizeof(double));
+  return b;
 }
 
 namespace {
-const void* dense_kernel(bool fp32, bool vec_lds) {
-  if (fp32) return vec_lds ? (const void*)k_cg_dense<float, true> : (const void*)k_cg_dense<float, false>;
-  return vec_lds ? (const void*)k_cg_dense<double, true> : (const void*)k_cg_dense<double, false>;
+template <typename T>
+const void* dense_kernel_t(int mode) {
+  switch (mode & 3) {
+    case 0: return (const void*)k_cg_dense<T, false, false>;
+    case kDenseVecLds: return (const void*)k_cg_dense<T, true, false>;
+    case kDenseAinvLds: return (const void*)k_cg_dense<T, false, true>;
+    default: return (const void*)k_cg_dense<T, true, true>;
+  }
+}
+const void* dense_kernel(bool fp32, int mode) {
+  return fp32 ? dense_kernel_t<float>(mode) : dense_kernel_t<double>(mode);
 }
 }  // namespace
 
-int cg_dense_max_blocks(int n, bool vec_lds, bool fp32) {
+int cg_dense_max_blocks(int n, int rows, int mode, bool fp32) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t lds = cg_dense_lds_bytes(n, vec_lds);
-  const void* fn = dense_kernel(fp32, vec_lds);
+  const size_t lds = cg_dense_lds_bytes(n, rows, mode, fp32);
+  const void* fn = dense_kernel(fp32, mode);
   if (lds > 48 * 1024 &&
       hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     (void)hipGetLastError();
@@ -541,25 +565,28 @@ int cg_dense_max_blocks(int n, bool vec_lds, bool fp32) {
 }
 
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
-                           const double* cache, const double* rhs, double* z_out, IterState* st) {
+                           const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
+                           double* z_out, IterState* st) {
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar);
-  const bool vec = D.vec_lds != 0;
-  const size_t lds = cg_dense_lds_bytes(D.n, vec);
+  const int mode = fp32 ? D.mode32 : D.mode64;
+  const size_t lds = cg_dense_lds_bytes(D.n, D.rows, mode, fp32);
   DevMesh m = M;
   DenseCG d = D;
   IterState* stp = st;
   const double* cp = cache;
   const double* rp = rhs;
   double* zp = z_out;
+  double sc = rhs_scale;
+  int pf = pd_fallback;
   if (fp32) {
     const float* a = D.ainv32;
-    void* args[] = {&m, &d, &a, &cp, &rp, &zp, &stp};
-    return hipLaunchCooperativeKernel(dense_kernel(true, vec), dim3(blocks), dim3(kDenseBlock), args,
+    void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp};
+    return hipLaunchCooperativeKernel(dense_kernel(true, mode), dim3(blocks), dim3(kDenseBlock), args,
                                       (unsigned)lds, s);
   }
   const double* a = D.ainv64;
-  void* args[] = {&m, &d, &a, &cp, &rp, &zp, &stp};
-  return hipLaunchCooperativeKernel(dense_kernel(false, vec), dim3(blocks), dim3(kDenseBlock), args,
+  void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp};
+  return hipLaunchCooperativeKernel(dense_kernel(false, mode), dim3(blocks), dim3(kDenseBlock), args,
                                     (unsigned)lds, s);
 }
 

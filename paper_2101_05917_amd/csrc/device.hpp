@@ -67,10 +67,13 @@ constexpr int kDenseBlock = 512;                // threads per workgroup
 constexpr int kDenseElems = kDenseBlock / 8;    // elements evaluated at once, one per 8 lanes
 static_assert(8 * kDenseMaxRows <= kDenseElems, "a workgroup's rows touch at most 8 R elements");
 constexpr int kDenseBarWords = 64 * 9;          // barrier counters (top, abort, 8 groups)
+constexpr int kDenseVecLds = 1;                 // r and q of every row live in each workgroup's LDS
+constexpr int kDenseAinvLds = 2;                // the workgroup's rows of A^{-1} live in its LDS
 struct DenseCG {
   int32_t n, rows;            // free nodes; rows per workgroup R
   int32_t max_elems;          // largest element list of a workgroup
-  int32_t vec_lds;            // 1: r and q of every row live in each workgroup's LDS
+  int32_t mode64, mode32;     // kDenseVecLds | kDenseAinvLds per precision of A^{-1}
+  int32_t pad;
   const int32_t* perm;        // [n] internal row -> public node
   const int32_t* inv;         // [N] public node -> internal row, -1 when fixed
   const double* ainv64;       // [n][n] A^{-1} (symmetric; row j = column j)
@@ -158,10 +161,11 @@ void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const
                         const double* cache, double* g_youngs, double* g_act);
 constexpr int kAdjCacheRows = 19;
 // fused dense solver (cg_dense.hip)
-size_t cg_dense_lds_bytes(int n, bool vec_lds);
-int cg_dense_max_blocks(int n, bool vec_lds, bool fp32);
+size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32);
+int cg_dense_max_blocks(int n, int rows, int mode, bool fp32);
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
-                           const double* cache, const double* rhs, double* z_out, IterState* st);
+                           const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
+                           double* z_out, IterState* st);
 void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, double* b);
 void launch_collect_rows(hipStream_t s, int N, int n, const int32_t* perm, int j0, const double* x,
                          double* ainv);

@@ -295,3 +295,30 @@ def test_fused_dense_cg_iteration_cap(name):
     assert r1[3]["bwd_iters"] == 3 and r0[3]["bwd_iters"] == 3
     assert r1[3]["converged"] == 0 and r0[3]["converged"] == 0
     assert rel(soa(r1[0]), soa(r0[0])) <= 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_dense_cg_lds_placements_agree_bitwise(precision):
+    """Where the vectors and the rows of A^{-1} are read from (LDS or device
+    memory) does not change the arithmetic: all four placements give the
+    same bits."""
+    sc = SCENES["robot"]()
+    kw = dict(precision=precision, fwd_solver="newton_pcg", fwd_rel_tol=1e-10, bwd_rel_tol=1e-10,
+              fwd_max_iter=100000, bwd_max_iter=100000)
+    o = None
+    out = []
+    for mode in range(4):
+        g, o = pair(sc, fused_cg=2 + mode, **kw)
+        lds = g.info["fused_lds"] >> (2 if precision == "mixed" else 0) & 3
+        print(mode, g.info["fused_blocks"], lds, flush=True)
+        assert g.info["fused_blocks"] > 0 and lds == mode
+        x, v = _perturbed(o, seed=51)
+        act = elem_dev(np.random.default_rng(52).uniform(0, 1, o.E))
+        xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+        xn, _, st = g.forward_step(xd, vd, act)
+        gxn = to_dev(np.random.default_rng(53).standard_normal(3 * o.N), o.N)
+        gx, gv, _, bst = g.backward_step(xd, vd, act, xn, gxn, torch.zeros_like(gxn))
+        out.append((xn, gx, st["fwd_iters"], bst["bwd_iters"]))
+    for xn, gx, fi, bi in out[1:]:
+        assert torch.equal(xn, out[0][0]) and torch.equal(gx, out[0][1])
+        assert fi == out[0][2] and bi == out[0][3]
