@@ -113,6 +113,16 @@ def rollout(mesh, X, c_dev, T, torch, acts=None, checkpoint_every=1):
     return xT, gx, gv, gE, g_act, fwd_iters, bwd_iters
 
 
+def progress(msg: str):
+    """A progress line on stderr (the JSON result stays the last stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+# the oracle's explicit 9Q x 3N operators make its set-up alone take minutes
+# beyond this size, so the CPU baseline is taken on the smaller workloads only
+CPU_BASELINE_MAX_DOFS = 20000
+
+
 def cpu_baseline(scene, T_budget_s):
     """The oracle on the host: Newton (sparse LU) forward + direct adjoint, a
     prefix of the rollout bounded to about ``T_budget_s`` seconds."""
@@ -248,6 +258,7 @@ def main():
 
     scene = W.config(args.config)
     T = args.rollout_steps or scene.steps
+    progress(f"{scene.name}: mesh set-up and factorization")
     mesh = Mesh.from_scene(scene, fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol,
                            fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
                            bwd_max_iter=200000, precision=args.precision, check_every=16)
@@ -266,14 +277,17 @@ def main():
         a = W.actuation_sequence(T, mesh.n_elements, seed=scene.act_seed)
         acts = torch.from_numpy(np.ascontiguousarray(a)).to(X.device)
     K = args.checkpoint_every if args.checkpoint_every else (20 if args.config == "c3" else 1)
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
+        progress(f"warm-up rollout {w + 1}/{args.warmup} ({T} steps)")
         rollout(mesh, X, c_dev, T, torch, acts, K)
     torch.cuda.synchronize()
     mesh.profile_start(args.roofline_kernel)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        progress(f"timed rollout {k + 1}/{args.steps}")
         xT, gx, gv, gE, g_act, fi, bi = rollout(mesh, X, c_dev, T, torch, acts, K)
     torch.cuda.synchronize()
+    progress("timed region done")
     dt = (time.perf_counter() - t0) / args.steps
     prof = mesh.profile_read()
     value = 3 * N * T / dt
@@ -334,7 +348,13 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
+        if 3 * N <= CPU_BASELINE_MAX_DOFS:
+            progress("cpu baseline (oracle on the host)")
+            out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
+        else:
+            out["cpu_baseline"] = {"value": None, "kind": "oracle",
+                                   "sample": f"not taken: {3 * N} DoFs exceed the oracle's practical "
+                                             f"size ({CPU_BASELINE_MAX_DOFS})"}
     print(json.dumps(out), flush=True)
 
 

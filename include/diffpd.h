@@ -52,7 +52,11 @@ typedef enum {
   DPD_ECURVATURE = -7      /* adjoint CG met non-positive curvature and no fallback    */
 } dpd_status;
 
-/* Precision of the iteration (fwd/bwd local steps and triangular sweeps).   */
+/* Precision of the iteration.  DPD_MIXED: FP32 triangular sweeps (and dense
+ * A^{-1}) applied to FP64 residuals in correction form, and FP32 closest
+ * rotations in the local steps, each polished by one FP64 Newton step of the
+ * polar decomposition; factorization, residuals, corrections and reductions
+ * stay FP64 (spec precision growth; the fixed point is unchanged).    */
 enum { DPD_FP64 = 0, DPD_MIXED = 1 };
 /* Adjoint solver.                                                          */
 enum { DPD_BWD_FIXED_POINT = 0, DPD_BWD_PCG = 1 };

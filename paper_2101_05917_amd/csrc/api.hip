@@ -288,6 +288,7 @@ void fill_devmesh(dpd_mesh* m) {
   d.N = (int32_t)m->hm.n_nodes;
   d.E = (int32_t)m->hm.n_elems;
   d.nf = (int32_t)m->hm.n_free;
+  d.local32 = o.precision == DPD_MIXED ? 1 : 0;
   d.h = o.h;
   d.dx = o.dx;
   d.nu = o.nu;
@@ -761,6 +762,7 @@ dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
   const bool need32 = o->precision == DPD_MIXED && !m->have_fp32;
   m->opt = *o;
   if (m->opt.check_every < 1) m->opt.check_every = 1;
+  m->dm.local32 = m->opt.precision == DPD_MIXED ? 1 : 0;
   if (need32 && m->factored) {
     std::vector<double> tmp(m->S.panel_size);
     HIPCHECK(m, hipMemcpy(tmp.data(), m->panel64, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));

@@ -41,6 +41,7 @@ struct DevSolve {
 
 struct DevMesh {
   int32_t N, E, nf;
+  int32_t local32;            // 1: FP32 closest rotations polished in FP64 (mixed precision)
   double h, dx, nu, Vq;
   double g[3];
   double contact_k, friction_mu, friction_eps;

@@ -80,33 +80,49 @@ __device__ inline GradTable grad_table(double dx) {
 // Closest rotation to F (row-major 3x3), i.e. argmax over SO(3) of tr(R^T F).
 // With R = R(quat) this is the largest-eigenvalue eigenvector of a symmetric
 // 4x4 matrix (Davenport's q-method); the eigenproblem is solved by cyclic
-// Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition).
-__device__ inline void jrot(double (&B)[4][4], double (&V)[4][4], int p, int q) {
-  const double apq = B[p][q];
-  if (fabs(apq) <= 1e-300) return;
-  const double tau = (B[q][q] - B[p][p]) / (2.0 * apq);
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+// Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition).  T is
+// the arithmetic type (FP64; FP32 for the mixed-precision local step, which
+// then polishes the result in FP64).
+template <typename T>
+struct JacobiEps;
+template <>
+struct JacobiEps<double> {
+  static constexpr double tiny = 1e-300, off = 1e-34;
+};
+template <>
+struct JacobiEps<float> {
+  static constexpr float tiny = 1e-30f, off = 1e-14f;
+};
+
+template <typename T>
+__device__ inline void jrot(T (&B)[4][4], T (&V)[4][4], int p, int q) {
+  const T apq = B[p][q];
+  if (fabs(apq) <= JacobiEps<T>::tiny) return;
+  const T tau = (B[q][q] - B[p][p]) / (T(2) * apq);
+  const T t = (tau >= T(0) ? T(1) : T(-1)) / (fabs(tau) + sqrt(T(1) + tau * tau));
+  const T c = T(1) / sqrt(T(1) + t * t), s = t * c;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k == p || k == q) continue;
-    const double bkp = B[k][p], bkq = B[k][q];
+    const T bkp = B[k][p], bkq = B[k][q];
     B[k][p] = B[p][k] = c * bkp - s * bkq;
     B[k][q] = B[q][k] = s * bkp + c * bkq;
   }
   B[p][p] -= t * apq;
   B[q][q] += t * apq;
-  B[p][q] = B[q][p] = 0.0;
+  B[p][q] = B[q][p] = T(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const double vkp = V[k][p], vkq = V[k][q];
+    const T vkp = V[k][p], vkq = V[k][q];
     V[k][p] = c * vkp - s * vkq;
     V[k][q] = s * vkp + c * vkq;
   }
 }
 
-__device__ inline void closest_rotation(const double F[9], double R[9]) {
-  double B[4][4], V[4][4];
+// Unit-norm-free quaternion (w, x, y, z) of the closest rotation.
+template <typename T>
+__device__ inline void closest_quat_t(const T F[9], T qt[4]) {
+  T B[4][4], V[4][4];
   B[0][0] = F[0] + F[4] + F[8];
   B[1][1] = F[0] - F[4] - F[8];
   B[2][2] = -F[0] + F[4] - F[8];
@@ -120,16 +136,16 @@ __device__ inline void closest_rotation(const double F[9], double R[9]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
-  double nrm = 0.0;
+    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? T(1) : T(0);
+  T nrm = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) nrm += B[i][j] * B[i][j];
   for (int sweep = 0; sweep < 10; ++sweep) {
-    const double off = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[0][3] * B[0][3] +
-                       B[1][2] * B[1][2] + B[1][3] * B[1][3] + B[2][3] * B[2][3];
-    if (off <= 1e-34 * nrm) break;
+    const T off = B[0][1] * B[0][1] + B[0][2] * B[0][2] + B[0][3] * B[0][3] +
+                  B[1][2] * B[1][2] + B[1][3] * B[1][3] + B[2][3] * B[2][3];
+    if (off <= JacobiEps<T>::off * nrm) break;
     jrot(B, V, 0, 1);
     jrot(B, V, 0, 2);
     jrot(B, V, 0, 3);
@@ -138,22 +154,28 @@ __device__ inline void closest_rotation(const double F[9], double R[9]) {
     jrot(B, V, 2, 3);
   }
   int k = 0;
-  double best = B[0][0];
+  T best = B[0][0];
 #pragma unroll
   for (int i = 1; i < 4; ++i)
     if (B[i][i] > best) {
       best = B[i][i];
       k = i;
     }
-  double w = 1.0, x = 0.0, y = 0.0, z = 0.0;
+  qt[0] = T(1);
+  qt[1] = qt[2] = qt[3] = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
     if (i == k) {
-      w = V[0][i];
-      x = V[1][i];
-      y = V[2][i];
-      z = V[3][i];
+      qt[0] = V[0][i];
+      qt[1] = V[1][i];
+      qt[2] = V[2][i];
+      qt[3] = V[3][i];
     }
+}
+
+// Rotation of a (not necessarily normalised) quaternion, in FP64: orthogonal
+// to FP64 round-off whatever the precision the quaternion was found in.
+__device__ inline void quat_rotation(double w, double x, double y, double z, double R[9]) {
   const double s = 2.0 / (w * w + x * x + y * y + z * z);
   R[0] = 1.0 - s * (y * y + z * z);
   R[1] = s * (x * y - w * z);
@@ -164,6 +186,12 @@ __device__ inline void closest_rotation(const double F[9], double R[9]) {
   R[6] = s * (x * z - w * y);
   R[7] = s * (y * z + w * x);
   R[8] = 1.0 - s * (x * x + y * y);
+}
+
+__device__ inline void closest_rotation(const double F[9], double R[9]) {
+  double qt[4];
+  closest_quat_t<double>(F, qt);
+  quat_rotation(qt[0], qt[1], qt[2], qt[3], R);
 }
 
 __device__ inline double det3(const double F[9]) {
@@ -203,6 +231,57 @@ __device__ inline bool rotation_kinv(const double F[9], const double R[9], doubl
   Ki[4] = cxz * id;
   Ki[5] = cyz * id;
   return true;
+}
+
+// Mixed-precision local step: the closest rotation's quaternion from the FP32
+// q-method, turned into an FP64 rotation, then one FP64 Newton step of the
+// polar decomposition.  With S = R0^T F,
+// K = tr(sym S) I - sym S and a = axial(S - S^T), the correction is
+// R = R0 exp([K^{-1} a]_x) (Rodrigues), the same linearisation of F = R S as
+// dR/dF; from an FP32-accurate R0 it leaves an error of order eps32^2.  When K
+// is singular the FP32 rotation is kept.
+__device__ inline void closest_rotation_mixed(const double F[9], double R[9]) {
+  float Ff[9], qf[4];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Ff[i] = (float)F[i];
+  closest_quat_t<float>(Ff, qf);
+  // R0 formed in FP64 from the FP32 quaternion: orthogonal to FP64 round-off,
+  // so the Newton step below only has to correct its direction
+  double R0[9], Ki[6], S[9];
+  quat_rotation(qf[0], qf[1], qf[2], qf[3], R0);
+  if (!rotation_kinv(F, R0, Ki)) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = R0[i];
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = R0[i] * F[j] + R0[3 + i] * F[3 + j] + R0[6 + i] * F[6 + j];
+  const double a0 = S[7] - S[5], a1 = S[2] - S[6], a2 = S[3] - S[1];
+  const double w0 = Ki[0] * a0 + Ki[3] * a1 + Ki[4] * a2;
+  const double w1 = Ki[3] * a0 + Ki[1] * a1 + Ki[5] * a2;
+  const double w2 = Ki[4] * a0 + Ki[5] * a1 + Ki[2] * a2;
+  const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+  double c1, c2;  // sin(t)/t and (1 - cos(t))/t^2
+  if (th2 < 1e-4) {
+    c1 = 1.0 - th2 / 6.0 * (1.0 - th2 / 20.0);
+    c2 = 0.5 - th2 / 24.0 * (1.0 - th2 / 30.0);
+  } else {
+    const double t = sqrt(th2);
+    c1 = sin(t) / t;
+    c2 = (1.0 - cos(t)) / th2;
+  }
+  // E = I + c1 [w]_x + c2 [w]_x^2
+  const double E[9] = {1.0 - c2 * (w1 * w1 + w2 * w2), -c1 * w2 + c2 * w0 * w1, c1 * w1 + c2 * w0 * w2,
+                       c1 * w2 + c2 * w0 * w1, 1.0 - c2 * (w0 * w0 + w2 * w2), -c1 * w0 + c2 * w1 * w2,
+                       -c1 * w1 + c2 * w0 * w2, c1 * w0 + c2 * w1 * w2, 1.0 - c2 * (w0 * w0 + w1 * w1)};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      R[3 * i + j] = R0[3 * i] * E[j] + R0[3 * i + 1] * E[3 + j] + R0[3 * i + 2] * E[6 + j];
 }
 
 __device__ inline void rotation_apply_diff(const double R[9], const double Ki[6], const double dF[9],

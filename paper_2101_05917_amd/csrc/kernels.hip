@@ -44,7 +44,10 @@ __global__ void __launch_bounds__(kBlock) k_elem_forces(DevMesh M, const double*
   if (valid) {
     double F[9], R[9];
     deformation_gradient(T, le, q, G, F);
-    closest_rotation(F, R);
+    if (M.local32)
+      closest_rotation_mixed(F, R);
+    else
+      closest_rotation(F, R);
     if (st && det3(F) <= 0.0) atomicAdd(&st->inverted, 1);
     const double w = M.w_e[e];
     double* P = T.Ps[le][q];
@@ -221,7 +224,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
   if (!valid) return;
   double F[9], R[9], Ki[6];
   deformation_gradient(T, le, q, G, F);
-  closest_rotation(F, R);
+  if (M.local32)
+    closest_rotation_mixed(F, R);
+  else
+    closest_rotation(F, R);
   const bool ok = rotation_kinv(F, R, Ki);
   if (st && (!ok || det3(F) <= 0.0)) atomicAdd(&st->inverted, 1);
   const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;

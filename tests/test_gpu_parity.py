@@ -322,3 +322,17 @@ def test_fused_dense_cg_lds_placements_agree_bitwise(precision):
     for xn, gx, fi, bi in out[1:]:
         assert torch.equal(xn, out[0][0]) and torch.equal(gx, out[0][1])
         assert fi == out[0][2] and bi == out[0][3]
+
+
+@pytest.mark.parametrize("name", ["c1", "robot"])
+def test_mixed_local_step_rotations(name):
+    """Mixed precision: FP32 q-method rotations polished by one FP64 Newton step
+    agree with the oracle's SVD polar decomposition to FP64 round-off."""
+    sc = SCENES[name]()
+    g, o = pair(sc, precision="mixed")
+    x, _ = _perturbed(o, scale=3e-3, seed=61)
+    R = g.rotations(to_dev(x, o.N)).cpu().numpy()          # [9, Q]
+    Rref = op.closest_rotation(o.deformation_gradients(x)).reshape(o.Q, 9).T
+    err = np.abs(R - Rref).max()
+    print(name, err, flush=True)
+    assert err <= 1e-12
