@@ -199,11 +199,22 @@ def serve_bench(args):
     }
 
 
-def kernel_source_hash() -> str:
+# device sources that determine each timed kernel's code
+KERNEL_SOURCES = {
+    "cg_dense": ["cg_dense.hip", "device_math.hpp", "device.hpp"],
+    "elem_hvp": ["kernels.hip", "device_math.hpp", "device.hpp"],
+    "elem_forces": ["kernels.hip", "device_math.hpp", "device.hpp"],
+}
+SWEEP_SOURCES = ["sweeps.hip", "device.hpp", "internal.hpp"]
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """sha256 prefix of the sources a kernel is built from (a changed kernel
+    invalidates its recorded counters)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2101_05917_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES.get(kernel, SWEEP_SOURCES):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -219,7 +230,7 @@ def measured_traffic(workload: str, kernel: str, precision: str, iters_per_launc
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload, {}).get(f"{kernel}/{precision}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     per = rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
     return per * iters_per_launch if rec.get("per") == "iteration" else per
@@ -303,6 +314,10 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_per_launch}
     if prof["iterations"]:
         roofline["iterations_per_launch"] = prof["iterations"] / max(1, prof["launches"])
+    if args.roofline_kernel == "cg_dense":
+        roofline["timing"] = ("device clock (s_memrealtime, 100 MHz) at the launch's entry and exit; "
+                              "HIP-event bracket on the same launches: "
+                              f"{prof['event_ms'] / max(1, prof['launches']) * 1e3:.1f} us")
 
     # accuracy against the oracle's reference gradient
     err = None

@@ -243,11 +243,17 @@ enum {
 };
 typedef struct {
   int64_t launches;
-  double total_ms;         /* summed event-measured durations                    */
+  double total_ms;         /* summed durations: event pairs on the launch stream;
+                              for DPD_PROF_CG_DENSE the launch's own device clock
+                              (workgroup 0 at entry and at exit), because the
+                              events around a cooperative launch also bracket the
+                              host's enqueue time                              */
   double bytes;            /* summed algorithmic bytes                           */
   double flops;            /* summed algorithmic floating-point operations       */
   int64_t iterations;      /* device-side iterations of the timed launches (class
                               DPD_PROF_CG_DENSE), else 0                         */
+  double event_ms;         /* summed event-pair durations (= total_ms except for
+                              DPD_PROF_CG_DENSE)                                 */
 } dpd_kernel_profile;
 dpd_status dpd_profile_start(dpd_mesh* mesh, int32_t kernel_class);
 dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* out);

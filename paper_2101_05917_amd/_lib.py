@@ -56,7 +56,7 @@ class MeshInfo(C.Structure):
 
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
-                ("flops", C.c_double), ("iterations", C.c_int64)]
+                ("flops", C.c_double), ("iterations", C.c_int64), ("event_ms", C.c_double)]
 
 
 class Request(C.Structure):

@@ -41,6 +41,9 @@ struct TimedLaunch {
   // multiplied at harvest by the iteration count of state iter_state
   int iter_state = -1;
   double iter_bytes = 0.0, iter_flops = 0.0;
+  // the duration is read from the launch's own device clock stamps in state
+  // iter_state (entry and exit of workgroup 0) instead of the event pair
+  bool device_clock = false;
 };
 
 struct dpd_mesh {
@@ -87,7 +90,8 @@ struct dpd_mesh {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   std::vector<TimedLaunch> ev_pending;
   int64_t prof_launches = 0, prof_seen = 0, prof_iters = 0;
-  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
+  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0, prof_event_ms = 0.0;
+  double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
 };
 
 namespace {
@@ -211,7 +215,13 @@ void prof_harvest(dpd_mesh* m) {
     }
     if (live) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, t.ev.first, t.ev.second) == hipSuccess) m->prof_ms += ms;
+      if (hipEventElapsedTime(&ms, t.ev.first, t.ev.second) == hipSuccess) m->prof_event_ms += ms;
+      if (t.device_clock) {
+        const IterState& h = m->h_st[t.iter_state];
+        m->prof_ms += (double)(h.clk1 - h.clk0) / m->clock_khz;
+      } else {
+        m->prof_ms += ms;
+      }
       m->prof_launches += 1;
       m->prof_bytes += t.bytes;
       m->prof_flops += t.flops;
@@ -1027,6 +1037,7 @@ dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const doubl
     const double n = (double)m->hm.n_free;
     ProfScope ps(m, s, DPD_PROF_CG_DENSE, dense_matvec_bytes(m, fp32), 6.0 * n * n);
     if (ps.on) {
+      ps.t.device_clock = true;
       ps.t.iter_state = st_idx;
       ps.t.iter_bytes = dense_iter_bytes(m, fp32);
       ps.t.iter_flops = 6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems;
@@ -1192,11 +1203,15 @@ dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
   if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CG_DENSE)
     return fail(m, DPD_EINVAL, "unknown kernel class");
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    m->clock_khz = khz;
   m->prof_class = kernel_class;
   m->prof_launches = 0;
   m->prof_seen = 0;
   m->prof_iters = 0;
-  m->prof_ms = m->prof_bytes = m->prof_flops = 0.0;
+  m->prof_ms = m->prof_bytes = m->prof_flops = m->prof_event_ms = 0.0;
   return DPD_OK;
 }
 
@@ -1206,6 +1221,7 @@ dpd_status dpd_profile_read(dpd_mesh* m, void* stream, dpd_kernel_profile* out) 
   prof_harvest(m);
   out->launches = m->prof_launches;
   out->iterations = m->prof_iters;
+  out->event_ms = m->prof_event_ms;
   out->total_ms = m->prof_ms;
   out->bytes = m->prof_bytes;
   out->flops = m->prof_flops;

@@ -181,6 +181,27 @@ __device__ __forceinline__ void dense_rows(const T* __restrict__ rows, int n, co
   __syncthreads();
 }
 
+// Two sums over the workgroup in one pass, valid in lane 0 only.
+__device__ inline void block_sum2(double& a, double& b, double* ws2) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    ws2[2 * wid] = a;
+    ws2[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      ta += ws2[2 * w];
+      tb += ws2[2 * w + 1];
+    }
+    a = ta;
+    b = tb;
+  }
+}
+
 // Two sums over the workgroup in one pass, returned to every lane.
 __device__ inline void block_all2(double& a, double& b, double* ws2, double* bc2) {
   a = wave_sum(a);
@@ -242,6 +263,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   const double tolsq = st->tolsq;
   const int max_iter = st->max_iter;
   const GradTable G = grad_table(M.dx);
+  const uint64_t clk0 = wall_clock64();
   uint32_t round = 0;
   bool alive = true;
   if (tid < 8 * 8 * 3) {
@@ -387,7 +409,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       gam = own_r[tid] * s0 + own_r[MR + tid] * s1 + own_r[2 * MR + tid] * s2;
       del = o0 * s0 + o1 * s1 + o2 * s2;
     }
-    block_all2(gam, del, ws2, bc2);
+    block_sum2(gam, del, ws2);   // totals in lane 0 only
     if (tid == 0) {
       st_dev(&D.part[4 * b + 0], gam);
       st_dev(&D.part[4 * b + 1], del);
@@ -451,7 +473,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
           const double ri = rr[u] - alpha * qi;
           rv[i] = ri;
           if (kVecLds) ql[i] = qi;
-          const int c = i / n, j = i - c * n;
+          const int c = (i >= n) + (i >= 2 * n), j = i - c * n;
           if (j >= j0 && j < j1) {
             const int o = c * MR + (j - j0);
             if (!kVecLds) {
@@ -490,6 +512,8 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     st->nonfinite = nonfinite;
     st->curvature = curvature;
     st->aborted = (!alive || __hip_atomic_load(&D.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ? 1 : 0;
+    st->clk0 = clk0;
+    st->clk1 = wall_clock64();
     st->done = 1;
   }
 }

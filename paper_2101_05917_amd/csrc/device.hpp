@@ -21,6 +21,7 @@ struct IterState {
   uint32_t counter;                  // last-block-done ticket
   int32_t max_iter;                  // iteration cap of the conjugate-gradient loop
   int32_t aborted;                   // the fused solver's grid barrier timed out
+  uint64_t clk0, clk1;               // fused solver: constant-rate device clock at entry and exit
 };
 
 struct DevSolve {
