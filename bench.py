@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--bwd-solver", default="pcg", choices=["pcg", "fixed_point"])
     ap.add_argument("--fwd-tol", type=float, default=1e-7)
     ap.add_argument("--bwd-tol", type=float, default=1e-7)
+    ap.add_argument("--fwd-inner-tol", type=float, default=1e-2,
+                    help="relative tolerance of each Newton step's conjugate-gradient solve")
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -271,6 +273,7 @@ def main():
     T = args.rollout_steps or scene.steps
     progress(f"{scene.name}: mesh set-up and factorization")
     mesh = Mesh.from_scene(scene, fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol,
+                           fwd_inner_tol=args.fwd_inner_tol,
                            fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
                            bwd_max_iter=200000, precision=args.precision, check_every=16)
     if args.roofline_kernel is None:
@@ -355,6 +358,7 @@ def main():
                                f"{T} steps fwd+adjoint, loss dot(N(0,1) seed 0, x_T)",
                    "fwd_solver": args.fwd_solver, "bwd_solver": args.bwd_solver,
                    "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol,
+                   "fwd_inner_tol": args.fwd_inner_tol,
                    "precision": args.precision, "fused_cg_workgroups": mesh.info["fused_blocks"]},
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,

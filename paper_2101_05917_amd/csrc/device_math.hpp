@@ -188,7 +188,46 @@ __device__ inline void quat_rotation(double w, double x, double y, double z, dou
   R[8] = 1.0 - s * (x * x + y * y);
 }
 
+// Orthogonal polar factor by Newton's iteration X <- (g X + X^{-T} / g) / 2
+// (Higham 1986, "Computing the polar decomposition -- with applications"),
+// with determinant scaling g = |det X|^{-1/3} while the steps are large.  For
+// det F > 0 the factor is the closest proper rotation; the iteration converges
+// quadratically, so it stops once a step is below sqrt(eps) and takes that
+// iterate.  Returns false (caller falls back to the q-method) when det X <= 0
+// or it has not converged within the cap.  With warm = true the iteration
+// starts from the X given (an approximate polar factor of F, e.g. from a
+// lower precision) instead of from F.
+template <typename T>
+__device__ inline bool polar_newton(const T F[9], T X[9], bool warm = false) {
+  const T stop = sizeof(T) == 8 ? T(1e-18) : T(1e-10);   // squared step norm
+  if (!warm) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) X[i] = F[i];
+  }
+  for (int it = 0; it < 12; ++it) {
+    // cofactors: X^{-T} = C / det X
+    const T c0 = X[4] * X[8] - X[5] * X[7], c1 = X[5] * X[6] - X[3] * X[8], c2 = X[3] * X[7] - X[4] * X[6];
+    const T c3 = X[2] * X[7] - X[1] * X[8], c4 = X[0] * X[8] - X[2] * X[6], c5 = X[1] * X[6] - X[0] * X[7];
+    const T c6 = X[1] * X[5] - X[2] * X[4], c7 = X[2] * X[3] - X[0] * X[5], c8 = X[0] * X[4] - X[1] * X[3];
+    const T det = X[0] * c0 + X[1] * c1 + X[2] * c2;
+    if (!(det > T(0))) return false;
+    const T g = it < 2 && !warm ? T(1) / cbrt(det) : T(1);
+    const T a = T(0.5) * g, b = T(0.5) / (g * det);
+    const T C[9] = {c0, c1, c2, c3, c4, c5, c6, c7, c8};
+    T d2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const T xn = a * X[i] + b * C[i];
+      d2 += (xn - X[i]) * (xn - X[i]);
+      X[i] = xn;
+    }
+    if (d2 <= stop) return true;
+  }
+  return false;
+}
+
 __device__ inline void closest_rotation(const double F[9], double R[9]) {
+  if (polar_newton<double>(F, R)) return;
   double qt[4];
   closest_quat_t<double>(F, qt);
   quat_rotation(qt[0], qt[1], qt[2], qt[3], R);
@@ -233,22 +272,13 @@ __device__ inline bool rotation_kinv(const double F[9], const double R[9], doubl
   return true;
 }
 
-// Mixed-precision local step: the closest rotation's quaternion from the FP32
-// q-method, turned into an FP64 rotation, then one FP64 Newton step of the
-// polar decomposition.  With S = R0^T F,
-// K = tr(sym S) I - sym S and a = axial(S - S^T), the correction is
-// R = R0 exp([K^{-1} a]_x) (Rodrigues), the same linearisation of F = R S as
-// dR/dF; from an FP32-accurate R0 it leaves an error of order eps32^2.  When K
-// is singular the FP32 rotation is kept.
-__device__ inline void closest_rotation_mixed(const double F[9], double R[9]) {
-  float Ff[9], qf[4];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Ff[i] = (float)F[i];
-  closest_quat_t<float>(Ff, qf);
-  // R0 formed in FP64 from the FP32 quaternion: orthogonal to FP64 round-off,
-  // so the Newton step below only has to correct its direction
-  double R0[9], Ki[6], S[9];
-  quat_rotation(qf[0], qf[1], qf[2], qf[3], R0);
+// One FP64 Newton step of the polar decomposition of F from an orthogonal
+// approximation R0: with S = R0^T F, K = tr(sym S) I - sym S and
+// a = axial(S - S^T), R = R0 exp([K^{-1} a]_x) (Rodrigues), the same
+// linearisation of F = R S as dR/dF.  From an FP32-accurate R0 it leaves an
+// error of order eps32^2.  When K is singular R0 is kept.
+__device__ inline void polish_rotation(const double F[9], const double R0[9], double R[9]) {
+  double Ki[6], S[9];
   if (!rotation_kinv(F, R0, Ki)) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) R[i] = R0[i];
@@ -282,6 +312,31 @@ __device__ inline void closest_rotation_mixed(const double F[9], double R[9]) {
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       R[3 * i + j] = R0[3 * i] * E[j] + R0[3 * i + 1] * E[3 + j] + R0[3 * i + 2] * E[6 + j];
+}
+
+// Mixed-precision local step: an FP32 rotation (the Newton polar factor, or
+// where that iteration does not apply, det F <= 0, the q-method's
+// quaternion), made orthogonal in FP64 (Newton steps on the FP32 factor
+// itself; the quaternion's rotation formed in FP64), then one FP64 polishing
+// step towards the polar factor of F.
+__device__ inline void closest_rotation_mixed(const double F[9], double R[9]) {
+  float Ff[9], Xf[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Ff[i] = (float)F[i];
+  double R0[9];
+  bool have = false;
+  if (polar_newton<float>(Ff, Xf)) {
+    double Xd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Xd[i] = R0[i] = (double)Xf[i];
+    have = polar_newton<double>(Xd, R0, true);   // orthogonal polar factor of the FP32 iterate
+  }
+  if (!have) {
+    float qf[4];
+    closest_quat_t<float>(Ff, qf);
+    quat_rotation(qf[0], qf[1], qf[2], qf[3], R0);
+  }
+  polish_rotation(F, R0, R);
 }
 
 __device__ inline void rotation_apply_diff(const double R[9], const double Ki[6], const double dF[9],
