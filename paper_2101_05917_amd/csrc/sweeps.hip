@@ -142,8 +142,11 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
   store_fwd_row(S, t, r, a0, a1, a2);
 }
 
-// Forward task, wide blocks: wave per panel row on the row-major copy.
-template <typename T>
+// Forward task, wide blocks: LPR lanes per panel row on the row-major copy
+// (64 / LPR rows per wave), each lane walking the row's columns with stride
+// LPR, then a reduction over the row's LPR lanes.  LPR is chosen per level so
+// that every lane reads at least about eight entries of its row.
+template <typename T, int LPR>
 __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
                                      const double* __restrict__ b, int N, bool pre, bool active, int tid,
                                      double* bs) {
@@ -151,39 +154,48 @@ __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, cons
   if (active) stage_rhs(S, t, b, N, pre, tid, bs);
   __syncthreads();
   if (!active) return;
+  constexpr int RPW = 64 / LPR;
   const int nc = t.ncols;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63, wid = tid >> 6, sub = lane / LPR, li = lane % LPR;
   const T* Pb = panelT + t.panel_off;
-  for (int rr = wid; rr < t.count; rr += kGroup / 64) {
+  for (int base = wid * RPW; base < t.count; base += (kGroup / 64) * RPW) {
+    const int rr = base + sub;
+    const bool act = rr < t.count;
     const int r = t.first + rr;
-    const T* row = Pb + (int64_t)r * nc;
-    const int cend = r < nc ? r + 1 : nc;
+    const T* row = Pb + (int64_t)(act ? r : 0) * nc;
+    const int cend = !act ? 0 : (r < nc ? r + 1 : nc);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    int c = lane;
-    for (; c + 192 < cend; c += 256) {
-      const double p0 = (double)row[c], p1 = (double)row[c + 64];
-      const double p2 = (double)row[c + 128], p3 = (double)row[c + 192];
-      a0 += p0 * bs[c] + p1 * bs[c + 64] + p2 * bs[c + 128] + p3 * bs[c + 192];
-      a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 64] + p2 * bs[nc + c + 128] + p3 * bs[nc + c + 192];
-      a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 64] + p2 * bs[2 * nc + c + 128] +
-            p3 * bs[2 * nc + c + 192];
+    int c = li;
+    for (; c + 3 * LPR < cend; c += 4 * LPR) {
+      const double p0 = (double)row[c], p1 = (double)row[c + LPR];
+      const double p2 = (double)row[c + 2 * LPR], p3 = (double)row[c + 3 * LPR];
+      a0 += p0 * bs[c] + p1 * bs[c + LPR] + p2 * bs[c + 2 * LPR] + p3 * bs[c + 3 * LPR];
+      a1 += p0 * bs[nc + c] + p1 * bs[nc + c + LPR] + p2 * bs[nc + c + 2 * LPR] + p3 * bs[nc + c + 3 * LPR];
+      a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + LPR] + p2 * bs[2 * nc + c + 2 * LPR] +
+            p3 * bs[2 * nc + c + 3 * LPR];
     }
-    for (; c < cend; c += 64) {
+    for (; c < cend; c += LPR) {
       const double p = (double)row[c];
       a0 += p * bs[c];
       a1 += p * bs[nc + c];
       a2 += p * bs[2 * nc + c];
     }
-    a0 = wsum(a0);
-    a1 = wsum(a1);
-    a2 = wsum(a2);
-    if (lane == 0) store_fwd_row(S, t, r, a0, a1, a2);
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
+    }
+    if (act && li == 0) store_fwd_row(S, t, r, a0, a1, a2);
   }
 }
 
-// Backward task: each wave owns up to four adjacent columns and walks their
-// rows (column-major panel); v from LDS (kLds) or from global memory.
-template <typename T, bool kLds>
+// Backward task: LPR lanes per panel column (64 / LPR columns per wave), each
+// lane walking the column's rows from the diagonal down with stride LPR
+// (column-major panel, contiguous), then a reduction over the column's lanes;
+// v from LDS (kLds) or from global memory.  LPR is chosen per level so that
+// every lane reads at least about eight entries of its column.
+template <typename T, bool kLds, int LPR>
 __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                      double* __restrict__ out, int N, double alpha, int accumulate,
                                      bool active, int tid, double* vs) {
@@ -191,51 +203,58 @@ __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, cons
   if (kLds && active) stage_solution(S, t, tid, vs);
   __syncthreads();
   if (!active) return;
+  constexpr int CPW = 64 / LPR;
   const int nc = t.ncols, ld = t.ncols + t.nrows;
   const int64_t nf = S.nf;
   const int* rows = S.rows + t.rows_off;
-  const int lane = tid & 63, wid = tid >> 6, nw = kGroup / 64;
-  const int cpw = (t.count + nw - 1) / nw;
-  const int cw = t.first + wid * cpw;
-  const int nown = min(cpw, t.first + t.count - cw);
-  if (nown <= 0) return;
-  const T* Pb = panel + t.panel_off + (int64_t)cw * ld;
-  double acc[4][3];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-  for (int r = cw + lane; r < ld; r += 64) {
-    double v0, v1, v2;
-    if (kLds) {
-      v0 = vs[r];
-      v1 = vs[ld + r];
-      v2 = vs[2 * ld + r];
-    } else {
-      const double* src = S.y_int;
-      int j = t.col0 + r;
-      if (r >= nc) {
-        src = S.x_int;
-        j = rows[r - nc];
+  const int lane = tid & 63, wid = tid >> 6, sub = lane / LPR, li = lane % LPR;
+  for (int base = wid * CPW; base < t.count; base += (kGroup / 64) * CPW) {
+    const int cc = base + sub;
+    const bool act = cc < t.count;
+    const int col = t.first + (act ? cc : 0);
+    const T* Pc = panel + t.panel_off + (int64_t)col * ld;
+    const int rend = act ? ld : 0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    auto term = [&](int r, double p) {
+      double v0, v1, v2;
+      if (kLds) {
+        v0 = vs[r];
+        v1 = vs[ld + r];
+        v2 = vs[2 * ld + r];
+      } else {
+        const double* src = S.y_int;
+        int j = t.col0 + r;
+        if (r >= nc) {
+          src = S.x_int;
+          j = rows[r - nc];
+        }
+        v0 = src[j];
+        v1 = src[nf + j];
+        v2 = src[2 * nf + j];
       }
-      v0 = src[j];
-      v1 = src[nf + j];
-      v2 = src[2 * nf + j];
+      a0 += p * v0;
+      a1 += p * v1;
+      a2 += p * v2;
+    };
+    // rows above the diagonal are zeros: start at the column's own row;
+    // four panel loads in flight per lane
+    int r = col + li;
+    for (; r + 3 * LPR < rend; r += 4 * LPR) {
+      const double p0 = (double)Pc[r], p1 = (double)Pc[r + LPR];
+      const double p2 = (double)Pc[r + 2 * LPR], p3 = (double)Pc[r + 3 * LPR];
+      term(r, p0);
+      term(r + LPR, p1);
+      term(r + 2 * LPR, p2);
+      term(r + 3 * LPR, p3);
     }
+    for (; r < rend; r += LPR) term(r, (double)Pc[r]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < nown) {
-        // rows above a column's diagonal hold explicit zeros in the panel
-        const double p = (double)Pb[(int64_t)q * ld + r];
-        acc[q][0] += p * v0;
-        acc[q][1] += p * v1;
-        acc[q][2] += p * v2;
-      }
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
     }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q >= nown) break;
-    const double a0 = wsum(acc[q][0]), a1 = wsum(acc[q][1]), a2 = wsum(acc[q][2]);
-    if (lane == 0) store_bwd_col(S, t, cw + q, a0, a1, a2, out, N, alpha, accumulate);
+    if (act && li == 0) store_bwd_col(S, t, col, a0, a1, a2, out, N, alpha, accumulate);
   }
 }
 
@@ -298,14 +317,14 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTas
   fwd_narrow_task<T>(S, tasks[blockIdx.x], panel, b, N, true, threadIdx.x, lds);
 }
 
-template <typename T>
+template <typename T, int LPR>
 __global__ void __launch_bounds__(kBlock) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
                                                            const T* __restrict__ panelT,
                                                            const double* __restrict__ b, int N, int pre,
                                                            const IterState* st) {
   if (st && st->done) return;
   extern __shared__ double lds[];
-  fwd_wide_task<T>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
+  fwd_wide_task<T, LPR>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
 }
 
 // Right-hand sides of one level with the descendants' updates added, once per
@@ -337,13 +356,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep_gather(DevSolve S, const int32
   }
 }
 
-template <typename T, bool kLds>
+template <typename T, bool kLds, int LPR>
 __global__ void __launch_bounds__(kBlock) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
                                                       const T* __restrict__ panel, double* __restrict__ out,
                                                       int N, double alpha, int accumulate, const IterState* st) {
   if (st && st->done) return;
   extern __shared__ double lds[];
-  bwd_cols_task<T, kLds>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true, threadIdx.x, lds);
+  bwd_cols_task<T, kLds, LPR>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true, threadIdx.x, lds);
 }
 
 template <typename T>
@@ -379,33 +398,46 @@ void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* ta
     hipLaunchKernelGGL(k_sweep_gather, dim3((n_gather + waves - 1) / waves), dim3(kBlock), 0, s, S,
                        gather_cols, n_gather, b, N, st);
   }
-  if (fp32)
-    DPD_LAUNCH(k_sweep_fwd_wide<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
-                       b, N, pre, st);
-  else
-    DPD_LAUNCH(k_sweep_fwd_wide<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
-                       b, N, pre, st);
+  // lanes per row: at least about eight columns per lane on the level's widest block
+  const int lpr = lds_cols >= 512 ? 64 : (lds_cols >= 256 ? 32 : 16);
+#define DPD_FWD_WIDE(T, L, P) \
+  DPD_LAUNCH((k_sweep_fwd_wide<T, L>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks, P, b, N, pre, st)
+  if (fp32) {
+    if (lpr == 64) DPD_FWD_WIDE(float, 64, S.panelT32);
+    else if (lpr == 32) DPD_FWD_WIDE(float, 32, S.panelT32);
+    else DPD_FWD_WIDE(float, 16, S.panelT32);
+  } else {
+    if (lpr == 64) DPD_FWD_WIDE(double, 64, S.panelT64);
+    else if (lpr == 32) DPD_FWD_WIDE(double, 32, S.panelT64);
+    else DPD_FWD_WIDE(double, 16, S.panelT64);
+  }
+#undef DPD_FWD_WIDE
 }
 
 void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks, int lds_rows,
                       bool use_lds, bool fp32, double* out, int N, double alpha, int accumulate,
                       const IterState* st) {
   const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
+  // lanes per column: at least about eight rows per lane on the level's longest panel
+  const int lpr = lds_rows >= 512 ? 64 : (lds_rows >= 256 ? 32 : 16);
+#define DPD_BWD(T, K, L, P) \
+  DPD_LAUNCH((k_sweep_bwd<T, K, L>), dim3(ntasks), dim3(kBlock), K ? lds : 0, s, S, tasks, P, out, N, alpha, \
+             accumulate, st)
+#define DPD_BWD_L(T, K, P)                 \
+  do {                                     \
+    if (lpr == 64) DPD_BWD(T, K, 64, P);   \
+    else if (lpr == 32) DPD_BWD(T, K, 32, P); \
+    else DPD_BWD(T, K, 16, P);             \
+  } while (0)
   if (fp32) {
-    if (use_lds)
-      DPD_LAUNCH((k_sweep_bwd<float, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                         S.panel32, out, N, alpha, accumulate, st);
-    else
-      DPD_LAUNCH((k_sweep_bwd<float, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks, S.panel32,
-                         out, N, alpha, accumulate, st);
+    if (use_lds) DPD_BWD_L(float, true, S.panel32);
+    else DPD_BWD_L(float, false, S.panel32);
   } else {
-    if (use_lds)
-      DPD_LAUNCH((k_sweep_bwd<double, true>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks,
-                         S.panel64, out, N, alpha, accumulate, st);
-    else
-      DPD_LAUNCH((k_sweep_bwd<double, false>), dim3(ntasks), dim3(kBlock), 0, s, S, tasks,
-                         S.panel64, out, N, alpha, accumulate, st);
+    if (use_lds) DPD_BWD_L(double, true, S.panel64);
+    else DPD_BWD_L(double, false, S.panel64);
   }
+#undef DPD_BWD_L
+#undef DPD_BWD
 }
 
 void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
