@@ -368,9 +368,10 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     // many small supernodes: one backward task each (LDS holds 3 x ld doubles)
     const bool narrow_b = !wide && (int64_t)by_level[l].size() >= 256 && max_ld <= 2048;
     P.bwd_narrow[l] = narrow_b ? 1 : 0;
-    // wide forward: rows per task in [4, 64]; backward: columns per task in {4, 8, 12, 16}
-    int32_t rpt = (int32_t)std::min<int64_t>(64, std::max<int64_t>(4, (rows + target - 1) / target));
-    rpt = (rpt + 3) / 4 * 4;
+    // wide forward: one pass of a task's waves (16 waves x 64 / lanes-per-row
+    // rows), so the block's staged right-hand sides serve that many rows;
+    // backward: columns per task in {4, 8, 12, 16}
+    const int32_t rpt = (kWideTaskThreads / 64) * (64 / sweep_lanes(max_nc));
     int32_t cpt = (int32_t)std::min<int64_t>(kColsPerTask, std::max<int64_t>(4, (cols + target - 1) / target));
     cpt = (cpt + 3) / 4 * 4;
     for (int32_t s : by_level[l]) {

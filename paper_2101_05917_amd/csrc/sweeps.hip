@@ -30,9 +30,9 @@ __device__ inline double wsum(double v) {
 
 // b~ for the task's supernode into bs[3][nc]: pre-gathered (bt) or gathered here.
 __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const double* __restrict__ b,
-                                 int N, bool pre, int tid, double* bs) {
+                                 int N, bool pre, int tid, double* bs, int nthreads = kGroup) {
   const int nc = t.ncols;
-  for (int c = tid; c < nc; c += kGroup) {
+  for (int c = tid; c < nc; c += nthreads) {
     const int j = t.col0 + c;
     double v0, v1, v2;
     if (pre) {
@@ -145,20 +145,22 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
 // Forward task, wide blocks: LPR lanes per panel row on the row-major copy
 // (64 / LPR rows per wave), each lane walking the row's columns with stride
 // LPR, then a reduction over the row's LPR lanes.  LPR is chosen per level so
-// that every lane reads at least about eight entries of its row.
-template <typename T, int LPR>
+// that every lane reads at least about eight entries of its row.  A task of NT
+// lanes (16 waves) covers one pass of rows, so the block's right-hand sides
+// staged in LDS serve 16 x 64 / LPR rows.
+template <typename T, int LPR, int NT>
 __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
                                      const double* __restrict__ b, int N, bool pre, bool active, int tid,
                                      double* bs) {
   __syncthreads();
-  if (active) stage_rhs(S, t, b, N, pre, tid, bs);
+  if (active) stage_rhs(S, t, b, N, pre, tid, bs, NT);
   __syncthreads();
   if (!active) return;
   constexpr int RPW = 64 / LPR;
   const int nc = t.ncols;
   const int lane = tid & 63, wid = tid >> 6, sub = lane / LPR, li = lane % LPR;
   const T* Pb = panelT + t.panel_off;
-  for (int base = wid * RPW; base < t.count; base += (kGroup / 64) * RPW) {
+  for (int base = wid * RPW; base < t.count; base += (NT / 64) * RPW) {
     const int rr = base + sub;
     const bool act = rr < t.count;
     const int r = t.first + rr;
@@ -318,13 +320,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTas
 }
 
 template <typename T, int LPR>
-__global__ void __launch_bounds__(kBlock) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
-                                                           const T* __restrict__ panelT,
-                                                           const double* __restrict__ b, int N, int pre,
-                                                           const IterState* st) {
+__global__ void __launch_bounds__(kWideTaskThreads) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                                     const T* __restrict__ panelT,
+                                                                     const double* __restrict__ b, int N, int pre,
+                                                                     const IterState* st) {
   if (st && st->done) return;
   extern __shared__ double lds[];
-  fwd_wide_task<T, LPR>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
+  fwd_wide_task<T, LPR, kWideTaskThreads>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
 }
 
 // Right-hand sides of one level with the descendants' updates added, once per
@@ -399,9 +401,10 @@ void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* ta
                        gather_cols, n_gather, b, N, st);
   }
   // lanes per row: at least about eight columns per lane on the level's widest block
-  const int lpr = lds_cols >= 512 ? 64 : (lds_cols >= 256 ? 32 : 16);
-#define DPD_FWD_WIDE(T, L, P) \
-  DPD_LAUNCH((k_sweep_fwd_wide<T, L>), dim3(ntasks), dim3(kBlock), lds, s, S, tasks, P, b, N, pre, st)
+  const int lpr = sweep_lanes(lds_cols);
+#define DPD_FWD_WIDE(T, L, P)                                                                       \
+  DPD_LAUNCH((k_sweep_fwd_wide<T, L>), dim3(ntasks), dim3(kWideTaskThreads), lds, s, S, tasks, P, b, N, \
+             pre, st)
   if (fp32) {
     if (lpr == 64) DPD_FWD_WIDE(float, 64, S.panelT32);
     else if (lpr == 32) DPD_FWD_WIDE(float, 32, S.panelT32);
@@ -419,7 +422,7 @@ void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
                       const IterState* st) {
   const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
   // lanes per column: at least about eight rows per lane on the level's longest panel
-  const int lpr = lds_rows >= 512 ? 64 : (lds_rows >= 256 ? 32 : 16);
+  const int lpr = sweep_lanes(lds_rows);
 #define DPD_BWD(T, K, L, P) \
   DPD_LAUNCH((k_sweep_bwd<T, K, L>), dim3(ntasks), dim3(kBlock), K ? lds : 0, s, S, tasks, P, out, N, alpha, \
              accumulate, st)
