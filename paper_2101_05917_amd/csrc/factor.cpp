@@ -370,10 +370,9 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     P.bwd_narrow[l] = narrow_b ? 1 : 0;
     // wide forward: one pass of a task's waves (16 waves x 64 / lanes-per-row
     // rows), so the block's staged right-hand sides serve that many rows;
-    // backward: columns per task in {4, 8, 12, 16}
+    // backward: likewise one pass of columns (16 x 64 / lanes-per-column)
     const int32_t rpt = (kWideTaskThreads / 64) * (64 / sweep_lanes(max_nc));
-    int32_t cpt = (int32_t)std::min<int64_t>(kColsPerTask, std::max<int64_t>(4, (cols + target - 1) / target));
-    cpt = (cpt + 3) / 4 * 4;
+    const int32_t cpt = (kWideTaskThreads / 64) * (64 / sweep_lanes(max_ld));
     for (int32_t s : by_level[l]) {
       const Supernode& sn = S.sn[s];
       const int32_t ld = sn.ncols + sn.nrows;

@@ -80,13 +80,14 @@ struct SweepTask {
 };
 
 constexpr int kBlock = 256;          // threads per workgroup of every kernel
-constexpr int kColsPerTask = 16;     // backward-sweep columns per workgroup
+constexpr int kColsPerTask = 64;     // most backward-sweep columns per workgroup
 
 // Lanes that share one panel row (wide forward sweep) or column (backward
 // sweep), from the level's widest row or longest column: every lane then
 // reads at least about eight panel entries.
 inline int sweep_lanes(int extent) { return extent >= 512 ? 64 : (extent >= 256 ? 32 : 16); }
-// Lanes of a wide forward task: one pass of its 16 waves covers the task's rows.
+// Lanes of a wide forward task and of a backward column task: one pass of
+// their 16 waves covers the task's rows (columns).
 constexpr int kWideTaskThreads = 1024;
 
 // Level schedule of the sweeps: supernodes of equal tree level are

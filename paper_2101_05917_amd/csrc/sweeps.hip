@@ -73,11 +73,12 @@ __device__ inline void store_fwd_row(const DevSolve& S, const SweepTask& t, int 
 }
 
 // v[3][ld] = [y_s; x_R] for the backward task.
-__device__ inline void stage_solution(const DevSolve& S, const SweepTask& t, int tid, double* vs) {
+__device__ inline void stage_solution(const DevSolve& S, const SweepTask& t, int tid, double* vs,
+                                      int nthreads = kGroup) {
   const int nc = t.ncols, ld = t.ncols + t.nrows;
   const int64_t nf = S.nf;
   const int* rows = S.rows + t.rows_off;
-  for (int r = tid; r < ld; r += kGroup) {
+  for (int r = tid; r < ld; r += nthreads) {
     const double* src = S.y_int;
     int j = t.col0 + r;
     if (r >= nc) {
@@ -197,12 +198,12 @@ __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, cons
 // (column-major panel, contiguous), then a reduction over the column's lanes;
 // v from LDS (kLds) or from global memory.  LPR is chosen per level so that
 // every lane reads at least about eight entries of its column.
-template <typename T, bool kLds, int LPR>
+template <typename T, bool kLds, int LPR, int NT>
 __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                      double* __restrict__ out, int N, double alpha, int accumulate,
                                      bool active, int tid, double* vs) {
   __syncthreads();
-  if (kLds && active) stage_solution(S, t, tid, vs);
+  if (kLds && active) stage_solution(S, t, tid, vs, NT);
   __syncthreads();
   if (!active) return;
   constexpr int CPW = 64 / LPR;
@@ -210,7 +211,7 @@ __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, cons
   const int64_t nf = S.nf;
   const int* rows = S.rows + t.rows_off;
   const int lane = tid & 63, wid = tid >> 6, sub = lane / LPR, li = lane % LPR;
-  for (int base = wid * CPW; base < t.count; base += (kGroup / 64) * CPW) {
+  for (int base = wid * CPW; base < t.count; base += (NT / 64) * CPW) {
     const int cc = base + sub;
     const bool act = cc < t.count;
     const int col = t.first + (act ? cc : 0);
@@ -359,12 +360,14 @@ __global__ void __launch_bounds__(kBlock) k_sweep_gather(DevSolve S, const int32
 }
 
 template <typename T, bool kLds, int LPR>
-__global__ void __launch_bounds__(kBlock) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
-                                                      const T* __restrict__ panel, double* __restrict__ out,
-                                                      int N, double alpha, int accumulate, const IterState* st) {
+__global__ void __launch_bounds__(kWideTaskThreads) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
+                                                                const T* __restrict__ panel,
+                                                                double* __restrict__ out, int N, double alpha,
+                                                                int accumulate, const IterState* st) {
   if (st && st->done) return;
   extern __shared__ double lds[];
-  bwd_cols_task<T, kLds, LPR>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true, threadIdx.x, lds);
+  bwd_cols_task<T, kLds, LPR, kWideTaskThreads>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true,
+                                                threadIdx.x, lds);
 }
 
 template <typename T>
@@ -424,8 +427,8 @@ void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
   // lanes per column: at least about eight rows per lane on the level's longest panel
   const int lpr = sweep_lanes(lds_rows);
 #define DPD_BWD(T, K, L, P) \
-  DPD_LAUNCH((k_sweep_bwd<T, K, L>), dim3(ntasks), dim3(kBlock), K ? lds : 0, s, S, tasks, P, out, N, alpha, \
-             accumulate, st)
+  DPD_LAUNCH((k_sweep_bwd<T, K, L>), dim3(ntasks), dim3(kWideTaskThreads), K ? lds : 0, s, S, tasks, P, out, \
+             N, alpha, accumulate, st)
 #define DPD_BWD_L(T, K, P)                 \
   do {                                     \
     if (lpr == 64) DPD_BWD(T, K, 64, P);   \

@@ -162,11 +162,11 @@ int main(int argc, char** argv) {
         const Supernode& sn = S.sn[t.sn];
         const int nc_ = sn.ncols, ld = sn.ncols + sn.nrows;
         CHECK(ld <= P.bwd_rows[l]);
-        const int nw = kBlock / 64, cpw = P.bwd_narrow[l] ? 1 : (t.count + nw - 1) / nw;
-        CHECK(P.bwd_narrow[l] ? (t.first == 0 && t.count == nc_ && nc_ <= 64 && ld <= 2048) : cpw <= 4);
+        CHECK(P.bwd_narrow[l] ? (t.first == 0 && t.count == nc_ && nc_ <= 64 && ld <= 2048)
+                              : t.count <= kColsPerTask);
         for (int cc = 0; cc < t.count; ++cc) {
           const int c = t.first + cc;
-          const int cw = P.bwd_narrow[l] ? c : t.first + (cc / cpw) * cpw;   // first row read
+          const int cw = c;   // first row read: the column's own row (zeros above it are skipped)
           double a[3] = {0, 0, 0};
           for (int r = cw; r < ld; ++r) {
             const int64_t pi = P.bwd_narrow[l] ? sn.panel_off + (int64_t)r * nc_ + c
