@@ -50,10 +50,14 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--fwd-solver", default="newton_pcg", choices=["newton_pcg", "pd"])
     ap.add_argument("--bwd-solver", default="pcg", choices=["pcg", "fixed_point"])
-    ap.add_argument("--fwd-tol", type=float, default=1e-7)
+    # forward: Newton steps until |grad g| <= 3e-8 |grad g(x0)|, each step's CG to an
+    # Eisenstat-Walker forcing term (capped at 0.1); adjoint CG to 1e-7: the
+    # end-to-end gradient error stays well inside the metric's 1e-6
+    ap.add_argument("--fwd-tol", type=float, default=3e-8)
     ap.add_argument("--bwd-tol", type=float, default=1e-7)
-    ap.add_argument("--fwd-inner-tol", type=float, default=1e-2,
-                    help="relative tolerance of each Newton step's conjugate-gradient solve")
+    ap.add_argument("--fwd-inner-tol", type=float, default=-0.1,
+                    help="relative tolerance of each Newton step's conjugate-gradient solve; "
+                         "negative: Eisenstat-Walker forcing terms capped at its magnitude")
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

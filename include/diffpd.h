@@ -86,7 +86,9 @@ typedef struct {
   double fwd_abs_tol_rel;  /* ... or |grad g| <= this * |M y / h^2| (free DoFs)   */
   int32_t fwd_solver;      /* DPD_FWD_PD or DPD_FWD_NEWTON_PCG                     */
   int32_t fwd_inner_max_iter; /* CG iterations per Newton step                    */
-  double fwd_inner_tol;    /* CG relative tolerance per Newton step               */
+  double fwd_inner_tol;    /* CG relative tolerance per Newton step; a negative
+                              value -e selects Eisenstat-Walker forcing terms
+                              capped at e                                        */
   /* backward iteration (Alg. 2 or CG) */
   int32_t bwd_max_iter;
   int32_t bwd_solver;      /* DPD_BWD_FIXED_POINT or DPD_BWD_PCG                   */

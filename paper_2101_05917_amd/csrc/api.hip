@@ -871,6 +871,13 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
     // count is read with the residual's convergence flag.
     const bool fused = m->dense_blocks > 0 && o.fused_cg;
     bool pending = false;
+    // Inner tolerance: fixed, or (fwd_inner_tol < 0) the Eisenstat-Walker
+    // forcing terms ("choice 2": eta_k = 0.9 (|g_k| / |g_{k-1}|)^2, safeguarded
+    // by 0.9 eta_{k-1}^2 when that exceeds 0.1, capped at |fwd_inner_tol|, and
+    // kept above half the outer tolerance relative to |g_k|).
+    const bool adaptive = o.fwd_inner_tol < 0.0;
+    const double eta_max = std::fabs(o.fwd_inner_tol);
+    double eta = eta_max, g_prev = -1.0;
     for (outer = 0;; ++outer) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
       if (pending) {
@@ -879,9 +886,20 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
         pending = false;
       }
       if (m->h_st[0].done || solves >= max_it) break;
+      if (adaptive) {
+        const double gk = std::sqrt(m->h_st[0].rsq);
+        if (g_prev > 0.0 && gk > 0.0) {
+          double e = 0.9 * (gk / g_prev) * (gk / g_prev);
+          const double safe = 0.9 * eta * eta;
+          if (safe > 0.1) e = std::max(e, safe);
+          const double floor = 0.5 * o.fwd_rel_tol * std::sqrt(m->h_st[0].r0sq) / gk;
+          eta = std::min(eta_max, std::max(e, floor));
+        }
+        g_prev = gk;
+      }
       launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
       const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
-      launch_reset(s, inner, o.fwd_inner_tol * o.fwd_inner_tol, inner_max);
+      launch_reset(s, inner, eta * eta, inner_max);
       if (fused) {
         if ((rc = cg_dense_async(m, s, inner, m->r, -1.0, fp32, true)) != DPD_OK) return rc;
         pending = true;

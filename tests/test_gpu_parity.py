@@ -336,3 +336,19 @@ def test_mixed_local_step_rotations(name):
     err = np.abs(R - Rref).max()
     print(name, err, flush=True)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "robot"])
+def test_forward_newton_eisenstat_walker(name):
+    """Adaptive inner tolerances (Eisenstat-Walker forcing terms) reach the same
+    converged implicit-Euler state."""
+    sc = SCENES[name]()
+    g, o = pair(sc, fwd_solver="newton_pcg", fwd_inner_tol=-0.1, fwd_max_iter=100000,
+                fwd_rel_tol=1e-13, check_every=64)
+    x, v = _perturbed(o, seed=71)
+    act = None if o.Gm is None else np.random.default_rng(72).uniform(0, 1, o.E)
+    xn, vn, st = g.forward_step(to_dev(x, o.N), to_dev(v, o.N), None if act is None else elem_dev(act))
+    print(name, st, flush=True)
+    assert st["converged"] == 1
+    xr = converged_state(o, x, v, act)
+    assert np.linalg.norm(soa(xn) - xr) <= 1e-9 * np.linalg.norm(xr - x)
