@@ -29,6 +29,8 @@ constexpr int64_t kProfStride = 16;
 constexpr int kHoldPeriods = 8;         // about 25 us of s_sleep ahead of one timed kernel
 constexpr int kHoldPeriodsAround = 40;  // about 130 us ahead of a timed multi-launch solve
 constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
+constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before the first check
+constexpr int kNewtonMore = 2;   // ... and per later check
 
 }  // namespace
 
@@ -41,9 +43,6 @@ struct TimedLaunch {
   // multiplied at harvest by the iteration count of state iter_state
   int iter_state = -1;
   double iter_bytes = 0.0, iter_flops = 0.0;
-  // the duration is read from the launch's own device clock stamps in state
-  // iter_state (entry and exit of workgroup 0) instead of the event pair
-  bool device_clock = false;
 };
 
 struct dpd_mesh {
@@ -92,6 +91,7 @@ struct dpd_mesh {
   int64_t prof_launches = 0, prof_seen = 0, prof_iters = 0;
   double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0, prof_event_ms = 0.0;
   double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
+  ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
 };
 
 namespace {
@@ -215,11 +215,8 @@ void prof_harvest(dpd_mesh* m) {
     }
     if (live) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, t.ev.first, t.ev.second) == hipSuccess) m->prof_event_ms += ms;
-      if (t.device_clock) {
-        const IterState& h = m->h_st[t.iter_state];
-        m->prof_ms += (double)(h.clk1 - h.clk0) / m->clock_khz;
-      } else {
+      if (hipEventElapsedTime(&ms, t.ev.first, t.ev.second) == hipSuccess) {
+        m->prof_event_ms += ms;
         m->prof_ms += ms;
       }
       m->prof_launches += 1;
@@ -865,26 +862,42 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
     }
     launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, 0, never, 0);
-    // With the fused solver a Newton step needs one synchronisation: its
-    // solve, the update x += z (z = the PD step after a curvature failure)
-    // and the next residual are enqueued together, and the solve's iteration
-    // count is read with the residual's convergence flag.
-    const bool fused = m->dense_blocks > 0 && o.fused_cg;
-    bool pending = false;
     // Inner tolerance: fixed, or (fwd_inner_tol < 0) the Eisenstat-Walker
     // forcing terms ("choice 2": eta_k = 0.9 (|g_k| / |g_{k-1}|)^2, safeguarded
     // by 0.9 eta_{k-1}^2 when that exceeds 0.1, capped at |fwd_inner_tol|, and
     // kept above half the outer tolerance relative to |g_k|).
     const bool adaptive = o.fwd_inner_tol < 0.0;
     const double eta_max = std::fabs(o.fwd_inner_tol);
+    if (m->dense_blocks > 0 && o.fused_cg) {
+      // Fused solver: Newton steps are enqueued ahead of their convergence
+      // test (kNewtonAhead, then kNewtonMore at a time) and decide on the
+      // device: inner set-up (forcing term, cap), solve (-grad g; the plain
+      // PD step after a curvature failure), x += z, next residual; every
+      // kernel does nothing once the outer iteration has finished.  One host
+      // synchronisation per batch.
+      for (int batch = kNewtonAhead;; batch = kNewtonMore) {
+        for (int i = 0; i < batch; ++i, ++outer) {
+          launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr, m->st);
+          launch_newton_inner(s, m->st, inner, eta_max, adaptive ? 1 : 0, o.fwd_rel_tol, o.fwd_inner_max_iter,
+                              max_it);
+          if ((rc = cg_dense_async(m, s, inner, m->r, -1.0, fp32, true)) != DPD_OK) return rc;
+          launch_newton_update(s, n3, m->st, inner, xn, m->z);
+          {
+            ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
+            launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+          }
+          launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
+        }
+        if ((rc = read_state(m, s)) != DPD_OK) return rc;
+        if ((rc = check_aborted(m, 1)) != DPD_OK) return rc;
+        if (m->h_st[0].done) break;
+      }
+      solves = m->h_st[0].solves;
+      outer = m->h_st[0].iter;
+    } else {
     double eta = eta_max, g_prev = -1.0;
     for (outer = 0;; ++outer) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      if (pending) {
-        if ((rc = check_aborted(m, 1)) != DPD_OK) return rc;
-        solves += std::max(1, m->h_st[1].iter);
-        pending = false;
-      }
       if (m->h_st[0].done || solves >= max_it) break;
       if (adaptive) {
         const double gk = std::sqrt(m->h_st[0].rsq);
@@ -900,17 +913,6 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
       const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
       launch_reset(s, inner, eta * eta, inner_max);
-      if (fused) {
-        if ((rc = cg_dense_async(m, s, inner, m->r, -1.0, fp32, true)) != DPD_OK) return rc;
-        pending = true;
-        launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
-        {
-          ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
-          launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
-        }
-        launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
-        continue;
-      }
       launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
       if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
           DPD_OK)
@@ -928,6 +930,7 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
     }
       launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
+    }
     }
   }
   for (int k = 0; solves < 0; ++k) {
@@ -1049,25 +1052,18 @@ double dense_iter_bytes(const dpd_mesh* m, bool fp32) {
 // z = A^{-1} rhs, the plain PD step.
 dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
                           bool fp32, bool pd_fallback) {
-  const int st_idx = st == m->st ? 0 : 1;
   if (fp32 && !m->ainv32) return fail(m, DPD_ESTATE, "no FP32 copy of the dense inverse");
-  {
-    const double n = (double)m->hm.n_free;
-    ProfScope ps(m, s, DPD_PROF_CG_DENSE, dense_matvec_bytes(m, fp32), 6.0 * n * n);
-    if (ps.on) {
-      ps.t.device_clock = true;
-      ps.t.iter_state = st_idx;
-      ps.t.iter_bytes = dense_iter_bytes(m, fp32);
-      ps.t.iter_flops = 6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems;
-    }
-    HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, rhs_scale,
-                                pd_fallback ? 1 : 0, m->z, st));
-  }
+  // while timed, every launch adds its own device-clock duration, iterations
+  // and itself to m->prof_acc (HIP events around a cooperative launch would
+  // also bracket the host's enqueue time)
+  ProfAcc* acc = m->prof_class == DPD_PROF_CG_DENSE && !m->capturing ? m->prof_acc : nullptr;
+  HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, rhs_scale,
+                              pd_fallback ? 1 : 0, m->z, st, acc));
   return DPD_OK;
 }
 
 dpd_status check_aborted(dpd_mesh* m, int st_idx) {
-  if (m->h_st[st_idx].aborted)
+  if (m->h_st[st_idx].aborted || m->h_st[0].aborted)
     return fail(m, DPD_EHIP, "fused conjugate-gradient solver: grid barrier timed out");
   return DPD_OK;
 }
@@ -1225,6 +1221,13 @@ dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
     m->clock_khz = khz;
+  if (kernel_class == DPD_PROF_CG_DENSE) {
+    if (!m->prof_acc) {
+      dpd_status st = dev_alloc(m, &m->prof_acc, 1);
+      if (st != DPD_OK) return st;
+    }
+    HIPCHECK(m, hipMemset(m->prof_acc, 0, sizeof(ProfAcc)));
+  }
   m->prof_class = kernel_class;
   m->prof_launches = 0;
   m->prof_seen = 0;
@@ -1237,6 +1240,19 @@ dpd_status dpd_profile_read(dpd_mesh* m, void* stream, dpd_kernel_profile* out) 
   if (!m || !out) return fail(m, DPD_EINVAL, "null argument");
   HIPCHECK(m, hipStreamSynchronize((hipStream_t)stream));
   prof_harvest(m);
+  if (m->prof_class == DPD_PROF_CG_DENSE && m->prof_acc) {
+    ProfAcc a{};
+    HIPCHECK(m, hipMemcpy(&a, m->prof_acc, sizeof(ProfAcc), hipMemcpyDeviceToHost));
+    const bool fp32 = m->opt.precision == DPD_MIXED;
+    const double n = (double)m->hm.n_free;
+    m->prof_launches = (int64_t)a.launches;
+    m->prof_iters = (int64_t)a.iters;
+    m->prof_ms = (double)a.ticks / m->clock_khz;
+    m->prof_event_ms = 0.0;
+    m->prof_bytes = (double)a.launches * dense_matvec_bytes(m, fp32) + (double)a.iters * dense_iter_bytes(m, fp32);
+    m->prof_flops = (double)a.launches * 6.0 * n * n +
+                    (double)a.iters * (6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems);
+  }
   out->launches = m->prof_launches;
   out->iterations = m->prof_iters;
   out->event_ms = m->prof_event_ms;

@@ -232,7 +232,10 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
                                                           const double* __restrict__ cache,
                                                           const double* __restrict__ rhs, double rhs_scale,
                                                           int pd_fallback, double* __restrict__ z_out,
-                                                          IterState* st) {
+                                                          IterState* st, ProfAcc* prof) {
+  // a solve whose state is already finished (the Newton forward step enqueues
+  // solves ahead of its convergence test) does nothing
+  if (st->done) return;
   extern __shared__ double lds[];
   // r_k of every row in LDS ([3][n]); with kVecLds also q_k of every row, so
   // that r and q never go through device memory (every workgroup forms the
@@ -512,8 +515,11 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     st->nonfinite = nonfinite;
     st->curvature = curvature;
     st->aborted = (!alive || __hip_atomic_load(&D.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ? 1 : 0;
-    st->clk0 = clk0;
-    st->clk1 = wall_clock64();
+    if (prof) {
+      atomicAdd(&prof->ticks, (unsigned long long)(wall_clock64() - clk0));
+      atomicAdd(&prof->iters, (unsigned long long)k);
+      atomicAdd(&prof->launches, 1ull);
+    }
     st->done = 1;
   }
 }
@@ -590,7 +596,7 @@ int cg_dense_max_blocks(int n, int rows, int mode, bool fp32) {
 
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
-                           double* z_out, IterState* st) {
+                           double* z_out, IterState* st, ProfAcc* prof) {
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar);
   const int mode = fp32 ? D.mode32 : D.mode64;
   const size_t lds = cg_dense_lds_bytes(D.n, D.rows, mode, fp32);
@@ -602,14 +608,15 @@ hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, in
   double* zp = z_out;
   double sc = rhs_scale;
   int pf = pd_fallback;
+  ProfAcc* pa = prof;
   if (fp32) {
     const float* a = D.ainv32;
-    void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp};
+    void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp, &pa};
     return hipLaunchCooperativeKernel(dense_kernel(true, mode), dim3(blocks), dim3(kDenseBlock), args,
                                       (unsigned)lds, s);
   }
   const double* a = D.ainv64;
-  void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp};
+  void* args[] = {&m, &d, &a, &cp, &rp, &sc, &pf, &zp, &stp, &pa};
   return hipLaunchCooperativeKernel(dense_kernel(false, mode), dim3(blocks), dim3(kDenseBlock), args,
                                     (unsigned)lds, s);
 }

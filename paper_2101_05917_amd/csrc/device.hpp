@@ -21,7 +21,15 @@ struct IterState {
   uint32_t counter;                  // last-block-done ticket
   int32_t max_iter;                  // iteration cap of the conjugate-gradient loop
   int32_t aborted;                   // the fused solver's grid barrier timed out
-  uint64_t clk0, clk1;               // fused solver: constant-rate device clock at entry and exit
+  int32_t solves;                    // Newton forward: conjugate-gradient iterations so far
+  double g_prev, eta;                // Newton forward: previous |grad g| and forcing term
+};
+
+// Device-side accumulation of the fused solver's launches while it is being
+// profiled: constant-rate clock ticks from workgroup 0's entry to its exit,
+// iterations and launches (launches that exit at once are not counted).
+struct ProfAcc {
+  unsigned long long ticks, iters, launches, pad;
 };
 
 struct DevSolve {
@@ -145,7 +153,11 @@ void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
                       int lds_rows, bool use_lds, bool fp32, double* out, int N, double alpha,
                       int accumulate, const IterState* st);
 void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
-                      double* cache, IterState* st);
+                      double* cache, IterState* st, const IterState* gate = nullptr);
+void launch_newton_inner(hipStream_t s, IterState* outer, IterState* inner, double eta_max, int adaptive,
+                         double rel_tol, int inner_max_iter, int max_iter);
+void launch_newton_update(hipStream_t s, int64_t n3, IterState* outer, const IterState* inner, double* xn,
+                          const double* z);
 void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
                      double* fe, const IterState* st);
 void launch_node_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* fe,
@@ -167,7 +179,7 @@ size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32);
 int cg_dense_max_blocks(int n, int rows, int mode, bool fp32);
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
-                           double* z_out, IterState* st);
+                           double* z_out, IterState* st, ProfAcc* prof);
 void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, double* b);
 void launch_collect_rows(hipStream_t s, int N, int n, const int32_t* perm, int j0, const double* x,
                          double* ainv);

@@ -140,6 +140,9 @@ __global__ void k_reset_state(IterState* st, double tolsq, int max_iter) {
     st->tolsq = tolsq;
     st->nb2 = st->rs = st->pq = st->alpha = st->beta = st->acc = 0.0;
     st->iter = st->done = st->converged = st->nonfinite = st->curvature = st->inverted = 0;
+    st->aborted = st->solves = 0;
+    st->g_prev = -1.0;
+    st->eta = 0.0;
     st->counter = 0u;
   }
 }
@@ -213,7 +216,16 @@ constexpr int kCacheRows = 19;
 
 __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* __restrict__ x,
                                                       const double* __restrict__ act,
-                                                      double* __restrict__ cache, IterState* st) {
+                                                      double* __restrict__ cache, IterState* st,
+                                                      const IterState* gate, int elem_blocks) {
+  if (gate && gate->done) return;
+  if ((int)blockIdx.x >= elem_blocks) {
+    // ground contact active at the linearisation point (height below zero):
+    // the contact term of A - dA is k on the vertical coordinate there
+    const int n = (blockIdx.x - elem_blocks) * blockDim.x + threadIdx.x;
+    if (n < M.N) M.cmask[n] = (M.contact[n] && x[2 * (int64_t)M.N + n] < 0.0) ? 1 : 0;
+    return;
+  }
   __shared__ ElemTile T;
   const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
   const int e = blockIdx.x * kElemsPerBlock + le;
@@ -256,14 +268,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
   }
 }
 
-// Ground contact active at the linearisation point x (height below zero): the
-// contact term of A - dA is k on the vertical coordinate there, zero elsewhere.
-__global__ void __launch_bounds__(kBlock) k_contact_mask(DevMesh M, const double* __restrict__ x) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < M.N) M.cmask[n] = (M.contact[n] && x[2 * (int64_t)M.N + n] < 0.0) ? 1 : 0;
-}
-
-// Element part of (A - dA) p: stress w (dF - dR[dF]) (+ muscle (I - dp/df) term).
 __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
                                                      const double* __restrict__ cache,
                                                      double* __restrict__ fe, const IterState* st) {
@@ -652,10 +656,72 @@ void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v) {
 
 
 void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
-                      double* cache, IterState* st) {
+                      double* cache, IterState* st, const IterState* gate) {
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
-  hipLaunchKernelGGL(k_adj_cache, dim3(nb), dim3(kBlock), 0, s, M, x, act, cache, st);
-  hipLaunchKernelGGL(k_contact_mask, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x);
+  hipLaunchKernelGGL(k_adj_cache, dim3(nb + blocks_for(M.N)), dim3(kBlock), 0, s, M, x, act, cache, st, gate,
+                     nb);
+}
+
+// Newton forward step, inner-solve set-up on the device (no host round trip):
+// unless the outer iteration has finished (then the inner state is marked
+// done, so the solve and the update that follow do nothing), the forcing term
+// eta (fixed, or Eisenstat-Walker "choice 2": 0.9 (|g_k| / |g_{k-1}|)^2,
+// safeguarded by 0.9 eta_{k-1}^2 above 0.1, capped at eta_max, and kept above
+// half the outer tolerance relative to |g_k|) and the iteration cap.
+__global__ void k_newton_inner(IterState* outer, IterState* inner, double eta_max, int adaptive,
+                               double rel_tol, int inner_max_iter, int max_iter) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (inner->aborted) {   // a fused solve of this batch failed: stop the step, keep the flag
+    outer->aborted = 1;
+    outer->done = 1;
+  }
+  inner->r0sq = inner->rsq = inner->atolsq = 0.0;
+  inner->nb2 = inner->rs = inner->pq = inner->alpha = inner->beta = inner->acc = 0.0;
+  inner->iter = inner->converged = inner->nonfinite = inner->curvature = inner->inverted = 0;
+  inner->aborted = 0;
+  inner->counter = 0u;
+  if (outer->done || outer->solves >= max_iter) {
+    outer->done = 1;
+    inner->done = 1;
+    return;
+  }
+  inner->done = 0;
+  double eta = eta_max;
+  const double gk = sqrt(outer->rsq);
+  if (adaptive) {
+    if (outer->g_prev > 0.0 && gk > 0.0) {
+      double e = 0.9 * (gk / outer->g_prev) * (gk / outer->g_prev);
+      const double safe = 0.9 * outer->eta * outer->eta;
+      if (safe > 0.1) e = fmax(e, safe);
+      eta = fmin(eta_max, fmax(e, 0.5 * rel_tol * sqrt(outer->r0sq) / gk));
+    }
+    outer->g_prev = gk;
+  }
+  outer->eta = eta;
+  inner->tolsq = eta * eta;
+  inner->max_iter = max(1, min(inner_max_iter, max_iter - outer->solves));
+}
+
+// x += z after the inner solve, and the solve's iterations added to the
+// outer count (unless the outer iteration had already finished).
+__global__ void __launch_bounds__(kBlock) k_newton_update(int64_t n3, IterState* outer, const IterState* inner,
+                                                          double* __restrict__ xn, const double* __restrict__ z) {
+  if (outer->done) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) xn[i] += z[i];
+  if (i == 0) outer->solves += max(1, inner->iter);
+}
+
+void launch_newton_inner(hipStream_t s, IterState* outer, IterState* inner, double eta_max, int adaptive,
+                         double rel_tol, int inner_max_iter, int max_iter) {
+  hipLaunchKernelGGL(k_newton_inner, dim3(1), dim3(64), 0, s, outer, inner, eta_max, adaptive, rel_tol,
+                     inner_max_iter, max_iter);
+}
+
+void launch_newton_update(hipStream_t s, int64_t n3, IterState* outer, const IterState* inner, double* xn,
+                          const double* z) {
+  hipLaunchKernelGGL(k_newton_update, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n3, outer,
+                     inner, xn, z);
 }
 
 void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
