@@ -1133,7 +1133,13 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   launch_zero_fixed(m->dm, s, m->xbar);
   launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
   int fallbacks = 0;
-  if (o.bwd_solver == DPD_BWD_PCG) {
+  // With the fused solver the epilogue is enqueued with the solve and gated
+  // on the device: it does nothing if the solve met non-positive curvature,
+  // in which case the fallback below finishes the adjoint and runs it again.
+  const bool gated = o.bwd_solver == DPD_BWD_PCG && m->dense_blocks > 0 && o.fused_cg;
+  if (gated) {
+    if ((rc = cg_dense_async(m, s, m->st, m->xbar, 1.0, fp32, false)) != DPD_OK) return rc;
+  } else if (o.bwd_solver == DPD_BWD_PCG) {
     if ((rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every)) !=
         DPD_OK)
       return rc;
@@ -1151,10 +1157,25 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
     launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
     if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
   }
-  launch_adj_epilogue(m->dm, s, x, v, m->z, gv_next, gx, gv);
-  if (g_youngs || g_act) launch_grad_params(m->dm, s, xn, m->z, m->cache, g_youngs, g_act);
+  launch_adj_epilogue(m->dm, s, x, v, m->z, gv_next, gx, gv, gated ? m->st : nullptr);
+  if (g_youngs || g_act) launch_grad_params(m->dm, s, xn, m->z, m->cache, g_youngs, g_act, gated ? m->st : nullptr);
   HIPCHECK(m, hipGetLastError());
   if ((rc = read_state(m, s)) != DPD_OK) return rc;
+  if (gated) {
+    if ((rc = check_aborted(m, 0)) != DPD_OK) return rc;
+    if (m->h_st->curvature) {
+      // the paper's safeguard when the quasi-Newton step is not a descent:
+      // continue with the plain fixed-point iteration from the current z
+      fallbacks = 1;
+      launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
+      launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
+      if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+      launch_adj_epilogue(m->dm, s, x, v, m->z, gv_next, gx, gv);
+      if (g_youngs || g_act) launch_grad_params(m->dm, s, xn, m->z, m->cache, g_youngs, g_act);
+      HIPCHECK(m, hipGetLastError());
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+    }
+  }
   const IterState& h = *m->h_st;
   if (stats) {
     stats->bwd_iters = h.iter;

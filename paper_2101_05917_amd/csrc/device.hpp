@@ -169,10 +169,13 @@ void launch_cg_hvp_dots(const DevMesh& M, hipStream_t s, const double* sv, const
                         const double* r, double* w, IterState* st, double* partials);
 void launch_cg_step(const DevMesh& M, hipStream_t s, double* z, double* r, double* p, double* q,
                     const double* sv, const double* w, IterState* st, double* partials);
+// gate: when given and its iteration met non-positive curvature, the kernel
+// does nothing (the adjoint is finished by the fallback first)
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
-                         const double* z, const double* gv_next, double* gx, double* gv);
+                         const double* z, const double* gv_next, double* gx, double* gv,
+                         const IterState* gate = nullptr);
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
-                        const double* cache, double* g_youngs, double* g_act);
+                        const double* cache, double* g_youngs, double* g_act, const IterState* gate = nullptr);
 constexpr int kAdjCacheRows = 19;
 // fused dense solver (cg_dense.hip)
 size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32);

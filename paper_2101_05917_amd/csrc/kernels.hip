@@ -480,7 +480,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_epilogue(DevMesh M, const double
                                                          const double* __restrict__ z,
                                                          const double* __restrict__ gv_next,
                                                          double* __restrict__ gx,
-                                                         double* __restrict__ gv) {
+                                                         double* __restrict__ gv, const IterState* gate) {
+  if (gate && gate->curvature) return;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= M.N) return;
   const int64_t N = M.N;
@@ -521,7 +522,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_params(DevMesh M, const double*
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ cache,
                                                         double* __restrict__ g_youngs,
-                                                        double* __restrict__ g_act) {
+                                                        double* __restrict__ g_act, const IterState* gate) {
+  if (gate && gate->curvature) return;
   __shared__ ElemTile T;
   __shared__ double Zs[kElemsPerBlock][8][3];
   __shared__ double red[kElemsPerBlock][8][2];
@@ -757,15 +759,15 @@ void launch_cg_step(const DevMesh& M, hipStream_t s, double* z, double* r, doubl
 
 
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
-                         const double* z, const double* gv_next, double* gx, double* gv) {
+                         const double* z, const double* gv_next, double* gx, double* gv, const IterState* gate) {
   hipLaunchKernelGGL(k_adj_epilogue, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x, v, z, gv_next,
-                     gx, gv);
+                     gx, gv, gate);
 }
 
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
-                        const double* cache, double* g_youngs, double* g_act) {
+                        const double* cache, double* g_youngs, double* g_act, const IterState* gate) {
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
-  hipLaunchKernelGGL(k_grad_params, dim3(nb), dim3(kBlock), 0, s, M, xn, z, cache, g_youngs, g_act);
+  hipLaunchKernelGGL(k_grad_params, dim3(nb), dim3(kBlock), 0, s, M, xn, z, cache, g_youngs, g_act, gate);
 }
 
 }  // namespace dpd
