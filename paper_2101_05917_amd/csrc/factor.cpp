@@ -376,7 +376,7 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     for (int32_t s : by_level[l]) {
       const Supernode& sn = S.sn[s];
       const int32_t ld = sn.ncols + sn.nrows;
-      const int32_t fstep = wide ? rpt : kBlock;
+      const int32_t fstep = wide ? rpt : 64;   // narrow forward: 64 rows per task
       for (int32_t f = 0; f < ld; f += fstep) P.fwd.push_back(make_task(sn, s, f, std::min(fstep, ld - f)));
       if (narrow_b)
         P.bwd.push_back(make_task(sn, s, 0, sn.ncols));

@@ -111,8 +111,11 @@ __device__ inline void store_bwd_col(const DevSolve& S, const SweepTask& t, int 
   }
 }
 
-// Forward task, blocks of at most 64 columns: lane per panel row, columns in
-// sequence (column-major panel, coalesced across lanes).
+// Forward task, blocks of at most 64 columns: 64 panel rows, lane per row
+// (column-major panel, coalesced across lanes), the columns split over the
+// four waves (c = wave mod 4) so that each row has four streams of loads in
+// flight; the four partial sums meet in LDS (after the staged right-hand
+// sides) and are added in wave order.
 template <typename T>
 __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                        const double* __restrict__ b, int N, bool active, int tid,
@@ -120,27 +123,41 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
   __syncthreads();
   if (active) stage_rhs(S, t, b, N, false, tid, bs);
   __syncthreads();
-  if (!active || tid >= t.count) return;
+  if (!active) return;
   const int nc = t.ncols, ld = t.ncols + t.nrows;
-  const int r = t.first + tid;
+  const int lane = tid & 63, wid = tid >> 6;
+  const bool act = lane < t.count;
+  const int r = t.first + (act ? lane : 0);
   const T* P = panel + t.panel_off + r;
-  const int cend = r < nc ? r + 1 : nc;
+  const int cend = act ? (r < nc ? r + 1 : nc) : 0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  int c = 0;
-  for (; c + 4 <= cend; c += 4) {
-    const double p0 = (double)P[(int64_t)(c + 0) * ld], p1 = (double)P[(int64_t)(c + 1) * ld];
-    const double p2 = (double)P[(int64_t)(c + 2) * ld], p3 = (double)P[(int64_t)(c + 3) * ld];
-    a0 += p0 * bs[c] + p1 * bs[c + 1] + p2 * bs[c + 2] + p3 * bs[c + 3];
-    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 1] + p2 * bs[nc + c + 2] + p3 * bs[nc + c + 3];
-    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 1] + p2 * bs[2 * nc + c + 2] + p3 * bs[2 * nc + c + 3];
+  int c = wid;
+  for (; c + 12 < cend; c += 16) {
+    const double p0 = (double)P[(int64_t)c * ld], p1 = (double)P[(int64_t)(c + 4) * ld];
+    const double p2 = (double)P[(int64_t)(c + 8) * ld], p3 = (double)P[(int64_t)(c + 12) * ld];
+    a0 += p0 * bs[c] + p1 * bs[c + 4] + p2 * bs[c + 8] + p3 * bs[c + 12];
+    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 4] + p2 * bs[nc + c + 8] + p3 * bs[nc + c + 12];
+    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 4] + p2 * bs[2 * nc + c + 8] + p3 * bs[2 * nc + c + 12];
   }
-  for (; c < cend; ++c) {
+  for (; c < cend; c += 4) {
     const double p = (double)P[(int64_t)c * ld];
     a0 += p * bs[c];
     a1 += p * bs[nc + c];
     a2 += p * bs[2 * nc + c];
   }
-  store_fwd_row(S, t, r, a0, a1, a2);
+  double* red = bs + 3 * nc;   // [4][64][3]
+  red[(wid * 64 + lane) * 3 + 0] = a0;
+  red[(wid * 64 + lane) * 3 + 1] = a1;
+  red[(wid * 64 + lane) * 3 + 2] = a2;
+  __syncthreads();
+  if (wid == 0 && act) {
+    double x[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      x[q] = red[(0 * 64 + lane) * 3 + q] + red[(1 * 64 + lane) * 3 + q] + red[(2 * 64 + lane) * 3 + q] +
+             red[(3 * 64 + lane) * 3 + q];
+    store_fwd_row(S, t, r, x[0], x[1], x[2]);
+  }
 }
 
 // Forward task, wide blocks: LPR lanes per panel row on the row-major copy
@@ -386,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_bwd_narrow(DevSolve S, const S
 
 void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks, int lds_cols,
                       bool fp32, const double* b, int N, const IterState* st) {
-  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
+  const size_t lds = ((size_t)3 * lds_cols + 4 * 64 * 3) * sizeof(double);
   if (fp32)
     DPD_LAUNCH(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32, b, N, st);
   else
