@@ -35,7 +35,8 @@ KERNEL_NAMES = {"solve": "global step A^{-1} b: the per-level k_sweep_* launches
                             "cooperative launch, dense A^{-1})",
                 "sweep_fwd": "k_sweep_fwd (forward triangular sweep, one tree level per launch)",
                 "sweep_bwd": "k_sweep_bwd (backward triangular sweep, one tree level per launch)",
-                "sweep_fwd_wide": "k_sweep_gather + k_sweep_fwd_wide (forward sweep level with wide blocks)",
+                "sweep_fwd_wide": "k_sweep_fwd_wide (forward sweep level with wide blocks, every "
+                                  "lanes-per-row variant)",
                 "sweep_bwd_narrow": "k_sweep_bwd_narrow (backward sweep level of many small blocks)",
                 "elem_hvp": "k_elem_hvp (adjoint local step dA p)",
                 "elem_forces": "k_elem_forces (forward local step)"}

@@ -25,7 +25,7 @@ constexpr double kLaunchSeconds = 4e-6;      // measured time of a small depende
 constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of the sweeps
 constexpr int32_t kSepMax = 2048;
 constexpr int64_t kLdsBudget = 60 * 1024;
-constexpr int64_t kProfStride = 16;
+constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
 constexpr int kHoldPeriods = 8;         // about 25 us of s_sleep ahead of one timed kernel
 constexpr int kHoldPeriodsAround = 40;  // about 130 us ahead of a timed multi-launch solve
 constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
@@ -180,12 +180,13 @@ struct ProfScope {
     t.strict = strict;
     // Hold the stream while the timed launch and its events are enqueued, so
     // the GPU reaches them back to back and the host's enqueue time between
-    // the start event and the kernel is not counted.
-    if (!every) launch_hold(s, cls == DPD_PROF_SOLVE ? kHoldPeriodsAround : kHoldPeriods);
+    // the start event and the kernel is not counted.  A single timed kernel
+    // gets its hold from DPD_LAUNCH, directly ahead of its own dispatch.
     if (around) {
+      if (!every) launch_hold(s, kHoldPeriodsAround);
       (void)hipEventRecord(t.ev.first, s);  // several launches: bracket them in the stream
     } else {
-      g_launch_events = {t.ev.first, t.ev.second, false};  // one kernel: timed at its dispatch
+      g_launch_events = {t.ev.first, t.ev.second, false, kHoldPeriods};  // one kernel
     }
   }
   ~ProfScope() {
@@ -895,42 +896,42 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
       solves = m->h_st[0].solves;
       outer = m->h_st[0].iter;
     } else {
-    double eta = eta_max, g_prev = -1.0;
-    for (outer = 0;; ++outer) {
-      if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      if (m->h_st[0].done || solves >= max_it) break;
-      if (adaptive) {
-        const double gk = std::sqrt(m->h_st[0].rsq);
-        if (g_prev > 0.0 && gk > 0.0) {
-          double e = 0.9 * (gk / g_prev) * (gk / g_prev);
-          const double safe = 0.9 * eta * eta;
-          if (safe > 0.1) e = std::max(e, safe);
-          const double floor = 0.5 * o.fwd_rel_tol * std::sqrt(m->h_st[0].r0sq) / gk;
-          eta = std::min(eta_max, std::max(e, floor));
+      double eta = eta_max, g_prev = -1.0;
+      for (outer = 0;; ++outer) {
+        if ((rc = read_state(m, s)) != DPD_OK) return rc;
+        if (m->h_st[0].done || solves >= max_it) break;
+        if (adaptive) {
+          const double gk = std::sqrt(m->h_st[0].rsq);
+          if (g_prev > 0.0 && gk > 0.0) {
+            double e = 0.9 * (gk / g_prev) * (gk / g_prev);
+            const double safe = 0.9 * eta * eta;
+            if (safe > 0.1) e = std::max(e, safe);
+            const double floor = 0.5 * o.fwd_rel_tol * std::sqrt(m->h_st[0].r0sq) / gk;
+            eta = std::min(eta_max, std::max(e, floor));
+          }
+          g_prev = gk;
         }
-        g_prev = gk;
+        launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
+        const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
+        launch_reset(s, inner, eta * eta, inner_max);
+        launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
+        if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
+            DPD_OK)
+          return rc;
+        if ((rc = read_state(m, s)) != DPD_OK) return rc;
+        solves += std::max(1, m->h_st[1].iter);
+        if (m->h_st[1].curvature) {
+          // not a descent direction: take one plain PD step instead
+          solve(m, s, fp32, m->r, xn, -1.0, 1, nullptr);
+        } else {
+          launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
+        }
+        {
+          ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
+          launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+        }
+        launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
       }
-      launch_adj_cache(m->dm, s, xn, act, m->cache, nullptr);
-      const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
-      launch_reset(s, inner, eta * eta, inner_max);
-      launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
-      if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
-          DPD_OK)
-        return rc;
-      if ((rc = read_state(m, s)) != DPD_OK) return rc;
-      solves += std::max(1, m->h_st[1].iter);
-      if (m->h_st[1].curvature) {
-        // not a descent direction: take one plain PD step instead
-        solve(m, s, fp32, m->r, xn, -1.0, 1, nullptr);
-      } else {
-        launch_lincomb(s, n3, xn, 1.0, xn, 1.0, m->z);
-      }
-      {
-      ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0);
-      launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
-    }
-      launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, m->st, m->partials, outer + 1, never, 0);
-    }
     }
   }
   for (int k = 0; solves < 0; ++k) {

@@ -101,18 +101,25 @@ struct DenseCG {
   uint32_t* bar;              // [kDenseBarWords] barrier counters and abort flag
 };
 
+void launch_hold(hipStream_t s, int periods);
+
 // Kernel timing: when start/stop events are set, the next launch made with
-// DPD_LAUNCH records them at its own dispatch start and completion
-// (hipExtLaunchKernelGGL), so the measured time is the kernel's alone.
+// DPD_LAUNCH records them around its dispatch (hipExtLaunchKernelGGL).  A
+// bounded hold kernel (hold periods of s_sleep) goes directly ahead of that
+// dispatch, so the GPU reaches the start event and the kernel back to back
+// (the host's enqueue time is not counted) and no other kernel of the same
+// launcher (a gather pass) runs between them.
 struct LaunchEvents {
   hipEvent_t start = nullptr, stop = nullptr;
   bool used = false;
+  int hold = 0;
 };
 extern thread_local LaunchEvents g_launch_events;
 
 #define DPD_LAUNCH(kernel, grid, block, shmem, stream, ...)                                        \
   do {                                                                                             \
     if (::dpd::g_launch_events.start) {                                                            \
+      if (::dpd::g_launch_events.hold > 0) ::dpd::launch_hold(stream, ::dpd::g_launch_events.hold); \
       hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ::dpd::g_launch_events.start,      \
                             ::dpd::g_launch_events.stop, 0, __VA_ARGS__);                          \
       ::dpd::g_launch_events.start = nullptr;                                                      \
@@ -130,7 +137,6 @@ namespace dpd {
 void launch_lincomb(hipStream_t s, int64_t n, double* out, double a, const double* x, double b,
                     const double* y);
 void launch_fill(hipStream_t s, int64_t n, double* out, double v);
-void launch_hold(hipStream_t s, int periods);
 void launch_reset(hipStream_t s, IterState* st, double tolsq, int max_iter);
 void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const double* v, double* y,
                      double* xn, IterState* st, double* partials, double abs_tol_rel);

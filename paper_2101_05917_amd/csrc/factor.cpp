@@ -412,10 +412,12 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
       const double nc = sn.ncols, nr = sn.nrows, nnz = nc * (nc + 1) / 2 + nr * nc;
       double contribs = 0;
       for (int32_t j = sn.col0; j < sn.col0 + sn.ncols; ++j) contribs += S.cptr[j + 1] - S.cptr[j];
-      // forward: panel, b_s and incoming updates read, y_s and outgoing updates written
-      // (pre-gathered levels read the gathered b~_s instead: the gather pass
-      // is timed with its level)
-      P.fwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + contribs) + 24.0 * (nc + nr) + 4.0 * contribs;
+      // forward: panel, b_s and incoming updates read, y_s and outgoing updates written;
+      // a pre-gathered level's sweep kernel reads the gathered b~_s instead (the
+      // gather pass, a kernel of its own, moves the updates)
+      const bool pre = P.gather_off[l + 1] > P.gather_off[l];
+      P.fwd_bytes[l] += pre ? 8.0 * nnz + 24.0 * nc + 24.0 * (nc + nr)
+                            : 8.0 * nnz + 24.0 * (nc + contribs) + 24.0 * (nc + nr) + 4.0 * contribs;
       // backward: panel, y_s and x_R read, x_s written (internal and public copies)
       P.bwd_bytes[l] += 8.0 * nnz + 24.0 * (nc + nr) + 4.0 * nr + 48.0 * nc;
       P.fwd_flops[l] += 6.0 * nnz;

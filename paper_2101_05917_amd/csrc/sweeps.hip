@@ -10,7 +10,7 @@
 //   backward  x_s = P_s^T [y_s; x_R].
 // Updates are gathered by their consumer in a fixed order (no atomics).
 //
-// Each kernel launch processes one level; a task (256 threads) is one block
+// Each kernel launch processes one level; a task (one workgroup) is one block
 // of rows or columns of one supernode.
 #include <hip/hip_runtime.h>
 
