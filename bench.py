@@ -325,6 +325,13 @@ def main():
     if args.roofline_kernel == "cg_dense":
         roofline["timing"] = ("every launch of the timed region, by its own device clock (s_memrealtime, "
                               "100 MHz) from workgroup 0's entry to its exit, accumulated on the device")
+    elif args.roofline_kernel == "solve":
+        roofline["timing"] = "one solve in 17, HIP events around its launches behind a bounded stream hold"
+    else:
+        roofline["timing"] = ("every launch made outside graphs in the timed region (the conjugate-gradient "
+                              "loop replays one chunk of iterations in 17 as direct launches), by the device "
+                              "clock (s_memrealtime, 100 MHz) from workgroup 0's entry to the last workgroup's "
+                              "exit, accumulated on the device")
 
     # accuracy against the oracle's reference gradient
     err = None

@@ -222,16 +222,24 @@ dpd_status dpd_hessian_apply(dpd_mesh* mesh, void* stream, const double* x, cons
 dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* R_out);
 
 /* Kernel timing for roofline measurement.  After dpd_profile_start(mesh, k),
- * every launch of kernel class k made by calls on this handle is bracketed by
- * HIP events recorded on the launch stream, and the algorithmic bytes and
- * flops of that launch (what the method must move or compute, from the factor
- * structure and the mesh) are added up.  dpd_profile_read synchronizes the
- * stream, returns the totals since the start and stops timing.  One launch
- * in every 16 of the class is timed (two event records each), so the totals
- * describe that sample; launches that exit early because their iteration had
- * already converged are not counted.  Launches of DPD_PROF_CG_DENSE (each a
- * whole solve of varying length) are all timed.  Class DPD_PROF_OFF disables
- * timing. */
+ * launches of kernel class k made by calls on this handle are timed and the
+ * algorithmic bytes and flops of each timed launch (what the method must move
+ * or compute, from the factor structure and the mesh) are added up;
+ * dpd_profile_read synchronizes the stream, returns the totals since the start
+ * and stops timing.  Launches that exit at once because their iteration had
+ * already converged are not counted.
+ *  - Single-kernel classes (sweeps, local steps): every launch outside graph
+ *    capture is timed on the device by the constant-rate clock
+ *    (hipDeviceAttributeWallClockRate): from the entry of workgroup 0 to the
+ *    exit of the last workgroup to finish.  While such a class is profiled,
+ *    the conjugate-gradient loop replays one chunk of iterations in every 17
+ *    as direct launches (the rest as graphs), so the totals describe those.
+ *  - DPD_PROF_SOLVE: one whole A^{-1} b in every 17 is bracketed by events on
+ *    the launch stream behind a bounded stream hold.
+ *  - DPD_PROF_CG_DENSE: every fused solve, by its own device clock
+ *    (workgroup 0 at entry and at exit).
+ * Class DPD_PROF_OFF disables timing.  Profiling one handle from several
+ * streams at once is not supported. */
 enum {
   DPD_PROF_OFF = 0,
   DPD_PROF_SWEEP_FWD = 1,        /* k_sweep_fwd: forward level, blocks of <= 64 columns     */
@@ -245,17 +253,13 @@ enum {
 };
 typedef struct {
   int64_t launches;
-  double total_ms;         /* summed durations: event pairs on the launch stream;
-                              for DPD_PROF_CG_DENSE the launch's own device clock
-                              (workgroup 0 at entry and at exit), because the
-                              events around a cooperative launch also bracket the
-                              host's enqueue time                              */
+  double total_ms;         /* summed durations of the timed launches (device
+                              clock; event pairs for DPD_PROF_SOLVE)           */
   double bytes;            /* summed algorithmic bytes                           */
   double flops;            /* summed algorithmic floating-point operations       */
   int64_t iterations;      /* device-side iterations of the timed launches (class
                               DPD_PROF_CG_DENSE), else 0                         */
-  double event_ms;         /* summed event-pair durations (= total_ms except for
-                              DPD_PROF_CG_DENSE)                                 */
+  double event_ms;         /* summed event-pair durations (DPD_PROF_SOLVE), else 0 */
 } dpd_kernel_profile;
 dpd_status dpd_profile_start(dpd_mesh* mesh, int32_t kernel_class);
 dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* out);

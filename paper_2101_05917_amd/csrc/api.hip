@@ -26,8 +26,7 @@ constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of t
 constexpr int32_t kSepMax = 2048;
 constexpr int64_t kLdsBudget = 60 * 1024;
 constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
-constexpr int kHoldPeriods = 8;         // about 25 us of s_sleep ahead of one timed kernel
-constexpr int kHoldPeriodsAround = 40;  // about 130 us ahead of a timed multi-launch solve
+constexpr int kHoldPeriodsAround = 40;  // about 130 us of s_sleep ahead of a timed multi-launch solve
 constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
 constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before the first check
 constexpr int kNewtonMore = 2;   // ... and per later check
@@ -39,10 +38,6 @@ struct TimedLaunch {
   double bytes, flops;
   int st_idx, k;
   bool strict;
-  // a launch that iterates on the device: bytes and flops per iteration,
-  // multiplied at harvest by the iteration count of state iter_state
-  int iter_state = -1;
-  double iter_bytes = 0.0, iter_flops = 0.0;
 };
 
 struct dpd_mesh {
@@ -92,6 +87,7 @@ struct dpd_mesh {
   double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0, prof_event_ms = 0.0;
   double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
   ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
+  LaunchClock* prof_clock = nullptr;  // device-side timing of the single-kernel classes
 };
 
 namespace {
@@ -137,33 +133,39 @@ void free_dev(dpd_mesh* m, void* p) {
   (void)hipFree(p);
 }
 
-// Bracket one launch of kernel class cls with events when it is being timed.
-// A launch inside an iteration is tagged with its iteration k and the state
-// (0 outer, 1 inner) that gates it; kernels enqueued after the iteration
-// converged exit at once, and such launches are dropped when harvested.
+// Time one launch of kernel class cls when that class is being profiled.
+// Single-kernel classes: every launch outside graph capture carries the
+// handle's device-side clock and its algorithmic work (DPD_LAUNCH passes them
+// to the kernel, which stamps itself).  A whole solve (several launches): one
+// in every kProfStride is bracketed by events behind a bounded stream hold; it
+// is tagged with its iteration k and the state (0 outer, 1 inner) that gates
+// it, and dropped when harvested if the iteration had converged before it.
+// (The fused solver times itself: cg_dense_async.)
 struct ProfScope {
   dpd_mesh* m;
   hipStream_t s;
-  bool on, around;
+  bool on, clocked = false;
   TimedLaunch t{};
   ProfScope(dpd_mesh* mm, hipStream_t ss, int32_t cls, double bytes, double flops, int st_idx = -1,
             int k = 0, bool strict = true)
-      : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF && !mm->capturing),
-        around(cls == DPD_PROF_SOLVE || cls == DPD_PROF_CG_DENSE) {
+      : m(mm), s(ss), on(mm->prof_class == cls && cls != DPD_PROF_OFF && cls != DPD_PROF_CG_DENSE &&
+                         !mm->capturing) {
     if (!on) return;
-    // Short kernels: time one launch in every kProfStride, behind a bounded
-    // stream hold (below).  The fused solver's launches run for hundreds of
-    // microseconds and their work differs from launch to launch (the number of
-    // iterations), so every one of them is timed, without a hold: the host's
-    // enqueue delay is then a few percent of a launch.
-    const bool every = cls == DPD_PROF_CG_DENSE;
-    on = every || (m->prof_seen++ % kProfStride) == 0;
+    if (cls != DPD_PROF_SOLVE) {
+      on = false;
+      if (m->prof_clock) {
+        g_launch_clock = ClockArg{m->prof_clock, bytes, flops};
+        clocked = true;
+      }
+      return;
+    }
+    on = (m->prof_seen++ % kProfStride) == 0;
     if (!on) return;
     if (m->ev_free.empty()) {
       hipEvent_t a = nullptr, b = nullptr;
       // timing-only events: no system-scope fence (cache writeback and
-      // invalidate) when they are recorded, which would lengthen the kernel
-      // they bracket; they are read after a stream synchronisation
+      // invalidate) when they are recorded; they are read after a stream
+      // synchronisation
       const unsigned fl = hipEventDisableSystemFence;
       if (hipEventCreateWithFlags(&a, fl) != hipSuccess || hipEventCreateWithFlags(&b, fl) != hipSuccess) {
         on = false;
@@ -178,30 +180,16 @@ struct ProfScope {
     t.st_idx = st_idx;
     t.k = k;
     t.strict = strict;
-    // Hold the stream while the timed launch and its events are enqueued, so
-    // the GPU reaches them back to back and the host's enqueue time between
-    // the start event and the kernel is not counted.  A single timed kernel
-    // gets its hold from DPD_LAUNCH, directly ahead of its own dispatch.
-    if (around) {
-      if (!every) launch_hold(s, kHoldPeriodsAround);
-      (void)hipEventRecord(t.ev.first, s);  // several launches: bracket them in the stream
-    } else {
-      g_launch_events = {t.ev.first, t.ev.second, false, kHoldPeriods};  // one kernel
-    }
+    // Hold the stream while the solve's launches are enqueued, so the GPU
+    // reaches them back to back and the host's enqueue time is not counted.
+    launch_hold(s, kHoldPeriodsAround);
+    (void)hipEventRecord(t.ev.first, s);
   }
   ~ProfScope() {
+    if (clocked) g_launch_clock = ClockArg{};
     if (!on) return;
-    bool timed = true;
-    if (around) {
-      (void)hipEventRecord(t.ev.second, s);
-    } else {
-      timed = g_launch_events.used;
-      g_launch_events = {};
-    }
-    if (timed)
-      m->ev_pending.push_back(t);
-    else
-      m->ev_free.push_back(t.ev);
+    (void)hipEventRecord(t.ev.second, s);
+    m->ev_pending.push_back(t);
   }
 };
 
@@ -223,12 +211,6 @@ void prof_harvest(dpd_mesh* m) {
       m->prof_launches += 1;
       m->prof_bytes += t.bytes;
       m->prof_flops += t.flops;
-      if (t.iter_state >= 0) {
-        const double it = m->h_st[t.iter_state].iter;
-        m->prof_iters += m->h_st[t.iter_state].iter;
-        m->prof_bytes += it * t.iter_bytes;
-        m->prof_flops += it * t.iter_flops;
-      }
     }
     m->ev_free.push_back(t.ev);
   }
@@ -1249,6 +1231,12 @@ dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
       if (st != DPD_OK) return st;
     }
     HIPCHECK(m, hipMemset(m->prof_acc, 0, sizeof(ProfAcc)));
+  } else if (kernel_class != DPD_PROF_OFF && kernel_class != DPD_PROF_SOLVE) {
+    if (!m->prof_clock) {
+      dpd_status st = dev_alloc(m, &m->prof_clock, 1);
+      if (st != DPD_OK) return st;
+    }
+    HIPCHECK(m, hipMemset(m->prof_clock, 0, sizeof(LaunchClock)));
   }
   m->prof_class = kernel_class;
   m->prof_launches = 0;
@@ -1274,6 +1262,14 @@ dpd_status dpd_profile_read(dpd_mesh* m, void* stream, dpd_kernel_profile* out) 
     m->prof_bytes = (double)a.launches * dense_matvec_bytes(m, fp32) + (double)a.iters * dense_iter_bytes(m, fp32);
     m->prof_flops = (double)a.launches * 6.0 * n * n +
                     (double)a.iters * (6.0 * n * n + 600.0 * 8.0 * (double)m->hm.n_elems);
+  } else if (m->prof_class != DPD_PROF_OFF && m->prof_class != DPD_PROF_SOLVE && m->prof_clock) {
+    LaunchClock c{};
+    HIPCHECK(m, hipMemcpy(&c, m->prof_clock, sizeof(LaunchClock), hipMemcpyDeviceToHost));
+    m->prof_launches = (int64_t)c.launches;
+    m->prof_ms = (double)c.ticks / m->clock_khz;
+    m->prof_event_ms = 0.0;
+    m->prof_bytes = c.bytes;
+    m->prof_flops = c.flops;
   }
   out->launches = m->prof_launches;
   out->iterations = m->prof_iters;

@@ -1,7 +1,6 @@
 // Device-side data of one mesh and the kernel launchers (internal).
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -103,32 +102,53 @@ struct DenseCG {
 
 void launch_hold(hipStream_t s, int periods);
 
-// Kernel timing: when start/stop events are set, the next launch made with
-// DPD_LAUNCH records them around its dispatch (hipExtLaunchKernelGGL).  A
-// bounded hold kernel (hold periods of s_sleep) goes directly ahead of that
-// dispatch, so the GPU reaches the start event and the kernel back to back
-// (the host's enqueue time is not counted) and no other kernel of the same
-// launcher (a gather pass) runs between them.
-struct LaunchEvents {
-  hipEvent_t start = nullptr, stop = nullptr;
-  bool used = false;
-  int hold = 0;
+// Device-side timing of the launches of one kernel class while it is being
+// profiled, by the constant 100 MHz clock of s_memrealtime (the same on every
+// XCD): workgroup 0 subtracts its entry time from the total and the last
+// workgroup to finish adds its exit time (two additions to one counter, so
+// their order does not matter), then counts the launch and its work.
+// Launches that exit at once because their iteration has already finished
+// stamp nothing.  Launches of one class on one handle run in stream order, so
+// one record serves them all.
+struct LaunchClock {
+  unsigned long long ticks, launches;
+  double bytes, flops;          // algorithmic work of the counted launches
+  unsigned int arrived, pad;    // workgroups of the launch in flight that have finished
 };
-extern thread_local LaunchEvents g_launch_events;
+struct ClockArg {
+  LaunchClock* c;               // null: not timed
+  double bytes, flops;          // algorithmic work of this launch
+};
+extern thread_local ClockArg g_launch_clock;
+inline ClockArg take_launch_clock() {
+  const ClockArg a = g_launch_clock;
+  g_launch_clock = ClockArg{};
+  return a;
+}
 
-#define DPD_LAUNCH(kernel, grid, block, shmem, stream, ...)                                        \
-  do {                                                                                             \
-    if (::dpd::g_launch_events.start) {                                                            \
-      if (::dpd::g_launch_events.hold > 0) ::dpd::launch_hold(stream, ::dpd::g_launch_events.hold); \
-      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ::dpd::g_launch_events.start,      \
-                            ::dpd::g_launch_events.stop, 0, __VA_ARGS__);                          \
-      ::dpd::g_launch_events.start = nullptr;                                                      \
-      ::dpd::g_launch_events.used = true;                                                          \
-    } else {                                                                                       \
-      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                         \
-    }                                                                                              \
-  } while (0)
+// Launch of a kernel whose last parameter is a ClockArg: the clock set for the
+// next launch of its class (by the profiler's scope), else none.
+#define DPD_LAUNCH(kernel, grid, block, shmem, stream, ...) \
+  hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__, ::dpd::take_launch_clock())
 
+__device__ inline void clock_enter(const ClockArg& ck) {
+  if (ck.c && blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd(&ck.c->ticks, 0ull - (unsigned long long)wall_clock64());
+}
+
+// Every thread of the workgroup calls this last (it holds a workgroup barrier).
+__device__ inline void clock_exit(const ClockArg& ck) {
+  if (!ck.c) return;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const unsigned int n = gridDim.x * gridDim.y * gridDim.z;
+  if (atomicAdd(&ck.c->arrived, 1u) != n - 1) return;
+  atomicAdd(&ck.c->ticks, (unsigned long long)wall_clock64());
+  atomicAdd(&ck.c->launches, 1ull);
+  atomicAdd(&ck.c->bytes, ck.bytes);
+  atomicAdd(&ck.c->flops, ck.flops);
+  atomicExch(&ck.c->arrived, 0u);
+}
 
 }  // namespace dpd
 

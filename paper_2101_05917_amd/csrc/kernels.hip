@@ -24,7 +24,7 @@
 
 namespace dpd {
 
-thread_local LaunchEvents g_launch_events;
+thread_local ClockArg g_launch_clock;
 
 // ------------------------------------------------------------------ forward local step
 
@@ -32,8 +32,9 @@ __global__ void __launch_bounds__(kBlock) k_elem_forces(DevMesh M, const double*
                                                         const double* __restrict__ act,
                                                         double* __restrict__ fe,
                                                         double* __restrict__ R_out,
-                                                        IterState* st) {
+                                                        IterState* st, ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   __shared__ ElemTile T;
   const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
   const int e = blockIdx.x * kElemsPerBlock + le;
@@ -85,6 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_forces(DevMesh M, const double*
   }
   __syncthreads();
   element_forces_out(M, T, le, q, e, valid, G, fe);
+  clock_exit(ck);
 }
 
 
@@ -270,8 +272,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
 
 __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
                                                      const double* __restrict__ cache,
-                                                     double* __restrict__ fe, const IterState* st) {
+                                                     double* __restrict__ fe, const IterState* st,
+                                                     ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   __shared__ ElemTile T;
   const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
   const int e = blockIdx.x * kElemsPerBlock + le;
@@ -282,6 +286,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __
   if (valid) hvp_stress(M, T, le, q, e, G, cache);
   __syncthreads();
   element_forces_out(M, T, le, q, e, valid, G, fe);
+  clock_exit(ck);
 }
 
 // out = (A - dA) p (- rhs if given); mode 0: plain; mode 1: out = H p - rhs and

@@ -331,20 +331,24 @@ __device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, co
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTask* __restrict__ tasks,
                                                       const T* __restrict__ panel, const double* __restrict__ b,
-                                                      int N, const IterState* st) {
+                                                      int N, const IterState* st, ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   extern __shared__ double lds[];
   fwd_narrow_task<T>(S, tasks[blockIdx.x], panel, b, N, true, threadIdx.x, lds);
+  clock_exit(ck);
 }
 
 template <typename T, int LPR>
 __global__ void __launch_bounds__(kWideTaskThreads) k_sweep_fwd_wide(DevSolve S, const SweepTask* __restrict__ tasks,
                                                                      const T* __restrict__ panelT,
                                                                      const double* __restrict__ b, int N, int pre,
-                                                                     const IterState* st) {
+                                                                     const IterState* st, ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   extern __shared__ double lds[];
   fwd_wide_task<T, LPR, kWideTaskThreads>(S, tasks[blockIdx.x], panelT, b, N, pre != 0, true, threadIdx.x, lds);
+  clock_exit(ck);
 }
 
 // Right-hand sides of one level with the descendants' updates added, once per
@@ -380,21 +384,25 @@ template <typename T, bool kLds, int LPR>
 __global__ void __launch_bounds__(kWideTaskThreads) k_sweep_bwd(DevSolve S, const SweepTask* __restrict__ tasks,
                                                                 const T* __restrict__ panel,
                                                                 double* __restrict__ out, int N, double alpha,
-                                                                int accumulate, const IterState* st) {
+                                                                int accumulate, const IterState* st, ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   extern __shared__ double lds[];
   bwd_cols_task<T, kLds, LPR, kWideTaskThreads>(S, tasks[blockIdx.x], panel, out, N, alpha, accumulate, true,
                                                 threadIdx.x, lds);
+  clock_exit(ck);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sweep_bwd_narrow(DevSolve S, const SweepTask* __restrict__ tasks,
                                                              const T* __restrict__ panelT,
                                                              double* __restrict__ out, int N, double alpha,
-                                                             int accumulate, const IterState* st) {
+                                                             int accumulate, const IterState* st, ClockArg ck) {
   if (st && st->done) return;
+  clock_enter(ck);
   extern __shared__ double lds[];
   bwd_narrow_task<T>(S, tasks[blockIdx.x], panelT, out, N, alpha, accumulate, true, threadIdx.x, lds);
+  clock_exit(ck);
 }
 
 }  // namespace

@@ -240,7 +240,7 @@ class Mesh:
 
     # ------------------------------------------------------------------ timing
     def profile_start(self, kernel_class: str):
-        """Time every launch of one kernel class with HIP events (see dpd_profile_start)."""
+        """Time the launches of one kernel class (device clock or events, see dpd_profile_start)."""
         L.check(self.lib.dpd_profile_start(self.handle, L.DPD_PROF[kernel_class]), self.handle)
 
     def profile_read(self) -> dict:

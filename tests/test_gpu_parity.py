@@ -352,3 +352,40 @@ def test_forward_newton_eisenstat_walker(name):
     assert st["converged"] == 1
     xr = converged_state(o, x, v, act)
     assert np.linalg.norm(soa(xn) - xr) <= 1e-9 * np.linalg.norm(xr - x)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_profiling_leaves_results_unchanged_and_times_every_class(fused):
+    """Kernel timing (device clocks in the kernels, events around solves)
+    changes no result bit, and every class that ran reports a plausible
+    per-launch duration and nonzero algorithmic bytes."""
+    sc = wide_beam()
+    kw = dict(fwd_solver="newton_pcg", fused_cg=fused, fwd_rel_tol=1e-10, bwd_rel_tol=1e-10,
+              fwd_max_iter=100000, bwd_max_iter=100000)
+    g, o = pair(sc, **kw)
+    x, v = _perturbed(o, seed=41)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    gxn = to_dev(np.random.default_rng(41).standard_normal(3 * o.N), o.N)
+    ref_f = g.forward_step(xd, vd, None)
+    ref_b = g.backward_step(xd, vd, None, ref_f[0], gxn, torch.zeros_like(gxn))
+    classes = ["sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow", "elem_hvp", "elem_forces",
+               "solve", "cg_dense"]
+    ran = {}
+    for cls in classes:
+        g.profile_start(cls)
+        f = g.forward_step(xd, vd, None)
+        b = g.backward_step(xd, vd, None, f[0], gxn, torch.zeros_like(gxn))
+        prof = g.profile_read()
+        print(cls, prof, flush=True)
+        assert torch.equal(f[0], ref_f[0]) and torch.equal(b[0], ref_b[0]) and torch.equal(b[1], ref_b[1])
+        if prof["launches"]:
+            us = 1e3 * prof["total_ms"] / prof["launches"]
+            assert 0.2 < us < 1e5, (cls, us)
+            assert prof["bytes"] > 0
+        ran[cls] = prof["launches"]
+    assert ran["elem_forces"] > 0 and ran["elem_hvp"] + ran["cg_dense"] > 0
+    if fused:
+        assert ran["cg_dense"] > 0
+    else:
+        assert ran["solve"] > 0
+        assert sum(ran[c] for c in classes if c.startswith("sweep")) > 0
