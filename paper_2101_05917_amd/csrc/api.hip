@@ -389,6 +389,20 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
       eoff[b + 1] = (int32_t)elems.size();
       max_e = std::max(max_e, (int)list.size());
     }
+    // the workgroups whose rows of s workgroup b reads at its element corners
+    std::vector<int32_t> nbr_off(G + 1, 0), nbr;
+    for (int b = 0; b < G; ++b) {
+      std::vector<int32_t> owners;
+      for (int i = eoff[b]; i < eoff[b + 1]; ++i)
+        for (int a = 0; a < 8; ++a) {
+          const int32_t row = inv[hm.conn[(size_t)8 * elems[i] + a]];
+          if (row >= 0 && row / R != b) owners.push_back(row / R);
+        }
+      std::sort(owners.begin(), owners.end());
+      owners.erase(std::unique(owners.begin(), owners.end()), owners.end());
+      nbr.insert(nbr.end(), owners.begin(), owners.end());
+      nbr_off[b + 1] = (int32_t)nbr.size();
+    }
     // What lives in LDS, per precision of A^{-1}, in order of preference: the
     // full r and q and the workgroup's rows of A^{-1}; r and q alone; the rows
     // alone; neither.  The first that fits with one workgroup per CU wins
@@ -409,17 +423,18 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
     d.max_elems = max_e;
     d.mode64 = mode[0];
     d.mode32 = mode[1];
-    int32_t *dinv, *deoff, *delems, *drinc;
+    int32_t *dinv, *deoff, *delems, *drinc, *dnoff, *dnbr;
     double *r, *q, *p, *sv, *w, *z, *part;
-    uint32_t* bar;
+    uint32_t *bar, *ready;
     dpd_status st;
     if ((st = upload(m, &dinv, inv)) != DPD_OK || (st = upload(m, &deoff, eoff)) != DPD_OK ||
         (st = upload(m, &delems, elems)) != DPD_OK || (st = upload(m, &drinc, row_inc)) != DPD_OK ||
+        (st = upload(m, &dnoff, nbr_off)) != DPD_OK || (st = upload(m, &dnbr, nbr)) != DPD_OK ||
         (st = dev_alloc(m, &r, 6 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &q, 6 * (int64_t)n)) != DPD_OK ||
         (st = dev_alloc(m, &p, 3 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &sv, 3 * (int64_t)n)) != DPD_OK ||
-        (st = dev_alloc(m, &w, 3 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &z, 3 * (int64_t)n)) != DPD_OK ||
+        (st = dev_alloc(m, &w, 6 * (int64_t)n)) != DPD_OK || (st = dev_alloc(m, &z, 3 * (int64_t)n)) != DPD_OK ||
         (st = dev_alloc(m, &part, 4 * (int64_t)G)) != DPD_OK || (st = dev_alloc(m, &bar, kDenseBarWords)) != DPD_OK ||
-        (st = dev_alloc(m, &m->ainv64, (int64_t)n * n)) != DPD_OK)
+        (st = dev_alloc(m, &ready, G)) != DPD_OK || (st = dev_alloc(m, &m->ainv64, (int64_t)n * n)) != DPD_OK)
       return st;
     d.perm = m->ds.perm_pub;
     d.inv = dinv;
@@ -434,6 +449,9 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
     d.z = z;
     d.part = part;
     d.bar = bar;
+    d.ready = ready;
+    d.nbr_off = dnoff;
+    d.nbr = dnbr;
     d.ainv64 = m->ainv64;
     m->dense_alloc = true;
   }

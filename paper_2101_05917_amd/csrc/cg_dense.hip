@@ -12,19 +12,25 @@
 //   z_{k+1} = z_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k q_k.
 // What changes is the schedule: the launch-per-kernel path spends most of its
 // time between kernels at these sizes, so here every workgroup stays resident
-// and two grid barriers separate the phases of an iteration:
+// and an iteration has two phases:
 //   phase 1 (k+1): every workgroup forms r_{k+1} for all rows in LDS from the
-//       previous phase's vectors (no barrier needed for the update), the owner
-//       of a row stores it with p, q and z, and then multiplies its rows of
-//       A^{-1} (read once per iteration, coalesced) by r_{k+1};
+//       previous phase's vectors (no barrier needed for the update) and
+//       |r_{k+1}|^2 from them (the same sum, in the same order, everywhere),
+//       the owner of a row stores it with p, q and z, and then multiplies its
+//       rows of A^{-1} (read once per iteration, coalesced) by r_{k+1};
 //   phase 2 (k): the stopping test on |r_k|^2, then H s_k on the owned rows:
 //       the hex elements around them are evaluated in LDS (8 lanes per
 //       element), their corner forces gathered per node in the same fixed
 //       incidence order as the multi-launch kernels, and the two partial inner
 //       products are published.
-// Reductions are deterministic: every workgroup adds the published partials in
-// the same order.  Residuals and q alternate between two buffers, so that no
-// workgroup overwrites a vector another one may still read in the same phase.
+// Phase 2 needs s_k only at the corners of the workgroup's elements, so
+// between phase 1 and phase 2 a workgroup publishes its rows of s (a ready
+// count per workgroup) and waits only for the workgroups that own rows at its
+// corners; phase 1 needs w_k and the partial products of every workgroup, so a
+// grid barrier follows phase 2.  Reductions are deterministic: every workgroup
+// adds the published partials in the same order.  r, q, w and the partials
+// alternate between two buffers, so that no workgroup overwrites a vector
+// another one may still read.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -86,6 +92,38 @@ __device__ inline bool grid_barrier(uint32_t* bar, uint32_t& round) {
       __builtin_amdgcn_s_sleep(1);
     }
     ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Publication of s without a grid barrier: once its rows of s are stored, the
+// workgroup waits until its own stores have completed and raises its ready
+// count to seq, then waits until the ready counts of the nnb workgroups in nbr
+// (the owners of rows at its element corners) reach seq.  The wait is bounded
+// like the barrier's and shares its abort flag.  Returns false after an abort.
+__device__ inline bool publish_wait(uint32_t* ready, const int32_t* __restrict__ nbr, int nnb, uint32_t seq,
+                                    uint32_t* bar) {
+  __shared__ int ok;
+  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&ready[blockIdx.x], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = 1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nnb; i += blockDim.x) {
+    const int w = nbr[i];
+    for (uint32_t spin = 0;; ++spin) {
+      if (__hip_atomic_load(&ready[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= seq) break;
+      if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spin >= kSpinLimit) {
+        __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   __syncthreads();
   return ok != 0;
@@ -267,8 +305,10 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   const int max_iter = st->max_iter;
   const GradTable G = grad_table(M.dx);
   const uint64_t clk0 = wall_clock64();
-  uint32_t round = 0;
+  uint32_t round = 0, pub = 0;
   bool alive = true;
+  const int32_t* nbrs = D.nbr + D.nbr_off[b];
+  const int nnb = D.nbr_off[b + 1] - D.nbr_off[b];
   if (tid < 8 * 8 * 3) {
     const int q = tid / 24, a0 = (tid / 3) % 8, jj = tid % 3;
     gt[tid] = bgrad(q, jj, a0, G);
@@ -307,7 +347,6 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     for (int i = tid; i < R * n; i += kDenseBlock) arows[i] = ainv[(int64_t)j0 * n + i];
   const T* my_rows = kAinvLds ? arows : ainv + (int64_t)j0 * n;
   __syncthreads();
-  double acc = 0.0;
   if (tid < 3 * R) {
     const int c = tid / R, i = tid % R, j = j0 + i;
     const double v = rv[c * n + j];
@@ -319,21 +358,20 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
     own_r[c * MR + i] = v;
     own_p[c * MR + i] = 0.0;
     own_z[c * MR + i] = 0.0;
-    acc = v * v;
   }
-  acc = block_sum(acc, ws);
-  if (tid == 0) st_dev(&D.part[4 * b + 2], acc);
+  double acc = 0.0;
+  for (int i = tid; i < 3 * n; i += kDenseBlock) acc += rv[i] * rv[i];
+  double rsq_next = block_all(acc, ws, &bc);   // |r_0|^2, the same bits in every workgroup
   dense_rows<T>(my_rows, n, rv, j0, R, D.s, own_s);
   if (tid < 3 * MR) own_s0[tid] = own_s[tid];
-  alive = grid_barrier(D.bar, round);
+  alive = publish_wait(D.ready, nbrs, nnb, ++pub, D.bar);
 
   double nb2 = 0.0, rsq = 0.0, rs_old = 0.0, alpha_old = 0.0, alpha = 0.0, beta = 0.0;
   int k = 0, converged = 0, nonfinite = 0, curvature = 0;
   for (; alive; ++k) {
-    // ---- phase 2 (k): one round of device-coherent loads (the |r_k|^2
-    // partials and s_k at the workgroup's element corners), the stopping test,
-    // then w_k = H s_k on the own rows and the two inner products
-    const double pr = tid < G_ ? ld_dev(&D.part[4 * tid + 2]) : 0.0;
+    // ---- phase 2 (k): one round of device-coherent loads (s_k at the
+    // workgroup's element corners), the stopping test, then w_k = H s_k on the
+    // own rows and the two inner products
     // cache entries of this lane's Gauss point: read-only and L2-resident,
     // loaded in the same round as the device-coherent loads below; the index
     // is made opaque to the compiler so that it does not keep 19 loop-invariant
@@ -355,7 +393,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
         sv2 = ld_dev(&D.s[2 * n + row]);
       }
     }
-    rsq = block_all(pr, ws, &bc);
+    rsq = rsq_next;
     if (k == 0) nb2 = rsq;
     if (!isfinite(rsq)) {
       nonfinite = 1;
@@ -406,24 +444,26 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       o1 += cm * s1;
       o2 += cm * s2;
       o2 += row_k[tid] * s2;
-      st_dev(&D.w[j], o0);
-      st_dev(&D.w[n + j], o1);
-      st_dev(&D.w[2 * n + j], o2);
+      double* wk = D.w + (k & 1) * 3 * n;
+      st_dev(&wk[j], o0);
+      st_dev(&wk[n + j], o1);
+      st_dev(&wk[2 * n + j], o2);
       gam = own_r[tid] * s0 + own_r[MR + tid] * s1 + own_r[2 * MR + tid] * s2;
       del = o0 * s0 + o1 * s1 + o2 * s2;
     }
     block_sum2(gam, del, ws2);   // totals in lane 0 only
     if (tid == 0) {
-      st_dev(&D.part[4 * b + 0], gam);
-      st_dev(&D.part[4 * b + 1], del);
+      st_dev(&D.part[2 * ((k & 1) * G_ + b)], gam);
+      st_dev(&D.part[2 * ((k & 1) * G_ + b) + 1], del);
     }
     if (!(alive = grid_barrier(D.bar, round))) break;
 
     // ---- phase 1 (k + 1): one round of device-coherent loads (gamma and delta
     // partials, w_k, q_{k-1}, r_k on every row), the scalars, r_{k+1} for every
     // row into LDS, the owner's updates, then s_{k+1} = A^{-1} r_{k+1}
-    const double pg = tid < G_ ? ld_dev(&D.part[4 * tid + 0]) : 0.0;
-    const double pd = tid < G_ ? ld_dev(&D.part[4 * tid + 1]) : 0.0;
+    const double pg = tid < G_ ? ld_dev(&D.part[2 * ((k & 1) * G_ + tid)]) : 0.0;
+    const double pd = tid < G_ ? ld_dev(&D.part[2 * ((k & 1) * G_ + tid) + 1]) : 0.0;
+    const double* wk = D.w + (k & 1) * 3 * n;            // w_k
     const double* qprev = D.q + ((k + 1) & 1) * 3 * n;   // q_{k-1}
     double* qcur = D.q + (k & 1) * 3 * n;                // q_k
     const double* rk = D.r + (k & 1) * 3 * n;            // r_k
@@ -435,7 +475,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       const int i = u * kDenseBlock + tid;
       wv[u] = qv[u] = rr[u] = 0.0;
       if (i < 3 * n) {
-        wv[u] = ld_dev(&D.w[i]);
+        wv[u] = ld_dev(&wk[i]);
         qv[u] = kVecLds ? ql[i] : ld_dev(&qprev[i]);
         rr[u] = kVecLds ? rv[i] : ld_dev(&rk[i]);
       }
@@ -462,7 +502,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
           const int i = base + u * kDenseBlock + tid;
           wv[u] = qv[u] = rr[u] = 0.0;
           if (i < 3 * n) {
-            wv[u] = ld_dev(&D.w[i]);
+            wv[u] = ld_dev(&wk[i]);
             qv[u] = kVecLds ? ql[i] : ld_dev(&qprev[i]);
             rr[u] = kVecLds ? rv[i] : ld_dev(&rk[i]);
           }
@@ -475,6 +515,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
           const double qi = wv[u] + beta * qv[u];
           const double ri = rr[u] - alpha * qi;
           rv[i] = ri;
+          racc += ri * ri;
           if (kVecLds) ql[i] = qi;
           const int c = (i >= n) + (i >= 2 * n), j = i - c * n;
           if (j >= j0 && j < j1) {
@@ -487,16 +528,13 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
             const double pi = own_s[o] + beta * own_p[o];
             own_p[o] = pi;
             own_z[o] += alpha * pi;
-            racc += ri * ri;
           }
         }
       }
     }
-    racc = block_sum(racc, ws);
-    if (tid == 0) st_dev(&D.part[4 * b + 2], racc);
-    __syncthreads();
+    rsq_next = block_all(racc, ws, &bc);   // |r_{k+1}|^2, the same bits in every workgroup
     dense_rows<T>(my_rows, n, rv, j0, R, D.s, own_s);
-    if (!(alive = grid_barrier(D.bar, round))) break;
+    if (!(alive = publish_wait(D.ready, nbrs, nnb, ++pub, D.bar))) break;
   }
 
   // solution rows to the public layout (fixed rows are left as they are)
@@ -524,8 +562,9 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
   }
 }
 
-__global__ void k_bar_reset(uint32_t* bar) {
+__global__ void k_bar_reset(uint32_t* bar, uint32_t* ready, int G) {
   for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) bar[i] = 0u;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) ready[i] = 0u;
 }
 
 __global__ void __launch_bounds__(kBlock) k_unit_rhs(int N, int n, const int32_t* __restrict__ perm, int j0,
@@ -597,7 +636,7 @@ int cg_dense_max_blocks(int n, int rows, int mode, bool fp32) {
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
                            double* z_out, IterState* st, ProfAcc* prof) {
-  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar);
+  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar, D.ready, blocks);
   const int mode = fp32 ? D.mode32 : D.mode64;
   const size_t lds = cg_dense_lds_bytes(D.n, D.rows, mode, fp32);
   DevMesh m = M;

@@ -94,10 +94,13 @@ struct DenseCG {
   double* q;                  // [2][3][n] H p_k (k even, odd)
   double* p;                  // [3][n]
   double* s;                  // [3][n] A^{-1} r_k
-  double* w;                  // [3][n] H s_k
+  double* w;                  // [2][3][n] H s_k (k even, odd)
   double* z;                  // [3][n] solution
-  double* part;               // [G][4] per-workgroup partial sums
+  double* part;               // [2][G][2] per-workgroup partial inner products (k even, odd)
   uint32_t* bar;              // [kDenseBarWords] barrier counters and abort flag
+  uint32_t* ready;            // [G] how many s vectors workgroup b has published in this launch
+  const int32_t* nbr_off;     // [G + 1] ranges of nbr
+  const int32_t* nbr;         // workgroups owning rows at workgroup b's element corners (b excluded)
 };
 
 void launch_hold(hipStream_t s, int periods);
