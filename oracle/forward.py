@@ -75,13 +75,18 @@ def pd_step(model, x_i, v_i, act=None, **kw):
     return x, v, info
 
 
-def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=60):
+def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=200):
     """Minimise g(x) for fixed y with Newton steps and backtracking.
 
-    Dense solves up to 1500 free DoFs, sparse LU beyond.
+    Dense solves up to 1500 free DoFs, sparse LU beyond.  Where the Hessian is
+    not positive definite (the muscle energy is not convex) the Newton step
+    need not descend; then, and when its line search finds no decrease, the
+    step is the plain PD one, -A^{-1} grad g (Alg. 1's update, a descent
+    direction since A is SPD), so the iteration stays a descent method on g.
 
-    Stops when |grad g| <= tol_rel |M y / h^2| or when the gradient norm has
-    stopped decreasing for three iterations (round-off floor reached).
+    Stops when |grad g| <= tol_rel |M y / h^2| or, once |grad g| is below
+    1e-9 |M y / h^2|, when it has stopped decreasing for three iterations
+    (round-off floor reached).
     """
     free = model.free
     x = _initial_guess(model, y) if x0 is None else x0.copy()
@@ -98,7 +103,7 @@ def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=60):
             best, stall = ng, 0
         else:
             stall += 1
-            if stall >= 3:
+            if stall >= 3 and ng <= 1e-9 * scale:
                 break
         H = model.hessian(x, act)[free][:, free]
         if H.shape[0] <= 1500:
@@ -107,16 +112,23 @@ def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=60):
             dx = -spla.spsolve(H.tocsc(), gr)
         g0 = model.g(x, y, act)
         ng0 = np.linalg.norm(gr)
-        t = 1.0
-        for _ in range(30):
-            xt = x.copy()
-            xt[free] += t * dx
-            # sufficient decrease of g, or (near round-off, where g no longer
-            # resolves the decrease) a smaller gradient
-            if model.g(xt, y, act) <= g0 + 1e-4 * t * (gr @ dx):
+        directions = [dx, -model.solve_A(gr)] if gr @ dx < 0 else [-model.solve_A(gr)]
+        for d in directions:
+            t = 1.0
+            found = False
+            for _ in range(30):
+                xt = x.copy()
+                xt[free] += t * d
+                # sufficient decrease of g, or (near round-off, where g no longer
+                # resolves the decrease) a smaller gradient
+                if model.g(xt, y, act) <= g0 + 1e-4 * t * (gr @ d):
+                    found = True
+                    break
+                if np.linalg.norm(model.grad_g(xt, y, act)[free]) < 0.5 * ng0:
+                    found = True
+                    break
+                t *= 0.5
+            if found:
                 break
-            if np.linalg.norm(model.grad_g(xt, y, act)[free]) < 0.5 * ng0:
-                break
-            t *= 0.5
         x = xt
     return x, {"iters": its, "grad": float(np.linalg.norm(model.grad_g(x, y, act)[free]))}
