@@ -42,7 +42,7 @@ KERNEL_NAMES = {"solve": "global step A^{-1} b: the per-level k_sweep_* launches
                 "elem_forces": "k_elem_forces (forward local step)"}
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed rollouts")
@@ -79,7 +79,14 @@ def parse():
     ap.add_argument("--roofline-kernel", default=None,
                     choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
                              "elem_hvp", "elem_forces"])
-    return ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def solver_options(args) -> dict:
+    """Mesh options of the timed rollouts (also used by the full-size parity tests)."""
+    return dict(fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol, fwd_inner_tol=args.fwd_inner_tol,
+                fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
+                bwd_max_iter=200000, precision=args.precision, check_every=16, fused_cg=args.fused_cg)
 
 
 def rollout(mesh, X, c_dev, T, torch, acts=None, checkpoint_every=1):
@@ -279,11 +286,7 @@ def main():
     scene = W.config(args.config)
     T = args.rollout_steps or scene.steps
     progress(f"{scene.name}: mesh set-up and factorization")
-    mesh = Mesh.from_scene(scene, fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol,
-                           fwd_inner_tol=args.fwd_inner_tol,
-                           fwd_max_iter=200000, bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol,
-                           bwd_max_iter=200000, precision=args.precision, check_every=16,
-                           fused_cg=args.fused_cg)
+    mesh = Mesh.from_scene(scene, **solver_options(args))
     if args.roofline_kernel is None:
         # the kernel with the largest share of GPU time in the rocprofv3 summary of the workload:
         # the fused conjugate-gradient launch where the mesh is small enough for it, else the

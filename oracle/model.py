@@ -25,6 +25,8 @@ central differences of g; the Hessian against central differences of grad g.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
@@ -89,16 +91,31 @@ class Model:
             self.Gm = None
             self.wm = None
 
+    # The PD matrix and its factorization are built on first use, so that the
+    # local quantities (deformation gradients, projections, grad g) of a large
+    # mesh can be evaluated without factorizing A.
+    @functools.cached_property
+    def A(self) -> sp.csr_matrix:
+        """A = M/h^2 + sum_c w_c G_c^T G_c (eq:pd_global), assembled explicitly."""
         A = sp.diags(self.Mdiag / self.h ** 2)
         A = A + self.G.T @ sp.diags(np.repeat(self.wq, 9)) @ self.G
         if self.Gm is not None:
             A = A + self.Gm.T @ sp.diags(np.repeat(self.wm, 3)) @ self.Gm
         if len(self.contact_nodes):
             A = A + self.contact_k * (self.Sc.T @ self.Sc)
-        self.A = sp.csr_matrix(A)
-        self.A_ff = sp.csc_matrix(self.A[self.free][:, self.free])
-        self.A_fc = sp.csr_matrix(self.A[self.free][:, self.fixed])
-        self._lu = spla.splu(self.A_ff)
+        return sp.csr_matrix(A)
+
+    @functools.cached_property
+    def A_ff(self) -> sp.csc_matrix:
+        return sp.csc_matrix(self.A[self.free][:, self.free])
+
+    @functools.cached_property
+    def A_fc(self) -> sp.csr_matrix:
+        return sp.csr_matrix(self.A[self.free][:, self.fixed])
+
+    @functools.cached_property
+    def _lu(self):
+        return spla.splu(self.A_ff)
 
     # ---------------------------------------------------------------- helpers
     def solve_A(self, rhs_free: np.ndarray) -> np.ndarray:

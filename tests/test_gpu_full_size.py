@@ -1,0 +1,109 @@
+"""The GPU path at the benchmark sizes, with the solver options bench.py
+times, against the oracle: the 16x8x8 cantilever (fused dense solver) and the
+64x32x32 dropped block (level-scheduled sweeps, 212 k DoFs).
+
+The oracle is not factorized here: it assembles its explicit operators (G, A,
+the Hessian) and checks what they determine without a solve -- every entry of
+grad g, every closest rotation, the residual of the global step, the stopping
+test of a forward step evaluated by the oracle, and the residual of the
+adjoint system behind a backward step.
+"""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import workloads as W
+from oracle import model as om, projections as op
+from parity_helpers import soa, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["c2", "c5"])
+def block(request):
+    from paper_2101_05917_amd.mesh import Mesh
+    sc = W.config(request.param)
+    args = bench.parse(["--config", request.param])
+    g = Mesh.from_scene(sc, **bench.solver_options(args))
+    o = om.Model(sc)
+    print(request.param, g.info, flush=True)
+    return sc, args, g, o
+
+
+def _state(o, seed):
+    """Small seeded perturbations of the rest state (the dropped block is moved
+    down onto the ground first, so that its bottom layer straddles z = 0 and
+    ground contact is active); Dirichlet nodes stay at rest."""
+    rng = np.random.default_rng(seed)
+    x = o.X.copy()
+    x[2::3] -= o.scene.origin[2]
+    x += 1e-4 * rng.standard_normal(3 * o.N)
+    v = 0.02 * rng.standard_normal(3 * o.N)
+    x[o.fixed] = o.X[o.fixed]
+    v[o.fixed] = 0.0
+    return x, v
+
+
+def test_full_size_gradient_every_entry(block):
+    sc, args, g, o = block
+    x, v = _state(o, 1)
+    y = o.y_of(x, v)
+    r = soa(g.gradient(to_dev(x, o.N), to_dev(y, o.N)))
+    ref = o.grad_g(x, y)
+    ref[o.fixed] = 0.0
+    assert np.linalg.norm(r - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_full_size_rotations_every_gauss_point(block):
+    sc, args, g, o = block
+    x, _ = _state(o, 2)
+    R = g.rotations(to_dev(x, o.N)).cpu().numpy()                     # [9, Q]
+    Rref = op.closest_rotation(o.deformation_gradients(x)).reshape(o.Q, 9).T
+    assert np.abs(R - Rref).max() <= 1e-12
+
+
+def test_full_size_global_step_residual(block):
+    sc, args, g, o = block
+    b = np.random.default_rng(3).standard_normal(3 * o.N)
+    x = soa(g.apply_inverse(to_dev(b, o.N)))
+    f = o.free
+    res = o.A_ff @ x[f] - b[f]
+    assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(b[f])
+
+
+def test_full_size_forward_and_backward_step(block):
+    """One step with the bench's options: the oracle finds the returned state
+    inside the forward stopping test, and the adjoint recovered from the
+    returned dL/dv_i solves the oracle's adjoint system to the bench's
+    tolerance."""
+    sc, args, g, o = block
+    x, v = _state(o, 4)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    xn_d, vn_d, st = g.forward_step(xd, vd)
+    print("forward", st, flush=True)
+    assert st["converged"] == 1
+    xn, vn = soa(xn_d), soa(vn_d)
+    y = o.y_of(x, v)
+    f = o.free
+    x0 = y.copy()
+    x0[o.fixed] = o.X[o.fixed]     # the initial iterate: y, Dirichlet nodes at rest
+    g0 = np.linalg.norm(o.grad_g(x0, y)[f])
+    g1 = np.linalg.norm(o.grad_g(xn, y)[f])
+    floor = 1e-12 * np.linalg.norm((o.Mdiag * y / o.h ** 2)[f])
+    print("grad g", g0, g1, floor, flush=True)
+    assert g1 <= max(1.5 * args.fwd_tol * g0, 1.5 * floor)
+    assert np.abs(vn - (xn - x) / o.h).max() <= 1e-12 * max(1.0, np.abs(vn).max())
+
+    gxn = np.random.default_rng(5).standard_normal(3 * o.N)
+    gE = torch.zeros(o.E, dtype=torch.float64, device="cuda:0")
+    gx, gv, _, bst = g.backward_step(xd, vd, None, xn_d, to_dev(gxn, o.N), torch.zeros_like(xd), g_youngs=gE)
+    print("backward", bst, flush=True)
+    assert bst["converged"] == 1
+    # frictionless scenes: dL/dv_i = h dL/dy = M z / h, so z = h dL/dv_i / M
+    assert o.friction_mu == 0.0
+    z = soa(gv) * o.h / o.Mdiag
+    H = o.hessian(xn)[f][:, f]
+    res = H @ z[f] - gxn[f]
+    assert np.linalg.norm(res) <= 1.5 * args.bwd_tol * np.linalg.norm(gxn[f])
+    assert np.isfinite(gE.cpu().numpy()).all()
