@@ -107,3 +107,30 @@ def test_full_size_forward_and_backward_step(block):
     res = H @ z[f] - gxn[f]
     assert np.linalg.norm(res) <= 1.5 * args.bwd_tol * np.linalg.norm(gxn[f])
     assert np.isfinite(gE.cpu().numpy()).all()
+
+
+def test_full_size_forward_step_legged_body():
+    """The 744-cell legged body (ground contact, friction, muscles) with the
+    bench's options and actuation: the oracle finds the returned state inside
+    the forward stopping test."""
+    from paper_2101_05917_amd.mesh import Mesh
+    from parity_helpers import elem_dev
+    sc = W.config("c3")
+    args = bench.parse(["--config", "c3"])
+    g = Mesh.from_scene(sc, **bench.solver_options(args))
+    o = om.Model(sc)
+    act = W.actuation_sequence(2, o.E, seed=sc.act_seed)[1]
+    x, v = _state(o, 6)
+    xn_d, _, st = g.forward_step(to_dev(x, o.N), to_dev(v, o.N), elem_dev(act))
+    print("legged forward", st, flush=True)
+    assert st["converged"] == 1
+    xn = soa(xn_d)
+    y = o.y_of(x, v)
+    f = o.free
+    x0 = y.copy()
+    x0[o.fixed] = o.X[o.fixed]
+    g0 = np.linalg.norm(o.grad_g(x0, y, act)[f])
+    g1 = np.linalg.norm(o.grad_g(xn, y, act)[f])
+    floor = 1e-12 * np.linalg.norm((o.Mdiag * y / o.h ** 2)[f])
+    print("grad g", g0, g1, floor, flush=True)
+    assert g1 <= max(1.5 * args.fwd_tol * g0, 1.5 * floor)

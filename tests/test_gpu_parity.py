@@ -389,3 +389,37 @@ def test_profiling_leaves_results_unchanged_and_times_every_class(fused):
     else:
         assert ran["solve"] > 0
         assert sum(ran[c] for c in classes if c.startswith("sweep")) > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_inverted_elements_rotations_and_gradient(precision):
+    """Strongly perturbed state with many inverted Gauss points (det F <= 0):
+    the closest proper rotation (the Newton polar iteration hands over to the
+    q-method there) and grad g agree with the oracle's SVD-based projection."""
+    sc = W.config("c1")
+    g, o = pair(sc, precision=precision)
+    rng = np.random.default_rng(61)
+    x = o.X + 0.6 * sc.dx * rng.standard_normal(3 * o.N)
+    F = o.deformation_gradients(x)
+    det = np.linalg.det(F)
+    print("inverted", int((det <= 0).sum()), "of", o.Q, flush=True)
+    assert (det <= 0).sum() >= o.Q // 10
+    R = g.rotations(to_dev(x, o.N)).cpu().numpy()
+    Rref = op.closest_rotation(F).reshape(o.Q, 9).T
+    # compare where the projection is well conditioned: the two singular
+    # values that decide it (the two smallest when det F <= 0) are apart
+    s = np.linalg.svd(F, compute_uv=False)
+    gap = np.where(det > 0, s[:, 1] + s[:, 2], s[:, 1] - s[:, 2]) / s[:, 0]
+    ok = gap > 1e-2
+    assert ok.sum() >= o.Q // 2
+    assert np.abs(R - Rref)[:, ok].max() <= 1e-10
+    Rq = R.T.reshape(-1, 3, 3)                      # every Gauss point: a proper rotation
+    assert np.abs(Rq @ Rq.transpose(0, 2, 1) - np.eye(3)).max() <= 1e-12
+    assert np.abs(np.linalg.det(Rq) - 1.0).max() <= 1e-12
+    v = np.zeros(3 * o.N)
+    y = o.y_of(x, v)
+    r = soa(g.gradient(to_dev(x, o.N), to_dev(y, o.N)))
+    ref = o.grad_g(x, y)
+    ref[o.fixed] = 0.0
+    print("gradient rel", rel(r, ref), flush=True)
+    assert rel(r, ref) <= 1e-6
