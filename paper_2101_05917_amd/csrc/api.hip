@@ -1090,11 +1090,17 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
   const int chunk = std::max(kGraphIters, check_every / kGraphIters * kGraphIters);
-  int chunks = 0;
+  // Iterations are enqueued in chunks between host checks; every kernel of an
+  // iteration enqueued past convergence exits at once, but still costs a
+  // launch.  The first chunk has check_every iterations; later ones are sized
+  // from the residual reduction over the previous chunk: the iterations still
+  // needed at that rate, rounded up to whole graphs (at most 4 chunks).
+  int chunks = 0, next = chunk, k_prev = 0;
+  double rsq_prev = 0.0;
   for (int k = 0; k < max_it;) {
     const bool direct = !m->opt.use_graphs || (m->prof_class != DPD_PROF_OFF && chunks % kProfStride == 0);
     hipGraphExec_t ex = direct ? nullptr : cg_graph(m, s, st, fp32);
-    for (int i = 0; i < chunk && k < max_it; i += kGraphIters) {
+    for (int i = 0; i < next && k < max_it; i += kGraphIters) {
       if (ex) {
         HIPCHECK(m, hipGraphLaunch(ex, s));
         k += kGraphIters;
@@ -1104,7 +1110,20 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
     }
     chunks += 1;
     if ((rc = read_state(m, s)) != DPD_OK) return rc;
-    if (m->h_st[st_idx].done) break;
+    const IterState& h = m->h_st[st_idx];
+    if (h.done) break;
+    next = chunk;
+    const double r_ref = chunks > 1 ? rsq_prev : h.nb2;
+    const int it = chunks > 1 ? h.iter - k_prev : h.iter;
+    if (it > 0 && h.rsq > 0.0 && h.rsq < r_ref && h.tolsq * h.nb2 < h.rsq) {
+      const double need = std::log(h.tolsq * h.nb2 / h.rsq) / (std::log(h.rsq / r_ref) / it);
+      if (std::isfinite(need) && need > 0.0) {
+        const int want = ((int)std::ceil(need) + kGraphIters - 1) / kGraphIters * kGraphIters;
+        next = std::max(kGraphIters, std::min(4 * chunk, want));
+      }
+    }
+    rsq_prev = h.rsq;
+    k_prev = h.iter;
   }
   return DPD_OK;
 }
