@@ -52,13 +52,16 @@ def parse(argv=None):
     ap.add_argument("--fwd-solver", default="newton_pcg", choices=["newton_pcg", "pd"])
     ap.add_argument("--bwd-solver", default="pcg", choices=["pcg", "fixed_point"])
     # forward: Newton steps until |grad g| <= 3e-8 |grad g(x0)|, each step's CG to an
-    # Eisenstat-Walker forcing term (capped at 0.1); adjoint CG to 2e-7: the
-    # end-to-end gradient error stays well inside the metric's 1e-6
-    ap.add_argument("--fwd-tol", type=float, default=3e-8)
-    ap.add_argument("--bwd-tol", type=float, default=2e-7)
-    ap.add_argument("--fwd-inner-tol", type=float, default=-0.1,
+    ap.add_argument("--fwd-tol", type=float, default=None,
+                    help="relative tolerance of the forward step on grad g (default 3e-8; 3e-11 for the "
+                         "legged body)")
+    ap.add_argument("--bwd-tol", type=float, default=None,
+                    help="relative tolerance of the adjoint solve (default 2e-7; 1e-9 for the legged body)")
+    ap.add_argument("--fwd-inner-tol", type=float, default=None,
                     help="relative tolerance of each Newton step's conjugate-gradient solve; "
-                         "negative: Eisenstat-Walker forcing terms capped at its magnitude")
+                         "negative: Eisenstat-Walker forcing terms capped at its magnitude "
+                         "(default -0.1; -0.3 for the legged body, whose contact and muscles make "
+                         "Newton's early steps poor and over-solving them wasteful)")
     ap.add_argument("--rollout-steps", type=int, default=None)
     ap.add_argument("--fused-cg", type=int, default=1,
                     help="fused dense solver: 0 off, 1 automatic placement, 2 + m placement m")
@@ -79,7 +82,20 @@ def parse(argv=None):
     ap.add_argument("--roofline-kernel", default=None,
                     choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
                              "elem_hvp", "elem_forces"])
-    return ap.parse_args(argv)
+    args = ap.parse_args(argv)
+    # The legged body's ground contact, friction and inverted Gauss points
+    # amplify each step's solver error along the 200-step rollout (about 5e3
+    # from the forward tolerance to the end-to-end gradient), so the metric's
+    # 1e-6 needs tighter tolerances there (checked against the oracle's
+    # reference in every run); a looser Eisenstat-Walker cap saves iterations.
+    legged = args.config == "c3"
+    if args.fwd_tol is None:
+        args.fwd_tol = 3e-11 if legged else 3e-8
+    if args.bwd_tol is None:
+        args.bwd_tol = 1e-9 if legged else 2e-7
+    if args.fwd_inner_tol is None:
+        args.fwd_inner_tol = -0.3 if legged else -0.1
+    return args
 
 
 def solver_options(args) -> dict:
@@ -350,6 +366,9 @@ def main():
             err = {"g_x0": float(np.linalg.norm(gx_np - ref["g_x0"]) / np.linalg.norm(ref["g_x0"])),
                    "g_youngs": float(np.linalg.norm(gE_np - ref["g_youngs"]) /
                                      np.linalg.norm(ref["g_youngs"]))}
+            if g_act is not None and "g_act" in ref.files:
+                ga_np = g_act.cpu().numpy()
+                err["g_act"] = float(np.linalg.norm(ga_np - ref["g_act"]) / np.linalg.norm(ref["g_act"]))
 
     ckpt_check = None
     if args.check_checkpointing and K > 1:

@@ -27,9 +27,12 @@ def main():
     m = om.Model(sc)
     x, v = m.X.copy(), np.zeros(3 * m.N)
     xs, vs = [x], [v]
+    # muscle actuation per step and element, the benchmark's seeded sequence
+    acts = W.actuation_sequence(steps, m.E, seed=sc.act_seed) if sc.muscle_k > 0 else None
     t0 = time.time()
     for t in range(steps):
-        xn, info = of.newton_solve(m, m.y_of(x, v))
+        a = None if acts is None else acts[t]
+        xn, info = of.newton_solve(m, m.y_of(x, v), a)
         vn = (xn - x) / m.h
         xs.append(xn)
         vs.append(vn)
@@ -39,12 +42,17 @@ def main():
     c = W.loss_vector(m.N, sc.loss_seed)
     gx, gv = c.copy(), np.zeros(3 * m.N)
     gE = np.zeros(m.E)
+    g_act = None if acts is None else np.zeros_like(acts)
     for t in range(steps - 1, -1, -1):
-        gx, gv, ge, _, _ = oa.backward_step(m, xs[t], vs[t], None, xs[t + 1], gx, gv, solver="direct")
+        a = None if acts is None else acts[t]
+        gx, gv, ge, ga, _ = oa.backward_step(m, xs[t], vs[t], a, xs[t + 1], gx, gv, solver="direct")
         gE += ge
+        if g_act is not None:
+            g_act[t] = ga
     out = os.path.join(HERE, f"{name}_rollout_reference.npz")
+    extra = {} if g_act is None else {"g_act": g_act}
     np.savez_compressed(out, steps=steps, loss=float(c @ xs[-1]), x_T=xs[-1], g_x0=gx, g_v0=gv,
-                        g_youngs=gE)
+                        g_youngs=gE, **extra)
     print("wrote", out, f"{time.time() - t0:.0f}s")
 
 
