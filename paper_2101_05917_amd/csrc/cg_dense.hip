@@ -55,43 +55,53 @@ __device__ inline void st_dev(double* p, double v) {
 }
 
 // Grid-wide barrier of a cooperative launch, two levels: workgroup b counts
-// in at the counter of group b mod 8 (one 256-byte line each), the workgroup
-// that completes its group's count for this round counts the group in at the
-// top counter, and every workgroup polls the top counter.  Every wave first
-// waits until its own device-coherent stores have completed.  The wait is
-// bounded: a workgroup that times out raises the abort flag, every workgroup
-// that sees the flag stops waiting, and all of them leave the kernel, so the
-// launch always drains.  Returns false after an abort.
+// in at the counter of group b mod 8 (one 256-byte line each); the workgroup
+// that completes its group's count for this round stores the round number in
+// the group's flag (the eight flags share one line), and wave 0 of every
+// workgroup polls the eight flags with one load.  Every wave first waits until
+// its own device-coherent stores have completed.  The wait is bounded: a
+// workgroup that times out raises the abort flag, every workgroup that sees
+// the flag stops waiting, and all of them leave the kernel, so the launch
+// always drains.  Returns false after an abort.
 constexpr int kBarGroups = 8;
 constexpr int kBarStride = 64;   // uint32 entries between counters
+constexpr int kBarFlags = 16;    // first group flag (bar[0] unused, bar[1] abort)
 constexpr int kBarWords = kBarStride * (kBarGroups + 1);
 static_assert(kBarWords == kDenseBarWords, "barrier buffer size");
+static_assert(kBarFlags + kBarGroups <= kBarStride, "flags share the first line");
 
 __device__ inline bool grid_barrier(uint32_t* bar, uint32_t& round) {
   __shared__ int ok;
   __syncthreads();
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    round += 1;
+  round += 1;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     const uint32_t G = gridDim.x, g = blockIdx.x % kBarGroups;
-    const uint32_t gsize = G / kBarGroups + (g < G % kBarGroups ? 1u : 0u);
     const uint32_t ngroups = G < (uint32_t)kBarGroups ? G : (uint32_t)kBarGroups;
-    const uint32_t t =
-        __hip_atomic_fetch_add(&bar[kBarStride * (g + 1)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (t + 1 == round * gsize) __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t target = round * ngroups;
+    if (lane == 0) {
+      const uint32_t gsize = G / kBarGroups + (g < G % kBarGroups ? 1u : 0u);
+      const uint32_t t =
+          __hip_atomic_fetch_add(&bar[kBarStride * (g + 1)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t + 1 == round * gsize)
+        __hip_atomic_store(&bar[kBarFlags + g], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     int good = 1;
     for (uint32_t spin = 0;; ++spin) {
-      if (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-      if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spin >= kSpinLimit) {
-        __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t v = (uint32_t)lane < ngroups
+                             ? __hip_atomic_load(&bar[kBarFlags + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : round;
+      if (__all(v >= round)) break;
+      const uint32_t ab = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ab != 0u || spin >= kSpinLimit) {
+        if (lane == 0) __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    ok = good;
+    if (lane == 0) ok = good;
   }
   __syncthreads();
   return ok != 0;
