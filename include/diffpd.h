@@ -53,10 +53,11 @@ typedef enum {
 } dpd_status;
 
 /* Precision of the iteration.  DPD_MIXED: FP32 triangular sweeps (and dense
- * A^{-1}) applied to FP64 residuals in correction form, and FP32 closest
- * rotations in the local steps, each polished by one FP64 Newton step of the
- * polar decomposition; factorization, residuals, corrections and reductions
- * stay FP64 (spec precision growth; the fixed point is unchanged).    */
+ * A^{-1}) applied to FP64 residuals in correction form, and closest rotations
+ * computed in FP32 and refined in FP64 (Newton steps of the polar iteration on
+ * the FP32 factor, then one step of the rotation-derivative algebra against
+ * F), accurate to FP64 round-off; factorization, residuals, corrections and
+ * reductions stay FP64 (the fixed point is unchanged).                      */
 enum { DPD_FP64 = 0, DPD_MIXED = 1 };
 /* Adjoint solver.                                                          */
 enum { DPD_BWD_FIXED_POINT = 0, DPD_BWD_PCG = 1 };
@@ -94,7 +95,10 @@ typedef struct {
   int32_t bwd_solver;      /* DPD_BWD_FIXED_POINT or DPD_BWD_PCG                   */
   double bwd_rel_tol;      /* stop when |xbar - H z| <= tol |xbar|               */
   int32_t precision;       /* DPD_FP64 or DPD_MIXED                                */
-  int32_t check_every;     /* host convergence check period (iterations), >= 1   */
+  int32_t check_every;     /* iterations before the first host convergence check,
+                              >= 1 (Alg. 1: every check_every iterations; a
+                              multi-launch CG solve sizes its later chunks from
+                              the observed convergence rate)                     */
   int32_t use_graphs;      /* 1: run conjugate-gradient iterations as HIP graphs  */
   int32_t fused_cg;        /* 1: meshes of at most 2048 free nodes keep A^{-1}
                               dense and run each conjugate-gradient solve in one
@@ -110,7 +114,8 @@ typedef struct {
   int32_t bwd_iters;       /* adjoint iterations in the last backward step       */
   int32_t converged;       /* 1 if the last call met its tolerance                */
   int32_t fallbacks;       /* CG -> fixed-point fallbacks in the last backward    */
-  int32_t inverted_qps;    /* quadrature points with det F <= 0 (last local pass) */
+  int32_t inverted_qps;    /* quadrature points with det F <= 0, summed over the
+                              local passes of the last forward step              */
   double fwd_rel_res;      /* final |grad g| / |grad g(x^0)|                      */
   double bwd_rel_res;      /* final |xbar - H z| / |xbar|                          */
   double ms_total;         /* wall time of the call when stats were requested     */
@@ -144,8 +149,9 @@ dpd_status dpd_default_options(dpd_options* opt);
  *   out         receives the handle; NULL on failure
  * Assembles A = M/h^2 + sum_c w_c G_c^T G_c (eq:pd_global) over free nodes,
  * orders it by geometric nested dissection (leaf size chosen by an estimate of
- * the solve time) and performs the symbolic analysis.  No numeric factorization yet (dpd_factorize).  DPD_EINVAL on bad
- * input (duplicate voxels, fixed nodes not on the mesh, nu out of range, ...). */
+ * the solve time) and performs the symbolic analysis; the numeric
+ * factorization is dpd_factorize.  DPD_EINVAL on bad input (duplicate voxels,
+ * fixed nodes not on the mesh, nu out of range, ...). */
 dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
                            const int32_t* fixed_ijk, int64_t n_fixed,
                            const dpd_options* opt, dpd_mesh** out);
@@ -179,16 +185,20 @@ dpd_status dpd_set_youngs(dpd_mesh* mesh, const double* youngs, int32_t on_devic
  * non-positive pivot. */
 dpd_status dpd_factorize(dpd_mesh* mesh, void* stream);
 
-/* One implicit-Euler step (eq:time_integration) by Alg. 1:
+/* One implicit-Euler step (eq:time_integration):
  *   y = x + h v + h^2 M^{-1} (M g + f_friction(x, v)); x^0 = y (Dirichlet nodes
- *   at rest); repeat local projections and a global solve with A.
+ *   at rest); then Alg. 1 (local projections and a global solve with A) or,
+ *   with DPD_FWD_NEWTON_PCG, Newton steps on g whose systems are solved by
+ *   conjugate gradients preconditioned with A; both stop on the same test.
  *   x, v        device [3][N], read-only
  *   act         device [n_elements] muscle actuation (1 = rest length), or NULL
  *   x_next      device [3][N], overwritten; must not alias x or v
  *   v_next      device [3][N], overwritten: (x_next - x) / h
- *   stats       host or NULL; non-NULL synchronizes the stream
- * Asynchronous except for the periodic convergence checks (every
- * opt.check_every iterations the host waits for a 4-byte flag). */
+ *   stats       host or NULL
+ * The host reads the iteration state between chunks of enqueued iterations
+ * (see check_every; with the fused solver, after batches of Newton steps
+ * enqueued ahead of their test) and at the end: the call returns with the
+ * step complete on the stream. */
 dpd_status dpd_forward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
                             const double* act, double* x_next, double* v_next, dpd_stats* stats);
 
@@ -200,7 +210,9 @@ dpd_status dpd_forward_step(dpd_mesh* mesh, void* stream, const double* x, const
  *   gx, gv              device [3][N], overwritten; must not alias the inputs
  *   g_youngs            device [n_elements], ACCUMULATED (+=), or NULL
  *   g_act               device [n_elements], overwritten, or NULL
- *   stats               host or NULL */
+ *   stats               host or NULL
+ * Returns with the step complete on the stream (the host reads the adjoint
+ * iteration's state between chunks of iterations and at the end). */
 dpd_status dpd_backward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
                              const double* act, const double* x_next, const double* gx_next,
                              const double* gv_next, double* gx, double* gv, double* g_youngs,
