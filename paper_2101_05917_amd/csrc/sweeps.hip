@@ -44,7 +44,17 @@ __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const do
       v0 = b[node];
       v1 = b[(int64_t)N + node];
       v2 = b[2 * (int64_t)N + node];
-      for (int k = S.cptr[j]; k < S.cptr[j + 1]; ++k) {
+      // four contributions at a time, their loads issued together
+      int k = S.cptr[j];
+      const int k1 = S.cptr[j + 1];
+      for (; k + 3 < k1; k += 4) {
+        const int64_t p0 = 3 * (int64_t)S.cidx[k], p1 = 3 * (int64_t)S.cidx[k + 1];
+        const int64_t p2 = 3 * (int64_t)S.cidx[k + 2], p3 = 3 * (int64_t)S.cidx[k + 3];
+        v0 += (S.U[p0] + S.U[p1]) + (S.U[p2] + S.U[p3]);
+        v1 += (S.U[p0 + 1] + S.U[p1 + 1]) + (S.U[p2 + 1] + S.U[p3 + 1]);
+        v2 += (S.U[p0 + 2] + S.U[p1 + 2]) + (S.U[p2 + 2] + S.U[p3 + 2]);
+      }
+      for (; k < k1; ++k) {
         const int64_t pos = 3 * (int64_t)S.cidx[k];
         v0 += S.U[pos];
         v1 += S.U[pos + 1];
