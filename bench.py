@@ -1,16 +1,21 @@
 """Benchmark: DoF-steps/s of the PD forward step plus its adjoint on one MI355X.
 
 One benchmark step is one whole rollout of the workload: T implicit-Euler
-steps forward (PD local projections + global solves with the factor of A)
-followed by T adjoint steps back to the initial state, giving dL/dx0, dL/dv0
-and dL/dE for L = c . x_T (c ~ N(0, 1), seed 0).  Inputs are synthetic and
+steps forward followed by T adjoint steps back to the initial state, giving
+dL/dx0, dL/dv0, dL/dE (and dL/dact with muscles) for L = c . x_T
+(c ~ N(0, 1), seed 0).  The forward steps are Newton steps on g whose systems
+are solved by conjugate gradients preconditioned with the factor of A
+(Eisenstat-Walker inner tolerances; --fwd-solver pd runs Alg. 1), the adjoint
+is the A-preconditioned CG acceleration of Alg. 2.  Inputs are synthetic and
 already resident in HBM when timing starts; the factorization is done before
 the timed region (once per material, as in the method).
 
 The default workload is the 16x8x8-cell cantilever with log-uniform
 per-element Young's moduli (1377 nodes, 100 steps).  The gradient of the
 timed rollout is compared with the oracle's stored reference
-(tests/golden/<name>_rollout_reference.npz) and the relative error reported.
+(tests/golden/<name>_rollout_reference.npz, cantilever and legged body) and the
+relative error reported; the tolerances are chosen so that it stays below the
+metric's 1e-6.
 
   python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]
 """

@@ -126,13 +126,6 @@ dpd_status upload(dpd_mesh* m, T** out, const std::vector<T>& v) {
   return DPD_OK;
 }
 
-void free_dev(dpd_mesh* m, void* p) {
-  if (!p) return;
-  auto it = std::find(m->allocs.begin(), m->allocs.end(), p);
-  if (it != m->allocs.end()) m->allocs.erase(it);
-  (void)hipFree(p);
-}
-
 // Time one launch of kernel class cls when that class is being profiled.
 // Single-kernel classes: every launch outside graph capture carries the
 // handle's device-side clock and its algorithmic work (DPD_LAUNCH passes them
