@@ -299,7 +299,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the workload does not shard across GPUs in this build)", file=sys.stderr)
+              "(the workload is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2101_05917_amd.mesh import Mesh

@@ -3,8 +3,8 @@
 // Discretization (paper Sec. Background and supplemental Sec. Energy
 // Definitions): trilinear cubic voxels, energies integrated at the 2x2x2
 // Gauss points, lumped mass.  Every term of A = M/h^2 + sum_c w_c G_c^T G_c
-// (eq:pd_global) in this build acts identically on the x, y and z
-// coordinates, so A = I_3 (x) A_s with A_s an N x N scalar matrix:
+// (eq:pd_global) with the energies used here acts identically on the x, y
+// and z coordinates, so A = I_3 (x) A_s with A_s an N x N scalar matrix:
 //   A_s = diag(m)/h^2 + sum_q w_q B_q^T B_q + sum_q w_m b_q b_q^T + k [contact]
 // with B_q the 3x8 shape-gradient matrix and b_q = B_q^T m (fibre).
 #include <algorithm>
