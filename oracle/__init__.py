@@ -18,6 +18,8 @@ Everything is written out plainly, with explicit sparse operators in the
 * forward       -- Alg. 1 (local/global PD) and a Newton solver (eq:newton_update2).
 * adjoint       -- eq:adjoint solved directly, by Alg. 2 and by A-preconditioned CG,
   plus the chain rule of eq:chain_rule and parameter gradients.
+* contact       -- the global step with a prescribed contact set (Sec. Contact):
+  the reduced system solved directly, and by Alg. 4's Woodbury steps.
 * rollout       -- multi-step forward/backward and central finite differences.
 
 Parity status of each function is stated in its module header; pins live in
