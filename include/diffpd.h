@@ -233,6 +233,36 @@ dpd_status dpd_hessian_apply(dpd_mesh* mesh, void* stream, const double* x, cons
                              const double* p, double* out);
 dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* R_out);
 
+/* Global step with a contact set (Sec. Contact, complementarity contact; the
+ * low-rank update of Alg. 4): x with x_C = x* and A_{C̄×C̄} x_{C̄} = b_{C̄},
+ * from the factor of A.  C is a set of free nodes whose positions are
+ * prescribed; b is the right-hand side the contact step forms (the effect of
+ * x* through the elements is already in it).
+ *
+ * dpd_contact_prepare caches A^{-1} e_j for every candidate node j (the
+ * paper's precomputed A^{-1} I_{I×C} for the largest contact set: one scalar
+ * column per node since A = I_3 (x) A_s; n_cand x N doubles on the device).
+ *   nodes_host  host, [n_cand] int32 public ids of free nodes, distinct
+ * Once per factorization (after dpd_factorize; DPD_ESTATE if called again).
+ * Synchronizes the stream.  DPD_EINVAL for out-of-range, fixed or repeated
+ * nodes.
+ *
+ * dpd_contact_solve:
+ *   set_host    host, [c] int32 indices into the candidate list, distinct,
+ *               0 <= c <= 120 (the c x c capacitance matrix is factorized
+ *               in one workgroup's LDS); c = 0 is the plain global step
+ *   xstar       device, [3][c] prescribed positions of the set's nodes
+ *   b           device, [3][N]
+ *   x           device, [3][N], overwritten (rows of fixed nodes 0); must
+ *               not alias b
+ * Computes a1 = A^{-1} b, solves (A^{-1})_{C×C} lam = -(a1)_C by Cholesky
+ * (the Woodbury identity in capacitance form: c x c and SPD), x = a1 + the
+ * set's columns of A^{-1} times lam, x_C = x*.  Synchronizes the stream when
+ * c > 0 (to report DPD_ENOTSPD on a non-positive pivot). */
+dpd_status dpd_contact_prepare(dpd_mesh* mesh, void* stream, const int32_t* nodes_host, int32_t n_cand);
+dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_host, int32_t c,
+                             const double* xstar, const double* b, double* x);
+
 /* Kernel timing for roofline measurement.  After dpd_profile_start(mesh, k),
  * launches of kernel class k made by calls on this handle are timed and the
  * algorithmic bytes and flops of each timed launch (what the method must move
@@ -261,7 +291,8 @@ enum {
   DPD_PROF_SOLVE = 5,            /* a whole A^{-1} b, all of its launches                   */
   DPD_PROF_SWEEP_FWD_WIDE = 6,   /* k_sweep_fwd_wide: forward level, wide blocks            */
   DPD_PROF_SWEEP_BWD_NARROW = 7, /* k_sweep_bwd_narrow: backward level of many small blocks */
-  DPD_PROF_CG_DENSE = 8          /* k_cg_dense: a whole fused conjugate-gradient solve      */
+  DPD_PROF_CG_DENSE = 8,         /* k_cg_dense: a whole fused conjugate-gradient solve      */
+  DPD_PROF_CONTACT_UPDATE = 9    /* k_contact_update: active-set columns of A^{-1} applied  */
 };
 typedef struct {
   int64_t launches;

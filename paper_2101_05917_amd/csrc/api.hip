@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/diffpd.h"
+#include "contact.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -88,6 +89,13 @@ struct dpd_mesh {
   double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
   ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
   LaunchClock* prof_clock = nullptr;  // device-side timing of the single-kernel classes
+  // global step with a contact set (dpd_contact_prepare / dpd_contact_solve)
+  int32_t contact_n = 0;               // candidate nodes
+  int32_t* contact_cand = nullptr;     // [n] public ids
+  double* contact_B1 = nullptr;        // [n][N] columns of A_s^{-1}, fixed rows 0
+  int32_t* contact_set = nullptr;      // [kContactMaxSet] active set of the last solve
+  double* contact_lam = nullptr;       // [3][kContactMaxSet]
+  int32_t* contact_status = nullptr;   // non-positive pivot flag
 };
 
 namespace {
@@ -1247,9 +1255,88 @@ dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_o
   return DPD_OK;
 }
 
+dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_host, int32_t n_cand) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (m->contact_n) return fail(m, DPD_ESTATE, "contact candidates are already prepared");
+  if (!nodes_host || n_cand < 1) return fail(m, DPD_EINVAL, "need at least one candidate node");
+  const int N = (int)m->hm.n_nodes;
+  std::vector<int32_t> cand(nodes_host, nodes_host + n_cand);
+  std::vector<uint8_t> seen(N, 0);
+  for (int32_t v : cand) {
+    if (v < 0 || v >= N) return fail(m, DPD_EINVAL, "candidate node out of range");
+    if (m->hm.fixed[v]) return fail(m, DPD_EINVAL, "candidate nodes must be free");
+    if (seen[v]) return fail(m, DPD_EINVAL, "repeated candidate node");
+    seen[v] = 1;
+  }
+  int32_t *dcand, *dset, *dstatus;
+  double *B1, *lam;
+  if ((rc = upload(m, &dcand, cand)) != DPD_OK || (rc = dev_alloc(m, &B1, (int64_t)n_cand * N)) != DPD_OK ||
+      (rc = dev_alloc(m, &dset, kContactMaxSet)) != DPD_OK ||
+      (rc = dev_alloc(m, &lam, 3 * (int64_t)kContactMaxSet)) != DPD_OK ||
+      (rc = dev_alloc(m, &dstatus, 1)) != DPD_OK)
+    return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n3 = 3 * (int64_t)N;
+  launch_fill(s, n3, m->y, 0.0);  // fixed rows stay 0 in every solution below
+  for (int k0 = 0; k0 < n_cand; k0 += 3) {
+    launch_fill(s, n3, m->r, 0.0);
+    launch_contact_unit(s, N, n_cand, dcand, k0, m->r);
+    solve(m, s, false, m->r, m->y, 1.0, 0, nullptr);
+    launch_contact_collect(s, N, n_cand, k0, m->y, B1);
+  }
+  HIPCHECK(m, hipGetLastError());
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->contact_cand = dcand;
+  m->contact_B1 = B1;
+  m->contact_set = dset;
+  m->contact_lam = lam;
+  m->contact_status = dstatus;
+  m->contact_n = n_cand;
+  return DPD_OK;
+}
+
+dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host, int32_t c,
+                             const double* xstar, const double* b, double* x) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!m->contact_n) return fail(m, DPD_ESTATE, "no contact candidates (call dpd_contact_prepare)");
+  if (!b || !x || (c > 0 && (!set_host || !xstar))) return fail(m, DPD_EINVAL, "null argument");
+  if (x == b) return fail(m, DPD_EINVAL, "x must not alias b");
+  if (c < 0 || c > kContactMaxSet) return fail(m, DPD_EINVAL, "active set size must be 0..120");
+  std::vector<uint8_t> seen(m->contact_n, 0);
+  for (int32_t k = 0; k < c; ++k) {
+    const int32_t v = set_host[k];
+    if (v < 0 || v >= m->contact_n) return fail(m, DPD_EINVAL, "active-set index out of range");
+    if (seen[v]) return fail(m, DPD_EINVAL, "repeated active-set index");
+    seen[v] = 1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = (int)m->hm.n_nodes;
+  launch_fill(s, 3 * (int64_t)N, x, 0.0);
+  solve(m, s, false, b, x, 1.0, 0, nullptr);  // a1 = A^{-1} b
+  if (c > 0) {
+    HIPCHECK(m, hipMemcpyAsync(m->contact_set, set_host, sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+    HIPCHECK(m, launch_contact_capacitance(s, N, m->contact_cand, m->contact_set, c, m->contact_B1, x,
+                                           m->contact_lam, m->contact_status));
+    {
+      ProfScope ps(m, s, DPD_PROF_CONTACT_UPDATE,
+                   8.0 * ((double)c * N + 6.0 * N) + 8.0 * 4.0 * c, 6.0 * (double)c * N);
+      launch_contact_update(s, N, m->contact_set, c, m->contact_B1, m->contact_lam, x);
+    }
+    launch_contact_set(s, N, m->contact_cand, m->contact_set, c, xstar, x);
+    int32_t bad = 0;
+    HIPCHECK(m, hipMemcpyAsync(&bad, m->contact_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+    if (bad) return fail(m, DPD_ENOTSPD, "non-positive pivot in the contact capacitance matrix");
+  }
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CG_DENSE)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_UPDATE)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

@@ -1,0 +1,24 @@
+// Global step with a contact set: kernel launchers (contact.hip, internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dpd {
+
+constexpr int kContactMaxSet = 120;    // active-set size: the c x c Cholesky stays in LDS
+constexpr int kContactThreads = 1024;  // threads of the one-workgroup Cholesky
+
+size_t contact_capacitance_lds(int c);
+void launch_contact_unit(hipStream_t s, int N, int n_cand, const int32_t* cand, int k0, double* b);
+void launch_contact_collect(hipStream_t s, int N, int n_cand, int k0, const double* x, double* B1);
+hipError_t launch_contact_capacitance(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
+                                      const double* B1, const double* a1, double* lam, int* status);
+void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
+                           double* x);
+void launch_contact_set(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* xstar,
+                        double* x);
+
+}  // namespace dpd

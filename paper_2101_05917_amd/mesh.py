@@ -238,6 +238,30 @@ class Mesh:
                     self.handle)
         return out
 
+    # ------------------------------------------------------------------ contact global step
+    def contact_prepare(self, nodes):
+        """Cache A^{-1} e_j for the candidate nodes (public ids), see dpd_contact_prepare."""
+        arr = np.ascontiguousarray(np.asarray(nodes, dtype=np.int32))
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_contact_prepare(self.handle, _stream(self.device),
+                                                 arr.ctypes.data_as(C.c_void_p), int(arr.size)), self.handle)
+
+    def contact_solve(self, active, xstar, b):
+        """x with x_C = x* and A_{C̄×C̄} x_{C̄} = b_{C̄}; active: indices into the
+        candidate list; xstar: [3, c] float64 on the device (dpd_contact_solve)."""
+        self._check_state(b)
+        arr = np.ascontiguousarray(np.asarray(active, dtype=np.int32))
+        c = int(arr.size)
+        if c and (xstar is None or tuple(xstar.shape) != (3, c) or xstar.dtype != torch.float64
+                  or xstar.device != self.device or not xstar.is_contiguous()):
+            raise ValueError(f"xstar must be a contiguous float64 [3, {c}] tensor on {self.device}")
+        out = torch.empty_like(b)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_contact_solve(self.handle, _stream(self.device),
+                                               arr.ctypes.data_as(C.c_void_p) if c else None, c,
+                                               _ptr(xstar) if c else None, _ptr(b), _ptr(out)), self.handle)
+        return out
+
     # ------------------------------------------------------------------ timing
     def profile_start(self, kernel_class: str):
         """Time the launches of one kernel class (device clock or events, see dpd_profile_start)."""
