@@ -76,6 +76,10 @@ def parse(argv=None):
                     help="keep every K-th state and recompute segments (default: 20 for c3, else 1)")
     ap.add_argument("--check-checkpointing", action="store_true",
                     help="also run the rollout storing every state and compare the gradients")
+    ap.add_argument("--contact-set", type=int, default=0,
+                    help="time the global step with a contact set (Alg. 4) instead of rollouts: this many "
+                         "of the scene's ground-contact candidates active (at most 120)")
+    ap.add_argument("--contact-solves", type=int, default=300, help="timed contact global steps")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run one plain device copy of this many bytes (counter scaling)")
     ap.add_argument("--requests", type=int, default=64, help="c4: number of requests")
@@ -188,6 +192,75 @@ def cpu_baseline(scene, T_budget_s):
     return {"value": 3 * m.N * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"first {steps} of {scene.steps} steps, Newton (sparse LU) forward + direct "
                       f"adjoint, {dt:.1f} s wall, numpy/scipy on {cores} host cores"}
+
+
+def contact_bench(args, mesh, scene, torch):
+    """Global steps with a contact set (Sec. Contact, Alg. 4): the scene's
+    ground-contact candidates are cached once (their columns of A^{-1}), then
+    the same seeded active subset, prescribed positions and right-hand side are
+    solved repeatedly.  The oracle's reduced solve (sparse LU of the reduced
+    matrix) on the host is the CPU baseline where the mesh is small enough."""
+    cand = np.asarray(mesh.contact_nodes(), dtype=np.int64)
+    if not len(cand):
+        print("--contact-set needs a scene with ground-contact candidates (c3, c5)", file=sys.stderr)
+        sys.exit(2)
+    c = min(args.contact_set, len(cand), 120)
+    rng = np.random.default_rng(0)
+    active = np.sort(rng.choice(len(cand), c, replace=False)).astype(np.int32)
+    N = mesh.n_nodes
+    progress(f"caching A^-1 columns of {len(cand)} contact candidates")
+    mesh.contact_prepare(cand)
+    xs_np = 1e-3 * rng.standard_normal(3 * c)
+    b_np = rng.standard_normal(3 * N)
+    xs = torch.from_numpy(np.ascontiguousarray(xs_np.reshape(c, 3).T)).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(b_np.reshape(N, 3).T)).to("cuda:0")
+    for _ in range(max(1, args.warmup) * 10):
+        mesh.contact_solve(active, xs, b)
+    torch.cuda.synchronize()
+    K = args.contact_solves
+    mesh.profile_start("contact_update")
+    t0 = time.perf_counter()
+    for _ in range(K):
+        x = mesh.contact_solve(active, xs, b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    prof = mesh.profile_read()
+    avg_ms = prof["total_ms"] / max(1, prof["launches"])
+    bpl = prof["bytes"] / max(1, prof["launches"])
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    out = {
+        "metric": "contact global steps/s (Alg. 4)", "value": 1.0 / dt, "unit": "solves/s", "n_gpus": 1,
+        "steps": K, "warmup": max(1, args.warmup) * 10, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{scene.name}: {3 * N} DoFs, {c} of {len(cand)} ground-contact candidates "
+                               f"prescribed, one global step with the contact set per solve"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None,
+                     "kernel": "k_contact_update (the active set's columns of A^{-1} applied to lam)",
+                     "launches": prof["launches"], "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bpl,
+                     "timing": "every launch of the timed region, by the device clock (s_memrealtime) from "
+                               "workgroup 0's entry to the last workgroup's exit"},
+    }
+    if not args.no_cpu_baseline:
+        if 3 * N <= CPU_BASELINE_MAX_DOFS:
+            from oracle import model as om, contact as oc
+            m = om.Model(scene)
+            nodes = cand[active]
+            t0 = time.perf_counter()
+            n = 0
+            while time.perf_counter() - t0 < 0.5 * args.cpu_seconds:
+                oc.reduced_solve(m, nodes, xs_np, b_np)
+                n += 1
+            dtc = (time.perf_counter() - t0) / n
+            cores = len(os.sched_getaffinity(0))
+            out["cpu_baseline"] = {"value": 1.0 / dtc, "unit": "solves/s", "cores": cores, "kind": "oracle",
+                                   "sample": f"{n} reduced solves (sparse LU of the reduced matrix), "
+                                             f"{dtc * n:.1f} s wall, scipy on {cores} host cores"}
+        else:
+            out["cpu_baseline"] = {"value": None, "kind": "oracle",
+                                   "sample": f"not taken: {3 * N} DoFs exceed the oracle's practical "
+                                             f"size ({CPU_BASELINE_MAX_DOFS})"}
+    return out
 
 
 def serve_bench(args):
@@ -308,6 +381,9 @@ def main():
     T = args.rollout_steps or scene.steps
     progress(f"{scene.name}: mesh set-up and factorization")
     mesh = Mesh.from_scene(scene, **solver_options(args))
+    if args.contact_set:
+        print(json.dumps(contact_bench(args, mesh, scene, torch)), flush=True)
+        return
     if args.roofline_kernel is None:
         # the kernel with the largest share of GPU time in the rocprofv3 summary of the workload:
         # the fused conjugate-gradient launch where the mesh is small enough for it, else the

@@ -243,9 +243,9 @@ dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* 
  * paper's precomputed A^{-1} I_{I×C} for the largest contact set: one scalar
  * column per node since A = I_3 (x) A_s; n_cand x N doubles on the device).
  *   nodes_host  host, [n_cand] int32 public ids of free nodes, distinct
- * Once per factorization (after dpd_factorize; DPD_ESTATE if called again).
- * Synchronizes the stream.  DPD_EINVAL for out-of-range, fixed or repeated
- * nodes.
+ * After dpd_factorize (which discards the cache); calling it again replaces
+ * the candidate list.  Synchronizes the stream.  DPD_EINVAL for
+ * out-of-range, fixed or repeated nodes.
  *
  * dpd_contact_solve:
  *   set_host    host, [c] int32 indices into the candidate list, distinct,
@@ -255,10 +255,13 @@ dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* 
  *   b           device, [3][N]
  *   x           device, [3][N], overwritten (rows of fixed nodes 0); must
  *               not alias b
- * Computes a1 = A^{-1} b, solves (A^{-1})_{C×C} lam = -(a1)_C by Cholesky
- * (the Woodbury identity in capacitance form: c x c and SPD), x = a1 + the
- * set's columns of A^{-1} times lam, x_C = x*.  Synchronizes the stream when
- * c > 0 (to report DPD_ENOTSPD on a non-positive pivot). */
+ * Computes a1 = A^{-1} b, lam = -((A^{-1})_{C×C})^{-1} (a1)_C (the Woodbury
+ * identity in capacitance form: c x c and SPD), x = a1 + the set's columns of
+ * A^{-1} times lam, x_C = x*.  The inverse of the c x c matrix depends on
+ * the set only (fixed through Alg. 3's inner iterations): it is computed by
+ * Cholesky when the set differs from the previous call's, which synchronizes
+ * the stream (DPD_ENOTSPD on a non-positive pivot); otherwise the call is
+ * asynchronous. */
 dpd_status dpd_contact_prepare(dpd_mesh* mesh, void* stream, const int32_t* nodes_host, int32_t n_cand);
 dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_host, int32_t c,
                              const double* xstar, const double* b, double* x);

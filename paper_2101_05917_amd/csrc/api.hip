@@ -90,12 +90,15 @@ struct dpd_mesh {
   ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
   LaunchClock* prof_clock = nullptr;  // device-side timing of the single-kernel classes
   // global step with a contact set (dpd_contact_prepare / dpd_contact_solve)
-  int32_t contact_n = 0;               // candidate nodes
-  int32_t* contact_cand = nullptr;     // [n] public ids
-  double* contact_B1 = nullptr;        // [n][N] columns of A_s^{-1}, fixed rows 0
-  int32_t* contact_set = nullptr;      // [kContactMaxSet] active set of the last solve
+  int32_t contact_n = 0;               // candidates (0: not prepared for the current factor)
+  int32_t contact_cap = 0;             // candidates the buffers below hold
+  int32_t* contact_cand = nullptr;     // [cap] public ids
+  double* contact_B1 = nullptr;        // [cap][N] columns of A_s^{-1}, fixed rows 0
+  int32_t* contact_set = nullptr;      // [kContactMaxSet] active set of the cached inverse
+  double* contact_Sinv = nullptr;      // [c][c] inverse of (A^{-1})_{C×C} for that set
   double* contact_lam = nullptr;       // [3][kContactMaxSet]
   int32_t* contact_status = nullptr;   // non-positive pivot flag
+  std::vector<int32_t> contact_cached; // the set whose inverse is cached (empty: none)
 };
 
 namespace {
@@ -803,6 +806,10 @@ dpd_status dpd_set_youngs(dpd_mesh* m, const double* youngs, int32_t on_device, 
 }
 
 dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
+  if (m) {  // cached columns of A^{-1} for contact belong to the previous factor
+    m->contact_n = 0;
+    m->contact_cached.clear();
+  }
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
   std::vector<double> panels;
   std::string e;
@@ -1258,7 +1265,6 @@ dpd_status dpd_rotations(dpd_mesh* m, void* stream, const double* x, double* R_o
 dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_host, int32_t n_cand) {
   dpd_status rc = check_ready(m);
   if (rc != DPD_OK) return rc;
-  if (m->contact_n) return fail(m, DPD_ESTATE, "contact candidates are already prepared");
   if (!nodes_host || n_cand < 1) return fail(m, DPD_EINVAL, "need at least one candidate node");
   const int N = (int)m->hm.n_nodes;
   std::vector<int32_t> cand(nodes_host, nodes_host + n_cand);
@@ -1269,29 +1275,32 @@ dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_h
     if (seen[v]) return fail(m, DPD_EINVAL, "repeated candidate node");
     seen[v] = 1;
   }
-  int32_t *dcand, *dset, *dstatus;
-  double *B1, *lam;
-  if ((rc = upload(m, &dcand, cand)) != DPD_OK || (rc = dev_alloc(m, &B1, (int64_t)n_cand * N)) != DPD_OK ||
-      (rc = dev_alloc(m, &dset, kContactMaxSet)) != DPD_OK ||
-      (rc = dev_alloc(m, &lam, 3 * (int64_t)kContactMaxSet)) != DPD_OK ||
-      (rc = dev_alloc(m, &dstatus, 1)) != DPD_OK)
+  m->contact_n = 0;
+  m->contact_cached.clear();
+  if (n_cand > m->contact_cap) {
+    if ((rc = dev_alloc(m, &m->contact_cand, n_cand)) != DPD_OK ||
+        (rc = dev_alloc(m, &m->contact_B1, (int64_t)n_cand * N)) != DPD_OK)
+      return rc;
+    m->contact_cap = n_cand;
+  }
+  if (!m->contact_set &&
+      ((rc = dev_alloc(m, &m->contact_set, kContactMaxSet)) != DPD_OK ||
+       (rc = dev_alloc(m, &m->contact_Sinv, (int64_t)kContactMaxSet * kContactMaxSet)) != DPD_OK ||
+       (rc = dev_alloc(m, &m->contact_lam, 3 * (int64_t)kContactMaxSet)) != DPD_OK ||
+       (rc = dev_alloc(m, &m->contact_status, 1)) != DPD_OK))
     return rc;
   hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(m, hipMemcpyAsync(m->contact_cand, cand.data(), sizeof(int32_t) * n_cand, hipMemcpyHostToDevice, s));
   const int64_t n3 = 3 * (int64_t)N;
   launch_fill(s, n3, m->y, 0.0);  // fixed rows stay 0 in every solution below
   for (int k0 = 0; k0 < n_cand; k0 += 3) {
     launch_fill(s, n3, m->r, 0.0);
-    launch_contact_unit(s, N, n_cand, dcand, k0, m->r);
+    launch_contact_unit(s, N, n_cand, m->contact_cand, k0, m->r);
     solve(m, s, false, m->r, m->y, 1.0, 0, nullptr);
-    launch_contact_collect(s, N, n_cand, k0, m->y, B1);
+    launch_contact_collect(s, N, n_cand, k0, m->y, m->contact_B1);
   }
   HIPCHECK(m, hipGetLastError());
   HIPCHECK(m, hipStreamSynchronize(s));
-  m->contact_cand = dcand;
-  m->contact_B1 = B1;
-  m->contact_set = dset;
-  m->contact_lam = lam;
-  m->contact_status = dstatus;
   m->contact_n = n_cand;
   return DPD_OK;
 }
@@ -1313,22 +1322,29 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
   }
   hipStream_t s = (hipStream_t)stream;
   const int N = (int)m->hm.n_nodes;
+  if (c > 0 && !(m->contact_cached.size() == (size_t)c &&
+                 std::equal(set_host, set_host + c, m->contact_cached.begin()))) {
+    // a new active set: factorize and invert its capacitance matrix once
+    m->contact_cached.clear();
+    HIPCHECK(m, hipMemcpyAsync(m->contact_set, set_host, sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+    HIPCHECK(m, launch_contact_factor(s, N, m->contact_cand, m->contact_set, c, m->contact_B1, m->contact_Sinv,
+                                      m->contact_status));
+    int32_t bad = 0;
+    HIPCHECK(m, hipMemcpyAsync(&bad, m->contact_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+    if (bad) return fail(m, DPD_ENOTSPD, "non-positive pivot in the contact capacitance matrix");
+    m->contact_cached.assign(set_host, set_host + c);
+  }
   launch_fill(s, 3 * (int64_t)N, x, 0.0);
   solve(m, s, false, b, x, 1.0, 0, nullptr);  // a1 = A^{-1} b
   if (c > 0) {
-    HIPCHECK(m, hipMemcpyAsync(m->contact_set, set_host, sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
-    HIPCHECK(m, launch_contact_capacitance(s, N, m->contact_cand, m->contact_set, c, m->contact_B1, x,
-                                           m->contact_lam, m->contact_status));
+    launch_contact_lam(s, N, m->contact_cand, m->contact_set, c, m->contact_Sinv, x, m->contact_lam);
     {
       ProfScope ps(m, s, DPD_PROF_CONTACT_UPDATE,
                    8.0 * ((double)c * N + 6.0 * N) + 8.0 * 4.0 * c, 6.0 * (double)c * N);
       launch_contact_update(s, N, m->contact_set, c, m->contact_B1, m->contact_lam, x);
     }
     launch_contact_set(s, N, m->contact_cand, m->contact_set, c, xstar, x);
-    int32_t bad = 0;
-    HIPCHECK(m, hipMemcpyAsync(&bad, m->contact_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(m, hipStreamSynchronize(s));
-    if (bad) return fail(m, DPD_ENOTSPD, "non-positive pivot in the contact capacitance matrix");
   }
   HIPCHECK(m, hipGetLastError());
   return DPD_OK;

@@ -10,7 +10,9 @@
 // Rows outside C then satisfy A x = b, and x_C = 0 before x* is written, so
 // A_{C̄×C̄} x_{C̄} = b_{C̄}.  This is the Woodbury identity in capacitance form:
 // the small system is c x c and SPD (a principal block of A^{-1}) instead of
-// the paper's 2c x 2c I - V P^T B3, and is factorized by Cholesky in LDS.
+// the paper's 2c x 2c I - V P^T B3.  Its inverse depends on the active set
+// only, which stays fixed through Alg. 3's inner iterations, so it is
+// computed (Cholesky in LDS) when the set changes and reused otherwise.
 #include <hip/hip_runtime.h>
 
 #include "contact.hpp"
@@ -37,17 +39,25 @@ __global__ void __launch_bounds__(kBlock) k_contact_collect(int N, int n_cand, i
   if (k0 + c < n_cand) B1[(int64_t)(k0 + c) * N + node] = x[i];
 }
 
-// One workgroup: S = B1[set][cand[set]] (c x c), y = a1 at the set's nodes
-// (3 right-hand sides), S = L L^T by right-looking Cholesky, then
-// lam = -L^{-T} L^{-1} y.  status = 1 on a non-positive pivot.
-__global__ void __launch_bounds__(kContactThreads) k_contact_capacitance(int N, const int32_t* __restrict__ cand,
-                                                                         const int32_t* __restrict__ set, int c,
-                                                                         const double* __restrict__ B1,
-                                                                         const double* __restrict__ a1,
-                                                                         double* __restrict__ lam, int* status) {
+// One workgroup, once per active set: S = B1[set][cand[set]] (c x c, SPD),
+// S = L L^T, then Sinv = S^{-1} into device memory.
+//  * Cholesky, one barrier per column: in step j, column j - 1 is scaled by
+//    its pivot's square root while the trailing block is updated with
+//    column j's unscaled entries, S[i][k] -= S[i][j] S[k][j] / S[j][j]; the
+//    two touch disjoint entries.  The diagonal of L goes to ld.
+//  * Inversion: thread j computes column j of L^{-1} by forward substitution
+//    and keeps it in row j of the strict upper triangle (its diagonal in
+//    dinv), which nothing else reads.
+//  * Sinv[a][b] = sum_{i >= max(a, b)} L^{-1}[i][a] L^{-1}[i][b].
+// status = 1 on a non-positive pivot.
+__global__ void __launch_bounds__(kContactThreads) k_contact_factor(int N, const int32_t* __restrict__ cand,
+                                                                    const int32_t* __restrict__ set, int c,
+                                                                    const double* __restrict__ B1,
+                                                                    double* __restrict__ Sinv, int* status) {
   extern __shared__ double lds[];
-  double* S = lds;          // [c][c], lower triangle becomes L
-  double* y = lds + c * c;  // [3][c]
+  double* S = lds;            // [c][c]
+  double* ld = lds + c * c;   // [c] diagonal of L
+  double* dinv = ld + c;      // [c] diagonal of L^{-1}
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) bad = 0;
@@ -55,49 +65,63 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_capacitance(int N, 
     const int k = idx / c, l = idx % c;
     S[idx] = B1[(int64_t)set[k] * N + cand[set[l]]];
   }
-  for (int idx = tid; idx < 3 * c; idx += nt) {
-    const int comp = idx / c, k = idx % c;
-    y[idx] = a1[(int64_t)comp * N + cand[set[k]]];
+  __syncthreads();
+  for (int j = 0; j <= c; ++j) {
+    if (j > 0) {
+      const double d = S[(j - 1) * c + (j - 1)];
+      const double l = d > 0.0 ? sqrt(d) : 1.0;
+      if (tid == 0) ld[j - 1] = l;
+      for (int i = j + tid; i < c; i += nt) S[i * c + (j - 1)] /= l;
+    }
+    if (j < c) {
+      const double d = S[j * c + j];
+      if (tid == 0 && !(d > 0.0)) bad = 1;
+      const double rd = d > 0.0 ? 1.0 / d : 0.0;
+      const int m = c - j - 1;
+      for (int idx = tid; idx < m * (m + 1) / 2; idx += nt) {
+        // idx -> (i, k), 0 <= k <= i < m, row by row over the lower triangle
+        int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+        while (i * (i + 1) / 2 > idx) --i;
+        const int k = idx - i * (i + 1) / 2;
+        const int ii = j + 1 + i, kk = j + 1 + k;
+        S[ii * c + kk] -= S[ii * c + j] * S[kk * c + j] * rd;
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < c; j += nt) {
+    const double wj = 1.0 / ld[j];
+    dinv[j] = wj;
+    for (int i = j + 1; i < c; ++i) {
+      double acc = S[i * c + j] * wj;
+      for (int k = j + 1; k < i; ++k) acc += S[i * c + k] * S[j * c + k];
+      S[j * c + i] = -acc / ld[i];
+    }
   }
   __syncthreads();
-  for (int j = 0; j < c; ++j) {
-    if (tid == 0) {
-      const double d = S[j * c + j];
-      if (!(d > 0.0)) bad = 1;
-      S[j * c + j] = d > 0.0 ? sqrt(d) : 1.0;
-    }
-    __syncthreads();
-    const double ljj = S[j * c + j];
-    for (int i = j + 1 + tid; i < c; i += nt) S[i * c + j] /= ljj;
-    __syncthreads();
-    const int m = c - j - 1;
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) S[i * c + k] -= S[i * c + j] * S[k * c + j];
-    }
-    __syncthreads();
+  for (int idx = tid; idx < c * c; idx += nt) {
+    const int a = idx / c, b = idx % c;
+    if (b > a) continue;
+    double acc = dinv[a] * (a == b ? dinv[a] : S[b * c + a]);
+    for (int i = a + 1; i < c; ++i) acc += S[a * c + i] * S[b * c + i];
+    Sinv[a * c + b] = acc;
+    Sinv[b * c + a] = acc;
   }
-  for (int j = 0; j < c; ++j) {  // L z = y
-    if (tid < 3) y[tid * c + j] /= S[j * c + j];
-    __syncthreads();
-    const int m = c - j - 1;
-    for (int idx = tid; idx < 3 * m; idx += nt) {
-      const int comp = idx / m, i = j + 1 + idx % m;
-      y[comp * c + i] -= S[i * c + j] * y[comp * c + j];
-    }
-    __syncthreads();
-  }
-  for (int j = c - 1; j >= 0; --j) {  // L^T w = z
-    if (tid < 3) y[tid * c + j] /= S[j * c + j];
-    __syncthreads();
-    for (int idx = tid; idx < 3 * j; idx += nt) {
-      const int comp = idx / j, i = idx % j;
-      y[comp * c + i] -= S[j * c + i] * y[comp * c + j];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < 3 * c; idx += nt) lam[idx] = -y[idx];
   if (tid == 0) *status = bad;
+}
+
+// lam[comp][a] = -sum_b Sinv[a][b] a1[comp][cand[set[b]]].
+__global__ void k_contact_lam(int N, const int32_t* __restrict__ cand, const int32_t* __restrict__ set, int c,
+                              const double* __restrict__ Sinv, const double* __restrict__ a1,
+                              double* __restrict__ lam) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 3 * c) return;
+  const int comp = idx / c, a = idx % c;
+  const double* ac = a1 + (int64_t)comp * N;
+  double acc = 0.0;
+  for (int b = 0; b < c; ++b) acc += Sinv[a * c + b] * ac[cand[set[b]]];
+  lam[idx] = -acc;
 }
 
 // x[comp][node] += sum_k B1[set[k]][node] lam[comp][k] for every node (the
@@ -140,7 +164,7 @@ __global__ void k_contact_set(int N, const int32_t* __restrict__ cand, const int
 
 }  // namespace
 
-size_t contact_capacitance_lds(int c) { return ((size_t)c * c + 3 * (size_t)c) * sizeof(double); }
+size_t contact_factor_lds(int c) { return ((size_t)c * c + 2 * (size_t)c) * sizeof(double); }
 
 void launch_contact_unit(hipStream_t s, int N, int n_cand, const int32_t* cand, int k0, double* b) {
   hipLaunchKernelGGL(k_contact_unit, dim3(1), dim3(64), 0, s, N, n_cand, cand, k0, b);
@@ -152,17 +176,21 @@ void launch_contact_collect(hipStream_t s, int N, int n_cand, int k0, const doub
                      k0, x, B1);
 }
 
-hipError_t launch_contact_capacitance(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
-                                      const double* B1, const double* a1, double* lam, int* status) {
-  const size_t lds = contact_capacitance_lds(c);
+hipError_t launch_contact_factor(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
+                                 const double* B1, double* Sinv, int* status) {
+  const size_t lds = contact_factor_lds(c);
   if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_contact_capacitance,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_contact_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_contact_capacitance, dim3(1), dim3(kContactThreads), lds, s, N, cand, set, c, B1, a1, lam,
-                     status);
+  hipLaunchKernelGGL(k_contact_factor, dim3(1), dim3(kContactThreads), lds, s, N, cand, set, c, B1, Sinv, status);
   return hipGetLastError();
+}
+
+void launch_contact_lam(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* Sinv,
+                        const double* a1, double* lam) {
+  hipLaunchKernelGGL(k_contact_lam, dim3((3 * c + 63) / 64), dim3(64), 0, s, N, cand, set, c, Sinv, a1, lam);
 }
 
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,

@@ -9,13 +9,15 @@
 namespace dpd {
 
 constexpr int kContactMaxSet = 120;    // active-set size: the c x c Cholesky stays in LDS
-constexpr int kContactThreads = 1024;  // threads of the one-workgroup Cholesky
+constexpr int kContactThreads = 1024;  // threads of the one-workgroup factorization
 
-size_t contact_capacitance_lds(int c);
+size_t contact_factor_lds(int c);
 void launch_contact_unit(hipStream_t s, int N, int n_cand, const int32_t* cand, int k0, double* b);
 void launch_contact_collect(hipStream_t s, int N, int n_cand, int k0, const double* x, double* B1);
-hipError_t launch_contact_capacitance(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
-                                      const double* B1, const double* a1, double* lam, int* status);
+hipError_t launch_contact_factor(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
+                                 const double* B1, double* Sinv, int* status);
+void launch_contact_lam(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* Sinv,
+                        const double* a1, double* lam);
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
                            double* x);
 void launch_contact_set(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* xstar,

@@ -63,9 +63,8 @@ def test_contact_solve_argument_errors():
         g.contact_prepare([fixed_node])
     with pytest.raises(L.DiffPDError):
         g.contact_prepare([int(cand[0]), int(cand[0])])
-    g.contact_prepare(cand)
-    with pytest.raises(L.DiffPDError):
-        g.contact_prepare(cand)                          # once per factorization
+    g.contact_prepare(cand[:5])
+    g.contact_prepare(cand)                              # replaces the candidate list
     xs = torch.zeros(3, 2, dtype=torch.float64, device="cuda:0")
     with pytest.raises(L.DiffPDError):
         g.contact_solve([3, 3], xs, b)                   # repeated index
@@ -73,6 +72,24 @@ def test_contact_solve_argument_errors():
         g.contact_solve([0, len(cand)], xs, b)           # out of range
     # the handle stays usable after rejected calls
     _check(g, o, cand, np.array([1, 4], np.int32), rng)
+    # a new factor discards the cached columns
+    g.set_youngs(np.asarray(sc.youngs, dtype=np.float64) * 1.1)   # refactorizes
+    with pytest.raises(L.DiffPDError):
+        g.contact_solve([1, 4], xs, b)
+
+
+def test_contact_solve_reuses_the_set_factor():
+    """Same set with new right-hand sides (the cached inverse), another set,
+    then the first set again: every result matches the oracle."""
+    sc = robot_scene()
+    g, o = pair(sc)
+    rng = np.random.default_rng(74)
+    cand = _candidates(o, rng, 40)
+    g.contact_prepare(cand)
+    s1 = np.sort(rng.choice(len(cand), 17, replace=False)).astype(np.int32)
+    s2 = np.sort(rng.choice(len(cand), 9, replace=False)).astype(np.int32)
+    for act in (s1, s1, s2, s1, s1):
+        _check(g, o, cand, act, rng)
 
 
 def test_contact_solve_full_size_block():
