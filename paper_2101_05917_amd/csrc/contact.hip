@@ -111,17 +111,42 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_factor(int N, const
   if (tid == 0) *status = bad;
 }
 
-// lam[comp][a] = -sum_b Sinv[a][b] a1[comp][cand[set[b]]].
-__global__ void k_contact_lam(int N, const int32_t* __restrict__ cand, const int32_t* __restrict__ set, int c,
-                              const double* __restrict__ Sinv, const double* __restrict__ a1,
-                              double* __restrict__ lam) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 3 * c) return;
-  const int comp = idx / c, a = idx % c;
-  const double* ac = a1 + (int64_t)comp * N;
-  double acc = 0.0;
-  for (int b = 0; b < c; ++b) acc += Sinv[a * c + b] * ac[cand[set[b]]];
-  lam[idx] = -acc;
+// lam[comp][a] = -sum_b Sinv[a][b] a1[comp][cand[set[b]]]: one workgroup,
+// the set's entries of a1 gathered into LDS once, then a wave per row of Sinv
+// (lanes over its columns, coalesced) and three wave sums.
+__global__ void __launch_bounds__(kContactThreads) k_contact_lam(int N, const int32_t* __restrict__ cand,
+                                                                 const int32_t* __restrict__ set, int c,
+                                                                 const double* __restrict__ Sinv,
+                                                                 const double* __restrict__ a1,
+                                                                 double* __restrict__ lam) {
+  __shared__ double t[3 * kContactMaxSet];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 3 * c; idx += blockDim.x) {
+    const int comp = idx / c, k = idx % c;
+    t[idx] = a1[(int64_t)comp * N + cand[set[k]]];
+  }
+  __syncthreads();
+  const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  for (int a = wid; a < c; a += nw) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = lane; b < c; b += 64) {
+      const double v = Sinv[a * c + b];
+      s0 += v * t[b];
+      s1 += v * t[c + b];
+      s2 += v * t[2 * c + b];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    if (lane == 0) {
+      lam[a] = -s0;
+      lam[c + a] = -s1;
+      lam[2 * c + a] = -s2;
+    }
+  }
 }
 
 // x[comp][node] += sum_k B1[set[k]][node] lam[comp][k] for every node (the
@@ -190,7 +215,7 @@ hipError_t launch_contact_factor(hipStream_t s, int N, const int32_t* cand, cons
 
 void launch_contact_lam(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* Sinv,
                         const double* a1, double* lam) {
-  hipLaunchKernelGGL(k_contact_lam, dim3((3 * c + 63) / 64), dim3(64), 0, s, N, cand, set, c, Sinv, a1, lam);
+  hipLaunchKernelGGL(k_contact_lam, dim3(1), dim3(kContactThreads), 0, s, N, cand, set, c, Sinv, a1, lam);
 }
 
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
