@@ -266,6 +266,50 @@ dpd_status dpd_contact_prepare(dpd_mesh* mesh, void* stream, const int32_t* node
 dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_host, int32_t c,
                              const double* xstar, const double* b, double* x);
 
+/* Time step with complementarity contact against the ground plane z = 0
+ * (Sec. Contact: eq:lcp, eq:time_integration_with_contact; Alg. 3 forward,
+ * Alg. 5 backward), on the candidates of the last dpd_contact_prepare.
+ *
+ * dpd_contact_forward_step: collision detection (a candidate whose ray
+ * x_j + t v_j, 0 <= t <= h, meets the plane gets the meeting point as its
+ * target, kind 1; one already below it gets (x_j, y_j, 0), kind 2), then
+ * Alg. 3: for the set C of candidates with a target, x = y with x_C = x*,
+ * local steps and reduced global steps (each one A^{-1} solve and the
+ * low-rank correction of dpd_contact_solve) until |grad g| over the free
+ * nodes outside C is within fwd_rel_tol of its first value (or fwd_abs_tol_rel
+ * of |M y / h^2|); then the contact forces r = grad g(x) on C update the set:
+ * a node with r_z < 0 leaves it (at most once per step, so the loop ends), a
+ * candidate below the plane joins it with target (x_j, y_j, 0) of its
+ * start-of-step position.  Repeats until the set stays the same.
+ *   x, v, act, x_next, v_next   as dpd_forward_step
+ *   kind_out    host, [n_cand] int32, overwritten: 0 (not in contact), 1
+ *               (ray target), 2 (static target), per candidate; the input
+ *               of the backward step
+ *   stats       fwd_iters = PD iterations over all sets, fwd_outer = sets
+ *               tried, fwd_rel_res = the largest final relative residual
+ * Synchronizes the stream (the set decisions are taken on the host from
+ * device results).  DPD_ESTATE without candidates, DPD_EINVAL when the set
+ * would exceed 120 nodes, DPD_NOT_CONVERGED when a set's PD loop reached
+ * fwd_max_iter (the outputs are still written).  The fwd_solver option is not
+ * used: the inner loop is Alg. 3's PD iteration, in FP64.
+ *
+ * dpd_contact_backward_step: z solves (A - dA)_{C̄×C̄} z = xbar_{C̄} (the
+ * reduced adjoint system) by Alg. 5's iteration, each step a reduced global
+ * step; dL/dy = M z / h^2; the targets carry dL/dx* = xbar_C - ((A - dA) z)_C
+ * back to x and v through their formulas (kind 1: t = -z_j / v_{j,z});
+ * parameter gradients as dpd_backward_step.
+ *   kind_host   host, [n_cand] int32 from the forward step (values 0..2)
+ *   other arguments as dpd_backward_step
+ * The bwd_solver option is not used (Alg. 5's fixed-point iteration, FP64).
+ * Synchronizes the stream.  DPD_NOT_CONVERGED when bwd_max_iter is reached. */
+dpd_status dpd_contact_forward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
+                                    const double* act, double* x_next, double* v_next, int32_t* kind_out,
+                                    dpd_stats* stats);
+dpd_status dpd_contact_backward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
+                                     const double* act, const double* x_next, const int32_t* kind_host,
+                                     const double* gx_next, const double* gv_next, double* gx, double* gv,
+                                     double* g_youngs, double* g_act, dpd_stats* stats);
+
 /* Kernel timing for roofline measurement.  After dpd_profile_start(mesh, k),
  * launches of kernel class k made by calls on this handle are timed and the
  * algorithmic bytes and flops of each timed launch (what the method must move
@@ -295,7 +339,8 @@ enum {
   DPD_PROF_SWEEP_FWD_WIDE = 6,   /* k_sweep_fwd_wide: forward level, wide blocks            */
   DPD_PROF_SWEEP_BWD_NARROW = 7, /* k_sweep_bwd_narrow: backward level of many small blocks */
   DPD_PROF_CG_DENSE = 8,         /* k_cg_dense: a whole fused conjugate-gradient solve      */
-  DPD_PROF_CONTACT_UPDATE = 9    /* k_contact_update: active-set columns of A^{-1} applied  */
+  DPD_PROF_CONTACT_UPDATE = 9,   /* k_contact_update: active-set columns of A^{-1} applied  */
+  DPD_PROF_CONTACT_DESCEND = 10  /* k_contact_descend: reduced global step of a contact step */
 };
 typedef struct {
   int64_t launches;

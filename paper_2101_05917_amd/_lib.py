@@ -74,7 +74,8 @@ class Result(C.Structure):
 
 
 DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4, "solve": 5,
-            "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7, "cg_dense": 8, "contact_update": 9}
+            "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7, "cg_dense": 8, "contact_update": 9,
+            "contact_descend": 10}
 
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
@@ -102,6 +103,9 @@ PROTOTYPES = {
     "dpd_rotations": (C.c_int, [_P, _P, _P, _P]),
     "dpd_contact_prepare": (C.c_int, [_P, _P, _P, C.c_int32]),
     "dpd_contact_solve": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P]),
+    "dpd_contact_forward_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, C.POINTER(Stats)]),
+    "dpd_contact_backward_step": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                            C.POINTER(Stats)]),
     "dpd_profile_start": (C.c_int, [_P, C.c_int32]),
     "dpd_profile_read": (C.c_int, [_P, _P, C.POINTER(KernelProfile)]),
     "dpd_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(_P)]),

@@ -99,6 +99,11 @@ struct dpd_mesh {
   double* contact_lam = nullptr;       // [3][kContactMaxSet]
   int32_t* contact_status = nullptr;   // non-positive pivot flag
   std::vector<int32_t> contact_cached; // the set whose inverse is cached (empty: none)
+  // time step with contact (dpd_contact_forward_step / dpd_contact_backward_step)
+  double* contact_tgt = nullptr;       // [3][cap] target of each candidate
+  int32_t* contact_kind = nullptr;     // [cap] 0: free, 1: ray target, 2: static target
+  uint8_t* contact_left = nullptr;     // [cap] left the set once in this step
+  uint8_t* contact_mask = nullptr;     // [N] Dirichlet nodes and the set's nodes
 };
 
 namespace {
@@ -1279,10 +1284,14 @@ dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_h
   m->contact_cached.clear();
   if (n_cand > m->contact_cap) {
     if ((rc = dev_alloc(m, &m->contact_cand, n_cand)) != DPD_OK ||
-        (rc = dev_alloc(m, &m->contact_B1, (int64_t)n_cand * N)) != DPD_OK)
+        (rc = dev_alloc(m, &m->contact_B1, (int64_t)n_cand * N)) != DPD_OK ||
+        (rc = dev_alloc(m, &m->contact_tgt, 3 * (int64_t)n_cand)) != DPD_OK ||
+        (rc = dev_alloc(m, &m->contact_kind, n_cand)) != DPD_OK ||
+        (rc = dev_alloc(m, &m->contact_left, n_cand)) != DPD_OK)
       return rc;
     m->contact_cap = n_cand;
   }
+  if (!m->contact_mask && (rc = dev_alloc(m, &m->contact_mask, N)) != DPD_OK) return rc;
   if (!m->contact_set &&
       ((rc = dev_alloc(m, &m->contact_set, kContactMaxSet)) != DPD_OK ||
        (rc = dev_alloc(m, &m->contact_Sinv, (int64_t)kContactMaxSet * kContactMaxSet)) != DPD_OK ||
@@ -1305,6 +1314,213 @@ dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_h
   return DPD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Make `set` (ascending candidate indices, at most kContactMaxSet) the set
+// whose capacitance inverse is cached: factorize and invert it unless it is
+// the cached one already (host synchronisation only then).
+dpd_status contact_use_set(dpd_mesh* m, hipStream_t s, const int32_t* set, int32_t c) {
+  if (c == 0 || (m->contact_cached.size() == (size_t)c && std::equal(set, set + c, m->contact_cached.begin())))
+    return DPD_OK;
+  m->contact_cached.clear();
+  HIPCHECK(m, hipMemcpyAsync(m->contact_set, set, sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+  HIPCHECK(m, launch_contact_factor(s, m->dm.N, m->contact_cand, m->contact_set, c, m->contact_B1, m->contact_Sinv,
+                                    m->contact_status));
+  int32_t bad = 0;
+  HIPCHECK(m, hipMemcpyAsync(&bad, m->contact_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  if (bad) return fail(m, DPD_ENOTSPD, "non-positive pivot in the contact capacitance matrix");
+  m->contact_cached.assign(set, set + c);
+  return DPD_OK;
+}
+
+// The set {i : kind[i] != 0} of a host kind array, ascending.
+dpd_status contact_set_of(dpd_mesh* m, const std::vector<int32_t>& kind, std::vector<int32_t>* set) {
+  set->clear();
+  for (int32_t i = 0; i < (int32_t)kind.size(); ++i)
+    if (kind[i]) set->push_back(i);
+  if ((int)set->size() > kContactMaxSet) return fail(m, DPD_EINVAL, "contact set exceeds 120 nodes");
+  return DPD_OK;
+}
+
+// mask = Dirichlet flags with the set's nodes added (from the device kinds).
+dpd_status contact_mask(dpd_mesh* m, hipStream_t s) {
+  HIPCHECK(m, hipMemcpyAsync(m->contact_mask, m->dm.fixed, (size_t)m->dm.N, hipMemcpyDeviceToDevice, s));
+  launch_contact_mark(s, m->contact_n, m->contact_cand, m->contact_kind, m->contact_mask);
+  return DPD_OK;
+}
+
+// x <- x - (A_{C̄×C̄})^{-1} r_{C̄} on the nodes outside the mask: d = A^{-1} r
+// into `d`, the capacitance correction, the masked update.
+void contact_reduced_step(dpd_mesh* m, hipStream_t s, int32_t c, const double* r, double* d, double* x,
+                          IterState* st, int k) {
+  const int N = m->dm.N;
+  solve(m, s, false, r, d, 1.0, 0, st, k);
+  if (c > 0) launch_contact_lam(s, N, m->contact_cand, m->contact_set, c, m->contact_Sinv, d, m->contact_lam, st);
+  ProfScope ps(m, s, DPD_PROF_CONTACT_DESCEND, 8.0 * ((double)c * N + 10.0 * N) + 8.0 * 4.0 * c,
+               6.0 * (double)c * N, st == m->st ? 0 : 1, k, false);
+  launch_contact_descend(s, N, m->contact_set, c, m->contact_B1, m->contact_lam, d, m->contact_mask, x, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+dpd_status dpd_contact_forward_step(dpd_mesh* m, void* stream, const double* x, const double* v,
+                                    const double* act, double* xn, double* vn, int32_t* kind_out,
+                                    dpd_stats* stats) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!m->contact_n) return fail(m, DPD_ESTATE, "no contact candidates (call dpd_contact_prepare)");
+  if (!x || !v || !xn || !vn || !kind_out) return fail(m, DPD_EINVAL, "null argument");
+  if (xn == x || xn == v || vn == x || vn == v || xn == vn)
+    return fail(m, DPD_EINVAL, "outputs must not alias inputs");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const dpd_options& o = m->opt;
+  const int N = m->dm.N, nc = m->contact_n;
+  const int max_it = std::max(0, o.fwd_max_iter);
+  DevMesh dmc = m->dm;  // the contact set joins the Dirichlet nodes
+  dmc.fixed = m->contact_mask;
+  launch_contact_detect(s, N, nc, m->contact_cand, o.h, x, v, m->contact_tgt, m->contact_kind, m->contact_left);
+  std::vector<int32_t> kind(nc), next(nc), set;
+  HIPCHECK(m, hipMemcpyAsync(kind.data(), m->contact_kind, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  int iters = 0, sets = 0;
+  bool converged = true, nonfinite = false;
+  double rel_res = 0.0;
+  for (;;) {
+    ++sets;
+    if ((rc = contact_set_of(m, kind, &set)) != DPD_OK) return rc;
+    const int32_t c = (int32_t)set.size();
+    if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK) return rc;
+    if ((rc = contact_mask(m, s)) != DPD_OK) return rc;
+    // Alg. 3's inner loop: x = y with x_C = x*, then local and reduced global
+    // steps until |grad g| on the free nodes outside C meets the tolerance
+    launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol, max_it);
+    launch_prologue(dmc, s, x, v, m->y, xn, m->st, m->partials, o.fwd_abs_tol_rel);
+    launch_contact_place(s, N, nc, m->contact_cand, m->contact_kind, m->contact_tgt, xn);
+    for (int k = 0;; ++k) {
+      {
+        ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0, 0, k, false);
+        launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
+      }
+      launch_node_residual(dmc, s, xn, m->y, m->fe, m->r, m->st, m->partials, k, max_it, 0);
+      if (k >= max_it) break;
+      contact_reduced_step(m, s, c, m->r, m->z, xn, m->st, k);
+      if ((k + 1) % o.check_every == 0) {
+        if ((rc = read_state(m, s)) != DPD_OK) return rc;
+        if (m->h_st->done) break;
+      }
+    }
+    if ((rc = read_state(m, s)) != DPD_OK) return rc;
+    iters += m->h_st->iter;
+    converged = converged && m->h_st->converged;
+    nonfinite = nonfinite || m->h_st->nonfinite;
+    rel_res = std::max(rel_res, m->h_st->r0sq > 0 ? std::sqrt(m->h_st->rsq / m->h_st->r0sq) : 0.0);
+    if (nonfinite) break;
+    // contact forces r = grad g(x) on the set (eq:tic_1) and the update of C
+    IterState* aux = m->st + 1;
+    launch_reset(s, aux, 0.0, 0);
+    launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, aux);
+    launch_node_residual(m->dm, s, xn, m->y, m->fe, m->r, aux, m->partials, 0, 0, 1);
+    launch_contact_active_set(s, N, nc, m->contact_cand, x, xn, m->r, m->contact_kind, m->contact_left,
+                              m->contact_tgt);
+    HIPCHECK(m, hipMemcpyAsync(next.data(), m->contact_kind, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+    if (next == kind) break;
+    kind.swap(next);
+    if (sets > 2 * nc + 1) return fail(m, DPD_ESTATE, "contact active set did not settle");
+  }
+  launch_velocity(m->dm, s, x, xn, vn);
+  HIPCHECK(m, hipGetLastError());
+  std::memcpy(kind_out, kind.data(), sizeof(int32_t) * nc);
+  HIPCHECK(m, hipStreamSynchronize(s));
+  if (stats) {
+    stats->fwd_iters = iters;
+    stats->fwd_outer = sets;
+    stats->converged = converged;
+    stats->inverted_qps = m->h_st->inverted;
+    stats->fwd_rel_res = rel_res;
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (nonfinite) return fail(m, DPD_ENONFINITE, "non-finite residual in the forward iteration");
+  if (!converged) return DPD_NOT_CONVERGED;
+  return DPD_OK;
+}
+
+dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x, const double* v,
+                                     const double* act, const double* xn, const int32_t* kind_host,
+                                     const double* gx_next, const double* gv_next, double* gx, double* gv,
+                                     double* g_youngs, double* g_act, dpd_stats* stats) {
+  dpd_status rc = check_ready(m);
+  if (rc != DPD_OK) return rc;
+  if (!m->contact_n) return fail(m, DPD_ESTATE, "no contact candidates (call dpd_contact_prepare)");
+  if (!x || !v || !xn || !kind_host || !gx_next || !gv_next || !gx || !gv)
+    return fail(m, DPD_EINVAL, "null argument");
+  if (gx == gx_next || gx == gv_next || gv == gx_next || gv == gv_next || gx == gv)
+    return fail(m, DPD_EINVAL, "outputs must not alias inputs");
+  const int N = m->dm.N, nc = m->contact_n;
+  std::vector<int32_t> kind(kind_host, kind_host + nc), set;
+  for (int32_t k : kind)
+    if (k < 0 || k > 2) return fail(m, DPD_EINVAL, "contact kind must be 0, 1 or 2");
+  if ((rc = contact_set_of(m, kind, &set)) != DPD_OK) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)stream;
+  const dpd_options& o = m->opt;
+  const int32_t c = (int32_t)set.size();
+  if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK) return rc;
+  HIPCHECK(m, hipMemcpyAsync(m->contact_kind, kind.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+  if ((rc = contact_mask(m, s)) != DPD_OK) return rc;
+  DevMesh dmc = m->dm;
+  dmc.fixed = m->contact_mask;
+  const int64_t n3 = 3 * (int64_t)N;
+  const int max_it = std::max(0, o.bwd_max_iter);
+  launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
+  // xbar = dL/dx_{i+1} + dL/dv_{i+1} / h, kept on C (it reaches x* there)
+  launch_lincomb(s, n3, m->xbar, 1.0, gx_next, 1.0 / o.h, gv_next);
+  launch_zero_fixed(m->dm, s, m->xbar);
+  launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
+  launch_fill(s, n3, m->z, 0.0);
+  launch_dot(dmc, s, m->xbar, m->xbar, m->st, m->partials, 0);
+  // Alg. 5: z <- z - (A_{C̄×C̄})^{-1} ((A - dA) z - xbar)_{C̄}, z = 0 on C
+  for (int k = 0;; ++k) {
+    {
+      ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), 0, k, false);
+      launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
+    }
+    launch_node_hvp(dmc, s, m->z, m->fe, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
+    if (k >= max_it) break;
+    contact_reduced_step(m, s, c, m->r, m->p, m->z, m->st, k);
+    if ((k + 1) % o.check_every == 0) {
+      if ((rc = read_state(m, s)) != DPD_OK) return rc;
+      if (m->h_st->done) break;
+    }
+  }
+  // r = (A - dA) z - xbar on every free node: -dL/dx* on C
+  launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, nullptr);
+  launch_node_hvp(m->dm, s, m->z, m->fe, m->xbar, m->r, nullptr, m->partials, 0, 0, 0);
+  launch_adj_epilogue(dmc, s, x, v, m->z, gv_next, gx, gv);
+  if (g_youngs || g_act) launch_grad_params(m->dm, s, xn, m->z, m->cache, g_youngs, g_act);
+  launch_contact_target_vjp(s, N, nc, m->contact_cand, m->contact_kind, x, v, m->r, gx, gv);
+  HIPCHECK(m, hipGetLastError());
+  if ((rc = read_state(m, s)) != DPD_OK) return rc;
+  const IterState& h = *m->h_st;
+  if (stats) {
+    stats->bwd_iters = h.iter;
+    stats->converged = h.converged;
+    stats->fallbacks = 0;
+    stats->inverted_qps = h.inverted;
+    stats->bwd_rel_res = h.nb2 > 0 ? std::sqrt(h.rsq / h.nb2) : 0.0;
+    stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (h.nonfinite) return fail(m, DPD_ENONFINITE, "non-finite residual in the adjoint iteration");
+  if (!h.converged) return DPD_NOT_CONVERGED;
+  return DPD_OK;
+}
+
 dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host, int32_t c,
                              const double* xstar, const double* b, double* x) {
   dpd_status rc = check_ready(m);
@@ -1322,19 +1538,8 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
   }
   hipStream_t s = (hipStream_t)stream;
   const int N = (int)m->hm.n_nodes;
-  if (c > 0 && !(m->contact_cached.size() == (size_t)c &&
-                 std::equal(set_host, set_host + c, m->contact_cached.begin()))) {
-    // a new active set: factorize and invert its capacitance matrix once
-    m->contact_cached.clear();
-    HIPCHECK(m, hipMemcpyAsync(m->contact_set, set_host, sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
-    HIPCHECK(m, launch_contact_factor(s, N, m->contact_cand, m->contact_set, c, m->contact_B1, m->contact_Sinv,
-                                      m->contact_status));
-    int32_t bad = 0;
-    HIPCHECK(m, hipMemcpyAsync(&bad, m->contact_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(m, hipStreamSynchronize(s));
-    if (bad) return fail(m, DPD_ENOTSPD, "non-positive pivot in the contact capacitance matrix");
-    m->contact_cached.assign(set_host, set_host + c);
-  }
+  // a new active set: its capacitance matrix is factorized and inverted once
+  if ((rc = contact_use_set(m, s, set_host, c)) != DPD_OK) return rc;
   launch_fill(s, 3 * (int64_t)N, x, 0.0);
   solve(m, s, false, b, x, 1.0, 0, nullptr);  // a1 = A^{-1} b
   if (c > 0) {
@@ -1352,7 +1557,7 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_UPDATE)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_DESCEND)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

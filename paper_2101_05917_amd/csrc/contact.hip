@@ -118,7 +118,8 @@ __global__ void __launch_bounds__(kContactThreads) k_contact_lam(int N, const in
                                                                  const int32_t* __restrict__ set, int c,
                                                                  const double* __restrict__ Sinv,
                                                                  const double* __restrict__ a1,
-                                                                 double* __restrict__ lam) {
+                                                                 double* __restrict__ lam, const IterState* st) {
+  if (st && st->done) return;
   __shared__ double t[3 * kContactMaxSet];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < 3 * c; idx += blockDim.x) {
@@ -178,6 +179,146 @@ __global__ void __launch_bounds__(kBlock) k_contact_update(int N, const int32_t*
   clock_exit(ck);
 }
 
+// One reduced global step of Alg. 3 (or Alg. 5) in correction form: with
+// d = A^{-1} r and lam from d, x <- x - (d + B1_C lam) at every node outside
+// the mask (Dirichlet nodes and the contact set, whose rows stay at their
+// prescribed values).  d + B1_C lam vanishes on C, so this is
+// x_{C̄} <- x_{C̄} - (A_{C̄×C̄})^{-1} r_{C̄}.
+__global__ void __launch_bounds__(kBlock) k_contact_descend(int N, const int32_t* __restrict__ set, int c,
+                                                            const double* __restrict__ B1,
+                                                            const double* __restrict__ lam,
+                                                            const double* __restrict__ d,
+                                                            const uint8_t* __restrict__ mask,
+                                                            double* __restrict__ x, const IterState* st,
+                                                            ClockArg ck) {
+  if (st && st->done) return;
+  clock_enter(ck);
+  __shared__ double sl[3 * kContactMaxSet];
+  __shared__ int ss[kContactMaxSet];
+  for (int idx = threadIdx.x; idx < 3 * c; idx += blockDim.x) sl[idx] = lam[idx];
+  for (int k = threadIdx.x; k < c; k += blockDim.x) ss[k] = set[k];
+  __syncthreads();
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node < N && !mask[node]) {
+    double a0 = d[node], a1 = d[(int64_t)N + node], a2 = d[2 * (int64_t)N + node];
+#pragma unroll 8
+    for (int k = 0; k < c; ++k) {
+      const double bk = B1[(int64_t)ss[k] * N + node];
+      a0 += bk * sl[k];
+      a1 += bk * sl[c + k];
+      a2 += bk * sl[2 * c + k];
+    }
+    x[node] -= a0;
+    x[(int64_t)N + node] -= a1;
+    x[2 * (int64_t)N + node] -= a2;
+  }
+  clock_exit(ck);
+}
+
+// Collision detection against the ground plane z = 0 for every candidate
+// (Sec. Contact, remarks on friction: the target is where the ray
+// x_j + t v_j, 0 <= t <= h, meets the plane).  kind 1 (ray): z_j >= 0 and
+// z_j + h v_z < 0 with v_z < 0, target x_j + t v_j at t = -z_j / v_z; kind 2
+// (static): a node already below the plane, target (x_j, y_j, 0); kind 0:
+// no contact.  Products and sums are rounded one by one (no fused
+// multiply-add), so the decision and the target are those of the plain
+// formula.  `left` (a node has left the set in this step) is cleared.
+__global__ void k_contact_detect(int N, int n_cand, const int32_t* __restrict__ cand, double h,
+                                 const double* __restrict__ x, const double* __restrict__ v,
+                                 double* __restrict__ tgt, int32_t* __restrict__ kind,
+                                 uint8_t* __restrict__ left) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cand) return;
+  const int64_t j = cand[i];
+  const double z = x[2 * N + j], vz = v[2 * N + j];
+  double p0 = x[j], p1 = x[N + j];
+  int k = 0;
+  if (__dadd_rn(z, __dmul_rn(h, vz)) < 0.0 && vz < 0.0) {
+    if (z >= 0.0) {
+      const double t = -z / vz;
+      p0 = __dadd_rn(p0, __dmul_rn(t, v[j]));
+      p1 = __dadd_rn(p1, __dmul_rn(t, v[N + j]));
+      k = 1;
+    } else {
+      k = 2;
+    }
+  }
+  kind[i] = k;
+  left[i] = 0;
+  tgt[i] = p0;
+  tgt[n_cand + i] = p1;
+  tgt[2 * n_cand + i] = 0.0;
+}
+
+// mask[cand[i]] = 1 for the candidates in the set (on a copy of the Dirichlet
+// flags).
+__global__ void k_contact_mark(int n_cand, const int32_t* __restrict__ cand, const int32_t* __restrict__ kind,
+                               uint8_t* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cand && kind[i]) mask[cand[i]] = 1;
+}
+
+// x at the set's nodes = their targets.
+__global__ void k_contact_place(int N, int n_cand, const int32_t* __restrict__ cand,
+                                const int32_t* __restrict__ kind, const double* __restrict__ tgt,
+                                double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cand || !kind[i]) return;
+  const int64_t j = cand[i];
+  x[j] = tgt[i];
+  x[N + j] = tgt[n_cand + i];
+  x[2 * N + j] = tgt[2 * n_cand + i];
+}
+
+// Active-set update of Alg. 3 from the reduced solution xn and r = grad g(xn)
+// (eq:tic_1, the contact forces on the set): a node of the set whose normal
+// force r_z is negative leaves it, unless it has left once in this step; a
+// node outside it below the plane joins it with the target (x0_j, y0_j, 0)
+// of its start-of-step position x0 (kind 2).
+__global__ void k_contact_active_set(int N, int n_cand, const int32_t* __restrict__ cand,
+                                     const double* __restrict__ x0, const double* __restrict__ xn,
+                                     const double* __restrict__ r, int32_t* __restrict__ kind,
+                                     uint8_t* __restrict__ left, double* __restrict__ tgt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cand) return;
+  const int64_t j = cand[i];
+  if (kind[i]) {
+    if (r[2 * N + j] < 0.0 && !left[i]) {
+      kind[i] = 0;
+      left[i] = 1;
+    }
+  } else if (xn[2 * N + j] < 0.0) {
+    kind[i] = 2;
+    tgt[i] = x0[j];
+    tgt[n_cand + i] = x0[N + j];
+    tgt[2 * n_cand + i] = 0.0;
+  }
+}
+
+// dL/dx* = xbar_C - (H z)_C = -r_C (r = H z - xbar), carried to x and v of
+// the step's start through the targets: kind 2, x* = (x, y, 0); kind 1,
+// x* = (x + t v_x, y + t v_y, 0) with t = -z / v_z (dt/dz = -1 / v_z,
+// dt/dv_z = z / v_z^2).  The rows are distinct nodes: no two threads meet.
+__global__ void k_contact_target_vjp(int N, int n_cand, const int32_t* __restrict__ cand,
+                                     const int32_t* __restrict__ kind, const double* __restrict__ x,
+                                     const double* __restrict__ v, const double* __restrict__ r,
+                                     double* __restrict__ gx, double* __restrict__ gv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cand || !kind[i]) return;
+  const int64_t j = cand[i];
+  const double a = -r[j], b = -r[N + j];
+  gx[j] += a;
+  gx[N + j] += b;
+  if (kind[i] == 1) {
+    const double z = x[2 * N + j], vx = v[j], vy = v[N + j], vz = v[2 * N + j];
+    const double t = -z / vz, sxy = vx * a + vy * b;
+    gv[j] += t * a;
+    gv[N + j] += t * b;
+    gx[2 * N + j] += -sxy / vz;
+    gv[2 * N + j] += sxy * z / (vz * vz);
+  }
+}
+
 // x at the active set's nodes = x* ([3][c]).
 __global__ void k_contact_set(int N, const int32_t* __restrict__ cand, const int32_t* __restrict__ set, int c,
                               const double* __restrict__ xstar, double* __restrict__ x) {
@@ -214,8 +355,43 @@ hipError_t launch_contact_factor(hipStream_t s, int N, const int32_t* cand, cons
 }
 
 void launch_contact_lam(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* Sinv,
-                        const double* a1, double* lam) {
-  hipLaunchKernelGGL(k_contact_lam, dim3(1), dim3(kContactThreads), 0, s, N, cand, set, c, Sinv, a1, lam);
+                        const double* a1, double* lam, const IterState* st) {
+  hipLaunchKernelGGL(k_contact_lam, dim3(1), dim3(kContactThreads), 0, s, N, cand, set, c, Sinv, a1, lam, st);
+}
+
+void launch_contact_descend(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
+                            const double* d, const uint8_t* mask, double* x, const IterState* st) {
+  DPD_LAUNCH(k_contact_descend, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, N, set, c, B1, lam, d, mask,
+             x, st);
+}
+
+static unsigned cand_blocks(int n_cand) { return (unsigned)((n_cand + 255) / 256); }
+
+void launch_contact_detect(hipStream_t s, int N, int n_cand, const int32_t* cand, double h, const double* x,
+                           const double* v, double* tgt, int32_t* kind, uint8_t* left) {
+  hipLaunchKernelGGL(k_contact_detect, dim3(cand_blocks(n_cand)), dim3(256), 0, s, N, n_cand, cand, h, x, v, tgt,
+                     kind, left);
+}
+
+void launch_contact_mark(hipStream_t s, int n_cand, const int32_t* cand, const int32_t* kind, uint8_t* mask) {
+  hipLaunchKernelGGL(k_contact_mark, dim3(cand_blocks(n_cand)), dim3(256), 0, s, n_cand, cand, kind, mask);
+}
+
+void launch_contact_place(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
+                          const double* tgt, double* x) {
+  hipLaunchKernelGGL(k_contact_place, dim3(cand_blocks(n_cand)), dim3(256), 0, s, N, n_cand, cand, kind, tgt, x);
+}
+
+void launch_contact_active_set(hipStream_t s, int N, int n_cand, const int32_t* cand, const double* x0,
+                               const double* xn, const double* r, int32_t* kind, uint8_t* left, double* tgt) {
+  hipLaunchKernelGGL(k_contact_active_set, dim3(cand_blocks(n_cand)), dim3(256), 0, s, N, n_cand, cand, x0, xn, r,
+                     kind, left, tgt);
+}
+
+void launch_contact_target_vjp(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
+                               const double* x, const double* v, const double* r, double* gx, double* gv) {
+  hipLaunchKernelGGL(k_contact_target_vjp, dim3(cand_blocks(n_cand)), dim3(256), 0, s, N, n_cand, cand, kind, x, v,
+                     r, gx, gv);
 }
 
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,

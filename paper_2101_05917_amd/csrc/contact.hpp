@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "device.hpp"
+
 namespace dpd {
 
 constexpr int kContactMaxSet = 120;    // active-set size: the c x c Cholesky stays in LDS
@@ -17,7 +19,19 @@ void launch_contact_collect(hipStream_t s, int N, int n_cand, int k0, const doub
 hipError_t launch_contact_factor(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c,
                                  const double* B1, double* Sinv, int* status);
 void launch_contact_lam(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* Sinv,
-                        const double* a1, double* lam);
+                        const double* a1, double* lam, const IterState* st = nullptr);
+// time step with contact (Alg. 3 / Alg. 5)
+void launch_contact_descend(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
+                            const double* d, const uint8_t* mask, double* x, const IterState* st);
+void launch_contact_detect(hipStream_t s, int N, int n_cand, const int32_t* cand, double h, const double* x,
+                           const double* v, double* tgt, int32_t* kind, uint8_t* left);
+void launch_contact_mark(hipStream_t s, int n_cand, const int32_t* cand, const int32_t* kind, uint8_t* mask);
+void launch_contact_place(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
+                          const double* tgt, double* x);
+void launch_contact_active_set(hipStream_t s, int N, int n_cand, const int32_t* cand, const double* x0,
+                               const double* xn, const double* r, int32_t* kind, uint8_t* left, double* tgt);
+void launch_contact_target_vjp(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
+                               const double* x, const double* v, const double* r, double* gx, double* gv);
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
                            double* x);
 void launch_contact_set(hipStream_t s, int N, const int32_t* cand, const int32_t* set, int c, const double* xstar,

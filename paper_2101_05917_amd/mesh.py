@@ -245,6 +245,7 @@ class Mesh:
         with torch.cuda.device(self.device):
             L.check(self.lib.dpd_contact_prepare(self.handle, _stream(self.device),
                                                  arr.ctypes.data_as(C.c_void_p), int(arr.size)), self.handle)
+        self._contact_count = int(arr.size)
 
     def contact_solve(self, active, xstar, b):
         """x with x_C = x* and A_{C̄×C̄} x_{C̄} = b_{C̄}; active: indices into the
@@ -261,6 +262,60 @@ class Mesh:
                                                arr.ctypes.data_as(C.c_void_p) if c else None, c,
                                                _ptr(xstar) if c else None, _ptr(b), _ptr(out)), self.handle)
         return out
+
+    def contact_forward_step(self, x, v, act=None, out=None, strict=False):
+        """One implicit-Euler step with complementarity contact on the prepared
+        candidates (Alg. 3, dpd_contact_forward_step).  Returns (x_next,
+        v_next, kind, stats): kind is the int32 numpy array of 0 / 1 (ray
+        target) / 2 (static target) per candidate."""
+        self._check_state(x, v)
+        self._check_elem(act)
+        xn, vn = out if out is not None else (torch.empty_like(x), torch.empty_like(v))
+        kind = np.zeros(self._n_candidates(), dtype=np.int32)
+        st = L.Stats()
+        with torch.cuda.device(self.device):
+            code = L.check(self.lib.dpd_contact_forward_step(
+                self.handle, _stream(self.device), _ptr(x), _ptr(v), _ptr(act), _ptr(xn), _ptr(vn),
+                kind.ctypes.data_as(C.c_void_p), C.byref(st)), self.handle)
+        stats = st.as_dict()
+        if code == L.DPD_NOT_CONVERGED:
+            if strict:
+                raise L.DiffPDError(code, f"contact forward step not converged: {stats}")
+            warnings.warn(f"contact forward step not converged: {stats}", RuntimeWarning, stacklevel=2)
+        return xn, vn, kind, stats
+
+    def contact_backward_step(self, x, v, act, x_next, kind, gx_next, gv_next, g_youngs=None,
+                              want_act=False, strict=False):
+        """Adjoint of a step with contact (Alg. 5, dpd_contact_backward_step).
+        Returns (gx, gv, g_act or None, stats); ``g_youngs`` is accumulated."""
+        self._check_state(x, v, x_next, gx_next, gv_next)
+        self._check_elem(act)
+        self._check_elem(g_youngs)
+        k = np.ascontiguousarray(np.asarray(kind, dtype=np.int32))
+        if k.size != self._n_candidates():
+            raise ValueError(f"kind must hold {self._n_candidates()} entries")
+        gx = torch.empty_like(gx_next)
+        gv = torch.empty_like(gv_next)
+        g_act = (torch.empty(self.n_elements, dtype=torch.float64, device=self.device)
+                 if want_act else None)
+        st = L.Stats()
+        with torch.cuda.device(self.device):
+            code = L.check(self.lib.dpd_contact_backward_step(
+                self.handle, _stream(self.device), _ptr(x), _ptr(v), _ptr(act), _ptr(x_next),
+                k.ctypes.data_as(C.c_void_p), _ptr(gx_next), _ptr(gv_next), _ptr(gx), _ptr(gv),
+                _ptr(g_youngs), _ptr(g_act), C.byref(st)), self.handle)
+        stats = st.as_dict()
+        if code == L.DPD_NOT_CONVERGED:
+            if strict:
+                raise L.DiffPDError(code, f"contact adjoint not converged: {stats}")
+            warnings.warn(f"contact adjoint not converged: {stats}", RuntimeWarning, stacklevel=2)
+        return gx, gv, g_act, stats
+
+    def _n_candidates(self) -> int:
+        n = getattr(self, "_contact_count", 0)
+        if not n:
+            raise L.DiffPDError(-5, "no contact candidates (call contact_prepare)")
+        return n
 
     # ------------------------------------------------------------------ timing
     def profile_start(self, kernel_class: str):

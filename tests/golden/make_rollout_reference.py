@@ -5,6 +5,12 @@ method on g (the implicit-Euler solution, eq:time_integration), each backward
 step by a direct solve of the adjoint system (eq:adjoint).  The loss is
 dot(c, x_T) with c ~ N(0, 1) (seed 0), node-major.
 
+A scene with complementarity-contact candidates (the rolling sphere) starts
+from its rigid initial velocity and steps with the oracle's Alg. 3 (Newton to
+round-off on each reduced system) and its adjoint (Alg. 5, direct reduced
+solve); its loss also weighs the final velocity, dot(c, x_T) + dot(d, v_T)
+with d ~ N(0, 1) (seed 1), and the contact kinds of every step are stored.
+
 usage: python tests/golden/make_rollout_reference.py c2 [steps]
 """
 import os
@@ -17,13 +23,41 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import workloads as W  # noqa: E402
-from oracle import model as om, forward as of, adjoint as oa  # noqa: E402
+from oracle import model as om, forward as of, adjoint as oa, contact as oc  # noqa: E402
+
+
+def contact_reference(name, sc, steps):
+    m = om.Model(sc)
+    cand = W.candidate_nodes(sc)
+    x, v = m.X.copy(), W.initial_velocity(sc)
+    xs, vs, kinds = [x], [v], []
+    t0 = time.time()
+    for t in range(steps):
+        x, v, info = oc.forward_step_contact(m, x, v, cand)
+        xs.append(x)
+        vs.append(v)
+        kinds.append(info["kind"])
+        print(f"forward {t} sets {info['sets']} contact {int((info['kind'] > 0).sum())} "
+              f"{time.time() - t0:.0f}s", flush=True)
+    c = W.loss_vector(m.N, sc.loss_seed)
+    d = W.loss_vector(m.N, sc.loss_seed + 1)
+    gx, gv = c.copy(), d.copy()
+    gE = np.zeros(m.E)
+    for t in range(steps - 1, -1, -1):
+        gx, gv, ge, _, _ = oc.backward_step_contact(m, xs[t], vs[t], None, xs[t + 1], cand, kinds[t], gx, gv)
+        gE += ge
+    out = os.path.join(HERE, f"{name}_rollout_reference.npz")
+    np.savez_compressed(out, steps=steps, loss=float(c @ xs[-1] + d @ vs[-1]), x_T=xs[-1], g_x0=gx, g_v0=gv,
+                        g_youngs=gE, kinds=np.array(kinds, dtype=np.int8))
+    print("wrote", out, f"{time.time() - t0:.0f}s")
 
 
 def main():
     name = sys.argv[1]
     sc = W.config(name)
     steps = int(sys.argv[2]) if len(sys.argv) > 2 else sc.steps
+    if "candidates_ijk" in sc.extra:
+        return contact_reference(name, sc, steps)
     m = om.Model(sc)
     x, v = m.X.copy(), np.zeros(3 * m.N)
     xs, vs = [x], [v]

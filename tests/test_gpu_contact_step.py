@@ -1,0 +1,102 @@
+"""Time step with complementarity contact through the C ABI (Sec. Contact:
+Alg. 3 forward, Alg. 5 backward), against the oracle's step (Newton to
+round-off on the reduced system, direct solve of the reduced adjoint)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import contact as oc, model as om
+from oracle_scenes import landing_block
+from paper_2101_05917_amd import _lib as L
+from parity_helpers import elem_dev, pair, rel, soa, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(fwd_rel_tol=1e-13, fwd_abs_tol_rel=0.0, fwd_max_iter=20000,
+             bwd_rel_tol=1e-13, bwd_max_iter=20000)
+
+
+def _forward_parity(g, o, cand, x, v, act=None, tol=1e-9):
+    xn, vn, kind, st = g.contact_forward_step(to_dev(x, o.N), to_dev(v, o.N),
+                                              None if act is None else elem_dev(act), strict=True)
+    rx, rv, info = oc.forward_step_contact(o, x, v, cand, act)
+    print("sets", st["fwd_outer"], info["sets"], "c", int((kind > 0).sum()), "iters", st["fwd_iters"],
+          "rel x", rel(soa(xn), rx), flush=True)
+    assert np.array_equal(kind, info["kind"])
+    assert st["fwd_outer"] == info["sets"]
+    assert rel(soa(xn), rx) <= tol
+    assert rel(soa(vn), rv) <= tol * np.linalg.norm(rx) / (o.h * np.linalg.norm(rv))
+    C = cand[kind > 0]
+    got = soa(xn)
+    for j in C:
+        assert got[3 * j + 2] == 0.0                      # on the plane exactly
+    return soa(xn), kind, info
+
+
+@pytest.mark.parametrize("muscles", [False, True])
+def test_landing_block_forward_and_backward(muscles):
+    sc, cand, x, v = landing_block(muscles=muscles)
+    g, o = pair(sc, **TIGHT)
+    g.contact_prepare(cand)
+    # the actuation under which the set loop cycles without the leave-once rule
+    act = np.random.default_rng(7).uniform(0.0, 1.0, sc.n_elements) if muscles else None
+    rng = np.random.default_rng(11)
+    xn, kind, info = _forward_parity(g, o, cand, x, v, act)
+    if muscles:
+        assert info["sets"] > 2                           # the leave-once rule was used
+    cx, cv = rng.standard_normal(3 * o.N), rng.standard_normal(3 * o.N)
+    gE = torch.zeros(sc.n_elements, dtype=torch.float64, device="cuda:0")
+    gx, gv, gact, st = g.contact_backward_step(
+        to_dev(x, o.N), to_dev(v, o.N), None if act is None else elem_dev(act), to_dev(xn, o.N), kind,
+        to_dev(cx, o.N), to_dev(cv, o.N), g_youngs=gE, want_act=muscles, strict=True)
+    rx, rv, rE, ract, _ = oc.backward_step_contact(o, x, v, act, xn, cand, kind, cx, cv)
+    print("bwd iters", st["bwd_iters"], "gx", rel(soa(gx), rx), "gv", rel(soa(gv), rv),
+          "gE", rel(gE.cpu().numpy(), rE), flush=True)
+    assert rel(soa(gx), rx) <= 1e-9
+    assert rel(soa(gv), rv) <= 1e-9
+    assert rel(gE.cpu().numpy(), rE) <= 1e-9
+    if muscles:
+        assert rel(gact.cpu().numpy(), ract) <= 1e-9
+
+
+def test_no_contact_equals_the_plain_step():
+    sc, cand, x, v = landing_block(lift=0.05)
+    g, o = pair(sc, **TIGHT)
+    g.contact_prepare(cand)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    xn, vn, kind, st = g.contact_forward_step(xd, vd, strict=True)
+    assert not kind.any() and st["fwd_outer"] == 1
+    xp, _, _ = g.forward_step(xd, vd, strict=True)
+    assert rel(soa(xn), soa(xp)) <= 1e-11
+
+
+def test_rolling_sphere_steps():
+    """The rolling sphere (552 elements, 72 candidates): a few steps, each
+    from the oracle's own previous state, with the set checked exactly."""
+    sc = W.config("sphere")
+    g, o = pair(sc, **dict(TIGHT, fwd_rel_tol=1e-11, fwd_max_iter=5000))   # 1e-13 is below round-off here
+    cand = W.candidate_nodes(sc)
+    g.contact_prepare(cand)
+    x, v = o.X.copy(), W.initial_velocity(sc)
+    for step in range(3):
+        _forward_parity(g, o, cand, x, v, tol=1e-8)
+        x, v, _ = oc.forward_step_contact(o, x, v, cand)
+
+
+def test_contact_step_argument_errors():
+    sc, cand, x, v = landing_block()
+    g, o = pair(sc)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    with pytest.raises(L.DiffPDError):
+        g.contact_forward_step(xd, vd)                    # not prepared
+    g.contact_prepare(cand)
+    xn, vn, kind, _ = g.contact_forward_step(xd, vd)
+    z = torch.zeros_like(xd)
+    bad = kind.copy()
+    bad[0] = 3
+    with pytest.raises(L.DiffPDError):
+        g.contact_backward_step(xd, vd, None, xn, bad, z, z)
+    with pytest.raises(ValueError):
+        g.contact_backward_step(xd, vd, None, xn, kind[:-1], z, z)
+    g.contact_backward_step(xd, vd, None, xn, kind, z, z)   # the handle stays usable
