@@ -44,7 +44,11 @@ KERNEL_NAMES = {"solve": "global step A^{-1} b: the per-level k_sweep_* launches
                                   "lanes-per-row variant)",
                 "sweep_bwd_narrow": "k_sweep_bwd_narrow (backward sweep level of many small blocks)",
                 "elem_hvp": "k_elem_hvp (adjoint local step dA p)",
-                "elem_forces": "k_elem_forces (forward local step)"}
+                "elem_forces": "k_elem_forces (forward local step)",
+                "contact_descend": "k_contact_descend (reduced global step of a contact step: the set's "
+                                   "columns of A^{-1} applied, masked update)",
+                "contact_dense": "k_contact_dense_step (reduced global step of a contact step with the "
+                                 "set's dense (A_{C̄×C̄})^{-1}: one dense product, masked update)"}
 
 
 def parse(argv=None):
@@ -90,7 +94,7 @@ def parse(argv=None):
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
     ap.add_argument("--roofline-kernel", default=None,
                     choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
-                             "elem_hvp", "elem_forces"])
+                             "elem_hvp", "elem_forces", "contact_descend", "contact_dense"])
     args = ap.parse_args(argv)
     # The legged body's ground contact, friction and inverted Gauss points
     # amplify each step's solver error along the 200-step rollout (about 5e3
@@ -98,10 +102,11 @@ def parse(argv=None):
     # 1e-6 needs tighter tolerances there (checked against the oracle's
     # reference in every run); a looser Eisenstat-Walker cap saves iterations.
     legged = args.config == "c3"
+    sphere = args.config == "sphere"
     if args.fwd_tol is None:
-        args.fwd_tol = 3e-11 if legged else 3e-8
+        args.fwd_tol = 3e-11 if legged else (1e-9 if sphere else 3e-8)
     if args.bwd_tol is None:
-        args.bwd_tol = 1e-9 if legged else 2e-7
+        args.bwd_tol = 1e-9 if legged or sphere else 2e-7
     if args.fwd_inner_tol is None:
         args.fwd_inner_tol = -0.3 if legged else -0.1
     return args
@@ -192,6 +197,128 @@ def cpu_baseline(scene, T_budget_s):
     return {"value": 3 * m.N * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"first {steps} of {scene.steps} steps, Newton (sparse LU) forward + direct "
                       f"adjoint, {dt:.1f} s wall, numpy/scipy on {cores} host cores"}
+
+
+def contact_rollout(mesh, X, V0, cx, cv, T, torch):
+    """Forward T steps with complementarity contact (Alg. 3), then the adjoint
+    (Alg. 5) back to step 0.  Returns (x_T, gx, gv, gE, kinds, stats)."""
+    x, v = X.clone(), V0.clone()
+    xs, vs, kinds = [x], [v], []
+    fi = bi = sets = 0
+    for t in range(T):
+        x, v, kind, st = mesh.contact_forward_step(x, v)
+        xs.append(x)
+        vs.append(v)
+        kinds.append(kind)
+        fi += st["fwd_iters"]
+        sets += st["fwd_outer"]
+    gx, gv = cx.clone(), cv.clone()
+    gE = torch.zeros(mesh.n_elements, dtype=torch.float64, device=X.device)
+    for t in range(T - 1, -1, -1):
+        gx, gv, _, st = mesh.contact_backward_step(xs[t], vs[t], None, xs[t + 1], kinds[t], gx, gv, g_youngs=gE)
+        bi += st["bwd_iters"]
+    return xs[-1], gx, gv, gE, np.array(kinds), {"fwd_iters": fi, "bwd_iters": bi, "sets": sets}
+
+
+def contact_cpu_baseline(scene, T_budget_s):
+    """The oracle's contact step on the host (Newton to round-off per set,
+    direct reduced adjoint), a prefix of the rollout bounded to about
+    ``T_budget_s`` seconds."""
+    from oracle import model as om, contact as oc
+    m = om.Model(scene)
+    cand = W.candidate_nodes(scene)
+    x, v = m.X.copy(), W.initial_velocity(scene)
+    xs, vs, kinds = [x], [v], []
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        x, v, info = oc.forward_step_contact(m, x, v, cand)
+        xs.append(x)
+        vs.append(v)
+        kinds.append(info["kind"])
+        steps += 1
+        if time.perf_counter() - t0 > 0.5 * T_budget_s or steps >= scene.steps:
+            break
+    gx, gv = W.loss_vector(m.N, scene.loss_seed), W.loss_vector(m.N, scene.loss_seed + 1)
+    for t in range(steps - 1, -1, -1):
+        gx, gv, _, _, _ = oc.backward_step_contact(m, xs[t], vs[t], None, xs[t + 1], cand, kinds[t], gx, gv)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {"value": 3 * m.N * steps / dt, "unit": "DoF-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {steps} of {scene.steps} steps, Alg. 3 with Newton (sparse LU) per contact set "
+                      f"+ direct reduced adjoint, {dt:.1f} s wall, numpy/scipy on {cores} host cores"}
+
+
+def contact_rollout_bench(args, mesh, scene, torch):
+    """Rollouts with complementarity contact (Sec. Contact, Alg. 3 and Alg. 5)
+    on the rolling sphere: T steps forward from the rigid initial roll, then
+    the adjoint of L = c . x_T + d . v_T back to step 0."""
+    T = args.rollout_steps or scene.steps
+    cand = W.candidate_nodes(scene)
+    progress(f"caching A^-1 columns of {len(cand)} contact candidates")
+    mesh.contact_prepare(cand)
+    X = mesh.rest_positions()
+    N = mesh.n_nodes
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a.reshape(N, 3).T)).to(X.device)  # noqa: E731
+    V0 = dev(W.initial_velocity(scene))
+    cx, cv = dev(W.loss_vector(N, scene.loss_seed)), dev(W.loss_vector(N, scene.loss_seed + 1))
+    for w in range(args.warmup):
+        progress(f"warm-up rollout {w + 1}/{args.warmup} ({T} steps)")
+        contact_rollout(mesh, X, V0, cx, cv, T, torch)
+    # the reduced global step: one dense product where A^{-1} is held dense, else the low-rank update
+    # after the factor's sweeps
+    kernel = args.roofline_kernel or ("contact_dense" if mesh.info["fused_blocks"] > 0 else "contact_descend")
+    torch.cuda.synchronize()
+    mesh.profile_start(kernel)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        progress(f"timed rollout {k + 1}/{args.steps}")
+        xT, gx, gv, gE, kinds, st = contact_rollout(mesh, X, V0, cx, cv, T, torch)
+    torch.cuda.synchronize()
+    progress("timed region done")
+    dt = (time.perf_counter() - t0) / args.steps
+    prof = mesh.profile_read()
+    avg_ms = prof["total_ms"] / max(1, prof["launches"])
+    bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                "traffic": measured_traffic(scene.name, kernel, "fp64", 1.0),
+                "kernel": KERNEL_NAMES[kernel], "launches": prof["launches"],
+                "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "timing": ("one solve in 17, HIP events around its launches behind a bounded stream hold"
+                           if kernel == "solve" else
+                           "every launch of the timed region that did work, by the device clock (s_memrealtime, "
+                           "100 MHz) from workgroup 0's entry to the last workgroup's exit")}
+    err = None
+    ref_path = os.path.join(HERE, "tests", "golden", f"{args.config}_rollout_reference.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        if int(ref["steps"]) == T:
+            aos = lambda t: t.cpu().numpy().T.reshape(-1)  # noqa: E731
+            err = {"g_x0": float(np.linalg.norm(aos(gx) - ref["g_x0"]) / np.linalg.norm(ref["g_x0"])),
+                   "g_v0": float(np.linalg.norm(aos(gv) - ref["g_v0"]) / np.linalg.norm(ref["g_v0"])),
+                   "g_youngs": float(np.linalg.norm(gE.cpu().numpy() - ref["g_youngs"]) /
+                                     np.linalg.norm(ref["g_youngs"])),
+                   "steps_with_a_different_contact_set": int(np.sum(np.any(kinds != ref["kinds"], axis=1)))}
+    out = {
+        "metric": "DoF-steps/s fwd+adjoint with complementarity contact (Alg. 3 + Alg. 5)",
+        "value": 3 * N * T / dt, "unit": "DoF-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{scene.name}: rolling sphere, {len(scene.cells)} hex, {3 * N} DoFs, {len(cand)} "
+                               f"contact candidates, {T} steps fwd+adjoint, loss dot(N(0,1), x_T) + "
+                               f"dot(N(0,1), v_T)",
+                   "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol},
+        "fwd_iters_per_step": st["fwd_iters"] / T, "bwd_iters_per_step": st["bwd_iters"] / T,
+        "contact_sets_per_step": st["sets"] / T,
+        "max_contact_nodes": int((kinds > 0).sum(axis=1).max()),
+        "grad_rel_err_vs_oracle": err,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle on the host)")
+        out["cpu_baseline"] = contact_cpu_baseline(scene, args.cpu_seconds)
+    return out
 
 
 def contact_bench(args, mesh, scene, torch):
@@ -314,6 +441,8 @@ KERNEL_SOURCES = {
     "cg_dense": ["cg_dense.hip", "device_math.hpp", "device.hpp"],
     "elem_hvp": ["kernels.hip", "device_math.hpp", "device.hpp"],
     "elem_forces": ["kernels.hip", "device_math.hpp", "device.hpp"],
+    "contact_dense": ["contact.hip", "contact.hpp", "device.hpp"],
+    "contact_descend": ["contact.hip", "contact.hpp", "device.hpp"],
 }
 SWEEP_SOURCES = ["sweeps.hip", "device.hpp", "internal.hpp"]
 
@@ -383,6 +512,9 @@ def main():
     mesh = Mesh.from_scene(scene, **solver_options(args))
     if args.contact_set:
         print(json.dumps(contact_bench(args, mesh, scene, torch)), flush=True)
+        return
+    if "candidates_ijk" in scene.extra:
+        print(json.dumps(contact_rollout_bench(args, mesh, scene, torch)), flush=True)
         return
     if args.roofline_kernel is None:
         # the kernel with the largest share of GPU time in the rocprofv3 summary of the workload:

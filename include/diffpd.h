@@ -291,7 +291,11 @@ dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_ho
  * device results).  DPD_ESTATE without candidates, DPD_EINVAL when the set
  * would exceed 120 nodes, DPD_NOT_CONVERGED when a set's PD loop reached
  * fwd_max_iter (the outputs are still written).  The fwd_solver option is not
- * used: the inner loop is Alg. 3's PD iteration, in FP64.
+ * used: the inner loop is Alg. 3's PD iteration, in FP64.  Where A^{-1} is held
+ * dense (fused_cg on, at most 2048 free nodes) the reduced matrix's inverse
+ * is formed once per set from it and each reduced global step is one dense
+ * product; otherwise each is a sweep of the factor plus the low-rank
+ * correction.
  *
  * dpd_contact_backward_step: z solves (A - dA)_{C̄×C̄} z = xbar_{C̄} (the
  * reduced adjoint system) by Alg. 5's iteration, each step a reduced global
@@ -340,7 +344,8 @@ enum {
   DPD_PROF_SWEEP_BWD_NARROW = 7, /* k_sweep_bwd_narrow: backward level of many small blocks */
   DPD_PROF_CG_DENSE = 8,         /* k_cg_dense: a whole fused conjugate-gradient solve      */
   DPD_PROF_CONTACT_UPDATE = 9,   /* k_contact_update: active-set columns of A^{-1} applied  */
-  DPD_PROF_CONTACT_DESCEND = 10  /* k_contact_descend: reduced global step of a contact step */
+  DPD_PROF_CONTACT_DESCEND = 10, /* k_contact_descend: reduced global step of a contact step */
+  DPD_PROF_CONTACT_DENSE = 11    /* k_contact_dense_step: the same with a dense inverse      */
 };
 typedef struct {
   int64_t launches;

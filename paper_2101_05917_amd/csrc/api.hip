@@ -104,6 +104,12 @@ struct dpd_mesh {
   int32_t* contact_kind = nullptr;     // [cap] 0: free, 1: ray target, 2: static target
   uint8_t* contact_left = nullptr;     // [cap] left the set once in this step
   uint8_t* contact_mask = nullptr;     // [N] Dirichlet nodes and the set's nodes
+  // with a dense A^{-1}: (A_{C̄×C̄})^{-1} held dense for the current set
+  double* contact_W = nullptr;         // [n][n] internal order, rows and columns of C zero
+  double* contact_T = nullptr;         // [n][kContactMaxSet] work
+  uint8_t* contact_inc = nullptr;      // [n] internal rows in C
+  bool contact_red_ok = false;
+  std::vector<int32_t> contact_red;    // the set W belongs to
 };
 
 namespace {
@@ -814,6 +820,7 @@ dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
   if (m) {  // cached columns of A^{-1} for contact belong to the previous factor
     m->contact_n = 0;
     m->contact_cached.clear();
+    m->contact_red_ok = false;
   }
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
   std::vector<double> panels;
@@ -1282,6 +1289,7 @@ dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_h
   }
   m->contact_n = 0;
   m->contact_cached.clear();
+  m->contact_red_ok = false;
   if (n_cand > m->contact_cap) {
     if ((rc = dev_alloc(m, &m->contact_cand, n_cand)) != DPD_OK ||
         (rc = dev_alloc(m, &m->contact_B1, (int64_t)n_cand * N)) != DPD_OK ||
@@ -1352,16 +1360,47 @@ dpd_status contact_mask(dpd_mesh* m, hipStream_t s) {
   return DPD_OK;
 }
 
-// x <- x - (A_{C̄×C̄})^{-1} r_{C̄} on the nodes outside the mask: d = A^{-1} r
-// into `d`, the capacitance correction, the masked update.
-void contact_reduced_step(dpd_mesh* m, hipStream_t s, int32_t c, const double* r, double* d, double* x,
-                          IterState* st, int k) {
+// Where A^{-1} is held dense, (A_{C̄×C̄})^{-1} of the current set is formed once
+// (a rank-c downdate of the dense inverse) and each reduced global step is one
+// dense launch; *dense reports whether that path is taken.
+dpd_status contact_use_dense(dpd_mesh* m, hipStream_t s, const int32_t* set, int32_t c, bool* dense) {
+  const int n = m->dcg.n;
+  *dense = m->dense_blocks > 0 && m->opt.fused_cg && m->ainv64 && n >= 1 && n <= kContactDenseMaxRows;
+  if (!*dense) return DPD_OK;
+  dpd_status rc;
+  if (!m->contact_W &&
+      ((rc = dev_alloc(m, &m->contact_W, (int64_t)n * n)) != DPD_OK ||
+       (rc = dev_alloc(m, &m->contact_T, (int64_t)n * kContactMaxSet)) != DPD_OK ||
+       (rc = dev_alloc(m, &m->contact_inc, n)) != DPD_OK))
+    return rc;
+  if (m->contact_red_ok && m->contact_red.size() == (size_t)c && std::equal(set, set + c, m->contact_red.begin()))
+    return DPD_OK;
+  HIPCHECK(m, launch_contact_reduced_inverse(s, n, m->dcg.inv, m->contact_cand, m->contact_set, c, m->ainv64,
+                                             m->contact_Sinv, m->contact_T, m->contact_inc, m->contact_W));
+  m->contact_red.assign(set, set + c);
+  m->contact_red_ok = true;
+  return DPD_OK;
+}
+
+// x <- x - (A_{C̄×C̄})^{-1} r_{C̄} on the nodes outside the mask: one dense
+// launch, or d = A^{-1} r into `d` by the factor's sweeps, the capacitance
+// correction and the masked update.
+dpd_status contact_reduced_step(dpd_mesh* m, hipStream_t s, int32_t c, bool dense, const double* r, double* d,
+                                double* x, IterState* st, int k) {
   const int N = m->dm.N;
+  if (dense) {
+    const double n = m->dcg.n;
+    ProfScope ps(m, s, DPD_PROF_CONTACT_DENSE, 8.0 * n * n + 72.0 * n, 6.0 * n * n, st == m->st ? 0 : 1, k,
+                 false);
+    HIPCHECK(m, launch_contact_dense_step(s, m->dcg.n, N, m->dcg.perm, m->contact_W, r, x, st));
+    return DPD_OK;
+  }
   solve(m, s, false, r, d, 1.0, 0, st, k);
   if (c > 0) launch_contact_lam(s, N, m->contact_cand, m->contact_set, c, m->contact_Sinv, d, m->contact_lam, st);
   ProfScope ps(m, s, DPD_PROF_CONTACT_DESCEND, 8.0 * ((double)c * N + 10.0 * N) + 8.0 * 4.0 * c,
                6.0 * (double)c * N, st == m->st ? 0 : 1, k, false);
   launch_contact_descend(s, N, m->contact_set, c, m->contact_B1, m->contact_lam, d, m->contact_mask, x, st);
+  return DPD_OK;
 }
 
 }  // namespace
@@ -1395,7 +1434,10 @@ dpd_status dpd_contact_forward_step(dpd_mesh* m, void* stream, const double* x, 
     ++sets;
     if ((rc = contact_set_of(m, kind, &set)) != DPD_OK) return rc;
     const int32_t c = (int32_t)set.size();
-    if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK) return rc;
+    bool dense = false;
+    if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK ||
+        (rc = contact_use_dense(m, s, set.data(), c, &dense)) != DPD_OK)
+      return rc;
     if ((rc = contact_mask(m, s)) != DPD_OK) return rc;
     // Alg. 3's inner loop: x = y with x_C = x*, then local and reduced global
     // steps until |grad g| on the free nodes outside C meets the tolerance
@@ -1409,7 +1451,7 @@ dpd_status dpd_contact_forward_step(dpd_mesh* m, void* stream, const double* x, 
       }
       launch_node_residual(dmc, s, xn, m->y, m->fe, m->r, m->st, m->partials, k, max_it, 0);
       if (k >= max_it) break;
-      contact_reduced_step(m, s, c, m->r, m->z, xn, m->st, k);
+      if ((rc = contact_reduced_step(m, s, c, dense, m->r, m->z, xn, m->st, k)) != DPD_OK) return rc;
       if ((k + 1) % o.check_every == 0) {
         if ((rc = read_state(m, s)) != DPD_OK) return rc;
         if (m->h_st->done) break;
@@ -1471,7 +1513,10 @@ dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x,
   hipStream_t s = (hipStream_t)stream;
   const dpd_options& o = m->opt;
   const int32_t c = (int32_t)set.size();
-  if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK) return rc;
+  bool dense = false;
+  if ((rc = contact_use_set(m, s, set.data(), c)) != DPD_OK ||
+      (rc = contact_use_dense(m, s, set.data(), c, &dense)) != DPD_OK)
+    return rc;
   HIPCHECK(m, hipMemcpyAsync(m->contact_kind, kind.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
   if ((rc = contact_mask(m, s)) != DPD_OK) return rc;
   DevMesh dmc = m->dm;
@@ -1493,7 +1538,7 @@ dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x,
     }
     launch_node_hvp(dmc, s, m->z, m->fe, m->xbar, m->r, m->st, m->partials, 1, k, max_it);
     if (k >= max_it) break;
-    contact_reduced_step(m, s, c, m->r, m->p, m->z, m->st, k);
+    if ((rc = contact_reduced_step(m, s, c, dense, m->r, m->p, m->z, m->st, k)) != DPD_OK) return rc;
     if ((k + 1) % o.check_every == 0) {
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
       if (m->h_st->done) break;
@@ -1557,7 +1602,7 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_DESCEND)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_DENSE)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

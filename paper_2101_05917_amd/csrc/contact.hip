@@ -319,6 +319,121 @@ __global__ void k_contact_target_vjp(int N, int n_cand, const int32_t* __restric
   }
 }
 
+// Dense reduced inverse for meshes whose A^{-1} is held dense (internal
+// order, n free nodes): W = A^{-1} - A^{-1}_{:,C} S^{-1} A^{-1}_{C,:}, the
+// inverse of A_{C̄×C̄} on the rows and columns outside C, with the rows and
+// columns of C set to 0.  T = A^{-1}_{:,C} S^{-1} first ([n][c]), then W by
+// rows, thread j over the columns (coalesced), the row's T in LDS.
+__global__ void __launch_bounds__(256) k_contact_red_t(int n, const int32_t* __restrict__ inv,
+                                                       const int32_t* __restrict__ cand,
+                                                       const int32_t* __restrict__ set, int c,
+                                                       const double* __restrict__ Ainv,
+                                                       const double* __restrict__ Sinv, double* __restrict__ T) {
+  __shared__ double row[kContactMaxSet];
+  const int i = blockIdx.x;
+  for (int a = threadIdx.x; a < c; a += blockDim.x) row[a] = Ainv[(int64_t)i * n + inv[cand[set[a]]]];
+  __syncthreads();
+  for (int b = threadIdx.x; b < c; b += blockDim.x) {
+    double acc = 0.0;
+    for (int a = 0; a < c; ++a) acc += row[a] * Sinv[a * c + b];
+    T[(int64_t)i * c + b] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_contact_red_w(int n, const int32_t* __restrict__ inv,
+                                                       const int32_t* __restrict__ cand,
+                                                       const int32_t* __restrict__ set, int c,
+                                                       const double* __restrict__ Ainv,
+                                                       const double* __restrict__ T, uint8_t* __restrict__ in_c,
+                                                       double* __restrict__ W) {
+  __shared__ double trow[kContactMaxSet];
+  __shared__ int cb[kContactMaxSet];
+  const int i = blockIdx.y;
+  for (int b = threadIdx.x; b < c; b += blockDim.x) {
+    trow[b] = T[(int64_t)i * c + b];
+    cb[b] = inv[cand[set[b]]];
+  }
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double w = 0.0;
+  if (!in_c[i] && !in_c[j]) {
+    w = Ainv[(int64_t)i * n + j];
+    for (int b = 0; b < c; ++b) w -= trow[b] * Ainv[(int64_t)cb[b] * n + j];
+  }
+  W[(int64_t)i * n + j] = w;
+}
+
+__global__ void k_contact_zero_u8(int n, uint8_t* __restrict__ a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+// in_c[row] = 1 for the internal rows of the set's nodes (on a zeroed array).
+__global__ void k_contact_red_mark(const int32_t* __restrict__ inv, const int32_t* __restrict__ cand,
+                                   const int32_t* __restrict__ set, int c, uint8_t* __restrict__ in_c) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < c) in_c[inv[cand[set[a]]]] = 1;
+}
+
+// x[perm[i]] -= sum_j W[i][j] r[perm[j]] for the n free rows: the reduced
+// global step x_{C̄} <- x_{C̄} - (A_{C̄×C̄})^{-1} r_{C̄} in one launch (W's rows and
+// columns of C are 0, so x_C keeps its value bit for bit).  Each workgroup
+// gathers r into LDS ([3][n], internal order); a wave takes rows in turn,
+// lanes over the columns (coalesced rows of W), three wave sums.
+__global__ void __launch_bounds__(kContactDenseThreads) k_contact_dense_step(
+    int n, int N, const int32_t* __restrict__ perm, const double* __restrict__ W, const double* __restrict__ r,
+    double* __restrict__ x, const IterState* st, ClockArg ck) {
+  if (st && st->done) return;
+  clock_enter(ck);
+  extern __shared__ double rl[];  // [3][n]
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int64_t p = perm[j];
+    rl[j] = r[p];
+    rl[n + j] = r[N + p];
+    rl[2 * n + j] = r[2 * (int64_t)N + p];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  for (int i = blockIdx.x * waves + wid; i < n; i += gridDim.x * waves) {
+    const double* row = W + (int64_t)i * n;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    // eight loads in flight per lane before their products (a row is at most
+    // 32 loads per lane)
+    for (int j0 = lane; j0 < n; j0 += 8 * 64) {
+      double w[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + 64 * u;
+        w[u] = j < n ? row[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < n) {
+          s0 += w[u] * rl[j];
+          s1 += w[u] * rl[n + j];
+          s2 += w[u] * rl[2 * n + j];
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    if (lane == 0) {
+      const int64_t p = perm[i];
+      x[p] -= s0;
+      x[N + p] -= s1;
+      x[2 * (int64_t)N + p] -= s2;
+    }
+  }
+  clock_exit(ck);
+}
+
 // x at the active set's nodes = x* ([3][c]).
 __global__ void k_contact_set(int N, const int32_t* __restrict__ cand, const int32_t* __restrict__ set, int c,
                               const double* __restrict__ xstar, double* __restrict__ x) {
@@ -386,6 +501,31 @@ void launch_contact_active_set(hipStream_t s, int N, int n_cand, const int32_t* 
                                const double* xn, const double* r, int32_t* kind, uint8_t* left, double* tgt) {
   hipLaunchKernelGGL(k_contact_active_set, dim3(cand_blocks(n_cand)), dim3(256), 0, s, N, n_cand, cand, x0, xn, r,
                      kind, left, tgt);
+}
+
+hipError_t launch_contact_reduced_inverse(hipStream_t s, int n, const int32_t* inv, const int32_t* cand,
+                                          const int32_t* set, int c, const double* Ainv, const double* Sinv,
+                                          double* T, uint8_t* in_c, double* W) {
+  hipLaunchKernelGGL(k_contact_zero_u8, dim3((n + 255) / 256), dim3(256), 0, s, n, in_c);
+  if (c > 0) {
+    hipLaunchKernelGGL(k_contact_red_mark, dim3((c + 63) / 64), dim3(64), 0, s, inv, cand, set, c, in_c);
+    hipLaunchKernelGGL(k_contact_red_t, dim3(n), dim3(256), 0, s, n, inv, cand, set, c, Ainv, Sinv, T);
+  }
+  hipLaunchKernelGGL(k_contact_red_w, dim3((n + 255) / 256, n), dim3(256), 0, s, n, inv, cand, set, c, Ainv, T, in_c,
+                     W);
+  return hipGetLastError();
+}
+
+size_t contact_dense_lds(int n) { return 3 * (size_t)n * sizeof(double); }
+
+hipError_t launch_contact_dense_step(hipStream_t s, int n, int N, const int32_t* perm, const double* W,
+                                     const double* r, double* x, const IterState* st) {
+  if (n < 1 || n > kContactDenseMaxRows) return hipErrorInvalidValue;
+  const size_t lds = contact_dense_lds(n);  // at most 48 KiB: no attribute needed
+  const int waves = kContactDenseThreads / 64;
+  const unsigned blocks = (unsigned)((n + waves - 1) / waves);
+  DPD_LAUNCH(k_contact_dense_step, dim3(blocks), dim3(kContactDenseThreads), lds, s, n, N, perm, W, r, x, st);
+  return hipGetLastError();
 }
 
 void launch_contact_target_vjp(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,

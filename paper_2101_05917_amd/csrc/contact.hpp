@@ -12,6 +12,8 @@ namespace dpd {
 
 constexpr int kContactMaxSet = 120;    // active-set size: the c x c Cholesky stays in LDS
 constexpr int kContactThreads = 1024;  // threads of the one-workgroup factorization
+constexpr int kContactDenseThreads = 512;   // dense reduced step: 8 waves, a row each in turn
+constexpr int kContactDenseMaxRows = 2048;  // its r in LDS: 3 x 2048 doubles (the dense inverse's limit)
 
 size_t contact_factor_lds(int c);
 void launch_contact_unit(hipStream_t s, int N, int n_cand, const int32_t* cand, int k0, double* b);
@@ -30,6 +32,12 @@ void launch_contact_place(hipStream_t s, int N, int n_cand, const int32_t* cand,
                           const double* tgt, double* x);
 void launch_contact_active_set(hipStream_t s, int N, int n_cand, const int32_t* cand, const double* x0,
                                const double* xn, const double* r, int32_t* kind, uint8_t* left, double* tgt);
+hipError_t launch_contact_reduced_inverse(hipStream_t s, int n, const int32_t* inv, const int32_t* cand,
+                                          const int32_t* set, int c, const double* Ainv, const double* Sinv,
+                                          double* T, uint8_t* in_c, double* W);
+size_t contact_dense_lds(int n);
+hipError_t launch_contact_dense_step(hipStream_t s, int n, int N, const int32_t* perm, const double* W,
+                                     const double* r, double* x, const IterState* st);
 void launch_contact_target_vjp(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
                                const double* x, const double* v, const double* r, double* gx, double* gv);
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,
