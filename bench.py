@@ -48,7 +48,9 @@ KERNEL_NAMES = {"solve": "global step A^{-1} b: the per-level k_sweep_* launches
                 "contact_descend": "k_contact_descend (reduced global step of a contact step: the set's "
                                    "columns of A^{-1} applied, masked update)",
                 "contact_dense": "k_contact_dense_step (reduced global step of a contact step with the "
-                                 "set's dense (A_{C̄×C̄})^{-1}: one dense product, masked update)"}
+                                 "set's dense (A_{C̄×C̄})^{-1}: one dense product, masked update)",
+                "contact_fused": "k_contact_fused (a contact set's whole PD or adjoint loop in one cooperative "
+                                 "launch: local step, residual, dense reduced global step per iteration)"}
 
 
 def parse(argv=None):
@@ -94,7 +96,7 @@ def parse(argv=None):
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
     ap.add_argument("--roofline-kernel", default=None,
                     choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
-                             "elem_hvp", "elem_forces", "contact_descend", "contact_dense"])
+                             "elem_hvp", "elem_forces", "contact_descend", "contact_dense", "contact_fused"])
     args = ap.parse_args(argv)
     # The legged body's ground contact, friction and inverted Gauss points
     # amplify each step's solver error along the 200-step rollout (about 5e3

@@ -106,6 +106,10 @@ typedef struct {
                               0: off; 2 + m: only with LDS placement m (bit 0:
                               r and q, bit 1: the workgroup's rows of A^{-1}),
                               off when m does not fit; read at factorization  */
+  int32_t contact_fused;   /* 1: with the dense inverse, the inner loop of a time
+                              step with contact (all iterations for one contact
+                              set) runs as one cooperative launch; 0: a few
+                              launches per iteration (same iteration)           */
 } dpd_options;
 
 typedef struct {
@@ -294,7 +298,8 @@ dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_ho
  * used: the inner loop is Alg. 3's PD iteration, in FP64.  Where A^{-1} is held
  * dense (fused_cg on, at most 2048 free nodes) the reduced matrix's inverse
  * is formed once per set from it and each reduced global step is one dense
- * product; otherwise each is a sweep of the factor plus the low-rank
+ * product (with contact_fused, the set's whole loop is one cooperative
+ * launch); otherwise each is a sweep of the factor plus the low-rank
  * correction.
  *
  * dpd_contact_backward_step: z solves (A - dA)_{C̄×C̄} z = xbar_{C̄} (the
@@ -345,7 +350,8 @@ enum {
   DPD_PROF_CG_DENSE = 8,         /* k_cg_dense: a whole fused conjugate-gradient solve      */
   DPD_PROF_CONTACT_UPDATE = 9,   /* k_contact_update: active-set columns of A^{-1} applied  */
   DPD_PROF_CONTACT_DESCEND = 10, /* k_contact_descend: reduced global step of a contact step */
-  DPD_PROF_CONTACT_DENSE = 11    /* k_contact_dense_step: the same with a dense inverse      */
+  DPD_PROF_CONTACT_DENSE = 11,   /* k_contact_dense_step: the same with a dense inverse      */
+  DPD_PROF_CONTACT_FUSED = 12    /* k_contact_fused: a contact set's whole inner loop        */
 };
 typedef struct {
   int64_t launches;

@@ -109,6 +109,7 @@ struct dpd_mesh {
   double* contact_T = nullptr;         // [n][kContactMaxSet] work
   uint8_t* contact_inc = nullptr;      // [n] internal rows in C
   bool contact_red_ok = false;
+  uint32_t* contact_bar = nullptr;     // [kContactBarWords] grid barrier of the fused contact loop
   std::vector<int32_t> contact_red;    // the set W belongs to
 };
 
@@ -519,6 +520,7 @@ dpd_status dpd_default_options(dpd_options* o) {
   o->check_every = 8;
   o->use_graphs = 1;
   o->fused_cg = 1;
+  o->contact_fused = 1;
   return DPD_OK;
 }
 
@@ -1382,6 +1384,33 @@ dpd_status contact_use_dense(dpd_mesh* m, hipStream_t s, const int32_t* set, int
   return DPD_OK;
 }
 
+// The whole inner loop of one contact set in one cooperative launch (dense
+// path with contact_fused): x0 holds the start iterate and receives the last;
+// x1 is work.  Algorithmic bytes per iteration: W, the element forces written
+// and read, connectivity and weights, node incidences, and x, y (or xbar)
+// and the new x.
+dpd_status contact_fused_loop(dpd_mesh* m, hipStream_t s, const DevMesh& dmc, int mode, double* x0,
+                              const double* y, const double* act, int max_it) {
+  const int n = m->dcg.n, N = m->dm.N;
+  if (!m->contact_bar) {
+    dpd_status rc = dev_alloc(m, &m->contact_bar, kContactBarWords);
+    if (rc != DPD_OK) return rc;
+  }
+  const double E = m->dm.E;
+  const double bytes = 8.0 * n * n + 2.0 * 24.0 * 8.0 * E + 40.0 * E + 32.0 * N + 72.0 * n;
+  {
+    ProfScope ps(m, s, DPD_PROF_CONTACT_FUSED, bytes, 6.0 * (double)n * n);
+    HIPCHECK(m, launch_contact_fused(s, dmc, m->dcg, m->dense_blocks, m->contact_W, x0, y, act,
+                                     mode ? m->cache : nullptr, m->st, m->contact_bar, mode, max_it));
+  }
+  uint32_t abort_word = 0;
+  HIPCHECK(m, hipMemcpyAsync(&abort_word, m->contact_bar + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  dpd_status rc = read_state(m, s);
+  if (rc != DPD_OK) return rc;
+  if (abort_word) return fail(m, DPD_EHIP, "fused contact loop: a grid barrier timed out");
+  return DPD_OK;
+}
+
 // x <- x - (A_{C̄×C̄})^{-1} r_{C̄} on the nodes outside the mask: one dense
 // launch, or d = A^{-1} r into `d` by the factor's sweeps, the capacitance
 // correction and the masked update.
@@ -1444,7 +1473,9 @@ dpd_status dpd_contact_forward_step(dpd_mesh* m, void* stream, const double* x, 
     launch_reset(s, m->st, o.fwd_rel_tol * o.fwd_rel_tol, max_it);
     launch_prologue(dmc, s, x, v, m->y, xn, m->st, m->partials, o.fwd_abs_tol_rel);
     launch_contact_place(s, N, nc, m->contact_cand, m->contact_kind, m->contact_tgt, xn);
-    for (int k = 0;; ++k) {
+    const bool fused = dense && o.contact_fused;
+    if (fused && (rc = contact_fused_loop(m, s, dmc, 0, xn, m->y, act, max_it)) != DPD_OK) return rc;
+    for (int k = 0; !fused; ++k) {
       {
         ProfScope ps(m, s, DPD_PROF_ELEM_FORCES, elem_forces_bytes(m), 0.0, 0, k, false);
         launch_elem_forces(m->dm, s, xn, act, m->fe, nullptr, m->st);
@@ -1531,7 +1562,9 @@ dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x,
   launch_fill(s, n3, m->z, 0.0);
   launch_dot(dmc, s, m->xbar, m->xbar, m->st, m->partials, 0);
   // Alg. 5: z <- z - (A_{C̄×C̄})^{-1} ((A - dA) z - xbar)_{C̄}, z = 0 on C
-  for (int k = 0;; ++k) {
+  const bool fused = dense && o.contact_fused;
+  if (fused && (rc = contact_fused_loop(m, s, dmc, 1, m->z, m->xbar, nullptr, max_it)) != DPD_OK) return rc;
+  for (int k = 0; !fused; ++k) {
     {
       ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), 0, k, false);
       launch_elem_hvp(m->dm, s, m->z, m->cache, m->fe, m->st);
@@ -1602,7 +1635,7 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_DENSE)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_FUSED)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

@@ -38,6 +38,10 @@ hipError_t launch_contact_reduced_inverse(hipStream_t s, int n, const int32_t* i
 size_t contact_dense_lds(int n);
 hipError_t launch_contact_dense_step(hipStream_t s, int n, int N, const int32_t* perm, const double* W,
                                      const double* r, double* x, const IterState* st);
+constexpr int kContactBarWords = 64 * 9;    // fused loop's barrier: 8 group counters on own lines, flags, abort
+hipError_t launch_contact_fused(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
+                                const double* W, double* x, const double* y, const double* act, const double* cache,
+                                IterState* st, uint32_t* bar, int mode, int max_iter);
 void launch_contact_target_vjp(hipStream_t s, int N, int n_cand, const int32_t* cand, const int32_t* kind,
                                const double* x, const double* v, const double* r, double* gx, double* gv);
 void launch_contact_update(hipStream_t s, int N, const int32_t* set, int c, const double* B1, const double* lam,

@@ -34,14 +34,19 @@ def _forward_parity(g, o, cand, x, v, act=None, tol=1e-9):
     return soa(xn), kind, info
 
 
-@pytest.mark.parametrize("fused", [1, 0], ids=["dense", "sweeps"])
+PATHS = {"fused": dict(fused_cg=1, contact_fused=1), "dense": dict(fused_cg=1, contact_fused=0),
+         "sweeps": dict(fused_cg=0, contact_fused=0)}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("muscles", [False, True])
-def test_landing_block_forward_and_backward(muscles, fused):
-    """Both reduced global steps: the dense inverse of A_{C̄×C̄} (fused_cg on)
-    and the factor's sweeps with the low-rank correction."""
+def test_landing_block_forward_and_backward(muscles, path):
+    """The three forms of the inner loop: one cooperative launch per contact
+    set, a dense reduced global step per iteration (the inverse of A_{C̄×C̄}
+    held dense), and the factor's sweeps with the low-rank correction."""
     sc, cand, x, v = landing_block(muscles=muscles)
-    g, o = pair(sc, **TIGHT, fused_cg=fused)
-    assert (g.info["fused_blocks"] > 0) == bool(fused)
+    g, o = pair(sc, **TIGHT, **PATHS[path])
+    assert (g.info["fused_blocks"] > 0) == (path != "sweeps")
     g.contact_prepare(cand)
     # the actuation under which the set loop cycles without the leave-once rule
     act = np.random.default_rng(7).uniform(0.0, 1.0, sc.n_elements) if muscles else None
@@ -75,13 +80,13 @@ def test_no_contact_equals_the_plain_step():
     assert rel(soa(xn), soa(xp)) <= 1e-11
 
 
-@pytest.mark.parametrize("fused", [1, 0], ids=["dense", "sweeps"])
-def test_rolling_sphere_steps(fused):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_rolling_sphere_steps(path):
     """The rolling sphere (552 elements, 72 candidates): a few steps, each
     from the oracle's own previous state, with the set checked exactly."""
     sc = W.config("sphere")
     # 1e-13 is below round-off here
-    g, o = pair(sc, **dict(TIGHT, fwd_rel_tol=1e-11, fwd_max_iter=5000, fused_cg=fused))
+    g, o = pair(sc, **dict(TIGHT, fwd_rel_tol=1e-11, fwd_max_iter=5000, **PATHS[path]))
     cand = W.candidate_nodes(sc)
     g.contact_prepare(cand)
     x, v = o.X.copy(), W.initial_velocity(sc)
