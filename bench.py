@@ -267,9 +267,9 @@ def contact_rollout_bench(args, mesh, scene, torch):
     for w in range(args.warmup):
         progress(f"warm-up rollout {w + 1}/{args.warmup} ({T} steps)")
         contact_rollout(mesh, X, V0, cx, cv, T, torch)
-    # the reduced global step: one dense product where A^{-1} is held dense, else the low-rank update
-    # after the factor's sweeps
-    kernel = args.roofline_kernel or ("contact_dense" if mesh.info["fused_blocks"] > 0 else "contact_descend")
+    # where A^{-1} is held dense: the fused loop of a contact set (one cooperative launch), else the
+    # low-rank update after the factor's sweeps
+    kernel = args.roofline_kernel or ("contact_fused" if mesh.info["fused_blocks"] > 0 else "contact_descend")
     torch.cuda.synchronize()
     mesh.profile_start(kernel)
     t0 = time.perf_counter()
@@ -315,6 +315,9 @@ def contact_rollout_bench(args, mesh, scene, torch):
         "contact_sets_per_step": st["sets"] / T,
         "max_contact_nodes": int((kinds > 0).sum(axis=1).max()),
         "grad_rel_err_vs_oracle": err,
+        "paper_context": "DiffPD on the paper's Rolling sphere: 14.0 s forward + 5.7 s backward for 100 steps "
+                         "of 2469 DoFs on its CPU (8 threads), 12,533 DoF-steps/s (Sec. Evaluation; another "
+                         "machine, tolerance 1e-6)",
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

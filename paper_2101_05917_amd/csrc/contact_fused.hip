@@ -18,7 +18,9 @@
 //            every workgroup takes the same stopping decision: mode 0 against
 //            the first norm and the absolute floor, mode 1 against |xbar|),
 //            then updates its own rows, x <- x - W r, and publishes them.
-//   barrier
+//   wait     for the workgroups owning rows at its element corners (instead of
+//            a second barrier; the residual and the partial norms are double-
+//            buffered by iteration parity for the workgroups still reading)
 // The iterate's own rows live in LDS between iterations.  Workgroup 0 records
 // the iteration state.  The data workgroups exchange (iterate, residual,
 // partial norms) is written and read with device-coherent accesses
@@ -104,6 +106,37 @@ __device__ bool fused_barrier(uint32_t* bar, uint32_t& round) {
   return ok != 0;
 }
 
+// After phase 2: once its own rows of the iterate are stored, the workgroup
+// waits for its own stores, raises its ready count to seq, and waits until the
+// ready counts of the workgroups owning rows at its element corners (nbr)
+// reach seq.  Bounded like the barrier, sharing its abort word.
+__device__ bool publish_wait(uint32_t* ready, const int32_t* __restrict__ nbr, int nnb, uint32_t seq,
+                             uint32_t* bar) {
+  __shared__ int ok;
+  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&ready[blockIdx.x], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = 1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nnb; i += blockDim.x) {
+    const int g = nbr[i];
+    for (uint32_t spin = 0;; ++spin) {
+      if (__hip_atomic_load(&ready[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= seq) break;
+      if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spin >= kFusedSpin) {
+        __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
 __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, DenseCG D, ClockArg ck) {
   if (P.st->done) return;
   clock_enter(ck);
@@ -123,8 +156,11 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
   const int j0 = min(n, b * P.rows), j1 = min(n, j0 + P.rows), R = j1 - j0;
   const GradTable G = grad_table(M.dx);
   const double tolsq = P.st->tolsq, atolsq = P.st->atolsq, nb2 = P.st->nb2;
-  double* rg = D.r;     // [3][n] published residual
-  double* part = D.part;  // [G] published partial norms
+  // published residual [2][3][n] and partial norms [2][G], by iteration parity:
+  // a workgroup may start iteration k + 1 while others still read iteration k's
+  const int32_t* nbrs = D.nbr + D.nbr_off[b];
+  const int nnb = D.nbr_off[b + 1] - D.nbr_off[b];
+  uint32_t pub = 0;
 
   // the workgroup's elements and rows
   const int e0 = D.blk_eoff[b], ne = D.blk_eoff[b + 1] - e0;
@@ -153,8 +189,13 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
   double r0sq = 0.0;
   int k = 0;
   for (;; ++k) {
+    double* rg = D.r + (k & 1) * 3 * n;
+    double* part = D.part + (k & 1) * G_;
     // ---- phase 1: element corners of the iterate (device-coherent loads;
-    // Dirichlet corners: the rest position, or 0 for the adjoint direction)
+    // Dirichlet corners: the rest position, or 0 for the adjoint direction);
+    // the adjoint's cache entries of this lane's Gauss point in the same round
+    double cq[19];
+    if (ev && P.mode == 1) load_gauss_cache(M, P.cache, el, a, cq);
     if (ev) {
       double u0, u1, u2;
       if (D.inv[corner] < 0) {
@@ -174,8 +215,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
     if (ev) {
       const int q = a;
       if (P.mode == 1) {
-        double cq[19], dF[9];
-        load_gauss_cache(M, P.cache, el, q, cq);
+        double dF[9];
         deformation_gradient(Tl, le, q, G, dF);
         hvp_stress_from_dF(M, Tl.Ps[le][q], dF, M.w_e[el], cq);
       } else {
@@ -258,16 +298,21 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
     const double bsum = block_sum(acc, ws);
     if (tid == 0) st_dev(&part[b], bsum);
     if (!fused_barrier(P.bar, round)) return;
-    // ---- phase 2: the whole residual and its norm, the decision, own rows
+    // ---- phase 2: the whole residual and its norm, the decision, own rows.
+    // Wave 0 issues its loads of the partial norms (at most 4 per lane, G <=
+    // 256) together with its share of the residual.
+    double pv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tid < 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = 64 * u + lane;
+        if (g < G_) pv[u] = ld_dev(&part[g]);
+      }
+    }
     for (int i = tid; i < 3 * n; i += blockDim.x) rv[i] = ld_dev(&rg[i]);
     if (tid < 64) {
-      double t = 0.0;
-      for (int g0 = 0; g0 < G_; g0 += 64) {
-        const double v = g0 + lane < G_ ? ld_dev(&part[g0 + lane]) : 0.0;
-        // fixed order: lane partial sums, then the wave's sum
-        t += v;
-      }
-      t = wave_sum(t);
+      // fixed order: each lane's partials, then the wave's sum
+      const double t = wave_sum(((pv[0] + pv[1]) + pv[2]) + pv[3]);
       if (tid == 0) tot_s = t;
     }
     __syncthreads();
@@ -325,7 +370,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
         st_dev(&P.x0[2 * N + node], x2n);
       }
     }
-    if (!fused_barrier(P.bar, round)) return;
+    if (!publish_wait(D.ready, nbrs, nnb, ++pub, P.bar)) return;
   }
   ClockArg c2 = ck;
   c2.bytes = ck.bytes * (double)(k + 1);
@@ -333,8 +378,9 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
   clock_exit(c2);
 }
 
-__global__ void k_contact_fused_reset(uint32_t* bar) {
+__global__ void k_contact_fused_reset(uint32_t* bar, uint32_t* ready, int G) {
   for (int i = threadIdx.x; i < kContactBarWords; i += blockDim.x) bar[i] = 0u;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) ready[i] = 0u;
 }
 
 }  // namespace
@@ -342,7 +388,8 @@ __global__ void k_contact_fused_reset(uint32_t* bar) {
 hipError_t launch_contact_fused(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
                                 const double* W, double* x, const double* y, const double* act, const double* cache,
                                 IterState* st, uint32_t* bar, int mode, int max_iter) {
-  if (D.n < 1 || D.n > kContactDenseMaxRows || blocks < 1 || D.rows > kDenseMaxRows) return hipErrorInvalidValue;
+  if (D.n < 1 || D.n > kContactDenseMaxRows || blocks < 1 || blocks > 256 || D.rows > kDenseMaxRows)
+    return hipErrorInvalidValue;
   FusedContact P{};
   P.M = Mmask;
   P.n = D.n;
@@ -356,7 +403,7 @@ hipError_t launch_contact_fused(hipStream_t s, const DevMesh& Mmask, const Dense
   P.cache = cache;
   P.st = st;
   P.bar = bar;
-  hipLaunchKernelGGL(k_contact_fused_reset, dim3(1), dim3(256), 0, s, bar);
+  hipLaunchKernelGGL(k_contact_fused_reset, dim3(1), dim3(256), 0, s, bar, D.ready, blocks);
   ClockArg ck = take_launch_clock();
   DenseCG Dv = D;
   void* args[] = {&P, &Dv, &ck};
