@@ -111,3 +111,30 @@ def test_contact_step_argument_errors():
     with pytest.raises(ValueError):
         g.contact_backward_step(xd, vd, None, xn, kind[:-1], z, z)
     g.contact_backward_step(xd, vd, None, xn, kind, z, z)   # the handle stays usable
+
+
+def test_sphere_rollout_at_bench_settings_matches_the_reference():
+    """The benchmark's workload and launch configuration: the 100-step sphere
+    rollout with contact, forward and adjoint at bench.py's tolerances; the
+    contact sets of every step equal the oracle reference's and the gradient
+    is within 1e-6 of it."""
+    import os
+    import bench
+    args = bench.parse(["--config", "sphere"])
+    sc = W.config("sphere")
+    from paper_2101_05917_amd.mesh import Mesh
+    g = Mesh.from_scene(sc, **bench.solver_options(args))
+    cand = W.candidate_nodes(sc)
+    g.contact_prepare(cand)
+    N = g.n_nodes
+    X = g.rest_positions()
+    V0 = to_dev(W.initial_velocity(sc), N)
+    cx, cv = to_dev(W.loss_vector(N, sc.loss_seed), N), to_dev(W.loss_vector(N, sc.loss_seed + 1), N)
+    _, gx, gv, gE, kinds, _ = bench.contact_rollout(g, X, V0, cx, cv, sc.steps, torch)
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "sphere_rollout_reference.npz"))
+    assert np.array_equal(kinds, ref["kinds"])
+    print("g_x0", rel(soa(gx), ref["g_x0"]), "g_v0", rel(soa(gv), ref["g_v0"]),
+          "g_E", rel(gE.cpu().numpy(), ref["g_youngs"]), flush=True)
+    assert rel(soa(gx), ref["g_x0"]) <= 1e-6
+    assert rel(soa(gv), ref["g_v0"]) <= 1e-6
+    assert rel(gE.cpu().numpy(), ref["g_youngs"]) <= 1e-6
