@@ -309,7 +309,11 @@ dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_ho
  * parameter gradients as dpd_backward_step.
  *   kind_host   host, [n_cand] int32 from the forward step (values 0..2)
  *   other arguments as dpd_backward_step
- * The bwd_solver option is not used (Alg. 5's fixed-point iteration, FP64).
+ * Alg. 5's fixed-point iteration, FP64; where the fused loop runs (dense
+ * inverse, contact_fused) and bwd_solver is DPD_BWD_PCG, its quasi-Newton
+ * acceleration instead: conjugate gradients on the same reduced system
+ * preconditioned by the reduced inverse, falling back to Alg. 5's iteration
+ * from the current z on non-positive curvature (stats->fallbacks = 1).
  * Synchronizes the stream.  DPD_NOT_CONVERGED when bwd_max_iter is reached. */
 dpd_status dpd_contact_forward_step(dpd_mesh* mesh, void* stream, const double* x, const double* v,
                                     const double* act, double* x_next, double* v_next, int32_t* kind_out,
@@ -351,7 +355,8 @@ enum {
   DPD_PROF_CONTACT_UPDATE = 9,   /* k_contact_update: active-set columns of A^{-1} applied  */
   DPD_PROF_CONTACT_DESCEND = 10, /* k_contact_descend: reduced global step of a contact step */
   DPD_PROF_CONTACT_DENSE = 11,   /* k_contact_dense_step: the same with a dense inverse      */
-  DPD_PROF_CONTACT_FUSED = 12    /* k_contact_fused: a contact set's whole inner loop        */
+  DPD_PROF_CONTACT_FUSED = 12,   /* k_contact_fused: a contact set's whole inner loop        */
+  DPD_PROF_CONTACT_FUSED_CG = 13 /* k_contact_fused_cg: the contact adjoint's CG loop         */
 };
 typedef struct {
   int64_t launches;

@@ -75,7 +75,8 @@ class Result(C.Structure):
 
 DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4, "solve": 5,
             "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7, "cg_dense": 8, "contact_update": 9,
-            "contact_descend": 10, "contact_dense": 11, "contact_fused": 12}
+            "contact_descend": 10, "contact_dense": 11, "contact_fused": 12,
+            "contact_fused_cg": 13}
 
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)

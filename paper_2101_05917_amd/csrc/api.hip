@@ -1411,6 +1411,32 @@ dpd_status contact_fused_loop(dpd_mesh* m, hipStream_t s, const DevMesh& dmc, in
   return DPD_OK;
 }
 
+// The contact adjoint by conjugate gradients preconditioned with the set's
+// reduced inverse, one cooperative launch, into m->z (from z = 0).
+// Algorithmic bytes per iteration: W, the rotation cache, connectivity and
+// weights, node incidences, and the own-row vectors.
+dpd_status contact_fused_cg(dpd_mesh* m, hipStream_t s, const DevMesh& dmc, int max_it) {
+  const int n = m->dcg.n, N = m->dm.N;
+  if (!m->contact_bar) {
+    dpd_status rc = dev_alloc(m, &m->contact_bar, kContactBarWords);
+    if (rc != DPD_OK) return rc;
+  }
+  const double E = m->dm.E;
+  const double rows = m->opt.muscle_k > 0.0 ? 19.0 : 15.0;
+  const double bytes = 8.0 * n * n + 8.0 * rows * 8.0 * E + 40.0 * E + 32.0 * N + 8.0 * 3.0 * n * 6.0;
+  {
+    ProfScope ps(m, s, DPD_PROF_CONTACT_FUSED_CG, bytes, 6.0 * (double)n * n);
+    HIPCHECK(m, launch_contact_fused_cg(s, dmc, m->dcg, m->dense_blocks, m->contact_W, m->z, m->xbar, m->cache,
+                                        m->st, m->contact_bar, max_it));
+  }
+  uint32_t abort_word = 0;
+  HIPCHECK(m, hipMemcpyAsync(&abort_word, m->contact_bar + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  dpd_status rc = read_state(m, s);
+  if (rc != DPD_OK) return rc;
+  if (abort_word) return fail(m, DPD_EHIP, "fused contact adjoint: a grid barrier timed out");
+  return DPD_OK;
+}
+
 // x <- x - (A_{C̄×C̄})^{-1} r_{C̄} on the nodes outside the mask: one dense
 // launch, or d = A^{-1} r into `d` by the factor's sweeps, the capacitance
 // correction and the masked update.
@@ -1561,9 +1587,23 @@ dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x,
   launch_adj_cache(m->dm, s, xn, act, m->cache, m->st);
   launch_fill(s, n3, m->z, 0.0);
   launch_dot(dmc, s, m->xbar, m->xbar, m->st, m->partials, 0);
-  // Alg. 5: z <- z - (A_{C̄×C̄})^{-1} ((A - dA) z - xbar)_{C̄}, z = 0 on C
+  // Alg. 5: z <- z - (A_{C̄×C̄})^{-1} ((A - dA) z - xbar)_{C̄}, z = 0 on C; with
+  // the fused loop and bwd_solver = PCG, its quasi-Newton acceleration (CG
+  // preconditioned by the reduced inverse), continued by Alg. 5's iteration
+  // from the current z if it meets non-positive curvature
   const bool fused = dense && o.contact_fused;
-  if (fused && (rc = contact_fused_loop(m, s, dmc, 1, m->z, m->xbar, nullptr, max_it)) != DPD_OK) return rc;
+  int fallbacks = 0;
+  if (fused && o.bwd_solver == DPD_BWD_PCG) {
+    if ((rc = contact_fused_cg(m, s, dmc, max_it)) != DPD_OK) return rc;
+    if (m->h_st->curvature) {
+      fallbacks = 1;
+      launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
+      launch_dot(dmc, s, m->xbar, m->xbar, m->st, m->partials, 0);
+      if ((rc = contact_fused_loop(m, s, dmc, 1, m->z, m->xbar, nullptr, max_it)) != DPD_OK) return rc;
+    }
+  } else if (fused && (rc = contact_fused_loop(m, s, dmc, 1, m->z, m->xbar, nullptr, max_it)) != DPD_OK) {
+    return rc;
+  }
   for (int k = 0; !fused; ++k) {
     {
       ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), 0, k, false);
@@ -1589,7 +1629,7 @@ dpd_status dpd_contact_backward_step(dpd_mesh* m, void* stream, const double* x,
   if (stats) {
     stats->bwd_iters = h.iter;
     stats->converged = h.converged;
-    stats->fallbacks = 0;
+    stats->fallbacks = fallbacks;
     stats->inverted_qps = h.inverted;
     stats->bwd_rel_res = h.nb2 > 0 ? std::sqrt(h.rsq / h.nb2) : 0.0;
     stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1635,7 +1675,7 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_FUSED)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_FUSED_CG)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

@@ -39,6 +39,9 @@ size_t contact_dense_lds(int n);
 hipError_t launch_contact_dense_step(hipStream_t s, int n, int N, const int32_t* perm, const double* W,
                                      const double* r, double* x, const IterState* st);
 constexpr int kContactBarWords = 64 * 9;    // fused loop's barrier: 8 group counters on own lines, flags, abort
+hipError_t launch_contact_fused_cg(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
+                                   const double* W, double* z, const double* xbar, const double* cache,
+                                   IterState* st, uint32_t* bar, int max_iter);
 hipError_t launch_contact_fused(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
                                 const double* W, double* x, const double* y, const double* act, const double* cache,
                                 IterState* st, uint32_t* bar, int mode, int max_iter);

@@ -378,12 +378,285 @@ __global__ void __launch_bounds__(kDenseBlock) k_contact_fused(FusedContact P, D
   clock_exit(c2);
 }
 
+// Alg. 5's system solved by conjugate gradients preconditioned with the set's
+// reduced inverse W (the quasi-Newton acceleration of the adjoint, on the
+// reduced system; Chronopoulos-Gear arrangement, one exchange of partial sums
+// per iteration).  Same partition and exchange as k_contact_fused; per
+// iteration, with the whole residual r_k in LDS:
+//   own rows of s = W r_k, published; wait for the neighbours' rows;
+//   w = (A - dA) s on the own rows (elements touching them; zero on the set),
+//   partial sums r.s, s.w, r.r published;  barrier;
+//   every workgroup sums the partials in workgroup order (same bits), stops
+//   when |r_k| <= tol |xbar| (or at the cap, or on non-positive curvature,
+//   recorded for the host's fallback), else updates its rows of p, q, z, r and
+//   publishes r;  barrier;  gather r_{k+1}.
+// z (own rows, in LDS) is written to x0 at the end.
+__global__ void __launch_bounds__(kDenseBlock) k_contact_fused_cg(FusedContact P, DenseCG D, ClockArg ck) {
+  if (P.st->done) return;
+  clock_enter(ck);
+  extern __shared__ double rv[];  // [3][n] r_k, internal order
+  __shared__ ElemTileT<kDenseElems> Tl;
+  __shared__ double fl[kDenseElems][8][3];
+  __shared__ double ws[kDenseBlock / 64];
+  __shared__ double sums[3];
+  constexpr int MR = kDenseMaxRows;
+  __shared__ double own_z[3 * MR], own_r[3 * MR], own_p[3 * MR], own_q[3 * MR], own_s[3 * MR];
+  __shared__ double row_c[MR];
+  __shared__ int row_node[MR], row_inc[MR][8], row_free[MR], row_pen[MR];
+  const DevMesh& M = P.M;
+  const int n = P.n, tid = threadIdx.x, b = blockIdx.x, G_ = gridDim.x;
+  const int64_t N = M.N;
+  const int j0 = min(n, b * P.rows), j1 = min(n, j0 + P.rows), R = j1 - j0;
+  const GradTable G = grad_table(M.dx);
+  const double tolsq = P.st->tolsq, nb2 = P.st->nb2;
+  double* rg = D.r;      // [3][n] published r
+  double* sg = D.q;      // [3][n] published s
+  double* part = D.part; // [3][G] published partial sums
+  const int32_t* nbrs = D.nbr + D.nbr_off[b];
+  const int nnb = D.nbr_off[b + 1] - D.nbr_off[b];
+  const int e0 = D.blk_eoff[b], ne = D.blk_eoff[b + 1] - e0;
+  const int le = tid >> 3, a = tid & 7;
+  const bool ev = le < ne;
+  const int el = ev ? D.blk_elems[e0 + le] : 0;
+  const int corner = ev ? M.conn[(int64_t)a * M.E + el] : 0;
+  const int crow = ev ? D.inv[corner] : -1;
+  if (tid < R) {
+    const int node = D.perm[j0 + tid];
+    row_node[tid] = node;
+    row_c[tid] = M.mass[node] / (M.h * M.h);
+    row_free[tid] = M.fixed[node] ? 0 : 1;  // the contact set is masked
+    row_pen[tid] = M.cmask[node] ? 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) row_inc[tid][q] = D.row_inc[8 * (j0 + tid) + q];
+  }
+  __syncthreads();
+  // r_0 = xbar on the free rows outside the set, z = p = q = 0
+  if (tid < 3 * R) {
+    const int c = tid / R, i = tid % R;
+    const double v = row_free[i] ? P.y[c * N + row_node[i]] : 0.0;
+    own_r[c * MR + i] = v;
+    own_z[c * MR + i] = 0.0;
+    own_p[c * MR + i] = 0.0;
+    own_q[c * MR + i] = 0.0;
+    st_dev(&rg[c * n + j0 + i], v);
+  }
+  const int lane = tid & 63, wid = tid >> 6, waves = blockDim.x >> 6;
+  uint32_t round = 0, pub = 0;
+  double gamma_old = 1.0, alpha_old = 1.0;
+  int k = 0;
+  bool alive = fused_barrier(P.bar, round);
+  for (; alive; ++k) {
+    for (int i = tid; i < 3 * n; i += blockDim.x) rv[i] = ld_dev(&rg[i]);
+    __syncthreads();
+    // s = W r on the own rows (the set's rows of W are 0), published
+    for (int i = wid; i < R; i += waves) {
+      const double* row = P.W + (int64_t)(j0 + i) * n;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int jb = lane; jb < n; jb += 8 * 64) {
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = jb + 64 * u;
+          w[u] = j < n ? row[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = jb + 64 * u;
+          if (j < n) {
+            s0 += w[u] * rv[j];
+            s1 += w[u] * rv[n + j];
+            s2 += w[u] * rv[2 * n + j];
+          }
+        }
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        own_s[i] = s0;
+        own_s[MR + i] = s1;
+        own_s[2 * MR + i] = s2;
+        st_dev(&sg[j0 + i], s0);
+        st_dev(&sg[n + j0 + i], s1);
+        st_dev(&sg[2 * n + j0 + i], s2);
+      }
+    }
+    if (!publish_wait(D.ready, nbrs, nnb, ++pub, P.bar)) return;
+    // w = (A - dA) s on the own rows
+    double cq[19];
+    if (ev) load_gauss_cache(M, P.cache, el, a, cq);
+    if (ev) {
+      double u0 = 0.0, u1 = 0.0, u2 = 0.0;  // Dirichlet corners: 0
+      if (crow >= 0) {
+        u0 = ld_dev(&sg[crow]);
+        u1 = ld_dev(&sg[n + crow]);
+        u2 = ld_dev(&sg[2 * n + crow]);
+      }
+      Tl.xs[le][a][0] = u0;
+      Tl.xs[le][a][1] = u1;
+      Tl.xs[le][a][2] = u2;
+    }
+    __syncthreads();
+    if (ev) {
+      double dF[9];
+      deformation_gradient(Tl, le, a, G, dF);
+      hvp_stress_from_dF(M, Tl.Ps[le][a], dF, M.w_e[el], cq);
+    }
+    __syncthreads();
+    if (ev) corner_force(Tl, le, a, G, fl[le][a][0], fl[le][a][1], fl[le][a][2]);
+    __syncthreads();
+    double pg = 0.0, pd = 0.0, pr = 0.0;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    if (tid < R) {
+      const int i = tid;
+      if (row_free[i]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int code = row_inc[i][q];
+          if (code >= 0) {
+            w0 += fl[code >> 3][code & 7][0];
+            w1 += fl[code >> 3][code & 7][1];
+            w2 += fl[code >> 3][code & 7][2];
+          }
+        }
+        const double c = row_c[i];
+        const double s0 = own_s[i], s1 = own_s[MR + i], s2 = own_s[2 * MR + i];
+        w0 += c * s0;
+        w1 += c * s1;
+        w2 += c * s2;
+        if (row_pen[i]) w2 += M.contact_k * s2;
+        const double r0 = own_r[i], r1 = own_r[MR + i], r2 = own_r[2 * MR + i];
+        pg = r0 * s0 + r1 * s1 + r2 * s2;
+        pd = s0 * w0 + s1 * w1 + s2 * w2;
+        pr = r0 * r0 + r1 * r1 + r2 * r2;
+      }
+    }
+    const double bg = block_sum(pg, ws);
+    const double bd = block_sum(pd, ws);
+    const double br = block_sum(pr, ws);
+    if (tid == 0) {
+      st_dev(&part[b], bg);
+      st_dev(&part[G_ + b], bd);
+      st_dev(&part[2 * G_ + b], br);
+    }
+    if (!fused_barrier(P.bar, round)) return;
+    if (tid < 64) {
+      double tg = 0.0, td = 0.0, tr = 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = 64 * u + lane;
+        if (g < G_) {
+          tg += ld_dev(&part[g]);
+          td += ld_dev(&part[G_ + g]);
+          tr += ld_dev(&part[2 * G_ + g]);
+        }
+      }
+      tg = wave_sum(tg);
+      td = wave_sum(td);
+      tr = wave_sum(tr);
+      if (tid == 0) {
+        sums[0] = tg;
+        sums[1] = td;
+        sums[2] = tr;
+      }
+    }
+    __syncthreads();
+    const double gamma = sums[0], delta = sums[1], rsq = sums[2];
+    int done = 0, conv = 0, bad = 0, curv = 0;
+    double alpha = 0.0, beta = 0.0;
+    if (!isfinite(rsq)) {
+      bad = 1;
+      done = 1;
+    } else if (rsq <= tolsq * nb2) {
+      conv = 1;
+      done = 1;
+    } else if (k >= P.max_iter) {
+      done = 1;
+    } else {
+      beta = k == 0 ? 0.0 : gamma / gamma_old;
+      const double den = k == 0 ? delta : delta - beta * gamma / alpha_old;
+      if (!(den > 0.0) || !(gamma > 0.0)) {
+        curv = 1;
+        done = 1;
+      } else {
+        alpha = gamma / den;
+      }
+    }
+    if (b == 0 && tid == 0) {
+      P.st->rsq = rsq;
+      P.st->iter = k;
+      if (bad) P.st->nonfinite = 1;
+      if (conv) P.st->converged = 1;
+      if (curv) P.st->curvature = 1;
+      if (done) P.st->done = 1;
+    }
+    if (done) break;
+    if (tid < 3 * R) {
+      const int c = tid / R, i = tid % R, o = c * MR + i;
+      own_p[o] = own_s[o] + beta * own_p[o];
+    }
+    // q = w + beta q: w of own row i is held by thread i
+    if (tid < R) {
+      const int i = tid;
+      own_q[i] = w0 + beta * own_q[i];
+      own_q[MR + i] = w1 + beta * own_q[MR + i];
+      own_q[2 * MR + i] = w2 + beta * own_q[2 * MR + i];
+    }
+    __syncthreads();
+    if (tid < 3 * R) {
+      const int c = tid / R, i = tid % R, o = c * MR + i;
+      own_z[o] += alpha * own_p[o];
+      const double rn = own_r[o] - alpha * own_q[o];
+      own_r[o] = rn;
+      st_dev(&rg[c * n + j0 + i], rn);
+    }
+    gamma_old = gamma;
+    alpha_old = alpha;
+    if (!fused_barrier(P.bar, round)) return;
+  }
+  if (!alive) return;
+  __syncthreads();
+  if (tid < 3 * R) {
+    const int c = tid / R, i = tid % R;
+    P.x0[c * N + row_node[i]] = own_z[c * MR + i];
+  }
+  ClockArg c2 = ck;
+  c2.bytes = ck.bytes * (double)(k + 1);
+  c2.flops = ck.flops * (double)(k + 1);
+  clock_exit(c2);
+}
+
 __global__ void k_contact_fused_reset(uint32_t* bar, uint32_t* ready, int G) {
   for (int i = threadIdx.x; i < kContactBarWords; i += blockDim.x) bar[i] = 0u;
   for (int i = threadIdx.x; i < G; i += blockDim.x) ready[i] = 0u;
 }
 
 }  // namespace
+
+hipError_t launch_contact_fused_cg(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
+                                   const double* W, double* z, const double* xbar, const double* cache,
+                                   IterState* st, uint32_t* bar, int max_iter) {
+  if (D.n < 1 || D.n > kContactDenseMaxRows || blocks < 1 || blocks > 256 || D.rows > kDenseMaxRows)
+    return hipErrorInvalidValue;
+  FusedContact P{};
+  P.M = Mmask;
+  P.n = D.n;
+  P.rows = D.rows;
+  P.mode = 1;
+  P.max_iter = max_iter;
+  P.W = W;
+  P.x0 = z;
+  P.y = xbar;
+  P.cache = cache;
+  P.st = st;
+  P.bar = bar;
+  hipLaunchKernelGGL(k_contact_fused_reset, dim3(1), dim3(256), 0, s, bar, D.ready, blocks);
+  ClockArg ck = take_launch_clock();
+  DenseCG Dv = D;
+  void* args[] = {&P, &Dv, &ck};
+  return hipLaunchCooperativeKernel((const void*)k_contact_fused_cg, dim3(blocks), dim3(kDenseBlock), args,
+                                    (unsigned)contact_dense_lds(D.n), s);
+}
 
 hipError_t launch_contact_fused(hipStream_t s, const DevMesh& Mmask, const DenseCG& D, int blocks,
                                 const double* W, double* x, const double* y, const double* act, const double* cache,

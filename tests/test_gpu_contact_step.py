@@ -34,16 +34,18 @@ def _forward_parity(g, o, cand, x, v, act=None, tol=1e-9):
     return soa(xn), kind, info
 
 
-PATHS = {"fused": dict(fused_cg=1, contact_fused=1), "dense": dict(fused_cg=1, contact_fused=0),
-         "sweeps": dict(fused_cg=0, contact_fused=0)}
+PATHS = {"fused": dict(fused_cg=1, contact_fused=1),
+         "fused_fixed_point": dict(fused_cg=1, contact_fused=1, bwd_solver="fixed_point"),
+         "dense": dict(fused_cg=1, contact_fused=0), "sweeps": dict(fused_cg=0, contact_fused=0)}
 
 
 @pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("muscles", [False, True])
 def test_landing_block_forward_and_backward(muscles, path):
-    """The three forms of the inner loop: one cooperative launch per contact
-    set, a dense reduced global step per iteration (the inverse of A_{C̄×C̄}
-    held dense), and the factor's sweeps with the low-rank correction."""
+    """The forms of the inner loop: one cooperative launch per contact set
+    (the adjoint by CG preconditioned with the reduced inverse, or by Alg. 5's
+    iteration), a dense reduced global step per iteration (the inverse of
+    A_{C̄×C̄} held dense), and the factor's sweeps with the low-rank correction."""
     sc, cand, x, v = landing_block(muscles=muscles)
     g, o = pair(sc, **TIGHT, **PATHS[path])
     assert (g.info["fused_blocks"] > 0) == (path != "sweeps")
@@ -59,6 +61,7 @@ def test_landing_block_forward_and_backward(muscles, path):
     gx, gv, gact, st = g.contact_backward_step(
         to_dev(x, o.N), to_dev(v, o.N), None if act is None else elem_dev(act), to_dev(xn, o.N), kind,
         to_dev(cx, o.N), to_dev(cv, o.N), g_youngs=gE, want_act=muscles, strict=True)
+    print("fallbacks", st["fallbacks"], flush=True)
     rx, rv, rE, ract, _ = oc.backward_step_contact(o, x, v, act, xn, cand, kind, cx, cv)
     print("bwd iters", st["bwd_iters"], "gx", rel(soa(gx), rx), "gv", rel(soa(gv), rv),
           "gE", rel(gE.cpu().numpy(), rE), flush=True)
