@@ -141,3 +141,20 @@ def test_sphere_rollout_at_bench_settings_matches_the_reference():
     assert rel(soa(gx), ref["g_x0"]) <= 1e-6
     assert rel(soa(gv), ref["g_v0"]) <= 1e-6
     assert rel(gE.cpu().numpy(), ref["g_youngs"]) <= 1e-6
+
+
+def test_contact_set_beyond_the_limit_is_rejected():
+    """A flat 12x12 block landing on its 169 bottom nodes: every one is
+    detected, more than the 120 the capacitance factorization holds; the step
+    reports DPD_EINVAL and the handle stays usable with fewer candidates."""
+    sc, cand, x, v = landing_block(12, 12, 1)
+    assert len(cand) == 169
+    g, o = pair(sc)
+    g.contact_prepare(cand)
+    xd, vd = to_dev(x, o.N), to_dev(v, o.N)
+    with pytest.raises(L.DiffPDError) as e:
+        g.contact_forward_step(xd, vd)
+    assert e.value.code == -1
+    g.contact_prepare(cand[:100])
+    _, _, kind, _ = g.contact_forward_step(xd, vd)
+    assert (kind > 0).sum() == 100
