@@ -295,7 +295,8 @@ dpd_status dpd_contact_solve(dpd_mesh* mesh, void* stream, const int32_t* set_ho
  * device results).  DPD_ESTATE without candidates, DPD_EINVAL when the set
  * would exceed 120 nodes, DPD_NOT_CONVERGED when a set's PD loop reached
  * fwd_max_iter (the outputs are still written).  The fwd_solver option is not
- * used: the inner loop is Alg. 3's PD iteration, in FP64.  Where A^{-1} is held
+ * used: the inner loop is Alg. 3's PD iteration; its global steps run in FP64
+ * (the local step's rotations follow the precision option).  Where A^{-1} is held
  * dense (fused_cg on, at most 2048 free nodes) the reduced matrix's inverse
  * is formed once per set from it and each reduced global step is one dense
  * product (with contact_fused, the set's whole loop is one cooperative
