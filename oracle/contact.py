@@ -86,19 +86,21 @@ def collision_targets(model, x, v, candidates):
     """Collision detection against the ground plane z = 0 (phi(x) = x_z).
 
     A candidate is in contact when the ray x_j + t v_j, 0 <= t <= h, meets the
-    plane (z_j + h v_{j,z} < 0 with v_{j,z} < 0); its target x*_j is the point
-    where it does (Sec. Contact, remarks on friction: the third strategy, a
-    sticky surface), x*_j = x_j + t v_j with t = -z_j / v_{j,z} when z_j >= 0
-    (kind RAY).  Reading: a node already below the plane meets it at t = 0,
+    plane (z_j + h v_{j,z} <= 0 with v_{j,z} <= 0, the meeting point at t = 0
+    included: a node resting on the plane is in contact); its target x*_j is
+    the point where it does (Sec. Contact, remarks on friction: the third
+    strategy, a sticky surface), x*_j = x_j + t v_j with t = -z_j / v_{j,z}
+    when z_j >= 0 and v_{j,z} < 0 (kind RAY).  Reading: a node on the plane
+    that does not move along z, or one already below it, meets it at t = 0,
     x*_j = (x_j, y_j, 0) (kind STATIC).
     Returns {node: (x*_j, kind)}."""
     h = model.h
     out = {}
     for j in np.asarray(candidates, dtype=np.int64):
         z, vz = x[3 * j + 2], v[3 * j + 2]
-        if z + h * vz < 0.0 and vz < 0.0:
+        if z + h * vz <= 0.0 and vz <= 0.0:
             p = x[3 * j:3 * j + 3].copy()
-            if z >= 0.0:
+            if z >= 0.0 and vz < 0.0:
                 t = -z / vz
                 p[0] += t * v[3 * j]
                 p[1] += t * v[3 * j + 1]

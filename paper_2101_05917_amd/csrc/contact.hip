@@ -217,10 +217,11 @@ __global__ void __launch_bounds__(kBlock) k_contact_descend(int N, const int32_t
 
 // Collision detection against the ground plane z = 0 for every candidate
 // (Sec. Contact, remarks on friction: the target is where the ray
-// x_j + t v_j, 0 <= t <= h, meets the plane).  kind 1 (ray): z_j >= 0 and
-// z_j + h v_z < 0 with v_z < 0, target x_j + t v_j at t = -z_j / v_z; kind 2
-// (static): a node already below the plane, target (x_j, y_j, 0); kind 0:
-// no contact.  Products and sums are rounded one by one (no fused
+// x_j + t v_j, 0 <= t <= h, meets the plane, t = 0 included).  In contact
+// when z_j + h v_z <= 0 and v_z <= 0; kind 1 (ray): z_j >= 0 and v_z < 0,
+// target x_j + t v_j at t = -z_j / v_z; kind 2 (static): a node on the plane
+// not moving along z, or one below it, target (x_j, y_j, 0); kind 0: no
+// contact.  Products and sums are rounded one by one (no fused
 // multiply-add), so the decision and the target are those of the plain
 // formula.  `left` (a node has left the set in this step) is cleared.
 __global__ void k_contact_detect(int N, int n_cand, const int32_t* __restrict__ cand, double h,
@@ -233,8 +234,8 @@ __global__ void k_contact_detect(int N, int n_cand, const int32_t* __restrict__ 
   const double z = x[2 * N + j], vz = v[2 * N + j];
   double p0 = x[j], p1 = x[N + j];
   int k = 0;
-  if (__dadd_rn(z, __dmul_rn(h, vz)) < 0.0 && vz < 0.0) {
-    if (z >= 0.0) {
+  if (__dadd_rn(z, __dmul_rn(h, vz)) <= 0.0 && vz <= 0.0) {
+    if (z >= 0.0 && vz < 0.0) {
       const double t = -z / vz;
       p0 = __dadd_rn(p0, __dmul_rn(t, v[j]));
       p1 = __dadd_rn(p1, __dmul_rn(t, v[N + j]));

@@ -49,10 +49,29 @@ def test_ray_targets_lie_on_the_ray_and_the_plane():
         d, vj = xn[3 * j:3 * j + 3] - x[3 * j:3 * j + 3], v[3 * j:3 * j + 3]
         if k == oc.RAY:
             t = -x[3 * j + 2] / vj[2]
-            assert 0.0 < t < m.h
+            assert 0.0 <= t <= m.h
             assert np.allclose(d, t * vj, rtol=0, atol=1e-15)
         elif k == oc.STATIC:
             assert d[0] == 0.0 and d[1] == 0.0
+
+
+def test_a_node_resting_on_the_plane_is_in_contact():
+    """The ray of a node at z = 0 that does not move along z meets the plane
+    at t = 0: it is detected, with its own position as target; one moving up
+    is not, and one above the plane at rest is not."""
+    sc, cand, x, v = landing_block(1, 1, 1, lift=0.0)
+    m = om.Model(sc)
+    x, v = x.copy(), v.copy()
+    b = [int(j) for j in cand]
+    v[3 * b[0] + 2] = 0.0
+    v[3 * b[1] + 2] = 0.01
+    x[3 * b[2] + 2] = 1e-3
+    v[3 * b[2] + 2] = 0.0
+    t = oc.collision_targets(m, x, v, cand)
+    assert b[0] in t and t[b[0]][1] == oc.STATIC and np.array_equal(t[b[0]][0], x[3 * b[0]:3 * b[0] + 3])
+    assert b[1] not in t and b[2] not in t
+    assert b[3] in t and t[b[3]][1] == oc.RAY                 # z = 0, moving down: t = 0
+    assert np.array_equal(t[b[3]][0], x[3 * b[3]:3 * b[3] + 3])
 
 
 def test_no_contact_is_the_plain_implicit_step():
