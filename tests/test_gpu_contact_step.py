@@ -149,12 +149,12 @@ def test_contact_set_beyond_the_limit_is_rejected():
     reports DPD_EINVAL and the handle stays usable with fewer candidates."""
     sc, cand, x, v = landing_block(12, 12, 1)
     assert len(cand) == 169
-    g, o = pair(sc)
+    g, o = pair(sc, fwd_max_iter=5000)
     g.contact_prepare(cand)
     xd, vd = to_dev(x, o.N), to_dev(v, o.N)
     with pytest.raises(L.DiffPDError) as e:
         g.contact_forward_step(xd, vd)
     assert e.value.code == -1
     g.contact_prepare(cand[:100])
-    _, _, kind, _ = g.contact_forward_step(xd, vd)
+    _, _, kind, _ = g.contact_forward_step(xd, vd, strict=True)
     assert (kind > 0).sum() == 100
