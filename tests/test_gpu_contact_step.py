@@ -158,3 +158,35 @@ def test_contact_set_beyond_the_limit_is_rejected():
     g.contact_prepare(cand[:100])
     _, _, kind, _ = g.contact_forward_step(xd, vd, strict=True)
     assert (kind > 0).sum() == 100
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_clamped_beam_landing_forward_and_backward(path):
+    """Dirichlet nodes beside the contact set: a 6x2x2 cantilever held at
+    x = 0, 0.1 mm above the plane and falling at 0.1 m/s; its free bottom nodes
+    are the candidates.  Forward and adjoint against the oracle."""
+    sc = W.cantilever(6, 2, 2, steps=3)
+    sc.h = 5e-3
+    sc.youngs = np.full(sc.n_elements, 1e5)
+    sc.origin = (0.0, 0.0, 1e-4)
+    g, o = pair(sc, **TIGHT, **PATHS[path])
+    nodes = W.present_nodes(sc.cells)
+    cand = np.nonzero((nodes[:, 2] == 0) & ~o.fixed[0::3])[0].astype(np.int64)
+    g.contact_prepare(cand)
+    rng = np.random.default_rng(21)
+    x = o.X.copy()
+    v = np.tile([0.02, 0.0, -0.1], o.N) + 0.01 * rng.standard_normal(3 * o.N)
+    v[o.fixed] = 0.0
+    xn, kind, info = _forward_parity(g, o, cand, x, v)
+    assert (kind > 0).sum() > 0
+    assert np.all(xn[o.fixed] == o.X[o.fixed])
+    cx, cv = rng.standard_normal(3 * o.N), rng.standard_normal(3 * o.N)
+    gE = torch.zeros(sc.n_elements, dtype=torch.float64, device="cuda:0")
+    gx, gv, _, st = g.contact_backward_step(to_dev(x, o.N), to_dev(v, o.N), None, to_dev(xn, o.N), kind,
+                                            to_dev(cx, o.N), to_dev(cv, o.N), g_youngs=gE, strict=True)
+    rx, rv, rE, _, _ = oc.backward_step_contact(o, x, v, None, xn, cand, kind, cx, cv)
+    print("bwd iters", st["bwd_iters"], "gx", rel(soa(gx), rx), "gv", rel(soa(gv), rv),
+          "gE", rel(gE.cpu().numpy(), rE), flush=True)
+    assert rel(soa(gx), rx) <= 1e-9
+    assert rel(soa(gv), rv) <= 1e-9
+    assert rel(gE.cpu().numpy(), rE) <= 1e-9
