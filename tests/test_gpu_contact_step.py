@@ -190,3 +190,26 @@ def test_clamped_beam_landing_forward_and_backward(path):
     assert rel(soa(gx), rx) <= 1e-9
     assert rel(soa(gv), rv) <= 1e-9
     assert rel(gE.cpu().numpy(), rE) <= 1e-9
+
+
+@pytest.mark.parametrize("path", ["fused", "sweeps"])
+def test_landing_block_mixed_precision(path):
+    """precision = mixed: the local step's rotations in FP32 polished in FP64,
+    the reduced global steps in FP64; within the mixed path's 1e-5 of the
+    oracle (positions, displacement-relative, and gradients)."""
+    sc, cand, x, v = landing_block()
+    g, o = pair(sc, **dict(TIGHT, fwd_rel_tol=1e-10, bwd_rel_tol=1e-10), precision="mixed", **PATHS[path])
+    g.contact_prepare(cand)
+    xn, vn, kind, st = g.contact_forward_step(to_dev(x, o.N), to_dev(v, o.N), strict=True)
+    rx, _, info = oc.forward_step_contact(o, x, v, cand)
+    assert np.array_equal(kind, info["kind"])
+    err = np.linalg.norm(soa(xn) - rx) / np.linalg.norm(rx - x)
+    print("mixed displacement rel err", err, flush=True)
+    assert err <= 1e-5
+    rng = np.random.default_rng(31)
+    cx, cv = rng.standard_normal(3 * o.N), rng.standard_normal(3 * o.N)
+    gx, gv, _, _ = g.contact_backward_step(to_dev(x, o.N), to_dev(v, o.N), None, xn, kind,
+                                           to_dev(cx, o.N), to_dev(cv, o.N), strict=True)
+    rgx, rgv, _, _, _ = oc.backward_step_contact(o, x, v, None, rx, cand, kind, cx, cv)
+    print("mixed gx", rel(soa(gx), rgx), "gv", rel(soa(gv), rgv), flush=True)
+    assert rel(soa(gx), rgx) <= 1e-5 and rel(soa(gv), rgv) <= 1e-5
