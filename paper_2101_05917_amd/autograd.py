@@ -23,6 +23,9 @@ class PDStep(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, mesh: Mesh, x, v, act, youngs):
+        if youngs is not None:
+            # the step runs with these moduli: refactorize A if they changed
+            mesh.ensure_youngs(youngs)
         xn, vn, stats = mesh.forward_step(x.contiguous(), v.contiguous(),
                                           None if act is None else act.contiguous())
         ctx.mesh = mesh
@@ -61,8 +64,11 @@ def rollout(mesh: Mesh, x0, v0, steps: int, acts=None, youngs: Optional[torch.Te
             checkpoint_every: int = 1):
     """Run ``steps`` PD steps; differentiable w.r.t. x0, v0, acts and youngs.
 
-    ``youngs`` must hold the moduli the mesh was factorized with; it only
-    routes the gradient dL/dE.  With checkpoint_every = K > 1 only the
+    ``youngs`` (float64 [E] on the device, optional) are the per-element
+    moduli of the rollout: when they differ from those the mesh was last
+    factorized with, the mesh takes them and A is factorized again before the
+    first step (the factor is constant within a rollout); dL/dE flows back to
+    them.  With checkpoint_every = K > 1 only the
     segment-start states are stored and each segment is recomputed in the
     backward pass.
     """

@@ -63,7 +63,10 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
   dpd_status st = dpd::create_host(r->cells.data(), (int64_t)r->cells.size() / 3, r->youngs.data(),
                                    r->fixed.empty() ? nullptr : r->fixed.data(),
                                    (int64_t)r->fixed.size() / 3, &r->opt, &m);
+  // Everything a poll may read is published under srv->mu; the worker keeps
+  // its running figures in locals until then.
   auto finish_fail = [&](dpd_status code) {
+    std::lock_guard<std::mutex> lk(srv->mu);
     r->res.status = code;
     r->res.state = DPD_REQ_FAILED;
     r->res.t_done = now_s(srv->t0);
@@ -72,8 +75,11 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
   dpd_mesh_info info{};
   dpd_get_info(m, &info);
   const int64_t N = info.n_nodes, E = info.n_elements, T = r->steps;
-  r->res.n_nodes = N;
-  r->res.n_elements = E;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    r->res.n_nodes = N;
+    r->res.n_elements = E;
+  }
   if (N != r->n_nodes || (int64_t)r->loss_x.size() != 3 * N) {
     dpd::destroy_synced(m);
     return finish_fail(DPD_EINVAL);
@@ -81,7 +87,10 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
   const int64_t n3 = 3 * N;
   const int64_t state_bytes = 8 * ((T + 1) * 2 * n3 + 5 * n3 + E);
   const int64_t fp = dpd::footprint_bytes(m) + state_bytes;
-  r->res.footprint_bytes = fp;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    r->res.footprint_bytes = fp;
+  }
   if (fp > srv->budget) {
     dpd::destroy_synced(m);
     return finish_fail(DPD_ENOMEM);
@@ -98,6 +107,8 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
   }
   double* buf = nullptr;
   dpd_status result = DPD_OK;
+  int64_t fwd_iters = 0, bwd_iters = 0;
+  double loss = 0.0;
   auto soft = [&](dpd_status c) {
     if (c < 0) return false;
     if (c == DPD_NOT_CONVERGED) result = DPD_NOT_CONVERGED;
@@ -139,7 +150,7 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
       ok = soft(dpd_forward_step(m, s, xs + t * n3, vs + t * n3, nullptr, xs + (t + 1) * n3,
                                  vs + (t + 1) * n3, &fs));
       if (!ok) result = DPD_EHIP;
-      r->res.fwd_iters += fs.fwd_iters;
+      fwd_iters += fs.fwd_iters;
     }
     if (!ok) break;
     std::vector<double> xT(n3);
@@ -152,14 +163,14 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
     }
     double L = 0.0;
     for (int64_t i = 0; i < n3; ++i) L += r->loss_x[i] * xT[i];
-    r->res.loss = L;
+    loss = L;
     for (int64_t t = T - 1; t >= 0 && ok; --t) {
       dpd_stats bs{};
       dpd_status c2 = dpd_backward_step(m, s, xs + t * n3, vs + t * n3, nullptr, xs + (t + 1) * n3, gx,
                                         gv, gx2, gv2, gE, nullptr, &bs);
       ok = soft(c2);
       if (!ok) result = c2;
-      r->res.bwd_iters += bs.bwd_iters;
+      bwd_iters += bs.bwd_iters;
       std::swap(gx, gx2);
       std::swap(gv, gv2);
     }
@@ -180,6 +191,9 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->used -= fp;
     srv->active -= 1;
+    r->res.fwd_iters = fwd_iters;
+    r->res.bwd_iters = bwd_iters;
+    r->res.loss = loss;
     r->res.status = result;
     r->res.state = result < 0 ? DPD_REQ_FAILED : DPD_REQ_DONE;
     r->res.t_done = now_s(srv->t0);
@@ -200,14 +214,13 @@ void worker(dpd_server* srv) {
       r = srv->queue.front();
       srv->queue.pop_front();
     }
-    if (s)
-      run_request(srv, r, s);
-    else {
-      r->res.status = DPD_EHIP;
-      r->res.state = DPD_REQ_FAILED;
-    }
+    if (s) run_request(srv, r, s);
     {
       std::lock_guard<std::mutex> lk(srv->mu);
+      if (!s) {
+        r->res.status = DPD_EHIP;
+        r->res.state = DPD_REQ_FAILED;
+      }
       srv->pending -= 1;
     }
     srv->cv_done.notify_all();

@@ -6,8 +6,10 @@ State tensors are float64 with shape [3, N] (SoA, public node order).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import warnings
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -42,6 +44,29 @@ def make_options(physics: Optional[dict] = None, **iteration) -> L.Options:
     return o
 
 
+# Handles still open when the interpreter exits are destroyed by an exit hook,
+# after the device has finished its work, rather than from __del__ during
+# interpreter teardown (when the HIP runtime may already be shutting down).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_meshes():
+    meshes = list(_LIVE)
+    if not meshes:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for m in meshes:
+        try:
+            m.close()
+        except Exception:
+            pass
+
+
 def _ptr(t: Optional[torch.Tensor]):
     if t is None:
         return None
@@ -73,10 +98,13 @@ class Mesh:
                 fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
                 C.byref(self.options), C.byref(h)))
         self.handle = h
+        _LIVE.add(self)
         self._read_info()
         self.n_nodes = self.info["n_nodes"]
         self.n_elements = self.info["n_elements"]
         self.youngs = youngs.copy()
+        self._youngs_dev = None      # device copy of the factorized moduli (on first use)
+        self._youngs_seen = None     # (data_ptr, _version) of the last tensor found equal
         if factorize:
             self.factorize()
 
@@ -125,8 +153,34 @@ class Mesh:
         L.check(self.lib.dpd_set_youngs(self.handle, ym.ctypes.data_as(C.c_void_p), 0, None),
                 self.handle)
         self.youngs = ym.copy()
+        self._youngs_dev = None
+        self._youngs_seen = None
         if refactorize:
             self.factorize()
+
+    def ensure_youngs(self, youngs: torch.Tensor) -> bool:
+        """Make the factor match ``youngs`` (float64 [E] on the device): when its
+        values differ from the moduli the mesh was factorized with, they replace
+        them (dpd_set_youngs) and A is factorized again.  A tensor already found
+        equal and not modified in place since (same storage and version
+        counter) is not compared again.  Returns True if it refactorized."""
+        t = youngs.detach()
+        key = (t.data_ptr(), t._version)
+        if key == self._youngs_seen:
+            return False
+        self._check_elem(t)
+        if self._youngs_dev is None:
+            self._youngs_dev = torch.from_numpy(self.youngs).to(self.device)
+        changed = not torch.equal(t, self._youngs_dev)
+        if changed:
+            with torch.cuda.device(self.device):
+                L.check(self.lib.dpd_set_youngs(self.handle, _ptr(t), 1, _stream(self.device)),
+                        self.handle)
+                self.factorize()
+            self._youngs_dev = t.clone()
+            self.youngs = self._youngs_dev.cpu().numpy().copy()
+        self._youngs_seen = key
+        return changed
 
     def node_ijk(self) -> np.ndarray:
         out = np.zeros((self.n_nodes, 3), np.int32)

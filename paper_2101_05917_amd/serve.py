@@ -8,7 +8,9 @@ moduli.  Marshalling only: everything runs inside libdiffpd.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
@@ -19,6 +21,19 @@ from .mesh import make_options
 
 
 STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+# Servers still open at interpreter exit are drained and destroyed by an exit
+# hook (their worker threads joined) before the HIP runtime shuts down.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_servers():
+    for s in list(_LIVE):
+        try:
+            s.close()
+        except Exception:
+            pass
 
 
 @dataclass
@@ -53,6 +68,7 @@ class Server:
         L.check(self.lib.dpd_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
         self.handle = h
         self._sizes = {}
+        _LIVE.add(self)
 
     def submit(self, scene, loss_x: np.ndarray, steps: Optional[int] = None, **iteration) -> int:
         """Queue a rollout of ``scene``; ``loss_x`` node-major 3N weights of c . x_T."""

@@ -95,3 +95,35 @@ def test_mass_and_matrix_invariants():
         got = A @ ones
         assert np.abs(got - expect * ones).max() < 1e-9 * abs(A).max()
     assert len(m.contact_nodes) > 0
+
+
+def test_lumped_mass_per_node_closed_form_on_a_box():
+    """On a full nx x ny x nz box every node collects rho dx^3 / 8 from each
+    voxel it touches: 1 voxel at a corner, 2 on an edge, 4 on a face and 8
+    inside, i.e. prod over the axes of (1 on the box boundary, else 2)."""
+    nx, ny, nz, dx, rho = 4, 3, 5, 0.02, 1.3e3
+    mesh = disc.VoxelMesh(W.box_cells(nx, ny, nz), dx)
+    m = disc.lumped_mass(mesh, rho)
+    unit = rho * dx ** 3 / 8.0
+    for n, (i, j, k) in enumerate(mesh.node_ijk.tolist()):
+        count = 1
+        for c, top in ((i, nx), (j, ny), (k, nz)):
+            count *= 1 if c in (0, top) else 2
+        assert m[n] == pytest.approx(count * unit, rel=1e-14), (i, j, k)
+    kinds = {1: 8, 2: 4 * (nx - 1 + ny - 1 + nz - 1), 8: (nx - 1) * (ny - 1) * (nz - 1)}
+    for count, expect in kinds.items():
+        assert int(np.sum(np.isclose(m, count * unit, rtol=1e-12))) == expect
+
+
+def test_lumped_mass_per_node_irregular_voxels_brute_force():
+    """An irregular voxel set (the legged body): each node's mass is rho dx^3 / 8
+    times the number of voxels having it as one of their 8 corners, counted by
+    testing every voxel against every node."""
+    sc = W.legged_body(8, 6, 4, steps=1, leg_height=2)
+    mesh = disc.VoxelMesh(sc.cells, sc.dx)
+    m = disc.lumped_mass(mesh, sc.rho)
+    cells = np.asarray(sc.cells, dtype=np.int64)
+    for n, p in enumerate(mesh.node_ijk):
+        d = p[None, :] - cells
+        touching = int(np.sum(np.all((d == 0) | (d == 1), axis=1)))
+        assert m[n] == pytest.approx(touching * sc.rho * sc.dx ** 3 / 8.0, rel=1e-14)
