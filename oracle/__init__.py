@@ -25,4 +25,4 @@ Everything is written out plainly, with explicit sparse operators in the
 Parity status of each function is stated in its module header; pins live in
 ``tests/test_oracle_*.py``.
 """
-from . import discretization, projections, model, forward, adjoint, contact, rollout  # noqa: F401
+from . import discretization, projections, linsolve, model, forward, adjoint, contact, rollout  # noqa: F401

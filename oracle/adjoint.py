@@ -4,7 +4,8 @@ Sec. Background (backpropagation with implicit time integration): with
 grad g(x) = 0 tying x to y, dL/dy = z^T M / h^2 (eq:chain_rule) where z solves
 (A - dA) z = (dL/dx)^T (eq:adjoint, eq:hessian, eq:matrix_split).
 
-* ``adjoint_direct`` -- the plain definition: assemble A - dA and solve it.
+* ``adjoint_direct`` -- the plain definition: assemble A - dA and solve it
+  (sparse LU; on the largest meshes, CG to round-off, ``linsolve``).
 * ``adjoint_fixed_point`` -- Alg. 2: z = 0, then z = A^{-1}(dA z + dL/dx)
   (eq:iteration); convergence iff the spectral radius of A^{-1} dA is below 1
   (eq:sp_radius).  Stopping reading: |dL/dx - (A - dA) z| <= tol |dL/dx|.
@@ -28,7 +29,8 @@ forward map; central finite differences of whole rollouts.
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse.linalg as spla
+
+from . import linsolve
 
 
 def _free_blocks(model, x_next, act):
@@ -38,8 +40,11 @@ def _free_blocks(model, x_next, act):
 
 
 def adjoint_direct(model, x_next, act, xbar_free):
+    """Sparse LU of A - dA on free DoFs; beyond the LU size, conjugate
+    gradients to round-off (``linsolve``; the residual is in the info)."""
     H = _free_blocks(model, x_next, act)
-    return spla.spsolve(H, xbar_free), {"iters": 0}
+    z, info = linsolve.solve(H, xbar_free, dense_max=0)
+    return z, {"iters": info.get("iters", 0), "method": info["method"], "rel_res": info["rel_res"]}
 
 
 def adjoint_fixed_point(model, x_next, act, xbar_free, *, tol=1e-12, max_iter=20000):

@@ -25,7 +25,8 @@ body, static equilibrium, and agreement with Newton on small meshes.
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse.linalg as spla
+
+from . import linsolve
 
 
 def _initial_guess(model, y):
@@ -78,7 +79,8 @@ def pd_step(model, x_i, v_i, act=None, **kw):
 def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=200):
     """Minimise g(x) for fixed y with Newton steps and backtracking.
 
-    Dense solves up to 1500 free DoFs, sparse LU beyond.  Where the Hessian is
+    Dense solves up to 1500 free DoFs, sparse LU up to 60 k, conjugate
+    gradients to round-off beyond (``linsolve``).  Where the Hessian is
     not positive definite (the muscle energy is not convex) the Newton step
     need not descend; then, and when its line search finds no decrease, the
     step is the plain PD one, -A^{-1} grad g (Alg. 1's update, a descent
@@ -106,14 +108,13 @@ def newton_solve(model, y, act=None, *, x0=None, tol_rel=1e-13, max_iter=200):
             if stall >= 3 and ng <= 1e-9 * scale:
                 break
         H = model.hessian(x, act)[free][:, free]
-        if H.shape[0] <= 1500:
-            dx = -np.linalg.solve(H.toarray(), gr)
-        else:
-            dx = -spla.spsolve(H.tocsc(), gr)
+        dx = -linsolve.solve(H, gr)[0]
         g0 = model.g(x, y, act)
         ng0 = np.linalg.norm(gr)
-        directions = [dx, -model.solve_A(gr)] if gr @ dx < 0 else [-model.solve_A(gr)]
-        for d in directions:
+        # the PD step is only formed when the Newton step is not taken
+        directions = ([lambda: dx] if gr @ dx < 0 else []) + [lambda: -model.solve_A(gr)]
+        for make in directions:
+            d = make()
             t = 1.0
             found = False
             for _ in range(30):

@@ -32,6 +32,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import discretization as disc
+from . import linsolve
 from . import projections as proj
 
 
@@ -119,7 +120,10 @@ class Model:
 
     # ---------------------------------------------------------------- helpers
     def solve_A(self, rhs_free: np.ndarray) -> np.ndarray:
-        """A_ff^{-1} rhs on free DoFs (factor computed once, Sec. Background)."""
+        """A_ff^{-1} rhs on free DoFs (factor computed once, Sec. Background);
+        beyond the sparse-LU size, conjugate gradients to round-off."""
+        if self.A_ff.shape[0] > linsolve.LU_MAX:
+            return linsolve.solve(self.A_ff, rhs_free, dense_max=0)[0]
         return self._lu.solve(rhs_free)
 
     def act_per_qp(self, act):

@@ -104,7 +104,7 @@ class Mesh:
         self.n_elements = self.info["n_elements"]
         self.youngs = youngs.copy()
         self._youngs_dev = None      # device copy of the factorized moduli (on first use)
-        self._youngs_seen = None     # (data_ptr, _version) of the last tensor found equal
+        self._youngs_seen = None     # (weakref, _version) of the last tensor found equal
         if factorize:
             self.factorize()
 
@@ -162,12 +162,14 @@ class Mesh:
         """Make the factor match ``youngs`` (float64 [E] on the device): when its
         values differ from the moduli the mesh was factorized with, they replace
         them (dpd_set_youngs) and A is factorized again.  A tensor already found
-        equal and not modified in place since (same storage and version
-        counter) is not compared again.  Returns True if it refactorized."""
-        t = youngs.detach()
-        key = (t.data_ptr(), t._version)
-        if key == self._youngs_seen:
+        equal and not modified in place since (the same live tensor object with
+        the same version counter) is not compared again; a tensor allocated
+        later at the same address is a different object and is compared.
+        Returns True if it refactorized."""
+        seen = self._youngs_seen
+        if seen is not None and seen[0]() is youngs and seen[1] == youngs._version:
             return False
+        t = youngs.detach()
         self._check_elem(t)
         if self._youngs_dev is None:
             self._youngs_dev = torch.from_numpy(self.youngs).to(self.device)
@@ -179,7 +181,7 @@ class Mesh:
                 self.factorize()
             self._youngs_dev = t.clone()
             self.youngs = self._youngs_dev.cpu().numpy().copy()
-        self._youngs_seen = key
+        self._youngs_seen = (weakref.ref(youngs), youngs._version)
         return changed
 
     def node_ijk(self) -> np.ndarray:

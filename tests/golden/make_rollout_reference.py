@@ -11,6 +11,12 @@ round-off on each reduced system) and its adjoint (Alg. 5, direct reduced
 solve); its loss also weighs the final velocity, dot(c, x_T) + dot(d, v_T)
 with d ~ N(0, 1) (seed 1), and the contact kinds of every step are stored.
 
+With fewer steps than the scene's, the file holds the reference of that
+prefix of the rollout (the 64x32x32 block: the first 30 steps, through the
+landing; about an hour and a half on 8 host cores, where each Newton step and
+each adjoint solve runs conjugate gradients on the assembled Hessian to
+round-off, ``oracle.linsolve``).
+
 usage: python tests/golden/make_rollout_reference.py c2 [steps]
 """
 import os
@@ -79,8 +85,9 @@ def main():
     g_act = None if acts is None else np.zeros_like(acts)
     for t in range(steps - 1, -1, -1):
         a = None if acts is None else acts[t]
-        gx, gv, ge, ga, _ = oa.backward_step(m, xs[t], vs[t], a, xs[t + 1], gx, gv, solver="direct")
+        gx, gv, ge, ga, info = oa.backward_step(m, xs[t], vs[t], a, xs[t + 1], gx, gv, solver="direct")
         gE += ge
+        print(f"backward {t} {info['method']} rel res {info['rel_res']} {time.time() - t0:.0f}s", flush=True)
         if g_act is not None:
             g_act[t] = ga
     out = os.path.join(HERE, f"{name}_rollout_reference.npz")
