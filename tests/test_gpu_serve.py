@@ -119,3 +119,26 @@ def test_requests_join_while_others_run():
     # requests submitted while the long one ran were admitted and finished before it
     assert min(r.t_admit for r in res[1:]) < res[0].t_done
     assert st["peak_active"] >= 2
+
+
+def test_served_gradients_match_oracle():
+    """Served requests (three at once) against the oracle's rollout of the same
+    scene: loss, dL/dx0, dL/dv0 and dL/dE within 1e-6 relative."""
+    from paper_2101_05917_amd.serve import Server
+    from oracle import model as om, rollout as orr
+    reqs = _requests()[:3]
+    s = Server(8 << 30, max_slots=3)
+    res = _run(s, reqs)
+    s.close()
+    for (sc, c), r in zip(reqs, res):
+        assert r.state == "done", r
+        m = om.Model(sc)
+        L, g = orr.loss_and_grad(m, m.X.copy(), np.zeros(3 * m.N), None, c,
+                                 pd_kw={"max_iter": 20000, "tol": 1e-14})
+        aos = lambda a: np.asarray(a).T.reshape(-1)  # noqa: E731
+        errs = (abs(r.loss - L) / abs(L), np.linalg.norm(aos(r.g_x0) - g["x0"]) / np.linalg.norm(g["x0"]),
+                np.linalg.norm(aos(r.g_v0) - g["v0"]) / np.linalg.norm(g["v0"]),
+                np.linalg.norm(r.g_youngs - g["youngs"]) / np.linalg.norm(g["youngs"]))
+        print(sc.name, "loss, g_x0, g_v0, g_E errors", errs, flush=True)
+        assert errs[0] <= 1e-9
+        assert max(errs[1:]) <= 1e-6
