@@ -114,10 +114,7 @@ def backward_step(model, x_i, v_i, act, x_next, gx_next, gv_next, *, solver="dir
         gx = gx + fx
         gv = gv + fv
     # parameter gradients
-    Gz = (model.G @ z).reshape(model.Q, 3, 3)
-    D = model.youngs_force_derivative(x_next)
-    per_q = np.sum(Gz * D, axis=(1, 2)) * model.Vq / (1.0 + model.nu)
-    gE = -per_q.reshape(model.E, 8).sum(axis=1)
+    gE = model.youngs_gradient(x_next, z)
     gact = None
     if model.Gm is not None:
         Gmz = (model.Gm @ z).reshape(model.Q, 3)

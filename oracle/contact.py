@@ -269,9 +269,7 @@ def backward_step_contact(model, x, v, act, x_next, candidates, kind, gx_next, g
     tx, tv = target_vjp(model, x, v, cand, kind, gstar)
     gx = gx + tx
     gv = gv + tv
-    Gz = (model.G @ z).reshape(model.Q, 3, 3)
-    D = model.youngs_force_derivative(x_next)
-    gE = -(np.sum(Gz * D, axis=(1, 2)) * model.Vq / (1.0 + model.nu)).reshape(model.E, 8).sum(axis=1)
+    gE = model.youngs_gradient(x_next, z)
     gact = None
     if model.Gm is not None:
         Gmz = (model.Gm @ z).reshape(model.Q, 3)

@@ -83,6 +83,18 @@ class Model:
         self.friction_mu = float(scene.friction_mu)
         self.friction_eps = float(scene.friction_eps)
 
+        # volume-preserving term (supplemental Sec. Energy Definitions): reading,
+        # w_v = volume_scale * lambda * V_q per Gauss point with Lame's
+        # lambda = E nu / ((1 + nu)(1 - 2 nu)); off when volume_scale = 0
+        self.volume_scale = float(getattr(scene, "volume_scale", 0.0))
+        if self.volume_scale > 0.0:
+            lam_per_E = self.nu / ((1.0 + self.nu) * (1.0 - 2.0 * self.nu))
+            self.dwv_dE = self.volume_scale * lam_per_E * self.Vq
+            self.wv = np.repeat(self.dwv_dE * self.youngs, 8)            # [Q]
+        else:
+            self.dwv_dE = 0.0
+            self.wv = None
+
         self.muscle_k = float(scene.muscle_k)
         self.fiber = np.asarray(scene.fiber, dtype=np.float64)
         if self.muscle_k > 0.0:
@@ -100,6 +112,8 @@ class Model:
         """A = M/h^2 + sum_c w_c G_c^T G_c (eq:pd_global), assembled explicitly."""
         A = sp.diags(self.Mdiag / self.h ** 2)
         A = A + self.G.T @ sp.diags(np.repeat(self.wq, 9)) @ self.G
+        if self.wv is not None:
+            A = A + self.G.T @ sp.diags(np.repeat(self.wv, 9)) @ self.G
         if self.Gm is not None:
             A = A + self.Gm.T @ sp.diags(np.repeat(self.wm, 3)) @ self.Gm
         if len(self.contact_nodes):
@@ -176,6 +190,8 @@ class Model:
         F = self.deformation_gradients(x)
         R = proj.closest_rotation(F)
         e = 0.5 * np.sum(self.wq * np.sum((F - R) ** 2, axis=(1, 2)))
+        if self.wv is not None:
+            e += 0.5 * np.sum(self.wv * np.sum((F - proj.volume_projection(F)) ** 2, axis=(1, 2)))
         if self.Gm is not None:
             f = (self.Gm @ x).reshape(self.Q, 3)
             r = self.act_per_qp(act)
@@ -195,6 +211,8 @@ class Model:
         F = self.deformation_gradients(x)
         R = proj.closest_rotation(F)
         b = self.Mdiag * y / self.h ** 2 + self.G.T @ (np.repeat(self.wq, 9) * R.reshape(-1))
+        if self.wv is not None:
+            b = b + self.G.T @ (np.repeat(self.wv, 9) * proj.volume_projection(F).reshape(-1))
         if self.Gm is not None:
             f = (self.Gm @ x).reshape(self.Q, 3)
             p = proj.sphere_projection(f, self.act_per_qp(act), self.fiber)
@@ -212,6 +230,8 @@ class Model:
         """dA = sum_c w_c G_c^T (dp_c/dx) (eq:matrix_split), assembled explicitly."""
         F = self.deformation_gradients(x)
         J = proj.rotation_jacobian(F) * self.wq[:, None, None]
+        if self.wv is not None:
+            J = J + proj.volume_jacobian(F) * self.wv[:, None, None]
         blk = _block_diag(J)
         dA = self.G.T @ blk @ self.G
         if self.Gm is not None:
@@ -233,6 +253,20 @@ class Model:
         """Per qp: d(grad g)/dw_q contracted later; returns (F - R) [Q, 3, 3]."""
         F = self.deformation_gradients(x)
         return F - proj.closest_rotation(F)
+
+    def volume_youngs_derivative(self, x):
+        """Per qp: (F - D) [Q, 3, 3]; d(grad g)/dE_e through the volume weight is
+        sum_q G_q^T (F - D) dw_v/dE (zero when the term is off)."""
+        F = self.deformation_gradients(x)
+        return F - proj.volume_projection(F)
+
+    def youngs_gradient(self, x_next, z):
+        """dL/dE_e = -z^T d(grad g)/dE_e at the step's solution (both terms)."""
+        Gz = (self.G @ z).reshape(self.Q, 3, 3)
+        per_q = np.sum(Gz * self.youngs_force_derivative(x_next), axis=(1, 2)) * self.Vq / (1.0 + self.nu)
+        if self.wv is not None:
+            per_q = per_q + np.sum(Gz * self.volume_youngs_derivative(x_next), axis=(1, 2)) * self.dwv_dE
+        return -per_q.reshape(self.E, 8).sum(axis=1)
 
     def fiber_directions(self, x, act=None):
         """dp/dr per muscle qp: f/|f| (the fibre m where f = 0)."""

@@ -75,6 +75,141 @@ def rotation_jacobian(F: np.ndarray) -> np.ndarray:
     return J
 
 
+# ---------------------------------------------------------------- volume preservation
+#
+# Supplemental Sec. Energy Definitions, volume-preserving term: E = (w/2)|F - D|^2
+# with D the projection of F onto {det D = 1}.  With F = U diag(s) V^T,
+# D = U diag(s + d*) V^T where d* minimises |d|^2 subject to prod(s_i + d_i) = 1;
+# d* and the Lagrange multiplier satisfy the KKT conditions
+#   d + lam grad c(d) = 0,   c(d) = prod(s_i + d_i) - 1 = 0,
+# and their differential (eq:vol_kkt) gives dd*/ds.  Readings:
+# * the signed SVD (U, V proper rotations, s_3 carrying the sign of det F), as
+#   for the closest rotation;
+# * the KKT conditions are solved by Newton's method from d = 0, lam = 0 (its
+#   Jacobian is eq:vol_kkt's matrix), until the update stops changing d;
+# * where det F <= 0 (an inverted Gauss point) the constraint cannot be met on
+#   the branch continuous with s; there D is the closest rotation U V^T and
+#   dD/dF is dR/dF (so that the energy stays defined);
+# * dD/dF for the isotropic map F -> U diag(D_i(s)) V^T: with A = U^T dF V,
+#   (U^T dD V)_ii = sum_k dD_i/ds_k A_kk and, for i != j,
+#   (U^T dD V)_ij = (D_i - D_j)/(s_i - s_j) (A_ij + A_ji)/2
+#                 + (D_i + D_j)/(s_i + s_j) (A_ij - A_ji)/2,
+#   the first ratio taken as its limit dD_i/ds_i - dD_i/ds_j where s_i = s_j.
+
+def signed_svd(F: np.ndarray):
+    """F = U diag(s) V^T with det U = det V = +1; s_3 < 0 where det F < 0."""
+    U, s, Vt = np.linalg.svd(F)
+    U, s, Vt = U.copy(), s.copy(), Vt.copy()
+    nu = np.linalg.det(U) < 0
+    U[nu, :, 2] *= -1.0
+    s[nu, 2] *= -1.0
+    nv = np.linalg.det(Vt) < 0
+    Vt[nv, 2, :] *= -1.0
+    s[nv, 2] *= -1.0
+    return U, s, Vt
+
+
+def _kkt_parts(s, d):
+    """c(d), grad c(d) and the Hessian of c at s + d (batched)."""
+    D = s + d
+    c = np.prod(D, axis=-1) - 1.0
+    g = np.stack([D[..., 1] * D[..., 2], D[..., 0] * D[..., 2], D[..., 0] * D[..., 1]], axis=-1)
+    H = np.zeros(D.shape + (3,))
+    H[..., 0, 1] = H[..., 1, 0] = D[..., 2]
+    H[..., 0, 2] = H[..., 2, 0] = D[..., 1]
+    H[..., 1, 2] = H[..., 2, 1] = D[..., 0]
+    return c, g, H
+
+
+def volume_kkt(s: np.ndarray, max_iter: int = 60):
+    """(d*, lam*) for singular values s [..., 3] with prod(s) > 0: Newton's
+    method on the KKT conditions from d = 0, lam = 0."""
+    d = np.zeros_like(s)
+    lam = np.zeros(s.shape[:-1])
+    for _ in range(max_iter):
+        c, g, H = _kkt_parts(s, d)
+        r = np.concatenate([d + lam[..., None] * g, c[..., None]], axis=-1)
+        J = np.zeros(s.shape[:-1] + (4, 4))
+        J[..., :3, :3] = np.eye(3) + lam[..., None, None] * H
+        J[..., :3, 3] = g
+        J[..., 3, :3] = g
+        step = np.linalg.solve(J, -r[..., None])[..., 0]
+        d = d + step[..., :3]
+        lam = lam + step[..., 3]
+        if np.all(np.abs(step[..., :3]) <= 1e-16 * (1.0 + np.abs(s))):
+            break
+    return d, lam
+
+
+def volume_projection(F: np.ndarray) -> np.ndarray:
+    """D[..., 3, 3], the projection of F onto {det D = 1} (rotation where det F <= 0)."""
+    U, s, Vt = signed_svd(F)
+    ok = s[..., 2] > 0
+    Dd = np.ones_like(s)
+    if np.any(ok):
+        d, _ = volume_kkt(s[ok])
+        Dd[ok] = s[ok] + d
+    return U @ (Dd[..., :, None] * Vt)
+
+
+def volume_diag_jacobian(s: np.ndarray) -> np.ndarray:
+    """dD_i/ds_j [..., 3, 3] from eq:vol_kkt with one-hot ds."""
+    d, lam = volume_kkt(s)
+    c, g, H = _kkt_parts(s, d)
+    K = np.zeros(s.shape[:-1] + (4, 4))
+    K[..., :3, :3] = np.eye(3) + lam[..., None, None] * H
+    K[..., :3, 3] = g
+    K[..., 3, :3] = g
+    out = np.zeros(s.shape + (3,))
+    for j in range(3):
+        e = np.zeros(s.shape)
+        e[..., j] = 1.0
+        rhs = np.concatenate([-lam[..., None] * (H @ e[..., None])[..., 0], -(g * e).sum(-1, keepdims=True)],
+                             axis=-1)
+        sol = np.linalg.solve(K, rhs[..., None])[..., 0]
+        out[..., :, j] = e + sol[..., :3]          # dD_i/ds_j = delta_ij + dd*_i/ds_j
+    return out, s + d
+
+
+def volume_differential(F: np.ndarray, dF: np.ndarray) -> np.ndarray:
+    """dD[dF] for the volume projection (batched over leading axes)."""
+    U, s, Vt = signed_svd(F)
+    V = np.swapaxes(Vt, -1, -2)
+    A = np.swapaxes(U, -1, -2) @ dF @ V
+    ok = s[..., 2] > 0
+    out = np.zeros(F.shape)
+    if np.any(~ok):
+        R = U[~ok] @ Vt[~ok]
+        out[~ok] = rotation_differential(F[~ok], R, dF[~ok])
+    if np.any(ok):
+        G, Dd = volume_diag_jacobian(s[ok])
+        a = A[ok]
+        sk = s[ok]
+        B = np.zeros(a.shape)
+        for i in range(3):
+            B[:, i, i] = (G[:, i, :] * np.diagonal(a, axis1=1, axis2=2)).sum(-1)
+            for j in range(3):
+                if i == j:
+                    continue
+                ds = sk[:, i] - sk[:, j]
+                close = np.abs(ds) <= 1e-9 * (np.abs(sk[:, i]) + np.abs(sk[:, j]))
+                ratio = np.where(close, G[:, i, i] - G[:, i, j], (Dd[:, i] - Dd[:, j]) / np.where(close, 1.0, ds))
+                skew = (Dd[:, i] + Dd[:, j]) / (sk[:, i] + sk[:, j])
+                B[:, i, j] = ratio * 0.5 * (a[:, i, j] + a[:, j, i]) + skew * 0.5 * (a[:, i, j] - a[:, j, i])
+        out[ok] = U[ok] @ B @ Vt[ok]
+    return out
+
+
+def volume_jacobian(F: np.ndarray) -> np.ndarray:
+    """J[..., 9, 9] with J[(i,j),(k,l)] = dD_ij / dF_kl (row-major flattening)."""
+    J = np.zeros(F.shape[:-2] + (9, 9))
+    for kl in range(9):
+        E = np.zeros(F.shape)
+        E[..., kl // 3, kl % 3] = 1.0
+        J[..., :, kl] = volume_differential(F, E).reshape(F.shape[:-2] + (9,))
+    return J
+
+
 def sphere_projection(f: np.ndarray, r: np.ndarray, fiber: np.ndarray) -> np.ndarray:
     """p = r f/|f| (p = r m where f = 0)."""
     nrm = np.linalg.norm(f, axis=-1)

@@ -65,6 +65,8 @@ class Scene:
     friction_mu: float = 0.0          # Coulomb coefficient of the explicit friction
     friction_eps: float = 1e-3        # velocity regulariser of the friction, m/s
     muscle_k: float = 0.0             # fibre stiffness per unit volume, Pa (0 = off)
+    volume_scale: float = 0.0         # weight of the volume-preserving term in units of
+                                      # Lame's lambda per unit volume (0 = off)
     fiber: tuple = (1.0, 0.0, 0.0)    # unit fibre direction
     steps: int = 10
     loss_seed: int = 0
