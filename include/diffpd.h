@@ -110,6 +110,19 @@ typedef struct {
                               step with contact (all iterations for one contact
                               set) runs as one cooperative launch; 0: a few
                               launches per iteration (same iteration)           */
+  int32_t sweep_launch;    /* global step A^{-1} b through the factor's sweeps:
+                              1: both sweeps in one launch whose tasks wait on
+                              the tasks they depend on (default); 0: one launch
+                              per tree level and sweep.  Same arithmetic, same
+                              result bit for bit                                */
+  double volume_scale;     /* volume-preserving term (supplemental Sec. Energy
+                              Definitions, E = w/2 |F - D|^2, D the projection
+                              of F onto det D = 1): weight per Gauss point
+                              w = volume_scale * lambda * V_q with Lame's
+                              lambda = E nu / ((1 + nu)(1 - 2 nu)); 0 = off.
+                              With it on, solves use the factor's sweeps (the
+                              fused dense solver and fused contact loops are
+                              not used)                                        */
 } dpd_options;
 
 typedef struct {
@@ -136,6 +149,9 @@ typedef struct {
                               launch; 0 when solves use the multi-launch path    */
   int64_t fused_lds;       /* its LDS placement, FP64 | FP32 << 2 (bits as in
                               dpd_options.fused_cg)                              */
+  int64_t solve_workgroups;/* workgroups of the single-launch solve; 0 when its
+                              plan does not fit (solves use the level launches) */
+  int64_t solve_entries;   /* entries of its queue (both sweeps)                 */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
@@ -357,7 +373,8 @@ enum {
   DPD_PROF_CONTACT_DESCEND = 10, /* k_contact_descend: reduced global step of a contact step */
   DPD_PROF_CONTACT_DENSE = 11,   /* k_contact_dense_step: the same with a dense inverse      */
   DPD_PROF_CONTACT_FUSED = 12,   /* k_contact_fused: a contact set's whole inner loop        */
-  DPD_PROF_CONTACT_FUSED_CG = 13 /* k_contact_fused_cg: the contact adjoint's CG loop         */
+  DPD_PROF_CONTACT_FUSED_CG = 13,/* k_contact_fused_cg: the contact adjoint's CG loop         */
+  DPD_PROF_SOLVE_DAG = 14        /* k_solve_dag: a whole A^{-1} b in one launch (sweep_launch 1) */
 };
 typedef struct {
   int64_t launches;

@@ -33,7 +33,8 @@ class Options(C.Structure):
         ("fwd_solver", C.c_int32), ("fwd_inner_max_iter", C.c_int32), ("fwd_inner_tol", C.c_double),
         ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
         ("precision", C.c_int32), ("check_every", C.c_int32), ("use_graphs", C.c_int32),
-        ("fused_cg", C.c_int32), ("contact_fused", C.c_int32),
+        ("fused_cg", C.c_int32), ("contact_fused", C.c_int32), ("sweep_launch", C.c_int32),
+        ("volume_scale", C.c_double),
     ]
 
 
@@ -51,7 +52,8 @@ class Stats(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
-        "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds")]
+        "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds",
+        "solve_workgroups", "solve_entries")]
 
 
 class KernelProfile(C.Structure):
@@ -76,7 +78,7 @@ class Result(C.Structure):
 DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4, "solve": 5,
             "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7, "cg_dense": 8, "contact_update": 9,
             "contact_descend": 10, "contact_dense": 11, "contact_fused": 12,
-            "contact_fused_cg": 13}
+            "contact_fused_cg": 13, "solve_dag": 14}
 
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)

@@ -58,8 +58,13 @@ struct dpd_mesh {
   SweepTask* d_fwd = nullptr;
   SweepTask* d_bwd = nullptr;
   int32_t* d_gather = nullptr;
+  DagPlan dag;                                    // single-launch solve (both sweeps)
+  DevDag dd{};
+  bool dag_ok = false;                            // plan uploaded and fits the launch limits
+  uint32_t* h_dag_aborts = nullptr;               // pinned mirror of its abort count
   double solve_bytes = 0.0, solve_flops = 0.0;   // algorithmic work of one A^{-1} b
   int32_t leaf_max = 0;                           // chosen dissection leaf size
+  int64_t method_factor_nnz = 0;                  // packed entries of a sparse factor (64-node leaves)
   uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
   hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
   // fused dense conjugate gradients (meshes with few free nodes)
@@ -71,6 +76,7 @@ struct dpd_mesh {
   bool capturing = false;
   hipStream_t capture_stream = nullptr;
   double* w_e = nullptr;
+  double* wv_e = nullptr;                         // volume-preserving weights (null: term off)
   double* panel64 = nullptr;
   float* panel32 = nullptr;
   double* panelT64 = nullptr;
@@ -240,6 +246,11 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
   const double scale = fp32 ? 0.5 : 1.0;
   ProfScope whole(m, s, DPD_PROF_SOLVE, m->solve_bytes * scale, m->solve_flops, st_idx, k);
 
+  if (m->opt.sweep_launch && m->dag_ok) {
+    ProfScope ps(m, s, DPD_PROF_SOLVE_DAG, m->solve_bytes * scale, m->solve_flops, st_idx, k);
+    launch_solve_dag(m->ds, m->dd, s, fp32, b, out, m->dm.N, alpha, accumulate, st);
+    return;
+  }
   const LevelPlan& P = m->plan;
   const int32_t L = m->S.n_levels;
   for (int32_t l = 0; l < L; ++l) {
@@ -270,8 +281,12 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
 
 dpd_status read_state(dpd_mesh* m, hipStream_t s) {
   HIPCHECK(m, hipMemcpyAsync(m->h_st, m->st, 2 * sizeof(IterState), hipMemcpyDeviceToHost, s));
+  if (m->dag_ok)
+    HIPCHECK(m, hipMemcpyAsync(m->h_dag_aborts, m->dd.ctr + kDagAborts, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(m, hipStreamSynchronize(s));
   prof_harvest(m);
+  if (m->dag_ok && *m->h_dag_aborts != 0u)
+    return fail(m, DPD_EHIP, "single-launch solve: a dependency wait timed out (results invalid)");
   return DPD_OK;
 }
 
@@ -315,6 +330,19 @@ std::vector<double> corotated_weights(const HostMesh& hm, const dpd_options& o) 
   for (int64_t e = 0; e < hm.n_elems; ++e) w[e] = 2.0 * hm.youngs[e] / (2.0 * (1.0 + o.nu)) * Vq;
   return w;
 }
+
+// Volume-preserving weight per Gauss point, volume_scale lambda_e V_q, and its
+// derivative in E_e.
+double volume_weight_per_youngs(const dpd_options& o) {
+  return o.volume_scale * o.nu / ((1.0 + o.nu) * (1.0 - 2.0 * o.nu)) * (o.dx * o.dx * o.dx / 8.0);
+}
+std::vector<double> volume_weights(const HostMesh& hm, const dpd_options& o) {
+  std::vector<double> w(hm.n_elems);
+  const double c = volume_weight_per_youngs(o);
+  for (int64_t e = 0; e < hm.n_elems; ++e) w[e] = c * hm.youngs[e];
+  return w;
+}
+int cache_rows(const dpd_options& o) { return o.volume_scale > 0.0 ? kAdjCacheRowsVolume : kAdjCacheRows; }
 
 // FP32 copies (column-major and row-major) of the FP64 panels.
 dpd_status make_fp32_panels(dpd_mesh* m, const std::vector<double>& panels, hipStream_t s) {
@@ -368,7 +396,9 @@ dpd_status dense_fp32(dpd_mesh* m, hipStream_t s) {
 dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
   const int n = (int)m->hm.n_free, N = (int)m->hm.n_nodes;
   m->dense_blocks = 0;
-  if (!m->opt.fused_cg || n < 1 || n > kSepMax) return DPD_OK;
+  // the fused kernels' element phase carries the corotated, muscle and ground
+  // terms only: with the volume-preserving term solves use the sweeps
+  if (!m->opt.fused_cg || m->opt.volume_scale > 0.0 || n < 1 || n > kSepMax) return DPD_OK;
   int G = 0;
   if (!m->dense_alloc) {
     int dev = 0, cus = 0;
@@ -521,6 +551,7 @@ dpd_status dpd_default_options(dpd_options* o) {
   o->use_graphs = 1;
   o->fused_cg = 1;
   o->contact_fused = 1;
+  o->sweep_launch = 0;
   return DPD_OK;
 }
 
@@ -579,6 +610,14 @@ dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* 
       m->leaf_max = leaf;
     }
   }
+  // the sparse factor the method would sweep (for the dense path's traffic count)
+  if (m->leaf_max == 64) {
+    m->method_factor_nnz = m->S.packed_nnz;
+  } else {
+    Symbolic S;
+    analyse(m->hm, m->A, 64, kSepMax, S);
+    m->method_factor_nnz = S.packed_nnz;
+  }
   fill_devmesh(m);
   *out = m;
   return DPD_OK;
@@ -596,10 +635,11 @@ int64_t footprint_bytes(const dpd_mesh* m) {
   b += 16 * (int64_t)(m->plan.fwd.size() + m->plan.bwd.size());
   b += 8 * (9 * nf + 3 * S.u_size + 24 * E + 9 * 3 * N);    // sweep vectors, fe, work vectors
   b += 4 * (int64_t)m->plan.gather_cols.size();
-  b += 8 * ((int64_t)kAdjCacheRows * 8 * E + 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
+  b += 8 * ((int64_t)cache_rows(m->opt) * 8 * E + 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
+  if (m->opt.volume_scale > 0.0) b += 8 * E;                 // volume weights
   b += 2 * 8 * S.panel_size;                                 // FP64 panels, both layouts
   if (m->opt.precision == DPD_MIXED) b += 2 * 4 * S.panel_size;  // FP32 copies
-  if (m->opt.fused_cg && nf >= 1 && nf <= kSepMax) {             // dense inverse and its vectors
+  if (m->opt.fused_cg && m->opt.volume_scale == 0.0 && nf >= 1 && nf <= kSepMax) {  // dense inverse
     b += nf * nf * (m->opt.precision == DPD_MIXED ? 12 : 8);
     b += 8 * 24 * nf + 4 * (9 * nf + N + 8 * E) + 8 * nf;
   }
@@ -631,6 +671,7 @@ dpd_status upload_device(dpd_mesh* m) {
   UP(fixed, hm.fixed);
   UP(contact, hm.is_contact);
   UP(m->w_e, corotated_weights(hm, m->opt));
+  if (m->opt.volume_scale > 0.0) UP(m->wv_e, volume_weights(hm, m->opt));
   UP(pp, perm_pub);
   UP(rows, m->S.rows);
   UP(cptr, m->S.cptr);
@@ -638,6 +679,49 @@ dpd_status upload_device(dpd_mesh* m) {
   UP(m->d_fwd, m->plan.fwd);
   UP(m->d_bwd, m->plan.bwd);
   UP(m->d_gather, m->plan.gather_cols);
+  // single-launch solve: its queue, supernode table and counters (zeroed here,
+  // then by the last workgroup of each launch); off when its LDS does not fit
+  build_dag(m->S, m->plan, kLdsBudget, m->dag);
+  if (m->dag.usable && !m->dag.q.empty()) {
+    DagEntry* q = nullptr;
+    DagSn* sn = nullptr;
+    uint32_t* ctr = nullptr;
+    UP(q, m->dag.q);
+    UP(sn, m->dag.sn);
+    if ((st = dev_alloc(m, &ctr, m->dag.counter_words())) != DPD_OK) {
+      dpd_destroy_mesh(m);
+      return st;
+    }
+    if (hipMemset(ctr, 0, m->dag.counter_words() * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void**)&m->h_dag_aborts, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      dpd_destroy_mesh(m);
+      return fail(nullptr, DPD_EHIP, "single-launch solve set-up failed");
+    }
+    *m->h_dag_aborts = 0u;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      dpd_destroy_mesh(m);
+      return fail(nullptr, DPD_EHIP, "device query failed");
+    }
+    // resident workgroups of the FP64 kernel (the FP32 one uses no more resources)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_dag_kernel(false), kDagThreads,
+                                                     m->dag.lds_bytes) != hipSuccess)
+      per_cu = 1;
+    DevDag& dd = m->dd;
+    dd.q = q;
+    dd.nq = (int32_t)m->dag.q.size();
+    dd.ns = (int32_t)m->dag.sn.size();
+    dd.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(dd.nq, (int64_t)std::max(1, per_cu) * cus));
+    dd.bwd_region = m->dag.bwd_region;
+    dd.fwd = m->d_fwd;
+    dd.bwd = m->d_bwd;
+    dd.gcols = m->d_gather;
+    dd.sn = sn;
+    dd.ctr = ctr;
+    dd.lds_bytes = (size_t)m->dag.lds_bytes;
+    m->dag_ok = true;
+  }
   for (int32_t l = 0; l < m->S.n_levels; ++l) {
     m->solve_bytes += m->plan.fwd_bytes[l] + m->plan.bwd_bytes[l];
     m->solve_flops += m->plan.fwd_flops[l] + m->plan.bwd_flops[l];
@@ -651,6 +735,8 @@ dpd_status upload_device(dpd_mesh* m) {
   d.fixed = fixed;
   d.contact = contact;
   d.w_e = m->w_e;
+  d.wv_e = m->wv_e;
+  d.dwv_dE = m->opt.volume_scale > 0.0 ? volume_weight_per_youngs(m->opt) : 0.0;
   DevSolve& ds = m->ds;
   ds.nf = (int32_t)nf;
   ds.perm_pub = pp;
@@ -670,7 +756,7 @@ dpd_status upload_device(dpd_mesh* m) {
   AL(m->r, 3 * N);
   AL(m->y, 3 * N);
   AL(m->partials, 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
-  AL(m->cache, (int64_t)kAdjCacheRows * 8 * E);
+  AL(m->cache, (int64_t)cache_rows(m->opt) * 8 * E);
   AL(m->z, 3 * N);
   AL(m->p, 3 * N);
   AL(m->q, 3 * N);
@@ -731,6 +817,7 @@ void destroy_synced(dpd_mesh* m) {
     (void)hipEventDestroy(e.ev.second);
   }
   if (m->h_st) (void)hipHostFree(m->h_st);
+  if (m->h_dag_aborts) (void)hipHostFree(m->h_dag_aborts);
   delete m;
 }
 
@@ -753,6 +840,8 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->leaf_nodes = m->leaf_max;
   info->fused_blocks = m->opt.fused_cg ? m->dense_blocks : 0;
   info->fused_lds = info->fused_blocks ? m->dcg.mode64 | (m->dcg.mode32 << 2) : 0;
+  info->solve_workgroups = m->dag_ok ? m->dd.grid : 0;
+  info->solve_entries = m->dag_ok ? m->dd.nq : 0;
   return DPD_OK;
 }
 
@@ -780,7 +869,8 @@ dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
   const dpd_options& c = m->opt;
   bool same = c.dx == o->dx && c.rho == o->rho && c.nu == o->nu && c.h == o->h &&
               c.contact_k == o->contact_k && c.muscle_k == o->muscle_k &&
-              c.friction_mu == o->friction_mu && c.friction_eps == o->friction_eps;
+              c.friction_mu == o->friction_mu && c.friction_eps == o->friction_eps &&
+              c.volume_scale == o->volume_scale;
   for (int k = 0; k < 3; ++k)
     same = same && c.gravity[k] == o->gravity[k] && c.origin[k] == o->origin[k] && c.fiber[k] == o->fiber[k];
   if (!same) return fail(m, DPD_EINVAL, "physics options are fixed at mesh creation");
@@ -813,6 +903,10 @@ dpd_status dpd_set_youngs(dpd_mesh* m, const double* youngs, int32_t on_device, 
   m->hm.youngs = ym;
   std::vector<double> w = corotated_weights(m->hm, m->opt);
   HIPCHECK(m, hipMemcpy(m->w_e, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (m->wv_e) {
+    std::vector<double> wv = volume_weights(m->hm, m->opt);
+    HIPCHECK(m, hipMemcpy(m->wv_e, wv.data(), wv.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   assemble_As(m->hm, m->opt, m->A);
   m->factored = false;
   return DPD_OK;
@@ -1052,20 +1146,31 @@ hipGraphExec_t cg_graph(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32) {
 // must describe the linearisation point.  Iterations run as captured graphs of
 // kGraphIters, except that while a kernel class is being timed one chunk in
 // kProfStride runs as direct launches (timed live).
-// Algorithmic traffic of the fused solver: one product with A^{-1} (n^2
-// entries and the 3n-vectors r in, s out) and, per iteration, that product,
-// the rotation cache of every Gauss point (15 doubles, 19 with muscles), the
-// connectivity and weights, and the 3n-vectors r, q, w, s, p, z each read and
-// written once.
+// Algorithmic traffic of the fused solver, counted as the method's: the
+// preconditioner A^{-1} r costs what the factor's two sweeps move (the packed
+// entries of a sparse Cholesky factor of A_s, nested dissection with 64-node
+// leaves, read once per sweep, 8 bytes each; half for FP32), not the dense
+// n x n inverse this path holds instead.  Per launch one such product (plus
+// the 3n-vectors r in, s out); per iteration that product, the rotation cache
+// of every Gauss point (15 doubles, 19 with muscles), the connectivity and
+// weights, the product with A (12 bytes per stored entry of the lower
+// triangle of A_s, plus the 3N-vectors in and out) and the 3n-vectors r, q,
+// w, s, p, z each read and written once.
+double sparse_solve_bytes(const dpd_mesh* m, bool fp32) {
+  return 2.0 * (fp32 ? 4.0 : 8.0) * (double)m->method_factor_nnz;
+}
+
 double dense_matvec_bytes(const dpd_mesh* m, bool fp32) {
   const double n = (double)m->hm.n_free;
-  return n * n * (fp32 ? 4.0 : 8.0) + 2.0 * 3.0 * n * 8.0;
+  return sparse_solve_bytes(m, fp32) + 2.0 * 3.0 * n * 8.0;
 }
 
 double dense_iter_bytes(const dpd_mesh* m, bool fp32) {
-  const double n = (double)m->hm.n_free, E = (double)m->hm.n_elems;
+  const double n = (double)m->hm.n_free, E = (double)m->hm.n_elems, N = (double)m->hm.n_nodes;
   const double rows = m->opt.muscle_k > 0.0 ? 19.0 : 15.0;
-  return n * n * (fp32 ? 4.0 : 8.0) + rows * 8.0 * E * 8.0 + 8.0 * E * 4.0 + E * 8.0 + 12.0 * 3.0 * n * 8.0;
+  const double a_lower = 0.5 * ((double)m->A.col.size() + n);
+  return sparse_solve_bytes(m, fp32) + rows * 8.0 * E * 8.0 + 8.0 * E * 4.0 + E * 8.0 +
+         12.0 * a_lower + 2.0 * 3.0 * N * 8.0 + 12.0 * 3.0 * n * 8.0;
 }
 
 // One fused solve on state st (reset beforehand with its tolerance and cap)
@@ -1675,7 +1780,7 @@ dpd_status dpd_contact_solve(dpd_mesh* m, void* stream, const int32_t* set_host,
 
 dpd_status dpd_profile_start(dpd_mesh* m, int32_t kernel_class) {
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_CONTACT_FUSED_CG)
+  if (kernel_class < DPD_PROF_OFF || kernel_class > DPD_PROF_SOLVE_DAG)
     return fail(m, DPD_EINVAL, "unknown kernel class");
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) == hipSuccess &&

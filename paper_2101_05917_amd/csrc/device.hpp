@@ -61,6 +61,8 @@ struct DevMesh {
   const uint8_t* fixed;       // [N]
   const uint8_t* contact;     // [N]
   const double* w_e;          // [E] corotated weight per Gauss point, 2 mu_e V_q
+  const double* wv_e;         // [E] volume-preserving weight per Gauss point, or null (term off)
+  double dwv_dE;              // d(wv_e)/dE_e
   uint8_t* cmask;             // [N] ground contact active at the linearisation point
 };
 
@@ -104,6 +106,18 @@ struct DenseCG {
 };
 
 void launch_hold(hipStream_t s, int periods);
+
+// Device side of the single-launch solve (DagPlan uploaded).
+struct DevDag {
+  const DagEntry* q;
+  int32_t nq, ns, grid, bwd_region;
+  const SweepTask* fwd;
+  const SweepTask* bwd;
+  const int32_t* gcols;
+  const DagSn* sn;
+  uint32_t* ctr;
+  size_t lds_bytes;
+};
 
 // Device-side timing of the launches of one kernel class while it is being
 // profiled, by the constant 100 MHz clock of s_memrealtime (the same on every
@@ -170,6 +184,9 @@ void launch_node_residual(const DevMesh& M, hipStream_t s, const double* x, cons
                           int max_iter, int fixed_iters);
 void launch_velocity(const DevMesh& M, hipStream_t s, const double* x, const double* xn, double* vn);
 void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v);
+void launch_solve_dag(const DevSolve& S, const DevDag& D, hipStream_t s, bool fp32, const double* b, double* out,
+                      int N, double alpha, int accumulate, const IterState* st);
+const void* solve_dag_kernel(bool fp32);
 void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                       int lds_cols, bool fp32, const double* b, int N, const IterState* st);
 void launch_sweep_fwd_wide(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
@@ -206,6 +223,11 @@ void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
                         const double* cache, double* g_youngs, double* g_act, const IterState* gate = nullptr);
 constexpr int kAdjCacheRows = 19;
+// With the volume-preserving term the cache also holds, per Gauss point:
+// V (rows 19-27), G = dD/ds (28-36), r (37-39), k (40-42), the projected
+// singular values (43-45) and 1 where the projection applies (46).
+constexpr int kAdjCacheRowsVolume = 47;
+constexpr int kVolV = 19, kVolG = 28, kVolR = 37, kVolK = 40, kVolD = 43, kVolOk = 46;
 // fused dense solver (cg_dense.hip)
 size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32);
 int cg_dense_max_blocks(int n, int rows, int mode, bool fp32);

@@ -362,6 +362,223 @@ __device__ inline void rotation_apply_diff(const double R[9], const double Ki[6]
   }
 }
 
+// ------------------------------------------------------------------ volume preservation
+//
+// Volume-preserving term (supplemental Sec. Energy Definitions): the
+// projection D of F onto {det D = 1}.  F = R S with R the closest rotation
+// and S = R^T F symmetric; S = V diag(s) V^T (cyclic Jacobi rotations, V a
+// proper rotation) gives the signed SVD F = (R V) diag(s) V^T.  With d the
+// minimiser of |d|^2 subject to prod(s_i + d_i) = 1, found by Newton's method
+// on its KKT conditions d + lam grad c = 0, c = prod(s + d) - 1 from d = 0,
+// D = R V diag(s + d) V^T.  Where an eigenvalue of S is not positive (det F
+// <= 0) the constraint cannot be met on that branch and D = R (its derivative
+// then dR/dF).  For the adjoint, dD[dF] = U B V^T with U = R V, A = U^T dF V,
+// B_ii = sum_k G_ik A_kk (G = dD/ds from the differentiated KKT system,
+// eq:vol_kkt) and for i != j
+//   B_ij = r_ij (A_ij + A_ji)/2 + k_ij (A_ij - A_ji)/2,
+// r_ij = (D_i - D_j)/(s_i - s_j) (G_ii - G_ij where s_i = s_j),
+// k_ij = (D_i + D_j)/(s_i + s_j).
+
+// Symmetric 3x3 A (row-major, symmetric) = V diag(w) V^T by cyclic Jacobi
+// rotations; V is a product of plane rotations (det +1).
+__device__ inline void sym3_eigen(const double S[9], double V[9], double w[3]) {
+  double a[3][3] = {{S[0], 0.5 * (S[1] + S[3]), 0.5 * (S[2] + S[6])},
+                    {0.5 * (S[1] + S[3]), S[4], 0.5 * (S[5] + S[7])},
+                    {0.5 * (S[2] + S[6]), 0.5 * (S[5] + S[7]), S[8]}};
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-34 * dia)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+      // A <- J^T A J with J the rotation in the (p, q) plane
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double akp = a[k][p], akq = a[k][q];
+        a[k][p] = c * akp - sn * akq;
+        a[k][q] = sn * akp + c * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double apk = a[p][k], aqk = a[q][k];
+        a[p][k] = c * apk - sn * aqk;
+        a[q][k] = sn * apk + c * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = v[k][p], vkq = v[k][q];
+        v[k][p] = c * vkp - sn * vkq;
+        v[k][q] = sn * vkp + c * vkq;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    w[i] = a[i][i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[3 * i + j] = v[i][j];
+  }
+}
+
+// Solution of the KKT system [[K, g], [g^T, 0]] [x; y] = [b1; b2] with
+// K = I + lam H (H: the Hessian of c, zero diagonal, off-diagonal
+// h01 = D2, h02 = D1, h12 = D0) by the Schur complement on g.
+__device__ inline void kkt_solve(double lam, const double D[3], const double g[3], const double b1[3],
+                                 double b2, double x[3], double& y) {
+  const double k00 = 1.0, k11 = 1.0, k22 = 1.0, k01 = lam * D[2], k02 = lam * D[1], k12 = lam * D[0];
+  const double c00 = k11 * k22 - k12 * k12, c11 = k00 * k22 - k02 * k02, c22 = k00 * k11 - k01 * k01;
+  const double c01 = k02 * k12 - k01 * k22, c02 = k01 * k12 - k02 * k11, c12 = k01 * k02 - k00 * k12;
+  const double det = k00 * c00 + k01 * c01 + k02 * c02;
+  const double id = 1.0 / det;
+  auto kinv = [&](const double r[3], double o[3]) {
+    o[0] = (c00 * r[0] + c01 * r[1] + c02 * r[2]) * id;
+    o[1] = (c01 * r[0] + c11 * r[1] + c12 * r[2]) * id;
+    o[2] = (c02 * r[0] + c12 * r[1] + c22 * r[2]) * id;
+  };
+  double kb[3], kg[3];
+  kinv(b1, kb);
+  kinv(g, kg);
+  y = (g[0] * kb[0] + g[1] * kb[1] + g[2] * kb[2] - b2) / (g[0] * kg[0] + g[1] * kg[1] + g[2] * kg[2]);
+  x[0] = kb[0] - kg[0] * y;
+  x[1] = kb[1] - kg[1] * y;
+  x[2] = kb[2] - kg[2] * y;
+}
+
+// Per Gauss point: V (signed SVD F = R V diag(s) V^T), the projected singular
+// values Dd = s + d, and whether the projection applies (det F > 0).
+struct VolumeProj {
+  double V[9], s[3], Dd[3], lam;
+  bool ok;
+};
+
+__device__ inline void volume_project(const double F[9], const double R[9], VolumeProj& P) {
+  double S[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = R[i] * F[j] + R[3 + i] * F[3 + j] + R[6 + i] * F[6 + j];
+  sym3_eigen(S, P.V, P.s);
+  P.ok = P.s[0] > 0.0 && P.s[1] > 0.0 && P.s[2] > 0.0;
+  P.lam = 0.0;
+  if (!P.ok) {
+    P.Dd[0] = P.Dd[1] = P.Dd[2] = 1.0;
+    return;
+  }
+  double d[3] = {0.0, 0.0, 0.0}, lam = 0.0;
+  for (int it = 0; it < 40; ++it) {
+    const double D[3] = {P.s[0] + d[0], P.s[1] + d[1], P.s[2] + d[2]};
+    const double g[3] = {D[1] * D[2], D[0] * D[2], D[0] * D[1]};
+    const double c = D[0] * D[1] * D[2] - 1.0;
+    const double r1[3] = {-(d[0] + lam * g[0]), -(d[1] + lam * g[1]), -(d[2] + lam * g[2])};
+    double dd[3], dl;
+    kkt_solve(lam, D, g, r1, -c, dd, dl);
+    d[0] += dd[0];
+    d[1] += dd[1];
+    d[2] += dd[2];
+    lam += dl;
+    if (fabs(dd[0]) <= 1e-16 * (1.0 + fabs(P.s[0])) && fabs(dd[1]) <= 1e-16 * (1.0 + fabs(P.s[1])) &&
+        fabs(dd[2]) <= 1e-16 * (1.0 + fabs(P.s[2])))
+      break;
+  }
+  P.Dd[0] = P.s[0] + d[0];
+  P.Dd[1] = P.s[1] + d[1];
+  P.Dd[2] = P.s[2] + d[2];
+  P.lam = lam;
+}
+
+// D = R V diag(Dd) V^T.
+__device__ inline void volume_matrix(const double R[9], const double V[9], const double Dd[3], double D[9]) {
+  double M[9];   // V diag(Dd) V^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = V[3 * i] * Dd[0] * V[3 * j] + V[3 * i + 1] * Dd[1] * V[3 * j + 1] +
+                     V[3 * i + 2] * Dd[2] * V[3 * j + 2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      D[3 * i + j] = R[3 * i] * M[j] + R[3 * i + 1] * M[3 + j] + R[3 * i + 2] * M[6 + j];
+}
+
+// Derivative data of the projection: G = dD/ds (row-major 3x3) from the
+// differentiated KKT system, the ratios r (pairs 01, 02, 12) and k.
+__device__ inline void volume_derivative_data(const VolumeProj& P, double G[9], double r[3], double k[3]) {
+  const double* D = P.Dd;
+  const double g[3] = {D[1] * D[2], D[0] * D[2], D[0] * D[1]};
+  const double lam = P.lam;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    // right-hand side (-lam H e_j, -g_j)
+    double b1[3];
+    b1[0] = j == 0 ? 0.0 : -lam * (j == 1 ? D[2] : D[1]);
+    b1[1] = j == 1 ? 0.0 : -lam * (j == 0 ? D[2] : D[0]);
+    b1[2] = j == 2 ? 0.0 : -lam * (j == 0 ? D[1] : D[0]);
+    double x[3], y;
+    kkt_solve(lam, D, g, b1, -g[j], x, y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G[3 * i + j] = (i == j ? 1.0 : 0.0) + x[i];
+  }
+  const int I[3] = {0, 0, 1}, J[3] = {1, 2, 2};
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int i = I[p], j = J[p];
+    const double ds = P.s[i] - P.s[j];
+    r[p] = fabs(ds) <= 1e-9 * (fabs(P.s[i]) + fabs(P.s[j])) ? G[3 * i + i] - G[3 * i + j] : (D[i] - D[j]) / ds;
+    k[p] = (D[i] + D[j]) / (P.s[i] + P.s[j]);
+  }
+}
+
+// dD[dF] from the cached data (R, V, G, r, k).
+__device__ inline void volume_apply_diff(const double R[9], const double V[9], const double G[9], const double r[3],
+                                         const double k[3], const double dF[9], double dD[9]) {
+  double U[9], T[9], A[9], B[9];
+  // U = R V
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[3 * i + j] = R[3 * i] * V[j] + R[3 * i + 1] * V[3 + j] + R[3 * i + 2] * V[6 + j];
+  // A = U^T dF V
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = U[i] * dF[j] + U[3 + i] * dF[3 + j] + U[6 + i] * dF[6 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = T[3 * i] * V[j] + T[3 * i + 1] * V[3 + j] + T[3 * i + 2] * V[6 + j];
+  B[0] = G[0] * A[0] + G[1] * A[4] + G[2] * A[8];
+  B[4] = G[3] * A[0] + G[4] * A[4] + G[5] * A[8];
+  B[8] = G[6] * A[0] + G[7] * A[4] + G[8] * A[8];
+  const int I[3] = {0, 0, 1}, J[3] = {1, 2, 2};
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int i = I[p], j = J[p];
+    const double sym = 0.5 * (A[3 * i + j] + A[3 * j + i]), skw = 0.5 * (A[3 * i + j] - A[3 * j + i]);
+    B[3 * i + j] = r[p] * sym + k[p] * skw;
+    B[3 * j + i] = r[p] * sym - k[p] * skw;
+  }
+  // dD = U B V^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = U[3 * i] * B[j] + U[3 * i + 1] * B[3 + j] + U[3 * i + 2] * B[6 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      dD[3 * i + j] = T[3 * i] * V[3 * j] + T[3 * i + 1] * V[3 * j + 1] + T[3 * i + 2] * V[3 * j + 2];
+}
+
 // Element tile: 32 elements x 8 Gauss points per 256-thread block.
 template <int kE>
 struct ElemTileT {
@@ -463,12 +680,40 @@ __device__ inline void load_gauss_cache(const DevMesh& M, const double* __restri
   for (int i = 0; i < 19; ++i) cq[i] = i < rows ? cache[i * Q + qi] : 0.0;
 }
 
+// The volume-preserving term of (A - dA) p at Gauss point q of element e:
+// P += w_v (dF - dD[dF]) from the cached projection data.
+__device__ inline void hvp_volume(const DevMesh& M, double* P, const double dF[9], int e, int q,
+                                  const double* __restrict__ cache, const double cq[19]) {
+  const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
+  double dD[9];
+  if (cache[kVolOk * Q + qi] != 0.0) {
+    double V[9], Gm[9], r[3], k[3];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      V[i] = cache[(kVolV + i) * Q + qi];
+      Gm[i] = cache[(kVolG + i) * Q + qi];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      r[i] = cache[(kVolR + i) * Q + qi];
+      k[i] = cache[(kVolK + i) * Q + qi];
+    }
+    volume_apply_diff(cq, V, Gm, r, k, dF, dD);
+  } else {
+    rotation_apply_diff(cq, cq + 9, dF, dD);   // D = R where det F <= 0
+  }
+  const double wv = M.wv_e[e];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P[i] += wv * (dF[i] - dD[i]);
+}
+
 __device__ inline void hvp_stress(const DevMesh& M, ElemTile& T, int le, int q, int e, const GradTable& G,
                                   const double* __restrict__ cache) {
   double cq[19], dF[9];
   load_gauss_cache(M, cache, e, q, cq);
   deformation_gradient(T, le, q, G, dF);
   hvp_stress_from_dF(M, T.Ps[le][q], dF, M.w_e[e], cq);
+  if (M.wv_e) hvp_volume(M, T.Ps[le][q], dF, e, q, cache, cq);
 }
 
 // Sum the element forces of every node (fixed order) and form the residual.

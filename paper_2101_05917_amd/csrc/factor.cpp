@@ -427,4 +427,89 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
   P.bwd_off[L] = (int32_t)P.bwd.size();
 }
 
+
+void build_dag(const Symbolic& S, const LevelPlan& P, int64_t lds_budget_bytes, DagPlan& D) {
+  const int32_t L = S.n_levels, ns = (int32_t)S.sn.size();
+  D.q.clear();
+  D.bwd_region = 0;
+  D.usable = true;
+  D.sn.assign(ns, DagSn{});
+  for (int32_t s = 0; s < ns; ++s) {
+    D.sn[s].parent = S.sn[s].parent;
+    D.sn[s].nch = (int32_t)S.children[s].size();
+  }
+  int64_t lds = 0;
+  auto entry = [](int32_t kind, int32_t n, int32_t first, int32_t lpr, int32_t flags) {
+    DagEntry e{};
+    e.kind = kind;
+    e.n = n;
+    e.first = first;
+    e.lpr = lpr;
+    e.flags = flags;
+    for (int k = 0; k < kDagSub; ++k) e.sn[k] = -1;
+    return e;
+  };
+  for (int32_t l = 0; l < L; ++l) {
+    // gathers of the level: runs of at most kDagGatherCols columns of one supernode
+    for (int32_t g = P.gather_off[l]; g < P.gather_off[l + 1];) {
+      const int32_t s = S.snode_of[P.gather_cols[g]];
+      int32_t n = 1;
+      while (n < kDagGatherCols && g + n < P.gather_off[l + 1] && S.snode_of[P.gather_cols[g + n]] == s) ++n;
+      DagEntry e = entry(kDagGather, n, g, 0, 0);
+      e.sn[0] = s;
+      D.q.push_back(e);
+      D.sn[s].ngt += 1;
+      g += n;
+    }
+    const int32_t t0 = P.fwd_off[l], t1 = P.fwd_off[l + 1];
+    if (P.fwd_wide[l]) {
+      const int32_t lpr = sweep_lanes(P.fwd_cols[l]);
+      const int32_t pre = P.gather_off[l + 1] > P.gather_off[l] ? 1 : 0;
+      lds = std::max<int64_t>(lds, 3 * (int64_t)P.fwd_cols[l] * 8);
+      for (int32_t t = t0; t < t1; ++t) {
+        DagEntry e = entry(kDagFwdWide, 1, t, lpr, pre);
+        e.sn[0] = P.fwd[t].sn;
+        D.q.push_back(e);
+      }
+    } else {
+      lds = std::max<int64_t>(lds, kDagSub * lds_fwd_narrow(kDagNarrowCols) * 8);
+      for (int32_t t = t0; t < t1; t += kDagSub) {
+        const int32_t n = std::min(kDagSub, t1 - t);
+        DagEntry e = entry(kDagFwdNarrow, n, t, 0, 0);
+        for (int32_t k = 0; k < n; ++k) e.sn[k] = P.fwd[t + k].sn;
+        D.q.push_back(e);
+      }
+    }
+    for (int32_t t = t0; t < t1; ++t) D.sn[P.fwd[t].sn].ntf += 1;
+  }
+  D.n_fwd = (int32_t)D.q.size();
+  for (int32_t l = L - 1; l >= 0; --l) {
+    const int32_t t0 = P.bwd_off[l], t1 = P.bwd_off[l + 1];
+    if (P.bwd_narrow[l]) {
+      D.bwd_region = std::max<int32_t>(D.bwd_region, (int32_t)lds_bwd_narrow(P.bwd_rows[l]));
+      lds = std::max<int64_t>(lds, kDagSub * (int64_t)D.bwd_region * 8);
+      for (int32_t t = t0; t < t1; t += kDagSub) {
+        const int32_t n = std::min(kDagSub, t1 - t);
+        DagEntry e = entry(kDagBwdNarrow, n, t, 0, 0);
+        for (int32_t k = 0; k < n; ++k) e.sn[k] = P.bwd[t + k].sn;
+        D.q.push_back(e);
+      }
+    } else {
+      const int32_t lpr = sweep_lanes(P.bwd_rows[l]);
+      const int64_t need = 3 * (int64_t)P.bwd_rows[l] * 8;
+      const int32_t staged = need <= lds_budget_bytes ? 2 : 0;
+      if (staged) lds = std::max(lds, need);
+      else D.usable = false;   // the kernel stages every column task's vector in LDS
+      for (int32_t t = t0; t < t1; ++t) {
+        DagEntry e = entry(kDagBwdCols, 1, t, lpr, staged);
+        e.sn[0] = P.bwd[t].sn;
+        D.q.push_back(e);
+      }
+    }
+    for (int32_t t = t0; t < t1; ++t) D.sn[P.bwd[t].sn].ntb += 1;
+  }
+  D.lds_bytes = lds;
+  if (lds > lds_budget_bytes) D.usable = false;
+}
+
 }  // namespace dpd

@@ -44,6 +44,7 @@ std::string build_mesh(const int32_t* cells, int64_t n_cells, const double* youn
   if (!(o.dx > 0) || !(o.rho > 0) || !(o.h > 0)) return "dx, rho and h must be positive";
   if (!(o.nu >= 0.0 && o.nu < 0.5)) return "nu must lie in [0, 0.5)";
   if (o.contact_k < 0 || o.muscle_k < 0 || o.friction_mu < 0) return "negative contact/muscle/friction";
+  if (!(o.volume_scale >= 0.0) || !std::isfinite(o.volume_scale)) return "volume_scale must be >= 0";
   for (int64_t e = 0; e < n_cells; ++e)
     if (!(youngs[e] > 0) || !std::isfinite(youngs[e])) return "Young's moduli must be positive";
   for (int64_t e = 0; e < 3 * n_cells; ++e)
@@ -156,7 +157,9 @@ void assemble_As(const HostMesh& m, const dpd_options& o, Csr& A) {
   std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
   for (int64_t e = 0; e < m.n_elems; ++e) {
     const double mu = m.youngs[e] / (2.0 * (1.0 + o.nu));
-    const double w = 2.0 * mu;  // w_q = 2 mu V_q, V_q folded into K0
+    // w_q = 2 mu V_q (+ the volume term's volume_scale lambda V_q), V_q folded into K0
+    const double lam = m.youngs[e] * o.nu / ((1.0 + o.nu) * (1.0 - 2.0 * o.nu));
+    const double w = 2.0 * mu + o.volume_scale * lam;
     for (int a = 0; a < 8; ++a) {
       int32_t ia = m.free_index[m.conn[8 * e + a]];
       if (ia < 0) continue;

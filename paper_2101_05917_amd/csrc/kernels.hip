@@ -54,6 +54,19 @@ __global__ void __launch_bounds__(kBlock) k_elem_forces(DevMesh M, const double*
     double* P = T.Ps[le][q];
 #pragma unroll
     for (int i = 0; i < 9; ++i) P[i] = w * (F[i] - R[i]);
+    if (M.wv_e) {
+      // volume-preserving term: projection onto det D = 1 (D = R where det F <= 0)
+      VolumeProj vp;
+      volume_project(F, R, vp);
+      double D[9];
+      if (vp.ok) volume_matrix(R, vp.V, vp.Dd, D);
+      else
+#pragma unroll
+        for (int i = 0; i < 9; ++i) D[i] = R[i];
+      const double wv = M.wv_e[e];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) P[i] += wv * (F[i] - D[i]);
+    }
     if (R_out) {
       const int64_t Q = 8 * (int64_t)M.E, qi = 8 * (int64_t)e + q;
 #pragma unroll
@@ -249,6 +262,24 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
   for (int i = 0; i < 9; ++i) cache[i * Q + qi] = R[i];
 #pragma unroll
   for (int i = 0; i < 6; ++i) cache[(9 + i) * Q + qi] = Ki[i];
+  if (M.wv_e) {
+    VolumeProj vp;
+    volume_project(F, R, vp);
+    double Gm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, r[3] = {0, 0, 0}, k[3] = {0, 0, 0};
+    if (vp.ok) volume_derivative_data(vp, Gm, r, k);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      cache[(kVolV + i) * Q + qi] = vp.V[i];
+      cache[(kVolG + i) * Q + qi] = Gm[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cache[(kVolR + i) * Q + qi] = r[i];
+      cache[(kVolK + i) * Q + qi] = k[i];
+      cache[(kVolD + i) * Q + qi] = vp.Dd[i];
+    }
+    cache[kVolOk * Q + qi] = vp.ok ? 1.0 : 0.0;
+  }
   if (M.muscle_k > 0.0) {
     const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
     const double f0 = F[0] * m0 + F[1] * m1 + F[2] * m2;
@@ -565,6 +596,22 @@ __global__ void __launch_bounds__(kBlock) k_grad_params(DevMesh M, const double*
 #pragma unroll
     for (int i = 0; i < 9; ++i) ge += dF[i] * (F[i] - cache[i * Q + qi]);
     ge *= -M.Vq / (1.0 + M.nu);
+    if (M.wv_e) {
+      // through the volume weight: -dw_v/dE <G z, F - D>, D = R V diag(Dd) V^T (= R where det F <= 0)
+      double R[9], V[9], Dd[3], D[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        R[i] = cache[i * Q + qi];
+        V[i] = cache[(kVolV + i) * Q + qi];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Dd[i] = cache[(kVolD + i) * Q + qi];
+      volume_matrix(R, V, Dd, D);
+      double gv = 0.0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) gv += dF[i] * (F[i] - D[i]);
+      ge -= M.dwv_dE * gv;
+    }
     if (M.muscle_k > 0.0) {
       const double m0 = M.fiber[0], m1 = M.fiber[1], m2 = M.fiber[2];
       const double d0 = dF[0] * m0 + dF[1] * m1 + dF[2] * m2;

@@ -22,6 +22,23 @@ namespace {
 
 constexpr int kGroup = 256;  // threads per task
 
+// Accesses to the vectors that tasks exchange (right-hand sides gathered
+// ahead, forward updates, the two sweeps' solutions).  Between launches plain
+// loads and stores suffice; inside the single-launch solve (kCoh) they are
+// device-coherent (agent-scope relaxed atomics), so a task sees what a task
+// on another XCD wrote without cache write-backs or invalidations, and the
+// read-only panels stay cached.
+template <bool kCoh>
+__device__ inline double ldx(const double* p) {
+  if constexpr (kCoh) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool kCoh>
+__device__ inline void stx(double* p, double v) {
+  if constexpr (kCoh) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 __device__ inline double wsum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -29,6 +46,7 @@ __device__ inline double wsum(double v) {
 }
 
 // b~ for the task's supernode into bs[3][nc]: pre-gathered (bt) or gathered here.
+template <bool kCoh = false>
 __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const double* __restrict__ b,
                                  int N, bool pre, int tid, double* bs, int nthreads = kGroup) {
   const int nc = t.ncols;
@@ -36,9 +54,9 @@ __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const do
     const int j = t.col0 + c;
     double v0, v1, v2;
     if (pre) {
-      v0 = S.bt[j];
-      v1 = S.bt[(int64_t)S.nf + j];
-      v2 = S.bt[2 * (int64_t)S.nf + j];
+      v0 = ldx<kCoh>(S.bt + j);
+      v1 = ldx<kCoh>(S.bt + (int64_t)S.nf + j);
+      v2 = ldx<kCoh>(S.bt + 2 * (int64_t)S.nf + j);
     } else {
       const int node = S.perm_pub[j];
       v0 = b[node];
@@ -47,18 +65,19 @@ __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const do
       // four contributions at a time, their loads issued together
       int k = S.cptr[j];
       const int k1 = S.cptr[j + 1];
+      const double* U = S.U;
       for (; k + 3 < k1; k += 4) {
         const int64_t p0 = 3 * (int64_t)S.cidx[k], p1 = 3 * (int64_t)S.cidx[k + 1];
         const int64_t p2 = 3 * (int64_t)S.cidx[k + 2], p3 = 3 * (int64_t)S.cidx[k + 3];
-        v0 += (S.U[p0] + S.U[p1]) + (S.U[p2] + S.U[p3]);
-        v1 += (S.U[p0 + 1] + S.U[p1 + 1]) + (S.U[p2 + 1] + S.U[p3 + 1]);
-        v2 += (S.U[p0 + 2] + S.U[p1 + 2]) + (S.U[p2 + 2] + S.U[p3 + 2]);
+        v0 += (ldx<kCoh>(U + p0) + ldx<kCoh>(U + p1)) + (ldx<kCoh>(U + p2) + ldx<kCoh>(U + p3));
+        v1 += (ldx<kCoh>(U + p0 + 1) + ldx<kCoh>(U + p1 + 1)) + (ldx<kCoh>(U + p2 + 1) + ldx<kCoh>(U + p3 + 1));
+        v2 += (ldx<kCoh>(U + p0 + 2) + ldx<kCoh>(U + p1 + 2)) + (ldx<kCoh>(U + p2 + 2) + ldx<kCoh>(U + p3 + 2));
       }
       for (; k < k1; ++k) {
         const int64_t pos = 3 * (int64_t)S.cidx[k];
-        v0 += S.U[pos];
-        v1 += S.U[pos + 1];
-        v2 += S.U[pos + 2];
+        v0 += ldx<kCoh>(U + pos);
+        v1 += ldx<kCoh>(U + pos + 1);
+        v2 += ldx<kCoh>(U + pos + 2);
       }
     }
     bs[c] = v0;
@@ -67,22 +86,24 @@ __device__ inline void stage_rhs(const DevSolve& S, const SweepTask& t, const do
   }
 }
 
+template <bool kCoh = false>
 __device__ inline void store_fwd_row(const DevSolve& S, const SweepTask& t, int r, double a0, double a1,
                                      double a2) {
   if (r < t.ncols) {
     const int j = t.col0 + r;
-    S.y_int[j] = a0;
-    S.y_int[(int64_t)S.nf + j] = a1;
-    S.y_int[2 * (int64_t)S.nf + j] = a2;
+    stx<kCoh>(S.y_int + j, a0);
+    stx<kCoh>(S.y_int + (int64_t)S.nf + j, a1);
+    stx<kCoh>(S.y_int + 2 * (int64_t)S.nf + j, a2);
   } else {
     const int64_t pos = 3 * (t.u_off + (r - t.ncols));
-    S.U[pos] = a0;
-    S.U[pos + 1] = a1;
-    S.U[pos + 2] = a2;
+    stx<kCoh>(S.U + pos, a0);
+    stx<kCoh>(S.U + pos + 1, a1);
+    stx<kCoh>(S.U + pos + 2, a2);
   }
 }
 
 // v[3][ld] = [y_s; x_R] for the backward task.
+template <bool kCoh = false>
 __device__ inline void stage_solution(const DevSolve& S, const SweepTask& t, int tid, double* vs,
                                       int nthreads = kGroup) {
   const int nc = t.ncols, ld = t.ncols + t.nrows;
@@ -95,20 +116,21 @@ __device__ inline void stage_solution(const DevSolve& S, const SweepTask& t, int
       src = S.x_int;
       j = rows[r - nc];
     }
-    vs[r] = src[j];
-    vs[ld + r] = src[nf + j];
-    vs[2 * ld + r] = src[2 * nf + j];
+    vs[r] = ldx<kCoh>(src + j);
+    vs[ld + r] = ldx<kCoh>(src + nf + j);
+    vs[2 * ld + r] = ldx<kCoh>(src + 2 * nf + j);
   }
 }
 
+template <bool kCoh = false>
 __device__ inline void store_bwd_col(const DevSolve& S, const SweepTask& t, int c, double x0, double x1,
                                      double x2, double* __restrict__ out, int N, double alpha,
                                      int accumulate) {
   const int j = t.col0 + c;
   const int64_t nf = S.nf;
-  S.x_int[j] = x0;
-  S.x_int[nf + j] = x1;
-  S.x_int[2 * nf + j] = x2;
+  stx<kCoh>(S.x_int + j, x0);
+  stx<kCoh>(S.x_int + nf + j, x1);
+  stx<kCoh>(S.x_int + 2 * nf + j, x2);
   const int node = S.perm_pub[j];
   if (accumulate) {
     out[node] += alpha * x0;
@@ -126,17 +148,18 @@ __device__ inline void store_bwd_col(const DevSolve& S, const SweepTask& t, int 
 // four waves (c = wave mod 4) so that each row has four streams of loads in
 // flight; the four partial sums meet in LDS (after the staged right-hand
 // sides) and are added in wave order.
-template <typename T>
+// Every thread of the workgroup calls it (its barriers are the workgroup's);
+// tid is the lane within the task's 256-lane group, bs the group's LDS.
+template <typename T, bool kCoh = false>
 __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                        const double* __restrict__ b, int N, bool active, int tid,
                                        double* bs) {
   __syncthreads();
-  if (active) stage_rhs(S, t, b, N, false, tid, bs);
+  if (active) stage_rhs<kCoh>(S, t, b, N, false, tid, bs);
   __syncthreads();
-  if (!active) return;
-  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  const int nc = active ? t.ncols : 0, ld = active ? t.ncols + t.nrows : 0;
   const int lane = tid & 63, wid = tid >> 6;
-  const bool act = lane < t.count;
+  const bool act = active && lane < t.count;
   const int r = t.first + (act ? lane : 0);
   const T* P = panel + t.panel_off + r;
   const int cend = act ? (r < nc ? r + 1 : nc) : 0;
@@ -156,9 +179,11 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
     a2 += p * bs[2 * nc + c];
   }
   double* red = bs + 3 * nc;   // [4][64][3]
-  red[(wid * 64 + lane) * 3 + 0] = a0;
-  red[(wid * 64 + lane) * 3 + 1] = a1;
-  red[(wid * 64 + lane) * 3 + 2] = a2;
+  if (active) {
+    red[(wid * 64 + lane) * 3 + 0] = a0;
+    red[(wid * 64 + lane) * 3 + 1] = a1;
+    red[(wid * 64 + lane) * 3 + 2] = a2;
+  }
   __syncthreads();
   if (wid == 0 && act) {
     double x[3];
@@ -166,7 +191,7 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
     for (int q = 0; q < 3; ++q)
       x[q] = red[(0 * 64 + lane) * 3 + q] + red[(1 * 64 + lane) * 3 + q] + red[(2 * 64 + lane) * 3 + q] +
              red[(3 * 64 + lane) * 3 + q];
-    store_fwd_row(S, t, r, x[0], x[1], x[2]);
+    store_fwd_row<kCoh>(S, t, r, x[0], x[1], x[2]);
   }
 }
 
@@ -176,12 +201,12 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
 // that every lane reads at least about eight entries of its row.  A task of NT
 // lanes (16 waves) covers one pass of rows, so the block's right-hand sides
 // staged in LDS serve 16 x 64 / LPR rows.
-template <typename T, int LPR, int NT>
+template <typename T, int LPR, int NT, bool kCoh = false>
 __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
                                      const double* __restrict__ b, int N, bool pre, bool active, int tid,
                                      double* bs) {
   __syncthreads();
-  if (active) stage_rhs(S, t, b, N, pre, tid, bs, NT);
+  if (active) stage_rhs<kCoh>(S, t, b, N, pre, tid, bs, NT);
   __syncthreads();
   if (!active) return;
   constexpr int RPW = 64 / LPR;
@@ -216,7 +241,7 @@ __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, cons
       a1 += __shfl_xor(a1, off, 64);
       a2 += __shfl_xor(a2, off, 64);
     }
-    if (act && li == 0) store_fwd_row(S, t, r, a0, a1, a2);
+    if (act && li == 0) store_fwd_row<kCoh>(S, t, r, a0, a1, a2);
   }
 }
 
@@ -225,12 +250,12 @@ __device__ inline void fwd_wide_task(const DevSolve& S, const SweepTask& t, cons
 // (column-major panel, contiguous), then a reduction over the column's lanes;
 // v from LDS (kLds) or from global memory.  LPR is chosen per level so that
 // every lane reads at least about eight entries of its column.
-template <typename T, bool kLds, int LPR, int NT>
+template <typename T, bool kLds, int LPR, int NT, bool kCoh = false>
 __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                      double* __restrict__ out, int N, double alpha, int accumulate,
                                      bool active, int tid, double* vs) {
   __syncthreads();
-  if (kLds && active) stage_solution(S, t, tid, vs, NT);
+  if (kLds && active) stage_solution<kCoh>(S, t, tid, vs, NT);
   __syncthreads();
   if (!active) return;
   constexpr int CPW = 64 / LPR;
@@ -258,9 +283,9 @@ __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, cons
           src = S.x_int;
           j = rows[r - nc];
         }
-        v0 = src[j];
-        v1 = src[nf + j];
-        v2 = src[2 * nf + j];
+        v0 = ldx<kCoh>(src + j);
+        v1 = ldx<kCoh>(src + nf + j);
+        v2 = ldx<kCoh>(src + 2 * nf + j);
       }
       a0 += p * v0;
       a1 += p * v1;
@@ -284,21 +309,21 @@ __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, cons
       a1 += __shfl_xor(a1, off, 64);
       a2 += __shfl_xor(a2, off, 64);
     }
-    if (act && li == 0) store_bwd_col(S, t, col, a0, a1, a2, out, N, alpha, accumulate);
+    if (act && li == 0) store_bwd_col<kCoh>(S, t, col, a0, a1, a2, out, N, alpha, accumulate);
   }
 }
 
 // Backward task of a small supernode (at most 64 columns): lanes over its
 // columns on the row-major copy, rows split four ways, combined through LDS.
 // vs holds 3 ld doubles followed by 4 x 64 x 3 reduction slots.
-template <typename T>
+template <typename T, bool kCoh = false>
 __device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
                                        double* __restrict__ out, int N, double alpha, int accumulate,
                                        bool active, int tid, double* vs) {
   __syncthreads();
-  if (active) stage_solution(S, t, tid, vs);
+  if (active) stage_solution<kCoh>(S, t, tid, vs);
   __syncthreads();
-  const int nc = t.ncols, ld = t.ncols + t.nrows;
+  const int nc = active ? t.ncols : 0, ld = active ? t.ncols + t.nrows : 0;
   double* red = vs + 3 * ld;
   const int c = tid & 63, part = tid >> 6;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -332,7 +357,7 @@ __device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, co
     for (int q = 0; q < 3; ++q)
       x[q] = red[(0 * 64 + c) * 3 + q] + red[(1 * 64 + c) * 3 + q] + red[(2 * 64 + c) * 3 + q] +
              red[(3 * 64 + c) * 3 + q];
-    store_bwd_col(S, t, c, x[0], x[1], x[2], out, N, alpha, accumulate);
+    store_bwd_col<kCoh>(S, t, c, x[0], x[1], x[2], out, N, alpha, accumulate);
   }
 }
 
@@ -415,6 +440,238 @@ __global__ void __launch_bounds__(kBlock) k_sweep_bwd_narrow(DevSolve S, const S
   clock_exit(ck);
 }
 
+// ---------------------------------------------------------------- single-launch solve
+
+constexpr uint32_t kDagSpinLimit = 1u << 22;  // about 4 s of polling per wait: then abort
+
+__device__ inline uint32_t ldu(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t addu(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (one lane) until the entry's dependencies are met; false after an abort
+// (this wait timed out, or another one did).
+__device__ inline bool dag_wait(const DagEntry& e, const DagSn* __restrict__ sni, uint32_t* ctr, int ns) {
+  uint32_t* cdone = ctr + kDagHeader;
+  uint32_t* tdone = cdone + ns;
+  uint32_t* gdone = tdone + ns;
+  uint32_t* bdone = gdone + ns;
+  const int nsub = (e.kind == kDagFwdNarrow || e.kind == kDagBwdNarrow) ? e.n : 1;
+  // unrolled: constant indices keep the entry in registers
+#pragma unroll
+  for (int k = 0; k < kDagSub; ++k) {
+    if (k >= nsub) break;
+    const int s = e.sn[k];
+    const DagSn d = sni[s];
+    const uint32_t* w1 = nullptr;
+    const uint32_t* w2 = nullptr;
+    uint32_t n1 = 0, n2 = 0;
+    if (e.kind == kDagBwdCols || e.kind == kDagBwdNarrow) {
+      if (d.parent >= 0) {
+        w1 = bdone + d.parent;
+        n1 = (uint32_t)sni[d.parent].ntb;
+      } else {
+        w1 = tdone + s;
+        n1 = (uint32_t)d.ntf;
+      }
+    } else {
+      w1 = cdone + s;
+      n1 = (uint32_t)d.nch;
+      if (e.kind != kDagGather) {
+        w2 = gdone + s;
+        n2 = (uint32_t)d.ngt;
+      }
+    }
+    for (uint32_t spin = 0;; ++spin) {
+      if (ldu(w1) >= n1 && (!w2 || ldu(w2) >= n2)) break;
+      if (ldu(ctr + kDagAbort) != 0u || spin >= kDagSpinLimit) {
+        __hip_atomic_store(ctr + kDagAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return true;
+}
+
+// Report the entry's level tasks done (one lane, after the workgroup's
+// stores have completed).
+__device__ inline void dag_signal(const DagEntry& e, const DagSn* __restrict__ sni, uint32_t* ctr, int ns) {
+  uint32_t* cdone = ctr + kDagHeader;
+  uint32_t* tdone = cdone + ns;
+  uint32_t* gdone = tdone + ns;
+  uint32_t* bdone = gdone + ns;
+  if (e.kind == kDagGather) {
+    addu(gdone + e.sn[0], 1u);
+    return;
+  }
+  const bool narrow = e.kind == kDagFwdNarrow || e.kind == kDagBwdNarrow;
+  const int nsub = narrow ? e.n : 1;
+#pragma unroll
+  for (int k = 0; k < kDagSub; ++k) {
+    if (k >= nsub) break;
+    const int s = e.sn[k];
+    if (e.kind == kDagBwdCols || e.kind == kDagBwdNarrow) {
+      addu(bdone + s, 1u);
+    } else {
+      const DagSn d = sni[s];
+      if (addu(tdone + s, 1u) + 1u == (uint32_t)d.ntf && d.parent >= 0) addu(cdone + d.parent, 1u);
+    }
+  }
+}
+
+// The entry kinds of the single-launch solve.
+template <typename T>
+__device__ inline void dag_fwd_narrow(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ fwd,
+                                            const T* __restrict__ panel, const double* __restrict__ b, int N,
+                                            bool ok, int tid, double* lds) {
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 8);   // quarter: uniform per wave
+  const bool act = ok && g < e.n;
+  const SweepTask& tk = fwd[e.first + (g < e.n ? g : 0)];
+  fwd_narrow_task<T, true>(S, tk, panel, b, N, act, tid & 255, lds + g * (int64_t)lds_fwd_narrow(kDagNarrowCols));
+}
+
+template <typename T>
+__device__ inline void dag_fwd_wide(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ fwd,
+                                          const T* __restrict__ panelT, const double* __restrict__ b, int N,
+                                          bool ok, int tid, double* lds) {
+  const SweepTask& tk = fwd[e.first];
+  const bool pre = (e.flags & 1) != 0;
+  if (e.lpr == 64) fwd_wide_task<T, 64, kDagThreads, true>(S, tk, panelT, b, N, pre, ok, tid, lds);
+  else if (e.lpr == 32) fwd_wide_task<T, 32, kDagThreads, true>(S, tk, panelT, b, N, pre, ok, tid, lds);
+  else fwd_wide_task<T, 16, kDagThreads, true>(S, tk, panelT, b, N, pre, ok, tid, lds);
+}
+
+// Pre-gathered right-hand sides of up to 16 columns of one supernode, a wave
+// per column (the arithmetic of k_sweep_gather).
+__device__ inline void dag_gather(const DevSolve& S, const DagEntry& e, const int32_t* __restrict__ gcols,
+                                        const double* __restrict__ b, int N, bool ok, int tid) {
+  const int lane = tid & 63, w = tid >> 6;
+  if (!ok || w >= e.n) return;
+  const int j = gcols[e.first + w];
+  const int k0 = S.cptr[j], k1 = S.cptr[j + 1];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int k = k0 + lane; k < k1; k += 64) {
+    const int64_t pos = 3 * (int64_t)S.cidx[k];
+    v0 += ldx<true>(S.U + pos);
+    v1 += ldx<true>(S.U + pos + 1);
+    v2 += ldx<true>(S.U + pos + 2);
+  }
+  v0 = wsum(v0);
+  v1 = wsum(v1);
+  v2 = wsum(v2);
+  if (lane == 0) {
+    const int node = S.perm_pub[j];
+    stx<true>(S.bt + j, b[node] + v0);
+    stx<true>(S.bt + (int64_t)S.nf + j, b[(int64_t)N + node] + v1);
+    stx<true>(S.bt + 2 * (int64_t)S.nf + j, b[2 * (int64_t)N + node] + v2);
+  }
+}
+
+// The plan stages every backward column task's vector in LDS.
+template <typename T>
+__device__ inline void dag_bwd_cols(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ bwd,
+                                          const T* __restrict__ panel, double* __restrict__ out, int N,
+                                          double alpha, int accumulate, bool ok, int tid, double* lds) {
+  const SweepTask& tk = bwd[e.first];
+  if (e.lpr == 64) bwd_cols_task<T, true, 64, kDagThreads, true>(S, tk, panel, out, N, alpha, accumulate, ok, tid, lds);
+  else if (e.lpr == 32) bwd_cols_task<T, true, 32, kDagThreads, true>(S, tk, panel, out, N, alpha, accumulate, ok, tid, lds);
+  else bwd_cols_task<T, true, 16, kDagThreads, true>(S, tk, panel, out, N, alpha, accumulate, ok, tid, lds);
+}
+
+// Each quarter's LDS region holds the largest narrow backward extent of the plan.
+template <typename T>
+__device__ inline void dag_bwd_narrow(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ bwd,
+                                            const T* __restrict__ panelT, double* __restrict__ out, int N,
+                                            double alpha, int accumulate, bool ok, int tid, double* lds,
+                                            int bwd_region) {
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const bool act = ok && g < e.n;
+  const SweepTask& tk = bwd[e.first + (g < e.n ? g : 0)];
+  bwd_narrow_task<T, true>(S, tk, panelT, out, N, alpha, accumulate, act, tid & 255, lds + g * (int64_t)bwd_region);
+}
+
+// Both sweeps of x = A^{-1} b in one launch: persistent workgroups take queue
+// entries in order (a ticket claimed one entry ahead), wait for the entries
+// they depend on, run them with the level kernels' arithmetic and report
+// them.  Entries only depend on earlier ones and are claimed in order, so the
+// lowest unfinished entry can always run and the queue drains.  Waits are
+// bounded: a timeout raises the abort flag, every later wait gives up, the
+// remaining entries are skipped, and the launch still drains; the last
+// workgroup to leave zeroes the counters for the next launch and counts an
+// aborted launch in a word the host reads.
+template <typename T>
+__global__ void __launch_bounds__(kDagThreads) k_solve_dag(
+    DevSolve S, const DagEntry* __restrict__ q, int nq, const SweepTask* __restrict__ fwd,
+    const SweepTask* __restrict__ bwd, const int32_t* __restrict__ gcols, const DagSn* __restrict__ sni,
+    int ns, uint32_t* ctr, int bwd_region, const T* __restrict__ panel, const T* __restrict__ panelT,
+    const double* __restrict__ b, double* __restrict__ out, int N, double alpha, int accumulate,
+    const IterState* st, ClockArg ck) {
+  if (st && st->done) return;
+  clock_enter(ck);
+  extern __shared__ double lds[];
+  __shared__ int s_next, s_ok, s_last;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_next = (int)addu(ctr + kDagTicket, 1u);
+  __syncthreads();
+  for (;;) {
+    // uniform across the workgroup: the entry is read with scalar loads
+    const int t = __builtin_amdgcn_readfirstlane(s_next);
+    __syncthreads();
+    if (t >= nq) break;
+    const DagEntry e = q[t];
+    if (tid == 0) {
+      s_next = (int)addu(ctr + kDagTicket, 1u);
+      s_ok = dag_wait(e, sni, ctr, ns) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool ok = s_ok != 0;
+    switch (e.kind) {
+      case kDagFwdNarrow:
+        dag_fwd_narrow<T>(S, e, fwd, panel, b, N, ok, tid, lds);
+        break;
+      case kDagFwdWide:
+        dag_fwd_wide<T>(S, e, fwd, panelT, b, N, ok, tid, lds);
+        break;
+      case kDagGather:
+        dag_gather(S, e, gcols, b, N, ok, tid);
+        break;
+      case kDagBwdCols:
+        dag_bwd_cols<T>(S, e, bwd, panel, out, N, alpha, accumulate, ok, tid, lds);
+        break;
+      default:
+        dag_bwd_narrow<T>(S, e, bwd, panelT, out, N, alpha, accumulate, ok, tid, lds, bwd_region);
+        break;
+    }
+    // the entry's stores complete before it is reported
+    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0 && ok) dag_signal(e, sni, ctr, ns);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // this workgroup's counter updates complete before it counts itself out
+    __builtin_amdgcn_s_waitcnt(0);
+    s_last = addu(ctr + kDagExit, 1u) == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    uint32_t* cnt = ctr + kDagHeader;
+    for (int i = tid; i < 4 * ns; i += kDagThreads)
+      __hip_atomic_store(cnt + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      if (ldu(ctr + kDagAbort) != 0u) addu(ctr + kDagAborts, 1u);
+      __hip_atomic_store(ctr + kDagAbort, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctr + kDagTicket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctr + kDagExit, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  clock_exit(ck);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -491,6 +748,20 @@ void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* 
   else
     DPD_LAUNCH(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
                        out, N, alpha, accumulate, st);
+}
+
+void launch_solve_dag(const DevSolve& S, const DevDag& D, hipStream_t s, bool fp32, const double* b, double* out,
+                      int N, double alpha, int accumulate, const IterState* st) {
+  if (fp32)
+    DPD_LAUNCH(k_solve_dag<float>, dim3(D.grid), dim3(kDagThreads), D.lds_bytes, s, S, D.q, D.nq, D.fwd, D.bwd,
+               D.gcols, D.sn, D.ns, D.ctr, D.bwd_region, S.panel32, S.panelT32, b, out, N, alpha, accumulate, st);
+  else
+    DPD_LAUNCH(k_solve_dag<double>, dim3(D.grid), dim3(kDagThreads), D.lds_bytes, s, S, D.q, D.nq, D.fwd, D.bwd,
+               D.gcols, D.sn, D.ns, D.ctr, D.bwd_region, S.panel64, S.panelT64, b, out, N, alpha, accumulate, st);
+}
+
+const void* solve_dag_kernel(bool fp32) {
+  return fp32 ? (const void*)k_solve_dag<float> : (const void*)k_solve_dag<double>;
 }
 
 

@@ -17,7 +17,7 @@ import torch
 
 from . import _lib as L
 
-PHYSICS_KEYS = ("dx", "rho", "nu", "h", "contact_k", "friction_mu", "friction_eps", "muscle_k")
+PHYSICS_KEYS = ("dx", "rho", "nu", "h", "contact_k", "friction_mu", "friction_eps", "muscle_k", "volume_scale")
 
 
 def make_options(physics: Optional[dict] = None, **iteration) -> L.Options:
@@ -285,6 +285,41 @@ class Mesh:
             L.check(self.lib.dpd_hessian_apply(self.handle, _stream(self.device), _ptr(x),
                                                _ptr(act), _ptr(p), _ptr(out)), self.handle)
         return out
+
+    def spectral_radius(self, x, act=None, steps=40, seed=0):
+        """Largest eigenvalue of A^{-1} dA at state x (the contraction factor of
+        the adjoint fixed-point iteration, eq:sp_radius), by Lanczos on the
+        similar operator dA A^{-1} = I - H A^{-1}, which is self-adjoint in the
+        inner product <u, v> = u^T A^{-1} v.  Each step is one solve with the
+        factor (dpd_apply_inverse) and one Hessian product (dpd_hessian_apply);
+        the vectors are reorthogonalized in full.  Returns the Ritz values'
+        maximum (eigenvalues of A^{-1} dA are real and, without negative
+        curvature, in [0, 1))."""
+        self._check_state(x)
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        u = torch.randn((3, self.n_nodes), generator=g, dtype=torch.float64).to(self.device)
+        s = self.apply_inverse(u)
+        u = u * (s.abs() > 0)                   # free rows only
+        s = self.apply_inverse(u)
+        beta = float(torch.sqrt((u * s).sum()))
+        Q, S = [u / beta], [s / beta]
+        alphas, betas = [], []
+        for j in range(steps):
+            w = Q[j] - self.hessian_apply(x, S[j], act)
+            a = float((w * S[j]).sum())
+            alphas.append(a)
+            for qi, si in zip(Q, S):             # full reorthogonalization (A^{-1} inner product)
+                w = w - float((w * si).sum()) * qi
+            sw = self.apply_inverse(w)
+            b = float((w * sw).sum())
+            if b <= 1e-28 or j == steps - 1:
+                break
+            b = b ** 0.5
+            betas.append(b)
+            Q.append(w / b)
+            S.append(sw / b)
+        T = np.diag(alphas) + np.diag(betas[:len(alphas) - 1], 1) + np.diag(betas[:len(alphas) - 1], -1)
+        return float(np.linalg.eigvalsh(T).max())
 
     def rotations(self, x):
         self._check_state(x)

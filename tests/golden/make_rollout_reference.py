@@ -17,7 +17,12 @@ landing; about an hour and a half on 8 host cores, where each Newton step and
 each adjoint solve runs conjugate gradients on the assembled Hessian to
 round-off, ``oracle.linsolve``).
 
-usage: python tests/golden/make_rollout_reference.py c2 [steps]
+Newton stops at |grad g| <= tol |M y / h^2| (default 1e-13).  On the block,
+whose 212 k DoFs put the round-off floor of grad g near 3e-12 of that scale,
+the reference uses tol 1e-11 (position error about 1e-9 m; without it every
+step runs Newton into the floor, about six minutes a step).
+
+usage: python tests/golden/make_rollout_reference.py c2 [steps] [newton_tol]
 """
 import os
 import sys
@@ -62,6 +67,7 @@ def main():
     name = sys.argv[1]
     sc = W.config(name)
     steps = int(sys.argv[2]) if len(sys.argv) > 2 else sc.steps
+    newton_tol = float(sys.argv[3]) if len(sys.argv) > 3 else 1e-13
     if "candidates_ijk" in sc.extra:
         return contact_reference(name, sc, steps)
     m = om.Model(sc)
@@ -72,7 +78,7 @@ def main():
     t0 = time.time()
     for t in range(steps):
         a = None if acts is None else acts[t]
-        xn, info = of.newton_solve(m, m.y_of(x, v), a)
+        xn, info = of.newton_solve(m, m.y_of(x, v), a, tol_rel=newton_tol)
         vn = (xn - x) / m.h
         xs.append(xn)
         vs.append(vn)
@@ -93,7 +99,7 @@ def main():
     out = os.path.join(HERE, f"{name}_rollout_reference.npz")
     extra = {} if g_act is None else {"g_act": g_act}
     np.savez_compressed(out, steps=steps, loss=float(c @ xs[-1]), x_T=xs[-1], g_x0=gx, g_v0=gv,
-                        g_youngs=gE, **extra)
+                        g_youngs=gE, newton_tol=newton_tol, **extra)
     print("wrote", out, f"{time.time() - t0:.0f}s")
 
 

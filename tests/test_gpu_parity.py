@@ -423,3 +423,18 @@ def test_inverted_elements_rotations_and_gradient(precision):
     ref[o.fixed] = 0.0
     print("gradient rel", rel(r, ref), flush=True)
     assert rel(r, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["c1", "robot"])
+def test_spectral_radius_matches_oracle(name):
+    """Lanczos estimate of rho(A^{-1} dA) from the library's solve and Hessian
+    product against the oracle's dense eigenvalues (eq:sp_radius)."""
+    sc = SCENES[name]()
+    g, o = pair(sc)
+    x, v = _perturbed(o, seed=3)
+    act = np.random.default_rng(2).uniform(0, 1, o.E) if o.muscle_k > 0 else None
+    xr = converged_state(o, x, v, act)
+    rho = g.spectral_radius(to_dev(xr, o.N), None if act is None else elem_dev(act), steps=60)
+    ref = oa.spectral_radius(o, xr, act)
+    print(name, "rho", rho, "oracle", ref, flush=True)
+    assert abs(rho - ref) <= 1e-8 * ref

@@ -43,21 +43,26 @@ def sanitized_driver(tmp_path_factory):
     return out
 
 
+def write_input(path, sc, leaf_max, sep_max, rhs=None):
+    with open(path, "wb") as f:
+        np.array([len(sc.cells)], np.int64).tofile(f)
+        np.asarray(sc.cells, np.int32).tofile(f)
+        np.asarray(sc.youngs, np.float64).tofile(f)
+        np.array([len(sc.fixed_nodes)], np.int64).tofile(f)
+        np.asarray(sc.fixed_nodes, np.int32).reshape(-1).tofile(f)
+        ov = [sc.dx, sc.rho, sc.nu, sc.h, *sc.gravity, *sc.origin, sc.contact_k,
+              sc.friction_mu, sc.friction_eps, sc.muscle_k, *sc.fiber]
+        np.asarray(ov, np.float64).tofile(f)
+        np.array([leaf_max, sep_max], np.int32).tofile(f)
+        if rhs is not None:
+            np.array([len(rhs)], np.int64).tofile(f)
+            np.asarray(rhs, np.float64).tofile(f)
+
+
 def run_driver(driver, sc, rhs, leaf_max=64, sep_max=2048):
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
-        with open(fin, "wb") as f:
-            np.array([len(sc.cells)], np.int64).tofile(f)
-            np.asarray(sc.cells, np.int32).tofile(f)
-            np.asarray(sc.youngs, np.float64).tofile(f)
-            np.array([len(sc.fixed_nodes)], np.int64).tofile(f)
-            np.asarray(sc.fixed_nodes, np.int32).reshape(-1).tofile(f)
-            ov = [sc.dx, sc.rho, sc.nu, sc.h, *sc.gravity, *sc.origin, sc.contact_k,
-                  sc.friction_mu, sc.friction_eps, sc.muscle_k, *sc.fiber]
-            np.asarray(ov, np.float64).tofile(f)
-            np.array([leaf_max, sep_max], np.int32).tofile(f)
-            np.array([len(rhs)], np.int64).tofile(f)
-            np.asarray(rhs, np.float64).tofile(f)
+        write_input(fin, sc, leaf_max, sep_max, rhs)
         res = subprocess.run([driver, fin, fout], capture_output=True, text=True)
         assert res.returncode == 0, res.stderr
         raw = open(fout, "rb").read()
@@ -162,3 +167,34 @@ def test_host_code_under_sanitizers(sanitized_driver, name, leaf, sep):
     ref[o.free] = o.solve_A(b[o.free])
     got = out["x"][0].T.reshape(-1)
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def dag_driver(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("dag") / "dag_check")
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-o", out, os.path.join(HERE, "host", "dag_check.cpp"),
+           os.path.join(CSRC, "host_mesh.cpp"), os.path.join(CSRC, "factor.cpp")]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+DAG_CASES = dict(CASES, block_16=lambda: W.dropped_block(16, 8, 8, steps=1),
+                 block_64x32x32=lambda: W.config("c5"))
+
+
+@pytest.mark.parametrize("name", list(DAG_CASES))
+@pytest.mark.parametrize("leaf,sep", [(64, 2048), (8, 16), (512, 2048)])
+def test_single_launch_solve_queue(dag_driver, name, leaf, sep):
+    """The single-launch solve's queue: every level task in exactly one entry
+    in dependency order, and the launch played on the CPU with 1 to 512
+    workgroups and random interleavings drains, with every value read after
+    it was written and written once (dag_check.cpp)."""
+    sc = DAG_CASES[name]()
+    if name == "block_64x32x32" and (leaf, sep) != (64, 2048):
+        pytest.skip("the benchmark block is checked with the plan it uses")
+    with tempfile.TemporaryDirectory() as d:
+        fin = os.path.join(d, "in.bin")
+        write_input(fin, sc, leaf, sep)
+        res = subprocess.run([dag_driver, fin], capture_output=True, text=True)
+    print(res.stdout, res.stderr)
+    assert res.returncode == 0, res.stderr
