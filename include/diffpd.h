@@ -253,6 +253,21 @@ dpd_status dpd_hessian_apply(dpd_mesh* mesh, void* stream, const double* x, cons
                              const double* p, double* out);
 dpd_status dpd_rotations(dpd_mesh* mesh, void* stream, const double* x, double* R_out);
 
+/* dpd_gradient for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, but the element forces, the
+ * reduction partials and the reduction's state live in one library-owned
+ * static device array per GPU (3 MiB plus a few KiB, held until the process
+ * ends) instead of the mesh's workspace.  The call allocates nothing.
+ *   Limit: meshes of at most 16384 elements; larger ones get DPD_EINVAL and
+ *          nothing is launched.
+ *   Sharing: every call on one GPU uses that GPU's array; calls that overlap
+ *          on one GPU (other streams or threads) race.  Stream-ordered calls
+ *          are safe: each call resets the state it needs.
+ *   Arguments as dpd_gradient (device [3][N] x, y, out; act device [E] or NULL). */
+dpd_status dpd_gradient_noalloc(dpd_mesh* mesh, void* stream, const double* x, const double* y,
+                                const double* act, double* out);
+
 /* Global step with a contact set (Sec. Contact, complementarity contact; the
  * low-rank update of Alg. 4): x with x_C = x* and A_{C̄×C̄} x_{C̄} = b_{C̄},
  * from the factor of A.  C is a set of free nodes whose positions are

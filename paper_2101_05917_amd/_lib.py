@@ -102,6 +102,7 @@ PROTOTYPES = {
                                     C.POINTER(Stats)]),
     "dpd_apply_inverse": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "dpd_gradient": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dpd_gradient_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "dpd_hessian_apply": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "dpd_rotations": (C.c_int, [_P, _P, _P, _P]),
     "dpd_contact_prepare": (C.c_int, [_P, _P, _P, C.c_int32]),

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1369,6 +1370,74 @@ dpd_status dpd_hessian_apply(dpd_mesh* m, void* stream, const double* x, const d
   launch_adj_cache(m->dm, s, x, act, m->cache, nullptr);
   launch_elem_hvp(m->dm, s, p, m->cache, m->fe, nullptr);
   launch_node_hvp(m->dm, s, p, m->fe, nullptr, out, nullptr, nullptr, 0, 0, 0);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+namespace {
+
+// Scratch of dpd_gradient_noalloc, one copy per GPU for the life of the
+// process: the iteration state of the residual's grid reduction (its own
+// 256-byte slot), the per-workgroup partial sums of the node pass and the
+// element forces [3][8E].  A mesh of E elements has at most 8E nodes (every
+// node is a voxel corner), so the node pass has at most 8E / kBlock + 1
+// workgroups.
+constexpr int64_t kNoAllocMaxElems = 16384;
+constexpr int64_t kNoAllocStateBytes = 256;
+constexpr int64_t kNoAllocPartialBytes = ((8 * (8 * kNoAllocMaxElems / kBlock + 1) + 255) / 256) * 256;
+constexpr int64_t kNoAllocForceBytes = 24 * 8 * kNoAllocMaxElems;
+constexpr int64_t kNoAllocBytes = kNoAllocStateBytes + kNoAllocPartialBytes + kNoAllocForceBytes;
+static_assert(sizeof(IterState) <= kNoAllocStateBytes, "iteration state slot too small");
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+// In host code this name stands for the array, not its device address: the
+// address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+dpd_status noalloc_scratch(dpd_mesh* m, unsigned char** out) {
+  int dev = -1;
+  HIPCHECK(m, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(m, DPD_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHECK(m, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(m, DPD_EHIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DPD_OK;
+}
+
+}  // namespace
+
+dpd_status dpd_gradient_noalloc(dpd_mesh* m, void* stream, const double* x, const double* y,
+                                const double* act, double* out) {
+  if (!m || !x || !y || !out) return fail(m, DPD_EINVAL, "null argument");
+  if ((int64_t)m->dm.E > kNoAllocMaxElems)
+    return fail(m, DPD_EINVAL, "dpd_gradient_noalloc: the mesh has " + std::to_string(m->dm.E) +
+                                   " elements, more than its scratch holds (" +
+                                   std::to_string(kNoAllocMaxElems) + ")");
+  unsigned char* base = nullptr;
+  dpd_status rc = noalloc_scratch(m, &base);
+  if (rc != DPD_OK) return rc;
+  IterState* st = reinterpret_cast<IterState*>(base);
+  double* partials = reinterpret_cast<double*>(base + kNoAllocStateBytes);
+  double* fe = reinterpret_cast<double*>(base + kNoAllocStateBytes + kNoAllocPartialBytes);
+  hipStream_t s = (hipStream_t)stream;
+  // the reset kernel zeroes the reduction's ticket counter (kept from the last call)
+  launch_reset(s, st, 0.0, 0);
+  launch_elem_forces(m->dm, s, x, act, fe, nullptr, nullptr);
+  launch_node_residual(m->dm, s, x, y, fe, out, st, partials, 0, 0, 1);
   HIPCHECK(m, hipGetLastError());
   return DPD_OK;
 }

@@ -278,6 +278,19 @@ class Mesh:
                                           _ptr(act), _ptr(out)), self.handle)
         return out
 
+    def gradient_noalloc(self, x, y, act=None, out=None):
+        """grad g(x) through dpd_gradient_noalloc (no device allocation in the
+        library; at most 16384 elements).  ``out`` may be given preallocated."""
+        self._check_state(x, y)
+        self._check_elem(act)
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_state(out)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.dpd_gradient_noalloc(self.handle, _stream(self.device), _ptr(x), _ptr(y),
+                                                  _ptr(act), _ptr(out)), self.handle)
+        return out
+
     def hessian_apply(self, x, p, act=None):
         self._check_state(x, p)
         out = torch.empty_like(p)
