@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .forward import pd_step
+from .forward import pd_step, newton_solve
 from .adjoint import backward_step
 from .model import Model
 
@@ -22,12 +22,18 @@ def initial_state(model):
     return model.X.copy(), np.zeros(3 * model.N)
 
 
-def forward_rollout(model, x0, v0, acts=None, steps=None, **pd_kw):
+def forward_rollout(model, x0, v0, acts=None, steps=None, newton=False, **pd_kw):
+    """T steps by Alg. 1 (pd_kw: its iteration options), or with newton=True
+    by Newton's method on g to round-off (the same implicit-Euler states)."""
     T = model.scene.steps if steps is None else steps
     xs, vs, infos = [x0], [v0], []
     for t in range(T):
         a = None if acts is None else acts[t]
-        x, v, info = pd_step(model, xs[-1], vs[-1], a, **pd_kw)
+        if newton:
+            x, info = newton_solve(model, model.y_of(xs[-1], vs[-1]), a)
+            v = (x - xs[-1]) / model.h
+        else:
+            x, v, info = pd_step(model, xs[-1], vs[-1], a, **pd_kw)
         xs.append(x)
         vs.append(v)
         infos.append(info)
@@ -35,10 +41,10 @@ def forward_rollout(model, x0, v0, acts=None, steps=None, **pd_kw):
 
 
 def loss_and_grad(model, x0, v0, acts, cx, cv=None, steps=None, *, solver="direct",
-                  pd_kw=None, adj_kw=None):
+                  pd_kw=None, adj_kw=None, newton=False):
     pd_kw = pd_kw or {}
     adj_kw = adj_kw or {}
-    xs, vs, finfo = forward_rollout(model, x0, v0, acts, steps, **pd_kw)
+    xs, vs, finfo = forward_rollout(model, x0, v0, acts, steps, newton=newton, **pd_kw)
     T = len(xs) - 1
     cv = np.zeros_like(cx) if cv is None else cv
     L = float(cx @ xs[-1] + cv @ vs[-1])
@@ -58,10 +64,10 @@ def loss_and_grad(model, x0, v0, acts, cx, cv=None, steps=None, *, solver="direc
                "xs": xs, "vs": vs, "fwd_info": finfo, "bwd_info": binfo}
 
 
-def rollout_loss(scene, x0, v0, acts, cx, cv=None, youngs=None, steps=None, pd_kw=None):
+def rollout_loss(scene, x0, v0, acts, cx, cv=None, youngs=None, steps=None, pd_kw=None, newton=False):
     """Loss only, building a fresh model (for finite differences in E)."""
     model = Model(scene, youngs=youngs)
-    xs, vs, _ = forward_rollout(model, x0, v0, acts, steps, **(pd_kw or {}))
+    xs, vs, _ = forward_rollout(model, x0, v0, acts, steps, newton=newton, **(pd_kw or {}))
     cv = np.zeros_like(cx) if cv is None else cv
     return float(cx @ xs[-1] + cv @ vs[-1])
 
