@@ -365,8 +365,9 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
     P.fwd_wide[l] = wide ? 1 : 0;
     int32_t max_ld = 0;
     for (int32_t s : by_level[l]) max_ld = std::max(max_ld, S.sn[s].ncols + S.sn[s].nrows);
-    // many small supernodes: one backward task each (LDS holds 3 x ld doubles)
-    const bool narrow_b = !wide && (int64_t)by_level[l].size() >= 256 && max_ld <= 2048;
+    // many small supernodes: one backward task each (LDS holds 3 x ld doubles
+    // and 1024 x 3 partial sums, within 64 KiB)
+    const bool narrow_b = !wide && (int64_t)by_level[l].size() >= 256 && lds_bwd_narrow(max_ld) * 8 <= 65536;
     P.bwd_narrow[l] = narrow_b ? 1 : 0;
     // wide forward: one pass of a task's waves (16 waves x 64 / lanes-per-row
     // rows), so the block's staged right-hand sides serve that many rows;
@@ -386,6 +387,8 @@ void build_plan(const Symbolic& S, LevelPlan& P) {
       P.bwd_rows[l] = std::max(P.bwd_rows[l], ld);
     }
   }
+  P.fwd_off[L] = (int32_t)P.fwd.size();   // the last level's task range is read below
+  P.bwd_off[L] = (int32_t)P.bwd.size();
   // pre-gather on wide levels whose supernodes are split into several tasks
   P.gather_off.assign(L + 1, 0);
   P.gather_cols.clear();
@@ -472,11 +475,11 @@ void build_dag(const Symbolic& S, const LevelPlan& P, int64_t lds_budget_bytes, 
         D.q.push_back(e);
       }
     } else {
-      lds = std::max<int64_t>(lds, kDagSub * lds_fwd_narrow(kDagNarrowCols) * 8);
-      for (int32_t t = t0; t < t1; t += kDagSub) {
-        const int32_t n = std::min(kDagSub, t1 - t);
-        DagEntry e = entry(kDagFwdNarrow, n, t, 0, 0);
-        for (int32_t k = 0; k < n; ++k) e.sn[k] = P.fwd[t + k].sn;
+      // one task per entry on the whole workgroup
+      lds = std::max<int64_t>(lds, lds_fwd_narrow(kDagNarrowCols) * 8);
+      for (int32_t t = t0; t < t1; ++t) {
+        DagEntry e = entry(kDagFwdNarrow, 1, t, 0, 0);
+        e.sn[0] = P.fwd[t].sn;
         D.q.push_back(e);
       }
     }
@@ -486,12 +489,12 @@ void build_dag(const Symbolic& S, const LevelPlan& P, int64_t lds_budget_bytes, 
   for (int32_t l = L - 1; l >= 0; --l) {
     const int32_t t0 = P.bwd_off[l], t1 = P.bwd_off[l + 1];
     if (P.bwd_narrow[l]) {
+      // one task per entry on the whole workgroup
       D.bwd_region = std::max<int32_t>(D.bwd_region, (int32_t)lds_bwd_narrow(P.bwd_rows[l]));
-      lds = std::max<int64_t>(lds, kDagSub * (int64_t)D.bwd_region * 8);
-      for (int32_t t = t0; t < t1; t += kDagSub) {
-        const int32_t n = std::min(kDagSub, t1 - t);
-        DagEntry e = entry(kDagBwdNarrow, n, t, 0, 0);
-        for (int32_t k = 0; k < n; ++k) e.sn[k] = P.bwd[t + k].sn;
+      lds = std::max<int64_t>(lds, (int64_t)D.bwd_region * 8);
+      for (int32_t t = t0; t < t1; ++t) {
+        DagEntry e = entry(kDagBwdNarrow, 1, t, 0, 0);
+        e.sn[0] = P.bwd[t].sn;
         D.q.push_back(e);
       }
     } else {

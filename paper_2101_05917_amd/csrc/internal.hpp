@@ -111,14 +111,12 @@ struct LevelPlan {
 };
 
 // Single-launch solve: both sweeps as one queue of entries that persistent
-// workgroups of 1024 lanes claim in queue order.  An entry runs the level
-// tasks above, with the same arithmetic: one wide forward task or backward
-// column task (all 16 waves), up to four narrow forward tasks or narrow
-// backward tasks of one level (one per 256-lane quarter), or up to sixteen
-// pre-gathered columns of one supernode (a wave each).  Queue order is
-// forward levels ascending (a level's gathers before its row tasks), then
-// backward levels descending, so every entry depends only on entries before
-// it.  An entry waits, per supernode s it serves, for
+// workgroups of 1024 lanes claim in queue order.  An entry runs one level
+// task above with the level kernel's arithmetic (on the whole workgroup), or
+// up to sixteen pre-gathered columns of one supernode (a wave each).  Queue
+// order is forward levels ascending (a level's gathers before its row
+// tasks), then backward levels descending, so every entry depends only on
+// entries before it.  An entry waits, for the supernode s it serves, for
 //   forward row task:  every child of s finished its forward rows, and s's
 //                      gathers done;
 //   forward gather:    every child of s finished its forward rows;
@@ -128,13 +126,13 @@ struct LevelPlan {
 // are (they only start once its children's have), which the last of them
 // reports to the parent's child counter.
 enum DagKind : int32_t { kDagFwdNarrow = 0, kDagFwdWide = 1, kDagGather = 2, kDagBwdCols = 3, kDagBwdNarrow = 4 };
-constexpr int kDagSub = 4;          // narrow level tasks per entry
-constexpr int kDagNarrowCols = 64;  // widest block of a narrow forward level (its LDS region per quarter)
+constexpr int kDagSub = 4;          // supernode slots of an entry (one is used)
+constexpr int kDagNarrowCols = 64;  // widest block of a narrow forward level
 constexpr int kDagGatherCols = 16;  // gathered columns per entry
 constexpr int kDagThreads = 1024;
 struct DagEntry {
   int32_t kind;     // DagKind
-  int32_t n;        // level tasks (narrow kinds: <= kDagSub) or gathered columns (<= kDagGatherCols)
+  int32_t n;        // 1 level task, or gathered columns (<= kDagGatherCols)
   int32_t first;    // first level task (forward or backward task array) or first gather_cols index
   int32_t lpr;      // lanes per panel row (wide forward) or column (backward columns)
   int32_t flags;    // bit 0: right-hand sides pre-gathered; bit 1: backward vector staged in LDS
@@ -161,14 +159,14 @@ struct DagPlan {
   std::vector<DagSn> sn;
   int32_t n_fwd = 0;        // entries of the forward sweep (they come first)
   int64_t lds_bytes = 0;    // dynamic LDS of the launch: the largest entry's need
-  int32_t bwd_region = 0;   // doubles of LDS per quarter of a narrow backward entry
+  int32_t bwd_region = 0;   // doubles of LDS of a narrow backward entry
   bool usable = false;      // every entry's LDS fits the budget (else the level launches are used)
   int64_t counter_words() const { return kDagHeader + 4 * (int64_t)sn.size(); }
 };
 // LDS extents (doubles) of the level task kinds, shared by the level kernels'
 // launchers and the single-launch plan.
 constexpr int64_t lds_fwd_narrow(int cols) { return 3 * (int64_t)cols + 4 * 64 * 3; }
-constexpr int64_t lds_bwd_narrow(int rows) { return 3 * (int64_t)rows + 4 * 64 * 3; }
+constexpr int64_t lds_bwd_narrow(int rows) { return 3 * (int64_t)rows + 1024 * 3; }
 void build_dag(const Symbolic& S, const LevelPlan& P, int64_t lds_budget_bytes, DagPlan& D);
 
 // Geometric nested dissection of the free nodes on the voxel grid, then the

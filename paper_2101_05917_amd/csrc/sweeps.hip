@@ -145,17 +145,17 @@ __device__ inline void store_bwd_col(const DevSolve& S, const SweepTask& t, int 
 
 // Forward task, blocks of at most 64 columns: 64 panel rows, lane per row
 // (column-major panel, coalesced across lanes), the columns split over the
-// four waves (c = wave mod 4) so that each row has four streams of loads in
-// flight; the four partial sums meet in LDS (after the staged right-hand
-// sides) and are added in wave order.
-// Every thread of the workgroup calls it (its barriers are the workgroup's);
-// tid is the lane within the task's 256-lane group, bs the group's LDS.
-template <typename T, bool kCoh = false>
+// NT / 64 waves (c = wave mod NT / 64) so that each row has that many streams
+// of loads in flight; the partial sums meet in LDS (after the staged
+// right-hand sides) and are added in wave order.
+// Every thread of the workgroup calls it (its barriers are the workgroup's).
+template <typename T, int NT, bool kCoh = false>
 __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panel,
                                        const double* __restrict__ b, int N, bool active, int tid,
                                        double* bs) {
+  constexpr int kW = NT / 64;
   __syncthreads();
-  if (active) stage_rhs<kCoh>(S, t, b, N, false, tid, bs);
+  if (active) stage_rhs<kCoh>(S, t, b, N, false, tid, bs, NT);
   __syncthreads();
   const int nc = active ? t.ncols : 0, ld = active ? t.ncols + t.nrows : 0;
   const int lane = tid & 63, wid = tid >> 6;
@@ -165,20 +165,21 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
   const int cend = act ? (r < nc ? r + 1 : nc) : 0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int c = wid;
-  for (; c + 12 < cend; c += 16) {
-    const double p0 = (double)P[(int64_t)c * ld], p1 = (double)P[(int64_t)(c + 4) * ld];
-    const double p2 = (double)P[(int64_t)(c + 8) * ld], p3 = (double)P[(int64_t)(c + 12) * ld];
-    a0 += p0 * bs[c] + p1 * bs[c + 4] + p2 * bs[c + 8] + p3 * bs[c + 12];
-    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + 4] + p2 * bs[nc + c + 8] + p3 * bs[nc + c + 12];
-    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + 4] + p2 * bs[2 * nc + c + 8] + p3 * bs[2 * nc + c + 12];
+  for (; c + 3 * kW < cend; c += 4 * kW) {
+    const double p0 = (double)P[(int64_t)c * ld], p1 = (double)P[(int64_t)(c + kW) * ld];
+    const double p2 = (double)P[(int64_t)(c + 2 * kW) * ld], p3 = (double)P[(int64_t)(c + 3 * kW) * ld];
+    a0 += p0 * bs[c] + p1 * bs[c + kW] + p2 * bs[c + 2 * kW] + p3 * bs[c + 3 * kW];
+    a1 += p0 * bs[nc + c] + p1 * bs[nc + c + kW] + p2 * bs[nc + c + 2 * kW] + p3 * bs[nc + c + 3 * kW];
+    a2 += p0 * bs[2 * nc + c] + p1 * bs[2 * nc + c + kW] + p2 * bs[2 * nc + c + 2 * kW] +
+          p3 * bs[2 * nc + c + 3 * kW];
   }
-  for (; c < cend; c += 4) {
+  for (; c < cend; c += kW) {
     const double p = (double)P[(int64_t)c * ld];
     a0 += p * bs[c];
     a1 += p * bs[nc + c];
     a2 += p * bs[2 * nc + c];
   }
-  double* red = bs + 3 * nc;   // [4][64][3]
+  double* red = bs + 3 * nc;   // [kW][64][3]
   if (active) {
     red[(wid * 64 + lane) * 3 + 0] = a0;
     red[(wid * 64 + lane) * 3 + 1] = a1;
@@ -186,12 +187,14 @@ __device__ inline void fwd_narrow_task(const DevSolve& S, const SweepTask& t, co
   }
   __syncthreads();
   if (wid == 0 && act) {
-    double x[3];
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      x[q] = red[(0 * 64 + lane) * 3 + q] + red[(1 * 64 + lane) * 3 + q] + red[(2 * 64 + lane) * 3 + q] +
-             red[(3 * 64 + lane) * 3 + q];
-    store_fwd_row<kCoh>(S, t, r, x[0], x[1], x[2]);
+    for (int k = 0; k < kW; ++k) {
+      x0 += red[(k * 64 + lane) * 3 + 0];
+      x1 += red[(k * 64 + lane) * 3 + 1];
+      x2 += red[(k * 64 + lane) * 3 + 2];
+    }
+    store_fwd_row<kCoh>(S, t, r, x0, x1, x2);
   }
 }
 
@@ -313,32 +316,39 @@ __device__ inline void bwd_cols_task(const DevSolve& S, const SweepTask& t, cons
   }
 }
 
-// Backward task of a small supernode (at most 64 columns): lanes over its
-// columns on the row-major copy, rows split four ways, combined through LDS.
-// vs holds 3 ld doubles followed by 4 x 64 x 3 reduction slots.
-template <typename T, bool kCoh = false>
+// Backward task of a small supernode (at most 64 columns) on NT lanes: lane
+// t takes column c = t mod W and row class t / W, with W the power of two
+// at least the block's width (lanes are not left idle on narrow blocks), so
+// each of the NT / W row classes walks every (NT / W)-th row of the
+// row-major copy from the diagonal down (coalesced across the columns);
+// the classes' partial sums meet in LDS and are added in class order.
+// vs holds 3 ld doubles followed by NT x 3 reduction slots.
+template <typename T, int NT, bool kCoh = false>
 __device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, const T* __restrict__ panelT,
                                        double* __restrict__ out, int N, double alpha, int accumulate,
                                        bool active, int tid, double* vs) {
   __syncthreads();
-  if (active) stage_solution<kCoh>(S, t, tid, vs);
+  if (active) stage_solution<kCoh>(S, t, tid, vs, NT);
   __syncthreads();
   const int nc = active ? t.ncols : 0, ld = active ? t.ncols + t.nrows : 0;
   double* red = vs + 3 * ld;
-  const int c = tid & 63, part = tid >> 6;
+  const int W = nc <= 8 ? 8 : (nc <= 16 ? 16 : (nc <= 32 ? 32 : 64));
+  const int parts = NT / W;
+  const int c = tid % W, part = tid / W;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (active && c < nc) {
     const T* Pc = panelT + t.panel_off + c;
-    // first row >= c (rows above the diagonal are zeros) in this part's residue class
-    int r = c + ((part - c) & 3);
-    for (; r + 12 < ld; r += 16) {
-      const double p0 = (double)Pc[(int64_t)r * nc], p1 = (double)Pc[(int64_t)(r + 4) * nc];
-      const double p2 = (double)Pc[(int64_t)(r + 8) * nc], p3 = (double)Pc[(int64_t)(r + 12) * nc];
-      a0 += p0 * vs[r] + p1 * vs[r + 4] + p2 * vs[r + 8] + p3 * vs[r + 12];
-      a1 += p0 * vs[ld + r] + p1 * vs[ld + r + 4] + p2 * vs[ld + r + 8] + p3 * vs[ld + r + 12];
-      a2 += p0 * vs[2 * ld + r] + p1 * vs[2 * ld + r + 4] + p2 * vs[2 * ld + r + 8] + p3 * vs[2 * ld + r + 12];
+    // first row >= c (rows above the diagonal are zeros) in this class
+    int r = c + ((part - c) % parts + parts) % parts;
+    for (; r + 3 * parts < ld; r += 4 * parts) {
+      const double p0 = (double)Pc[(int64_t)r * nc], p1 = (double)Pc[(int64_t)(r + parts) * nc];
+      const double p2 = (double)Pc[(int64_t)(r + 2 * parts) * nc], p3 = (double)Pc[(int64_t)(r + 3 * parts) * nc];
+      a0 += p0 * vs[r] + p1 * vs[r + parts] + p2 * vs[r + 2 * parts] + p3 * vs[r + 3 * parts];
+      a1 += p0 * vs[ld + r] + p1 * vs[ld + r + parts] + p2 * vs[ld + r + 2 * parts] + p3 * vs[ld + r + 3 * parts];
+      a2 += p0 * vs[2 * ld + r] + p1 * vs[2 * ld + r + parts] + p2 * vs[2 * ld + r + 2 * parts] +
+            p3 * vs[2 * ld + r + 3 * parts];
     }
-    for (; r < ld; r += 4) {
+    for (; r < ld; r += parts) {
       const double p = (double)Pc[(int64_t)r * nc];
       a0 += p * vs[r];
       a1 += p * vs[ld + r];
@@ -346,18 +356,19 @@ __device__ inline void bwd_narrow_task(const DevSolve& S, const SweepTask& t, co
     }
   }
   if (active) {
-    red[(part * 64 + c) * 3 + 0] = a0;
-    red[(part * 64 + c) * 3 + 1] = a1;
-    red[(part * 64 + c) * 3 + 2] = a2;
+    red[tid * 3 + 0] = a0;
+    red[tid * 3 + 1] = a1;
+    red[tid * 3 + 2] = a2;
   }
   __syncthreads();
   if (active && part == 0 && c < nc) {
-    double x[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      x[q] = red[(0 * 64 + c) * 3 + q] + red[(1 * 64 + c) * 3 + q] + red[(2 * 64 + c) * 3 + q] +
-             red[(3 * 64 + c) * 3 + q];
-    store_bwd_col<kCoh>(S, t, c, x[0], x[1], x[2], out, N, alpha, accumulate);
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    for (int k = 0; k < parts; ++k) {
+      x0 += red[(k * W + c) * 3 + 0];
+      x1 += red[(k * W + c) * 3 + 1];
+      x2 += red[(k * W + c) * 3 + 2];
+    }
+    store_bwd_col<kCoh>(S, t, c, x0, x1, x2, out, N, alpha, accumulate);
   }
 }
 
@@ -370,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fwd(DevSolve S, const SweepTas
   if (st && st->done) return;
   clock_enter(ck);
   extern __shared__ double lds[];
-  fwd_narrow_task<T>(S, tasks[blockIdx.x], panel, b, N, true, threadIdx.x, lds);
+  fwd_narrow_task<T, kBlock>(S, tasks[blockIdx.x], panel, b, N, true, threadIdx.x, lds);
   clock_exit(ck);
 }
 
@@ -429,14 +440,15 @@ __global__ void __launch_bounds__(kWideTaskThreads) k_sweep_bwd(DevSolve S, cons
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sweep_bwd_narrow(DevSolve S, const SweepTask* __restrict__ tasks,
+__global__ void __launch_bounds__(kWideTaskThreads) k_sweep_bwd_narrow(DevSolve S, const SweepTask* __restrict__ tasks,
                                                              const T* __restrict__ panelT,
                                                              double* __restrict__ out, int N, double alpha,
                                                              int accumulate, const IterState* st, ClockArg ck) {
   if (st && st->done) return;
   clock_enter(ck);
   extern __shared__ double lds[];
-  bwd_narrow_task<T>(S, tasks[blockIdx.x], panelT, out, N, alpha, accumulate, true, threadIdx.x, lds);
+  bwd_narrow_task<T, kWideTaskThreads>(S, tasks[blockIdx.x], panelT, out, N, alpha, accumulate, true, threadIdx.x,
+                                       lds);
   clock_exit(ck);
 }
 
@@ -523,14 +535,13 @@ __device__ inline void dag_signal(const DagEntry& e, const DagSn* __restrict__ s
 }
 
 // The entry kinds of the single-launch solve.
+// One narrow forward task on the workgroup's first 256 lanes (the level
+// kernel's arithmetic; the other lanes only take part in the barriers).
 template <typename T>
 __device__ inline void dag_fwd_narrow(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ fwd,
                                             const T* __restrict__ panel, const double* __restrict__ b, int N,
                                             bool ok, int tid, double* lds) {
-  const int g = __builtin_amdgcn_readfirstlane(tid >> 8);   // quarter: uniform per wave
-  const bool act = ok && g < e.n;
-  const SweepTask& tk = fwd[e.first + (g < e.n ? g : 0)];
-  fwd_narrow_task<T, true>(S, tk, panel, b, N, act, tid & 255, lds + g * (int64_t)lds_fwd_narrow(kDagNarrowCols));
+  fwd_narrow_task<T, kBlock, true>(S, fwd[e.first], panel, b, N, ok && tid < kBlock, tid & (kBlock - 1), lds);
 }
 
 template <typename T>
@@ -581,16 +592,14 @@ __device__ inline void dag_bwd_cols(const DevSolve& S, const DagEntry& e, const 
   else bwd_cols_task<T, true, 16, kDagThreads, true>(S, tk, panel, out, N, alpha, accumulate, ok, tid, lds);
 }
 
-// Each quarter's LDS region holds the largest narrow backward extent of the plan.
+// One narrow backward task on the whole workgroup (the level kernel's arithmetic).
 template <typename T>
 __device__ inline void dag_bwd_narrow(const DevSolve& S, const DagEntry& e, const SweepTask* __restrict__ bwd,
                                             const T* __restrict__ panelT, double* __restrict__ out, int N,
                                             double alpha, int accumulate, bool ok, int tid, double* lds,
                                             int bwd_region) {
-  const int g = __builtin_amdgcn_readfirstlane(tid >> 8);
-  const bool act = ok && g < e.n;
-  const SweepTask& tk = bwd[e.first + (g < e.n ? g : 0)];
-  bwd_narrow_task<T, true>(S, tk, panelT, out, N, alpha, accumulate, act, tid & 255, lds + g * (int64_t)bwd_region);
+  (void)bwd_region;
+  bwd_narrow_task<T, kDagThreads, true>(S, bwd[e.first], panelT, out, N, alpha, accumulate, ok, tid, lds);
 }
 
 // Both sweeps of x = A^{-1} b in one launch: persistent workgroups take queue
@@ -676,9 +685,10 @@ __global__ void __launch_bounds__(kDagThreads) k_solve_dag(
 
 // ---------------------------------------------------------------- launchers
 
+
 void launch_sweep_fwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks, int lds_cols,
                       bool fp32, const double* b, int N, const IterState* st) {
-  const size_t lds = ((size_t)3 * lds_cols + 4 * 64 * 3) * sizeof(double);
+  const size_t lds = (size_t)lds_fwd_narrow(lds_cols) * sizeof(double);
   if (fp32)
     DPD_LAUNCH(k_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panel32, b, N, st);
   else
@@ -741,12 +751,12 @@ void launch_sweep_bwd(const DevSolve& S, hipStream_t s, const SweepTask* tasks, 
 void launch_sweep_bwd_narrow(const DevSolve& S, hipStream_t s, const SweepTask* tasks, int ntasks,
                              int lds_rows, bool fp32, double* out, int N, double alpha, int accumulate,
                              const IterState* st) {
-  const size_t lds = ((size_t)3 * lds_rows + 4 * 64 * 3) * sizeof(double);
+  const size_t lds = (size_t)lds_bwd_narrow(lds_rows) * sizeof(double);
   if (fp32)
-    DPD_LAUNCH(k_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT32,
+    DPD_LAUNCH(k_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kWideTaskThreads), lds, s, S, tasks, S.panelT32,
                        out, N, alpha, accumulate, st);
   else
-    DPD_LAUNCH(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kBlock), lds, s, S, tasks, S.panelT64,
+    DPD_LAUNCH(k_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kWideTaskThreads), lds, s, S, tasks, S.panelT64,
                        out, N, alpha, accumulate, st);
 }
 

@@ -263,8 +263,7 @@ int main(int argc, char** argv) {
       ngt[s]++;
       continue;
     }
-    const bool narrow = e.kind == kDagFwdNarrow || e.kind == kDagBwdNarrow;
-    CHECK(narrow ? e.n <= kDagSub : e.n == 1);
+    CHECK(e.n == 1);
     const std::vector<SweepTask>& tasks = bwd ? P.bwd : P.fwd;
     const int lvl = S.sn[tasks[e.first].sn].level;
     CHECK(bwd ? lvl <= last_level : lvl >= last_level);
@@ -300,7 +299,7 @@ int main(int argc, char** argv) {
     CHECK(ntf[s] >= 1 && ntb[s] >= 1);
   }
   CHECK(D.lds_bytes <= budget);
-  if (D.sn.size() && kDagSub * (int64_t)D.bwd_region * 8 > D.lds_bytes) CHECK(D.bwd_region == 0);
+  CHECK((int64_t)D.bwd_region * 8 <= D.lds_bytes);
 
   // the launch played with many interleavings and workgroup counts
   Sim sim(S, P, D);

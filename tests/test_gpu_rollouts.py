@@ -145,3 +145,17 @@ def test_c2_finite_differences_in_log_youngs():
           "error / |dL/dlog E|", abs(fd - an) / np.linalg.norm(glog), flush=True)
     assert worst <= 1e-5
     assert abs(fd - an) <= 1e-5 * np.linalg.norm(glog)
+
+
+def test_c5_prefix_rollout_at_bench_options():
+    """The 64x32x32 block's first 30 steps (free fall, landing on the penalty
+    ground, compression) with bench.py's options, against the oracle's
+    reference of that prefix: gradients within 1e-6."""
+    args = bench.parse(["--config", "c5"])
+    ref = _reference("c5")
+    T = int(ref["steps"])
+    sc, xT, gx, gv, gE, ga = _run("c5", bench.solver_options(args), steps=T)
+    e = _errors(ref, _rest(sc), xT, gx, gv, gE, ga)
+    assert e["x_T"] <= 1e-6
+    for k in ("g_x0", "g_v0", "g_youngs"):
+        assert e[k] <= 1e-6, (k, e[k])
