@@ -10,7 +10,8 @@ Follows Sec. Background and Sec. Differentiable Projective Dynamics:
 * Hessian = A - dA, dA = sum_c w_c G_c^T dp_c/dx                     (eq:matrix_split)
 
 Energies (readings): corotated w_q = 2 mu V_q with mu = E / (2 (1 + nu)) and
-V_q = dx^3 / 8 per Gauss point; muscle w_m = k_m V_q per Gauss point along a
+V_q = dx^3 / 8 per Gauss point (on a tetrahedral scene one point per element
+with V_q = the element's volume, oracle/tetmesh.py); muscle w_m = k_m V_q per Gauss point along a
 fixed fibre, actuation r_e per element; ground penalty (k / 2) min(z, 0)^2 on
 the nodes of minimal rest height; gravity f = M g; explicit friction
 (Sec. Penalty-Based Contact) added to the external force:
@@ -34,6 +35,7 @@ import scipy.sparse.linalg as spla
 from . import discretization as disc
 from . import linsolve
 from . import projections as proj
+from . import tetmesh as tm
 
 
 def _block_diag(blocks: np.ndarray) -> sp.csr_matrix:
@@ -47,25 +49,41 @@ def _block_diag(blocks: np.ndarray) -> sp.csr_matrix:
 class Model:
     def __init__(self, scene, youngs=None):
         self.scene = scene
-        self.mesh = disc.VoxelMesh(scene.cells, scene.dx, scene.origin)
-        mesh = self.mesh
+        self.tets = getattr(scene, "tets", None) is not None
+        if self.tets:
+            # linear tetrahedra: one deformation gradient per element, weight V_e
+            self.mesh = tm.TetMesh(scene.X, scene.tets)
+            mesh = self.mesh
+            self.qpe = 1
+            self.Vq = mesh.volumes.copy()                                 # [Q]
+            self.m = tm.lumped_mass(mesh, scene.rho)
+            self.G = tm.deformation_operator(mesh)
+            if float(scene.muscle_k) > 0.0 or float(getattr(scene, "volume_scale", 0.0)) > 0.0:
+                raise ValueError("tetrahedral scenes: corotated term, ground contact and gravity only")
+        else:
+            self.mesh = disc.VoxelMesh(scene.cells, scene.dx, scene.origin)
+            mesh = self.mesh
+            self.qpe = 8
+            self.dx = float(scene.dx)
+            self.Vq = self.dx ** 3 / 8.0
+            self.m = disc.lumped_mass(mesh, scene.rho)
+            self.G = disc.deformation_operator(mesh)
         N, E = mesh.n_nodes, mesh.n_elements
-        self.N, self.E, self.Q = N, E, 8 * E
+        self.N, self.E, self.Q = N, E, self.qpe * E
         self.h = float(scene.h)
         self.nu = float(scene.nu)
-        self.dx = float(scene.dx)
-        self.Vq = self.dx ** 3 / 8.0
-        self.m = disc.lumped_mass(mesh, scene.rho)
         self.Mdiag = np.repeat(self.m, 3)
         self.X = mesh.X.reshape(-1).copy()
         self.gravity = np.tile(np.asarray(scene.gravity, dtype=np.float64), N)
-        self.G = disc.deformation_operator(mesh)
         self.youngs = np.asarray(scene.youngs if youngs is None else youngs, dtype=np.float64).copy()
         mu = self.youngs / (2.0 * (1.0 + self.nu))
-        self.wq = np.repeat(2.0 * mu * self.Vq, 8)                    # [Q]
+        self.wq = np.repeat(2.0 * mu, self.qpe) * self.Vq              # [Q]
 
-        fixed_nodes = (mesh.node_index(scene.fixed_nodes) if len(scene.fixed_nodes)
-                       else np.zeros(0, np.int64))
+        if self.tets:
+            fixed_nodes = np.asarray(scene.fixed_nodes, dtype=np.int64).reshape(-1)
+        else:
+            fixed_nodes = (mesh.node_index(scene.fixed_nodes) if len(scene.fixed_nodes)
+                           else np.zeros(0, np.int64))
         fixed = np.zeros(3 * N, dtype=bool)
         for n in fixed_nodes:
             fixed[3 * n:3 * n + 3] = True
@@ -75,8 +93,13 @@ class Model:
 
         self.contact_k = float(scene.contact_k)
         if self.contact_k > 0.0:
-            zmin = mesh.node_ijk[:, 2].min()
-            self.contact_nodes = np.nonzero(mesh.node_ijk[:, 2] == zmin)[0]
+            # the nodes of minimal rest height
+            if self.tets:
+                z = mesh.X[:, 2]
+                self.contact_nodes = np.nonzero(z <= z.min() + 1e-12 * max(1.0, abs(z.min())))[0]
+            else:
+                zmin = mesh.node_ijk[:, 2].min()
+                self.contact_nodes = np.nonzero(mesh.node_ijk[:, 2] == zmin)[0]
         else:
             self.contact_nodes = np.zeros(0, np.int64)
         self.Sc = disc.selector(N, self.contact_nodes)
@@ -266,7 +289,7 @@ class Model:
         per_q = np.sum(Gz * self.youngs_force_derivative(x_next), axis=(1, 2)) * self.Vq / (1.0 + self.nu)
         if self.wv is not None:
             per_q = per_q + np.sum(Gz * self.volume_youngs_derivative(x_next), axis=(1, 2)) * self.dwv_dE
-        return -per_q.reshape(self.E, 8).sum(axis=1)
+        return -per_q.reshape(self.E, self.qpe).sum(axis=1)
 
     def fiber_directions(self, x, act=None):
         """dp/dr per muscle qp: f/|f| (the fibre m where f = 0)."""
