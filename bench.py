@@ -87,6 +87,8 @@ def parse(argv=None):
     ap.add_argument("--sweep-launch", type=int, default=None,
                     help="global step through the factor's sweeps: 1 one launch per solve, 0 one per "
                          "tree level (default: the library's)")
+    ap.add_argument("--leaf-nodes", type=int, default=0,
+                    help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--checkpoint-every", type=int, default=0,
@@ -104,6 +106,9 @@ def parse(argv=None):
     ap.add_argument("--rate", type=float, default=1.1,
                     help="c4: Poisson arrival rate, requests/s (inf: all at t = 0)")
     ap.add_argument("--slots", type=int, default=8, help="c4: resident requests")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="c4: 1 = resident requests' conjugate-gradient iterations share launches, "
+                         "0 = each request iterates on its own stream")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="c4: admission budget")
     ap.add_argument("--roofline-kernel", default=None,
                     choices=["solve", "cg_dense", "sweep_fwd", "sweep_fwd_wide", "sweep_bwd", "sweep_bwd_narrow",
@@ -140,6 +145,8 @@ def solver_options(args) -> dict:
                 bwd_max_iter=200000, precision=args.precision, check_every=16, fused_cg=args.fused_cg)
     if args.sweep_launch is not None:
         opts["sweep_launch"] = args.sweep_launch
+    if args.leaf_nodes:
+        opts["leaf_nodes"] = args.leaf_nodes
     return opts
 
 
@@ -440,7 +447,7 @@ def serve_bench(args):
     from paper_2101_05917_amd.serve import Server
     reqs = W.served_requests(n_requests=args.requests, lo=4, hi=args.max_cube, steps=50,
                              rate=args.rate, seed=0)
-    srv = Server(int(args.hbm_budget_gb * (1 << 30)), max_slots=args.slots)
+    srv = Server(int(args.hbm_budget_gb * (1 << 30)), max_slots=args.slots, batched=bool(args.batched))
     solve = dict(fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol, fwd_max_iter=200000,
                  bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol, bwd_max_iter=200000,
                  precision=args.precision, check_every=16)
@@ -457,6 +464,7 @@ def serve_bench(args):
     wall = time.perf_counter() - t0
     res = [srv.poll(t, gradients=False) for t in tickets]
     st = srv.stats()
+    bst = srv.batch_stats()
     srv.close()
     ok = [r for r in res if r.state == "done"]
     lat = np.array([r.latency for r in ok])
@@ -471,12 +479,13 @@ def serve_bench(args):
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} cube-cantilever rollout requests, n ~ U{{4..{args.max_cube}}}"
                                f" cells per side, 50 steps fwd+adjoint each, Poisson rate {args.rate}/s",
-                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb},
+                   "slots": args.slots, "hbm_budget_gb": args.hbm_budget_gb, "batched": bool(args.batched)},
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "dof_steps_per_s": dof_steps / (last - first),
         "completed": len(ok), "failed": len(res) - len(ok),
         "peak_hbm_bytes": st["peak_bytes"], "peak_resident_requests": st["peak_active"],
+        "batch": bst if args.batched else None,
     }
 
 
@@ -674,7 +683,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{scene.name}: {len(scene.cells)} hex, {N} nodes, {3 * N} DoFs, "
+        "config": {"workload": f"{scene.name}: {scene.n_elements} "
+                               f"{'tetrahedra' if getattr(scene, 'tets', None) is not None else 'hex'}, "
+                               f"{N} nodes, {3 * N} DoFs, "
                                f"{T} steps fwd+adjoint, loss dot(N(0,1) seed 0, x_T)",
                    "fwd_solver": args.fwd_solver, "bwd_solver": args.bwd_solver,
                    "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol,

@@ -123,6 +123,11 @@ typedef struct {
                               With it on, solves use the factor's sweeps (the
                               fused dense solver and fused contact loops are
                               not used)                                        */
+  int32_t leaf_nodes;      /* nested-dissection leaf size of the factor: 0 = chosen
+                              by the solve-time estimate among 64, 128, 256, 512
+                              (and all free nodes when they fit one block);
+                              > 0 forces it.  Read at mesh creation.            */
+  int32_t pad_opt;
 } dpd_options;
 
 typedef struct {
@@ -152,6 +157,8 @@ typedef struct {
   int64_t solve_workgroups;/* workgroups of the single-launch solve; 0 when its
                               plan does not fit (solves use the level launches) */
   int64_t solve_entries;   /* entries of its queue (both sweeps)                 */
+  int64_t qp_per_element;  /* 8 (voxels, 2x2x2 Gauss points) or 1 (tetrahedra):
+                              per-quadrature-point arrays hold this x n_elements */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
@@ -175,6 +182,28 @@ dpd_status dpd_default_options(dpd_options* opt);
 dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
                            const int32_t* fixed_ijk, int64_t n_fixed,
                            const dpd_options* opt, dpd_mesh** out);
+
+/* Build a mesh of linear tetrahedra (the paper's tetrahedral scenes, Sec.
+ * Evaluation; the same energies through a constant deformation gradient per
+ * element, F = D_s D_m^{-1}, i.e. G_e a constant 9 x 12 matrix, integrated
+ * with weight V_e = |det D_m| / 6; lumped mass rho V_e / 4 per corner).
+ *   X            host, [n_nodes][3] rest positions (m); public node order
+ *   tets         host, [n_tets][4] corner node ids (either orientation;
+ *                degenerate tetrahedra are rejected)
+ *   youngs       host, [n_tets] Young's moduli in Pa (> 0)
+ *   fixed_nodes  host, [n_fixed] node ids held at rest, or NULL
+ *   opt          host options (copied); dx, origin, muscles and the
+ *                volume-preserving term do not apply (muscle_k and
+ *                volume_scale must be 0); contact_k > 0 puts the ground
+ *                penalty on the nodes of minimal rest height
+ * Orders A_s by nested dissection of the node graph (median splits of the
+ * rest positions, the boundary nodes of one half as separators).  Every step,
+ * solve and gradient call accepts the handle; the fused dense solver, the
+ * complementarity-contact calls and dpd_node_ijk do not apply (the latter two
+ * return DPD_EINVAL).  DPD_EINVAL on bad input. */
+dpd_status dpd_create_tet_mesh(const double* X, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                               const double* youngs, const int32_t* fixed_nodes, int64_t n_fixed,
+                               const dpd_options* opt, dpd_mesh** out);
 
 /* Waits for the device to finish outstanding work, then frees the handle. */
 void dpd_destroy_mesh(dpd_mesh* mesh);
@@ -244,7 +273,8 @@ dpd_status dpd_backward_step(dpd_mesh* mesh, void* stream, const double* x, cons
  *   dpd_gradient:       out = grad g(x) = A x - b(x) for the given y (eq:energy_grad)
  *   dpd_hessian_apply:  out = (A - dA(x)) p (eq:matrix_split)
  *   dpd_rotations:      R_out device [9][8 n_elements]: closest rotation at each
- *                       Gauss point q = 8e + (qx + 2 qy + 4 qz), row-major 3x3 */
+ *                       Gauss point q = 8e + (qx + 2 qy + 4 qz), row-major 3x3
+ *                       (tetrahedra: [9][n_elements], one per element) */
 dpd_status dpd_apply_inverse(dpd_mesh* mesh, void* stream, int32_t precision, const double* b,
                              double* out);
 dpd_status dpd_gradient(dpd_mesh* mesh, void* stream, const double* x, const double* y,
@@ -410,13 +440,32 @@ dpd_status dpd_profile_read(dpd_mesh* mesh, void* stream, dpd_kernel_profile* ou
  * A request is a whole differentiable rollout: build the mesh, factorize A,
  * run T forward steps from rest, evaluate L = c . x_T and run the T adjoint
  * steps back to the initial state.  The server keeps up to max_slots requests
- * resident on the device at once, each with its own factor, states and HIP
- * stream (all streams at default priority), so their kernels overlap on the
- * GPU.  A queued request is admitted as soon as a slot is free and its device
+ * resident on the device at once, each with its own factor and states (the
+ * factorization is done once per request and kept, Sec. Background).  A
+ * queued request is admitted as soon as a slot is free and its device
  * footprint (factor panels, mesh buffers, the T + 1 stored states) fits in
  * what remains of hbm_budget_bytes; requests arriving while others run join
- * as slots and memory free up.  Results are independent of what else runs
- * (every kernel is deterministic), bitwise.
+ * as slots and memory free up.
+ *
+ * batched != 0: the conjugate-gradient solves of all resident requests (the
+ * Newton steps of the forward steps and the adjoint systems of Alg. 2's
+ * quasi-Newton acceleration, Sec. DiffPD) run together: each iteration is
+ * one launch per triangular-sweep level and kernel shape over every
+ * request's tasks, then one launch each for the element Hessian product (the
+ * adjoint local step), the node gather with the inner products, and the
+ * vector update; solves join and leave the batch every few iterations.  The
+ * rest of each step (the forward local step and residual, prologue and
+ * epilogue kernels) runs on the request's own stream.  Requests take the
+ * multi-launch solver (dpd_options.fused_cg is ignored).  Served
+ * requests never capture HIP graphs (dpd_options.use_graphs is ignored): a
+ * capture under way in one worker would make another worker's synchronous
+ * runtime calls fail.
+ * batched == 0: each request iterates on its own HIP stream (default
+ * priority); kernels of different requests overlap on the device.
+ *
+ * Either way a request's results do not depend on what else runs, bitwise:
+ * every kernel is deterministic and a batched slot runs exactly its own
+ * blocks' arithmetic.
  * ------------------------------------------------------------------------ */
 typedef struct dpd_server dpd_server;
 
@@ -445,8 +494,10 @@ typedef struct {
 } dpd_result;
 
 /* max_slots >= 1 requests resident at once within hbm_budget_bytes of device
- * memory, on the device current at creation. */
-dpd_status dpd_server_create(int64_t hbm_budget_bytes, int32_t max_slots, dpd_server** out);
+ * memory, on the device current at creation; batched selects the batch engine
+ * (above). */
+dpd_status dpd_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t batched,
+                             dpd_server** out);
 /* Queue a request (copied); returns its ticket.  Never blocks on the GPU. */
 dpd_status dpd_server_submit(dpd_server* srv, const dpd_request* req, int64_t* ticket);
 /* Result of a ticket; the gradient outputs (host, or NULL) are filled once the
@@ -458,6 +509,17 @@ dpd_status dpd_server_drain(dpd_server* srv);
 /* Peak device bytes admitted at once and peak number of resident requests. */
 dpd_status dpd_server_stats(dpd_server* srv, int64_t* peak_bytes, int32_t* peak_active);
 void dpd_server_destroy(dpd_server* srv);   /* drains first */
+
+typedef struct {
+  int64_t iterations;       /* batched conjugate-gradient iterations launched      */
+  int64_t slot_iterations;  /* their sum over the solves taking part (occupancy)   */
+  int64_t launches;         /* kernel launches made for them                       */
+  int64_t solves;           /* solves completed in the batch engine                */
+  int32_t peak_slots;       /* most solves in one batch                            */
+  int32_t pad;
+} dpd_batch_stats;
+/* Counters of the batch engine since creation (all zero when batched == 0). */
+dpd_status dpd_server_batch_stats(dpd_server* srv, dpd_batch_stats* out);
 
 const char* dpd_status_string(dpd_status s);
 const char* dpd_last_error(const dpd_mesh* mesh);   /* thread-local if mesh is NULL */

@@ -34,7 +34,7 @@ class Options(C.Structure):
         ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
         ("precision", C.c_int32), ("check_every", C.c_int32), ("use_graphs", C.c_int32),
         ("fused_cg", C.c_int32), ("contact_fused", C.c_int32), ("sweep_launch", C.c_int32),
-        ("volume_scale", C.c_double),
+        ("volume_scale", C.c_double), ("leaf_nodes", C.c_int32), ("pad_opt", C.c_int32),
     ]
 
 
@@ -53,7 +53,7 @@ class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
         "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds",
-        "solve_workgroups", "solve_entries")]
+        "solve_workgroups", "solve_entries", "qp_per_element")]
 
 
 class KernelProfile(C.Structure):
@@ -75,6 +75,11 @@ class Result(C.Structure):
                 ("fwd_iters", C.c_int64), ("bwd_iters", C.c_int64)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("slot_iterations", C.c_int64), ("launches", C.c_int64),
+                ("solves", C.c_int64), ("peak_slots", C.c_int32), ("pad", C.c_int32)]
+
+
 DPD_PROF = {"off": 0, "sweep_fwd": 1, "sweep_bwd": 2, "elem_hvp": 3, "elem_forces": 4, "solve": 5,
             "sweep_fwd_wide": 6, "sweep_bwd_narrow": 7, "cg_dense": 8, "contact_update": 9,
             "contact_descend": 10, "contact_dense": 11, "contact_fused": 12,
@@ -89,6 +94,8 @@ PROTOTYPES = {
     "dpd_default_options": (C.c_int, [C.POINTER(Options)]),
     "dpd_create_mesh": (C.c_int, [_I32, C.c_int64, _D, _I32, C.c_int64, C.POINTER(Options),
                                   C.POINTER(_P)]),
+    "dpd_create_tet_mesh": (C.c_int, [_D, C.c_int64, _I32, C.c_int64, _D, _I32, C.c_int64,
+                                      C.POINTER(Options), C.POINTER(_P)]),
     "dpd_destroy_mesh": (None, [_P]),
     "dpd_get_info": (C.c_int, [_P, C.POINTER(MeshInfo)]),
     "dpd_node_ijk": (C.c_int, [_P, _I32]),
@@ -112,7 +119,8 @@ PROTOTYPES = {
                                             C.POINTER(Stats)]),
     "dpd_profile_start": (C.c_int, [_P, C.c_int32]),
     "dpd_profile_read": (C.c_int, [_P, _P, C.POINTER(KernelProfile)]),
-    "dpd_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(_P)]),
+    "dpd_server_create": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "dpd_server_batch_stats": (C.c_int, [_P, C.POINTER(BatchStats)]),
     "dpd_server_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_int64)]),
     "dpd_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(Result), _P, _P, _P]),
     "dpd_server_drain": (C.c_int, [_P]),

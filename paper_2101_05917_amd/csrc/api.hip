@@ -13,8 +13,10 @@
 #include <vector>
 
 #include "../../include/diffpd.h"
+#include "batch.hpp"
 #include "contact.hpp"
 #include "device.hpp"
+#include "handle.hpp"
 #include "internal.hpp"
 
 using namespace dpd;
@@ -26,7 +28,6 @@ thread_local std::string g_last_error;
 constexpr double kLaunchSeconds = 4e-6;      // measured time of a small dependent launch
 constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of the sweeps
 constexpr int32_t kSepMax = 2048;
-constexpr int64_t kLdsBudget = 60 * 1024;
 constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
 constexpr int kHoldPeriodsAround = 40;  // about 130 us of s_sleep ahead of a timed multi-launch solve
 constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
@@ -34,91 +35,6 @@ constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before 
 constexpr int kNewtonMore = 2;   // ... and per later check
 
 }  // namespace
-
-struct TimedLaunch {
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  double bytes, flops;
-  int st_idx, k;
-  bool strict;
-};
-
-struct dpd_mesh {
-  dpd_options opt{};
-  HostMesh hm;
-  Csr A;
-  Symbolic S;
-  LevelPlan plan;
-  DevMesh dm{};
-  DevSolve ds{};
-  bool factored = false;
-  bool have_fp32 = false;
-  std::string err;
-  int64_t device_bytes = 0;
-  std::vector<void*> allocs;
-  // device buffers
-  SweepTask* d_fwd = nullptr;
-  SweepTask* d_bwd = nullptr;
-  int32_t* d_gather = nullptr;
-  DagPlan dag;                                    // single-launch solve (both sweeps)
-  DevDag dd{};
-  bool dag_ok = false;                            // plan uploaded and fits the launch limits
-  uint32_t* h_dag_aborts = nullptr;               // pinned mirror of its abort count
-  double solve_bytes = 0.0, solve_flops = 0.0;   // algorithmic work of one A^{-1} b
-  int32_t leaf_max = 0;                           // chosen dissection leaf size
-  int64_t method_factor_nnz = 0;                  // packed entries of a sparse factor (64-node leaves)
-  uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
-  hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
-  // fused dense conjugate gradients (meshes with few free nodes)
-  DenseCG dcg{};
-  int dense_blocks = 0;                           // workgroups of its launch; 0: not available
-  bool dense_alloc = false;
-  double* ainv64 = nullptr;
-  float* ainv32 = nullptr;
-  bool capturing = false;
-  hipStream_t capture_stream = nullptr;
-  double* w_e = nullptr;
-  double* wv_e = nullptr;                         // volume-preserving weights (null: term off)
-  double* panel64 = nullptr;
-  float* panel32 = nullptr;
-  double* panelT64 = nullptr;
-  float* panelT32 = nullptr;
-  double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
-  double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
-  double* xbar_w = nullptr;   // H s of the conjugate-gradient iteration
-  IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
-  IterState* h_st = nullptr;   // pinned host mirror [2]
-  // kernel timing (dpd_profile_start / dpd_profile_read)
-  int32_t prof_class = DPD_PROF_OFF;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-  std::vector<TimedLaunch> ev_pending;
-  int64_t prof_launches = 0, prof_seen = 0, prof_iters = 0;
-  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0, prof_event_ms = 0.0;
-  double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
-  ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
-  LaunchClock* prof_clock = nullptr;  // device-side timing of the single-kernel classes
-  // global step with a contact set (dpd_contact_prepare / dpd_contact_solve)
-  int32_t contact_n = 0;               // candidates (0: not prepared for the current factor)
-  int32_t contact_cap = 0;             // candidates the buffers below hold
-  int32_t* contact_cand = nullptr;     // [cap] public ids
-  double* contact_B1 = nullptr;        // [cap][N] columns of A_s^{-1}, fixed rows 0
-  int32_t* contact_set = nullptr;      // [kContactMaxSet] active set of the cached inverse
-  double* contact_Sinv = nullptr;      // [c][c] inverse of (A^{-1})_{C×C} for that set
-  double* contact_lam = nullptr;       // [3][kContactMaxSet]
-  int32_t* contact_status = nullptr;   // non-positive pivot flag
-  std::vector<int32_t> contact_cached; // the set whose inverse is cached (empty: none)
-  // time step with contact (dpd_contact_forward_step / dpd_contact_backward_step)
-  double* contact_tgt = nullptr;       // [3][cap] target of each candidate
-  int32_t* contact_kind = nullptr;     // [cap] 0: free, 1: ray target, 2: static target
-  uint8_t* contact_left = nullptr;     // [cap] left the set once in this step
-  uint8_t* contact_mask = nullptr;     // [N] Dirichlet nodes and the set's nodes
-  // with a dense A^{-1}: (A_{C̄×C̄})^{-1} held dense for the current set
-  double* contact_W = nullptr;         // [n][n] internal order, rows and columns of C zero
-  double* contact_T = nullptr;         // [n][kContactMaxSet] work
-  uint8_t* contact_inc = nullptr;      // [n] internal rows in C
-  bool contact_red_ok = false;
-  uint32_t* contact_bar = nullptr;     // [kContactBarWords] grid barrier of the fused contact loop
-  std::vector<int32_t> contact_red;    // the set W belongs to
-};
 
 namespace {
 
@@ -267,7 +183,7 @@ void solve(dpd_mesh* m, hipStream_t s, bool fp32, const double* b, double* out, 
   }
   for (int32_t l = L - 1; l >= 0; --l) {
     const int n = P.bwd_off[l + 1] - P.bwd_off[l];
-    const bool lds = (int64_t)3 * P.bwd_rows[l] * (int64_t)sizeof(double) <= kLdsBudget;
+    const bool lds = (int64_t)3 * P.bwd_rows[l] * (int64_t)sizeof(double) <= kSweepLdsBudget;
     if (!n) continue;
     ProfScope ps(m, s, P.bwd_narrow[l] ? DPD_PROF_SWEEP_BWD_NARROW : DPD_PROF_SWEEP_BWD,
                  P.bwd_bytes[l] * (fp32 ? 0.5 : 1.0), P.bwd_flops[l], st_idx, k);
@@ -323,12 +239,15 @@ void fill_devmesh(dpd_mesh* m) {
   d.friction_mu = o.friction_mu;
   d.friction_eps = o.friction_eps;
   d.muscle_k = o.muscle_k;
+  d.corners = m->hm.corners;
 }
 
+// 2 mu_e V_q per Gauss point (tetrahedra: 2 mu_e V_e per element).
 std::vector<double> corotated_weights(const HostMesh& hm, const dpd_options& o) {
   std::vector<double> w(hm.n_elems);
   const double Vq = o.dx * o.dx * o.dx / 8.0;
-  for (int64_t e = 0; e < hm.n_elems; ++e) w[e] = 2.0 * hm.youngs[e] / (2.0 * (1.0 + o.nu)) * Vq;
+  for (int64_t e = 0; e < hm.n_elems; ++e)
+    w[e] = 2.0 * hm.youngs[e] / (2.0 * (1.0 + o.nu)) * (hm.corners == 4 ? hm.vol[e] : Vq);
   return w;
 }
 
@@ -399,7 +318,7 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
   m->dense_blocks = 0;
   // the fused kernels' element phase carries the corotated, muscle and ground
   // terms only: with the volume-preserving term solves use the sweeps
-  if (!m->opt.fused_cg || m->opt.volume_scale > 0.0 || n < 1 || n > kSepMax) return DPD_OK;
+  if (!m->opt.fused_cg || m->opt.volume_scale > 0.0 || m->hm.corners != 8 || n < 1 || n > kSepMax) return DPD_OK;
   int G = 0;
   if (!m->dense_alloc) {
     int dev = 0, cus = 0;
@@ -566,6 +485,16 @@ dpd_status dpd_create_mesh(const int32_t* cells_ijk, int64_t n_cells, const doub
   return st;
 }
 
+dpd_status dpd_create_tet_mesh(const double* X, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                               const double* youngs, const int32_t* fixed_nodes, int64_t n_fixed,
+                               const dpd_options* opt, dpd_mesh** out) {
+  dpd_status st = dpd::create_tet_host(X, n_nodes, tets, n_tets, youngs, fixed_nodes, n_fixed, opt, out);
+  if (st != DPD_OK) return st;
+  st = dpd::upload_device(*out);
+  if (st != DPD_OK) *out = nullptr;
+  return st;
+}
+
 }  // extern "C"
 
 namespace dpd {
@@ -587,6 +516,36 @@ dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* 
     delete m;
     return fail(nullptr, DPD_EINVAL, e);
   }
+  plan_host(m);
+  *out = m;
+  return DPD_OK;
+}
+
+dpd_status create_tet_host(const double* X, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                           const double* youngs, const int32_t* fixed_nodes, int64_t n_fixed, const dpd_options* opt,
+                           dpd_mesh** out) {
+  if (!out) return fail(nullptr, DPD_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!opt) return fail(nullptr, DPD_EINVAL, "null options");
+  if (n_fixed > 0 && !fixed_nodes) return fail(nullptr, DPD_EINVAL, "null fixed-node list");
+  dpd_mesh* m = new (std::nothrow) dpd_mesh();
+  if (!m) return fail(nullptr, DPD_ENOMEM, "host allocation failed");
+  m->opt = *opt;
+  if (m->opt.check_every < 1) m->opt.check_every = 1;
+  m->opt.fused_cg = 0;   // the fused dense solver's element phase is the voxel one
+  std::string e = build_tet_mesh(X, n_nodes, tets, n_tets, youngs, fixed_nodes, n_fixed, m->opt, m->hm);
+  if (!e.empty()) {
+    delete m;
+    return fail(nullptr, DPD_EINVAL, e);
+  }
+  plan_host(m);
+  *out = m;
+  return DPD_OK;
+}
+
+// A_s, its ordering (leaf size by the solve-time estimate) and symbolic
+// analysis, the sweep plan and the device mesh description.
+void plan_host(dpd_mesh* m) {
   assemble_As(m->hm, m->opt, m->A);
   // Partition: among candidate leaf sizes pick the one with the smallest
   // estimated solve time, launches x kLaunchSeconds + factor bytes / kSweepBandwidth.
@@ -595,6 +554,7 @@ dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* 
   double best = 1e300;
   std::vector<int32_t> leaves = {64, 128, 256, 512};
   if (m->hm.n_free <= kSepMax) leaves.push_back((int32_t)m->hm.n_free);
+  if (m->opt.leaf_nodes > 0) leaves = {m->opt.leaf_nodes};
   for (int32_t leaf : leaves) {
     Symbolic S;
     analyse(m->hm, m->A, leaf, kSepMax, S);
@@ -620,8 +580,6 @@ dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* 
     m->method_factor_nnz = S.packed_nnz;
   }
   fill_devmesh(m);
-  *out = m;
-  return DPD_OK;
 }
 
 // Device bytes the handle will own once uploaded and factorized.
@@ -651,9 +609,11 @@ int64_t footprint_bytes(const dpd_mesh* m) {
 dpd_status upload_device(dpd_mesh* m) {
   const HostMesh& hm = m->hm;
   const int64_t N = hm.n_nodes, E = hm.n_elems, nf = hm.n_free;
-  std::vector<int32_t> conn_soa(8 * E);
+  const int K = hm.corners;
+  const int64_t Q = K == 4 ? E : 8 * E;   // quadrature points
+  std::vector<int32_t> conn_soa(K * E);
   for (int64_t el = 0; el < E; ++el)
-    for (int a = 0; a < 8; ++a) conn_soa[a * E + el] = hm.conn[8 * el + a];
+    for (int a = 0; a < K; ++a) conn_soa[a * E + el] = hm.conn[K * el + a];
   std::vector<int32_t> perm_pub(nf);
   for (int64_t i = 0; i < nf; ++i) perm_pub[i] = hm.free_nodes[m->S.perm[i]];
   dpd_status st = DPD_OK;
@@ -668,7 +628,20 @@ dpd_status upload_device(dpd_mesh* m) {
   UP(X, hm.X);
   UP(mass, hm.mass);
   UP(conn, conn_soa);
-  UP(inc, hm.node_inc);
+  inc = nullptr;
+  double *dminv = nullptr, *vol = nullptr;
+  int32_t *inc_ptr = nullptr, *inc_csr = nullptr;
+  if (K == 4) {
+    std::vector<double> dminv_soa(9 * E);
+    for (int64_t el = 0; el < E; ++el)
+      for (int i = 0; i < 9; ++i) dminv_soa[i * E + el] = hm.dminv[9 * el + i];
+    UP(dminv, dminv_soa);
+    UP(vol, hm.vol);
+    UP(inc_ptr, hm.inc_ptr);
+    UP(inc_csr, hm.inc);
+  } else {
+    UP(inc, hm.node_inc);
+  }
   UP(fixed, hm.fixed);
   UP(contact, hm.is_contact);
   UP(m->w_e, corotated_weights(hm, m->opt));
@@ -682,7 +655,7 @@ dpd_status upload_device(dpd_mesh* m) {
   UP(m->d_gather, m->plan.gather_cols);
   // single-launch solve: its queue, supernode table and counters (zeroed here,
   // then by the last workgroup of each launch); off when its LDS does not fit
-  build_dag(m->S, m->plan, kLdsBudget, m->dag);
+  build_dag(m->S, m->plan, kSweepLdsBudget, m->dag);
   if (m->dag.usable && !m->dag.q.empty()) {
     DagEntry* q = nullptr;
     DagSn* sn = nullptr;
@@ -733,6 +706,10 @@ dpd_status upload_device(dpd_mesh* m) {
   d.mass = mass;
   d.conn = conn;
   d.node_inc = inc;
+  d.dminv = dminv;
+  d.vol = vol;
+  d.inc_ptr = inc_ptr;
+  d.inc = inc_csr;
   d.fixed = fixed;
   d.contact = contact;
   d.w_e = m->w_e;
@@ -753,11 +730,11 @@ dpd_status upload_device(dpd_mesh* m) {
   AL(ds.x_int, 3 * nf);
   AL(ds.U, 3 * m->S.u_size);
   AL(ds.bt, 3 * nf);
-  AL(m->fe, 3 * 8 * E);
+  AL(m->fe, 3 * K * E);
   AL(m->r, 3 * N);
   AL(m->y, 3 * N);
   AL(m->partials, 2 * (std::max<int64_t>(N, 8 * E) / kBlock + 16));
-  AL(m->cache, (int64_t)cache_rows(m->opt) * 8 * E);
+  AL(m->cache, (int64_t)cache_rows(m->opt) * Q);
   AL(m->z, 3 * N);
   AL(m->p, 3 * N);
   AL(m->q, 3 * N);
@@ -830,6 +807,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   if (!m || !info) return fail(nullptr, DPD_EINVAL, "null argument");
   info->n_nodes = m->hm.n_nodes;
   info->n_elements = m->hm.n_elems;
+  info->qp_per_element = m->hm.corners == 4 ? 1 : 8;
   info->n_free = m->hm.n_free;
   info->n_fixed = m->hm.n_nodes - m->hm.n_free;
   info->n_contact = (int64_t)m->hm.contact.size();
@@ -848,6 +826,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
 
 dpd_status dpd_node_ijk(const dpd_mesh* m, int32_t* ijk) {
   if (!m || !ijk) return fail(nullptr, DPD_EINVAL, "null argument");
+  if (m->hm.corners != 8) return fail(nullptr, DPD_EINVAL, "a tetrahedral mesh has no grid coordinates");
   std::memcpy(ijk, m->hm.node_ijk.data(), m->hm.node_ijk.size() * sizeof(int32_t));
   return DPD_OK;
 }
@@ -1130,13 +1109,30 @@ hipGraphExec_t cg_graph(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32) {
   if (!m->capture_stream &&
       hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking) != hipSuccess)
     return nullptr;
+  // A capture that fails (or is invalidated) leaves the iterations to direct
+  // launches from then on; its error is cleared so that it does not surface
+  // as the failure of a later call.
+  if (m->graphs_failed) return nullptr;
   hipGraph_t g = nullptr;
-  if (hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  if (hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    m->graphs_failed = true;
+    (void)hipGetLastError();
+    return nullptr;
+  }
   m->capturing = true;
   for (int i = 0; i < kGraphIters; ++i) cg_iteration(m, m->capture_stream, st, fp32, 0);
   m->capturing = false;
-  if (hipStreamEndCapture(m->capture_stream, &g) != hipSuccess || !g) return nullptr;
-  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+  if (hipStreamEndCapture(m->capture_stream, &g) != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    m->graphs_failed = true;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    ex = nullptr;
+    m->graphs_failed = true;
+    (void)hipGetLastError();
+  }
   (void)hipGraphDestroy(g);
   return ex;
 }
@@ -1217,6 +1213,14 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
+  if (m->batcher) {
+    // the iterations run in the batch engine's launches, together with other
+    // handles' solves; the set-up above must be complete first
+    HIPCHECK(m, hipStreamSynchronize(s));
+    if ((rc = m->batcher->solve(m, st, fp32, max_it)) != DPD_OK)
+      return fail(m, rc, "batched conjugate-gradient iterations failed");
+    return DPD_OK;
+  }
   const int chunk = std::max(kGraphIters, check_every / kGraphIters * kGraphIters);
   // Iterations are enqueued in chunks between host checks; every kernel of an
   // iteration enqueued past convergence exits at once, but still costs a
@@ -1454,6 +1458,7 @@ dpd_status dpd_contact_prepare(dpd_mesh* m, void* stream, const int32_t* nodes_h
   dpd_status rc = check_ready(m);
   if (rc != DPD_OK) return rc;
   if (!nodes_host || n_cand < 1) return fail(m, DPD_EINVAL, "need at least one candidate node");
+  if (m->hm.corners != 8) return fail(m, DPD_EINVAL, "complementarity contact is available on voxel meshes");
   const int N = (int)m->hm.n_nodes;
   std::vector<int32_t> cand(nodes_host, nodes_host + n_cand);
   std::vector<uint8_t> seen(N, 0);

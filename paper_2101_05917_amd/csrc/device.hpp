@@ -64,6 +64,13 @@ struct DevMesh {
   const double* wv_e;         // [E] volume-preserving weight per Gauss point, or null (term off)
   double dwv_dE;              // d(wv_e)/dE_e
   uint8_t* cmask;             // [N] ground contact active at the linearisation point
+  // linear tetrahedra (corners = 4; voxels: 8): conn is [4][E]; the node
+  // gather runs over the compressed incidence instead of node_inc
+  int32_t corners;
+  const double* dminv;        // [9][E] D_m^{-1} (row-major entries), tetrahedra
+  const double* vol;          // [E] element volumes, tetrahedra
+  const int32_t* inc_ptr;     // [N + 1] incidence ranges, tetrahedra (else null)
+  const int32_t* inc;         // [4E] entries 4e + a
 };
 
 constexpr int kElemsPerBlock = kBlock / 8;
@@ -106,6 +113,64 @@ struct DenseCG {
 };
 
 void launch_hold(hipStream_t s, int periods);
+
+// Element kernels of linear tetrahedra (one lane per element; the element
+// launchers above dispatch to them when DevMesh::corners == 4).
+void launch_tet_forces(const DevMesh& M, hipStream_t s, const double* x, double* fe, double* R_out, IterState* st);
+void launch_tet_adj_cache(const DevMesh& M, hipStream_t s, const double* x, double* cache, IterState* st,
+                          const IterState* gate);
+void launch_tet_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache, double* fe,
+                    const IterState* st);
+void launch_tet_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z, const double* cache,
+                            double* g_youngs, const IterState* gate);
+
+// Dynamic LDS a backward column task may use to stage [y_s; x_R] (3 doubles per
+// panel row); longer panels read the vector from memory.
+constexpr int64_t kSweepLdsBudget = 60 * 1024;
+
+// One handle's conjugate-gradient solve inside a batched iteration (several
+// handles' iterations in the same launches): its mesh, vectors and state, and
+// where its blocks start in the batched element and node launches.
+struct BatchCgSlot {
+  DevMesh M;
+  const double* cache;        // per-Gauss-point adjoint cache at the linearisation point
+  double* fe;                 // [3][8E] element corner forces
+  double* sv;                 // [3][N] s = A^{-1} r
+  double* r;                  // [3][N] residual
+  double* w;                  // [3][N] H s
+  double *z, *p, *q;          // [3][N] solution and direction vectors
+  IterState* st;              // the solve's scalars and stopping state
+  double* partials;           // per-block partial sums of its reductions
+  int32_t elem_block0, node_block0, node_blocks, pad;
+};
+
+// One handle's triangular solve inside a batched sweep launch: its factor and
+// the right-hand side / solution vectors (public order, [3][N]).  Tasks of a
+// batched launch name their slot in SweepTask::pad0 and, on pre-gathered wide
+// forward levels, carry pad1 = 1.
+struct BatchSolveSlot {
+  DevSolve S;
+  const double* b;
+  double* out;
+  const IterState* st;
+  int32_t N, pad;
+};
+
+// Batched launches.  Forward and backward level launches take the tasks of one
+// kernel shape (kind, lanes per row or column, LDS staging) from any number of
+// slots; gather entries are (slot, internal column) pairs.
+void launch_batch_sweep_fwd(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                            int lds_cols, bool fp32);
+void launch_batch_sweep_fwd_wide(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                                 int lpr, int lds_cols, bool fp32);
+void launch_batch_sweep_gather(const BatchSolveSlot* slots, hipStream_t s, const int2* cols, int ncols);
+void launch_batch_sweep_bwd(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                            int lpr, bool use_lds, int lds_rows, bool fp32);
+void launch_batch_sweep_bwd_narrow(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks,
+                                   int ntasks, int lds_rows, bool fp32);
+// element Hessian product, node gather + inner products, vector update
+void launch_batch_cg_iteration_tail(const BatchCgSlot* slots, int nslots, int elem_blocks, int node_blocks,
+                                    hipStream_t s);
 
 // Device side of the single-launch solve (DagPlan uploaded).
 struct DevDag {

@@ -33,21 +33,23 @@ __device__ inline double block_sum(double v, double* ws) {
 
 // Grid-wide sum with a deterministic order: each block publishes its partial,
 // the last block to arrive sums the partials in block order.  Returns true in
-// thread 0 of the last block, with the total in *total.
-__device__ inline bool grid_sum(double v, double* partials, IterState* st, double* total) {
+// thread 0 of the last block, with the total in *total.  bid / nblk: this
+// block's index among the nblk blocks taking part (a batched launch runs
+// several such grids side by side).
+__device__ inline bool grid_sum_at(double v, double* partials, IterState* st, double* total, int bid, int nblk) {
   __shared__ double ws[kBlock / 64];
   __shared__ int last;
   const double bs = block_sum(v, ws);
   if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&partials[bid], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t t =
         __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
+    last = (t == (uint32_t)nblk - 1);
   }
   __syncthreads();
   if (!last) return false;
   double s = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x)
     s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // keep the order fixed: strided partial sums, then the block tree
   s = block_sum(s, ws);
@@ -56,6 +58,10 @@ __device__ inline bool grid_sum(double v, double* partials, IterState* st, doubl
     *total = s;
   }
   return threadIdx.x == 0;
+}
+
+__device__ inline bool grid_sum(double v, double* partials, IterState* st, double* total) {
+  return grid_sum_at(v, partials, st, total, blockIdx.x, gridDim.x);
 }
 
 // dN_a/dX_j at Gauss point q of a cubic voxel: (1/8) s_aj prod_{k != j}(1 +- g) * 2/dx,
@@ -719,6 +725,17 @@ __device__ inline void hvp_stress(const DevMesh& M, ElemTile& T, int le, int q, 
 // Sum the element forces of every node (fixed order) and form the residual.
 __device__ inline void node_force(const DevMesh& M, const double* __restrict__ fe, int n,
                                   double& f0, double& f1, double& f2) {
+  if (M.inc_ptr) {   // tetrahedra: [3][4E] corner forces, compressed incidence in (e, a) order
+    const int64_t E4 = 4 * (int64_t)M.E;
+    f0 = f1 = f2 = 0.0;
+    for (int k = M.inc_ptr[n]; k < M.inc_ptr[n + 1]; ++k) {
+      const int p = M.inc[k];
+      f0 += fe[p];
+      f1 += fe[E4 + p];
+      f2 += fe[2 * E4 + p];
+    }
+    return;
+  }
   const int64_t E8 = 8 * (int64_t)M.E;
   f0 = f1 = f2 = 0.0;
 #pragma unroll

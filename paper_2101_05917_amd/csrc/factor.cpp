@@ -6,7 +6,9 @@
 // (Sec. Background, Projective Dynamics; Sec. Differentiable Projective
 // Dynamics).  Here:
 //   * nested dissection on the voxel grid (a grid plane separates the two
-//     halves because hex neighbours differ by at most one in each index);
+//     halves because hex neighbours differ by at most one in each index), or,
+//     on tetrahedral meshes, by median splits of the rest positions with the
+//     lower half's boundary nodes as separators;
 //   * one supernode per dissection leaf and per separator (split into chunks
 //     of at most sep_max columns), ordered children before parents;
 //   * multifrontal Cholesky with dense fronts;
@@ -31,11 +33,23 @@ namespace {
 
 struct NdCtx {
   const HostMesh* m;
+  const Csr* A;                              // adjacency of the free nodes (tetrahedra)
   int32_t leaf_max, sep_max;
   std::vector<std::vector<int32_t>> groups;  // emitted supernode node lists (free indices)
+  std::vector<int8_t> side;                  // bisection side of each free node, -1 outside
 };
 
 void sort_lex(const HostMesh& m, std::vector<int32_t>& v) {
+  if (m.node_ijk.empty()) {   // tetrahedra: by rest position (z, y, x), then id
+    const int64_t N = m.n_nodes;
+    std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+      const int64_t na = m.free_nodes[a], nb = m.free_nodes[b];
+      for (int c = 2; c >= 0; --c)
+        if (m.X[c * N + na] != m.X[c * N + nb]) return m.X[c * N + na] < m.X[c * N + nb];
+      return a < b;
+    });
+    return;
+  }
   std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
     const int32_t* pa = &m.node_ijk[3 * (int64_t)m.free_nodes[a]];
     const int32_t* pb = &m.node_ijk[3 * (int64_t)m.free_nodes[b]];
@@ -89,14 +103,67 @@ void nd(NdCtx& c, std::vector<int32_t>& nodes) {
   if (!sep.empty()) emit(c, sep, c.sep_max);
 }
 
+// Nested dissection of an unstructured mesh (tetrahedra): split the nodes at
+// the median of their rest positions along the longest extent; the nodes of
+// the lower half with a neighbour (an off-diagonal entry of A_s) in the upper
+// half form the separator, which leaves the two remaining parts unconnected.
+void nd_graph(NdCtx& c, std::vector<int32_t>& nodes) {
+  if (nodes.empty()) return;
+  const HostMesh& m = *c.m;
+  if ((int64_t)nodes.size() <= c.leaf_max) {
+    emit(c, nodes, c.sep_max);
+    return;
+  }
+  const int64_t N = m.n_nodes;
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) lo[k] = hi[k] = m.X[k * N + m.free_nodes[nodes[0]]];
+  for (int32_t f : nodes)
+    for (int k = 0; k < 3; ++k) {
+      const double v = m.X[k * N + m.free_nodes[f]];
+      lo[k] = std::min(lo[k], v);
+      hi[k] = std::max(hi[k], v);
+    }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+  const size_t half = nodes.size() / 2;
+  std::nth_element(nodes.begin(), nodes.begin() + half, nodes.end(), [&](int32_t a, int32_t b) {
+    const double va = m.X[ax * N + m.free_nodes[a]], vb = m.X[ax * N + m.free_nodes[b]];
+    return va != vb ? va < vb : a < b;
+  });
+  for (size_t i = 0; i < nodes.size(); ++i) c.side[nodes[i]] = i < half ? 0 : 1;
+  std::vector<int32_t> left, right, sep;
+  const Csr& A = *c.A;
+  for (size_t i = 0; i < nodes.size(); ++i) {
+    const int32_t f = nodes[i];
+    if (i >= half) {
+      right.push_back(f);
+      continue;
+    }
+    bool cut = false;
+    for (int64_t k = A.ptr[f]; k < A.ptr[f + 1] && !cut; ++k) cut = c.side[A.col[k]] == 1;
+    (cut ? sep : left).push_back(f);
+  }
+  for (int32_t f : nodes) c.side[f] = -1;
+  std::vector<int32_t>().swap(nodes);
+  nd_graph(c, left);
+  nd_graph(c, right);
+  if (!sep.empty()) emit(c, sep, c.sep_max);
+}
+
 }  // namespace
 
 void analyse(const HostMesh& m, const Csr& A, int32_t leaf_max, int32_t sep_max, Symbolic& S) {
   const int32_t n = A.n;
-  NdCtx c{&m, leaf_max, sep_max, {}};
+  NdCtx c{&m, &A, leaf_max, sep_max, {}, {}};
   std::vector<int32_t> all(n);
   std::iota(all.begin(), all.end(), 0);
-  nd(c, all);
+  if (m.corners == 4) {
+    c.side.assign(n, -1);
+    nd_graph(c, all);
+  } else {
+    nd(c, all);
+  }
 
   S.n = n;
   S.perm.clear();

@@ -1,0 +1,110 @@
+// The library's mesh handle (the opaque dpd_mesh of the C ABI): host mesh,
+// factor, plan, device buffers and per-handle solver state.  Shared by the
+// step drivers (api.hip) and the batched conjugate-gradient engine
+// (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/diffpd.h"
+#include "contact.hpp"
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace dpd {
+class Batcher;
+}
+
+struct TimedLaunch {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  double bytes, flops;
+  int st_idx, k;
+  bool strict;
+};
+
+struct dpd_mesh {
+  dpd_options opt{};
+  dpd::HostMesh hm;
+  dpd::Csr A;
+  dpd::Symbolic S;
+  dpd::LevelPlan plan;
+  dpd::DevMesh dm{};
+  dpd::DevSolve ds{};
+  bool factored = false;
+  bool have_fp32 = false;
+  std::string err;
+  int64_t device_bytes = 0;
+  std::vector<void*> allocs;
+  // device buffers
+  dpd::SweepTask* d_fwd = nullptr;
+  dpd::SweepTask* d_bwd = nullptr;
+  int32_t* d_gather = nullptr;
+  dpd::DagPlan dag;                                    // single-launch solve (both sweeps)
+  dpd::DevDag dd{};
+  bool dag_ok = false;                            // plan uploaded and fits the launch limits
+  uint32_t* h_dag_aborts = nullptr;               // pinned mirror of its abort count
+  double solve_bytes = 0.0, solve_flops = 0.0;   // algorithmic work of one A^{-1} b
+  int32_t leaf_max = 0;                           // chosen dissection leaf size
+  int64_t method_factor_nnz = 0;                  // packed entries of a sparse factor (64-node leaves)
+  uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
+  hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
+  bool graphs_failed = false;                     // a capture failed: direct launches only
+  // fused dense conjugate gradients (meshes with few free nodes)
+  dpd::DenseCG dcg{};
+  int dense_blocks = 0;                           // workgroups of its launch; 0: not available
+  bool dense_alloc = false;
+  double* ainv64 = nullptr;
+  float* ainv32 = nullptr;
+  bool capturing = false;
+  hipStream_t capture_stream = nullptr;
+  double* w_e = nullptr;
+  double* wv_e = nullptr;                         // volume-preserving weights (null: term off)
+  double* panel64 = nullptr;
+  float* panel32 = nullptr;
+  double* panelT64 = nullptr;
+  float* panelT32 = nullptr;
+  double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
+  double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
+  double* xbar_w = nullptr;   // H s of the conjugate-gradient iteration
+  dpd::IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
+  dpd::IterState* h_st = nullptr;   // pinned host mirror [2]
+  // kernel timing (dpd_profile_start / dpd_profile_read)
+  int32_t prof_class = DPD_PROF_OFF;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  std::vector<TimedLaunch> ev_pending;
+  int64_t prof_launches = 0, prof_seen = 0, prof_iters = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0, prof_event_ms = 0.0;
+  double clock_khz = 1.0e5;   // device wall-clock rate (hipDeviceAttributeWallClockRate)
+  dpd::ProfAcc* prof_acc = nullptr;  // fused solver's device-side timing (class DPD_PROF_CG_DENSE)
+  dpd::LaunchClock* prof_clock = nullptr;  // device-side timing of the single-kernel classes
+  // global step with a contact set (dpd_contact_prepare / dpd_contact_solve)
+  int32_t contact_n = 0;               // candidates (0: not prepared for the current factor)
+  int32_t contact_cap = 0;             // candidates the buffers below hold
+  int32_t* contact_cand = nullptr;     // [cap] public ids
+  double* contact_B1 = nullptr;        // [cap][N] columns of A_s^{-1}, fixed rows 0
+  int32_t* contact_set = nullptr;      // [kContactMaxSet] active set of the cached inverse
+  double* contact_Sinv = nullptr;      // [c][c] inverse of (A^{-1})_{C×C} for that set
+  double* contact_lam = nullptr;       // [3][kContactMaxSet]
+  int32_t* contact_status = nullptr;   // non-positive pivot flag
+  std::vector<int32_t> contact_cached; // the set whose inverse is cached (empty: none)
+  // time step with contact (dpd_contact_forward_step / dpd_contact_backward_step)
+  double* contact_tgt = nullptr;       // [3][cap] target of each candidate
+  int32_t* contact_kind = nullptr;     // [cap] 0: free, 1: ray target, 2: static target
+  uint8_t* contact_left = nullptr;     // [cap] left the set once in this step
+  uint8_t* contact_mask = nullptr;     // [N] Dirichlet nodes and the set's nodes
+  // with a dense A^{-1}: (A_{C̄×C̄})^{-1} held dense for the current set
+  double* contact_W = nullptr;         // [n][n] internal order, rows and columns of C zero
+  double* contact_T = nullptr;         // [n][kContactMaxSet] work
+  uint8_t* contact_inc = nullptr;      // [n] internal rows in C
+  bool contact_red_ok = false;
+  uint32_t* contact_bar = nullptr;     // [kContactBarWords] grid barrier of the fused contact loop
+  std::vector<int32_t> contact_red;    // the set W belongs to
+  // conjugate-gradient solves of the multi-launch path go through this engine
+  // (several handles' iterations in the same launches) when set; not owned
+  dpd::Batcher* batcher = nullptr;
+};
+

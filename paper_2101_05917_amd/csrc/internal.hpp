@@ -14,8 +14,8 @@ namespace dpd {
 // Physical gradients are these times 2/dx.
 void reference_gradients(double Bxi[8][3][8]);
 
-// Voxel mesh on the host: public node numbering, connectivity, mass, the
-// Dirichlet and contact sets, and the scalar node matrix A_s (free nodes).
+// Mesh on the host (voxels or tetrahedra): public node numbering,
+// connectivity, mass, the Dirichlet and contact sets.
 struct HostMesh {
   int64_t n_nodes = 0, n_elems = 0, n_free = 0;
   std::vector<int32_t> node_ijk;     // [N][3]
@@ -31,6 +31,14 @@ struct HostMesh {
   // node -> incident (element, local corner) pairs, 8e + a, -1 padded: [8][N]
   std::vector<int32_t> node_inc;
   int32_t grid_min[3] = {0, 0, 0}, grid_max[3] = {0, 0, 0};
+  // element kind: 8 (trilinear voxels, 8 Gauss points) or 4 (linear
+  // tetrahedra, one constant deformation gradient); for tetrahedra conn is
+  // [E][4], node_ijk is empty and these hold the element geometry and a
+  // compressed node -> (element, corner) incidence
+  int32_t corners = 8;
+  std::vector<double> dminv;         // [E][9] D_m^{-1} row-major (tetrahedra)
+  std::vector<double> vol;           // [E] element volumes (tetrahedra)
+  std::vector<int32_t> inc_ptr, inc; // [N + 1], [4E]: entries 4e + a in (e, a) order
 };
 
 // Sparse symmetric matrix over free nodes in free-index order, full pattern
@@ -46,6 +54,11 @@ std::string build_mesh(const int32_t* cells, int64_t n_cells, const double* youn
                        const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options& o,
                        HostMesh& m);
 void assemble_As(const HostMesh& m, const dpd_options& o, Csr& A);
+// Linear tetrahedra: positions X [N][3] (host), corners tets [E][4], moduli
+// [E], fixed node ids; the corotated term, gravity and the ground penalty only.
+std::string build_tet_mesh(const double* X, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                           const double* youngs, const int32_t* fixed_nodes, int64_t n_fixed, const dpd_options& o,
+                           HostMesh& m);
 
 // Supernode of the nested-dissection factor.  Its panel is an ld x ncols
 // column-major block, ld = ncols + nrows: rows [0, ncols) hold the inverse of
@@ -197,6 +210,10 @@ std::vector<T> transpose_panels(const Symbolic& S, const std::vector<double>& pa
 dpd_status create_host(const int32_t* cells_ijk, int64_t n_cells, const double* youngs,
                        const int32_t* fixed_ijk, int64_t n_fixed, const dpd_options* opt,
                        dpd_mesh** out);
+dpd_status create_tet_host(const double* X, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                           const double* youngs, const int32_t* fixed_nodes, int64_t n_fixed, const dpd_options* opt,
+                           dpd_mesh** out);
+void plan_host(dpd_mesh* m);
 int64_t footprint_bytes(const dpd_mesh* m);
 dpd_status upload_device(dpd_mesh* m);
 void destroy_synced(dpd_mesh* m);

@@ -301,15 +301,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_cache(DevMesh M, const double* _
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
-                                                     const double* __restrict__ cache,
-                                                     double* __restrict__ fe, const IterState* st,
-                                                     ClockArg ck) {
-  if (st && st->done) return;
-  clock_enter(ck);
+// dA p per element (the adjoint local step): corner forces of block bid's
+// elements into fe.
+__device__ inline void elem_hvp_block(const DevMesh& M, const double* __restrict__ p,
+                                      const double* __restrict__ cache, double* __restrict__ fe, int bid) {
   __shared__ ElemTile T;
   const int le = threadIdx.x >> 3, q = threadIdx.x & 7;
-  const int e = blockIdx.x * kElemsPerBlock + le;
+  const int e = bid * kElemsPerBlock + le;
   const bool valid = e < M.E;
   const GradTable G = grad_table(M.dx);
   gather_nodes(M, p, T, le, q, e, valid);
@@ -317,6 +315,15 @@ __global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __
   if (valid) hvp_stress(M, T, le, q, e, G, cache);
   __syncthreads();
   element_forces_out(M, T, le, q, e, valid, G, fe);
+}
+
+__global__ void __launch_bounds__(kBlock) k_elem_hvp(DevMesh M, const double* __restrict__ p,
+                                                     const double* __restrict__ cache,
+                                                     double* __restrict__ fe, const IterState* st,
+                                                     ClockArg ck) {
+  if (st && st->done) return;
+  clock_enter(ck);
+  elem_hvp_block(M, p, cache, fe, blockIdx.x);
   clock_exit(ck);
 }
 
@@ -391,22 +398,22 @@ __global__ void __launch_bounds__(kBlock) k_dot(DevMesh M, const double* __restr
 
 // Two grid sums at once (same fixed order as grid_sum).
 __device__ inline bool grid_sum2(double a, double b, double* partials, IterState* st, double* ta,
-                                 double* tb) {
+                                 double* tb, int bid, int nblk) {
   __shared__ double ws[kBlock / 64];
   __shared__ int last;
   const double ba = block_sum(a, ws);
   const double bb = block_sum(b, ws);
   if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[2 * blockIdx.x], ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[2 * blockIdx.x + 1], bb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&partials[2 * bid], ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&partials[2 * bid + 1], bb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t t =
         __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
+    last = (t == (uint32_t)nblk - 1);
   }
   __syncthreads();
   if (!last) return false;
   double sa = 0.0, sb = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
     sa += __hip_atomic_load(&partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sb += __hip_atomic_load(&partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -425,14 +432,12 @@ __device__ inline bool grid_sum2(double a, double b, double* partials, IterState
 //   gamma = r.s, delta = w.s, beta = gamma/gamma_old,
 //   alpha = gamma / (delta - beta gamma / alpha_old)   (= gamma / p^T H p),
 //   p = s + beta p, q = w + beta q, z += alpha p, r -= alpha q.
-// This kernel forms w = H s (node part) and both inner products.
-__global__ void __launch_bounds__(kBlock) k_cg_hvp_dots(DevMesh M, const double* __restrict__ sv,
-                                                        const double* __restrict__ fe,
-                                                        const double* __restrict__ r,
-                                                        double* __restrict__ w, IterState* st,
-                                                        double* partials) {
-  if (st->done) return;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// This step forms w = H s (node part) and both inner products; block bid of nblk.
+__device__ inline void cg_hvp_dots_block(const DevMesh& M, const double* __restrict__ sv,
+                                         const double* __restrict__ fe, const double* __restrict__ r,
+                                         double* __restrict__ w, IterState* st, double* partials, int bid,
+                                         int nblk) {
+  const int n = bid * blockDim.x + threadIdx.x;
   double rs = 0.0, ws_ = 0.0;
   if (n < M.N) {
     const int64_t N = M.N;
@@ -453,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp_dots(DevMesh M, const double*
     w[2 * N + n] = o2;
   }
   double gamma, delta;
-  if (grid_sum2(rs, ws_, partials, st, &gamma, &delta)) {
+  if (grid_sum2(rs, ws_, partials, st, &gamma, &delta, bid, nblk)) {
     const bool first = st->iter == 0;
     const double beta = first ? 0.0 : gamma / st->rs;
     const double den = first ? delta : delta - beta * gamma / st->alpha;
@@ -468,15 +473,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp_dots(DevMesh M, const double*
   }
 }
 
-// p = s + beta p; q = w + beta q; z += alpha p; r -= alpha q; |r|^2 -> stopping test.
-__global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restrict__ z, double* __restrict__ r,
-                                                    double* __restrict__ p, double* __restrict__ q,
-                                                    const double* __restrict__ sv,
-                                                    const double* __restrict__ w, IterState* st,
-                                                    double* partials) {
+__global__ void __launch_bounds__(kBlock) k_cg_hvp_dots(DevMesh M, const double* __restrict__ sv,
+                                                        const double* __restrict__ fe,
+                                                        const double* __restrict__ r,
+                                                        double* __restrict__ w, IterState* st,
+                                                        double* partials) {
   if (st->done) return;
+  cg_hvp_dots_block(M, sv, fe, r, w, st, partials, blockIdx.x, gridDim.x);
+}
+
+// p = s + beta p; q = w + beta q; z += alpha p; r -= alpha q; |r|^2 -> stopping test.
+__device__ inline void cg_step_block(const DevMesh& M, double* __restrict__ z, double* __restrict__ r,
+                                     double* __restrict__ p, double* __restrict__ q,
+                                     const double* __restrict__ sv, const double* __restrict__ w, IterState* st,
+                                     double* partials, int bid, int nblk) {
   const double alpha = st->alpha, beta = st->beta;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = bid * blockDim.x + threadIdx.x;
   double acc = 0.0;
   if (n < M.N && !M.fixed[n]) {
     const int64_t N = M.N;
@@ -494,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restric
     }
   }
   double tot;
-  if (grid_sum(acc, partials, st, &tot)) {
+  if (grid_sum_at(acc, partials, st, &tot, bid, nblk)) {
     st->rsq = tot;
     st->iter += 1;
     if (!isfinite(tot)) {
@@ -506,6 +518,53 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restric
     }
     if (st->iter >= st->max_iter) st->done = 1;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restrict__ z, double* __restrict__ r,
+                                                    double* __restrict__ p, double* __restrict__ q,
+                                                    const double* __restrict__ sv,
+                                                    const double* __restrict__ w, IterState* st,
+                                                    double* partials) {
+  if (st->done) return;
+  cg_step_block(M, z, r, p, q, sv, w, st, partials, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------- batched iterations
+//
+// The same three steps over several handles' conjugate-gradient solves in one
+// launch: the blocks of slot j are [block0, block0 + nblk) of the grid, and
+// each block runs exactly the arithmetic of the single-handle kernel's block
+// (bid = its index within the slot), so a slot's results do not depend on the
+// other slots of the batch.  A slot whose solve has finished does nothing.
+
+__device__ inline int batch_slot(const BatchCgSlot* __restrict__ slots, int nslots, int elem) {
+  const int b = blockIdx.x;
+  int j = 0;
+  for (int i = 1; i < nslots; ++i)
+    if ((elem ? slots[i].elem_block0 : slots[i].node_block0) <= b) j = i;
+  return j;
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_elem_hvp(const BatchCgSlot* __restrict__ slots, int nslots) {
+  const int j = batch_slot(slots, nslots, 1);
+  const BatchCgSlot& S = slots[j];
+  if (S.st->done) return;
+  elem_hvp_block(S.M, S.sv, S.cache, S.fe, blockIdx.x - S.elem_block0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_cg_hvp_dots(const BatchCgSlot* __restrict__ slots, int nslots) {
+  const int j = batch_slot(slots, nslots, 0);
+  const BatchCgSlot& S = slots[j];
+  if (S.st->done) return;
+  cg_hvp_dots_block(S.M, S.sv, S.fe, S.r, S.w, S.st, S.partials, blockIdx.x - S.node_block0, S.node_blocks);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_cg_step(const BatchCgSlot* __restrict__ slots, int nslots) {
+  const int j = batch_slot(slots, nslots, 0);
+  const BatchCgSlot& S = slots[j];
+  if (S.st->done) return;
+  cg_step_block(S.M, S.z, S.r, S.p, S.q, S.sv, S.w, S.st, S.partials, blockIdx.x - S.node_block0,
+                S.node_blocks);
 }
 
 // Backward epilogue: dL/dy = M z/h^2 (eq:chain_rule); through
@@ -685,6 +744,7 @@ void launch_prologue(const DevMesh& M, hipStream_t s, const double* x, const dou
 
 void launch_elem_forces(const DevMesh& M, hipStream_t s, const double* x, const double* act,
                         double* fe, double* R_out, IterState* st) {
+  if (M.corners == 4) return launch_tet_forces(M, s, x, fe, R_out, st);
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
   DPD_LAUNCH(k_elem_forces, dim3(nb), dim3(kBlock), 0, s, M, x, act, fe, R_out, st);
 }
@@ -711,6 +771,7 @@ void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v) {
 
 void launch_adj_cache(const DevMesh& M, hipStream_t s, const double* x, const double* act,
                       double* cache, IterState* st, const IterState* gate) {
+  if (M.corners == 4) return launch_tet_adj_cache(M, s, x, cache, st, gate);
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
   hipLaunchKernelGGL(k_adj_cache, dim3(nb + blocks_for(M.N)), dim3(kBlock), 0, s, M, x, act, cache, st, gate,
                      nb);
@@ -780,6 +841,7 @@ void launch_newton_update(hipStream_t s, int64_t n3, IterState* outer, const Ite
 
 void launch_elem_hvp(const DevMesh& M, hipStream_t s, const double* p, const double* cache,
                      double* fe, const IterState* st) {
+  if (M.corners == 4) return launch_tet_hvp(M, s, p, cache, fe, st);
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
   DPD_LAUNCH(k_elem_hvp, dim3(nb), dim3(kBlock), 0, s, M, p, cache, fe, st);
 }
@@ -810,6 +872,13 @@ void launch_cg_step(const DevMesh& M, hipStream_t s, double* z, double* r, doubl
 }
 
 
+void launch_batch_cg_iteration_tail(const BatchCgSlot* slots, int nslots, int elem_blocks, int node_blocks,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_elem_hvp, dim3(elem_blocks), dim3(kBlock), 0, s, slots, nslots);
+  hipLaunchKernelGGL(k_batch_cg_hvp_dots, dim3(node_blocks), dim3(kBlock), 0, s, slots, nslots);
+  hipLaunchKernelGGL(k_batch_cg_step, dim3(node_blocks), dim3(kBlock), 0, s, slots, nslots);
+}
+
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,
                          const double* z, const double* gv_next, double* gx, double* gv, const IterState* gate) {
   hipLaunchKernelGGL(k_adj_epilogue, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, x, v, z, gv_next,
@@ -818,6 +887,7 @@ void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const
 
 void launch_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z,
                         const double* cache, double* g_youngs, double* g_act, const IterState* gate) {
+  if (M.corners == 4) return launch_tet_grad_params(M, s, xn, z, cache, g_youngs, gate);
   const int nb = (M.E + kElemsPerBlock - 1) / kElemsPerBlock;
   hipLaunchKernelGGL(k_grad_params, dim3(nb), dim3(kBlock), 0, s, M, xn, z, cache, g_youngs, g_act, gate);
 }

@@ -3,14 +3,21 @@
 // Worker threads (one per slot) take queued requests in arrival order, run
 // the host analysis, wait until the request's device footprint fits in the
 // remaining HBM budget, then keep the request's factor and states resident
-// while its forward and adjoint steps run on the worker's own HIP stream.
-// Kernels of different slots overlap on the device; a slot is refilled as
-// soon as its request finishes.
+// while its forward and adjoint steps run on the worker's own HIP stream; a
+// slot is refilled as soon as its request finishes.  With batching on, every
+// request takes the multi-launch solver and every conjugate-gradient solve of
+// a resident request (the Newton steps of its forward steps and the adjoint
+// systems of its backward steps) runs in a shared batch engine: one launch per
+// sweep level and kernel shape, and one for each of the element Hessian
+// product, the node gather and the vector update, over all requests whose
+// solves are under way.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -19,6 +26,8 @@
 #include <vector>
 
 #include "../../include/diffpd.h"
+#include "batch.hpp"
+#include "handle.hpp"
 #include "internal.hpp"
 
 namespace {
@@ -53,6 +62,8 @@ struct dpd_server {
   int32_t active = 0, peak_active = 0, pending = 0;
   bool stop = false;
   std::vector<std::thread> workers;
+  std::unique_ptr<dpd::Batcher> batcher;   // null: each slot iterates on its own stream
+  bool verbose = false;                    // DPD_SERVER_VERBOSE set: failed requests reported on stderr
 };
 
 namespace {
@@ -72,6 +83,7 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
     r->res.t_done = now_s(srv->t0);
   };
   if (st != DPD_OK) return finish_fail(st);
+  m->batcher = srv->batcher.get();
   dpd_mesh_info info{};
   dpd_get_info(m, &info);
   const int64_t N = info.n_nodes, E = info.n_elements, T = r->steps;
@@ -147,9 +159,10 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
     bool ok = true;
     for (int64_t t = 0; t < T && ok; ++t) {
       dpd_stats fs{};
-      ok = soft(dpd_forward_step(m, s, xs + t * n3, vs + t * n3, nullptr, xs + (t + 1) * n3,
-                                 vs + (t + 1) * n3, &fs));
-      if (!ok) result = DPD_EHIP;
+      const dpd_status c1 = dpd_forward_step(m, s, xs + t * n3, vs + t * n3, nullptr, xs + (t + 1) * n3,
+                                             vs + (t + 1) * n3, &fs);
+      ok = soft(c1);
+      if (!ok) result = c1;
       fwd_iters += fs.fwd_iters;
     }
     if (!ok) break;
@@ -184,6 +197,9 @@ void run_request(dpd_server* srv, Request* r, hipStream_t s) {
         hipStreamSynchronize(s) != hipSuccess)
       result = DPD_EHIP;
   } while (false);
+  if (result < 0 && srv->verbose)
+    std::fprintf(stderr, "dpd_server: request %lld failed (%s): %s\n", (long long)r->id, dpd_status_string(result),
+                 m ? dpd_last_error(m) : "mesh upload");
   (void)hipStreamSynchronize(s);
   if (buf) (void)hipFree(buf);
   if (m) dpd::destroy_synced(m);
@@ -232,15 +248,30 @@ void worker(dpd_server* srv) {
 
 extern "C" {
 
-dpd_status dpd_server_create(int64_t budget, int32_t max_slots, dpd_server** out) {
+dpd_status dpd_server_create(int64_t budget, int32_t max_slots, int32_t batched, dpd_server** out) {
   if (!out || budget <= 0 || max_slots < 1) return DPD_EINVAL;
   dpd_server* srv = new dpd_server();
   srv->budget = budget;
   srv->max_slots = max_slots;
   (void)hipGetDevice(&srv->device);
+  if (batched) srv->batcher = std::make_unique<dpd::Batcher>(srv->device, max_slots);
+  srv->verbose = std::getenv("DPD_SERVER_VERBOSE") != nullptr;
   srv->t0 = std::chrono::steady_clock::now();
   for (int32_t i = 0; i < max_slots; ++i) srv->workers.emplace_back(worker, srv);
   *out = srv;
+  return DPD_OK;
+}
+
+dpd_status dpd_server_batch_stats(dpd_server* srv, dpd_batch_stats* out) {
+  if (!srv || !out) return DPD_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  if (!srv->batcher) return DPD_OK;
+  const dpd::BatchStats b = srv->batcher->stats();
+  out->iterations = b.iterations;
+  out->slot_iterations = b.slot_iterations;
+  out->launches = b.launches;
+  out->solves = b.solves;
+  out->peak_slots = b.peak_slots;
   return DPD_OK;
 }
 
@@ -256,6 +287,14 @@ dpd_status dpd_server_submit(dpd_server* srv, const dpd_request* q, int64_t* tic
   r->n_nodes = q->n_nodes;
   r->steps = q->steps;
   r->opt = q->opt;
+  // no stream capture in the workers: a capture under way in one worker makes
+  // the synchronous runtime calls of another (a mesh upload's copies and
+  // memsets) fail; the batch engine is what amortizes launches here
+  r->opt.use_graphs = 0;
+  // with the batch engine every request takes the multi-launch solver, whose
+  // iterations the engine shares (not the fused dense solver's one
+  // cooperative launch per request and solve)
+  if (srv->batcher) r->opt.fused_cg = 0;
   r->res.state = DPD_REQ_QUEUED;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -309,6 +348,7 @@ void dpd_server_destroy(dpd_server* srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();
+  srv->batcher.reset();
   delete srv;
 }
 

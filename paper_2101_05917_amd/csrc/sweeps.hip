@@ -452,6 +452,102 @@ __global__ void __launch_bounds__(kWideTaskThreads) k_sweep_bwd_narrow(DevSolve 
   clock_exit(ck);
 }
 
+// ---------------------------------------------------------------- batched level kernels
+//
+// Tasks of several handles' solves in one launch: each task names its slot
+// (pad0), whose factor and vectors it uses, and runs the level kernel's own
+// task code, so a slot's result is bitwise what its own level launches give.
+// Every batched solve is out = A^{-1} b.
+
+template <typename T>
+__device__ inline const T* col_panel(const DevSolve& S);
+template <>
+__device__ inline const double* col_panel<double>(const DevSolve& S) { return S.panel64; }
+template <>
+__device__ inline const float* col_panel<float>(const DevSolve& S) { return S.panel32; }
+template <typename T>
+__device__ inline const T* row_panel(const DevSolve& S);
+template <>
+__device__ inline const double* row_panel<double>(const DevSolve& S) { return S.panelT64; }
+template <>
+__device__ inline const float* row_panel<float>(const DevSolve& S) { return S.panelT32; }
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_batch_sweep_fwd(const BatchSolveSlot* __restrict__ slots,
+                                                            const SweepTask* __restrict__ tasks) {
+  const SweepTask t = tasks[blockIdx.x];
+  const BatchSolveSlot& B = slots[t.pad0];
+  if (B.st && B.st->done) return;
+  const DevSolve S = B.S;
+  extern __shared__ double lds[];
+  fwd_narrow_task<T, kBlock>(S, t, col_panel<T>(S), B.b, B.N, true, threadIdx.x, lds);
+}
+
+template <typename T, int LPR>
+__global__ void __launch_bounds__(kWideTaskThreads) k_batch_sweep_fwd_wide(const BatchSolveSlot* __restrict__ slots,
+                                                                           const SweepTask* __restrict__ tasks) {
+  const SweepTask t = tasks[blockIdx.x];
+  const BatchSolveSlot& B = slots[t.pad0];
+  if (B.st && B.st->done) return;
+  const DevSolve S = B.S;
+  extern __shared__ double lds[];
+  fwd_wide_task<T, LPR, kWideTaskThreads>(S, t, row_panel<T>(S), B.b, B.N, t.pad1 != 0, true, threadIdx.x, lds);
+}
+
+// k_sweep_gather's arithmetic on (slot, column) entries, wave per entry.
+__global__ void __launch_bounds__(kBlock) k_batch_sweep_gather(const BatchSolveSlot* __restrict__ slots,
+                                                               const int2* __restrict__ cols, int ncols) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= ncols) return;
+  const int2 e = cols[w];
+  const BatchSolveSlot& B = slots[e.x];
+  if (B.st && B.st->done) return;
+  const DevSolve& S = B.S;
+  const int j = e.y;
+  const int k0 = S.cptr[j], k1 = S.cptr[j + 1];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int k = k0 + lane; k < k1; k += 64) {
+    const int64_t pos = 3 * (int64_t)S.cidx[k];
+    v0 += S.U[pos];
+    v1 += S.U[pos + 1];
+    v2 += S.U[pos + 2];
+  }
+  v0 = wsum(v0);
+  v1 = wsum(v1);
+  v2 = wsum(v2);
+  if (lane == 0) {
+    const int node = S.perm_pub[j];
+    const int64_t N = B.N;
+    S.bt[j] = B.b[node] + v0;
+    S.bt[(int64_t)S.nf + j] = B.b[N + node] + v1;
+    S.bt[2 * (int64_t)S.nf + j] = B.b[2 * N + node] + v2;
+  }
+}
+
+template <typename T, bool kLds, int LPR>
+__global__ void __launch_bounds__(kWideTaskThreads) k_batch_sweep_bwd(const BatchSolveSlot* __restrict__ slots,
+                                                                      const SweepTask* __restrict__ tasks) {
+  const SweepTask t = tasks[blockIdx.x];
+  const BatchSolveSlot& B = slots[t.pad0];
+  if (B.st && B.st->done) return;
+  const DevSolve S = B.S;
+  extern __shared__ double lds[];
+  bwd_cols_task<T, kLds, LPR, kWideTaskThreads>(S, t, col_panel<T>(S), B.out, B.N, 1.0, 0, true, threadIdx.x,
+                                                lds);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWideTaskThreads) k_batch_sweep_bwd_narrow(const BatchSolveSlot* __restrict__ slots,
+                                                                             const SweepTask* __restrict__ tasks) {
+  const SweepTask t = tasks[blockIdx.x];
+  const BatchSolveSlot& B = slots[t.pad0];
+  if (B.st && B.st->done) return;
+  const DevSolve S = B.S;
+  extern __shared__ double lds[];
+  bwd_narrow_task<T, kWideTaskThreads>(S, t, row_panel<T>(S), B.out, B.N, 1.0, 0, true, threadIdx.x, lds);
+}
+
 // ---------------------------------------------------------------- single-launch solve
 
 constexpr uint32_t kDagSpinLimit = 1u << 22;  // about 4 s of polling per wait: then abort
@@ -768,6 +864,70 @@ void launch_solve_dag(const DevSolve& S, const DevDag& D, hipStream_t s, bool fp
   else
     DPD_LAUNCH(k_solve_dag<double>, dim3(D.grid), dim3(kDagThreads), D.lds_bytes, s, S, D.q, D.nq, D.fwd, D.bwd,
                D.gcols, D.sn, D.ns, D.ctr, D.bwd_region, S.panel64, S.panelT64, b, out, N, alpha, accumulate, st);
+}
+
+void launch_batch_sweep_fwd(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                            int lds_cols, bool fp32) {
+  const size_t lds = (size_t)lds_fwd_narrow(lds_cols) * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_batch_sweep_fwd<float>, dim3(ntasks), dim3(kBlock), lds, s, slots, tasks);
+  else
+    hipLaunchKernelGGL(k_batch_sweep_fwd<double>, dim3(ntasks), dim3(kBlock), lds, s, slots, tasks);
+}
+
+void launch_batch_sweep_fwd_wide(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                                 int lpr, int lds_cols, bool fp32) {
+  const size_t lds = (size_t)3 * lds_cols * sizeof(double);
+#define DPD_BFWD(T, L) \
+  hipLaunchKernelGGL((k_batch_sweep_fwd_wide<T, L>), dim3(ntasks), dim3(kWideTaskThreads), lds, s, slots, tasks)
+  if (fp32) {
+    if (lpr == 64) DPD_BFWD(float, 64);
+    else if (lpr == 32) DPD_BFWD(float, 32);
+    else DPD_BFWD(float, 16);
+  } else {
+    if (lpr == 64) DPD_BFWD(double, 64);
+    else if (lpr == 32) DPD_BFWD(double, 32);
+    else DPD_BFWD(double, 16);
+  }
+#undef DPD_BFWD
+}
+
+void launch_batch_sweep_gather(const BatchSolveSlot* slots, hipStream_t s, const int2* cols, int ncols) {
+  const int waves = kBlock / 64;
+  hipLaunchKernelGGL(k_batch_sweep_gather, dim3((ncols + waves - 1) / waves), dim3(kBlock), 0, s, slots, cols,
+                     ncols);
+}
+
+void launch_batch_sweep_bwd(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks, int ntasks,
+                            int lpr, bool use_lds, int lds_rows, bool fp32) {
+  const size_t lds = use_lds ? (size_t)3 * lds_rows * sizeof(double) : 0;
+#define DPD_BBWD(T, K, L) \
+  hipLaunchKernelGGL((k_batch_sweep_bwd<T, K, L>), dim3(ntasks), dim3(kWideTaskThreads), lds, s, slots, tasks)
+#define DPD_BBWD_L(T, K)                    \
+  do {                                      \
+    if (lpr == 64) DPD_BBWD(T, K, 64);      \
+    else if (lpr == 32) DPD_BBWD(T, K, 32); \
+    else DPD_BBWD(T, K, 16);                \
+  } while (0)
+  if (fp32) {
+    if (use_lds) DPD_BBWD_L(float, true);
+    else DPD_BBWD_L(float, false);
+  } else {
+    if (use_lds) DPD_BBWD_L(double, true);
+    else DPD_BBWD_L(double, false);
+  }
+#undef DPD_BBWD_L
+#undef DPD_BBWD
+}
+
+void launch_batch_sweep_bwd_narrow(const BatchSolveSlot* slots, hipStream_t s, const SweepTask* tasks,
+                                   int ntasks, int lds_rows, bool fp32) {
+  const size_t lds = (size_t)lds_bwd_narrow(lds_rows) * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_batch_sweep_bwd_narrow<float>, dim3(ntasks), dim3(kWideTaskThreads), lds, s, slots, tasks);
+  else
+    hipLaunchKernelGGL(k_batch_sweep_bwd_narrow<double>, dim3(ntasks), dim3(kWideTaskThreads), lds, s, slots,
+                       tasks);
 }
 
 const void* solve_dag_kernel(bool fp32) {

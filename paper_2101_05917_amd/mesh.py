@@ -78,25 +78,39 @@ def _stream(device) -> C.c_void_p:
 
 
 class Mesh:
-    """A voxel body: mesh, factor and workspaces live in the library handle."""
+    """A voxel body (or, through ``from_tets``, a tetrahedral one): mesh,
+    factor and workspaces live in the library handle."""
 
     def __init__(self, cells, youngs, fixed_nodes=None, physics: Optional[dict] = None,
-                 device="cuda:0", factorize=True, **iteration):
+                 device="cuda:0", factorize=True, tets=None, **iteration):
         self.lib = L.load()
         self.device = torch.device(device)
-        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
         youngs = np.ascontiguousarray(np.asarray(youngs, dtype=np.float64).reshape(-1))
-        fixed = (np.zeros((0, 3), np.int32) if fixed_nodes is None
-                 else np.ascontiguousarray(np.asarray(fixed_nodes, dtype=np.int32).reshape(-1, 3)))
         self.options = make_options(physics, **iteration)
         self.physics = dict(physics or {})
         h = C.c_void_p()
-        with torch.cuda.device(self.device):
-            L.check(self.lib.dpd_create_mesh(
-                cells.ctypes.data_as(L._I32), cells.shape[0],
-                youngs.ctypes.data_as(L._D),
-                fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
-                C.byref(self.options), C.byref(h)))
+        if tets is None:
+            cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+            fixed = (np.zeros((0, 3), np.int32) if fixed_nodes is None
+                     else np.ascontiguousarray(np.asarray(fixed_nodes, dtype=np.int32).reshape(-1, 3)))
+            with torch.cuda.device(self.device):
+                L.check(self.lib.dpd_create_mesh(
+                    cells.ctypes.data_as(L._I32), cells.shape[0],
+                    youngs.ctypes.data_as(L._D),
+                    fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
+                    C.byref(self.options), C.byref(h)))
+        else:
+            # cells holds the rest positions [N, 3] of a tetrahedral mesh
+            X = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 3))
+            T = np.ascontiguousarray(np.asarray(tets, dtype=np.int32).reshape(-1, 4))
+            fixed = (np.zeros(0, np.int32) if fixed_nodes is None
+                     else np.ascontiguousarray(np.asarray(fixed_nodes, dtype=np.int32).reshape(-1)))
+            with torch.cuda.device(self.device):
+                L.check(self.lib.dpd_create_tet_mesh(
+                    X.ctypes.data_as(L._D), X.shape[0], T.ctypes.data_as(L._I32), T.shape[0],
+                    youngs.ctypes.data_as(L._D),
+                    fixed.ctypes.data_as(L._I32) if len(fixed) else None, fixed.shape[0],
+                    C.byref(self.options), C.byref(h)))
         self.handle = h
         _LIVE.add(self)
         self._read_info()
@@ -110,8 +124,18 @@ class Mesh:
 
     @classmethod
     def from_scene(cls, scene, device="cuda:0", **iteration):
+        if getattr(scene, "tets", None) is not None:
+            return cls.from_tets(scene.X, scene.tets, scene.youngs, scene.fixed_nodes, scene.physics(),
+                                 device=device, **iteration)
         return cls(scene.cells, scene.youngs, scene.fixed_nodes, scene.physics(), device=device,
                    **iteration)
+
+    @classmethod
+    def from_tets(cls, X, tets, youngs, fixed_nodes=None, physics: Optional[dict] = None, device="cuda:0",
+                  factorize=True, **iteration):
+        """Linear tetrahedra: rest positions X [N, 3], corners tets [E, 4],
+        moduli [E], fixed node ids (dpd_create_tet_mesh)."""
+        return cls(X, youngs, fixed_nodes, physics, device=device, factorize=factorize, tets=tets, **iteration)
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -336,7 +360,8 @@ class Mesh:
 
     def rotations(self, x):
         self._check_state(x)
-        out = torch.empty(9, 8 * self.n_elements, dtype=torch.float64, device=self.device)
+        out = torch.empty(9, self.info["qp_per_element"] * self.n_elements, dtype=torch.float64,
+                          device=self.device)
         with torch.cuda.device(self.device):
             L.check(self.lib.dpd_rotations(self.handle, _stream(self.device), _ptr(x), _ptr(out)),
                     self.handle)

@@ -1,10 +1,13 @@
 """Python front of the rollout server (dpd_server_* in the C ABI).
 
 Each request is a whole differentiable rollout of a voxel body; the server
-keeps several of them resident on the GPU (each with its own factor, states
-and stream), admits queued requests as slots and HBM budget free up, and
-returns the loss c . x_T with its gradients w.r.t. x0, v0 and the Young's
-moduli.  Marshalling only: everything runs inside libdiffpd.
+keeps several of them resident on the GPU (each with its own factor and
+states), admits queued requests as slots and HBM budget free up, and returns
+the loss c . x_T with its gradients w.r.t. x0, v0 and the Young's moduli.
+With ``batched`` (the default) the conjugate-gradient iterations of all
+resident requests share their launches (the batch engine of the library);
+without it each request iterates on its own stream.  Marshalling only:
+everything runs inside libdiffpd.
 """
 from __future__ import annotations
 
@@ -60,12 +63,14 @@ class RolloutResult:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, batched: bool = True):
         import torch  # the device must be initialised in this process first
         torch.cuda.init()
         self.lib = L.load()
         h = C.c_void_p()
-        L.check(self.lib.dpd_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        L.check(self.lib.dpd_server_create(int(hbm_budget_bytes), int(max_slots), 1 if batched else 0,
+                                           C.byref(h)))
+        self.batched = bool(batched)
         self.handle = h
         self._sizes = {}
         _LIVE.add(self)
@@ -114,6 +119,13 @@ class Server:
         pb, pa = C.c_int64(), C.c_int32()
         L.check(self.lib.dpd_server_stats(self.handle, C.byref(pb), C.byref(pa)))
         return {"peak_bytes": pb.value, "peak_active": pa.value}
+
+    def batch_stats(self):
+        b = L.BatchStats()
+        L.check(self.lib.dpd_server_batch_stats(self.handle, C.byref(b)))
+        return {"iterations": b.iterations, "slot_iterations": b.slot_iterations, "launches": b.launches,
+                "solves": b.solves, "peak_slots": b.peak_slots,
+                "mean_slots": b.slot_iterations / b.iterations if b.iterations else 0.0}
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -34,7 +34,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sz.c"
     fields = {"dpd_options": L.Options, "dpd_stats": L.Stats, "dpd_mesh_info": L.MeshInfo,
               "dpd_kernel_profile": L.KernelProfile, "dpd_request": L.Request,
-              "dpd_result": L.Result}
+              "dpd_result": L.Result, "dpd_batch_stats": L.BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, cls in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -84,6 +84,37 @@ def test_create_mesh_rejects_bad_input_without_gpu(case):
     code = lib.dpd_create_mesh(cells.ctypes.data_as(L._I32), n, ym.ctypes.data_as(L._D),
                                fixed.ctypes.data_as(L._I32) if len(fixed) else None, len(fixed),
                                C.byref(o), C.byref(h))
+    assert code == -1 and not h.value
+    assert lib.dpd_last_error(None)
+
+
+@pytest.mark.parametrize("case", ["range", "flat", "youngs", "fixed", "muscle", "volume", "orphan"])
+def test_create_tet_mesh_rejects_bad_input_without_gpu(case):
+    lib = L.load()
+    o = L.Options()
+    lib.dpd_default_options(C.byref(o))
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]], np.float64) * 0.01
+    T = np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32)
+    ym = np.array([1e6, 1e6])
+    fixed = np.zeros(0, np.int32)
+    if case == "range":
+        T[1, 3] = 5
+    elif case == "flat":
+        X[3] = [0.005, 0.005, 0.0]    # all four corners of the first in one plane
+    elif case == "youngs":
+        ym[1] = 0.0
+    elif case == "fixed":
+        fixed = np.array([7], np.int32)
+    elif case == "muscle":
+        o.muscle_k = 1e5
+    elif case == "volume":
+        o.volume_scale = 1.0
+    elif case == "orphan":
+        X = np.vstack([X, [[0.05, 0.05, 0.05]]])
+    h = C.c_void_p()
+    code = lib.dpd_create_tet_mesh(X.ctypes.data_as(L._D), len(X), T.ctypes.data_as(L._I32), len(T),
+                                   ym.ctypes.data_as(L._D), fixed.ctypes.data_as(L._I32) if len(fixed) else None,
+                                   len(fixed), C.byref(o), C.byref(h))
     assert code == -1 and not h.value
     assert lib.dpd_last_error(None)
 

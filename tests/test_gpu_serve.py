@@ -1,4 +1,6 @@
-"""Rollout server: each result is the same alone and in the mix; admission by HBM budget."""
+"""Rollout server: each result is the same alone and in the mix, with and
+without the batch engine; admission by HBM budget; served gradients against
+the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -20,21 +22,22 @@ def _requests():
     return out
 
 
-def _run(server, reqs):
-    tickets = [server.submit(sc, c, **SOLVE) for sc, c in reqs]
+def _run(server, reqs, **extra):
+    tickets = [server.submit(sc, c, **SOLVE, **extra) for sc, c in reqs]
     server.drain()
     return [server.poll(t) for t in tickets]
 
 
-def test_alone_equals_in_mix_bitwise():
+@pytest.mark.parametrize("batched", [True, False], ids=["batch_engine", "own_streams"])
+def test_alone_equals_in_mix_bitwise(batched):
     from paper_2101_05917_amd.serve import Server
     reqs = _requests()
     alone = []
     for sc, c in reqs:
-        s = Server(8 << 30, max_slots=1)
+        s = Server(8 << 30, max_slots=1, batched=batched)
         alone += _run(s, [(sc, c)])
         s.close()
-    s = Server(8 << 30, max_slots=4)
+    s = Server(8 << 30, max_slots=4, batched=batched)
     mix = _run(s, reqs)
     stats = s.stats()
     s.close()
@@ -48,14 +51,19 @@ def test_alone_equals_in_mix_bitwise():
         assert np.array_equal(a.g_youngs, b.g_youngs)
 
 
-def test_server_matches_direct_rollout():
+@pytest.mark.parametrize("batched", [True, False])
+def test_server_matches_direct_rollout(batched):
+    """A served request against the same rollout through the mesh API: on the
+    batch engine (multi-launch solver) the same bits as the direct rollout with
+    that solver; without it, the default solver, within round-off."""
     from paper_2101_05917_amd.serve import Server
     from paper_2101_05917_amd.mesh import Mesh
     sc, c = _requests()[1]
-    s = Server(8 << 30, max_slots=2)
-    res = _run(s, [(sc, c)])[0]
+    extra = {"fused_cg": 0} if batched else {}   # the batch engine serves the multi-launch path
+    s = Server(8 << 30, max_slots=2, batched=batched)
+    res = _run(s, [(sc, c)], **extra)[0]
     s.close()
-    mesh = Mesh.from_scene(sc, **SOLVE)
+    mesh = Mesh.from_scene(sc, **SOLVE, **extra)
     X = mesh.rest_positions()
     x, v = X.clone(), torch.zeros_like(X)
     xs, vs = [x], [v]
@@ -70,10 +78,41 @@ def test_server_matches_direct_rollout():
     gE = torch.zeros(mesh.n_elements, dtype=torch.float64, device="cuda:0")
     for t in range(sc.steps - 1, -1, -1):
         gx, gv, _, _ = mesh.backward_step(xs[t], vs[t], None, xs[t + 1], gx, gv, g_youngs=gE)
+    mesh.close()
+    if batched:
+        assert np.array_equal(res.g_x0, gx.cpu().numpy())
+        assert np.array_equal(res.g_v0, gv.cpu().numpy())
+        assert np.array_equal(res.g_youngs, gE.cpu().numpy())
     assert abs(L - res.loss) <= 1e-13 * abs(L)
     assert np.allclose(res.g_x0, gx.cpu().numpy(), rtol=0, atol=1e-12 * np.abs(res.g_x0).max())
     assert np.allclose(res.g_youngs, gE.cpu().numpy(), rtol=0,
                        atol=1e-12 * np.abs(res.g_youngs).max())
+
+
+def test_batch_engine_shares_launches():
+    """Six requests at once on the batch engine: their solves share iterations
+    (more than one solve per batched iteration on average), and every result
+    is bitwise the one the request gets on its own stream with the same
+    multi-launch solver."""
+    from paper_2101_05917_amd.serve import Server
+    reqs = _requests()
+    s = Server(8 << 30, max_slots=6, batched=True)
+    mix = _run(s, reqs, fused_cg=0)
+    bst = s.batch_stats()
+    s.close()
+    print("batch stats", bst, flush=True)
+    assert bst["peak_slots"] >= 2
+    assert bst["mean_slots"] > 1.2
+    assert bst["solves"] > 0
+    s = Server(8 << 30, max_slots=6, batched=False)
+    own = _run(s, reqs, fused_cg=0)
+    s.close()
+    for a, b in zip(mix, own):
+        assert a.state == "done" and b.state == "done", (a, b)
+        assert a.loss == b.loss
+        assert np.array_equal(a.g_x0, b.g_x0)
+        assert np.array_equal(a.g_v0, b.g_v0)
+        assert np.array_equal(a.g_youngs, b.g_youngs)
 
 
 def test_admission_respects_budget_and_rejects_oversized():

@@ -381,7 +381,7 @@ def served_requests(n_requests: int = 64, lo: int = 4, hi: int = 24, steps: int 
     return reqs
 
 
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "sphere")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "sphere", "tet")
 
 
 def config(name: str) -> Scene:
@@ -392,6 +392,8 @@ def config(name: str) -> Scene:
     c3: legged 20x10x6 body, muscles, penalty ground + friction, h = 5 ms, 200 steps.
     c5: 64x32x32 block dropped 2 cm onto a penalty ground, 200 steps.
     sphere: 552-element sphere rolling on a complementarity ground, 100 steps.
+    tet: 25,344-tetrahedron ball dropped 1 cm onto a penalty ground with
+         friction, h = 5 ms, 100 steps (a ``TetScene``).
     (c4 is a request trace, see ``served_requests``.)
     """
     if name == "c1":
@@ -405,4 +407,6 @@ def config(name: str) -> Scene:
         return dropped_block()
     if name == "sphere":
         return rolling_sphere()
+    if name == "tet":
+        return tet_ball(name="tet_ball_25344")
     raise KeyError(name)
