@@ -89,6 +89,10 @@ def parse(argv=None):
                          "tree level (default: the library's)")
     ap.add_argument("--leaf-nodes", type=int, default=0,
                     help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
+    ap.add_argument("--deflation", type=int, default=None,
+                    help="adjoint CG deflated by this many Lanczos Ritz vectors (0: off)")
+    ap.add_argument("--deflation-refresh", type=int, default=25,
+                    help="backward steps between rebuilds of the deflation vectors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--checkpoint-every", type=int, default=0,
@@ -135,6 +139,8 @@ def parse(argv=None):
         args.bwd_tol = 1e-9 if legged or sphere else (2e-8 if block else 2e-7)
     if args.fwd_inner_tol is None:
         args.fwd_inner_tol = -0.3 if legged else -0.1
+    if args.deflation is None:
+        args.deflation = 0
     return args
 
 
@@ -147,6 +153,9 @@ def solver_options(args) -> dict:
         opts["sweep_launch"] = args.sweep_launch
     if args.leaf_nodes:
         opts["leaf_nodes"] = args.leaf_nodes
+    if args.deflation:
+        opts["deflation"] = args.deflation
+        opts["deflation_refresh"] = args.deflation_refresh
     return opts
 
 
@@ -690,7 +699,8 @@ def main():
                    "fwd_solver": args.fwd_solver, "bwd_solver": args.bwd_solver,
                    "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol,
                    "fwd_inner_tol": args.fwd_inner_tol,
-                   "precision": args.precision, "fused_cg_workgroups": mesh.info["fused_blocks"]},
+                   "precision": args.precision, "fused_cg_workgroups": mesh.info["fused_blocks"],
+                   "deflation": args.deflation, "deflation_refresh": args.deflation_refresh if args.deflation else None},
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,
         "grad_rel_err_vs_oracle": err,

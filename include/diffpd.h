@@ -127,6 +127,16 @@ typedef struct {
                               by the solve-time estimate among 64, 128, 256, 512
                               (and all free nodes when they fit one block);
                               > 0 forces it.  Read at mesh creation.            */
+  int32_t deflation;       /* adjoint CG on the multi-launch path: keep the search
+                              directions H-orthogonal to this many (<= 16) Ritz
+                              vectors of A^{-1} dA's largest eigenvalues (the
+                              modes that make Alg. 2 and its acceleration slow),
+                              built by Lanczos on the factor's solve and the
+                              Hessian product; 0 = off.  The solution is the
+                              same (to the tolerance); only iterations change  */
+  int32_t deflation_refresh;  /* backward steps between rebuilds of those vectors
+                              (0 = 25); the Hessian's products with them are
+                              recomputed every step                            */
   int32_t pad_opt;
 } dpd_options;
 

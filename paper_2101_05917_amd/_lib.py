@@ -34,7 +34,8 @@ class Options(C.Structure):
         ("bwd_max_iter", C.c_int32), ("bwd_solver", C.c_int32), ("bwd_rel_tol", C.c_double),
         ("precision", C.c_int32), ("check_every", C.c_int32), ("use_graphs", C.c_int32),
         ("fused_cg", C.c_int32), ("contact_fused", C.c_int32), ("sweep_launch", C.c_int32),
-        ("volume_scale", C.c_double), ("leaf_nodes", C.c_int32), ("pad_opt", C.c_int32),
+        ("volume_scale", C.c_double), ("leaf_nodes", C.c_int32), ("deflation", C.c_int32),
+        ("deflation_refresh", C.c_int32), ("pad_opt", C.c_int32),
     ]
 
 

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -781,9 +782,11 @@ namespace dpd {
 // Free a handle whose streams the caller has already synchronized.
 void destroy_synced(dpd_mesh* m) {
   if (!m) return;
-  for (auto& row : m->cg_exec)
-    for (auto& ex : row)
-      if (ex) (void)hipGraphExecDestroy(ex);
+  for (auto& plane : m->cg_exec)
+    for (auto& row : plane)
+      for (auto& ex : row)
+        if (ex) (void)hipGraphExecDestroy(ex);
+  if (m->h_defl) (void)hipHostFree(m->h_defl);
   if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
   for (void* p : m->allocs) (void)hipFree(p);
   for (auto& e : m->ev_free) {
@@ -1091,10 +1094,18 @@ dpd_status fixed_point(dpd_mesh* m, hipStream_t s, const double* xn, bool fp32, 
 // buffer of the handle, so the sequence can be captured once and replayed.
 void cg_iteration(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32, int k) {
   const int st_idx = st == m->st ? 0 : 1;
+  const bool defl = st == m->st && m->defl_active;
   solve(m, s, fp32, m->cg_r, m->s, 1.0, 0, st, k);
   {
     ProfScope ps(m, s, DPD_PROF_ELEM_HVP, elem_hvp_bytes(m), elem_hvp_flops(m), st_idx, k);
     launch_elem_hvp(m->dm, s, m->s, m->cache, m->fe, st);
+  }
+  if (defl) {
+    launch_cg_hvp_dots_defl(m->dm, s, m->s, m->fe, m->cg_r, m->xbar_w, st, m->defl_part, m->defl_HW, m->defl_k,
+                            m->defl_state);
+    launch_cg_step_defl(m->dm, s, m->z, m->cg_r, m->p, m->q, m->s, m->xbar_w, st, m->partials, m->defl_W,
+                        m->defl_HW, m->defl_k, m->defl_state);
+    return;
   }
   launch_cg_hvp_dots(m->dm, s, m->s, m->fe, m->cg_r, m->xbar_w, st, m->partials);
   launch_cg_step(m->dm, s, m->z, m->cg_r, m->p, m->q, m->s, m->xbar_w, st, m->partials);
@@ -1102,8 +1113,14 @@ void cg_iteration(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32, int k) {
 
 // Graph of kGraphIters iterations on state st (captured on first use).
 hipGraphExec_t cg_graph(dpd_mesh* m, hipStream_t s, IterState* st, bool fp32) {
-  hipGraphExec_t& ex = m->cg_exec[st == m->st ? 0 : 1][fp32 ? 1 : 0];
+  const bool defl = st == m->st && m->defl_active;
+  hipGraphExec_t& ex = m->cg_exec[st == m->st ? 0 : 1][fp32 ? 1 : 0][defl ? 1 : 0];
+  if (ex && defl && m->defl_graph_k != m->defl_k) {   // captured with another number of vectors
+    (void)hipGraphExecDestroy(ex);
+    ex = nullptr;
+  }
   if (ex) return ex;
+  if (defl) m->defl_graph_k = m->defl_k;
   // capture on a private stream (the caller's may be the null stream); nothing
   // executes during capture, and the graph is then launched on the caller's stream
   if (!m->capture_stream &&
@@ -1202,6 +1219,242 @@ dpd_status cg_dense(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs
   return check_aborted(m, st_idx);
 }
 
+// ---------------------------------------------------------------- deflation
+//
+// The adjoint systems (A - dA) z = xbar are solved by CG preconditioned by
+// A^{-1}; its iteration count grows with 1 / (1 - lambda_max(A^{-1} dA)), and the
+// largest eigenvalues belong to a few slow modes (near-rigid rotations and the
+// softest bending modes).  Keeping the search directions H-orthogonal to a
+// space W holding approximations of those modes removes them from the
+// iteration (deflated CG): the solution is the same, the contraction is set by
+// the next eigenvalues.  W is built by Lanczos on B = dA A^{-1} = I - H A^{-1},
+// which is self-adjoint in <u, v> = u^T A^{-1} v: with Q the Lanczos vectors and
+// S = A^{-1} Q, an eigenvector u = Q y of B gives w = A^{-1} u = S y with
+// dA w = lambda A w.  W is rebuilt every deflation_refresh backward steps; H W
+// and E = W^T H W follow the linearisation point every step.
+
+constexpr int kLanczosSteps = 40;
+
+// Eigen-decomposition of a symmetric n x n matrix (row-major) by cyclic Jacobi
+// rotations; eigenvalues in w, eigenvectors in the columns of V.
+void sym_eig_jacobi(int n, std::vector<double> a, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) (i == j ? diag : off) += a[(size_t)i * n + j] * a[(size_t)i * n + j];
+    if (off <= 1e-30 * std::max(diag, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = c * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = c * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
+}
+
+dpd_status defl_alloc(dpd_mesh* m) {
+  if (m->defl_W) return DPD_OK;
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  const int64_t blocks = (m->dm.N + kBlock - 1) / kBlock;
+  dpd_status st;
+  if ((st = dev_alloc(m, &m->defl_W, kDeflMax * n3)) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_HW, kDeflMax * n3)) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_Q, (kLanczosSteps + 1) * n3)) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_S, (kLanczosSteps + 1) * n3)) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_part, std::max<int64_t>((kDeflMax + 2) * blocks, 256 * 64))) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_dots, 64)) != DPD_OK || (st = dev_alloc(m, &m->defl_coef, 64)) != DPD_OK ||
+      (st = dev_alloc(m, &m->defl_state, 1)) != DPD_OK)
+    return st;
+  HIPCHECK(m, hipHostMalloc((void**)&m->h_defl, 64 * 64 * sizeof(double), hipHostMallocDefault));
+  m->defl_steps = kLanczosSteps + 1;
+  return DPD_OK;
+}
+
+// Device multi-dot out = X^T y (cnt vectors) copied to m->h_defl (synchronizes).
+dpd_status defl_dots_host(dpd_mesh* m, hipStream_t s, const double* X, int cnt, const double* y) {
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  launch_multi_dot(s, X, cnt, y, n3, m->defl_part, m->defl_dots);
+  HIPCHECK(m, hipMemcpyAsync(m->h_defl, m->defl_dots, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  return DPD_OK;
+}
+
+// y += sign * X c for host coefficients c (cnt of them).
+dpd_status defl_axpy_host(dpd_mesh* m, hipStream_t s, double* y, const double* X, int cnt, const double* c,
+                          double sign) {
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  // the coefficients are staged through pinned memory: wait for their previous use first
+  HIPCHECK(m, hipStreamSynchronize(s));
+  std::memcpy(m->h_defl, c, cnt * sizeof(double));
+  HIPCHECK(m, hipMemcpyAsync(m->defl_coef, m->h_defl, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_multi_axpy(s, y, X, cnt, m->defl_coef, n3, sign);
+  HIPCHECK(m, hipGetLastError());
+  return DPD_OK;
+}
+
+// H p with the cached linearisation point (fixed rows zero).
+void defl_hessian(dpd_mesh* m, hipStream_t s, const double* p, double* out) {
+  launch_elem_hvp(m->dm, s, p, m->cache, m->fe, nullptr);
+  launch_node_hvp(m->dm, s, p, m->fe, nullptr, out, nullptr, m->partials, 0, 0, 0);
+}
+
+// Lanczos on B = I - H A^{-1} (A^{-1} inner product) from a fixed start
+// vector, full reorthogonalization; W = the Ritz vectors S y of B's k largest
+// Ritz values.
+dpd_status defl_build(dpd_mesh* m, hipStream_t s, bool fp32) {
+  dpd_status rc;
+  if ((rc = defl_alloc(m)) != DPD_OK) return rc;
+  const int64_t N = m->dm.N, n3 = 3 * N;
+  const int K = std::min(kDeflMax, m->opt.deflation);
+  const int ms = kLanczosSteps;
+  double* Q = m->defl_Q;
+  double* S = m->defl_S;
+  // start vector: a fixed pseudo-random field on the free nodes
+  {
+    std::vector<double> u(n3, 0.0);
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    for (int64_t c = 0; c < 3; ++c)
+      for (int64_t n = 0; n < N; ++n) {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        if (!m->hm.fixed[n]) u[c * N + n] = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+      }
+    HIPCHECK(m, hipMemcpyAsync(Q, u.data(), n3 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+  }
+  solve(m, s, fp32, Q, S, 1.0, 0, nullptr);
+  if ((rc = defl_dots_host(m, s, Q, 1, S)) != DPD_OK) return rc;
+  double b0 = std::sqrt(std::max(m->h_defl[0], 0.0));
+  if (!(b0 > 0.0)) return DPD_OK;
+  launch_lincomb(s, n3, Q, 1.0 / b0, Q, 0.0, nullptr);
+  launch_lincomb(s, n3, S, 1.0 / b0, S, 0.0, nullptr);
+  std::vector<double> alpha, beta;
+  int steps = 0;
+  for (int j = 0; j < ms; ++j) {
+    double* w = Q + (j + 1) * n3;
+    double* sw = S + (j + 1) * n3;
+    defl_hessian(m, s, S + j * n3, sw);                   // H S_j (staged in the next S slot)
+    launch_lincomb(s, n3, w, 1.0, Q + j * n3, -1.0, sw);  // w = Q_j - H S_j = B Q_j
+    // full reorthogonalization against Q_0..Q_j in the A^{-1} inner product, twice
+    std::vector<double> c(j + 1);
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((rc = defl_dots_host(m, s, S, j + 1, w)) != DPD_OK) return rc;
+      std::copy(m->h_defl, m->h_defl + j + 1, c.begin());
+      if (pass == 0) alpha.push_back(c[j]);
+      if ((rc = defl_axpy_host(m, s, w, Q, j + 1, c.data(), -1.0)) != DPD_OK) return rc;
+    }
+    solve(m, s, fp32, w, sw, 1.0, 0, nullptr);
+    if ((rc = defl_dots_host(m, s, w, 1, sw)) != DPD_OK) return rc;
+    const double bj = std::sqrt(std::max(m->h_defl[0], 0.0));
+    steps = j + 1;
+    if (!(bj > 1e-10 * std::fabs(alpha[0]) + 1e-300)) break;
+    beta.push_back(bj);
+    launch_lincomb(s, n3, w, 1.0 / bj, w, 0.0, nullptr);
+    launch_lincomb(s, n3, sw, 1.0 / bj, sw, 0.0, nullptr);
+  }
+  // Ritz pairs of the tridiagonal T (steps x steps)
+  std::vector<double> T((size_t)steps * steps, 0.0), theta, Y;
+  for (int i = 0; i < steps; ++i) {
+    T[(size_t)i * steps + i] = alpha[i];
+    if (i + 1 < steps) T[(size_t)i * steps + i + 1] = T[(size_t)(i + 1) * steps + i] = beta[i];
+  }
+  sym_eig_jacobi(steps, T, theta, Y);
+  std::vector<int> order(steps);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return theta[a] > theta[b]; });
+  const int k = std::min(K, steps);
+  HIPCHECK(m, hipMemsetAsync(m->defl_W, 0, k * n3 * sizeof(double), s));
+  for (int j = 0; j < k; ++j) {
+    std::vector<double> y(steps);
+    for (int i = 0; i < steps; ++i) y[i] = Y[(size_t)i * steps + order[j]];
+    if ((rc = defl_axpy_host(m, s, m->defl_W + j * n3, S, steps, y.data(), 1.0)) != DPD_OK) return rc;
+  }
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->defl_k = k;
+  m->defl_age = 0;
+  return DPD_OK;
+}
+
+// Per backward step (the cache holds the linearisation point): rebuild W when
+// due, then H W and E^{-1} = (W^T H W)^{-1}.  Leaves deflation off for this
+// step when E is not positive definite.
+dpd_status defl_prepare(dpd_mesh* m, hipStream_t s, bool fp32) {
+  dpd_status rc;
+  m->defl_active = false;
+  const int refresh = m->opt.deflation_refresh > 0 ? m->opt.deflation_refresh : 25;
+  if (m->defl_k == 0 || m->defl_age >= refresh)
+    if ((rc = defl_build(m, s, fp32)) != DPD_OK) return rc;
+  m->defl_age += 1;
+  const int k = m->defl_k;
+  if (k == 0) return DPD_OK;
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  for (int j = 0; j < k; ++j) defl_hessian(m, s, m->defl_W + j * n3, m->defl_HW + j * n3);
+  std::vector<double> E((size_t)k * k);
+  for (int j = 0; j < k; ++j) {
+    if ((rc = defl_dots_host(m, s, m->defl_W, k, m->defl_HW + j * n3)) != DPD_OK) return rc;
+    for (int i = 0; i < k; ++i) E[(size_t)i * k + j] = m->h_defl[i];
+  }
+  // symmetrize and invert by Gauss-Jordan (k <= 16), requiring positive pivots
+  std::vector<double> a((size_t)k * 2 * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    for (int j = 0; j < k; ++j) a[(size_t)i * 2 * k + j] = 0.5 * (E[(size_t)i * k + j] + E[(size_t)j * k + i]);
+    a[(size_t)i * 2 * k + k + i] = 1.0;
+  }
+  for (int c = 0; c < k; ++c) {
+    const double piv = a[(size_t)c * 2 * k + c];
+    if (!(piv > 0.0) || !std::isfinite(piv)) return DPD_OK;
+    for (int j = 0; j < 2 * k; ++j) a[(size_t)c * 2 * k + j] /= piv;
+    for (int i = 0; i < k; ++i) {
+      if (i == c) continue;
+      const double f = a[(size_t)i * 2 * k + c];
+      for (int j = 0; j < 2 * k; ++j) a[(size_t)i * 2 * k + j] -= f * a[(size_t)c * 2 * k + j];
+    }
+  }
+  DeflState h{};
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) h.einv[i * kDeflMax + j] = a[(size_t)i * 2 * k + k + j];
+  HIPCHECK(m, hipMemcpy(m->defl_state, &h, sizeof(DeflState), hipMemcpyHostToDevice));
+  m->defl_active = true;
+  return DPD_OK;
+}
+
+// z0 = W E^{-1} W^T rhs into m->z (zeroed before), r0 = rhs - HW E^{-1} W^T rhs into m->cg_r.
+dpd_status deflated_start(dpd_mesh* m, hipStream_t s, const double* rhs) {
+  dpd_status rc;
+  const int k = m->defl_k;
+  if ((rc = defl_dots_host(m, s, m->defl_W, k, rhs)) != DPD_OK) return rc;
+  std::vector<double> c(m->h_defl, m->h_defl + k), a(k, 0.0);
+  DeflState h{};
+  HIPCHECK(m, hipMemcpy(&h, m->defl_state, sizeof(DeflState), hipMemcpyDeviceToHost));
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) a[i] += h.einv[i * kDeflMax + j] * c[j];
+  if ((rc = defl_axpy_host(m, s, m->z, m->defl_W, k, a.data(), 1.0)) != DPD_OK) return rc;
+  if ((rc = defl_axpy_host(m, s, m->cg_r, m->defl_HW, k, a.data(), -1.0)) != DPD_OK) return rc;
+  return DPD_OK;
+}
+
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
                               int max_it, int check_every) {
   if (m->dense_blocks > 0 && m->opt.fused_cg) return cg_dense(m, s, st, rhs, fp32);
@@ -1213,6 +1466,11 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
+  if (st == m->st && m->defl_active && !m->batcher) {
+    // start from the solution's component in W: z0 = W E^{-1} W^T rhs, r0 = rhs - HW E^{-1} W^T rhs
+    // (r0 is then orthogonal to W, and stays so)
+    if ((rc = deflated_start(m, s, rhs)) != DPD_OK) return rc;
+  }
   if (m->batcher) {
     // the iterations run in the batch engine's launches, together with other
     // handles' solves; the set-up above must be complete first
@@ -1292,9 +1550,11 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   if (gated) {
     if ((rc = cg_dense_async(m, s, m->st, m->xbar, 1.0, fp32, false)) != DPD_OK) return rc;
   } else if (o.bwd_solver == DPD_BWD_PCG) {
-    if ((rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every)) !=
-        DPD_OK)
-      return rc;
+    m->defl_active = false;
+    if (o.deflation > 0 && !m->batcher && (rc = defl_prepare(m, s, fp32)) != DPD_OK) return rc;
+    rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every);
+    m->defl_active = false;
+    if (rc != DPD_OK) return rc;
     if ((rc = read_state(m, s)) != DPD_OK) return rc;
     if (m->h_st->curvature) {
       // the paper's safeguard when the quasi-Newton step is not a descent:

@@ -124,6 +124,30 @@ void launch_tet_hvp(const DevMesh& M, hipStream_t s, const double* p, const doub
 void launch_tet_grad_params(const DevMesh& M, hipStream_t s, const double* xn, const double* z, const double* cache,
                             double* g_youngs, const IterState* gate);
 
+// Deflated conjugate gradients: the adjoint solve's search directions are kept
+// H-orthogonal to a space W of k <= kDeflMax vectors (Ritz vectors of the
+// preconditioned operator's slowest modes), with E = W^T H W.
+constexpr int kDeflMax = 16;
+struct DeflState {
+  double einv[kDeflMax * kDeflMax];  // E^{-1}, row-major k x k
+  double mu[kDeflMax];               // this iteration's projection coefficients E^{-1} (HW)^T s
+};
+// Chronopoulos-Gear step with deflation: w = H s, gamma = r.s, delta = w.s and
+// c = (HW)^T s in one deterministic grid reduction (partials: (k + 2) per
+// block); mu = E^{-1} c; alpha = gamma / (delta - beta gamma / alpha_old - mu.c).
+void launch_cg_hvp_dots_defl(const DevMesh& M, hipStream_t s, const double* sv, const double* fe, const double* r,
+                             double* w, IterState* st, double* partials, const double* HW, int k, DeflState* D);
+// p = s + beta p - W mu; q = w + beta q - HW mu; z += alpha p; r -= alpha q; |r|^2.
+void launch_cg_step_defl(const DevMesh& M, hipStream_t s, double* z, double* r, double* p, double* q,
+                         const double* sv, const double* w, IterState* st, double* partials, const double* W,
+                         const double* HW, int k, const DeflState* D);
+// out[i] = X_i . y for the cnt vectors X_i = X + i * n (n doubles each), in a
+// fixed summation order (per-chunk partials, then one block per i).
+void launch_multi_dot(hipStream_t s, const double* X, int cnt, const double* y, int64_t n, double* partials,
+                      double* out);
+// y += sign * sum_i c[i] X_i (c on the device, cnt <= 64).
+void launch_multi_axpy(hipStream_t s, double* y, const double* X, int cnt, const double* c, int64_t n, double sign);
+
 // Dynamic LDS a backward column task may use to stage [y_s; x_R] (3 doubles per
 // panel row); longer panels read the vector from memory.
 constexpr int64_t kSweepLdsBudget = 60 * 1024;

@@ -51,7 +51,7 @@ struct dpd_mesh {
   int32_t leaf_max = 0;                           // chosen dissection leaf size
   int64_t method_factor_nnz = 0;                  // packed entries of a sparse factor (64-node leaves)
   uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
-  hipGraphExec_t cg_exec[2][2] = {};              // captured CG iterations [state][fp32]
+  hipGraphExec_t cg_exec[2][2][2] = {};           // captured CG iterations [state][fp32][deflated]
   bool graphs_failed = false;                     // a capture failed: direct launches only
   // fused dense conjugate gradients (meshes with few free nodes)
   dpd::DenseCG dcg{};
@@ -103,6 +103,21 @@ struct dpd_mesh {
   bool contact_red_ok = false;
   uint32_t* contact_bar = nullptr;     // [kContactBarWords] grid barrier of the fused contact loop
   std::vector<int32_t> contact_red;    // the set W belongs to
+  // deflated adjoint conjugate gradients (dpd_options.deflation)
+  int32_t defl_k = 0;                  // vectors in W (0: not built)
+  int32_t defl_age = 0;                // backward steps since W was built
+  int32_t defl_steps = 0;              // Lanczos vectors allocated (m + 1)
+  int32_t defl_graph_k = 0;            // vectors the captured deflated iterations use
+  bool defl_active = false;            // the current backward solve runs deflated
+  double* defl_W = nullptr;            // [kDeflMax][3N]
+  double* defl_HW = nullptr;           // [kDeflMax][3N] H W at the current linearisation point
+  double* defl_Q = nullptr;            // [m + 1][3N] Lanczos vectors
+  double* defl_S = nullptr;            // [m + 1][3N] A^{-1} Q
+  double* defl_part = nullptr;         // partial sums of the deflated reductions
+  double* defl_dots = nullptr;         // [64] device results of multi-dots
+  double* defl_coef = nullptr;         // [64] device coefficients of multi-axpys
+  dpd::DeflState* defl_state = nullptr;
+  double* h_defl = nullptr;            // pinned host scratch [64 * 64]
   // conjugate-gradient solves of the multi-launch path go through this engine
   // (several handles' iterations in the same launches) when set; not owned
   dpd::Batcher* batcher = nullptr;

@@ -17,6 +17,8 @@
 //    [inv(L_ss); -L_Rs inv(L_ss)] (dense matrix-vector products per level).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 
 #include "device.hpp"
@@ -529,6 +531,165 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(DevMesh M, double* __restric
   cg_step_block(M, z, r, p, q, sv, w, st, partials, blockIdx.x, gridDim.x);
 }
 
+// ---------------------------------------------------------------- deflated iterations
+
+__global__ void __launch_bounds__(kBlock) k_cg_hvp_dots_defl(DevMesh M, const double* __restrict__ sv,
+                                                             const double* __restrict__ fe,
+                                                             const double* __restrict__ r, double* __restrict__ w,
+                                                             IterState* st, double* partials,
+                                                             const double* __restrict__ HW, int k, DeflState* D) {
+  if (st->done) return;
+  __shared__ double ws[kBlock / 64];
+  __shared__ int last;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = M.N, n3 = 3 * N;
+  double v[kDeflMax + 2];
+#pragma unroll
+  for (int j = 0; j < kDeflMax + 2; ++j) v[j] = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (n < M.N) {
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (!M.fixed[n]) {
+      node_force(M, fe, n, o0, o1, o2);
+      const double c = M.mass[n] / (M.h * M.h);
+      s0 = sv[n];
+      s1 = sv[N + n];
+      s2 = sv[2 * N + n];
+      o0 += c * s0;
+      o1 += c * s1;
+      o2 += c * s2;
+      if (M.cmask[n]) o2 += M.contact_k * s2;
+      v[0] = r[n] * s0 + r[N + n] * s1 + r[2 * N + n] * s2;
+      v[1] = o0 * s0 + o1 * s1 + o2 * s2;
+#pragma unroll
+      for (int j = 0; j < kDeflMax; ++j)
+        if (j < k) v[2 + j] = HW[j * n3 + n] * s0 + HW[j * n3 + N + n] * s1 + HW[j * n3 + 2 * N + n] * s2;
+    }
+    w[n] = o0;
+    w[N + n] = o1;
+    w[2 * N + n] = o2;
+  }
+  const int nv = k + 2, nb = gridDim.x;
+#pragma unroll
+  for (int j = 0; j < kDeflMax + 2; ++j) {
+    if (j >= nv) break;
+    const double b = block_sum(v[j], ws);
+    if (threadIdx.x == 0) __hip_atomic_store(&partials[j * nb + blockIdx.x], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t t = __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == (uint32_t)nb - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  double tot[kDeflMax + 2];
+#pragma unroll
+  for (int j = 0; j < kDeflMax + 2; ++j) {
+    tot[j] = 0.0;
+    if (j >= nv) continue;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+      a += __hip_atomic_load(&partials[j * nb + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tot[j] = block_sum(a, ws);
+  }
+  if (threadIdx.x != 0) return;
+  __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double gamma = tot[0], delta = tot[1];
+  double mc = 0.0;
+  for (int i = 0; i < k; ++i) {
+    double m = 0.0;
+    for (int j = 0; j < k; ++j) m += D->einv[i * kDeflMax + j] * tot[2 + j];
+    D->mu[i] = m;
+    mc += m * tot[2 + i];
+  }
+  const bool first = st->iter == 0;
+  const double beta = first ? 0.0 : gamma / st->rs;
+  const double den = (first ? delta : delta - beta * gamma / st->alpha) - mc;
+  if (!(den > 0.0) || !isfinite(den) || !isfinite(gamma)) {
+    st->curvature = 1;
+    st->done = 1;
+  } else {
+    st->beta = beta;
+    st->alpha = gamma / den;
+    st->rs = gamma;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_step_defl(DevMesh M, double* __restrict__ z, double* __restrict__ r,
+                                                         double* __restrict__ p, double* __restrict__ q,
+                                                         const double* __restrict__ sv,
+                                                         const double* __restrict__ w, IterState* st,
+                                                         double* partials, const double* __restrict__ W,
+                                                         const double* __restrict__ HW, int k,
+                                                         const DeflState* __restrict__ D) {
+  if (st->done) return;
+  const double alpha = st->alpha, beta = st->beta;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (n < M.N && !M.fixed[n]) {
+    const int64_t N = M.N, n3 = 3 * N;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t i = c * N + n;
+      double pi = sv[i] + beta * p[i], qi = w[i] + beta * q[i];
+      for (int j = 0; j < k; ++j) {
+        const double m = D->mu[j];
+        pi -= m * W[j * n3 + i];
+        qi -= m * HW[j * n3 + i];
+      }
+      p[i] = pi;
+      q[i] = qi;
+      z[i] += alpha * pi;
+      const double ri = r[i] - alpha * qi;
+      r[i] = ri;
+      acc += ri * ri;
+    }
+  }
+  double tot;
+  if (grid_sum(acc, partials, st, &tot)) {
+    st->rsq = tot;
+    st->iter += 1;
+    if (!isfinite(tot)) {
+      st->nonfinite = 1;
+      st->done = 1;
+    } else if (tot <= st->tolsq * st->nb2) {
+      st->converged = 1;
+      st->done = 1;
+    }
+    if (st->iter >= st->max_iter) st->done = 1;
+  }
+}
+
+// Partial dot products of chunk blockIdx.x for vector blockIdx.y.
+__global__ void __launch_bounds__(kBlock) k_multi_dot_part(const double* __restrict__ X, const double* __restrict__ y,
+                                                           int64_t n, int64_t chunk, double* __restrict__ partials) {
+  __shared__ double ws[kBlock / 64];
+  const double* x = X + (int64_t)blockIdx.y * n;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+  double a = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) a += x[i] * y[i];
+  a = block_sum(a, ws);
+  if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = a;
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_dot_sum(const double* __restrict__ partials, int chunks,
+                                                          double* __restrict__ out) {
+  __shared__ double ws[kBlock / 64];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < chunks; i += blockDim.x) a += partials[(int64_t)blockIdx.x * chunks + i];
+  a = block_sum(a, ws);
+  if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_axpy(double* __restrict__ y, const double* __restrict__ X, int cnt,
+                                                       const double* __restrict__ c, int64_t n, double sign) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int j = 0; j < cnt; ++j) a += c[j] * X[(int64_t)j * n + i];
+  y[i] += sign * a;
+}
+
 // ---------------------------------------------------------------- batched iterations
 //
 // The same three steps over several handles' conjugate-gradient solves in one
@@ -877,6 +1038,31 @@ void launch_batch_cg_iteration_tail(const BatchCgSlot* slots, int nslots, int el
   hipLaunchKernelGGL(k_batch_elem_hvp, dim3(elem_blocks), dim3(kBlock), 0, s, slots, nslots);
   hipLaunchKernelGGL(k_batch_cg_hvp_dots, dim3(node_blocks), dim3(kBlock), 0, s, slots, nslots);
   hipLaunchKernelGGL(k_batch_cg_step, dim3(node_blocks), dim3(kBlock), 0, s, slots, nslots);
+}
+
+void launch_cg_hvp_dots_defl(const DevMesh& M, hipStream_t s, const double* sv, const double* fe, const double* r,
+                             double* w, IterState* st, double* partials, const double* HW, int k, DeflState* D) {
+  hipLaunchKernelGGL(k_cg_hvp_dots_defl, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, sv, fe, r, w, st, partials,
+                     HW, k, D);
+}
+
+void launch_cg_step_defl(const DevMesh& M, hipStream_t s, double* z, double* r, double* p, double* q,
+                         const double* sv, const double* w, IterState* st, double* partials, const double* W,
+                         const double* HW, int k, const DeflState* D) {
+  hipLaunchKernelGGL(k_cg_step_defl, dim3(blocks_for(M.N)), dim3(kBlock), 0, s, M, z, r, p, q, sv, w, st, partials,
+                     W, HW, k, D);
+}
+
+void launch_multi_dot(hipStream_t s, const double* X, int cnt, const double* y, int64_t n, double* partials,
+                      double* out) {
+  const int chunks = (int)std::min<int64_t>(256, (n + kBlock * 4 - 1) / (kBlock * 4));
+  const int64_t chunk = (n + chunks - 1) / chunks;
+  hipLaunchKernelGGL(k_multi_dot_part, dim3(chunks, cnt), dim3(kBlock), 0, s, X, y, n, chunk, partials);
+  hipLaunchKernelGGL(k_multi_dot_sum, dim3(cnt), dim3(kBlock), 0, s, partials, chunks, out);
+}
+
+void launch_multi_axpy(hipStream_t s, double* y, const double* X, int cnt, const double* c, int64_t n, double sign) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(blocks_for(n)), dim3(kBlock), 0, s, y, X, cnt, c, n, sign);
 }
 
 void launch_adj_epilogue(const DevMesh& M, hipStream_t s, const double* x, const double* v,

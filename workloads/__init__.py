@@ -306,7 +306,7 @@ def tet_cantilever(nx: int, ny: int, nz: int, *, youngs="const", jitter: float =
 
 
 def tet_ball(radius: float = 10.0, *, jitter: float = 0.15, steps: int = 100, drop: float = 0.01,
-             youngs: float = 1e5, seed: int = 0, name: Optional[str] = None) -> TetScene:
+             youngs: float = 1e6, seed: int = 0, name: Optional[str] = None) -> TetScene:
     """Free tetrahedral ball dropped ``drop`` metres onto a penalty ground
     (k = 1e4, friction 0.5): the voxels of a 2r-cell grid whose centres lie
     within ``radius`` cells of its centre, six tetrahedra each, nodes off the
