@@ -209,8 +209,9 @@ def progress(msg: str):
 CPU_BASELINE_MAX_DOFS = 20000
 # Newton's stopping tolerance of the oracle (relative to |M y / h^2|): 1e-13,
 # except on the 212 k-DoF block, whose round-off floor of grad g lies near
-# 3e-12 of that scale (the reference of its rollout uses 1e-11 too)
-NEWTON_TOL = {"c5": 1e-11}
+# 3e-12 of that scale, and the tetrahedral ball, whose contact steps stall
+# Newton near its floor (the references of their rollouts use 1e-11 too)
+NEWTON_TOL = {"c5": 1e-11, "tet": 1e-11}
 
 
 def cpu_baseline(scene, T_budget_s, newton_tol=1e-13):

@@ -15,14 +15,17 @@ With fewer steps than the scene's, the file holds the reference of that
 prefix of the rollout (the 64x32x32 block: the first 30 steps, through the
 landing; about an hour and a half on 8 host cores, where each Newton step and
 each adjoint solve runs conjugate gradients on the assembled Hessian to
-round-off, ``oracle.linsolve``).
+round-off, ``oracle.linsolve``; the tetrahedral ball: the first 30 of 100
+steps, landing at step 8 and bouncing, about 16 minutes).
 
 Newton stops at |grad g| <= tol |M y / h^2| (default 1e-13).  On the block,
 whose 212 k DoFs put the round-off floor of grad g near 3e-12 of that scale,
 the reference uses tol 1e-11 (position error about 1e-9 m; without it every
-step runs Newton into the floor, about six minutes a step).
+step runs Newton into the floor, about six minutes a step), and so does the
+tetrahedral ball (its contact steps stall Newton near the floor).
 
 usage: python tests/golden/make_rollout_reference.py c2 [steps] [newton_tol]
+       (c5 30 1e-11 and tet 30 1e-11 for the stored prefixes)
 """
 import os
 import sys
