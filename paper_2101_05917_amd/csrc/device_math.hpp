@@ -728,7 +728,28 @@ __device__ inline void node_force(const DevMesh& M, const double* __restrict__ f
   if (M.inc_ptr) {   // tetrahedra: [3][4E] corner forces, compressed incidence in (e, a) order
     const int64_t E4 = 4 * (int64_t)M.E;
     f0 = f1 = f2 = 0.0;
-    for (int k = M.inc_ptr[n]; k < M.inc_ptr[n + 1]; ++k) {
+    int k = M.inc_ptr[n];
+    const int k1 = M.inc_ptr[n + 1];
+    // four incidences' loads issued together, added in incidence order
+    for (; k + 3 < k1; k += 4) {
+      const int p0 = M.inc[k], p1 = M.inc[k + 1], p2 = M.inc[k + 2], p3 = M.inc[k + 3];
+      const double a0 = fe[p0], a1 = fe[p1], a2 = fe[p2], a3 = fe[p3];
+      const double b0 = fe[E4 + p0], b1 = fe[E4 + p1], b2 = fe[E4 + p2], b3 = fe[E4 + p3];
+      const double c0 = fe[2 * E4 + p0], c1 = fe[2 * E4 + p1], c2 = fe[2 * E4 + p2], c3 = fe[2 * E4 + p3];
+      f0 += a0;
+      f0 += a1;
+      f0 += a2;
+      f0 += a3;
+      f1 += b0;
+      f1 += b1;
+      f1 += b2;
+      f1 += b3;
+      f2 += c0;
+      f2 += c1;
+      f2 += c2;
+      f2 += c3;
+    }
+    for (; k < k1; ++k) {
       const int p = M.inc[k];
       f0 += fe[p];
       f1 += fe[E4 + p];

@@ -62,6 +62,8 @@ def _errors(ref, X, xT, gx, gv, gE, g_act):
 
 
 def _rest(sc):
+    if getattr(sc, "tets", None) is not None:
+        return np.asarray(sc.X, dtype=np.float64).reshape(-1)
     from oracle import discretization as od
     return od.VoxelMesh(sc.cells, sc.dx, sc.origin).X.reshape(-1)
 
@@ -157,5 +159,19 @@ def test_c5_prefix_rollout_at_bench_options():
     sc, xT, gx, gv, gE, ga = _run("c5", bench.solver_options(args), steps=T)
     e = _errors(ref, _rest(sc), xT, gx, gv, gE, ga)
     assert e["x_T"] <= 1e-6
+    for k in ("g_x0", "g_v0", "g_youngs"):
+        assert e[k] <= 1e-6, (k, e[k])
+
+
+def test_tet_ball_prefix_rollout_at_bench_options():
+    """The tetrahedral ball's first 30 steps (free fall, landing on the
+    penalty ground with friction, bounce) with bench.py's options, against the
+    oracle's reference of that prefix: gradients within 1e-6."""
+    args = bench.parse(["--config", "tet"])
+    ref = _reference("tet")
+    T = int(ref["steps"])
+    sc, xT, gx, gv, gE, ga = _run("tet", bench.solver_options(args), steps=T)
+    e = _errors(ref, _rest(sc), xT, gx, gv, gE, ga)
+    assert e["x_T"] <= 1e-8
     for k in ("g_x0", "g_v0", "g_youngs"):
         assert e[k] <= 1e-6, (k, e[k])
