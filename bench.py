@@ -89,6 +89,8 @@ def parse(argv=None):
                          "tree level (default: the library's)")
     ap.add_argument("--leaf-nodes", type=int, default=0,
                     help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
+    ap.add_argument("--factor-on-host", action="store_true",
+                    help="numeric factorization on the host (default: on the device)")
     ap.add_argument("--deflation", type=int, default=None,
                     help="adjoint CG deflated by this many Lanczos Ritz vectors (0: off)")
     ap.add_argument("--deflation-refresh", type=int, default=25,
@@ -159,6 +161,8 @@ def solver_options(args) -> dict:
         opts["sweep_launch"] = args.sweep_launch
     if args.leaf_nodes:
         opts["leaf_nodes"] = args.leaf_nodes
+    if getattr(args, "factor_on_host", False):
+        opts["factor_on_host"] = 1
     if args.deflation:
         opts["deflation"] = args.deflation
         opts["deflation_refresh"] = args.deflation_refresh
@@ -713,6 +717,10 @@ def main():
         "grad_rel_err_vs_oracle": err,
         "accuracy_gate": gate,
         "checkpointing": {"checkpoint_every": K, "check": ckpt_check},
+        "setup": {"factorize_ms": mesh.info["factor_us"] / 1e3,
+                  "factorization": "host" if args.factor_on_host else
+                  "device (multifrontal, FP64 MFMA on the dense fronts)",
+                  "supernodes": mesh.info["n_supernodes"], "levels": mesh.info["n_levels"]},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -137,7 +137,12 @@ typedef struct {
   int32_t deflation_refresh;  /* backward steps between rebuilds of those vectors
                               (0 = 25); the Hessian's products with them are
                               recomputed every step                            */
-  int32_t pad_opt;
+  int32_t factor_on_host;  /* 0 (default): dpd_factorize runs the multifrontal
+                              Cholesky on the device (dense fronts, FP64 MFMA
+                              updates; a transient workspace of sum ld^2 doubles
+                              over the supernodes is allocated and freed by the
+                              call); 1: on the host (C++ with OpenMP), the
+                              panels then uploaded.  Same factor to rounding   */
 } dpd_options;
 
 typedef struct {
@@ -169,6 +174,8 @@ typedef struct {
   int64_t solve_entries;   /* entries of its queue (both sweeps)                 */
   int64_t qp_per_element;  /* 8 (voxels, 2x2x2 Gauss points) or 1 (tetrahedra):
                               per-quadrature-point arrays hold this x n_elements */
+  int64_t factor_us;       /* wall time of the last dpd_factorize (microseconds,
+                              including the FP32 copies; 0 before the first)    */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),
@@ -239,9 +246,11 @@ dpd_status dpd_set_youngs(dpd_mesh* mesh, const double* youngs, int32_t on_devic
 
 /* Numeric Cholesky factorization of A, computed once per material
  * (Sec. Background: the factorization of the constant matrix A can be
- * precomputed).  Builds the FP64 panels (and FP32 copies when precision is
- * DPD_MIXED) and uploads them.  Synchronizes the stream.  DPD_ENOTSPD on a
- * non-positive pivot. */
+ * precomputed).  Builds the FP64 panels of the sweeps (and FP32 copies when
+ * precision is DPD_MIXED): on the device by default (multifrontal, level by
+ * level, FP64 MFMA on the dense fronts; see dpd_options.factor_on_host).
+ * Synchronizes the stream.  DPD_ENOTSPD on a non-positive (or non-finite)
+ * pivot, DPD_ENOMEM if the transient front workspace cannot be allocated. */
 dpd_status dpd_factorize(dpd_mesh* mesh, void* stream);
 
 /* One implicit-Euler step (eq:time_integration):

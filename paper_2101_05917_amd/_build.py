@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdiffpd.so")
 SOURCES = ["host_mesh.cpp", "factor.cpp", "kernels.hip", "sweeps.hip", "cg_dense.hip", "contact.hip", "contact_fused.hip", "api.hip",
-           "batch.hip", "tets.hip", "server.cpp"]
+           "batch.hip", "tets.hip", "factor_gpu.hip", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

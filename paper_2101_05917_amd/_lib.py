@@ -35,7 +35,7 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("check_every", C.c_int32), ("use_graphs", C.c_int32),
         ("fused_cg", C.c_int32), ("contact_fused", C.c_int32), ("sweep_launch", C.c_int32),
         ("volume_scale", C.c_double), ("leaf_nodes", C.c_int32), ("deflation", C.c_int32),
-        ("deflation_refresh", C.c_int32), ("pad_opt", C.c_int32),
+        ("deflation_refresh", C.c_int32), ("factor_on_host", C.c_int32),
     ]
 
 
@@ -54,7 +54,7 @@ class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
         "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds",
-        "solve_workgroups", "solve_entries", "qp_per_element")]
+        "solve_workgroups", "solve_entries", "qp_per_element", "factor_us")]
 
 
 class KernelProfile(C.Structure):

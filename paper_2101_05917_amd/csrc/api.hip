@@ -266,7 +266,8 @@ std::vector<double> volume_weights(const HostMesh& hm, const dpd_options& o) {
 int cache_rows(const dpd_options& o) { return o.volume_scale > 0.0 ? kAdjCacheRowsVolume : kAdjCacheRows; }
 
 // FP32 copies (column-major and row-major) of the FP64 panels.
-dpd_status make_fp32_panels(dpd_mesh* m, const std::vector<double>& panels, hipStream_t s) {
+// FP32 copies of both panel layouts, converted on the device.
+dpd_status make_fp32_panels(dpd_mesh* m, hipStream_t s) {
   if (!m->panel32) {
     dpd_status st = dev_alloc(m, &m->panel32, m->S.panel_size);
     if (st != DPD_OK) return st;
@@ -275,14 +276,60 @@ dpd_status make_fp32_panels(dpd_mesh* m, const std::vector<double>& panels, hipS
     dpd_status st = dev_alloc(m, &m->panelT32, m->S.panel_size);
     if (st != DPD_OK) return st;
   }
-  const std::vector<float> f(panels.begin(), panels.end());
-  const std::vector<float> ft = transpose_panels<float>(m->S, panels);
-  HIPCHECK(m, hipMemcpyAsync(m->panel32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
-  HIPCHECK(m, hipMemcpyAsync(m->panelT32, ft.data(), ft.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  launch_to_fp32(s, m->S.panel_size, m->panel64, m->panel32);
+  launch_to_fp32(s, m->S.panel_size, m->panelT64, m->panelT32);
+  HIPCHECK(m, hipGetLastError());
   HIPCHECK(m, hipStreamSynchronize(s));
   m->ds.panel32 = m->panel32;
   m->ds.panelT32 = m->panelT32;
   m->have_fp32 = true;
+  return DPD_OK;
+}
+
+// Multifrontal Cholesky on the device (factor_gpu.hip): A's entries scattered
+// into zeroed fronts, then the plan's launches level by level, then the
+// row-major panel copy.  The fronts live in a workspace allocated for the call.
+dpd_status factor_on_device(dpd_mesh* m, hipStream_t s) {
+  if (!m->fplan_ready) {
+    const std::string e = build_factor_plan(m->S, m->A, m->fplan);
+    if (!e.empty()) return fail(m, DPD_EINVAL, "device factorization plan: " + e);
+    const FactorPlan& P = m->fplan;
+    dpd_status st;
+    if ((st = upload(m, &m->d_fronts, P.fronts)) != DPD_OK) return st;
+    if ((st = upload(m, &m->d_adst, P.a_dst)) != DPD_OK) return st;
+    if ((st = upload(m, &m->d_asrc, P.a_src)) != DPD_OK) return st;
+    if ((st = upload(m, &m->d_relmap, P.relmap)) != DPD_OK) return st;
+    if ((st = upload(m, &m->d_fints, P.ints)) != DPD_OK) return st;
+    if ((st = upload(m, &m->d_snode_of, m->S.snode_of)) != DPD_OK) return st;
+    if ((st = dev_alloc(m, &m->d_aval, (int64_t)m->A.val.size())) != DPD_OK) return st;
+    if ((st = dev_alloc(m, &m->d_fstatus, 1)) != DPD_OK) return st;
+    m->fplan_ready = true;
+  }
+  const FactorPlan& P = m->fplan;
+  HIPCHECK(m, hipMemcpyAsync(m->d_aval, m->A.val.data(), m->A.val.size() * sizeof(double), hipMemcpyHostToDevice,
+                             s));
+  double* F = nullptr;
+  if (hipMalloc(&F, (size_t)std::max<int64_t>(1, P.front_size) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(m, DPD_ENOMEM,
+                "hipMalloc of the factorization workspace (" + std::to_string(P.front_size * 8) + " bytes) failed");
+  }
+  HIPCHECK(m, hipMemsetAsync(m->d_fstatus, 0, sizeof(int32_t), s));
+  launch_fill(s, P.front_size, F, 0.0);
+  launch_fill(s, m->S.panel_size, m->panel64, 0.0);
+  launch_factor_identity(s, m->d_fronts, m->d_snode_of, m->S.n, m->panel64);
+  launch_factor_scatter(s, m->d_adst, m->d_asrc, m->d_aval, (int64_t)P.a_dst.size(), F);
+  for (const FactorOp& op : P.ops)
+    launch_factor_op(s, op, m->d_fronts, m->d_fints, m->d_relmap, F, m->panel64, m->d_fstatus);
+  launch_factor_transpose(s, m->d_fronts, (int)P.fronts.size(), m->S.panel_size, m->panel64, m->panelT64);
+  const hipError_t le = hipGetLastError();
+  const hipError_t se = hipStreamSynchronize(s);
+  (void)hipFree(F);
+  if (le != hipSuccess || se != hipSuccess)
+    return fail(m, DPD_EHIP, std::string("device factorization: ") + hipGetErrorString(le != hipSuccess ? le : se));
+  int32_t status = 0;
+  HIPCHECK(m, hipMemcpy(&status, m->d_fstatus, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (status) return fail(m, DPD_ENOTSPD, "non-positive pivot in the device factorization");
   return DPD_OK;
 }
 
@@ -818,6 +865,7 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->n_levels = m->S.n_levels;
   info->factor_nnz = m->S.packed_nnz;
   info->factor_bytes = 2 * m->S.panel_size * (int64_t)sizeof(double);
+  info->factor_us = (int64_t)(m->factor_ms * 1e3);
   info->device_bytes = m->device_bytes;
   info->leaf_nodes = m->leaf_max;
   info->fused_blocks = m->opt.fused_cg ? m->dense_blocks : 0;
@@ -862,9 +910,7 @@ dpd_status dpd_set_options(dpd_mesh* m, const dpd_options* o) {
   if (m->opt.check_every < 1) m->opt.check_every = 1;
   m->dm.local32 = m->opt.precision == DPD_MIXED ? 1 : 0;
   if (need32 && m->factored) {
-    std::vector<double> tmp(m->S.panel_size);
-    HIPCHECK(m, hipMemcpy(tmp.data(), m->panel64, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
-    dpd_status st = make_fp32_panels(m, tmp, nullptr);
+    dpd_status st = make_fp32_panels(m, nullptr);
     if (st != DPD_OK) return st;
     if ((st = dense_fp32(m, nullptr)) != DPD_OK) return st;
   }
@@ -900,11 +946,10 @@ dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
     m->contact_n = 0;
     m->contact_cached.clear();
     m->contact_red_ok = false;
+    m->factored = false;
   }
   if (!m) return fail(nullptr, DPD_EINVAL, "null mesh");
-  std::vector<double> panels;
-  std::string e;
-  if (!factor_panels(m->S, m->A, panels, e)) return fail(m, DPD_ENOTSPD, e);
+  const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = (hipStream_t)stream;
   if (!m->panel64) {
     dpd_status st = dev_alloc(m, &m->panel64, m->S.panel_size);
@@ -914,18 +959,27 @@ dpd_status dpd_factorize(dpd_mesh* m, void* stream) {
     dpd_status st = dev_alloc(m, &m->panelT64, m->S.panel_size);
     if (st != DPD_OK) return st;
   }
-  HIPCHECK(m, hipMemcpyAsync(m->panel64, panels.data(), panels.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s));
-  const std::vector<double> pt = transpose_panels<double>(m->S, panels);
-  HIPCHECK(m, hipMemcpyAsync(m->panelT64, pt.data(), pt.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHECK(m, hipStreamSynchronize(s));
+  if (m->opt.factor_on_host) {
+    std::vector<double> panels;
+    std::string e;
+    if (!factor_panels(m->S, m->A, panels, e)) return fail(m, DPD_ENOTSPD, e);
+    HIPCHECK(m, hipMemcpyAsync(m->panel64, panels.data(), panels.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+    const std::vector<double> pt = transpose_panels<double>(m->S, panels);
+    HIPCHECK(m, hipMemcpyAsync(m->panelT64, pt.data(), pt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+  } else {
+    dpd_status st = factor_on_device(m, s);
+    if (st != DPD_OK) return st;
+  }
   m->ds.panel64 = m->panel64;
   m->ds.panelT64 = m->panelT64;
   if (m->opt.precision == DPD_MIXED || m->have_fp32) {
-    dpd_status st = make_fp32_panels(m, panels, s);
+    dpd_status st = make_fp32_panels(m, s);
     if (st != DPD_OK) return st;
   }
   HIPCHECK(m, hipStreamSynchronize(s));
+  m->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   {
     dpd_status st = setup_dense(m, s);
     if (st != DPD_OK) return st;

@@ -327,4 +327,12 @@ void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, d
 void launch_collect_rows(hipStream_t s, int N, int n, const int32_t* perm, int j0, const double* x,
                          double* ainv);
 void launch_to_fp32(hipStream_t s, int64_t count, const double* in, float* out);
+// device factorization (factor_gpu.hip)
+void launch_factor_scatter(hipStream_t s, const int64_t* dst, const int32_t* src, const double* aval, int64_t n,
+                           double* F);
+void launch_factor_identity(hipStream_t s, const FrontDesc* fd, const int32_t* snode_of, int32_t n, double* P);
+void launch_factor_op(hipStream_t s, const FactorOp& op, const FrontDesc* fd, const int32_t* ints,
+                      const int32_t* relmap, double* F, double* P, int32_t* status);
+void launch_factor_transpose(hipStream_t s, const FrontDesc* fd, int ns, int64_t total, const double* P,
+                             double* out);
 }  // namespace dpd

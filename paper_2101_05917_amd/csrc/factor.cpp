@@ -582,4 +582,131 @@ void build_dag(const Symbolic& S, const LevelPlan& P, int64_t lds_budget_bytes, 
   if (lds > lds_budget_bytes) D.usable = false;
 }
 
+std::string build_factor_plan(const Symbolic& S, const Csr& A, FactorPlan& P) {
+  const int32_t ns = (int32_t)S.sn.size();
+  P = FactorPlan{};
+  P.fronts.resize(ns);
+  int64_t off = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    const Supernode& sn = S.sn[s];
+    FrontDesc& f = P.fronts[s];
+    f.front_off = off;
+    f.panel_off = sn.panel_off;
+    f.rows_off = sn.rows_off;
+    f.ld = sn.ncols + sn.nrows;
+    f.nc = sn.ncols;
+    f.nrows = sn.nrows;
+    f.parent = sn.parent;
+    f.col0 = sn.col0;
+    off += (int64_t)f.ld * f.ld;
+    const double n = sn.ncols, r = sn.nrows;
+    P.flops += n * n * n / 3.0 + n * n * r + n * r * r + n * n * n / 3.0 + r * n * n;
+  }
+  P.front_size = off;
+  // entries of A on or below the diagonal of each supernode's columns
+  std::vector<int32_t> loc(S.n, -1);
+  for (int32_t s = 0; s < ns; ++s) {
+    const Supernode& sn = S.sn[s];
+    const FrontDesc& f = P.fronts[s];
+    for (int32_t j = 0; j < sn.ncols; ++j) loc[sn.col0 + j] = j;
+    for (int32_t p = 0; p < sn.nrows; ++p) loc[S.rows[sn.rows_off + p]] = sn.ncols + p;
+    for (int32_t j = sn.col0; j < sn.col0 + sn.ncols; ++j) {
+      const int32_t fr = S.perm[j];
+      for (int64_t k = A.ptr[fr]; k < A.ptr[fr + 1]; ++k) {
+        const int32_t i = S.iperm[A.col[k]];
+        if (i < j) continue;
+        const int32_t li = loc[i];
+        if (li < 0 || li >= f.ld) return "entry of A outside its supernode's front";
+        P.a_dst.push_back(f.front_off + (int64_t)loc[j] * f.ld + li);
+        P.a_src.push_back((int32_t)k);
+      }
+    }
+    // the rows of s's children in s's front
+    for (int32_t ch : S.children[s]) {
+      const Supernode& cs = S.sn[ch];
+      for (int32_t p = 0; p < cs.nrows; ++p) {
+        const int32_t li = loc[S.rows[cs.rows_off + p]];
+        if (li < 0 || li >= f.ld) return "child row outside its parent's front";
+        if (P.relmap.size() < S.rows.size()) P.relmap.resize(S.rows.size(), -1);
+        P.relmap[cs.rows_off + p] = li;
+      }
+    }
+    for (int32_t j = 0; j < sn.ncols; ++j) loc[sn.col0 + j] = -1;
+    for (int32_t p = 0; p < sn.nrows; ++p) loc[S.rows[sn.rows_off + p]] = -1;
+  }
+  P.relmap.resize(S.rows.size(), -1);
+  for (int32_t s = 0; s < ns; ++s)
+    if (S.sn[s].parent >= 0)
+      for (int32_t p = 0; p < S.sn[s].nrows; ++p)
+        if (P.relmap[S.sn[s].rows_off + p] < 0) return "child row without a position in its parent";
+
+  auto add_op = [&](int32_t kind, int32_t level, int32_t k0, const std::vector<int32_t>& items,
+                    const std::vector<int64_t>& blocks) {
+    FactorOp op{};
+    op.kind = kind;
+    op.level = level;
+    op.k0 = k0;
+    op.n = (int32_t)items.size();
+    op.list_off = (int32_t)P.ints.size();
+    P.ints.insert(P.ints.end(), items.begin(), items.end());
+    int64_t acc = 0;
+    P.ints.push_back(0);
+    for (int64_t b : blocks) {
+      acc += b;
+      P.ints.push_back((int32_t)acc);
+    }
+    op.blocks = (int32_t)acc;
+    if (acc > 0) P.ops.push_back(op);
+    return acc < (int64_t)1 << 30;
+  };
+  const int64_t TT = kFactorTile, NB = kFactorNB;
+  for (int32_t l = 0; l < S.n_levels; ++l) {
+    std::vector<int32_t> lev;
+    int32_t max_nc = 0;
+    size_t max_ch = 0;
+    for (int32_t s = 0; s < ns; ++s)
+      if (S.sn[s].level == l) {
+        lev.push_back(s);
+        max_nc = std::max(max_nc, S.sn[s].ncols);
+        max_ch = std::max(max_ch, S.children[s].size());
+      }
+    // extend-add, one launch per sibling rank (fronts of one launch are distinct)
+    for (size_t c = 0; c < max_ch; ++c) {
+      std::vector<int32_t> items;
+      std::vector<int64_t> blocks;
+      for (int32_t s : lev)
+        if (S.children[s].size() > c) {
+          const int32_t ch = S.children[s][c];
+          if (S.sn[ch].nrows <= 0) return "child without rows";
+          items.push_back(ch);
+          blocks.push_back((S.sn[ch].nrows + 3) / 4);
+        }
+      if (!add_op(kFactorExtend, l, 0, items, blocks)) return "extend-add launch too large";
+    }
+    for (int32_t k0 = 0; k0 < max_nc; k0 += (int32_t)NB) {
+      std::vector<int32_t> i1, i2;
+      std::vector<int64_t> b1, b2;
+      for (int32_t s : lev) {
+        const FrontDesc& f = P.fronts[s];
+        if (f.nc <= k0) continue;
+        const int64_t kb = std::min<int64_t>(NB, f.nc - k0), k1 = k0 + kb, m = f.ld - k1;
+        i1.push_back(s);
+        b1.push_back((m + 255) / 256 + (k1 + 255) / 256);
+        if (m > 0) {
+          const int64_t T = (m + TT - 1) / TT;
+          i2.push_back(s);
+          b2.push_back(T * (T + 1) / 2 + T * ((k1 + TT - 1) / TT));
+        }
+      }
+      if (!add_op(kFactorPanel, l, k0, i1, b1)) return "panel launch too large";
+      if (!add_op(kFactorUpdate, l, k0, i2, b2)) return "update launch too large";
+    }
+  }
+  for (int64_t d : P.a_dst)
+    if (d < 0 || d >= P.front_size) return "front position out of range";
+  for (int32_t k : P.a_src)
+    if (k < 0 || k >= (int64_t)A.val.size()) return "entry index out of range";
+  return "";
+}
+
 }  // namespace dpd

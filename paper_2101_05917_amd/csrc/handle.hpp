@@ -63,6 +63,18 @@ struct dpd_mesh {
   hipStream_t capture_stream = nullptr;
   double* w_e = nullptr;
   double* wv_e = nullptr;                         // volume-preserving weights (null: term off)
+  // device factorization: plan (built on first use) and its device copies
+  dpd::FactorPlan fplan;
+  bool fplan_ready = false;
+  dpd::FrontDesc* d_fronts = nullptr;
+  int64_t* d_adst = nullptr;
+  int32_t* d_asrc = nullptr;
+  int32_t* d_relmap = nullptr;
+  int32_t* d_fints = nullptr;
+  int32_t* d_snode_of = nullptr;
+  double* d_aval = nullptr;
+  int32_t* d_fstatus = nullptr;
+  double factor_ms = 0.0;                         // wall time of the last dpd_factorize
   double* panel64 = nullptr;
   float* panel32 = nullptr;
   double* panelT64 = nullptr;

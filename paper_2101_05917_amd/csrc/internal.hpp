@@ -192,6 +192,49 @@ bool factor_panels(const Symbolic& S, const Csr& A, std::vector<double>& panels,
 
 void build_plan(const Symbolic& S, LevelPlan& P);
 
+// Multifrontal factorization on the device.  Every supernode s owns a dense
+// front F_s (ld x ld, column-major, lower triangle used; ld = ncols + nrows)
+// in one workspace: the entries of A in its columns, plus the Schur
+// complements of its children (extend-add).  Levels run in ascending order
+// (children first); within a level all fronts advance together, one block
+// column of kFactorNB at a time, right-looking:
+//   panel op:  Cholesky of the diagonal block, the rows below it solved
+//              against it (L_{below,k}), and block row k of the panel
+//              X = M^{-1}[I; 0] solved (M = [L11 0; L21 I]);
+//   update op: trailing lower triangle F_{>k,>k} -= L_{>k,k} L_{>k,k}^T and
+//              X_{>k,<=k} -= L_{>k,k} X_{k,<=k} (FP64 MFMA tiles of 64 x 64).
+// After the last block column X holds [inv(L11); -L21 inv(L11)], the panel
+// of the sweeps, and F_s's trailing block the update for the parent.
+constexpr int kFactorNB = 32;     // block-column width
+constexpr int kFactorTile = 64;   // output tile of the update op
+struct FrontDesc {
+  int64_t front_off;   // into the front workspace (doubles)
+  int64_t panel_off;   // into the panel array
+  int64_t rows_off;    // into Symbolic::rows (and the parent-position map)
+  int32_t ld, nc, nrows, parent, col0, pad;
+};
+static_assert(sizeof(FrontDesc) == 48, "device layout");
+enum FactorOpKind : int32_t { kFactorExtend = 0, kFactorPanel = 1, kFactorUpdate = 2 };
+// One launch: n items (supernodes; for extend-add the children of the level's
+// fronts with a given sibling rank) at ints[list_off ...], then their
+// workgroup prefix sums (n + 1 entries, the last = blocks).
+struct FactorOp {
+  int32_t kind, k0, n, list_off, blocks, level;
+};
+struct FactorPlan {
+  std::vector<FrontDesc> fronts;       // per supernode
+  int64_t front_size = 0;              // doubles of the workspace
+  std::vector<int64_t> a_dst;          // lower entries of A: position in the fronts
+  std::vector<int32_t> a_src;          //   and index into Csr::val
+  std::vector<int32_t> relmap;         // per Symbolic::rows entry: its position in the parent's front
+  std::vector<int32_t> ints;           // item lists and prefix sums of the ops
+  std::vector<FactorOp> ops;           // in launch order
+  double flops = 0.0;                  // of the dense work (Cholesky, updates, panel)
+};
+// Builds the plan and checks every index it holds against its buffer; returns
+// an error message if one is out of range (nothing is launched then).
+std::string build_factor_plan(const Symbolic& S, const Csr& A, FactorPlan& P);
+
 // Row-major copy of every panel (same offsets): element (r, c) of supernode s
 // at panel_off + r * ncols + c.
 template <typename T>

@@ -9,6 +9,7 @@
 //
 // usage: host_check <input.bin> <output.bin>
 #include <algorithm>
+#include <cmath>
 #include <cassert>
 #include <cstdio>
 #include <cstdlib>
@@ -35,6 +36,166 @@ static void rd(FILE* f, T* p, size_t n) {
 template <typename T>
 static void wr(FILE* f, const T* p, size_t n) {
   if (n) std::fwrite(p, sizeof(T), n, f);
+}
+
+static int find_item_h(const int32_t* prefix, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Replay of the device factorization (factor_gpu.hip) on the CPU, workgroup
+// by workgroup and lane by lane with the kernels' index arithmetic and a
+// bounds check on every access; returns the panels it produces.
+static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A, const FactorPlan& FP) {
+  const int NB = kFactorNB, TT = kFactorTile, TH = 256;
+  std::vector<double> F(FP.front_size, 0.0), P(S.panel_size, 0.0);
+  const int ns = (int)FP.fronts.size();
+  for (int c = 0; c < S.n; ++c) {
+    const int s = S.snode_of[c];
+    CHECK(s >= 0 && s < ns);
+    const FrontDesc f = FP.fronts[s];
+    const int j = c - f.col0;
+    CHECK(j >= 0 && j < f.nc);
+    const int64_t idx = f.panel_off + (int64_t)j * f.ld + j;
+    CHECK(idx >= 0 && idx < S.panel_size);
+    P[idx] = 1.0;
+  }
+  CHECK(FP.a_dst.size() == FP.a_src.size());
+  for (size_t i = 0; i < FP.a_dst.size(); ++i) {
+    CHECK(FP.a_dst[i] >= 0 && FP.a_dst[i] < FP.front_size);
+    CHECK(FP.a_src[i] >= 0 && FP.a_src[i] < (int32_t)A.val.size());
+    F[FP.a_dst[i]] = A.val[FP.a_src[i]];
+  }
+  auto fidx = [&](const FrontDesc& f, int64_t r, int64_t c) {
+    CHECK(r >= 0 && r < f.ld && c >= 0 && c < f.ld);
+    const int64_t i = f.front_off + r + c * f.ld;
+    CHECK(i >= 0 && i < FP.front_size);
+    return i;
+  };
+  auto pidx = [&](const FrontDesc& f, int64_t r, int64_t c) {
+    CHECK(r >= 0 && r < f.ld && c >= 0 && c < f.nc);
+    const int64_t i = f.panel_off + r + c * f.ld;
+    CHECK(i >= 0 && i < S.panel_size);
+    return i;
+  };
+  for (const FactorOp& op : FP.ops) {
+    CHECK(op.n > 0 && op.list_off >= 0 && (size_t)op.list_off + 2 * op.n + 1 <= FP.ints.size());
+    const int32_t* items = &FP.ints[op.list_off];
+    const int32_t* pre = items + op.n;
+    CHECK(pre[0] == 0 && pre[op.n] == op.blocks);
+    for (int b = 0; b < op.blocks; ++b) {
+      const int it = find_item_h(pre, op.n, b);
+      CHECK(pre[it] <= b && b < pre[it + 1]);
+      CHECK(items[it] >= 0 && items[it] < ns);
+      const FrontDesc f = FP.fronts[items[it]];
+      const int local = b - pre[it];
+      if (op.kind == kFactorExtend) {
+        CHECK(f.parent >= 0 && f.parent < ns);
+        const FrontDesc pa = FP.fronts[f.parent];
+        for (int w = 0; w < TH / 64; ++w) {
+          const int q = local * (TH / 64) + w;
+          if (q >= f.nrows) continue;
+          CHECK(f.rows_off + q < (int64_t)FP.relmap.size());
+          const int rq = FP.relmap[f.rows_off + q];
+          for (int p = q; p < f.nrows; ++p) {
+            const int rp = FP.relmap[f.rows_off + p];
+            CHECK(rp >= rq);
+            F[fidx(pa, rp, rq)] += F[fidx(f, f.nc + p, f.nc + q)];
+          }
+        }
+      } else if (op.kind == kFactorPanel) {
+        const int kb = std::min(NB, f.nc - op.k0), k0 = op.k0, k1 = k0 + kb;
+        CHECK(kb > 0);
+        const int rows_chunks = (f.ld - k1 + TH - 1) / TH;
+        double D[32][33], Li[32][33];
+        for (int i = 0; i < NB; ++i)
+          for (int j = 0; j < NB; ++j) {
+            D[i][j] = (i < kb && j <= i) ? F[fidx(f, k0 + i, k0 + j)] : (i == j ? 1.0 : 0.0);
+            Li[i][j] = 0.0;
+          }
+        for (int j = 0; j < kb; ++j) {
+          CHECK(D[j][j] > 0.0);
+          const double sd = std::sqrt(D[j][j]);
+          for (int i = j; i < kb; ++i) D[i][j] = (i == j) ? sd : D[i][j] / sd;
+          for (int t = j + 1; t < kb; ++t)
+            for (int i = t; i < kb; ++i) D[i][t] -= D[i][j] * D[t][j];
+        }
+        for (int j = 0; j < kb; ++j) {
+          Li[j][j] = 1.0 / D[j][j];
+          for (int i = j + 1; i < kb; ++i) {
+            double v = 0.0;
+            for (int t = j; t < i; ++t) v += D[i][t] * Li[t][j];
+            Li[i][j] = -v / D[i][i];
+          }
+        }
+        for (int tid = 0; tid < TH; ++tid) {
+          double x[32];
+          std::vector<int64_t> at(kb);
+          if (local < rows_chunks) {
+            const int i = k1 + local * TH + tid;
+            if (i >= f.ld) continue;
+            for (int t = 0; t < kb; ++t) at[t] = fidx(f, i, k0 + t);
+            for (int t = 0; t < NB; ++t) x[t] = t < kb ? F[at[t]] : 0.0;
+            for (int j = 0; j < kb; ++j) {
+              double sum = 0.0;
+              for (int t = 0; t < NB; ++t) sum += Li[j][t] * x[t];
+              F[at[j]] = sum;
+            }
+          } else {
+            const int c = (local - rows_chunks) * TH + tid;
+            CHECK(local - rows_chunks < (k1 + TH - 1) / TH);
+            if (c >= k1) continue;
+            for (int t = 0; t < kb; ++t) at[t] = pidx(f, k0 + t, c);
+            for (int t = 0; t < NB; ++t) x[t] = t < kb ? P[at[t]] : 0.0;
+            for (int j = 0; j < kb; ++j) {
+              double sum = 0.0;
+              for (int t = 0; t < NB; ++t) sum += Li[j][t] * x[t];
+              P[at[j]] = sum;
+            }
+          }
+        }
+      } else {
+        CHECK(op.kind == kFactorUpdate);
+        const int kb = std::min(NB, f.nc - op.k0), k0 = op.k0, k1 = k0 + kb, m = f.ld - k1;
+        CHECK(kb > 0 && m > 0);
+        const int T = (m + TT - 1) / TT, nsy = T * (T + 1) / 2, tc = (k1 + TT - 1) / TT;
+        CHECK(local < nsy + T * tc);
+        const bool syrk = local < nsy;
+        int ti, tj;
+        if (syrk) {
+          ti = (int)((std::sqrt(8.0 * local + 1.0) - 1.0) * 0.5);
+          while ((ti + 1) * (ti + 2) / 2 <= local) ++ti;
+          while (ti * (ti + 1) / 2 > local) --ti;
+          tj = local - ti * (ti + 1) / 2;
+          CHECK(tj >= 0 && tj <= ti && ti < T);
+        } else {
+          ti = (local - nsy) / tc;
+          tj = (local - nsy) % tc;
+          CHECK(ti < T && tj < tc);
+        }
+        for (int p = 0; p < TT; ++p)
+          for (int q = 0; q < TT; ++q) {
+            const int gp = ti * TT + p, gq = tj * TT + q;
+            if (gp >= m) continue;
+            if (syrk ? (gq > gp) : (gq >= k1)) continue;
+            double acc = 0.0;
+            for (int t = 0; t < kb; ++t) {
+              const double xv = F[fidx(f, k1 + gp, k0 + t)];
+              const double yv = syrk ? F[fidx(f, k1 + gq, k0 + t)] : P[pidx(f, k0 + t, gq)];
+              acc += xv * yv;
+            }
+            if (syrk) F[fidx(f, k1 + gp, k1 + gq)] -= acc;
+            else P[pidx(f, k1 + gp, gq)] -= acc;
+          }
+      }
+    }
+  }
+  return P;
 }
 
 int main(int argc, char** argv) {
@@ -83,6 +244,25 @@ int main(int argc, char** argv) {
     return 5;
   }
   CHECK((int64_t)panel.size() == S.panel_size);
+  {
+    // the device factorization's plan and arithmetic, replayed: the same panels
+    // to rounding; the sweeps below then run on the replayed panels
+    FactorPlan FP;
+    const std::string perr = build_factor_plan(S, A, FP);
+    if (!perr.empty()) {
+      std::fprintf(stderr, "factor plan: %s\n", perr.c_str());
+      return 6;
+    }
+    const std::vector<double> dev = replay_device_factor(S, A, FP);
+    double dmax = 0.0, pmax = 0.0;
+    for (int64_t i = 0; i < S.panel_size; ++i) {
+      dmax = std::max(dmax, std::abs(dev[i] - panel[i]));
+      pmax = std::max(pmax, std::abs(panel[i]));
+    }
+    if (std::getenv("HOST_CHECK_LEVELS")) std::fprintf(stderr, "device-factor replay: max |diff| %.3e of %.3e\n", dmax, pmax);
+    CHECK(dmax <= 1e-11 * pmax);
+    panel = dev;
+  }
   // structural checks of the plan
   for (const SweepTask& t : P.fwd) {
     CHECK(t.sn >= 0 && t.sn < (int32_t)S.sn.size());
