@@ -89,6 +89,9 @@ def parse(argv=None):
                          "tree level (default: the library's)")
     ap.add_argument("--leaf-nodes", type=int, default=0,
                     help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
+    ap.add_argument("--factorize-only", type=int, default=0,
+                    help="time this many numeric factorizations of the workload's A and report them "
+                         "(no rollouts)")
     ap.add_argument("--factor-on-host", action="store_true",
                     help="numeric factorization on the host (default: on the device)")
     ap.add_argument("--deflation", type=int, default=None,
@@ -549,6 +552,30 @@ def measured_traffic(workload: str, kernel: str, precision: str, iters_per_launc
     return per * iters_per_launch if rec.get("per") == "iteration" else per
 
 
+def factorize_bench(args, mesh, scene, torch):
+    """Numeric factorization of the workload's A, repeated (the one-time set-up
+    of Sec. Background), timed by wall clock around each synchronous
+    dpd_factorize; its floating-point work against the FP64 matrix peak."""
+    times = []
+    for k in range(args.factorize_only):
+        progress(f"factorization {k + 1}/{args.factorize_only}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh.factorize()
+        times.append(time.perf_counter() - t0)
+    best, mean = min(times), sum(times) / len(times)
+    flops = mesh.info["factor_flops"]
+    return {"metric": "numeric factorization time", "value": mean * 1e3, "unit": "ms",
+            "higher_is_better": False, "best_ms": best * 1e3, "repeats": len(times),
+            "where": "host" if args.factor_on_host else "device",
+            "config": {"workload": f"{scene.name}: {mesh.info['n_free']} free nodes, "
+                                   f"{mesh.info['n_supernodes']} supernodes, {mesh.info['n_levels']} levels",
+                       "leaf_nodes": mesh.info["leaf_nodes"]},
+            "flops": flops, "achieved_tflops": flops / mean / 1e12,
+            "peak_tflops": 78.6, "frac": flops / mean / 1e12 / 78.6,
+            "dtype": "f64"}
+
+
 def copy_calibration(nbytes: int):
     """A plain device copy of nbytes (read nbytes, write nbytes), for scaling
     the FETCH_SIZE / WRITE_SIZE hardware counters to bytes."""
@@ -584,6 +611,10 @@ def main():
     T = args.rollout_steps or scene.steps
     progress(f"{scene.name}: mesh set-up and factorization")
     mesh = Mesh.from_scene(scene, **solver_options(args))
+    if args.factorize_only:
+        print(json.dumps(factorize_bench(args, mesh, scene, torch)), flush=True)
+        mesh.close()
+        return
     if args.contact_set:
         print(json.dumps(contact_bench(args, mesh, scene, torch)), flush=True)
         return

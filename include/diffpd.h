@@ -176,6 +176,10 @@ typedef struct {
                               per-quadrature-point arrays hold this x n_elements */
   int64_t factor_us;       /* wall time of the last dpd_factorize (microseconds,
                               including the FP32 copies; 0 before the first)    */
+  int64_t factor_flops;    /* floating-point operations of the numeric
+                              factorization and panel construction: per
+                              supernode 2n^3/3 + 2rn^2 + r^2 n (n columns,
+                              r rows below)                                      */
 } dpd_mesh_info;
 
 /* Default options: dx 0.01, rho 1e3, nu 0.45, h 0.01, gravity (0,0,-9.81),

@@ -54,7 +54,7 @@ class MeshInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_nodes", "n_elements", "n_free", "n_fixed", "n_contact", "n_supernodes", "n_levels",
         "factor_nnz", "factor_bytes", "device_bytes", "leaf_nodes", "fused_blocks", "fused_lds",
-        "solve_workgroups", "solve_entries", "qp_per_element", "factor_us")]
+        "solve_workgroups", "solve_entries", "qp_per_element", "factor_us", "factor_flops")]
 
 
 class KernelProfile(C.Structure):

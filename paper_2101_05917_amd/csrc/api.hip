@@ -321,7 +321,7 @@ dpd_status factor_on_device(dpd_mesh* m, hipStream_t s) {
   launch_factor_scatter(s, m->d_adst, m->d_asrc, m->d_aval, (int64_t)P.a_dst.size(), F);
   for (const FactorOp& op : P.ops)
     launch_factor_op(s, op, m->d_fronts, m->d_fints, m->d_relmap, F, m->panel64, m->d_fstatus);
-  launch_factor_transpose(s, m->d_fronts, (int)P.fronts.size(), m->S.panel_size, m->panel64, m->panelT64);
+  launch_factor_transpose(s, P.transpose, m->d_fronts, m->d_fints, m->panel64, m->panelT64);
   const hipError_t le = hipGetLastError();
   const hipError_t se = hipStreamSynchronize(s);
   (void)hipFree(F);
@@ -858,6 +858,12 @@ dpd_status dpd_get_info(const dpd_mesh* m, dpd_mesh_info* info) {
   info->n_nodes = m->hm.n_nodes;
   info->n_elements = m->hm.n_elems;
   info->qp_per_element = m->hm.corners == 4 ? 1 : 8;
+  double fl = 0.0;
+  for (const Supernode& sn : m->S.sn) {
+    const double n = sn.ncols, r = sn.nrows;
+    fl += 2.0 * n * n * n / 3.0 + 2.0 * r * n * n + r * r * n;
+  }
+  info->factor_flops = (int64_t)fl;
   info->n_free = m->hm.n_free;
   info->n_fixed = m->hm.n_nodes - m->hm.n_free;
   info->n_contact = (int64_t)m->hm.contact.size();

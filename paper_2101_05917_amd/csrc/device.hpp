@@ -333,6 +333,6 @@ void launch_factor_scatter(hipStream_t s, const int64_t* dst, const int32_t* src
 void launch_factor_identity(hipStream_t s, const FrontDesc* fd, const int32_t* snode_of, int32_t n, double* P);
 void launch_factor_op(hipStream_t s, const FactorOp& op, const FrontDesc* fd, const int32_t* ints,
                       const int32_t* relmap, double* F, double* P, int32_t* status);
-void launch_factor_transpose(hipStream_t s, const FrontDesc* fd, int ns, int64_t total, const double* P,
-                             double* out);
+void launch_factor_transpose(hipStream_t s, const FactorOp& op, const FrontDesc* fd, const int32_t* ints,
+                             const double* P, double* out);
 }  // namespace dpd

@@ -656,8 +656,12 @@ std::string build_factor_plan(const Symbolic& S, const Csr& A, FactorPlan& P) {
       P.ints.push_back((int32_t)acc);
     }
     op.blocks = (int32_t)acc;
-    if (acc > 0) P.ops.push_back(op);
-    return acc < (int64_t)1 << 30;
+    if (acc >= (int64_t)1 << 30) return false;
+    for (size_t i = 0; i < blocks.size(); ++i)
+      for (int64_t b = 0; b < blocks[i]; ++b) P.ints.push_back((int32_t)i);
+    if (acc > 0 && kind != kFactorTranspose) P.ops.push_back(op);
+    if (kind == kFactorTranspose) P.transpose = op;
+    return (int64_t)P.ints.size() < (int64_t)1 << 31;
   };
   const int64_t TT = kFactorTile, NB = kFactorNB;
   for (int32_t l = 0; l < S.n_levels; ++l) {
@@ -691,7 +695,7 @@ std::string build_factor_plan(const Symbolic& S, const Csr& A, FactorPlan& P) {
         if (f.nc <= k0) continue;
         const int64_t kb = std::min<int64_t>(NB, f.nc - k0), k1 = k0 + kb, m = f.ld - k1;
         i1.push_back(s);
-        b1.push_back((m + 255) / 256 + (k1 + 255) / 256);
+        b1.push_back((m + 63) / 64 + (k1 + 63) / 64);   // rows, then panel columns, 64 per workgroup
         if (m > 0) {
           const int64_t T = (m + TT - 1) / TT;
           i2.push_back(s);
@@ -701,6 +705,16 @@ std::string build_factor_plan(const Symbolic& S, const Csr& A, FactorPlan& P) {
       if (!add_op(kFactorPanel, l, k0, i1, b1)) return "panel launch too large";
       if (!add_op(kFactorUpdate, l, k0, i2, b2)) return "update launch too large";
     }
+  }
+  {
+    std::vector<int32_t> all(ns);
+    std::vector<int64_t> blocks(ns);
+    for (int32_t s = 0; s < ns; ++s) {
+      all[s] = s;
+      const int64_t e = (int64_t)P.fronts[s].ld * P.fronts[s].nc;
+      blocks[s] = (e + kFactorTransposeChunk - 1) / kFactorTransposeChunk;
+    }
+    if (!add_op(kFactorTranspose, -1, 0, all, blocks)) return "transpose launch too large";
   }
   for (int64_t d : P.a_dst)
     if (d < 0 || d >= P.front_size) return "front position out of range";

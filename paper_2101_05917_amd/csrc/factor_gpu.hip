@@ -3,8 +3,9 @@
 // precomputes once, Sec. Background).  The plan (factor.cpp) lists the
 // launches; the dense work of a level's fronts advances one block column of
 // kFactorNB at a time:
-//   k_factor_panel   Cholesky of the diagonal block in LDS, the rows below
-//                    solved against it, and the panel's block row solved;
+//   k_factor_panel   Cholesky factor of the diagonal block and its inverse
+//                    (one wave), then the rows below the block and the
+//                    panel's block row solved with that inverse;
 //   k_factor_update  the trailing lower triangle and the panel's rows below
 //                    the block updated by FP64 MFMA (16x16x4) on 64 x 64 tiles.
 // The panel of a supernode is the first ncols columns of M^{-1} with
@@ -21,19 +22,13 @@ namespace {
 constexpr int NB = kFactorNB;
 constexpr int TT = kFactorTile;
 constexpr int kThreads = 256;
+constexpr int kPanelRows = kThreads / 4;   // rows (or panel columns) per panel-op workgroup
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Item of workgroup b: the largest i < n with prefix[i] <= b.
-__device__ inline int find_item(const int32_t* __restrict__ prefix, int n, int b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
+// Item of this workgroup (the op's per-workgroup table after its items and
+// their prefix sums).
+__device__ inline int item_of(const int32_t* __restrict__ items, int n) { return items[2 * n + 1 + blockIdx.x]; }
 
 __global__ void __launch_bounds__(kThreads) k_factor_scatter(const int64_t* __restrict__ dst,
                                                              const int32_t* __restrict__ src,
@@ -55,13 +50,15 @@ __global__ void __launch_bounds__(kThreads) k_factor_identity(const FrontDesc* _
 }
 
 // Extend-add: the child's update (trailing lower block of its front) into
-// its parent's front, one wave per column of the update.
+// its parent's front, one wave per column of the update, four entries per
+// lane in flight (the loads use clamped in-range indices, so they issue
+// together; the stores are masked).
 __global__ void __launch_bounds__(kThreads) k_factor_extend(const FrontDesc* __restrict__ fd,
                                                             const int32_t* __restrict__ items, int n,
                                                             const int32_t* __restrict__ relmap,
                                                             double* __restrict__ F) {
   const int32_t* pre = items + n;
-  const int it = find_item(pre, n, blockIdx.x);
+  const int it = item_of(items, n);
   const FrontDesc ch = fd[items[it]];
   const FrontDesc pa = fd[ch.parent];
   const int r = ch.nrows;
@@ -70,83 +67,133 @@ __global__ void __launch_bounds__(kThreads) k_factor_extend(const FrontDesc* __r
   const double* __restrict__ U = F + ch.front_off + (int64_t)(ch.nc + q) * ch.ld + ch.nc;
   const int32_t* __restrict__ rel = relmap + ch.rows_off;
   double* __restrict__ col = F + pa.front_off + (int64_t)rel[q] * pa.ld;
-  for (int p = q + (threadIdx.x & 63); p < r; p += 64) col[rel[p]] += U[p];
+  for (int p0 = q + (threadIdx.x & 63); p0 < r; p0 += 256) {
+    int pp[4], rp[4];
+    double u[4], c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pp[k] = min(p0 + 64 * k, r - 1);
+      rp[k] = rel[pp[k]];
+      u[k] = U[pp[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = col[rp[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (p0 + 64 * k < r) col[rp[k]] = c[k] + u[k];
+  }
 }
 
-// Block column [k0, k0 + kb) of a front: the diagonal block's Cholesky factor
-// L_kk and its inverse (in LDS; every workgroup of the front computes them),
-// then either a chunk of the rows below (l = f L_kk^{-T} for each row f) or a
-// chunk of the panel's columns c < k0 + kb (y = L_kk^{-1} x on block row k).
-// Both are products with the inverse (inverted diagonal blocks, as in blocked
-// triangular solves), which keeps a row's 32 entries in registers and the
-// inverse's rows in LDS.  A non-positive or non-finite pivot sets *status.
+// Lane l's value of v, for a wave-uniform l (two 32-bit lane reads).
+__device__ inline double lane_value(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Inverse of the Cholesky factor of a diagonal block, on one wave: lane i
+// holds row i of the block (entries t <= i, padded to NB x NB with an identity
+// block) in a[].  Right-looking Cholesky: at step j the pivot column's entries
+// are read across lanes before the pivot's square root, and every row below
+// subtracts a_ij a_tj / a_jj from its entries t <= i.  Lane j then forms
+// column j of L^{-1} by forward substitution into y[] (y[i] = (L^{-1})_ij).
+// Returns false on a non-positive or non-finite pivot.
+__device__ inline bool diag_inverse(double (&a)[NB], int lane, double (&y)[NB]) {
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double col[NB];
+#pragma unroll
+    for (int t = j; t < NB; ++t) col[t] = lane_value(a[j], t);
+    const double d = col[j];
+    const bool ok = d > 0.0 && __builtin_isfinite(d);
+    bad = bad || !ok;
+    const double dd = ok ? d : 1.0;
+    const double inv_d = 1.0 / dd;
+    const double sc = (lane > j) ? a[j] * inv_d : 0.0;
+#pragma unroll
+    for (int t = j + 1; t < NB; ++t) a[t] -= (t <= lane ? sc : 0.0) * col[t];
+    const double sd = sqrt(dd);
+    a[j] = (lane == j) ? sd : (lane > j ? a[j] * (1.0 / sd) : a[j]);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int u = 0; u < i; ++u) acc -= lane_value(a[u], i) * y[u];
+    y[i] = acc / lane_value(a[i], i);
+  }
+  return !bad;
+}
+
+// Block column [k0, k0 + kb) of a front.  Wave 0 forms the inverse of the
+// diagonal block's Cholesky factor, L_kk^{-1}, in LDS (every workgroup of the
+// front does this).  Then the workgroup handles either
+// 64 of the rows below (l = f L_kk^{-T} for each row f) or 64 of the panel's
+// columns c < k0 + kb (y = L_kk^{-1} x on block row k), four lanes per row or
+// column with NB / 4 outputs each: products with the inverse (inverted
+// diagonal blocks, as in blocked triangular solves).  The four lanes of a row
+// sit in one wave and load the whole row before any of them stores.  Global
+// loads use clamped in-range addresses (the padding is selected afterwards),
+// so each lane's loads issue together.  A non-positive or non-finite pivot
+// sets *status.
 __global__ void __launch_bounds__(kThreads) k_factor_panel(const FrontDesc* __restrict__ fd,
                                                            const int32_t* __restrict__ items, int n, int k0,
                                                            double* __restrict__ F, double* __restrict__ P,
                                                            int32_t* __restrict__ status) {
-  __shared__ double D[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   const int32_t* pre = items + n;
-  const int it = find_item(pre, n, blockIdx.x);
+  const int it = item_of(items, n);
   const FrontDesc f = fd[items[it]];
   const int kb = min(NB, f.nc - k0), k1 = k0 + kb;
   const int local = blockIdx.x - pre[it];
-  const int rows_chunks = (f.ld - k1 + kThreads - 1) / kThreads;
+  const int rows_chunks = (f.ld - k1 + kPanelRows - 1) / kPanelRows;
   double* __restrict__ Fa = F + f.front_off;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += kThreads) {
-    const int i = idx % NB, j = idx / NB;
-    D[i][j] = (i < kb && j <= i) ? Fa[(k0 + i) + (int64_t)(k0 + j) * f.ld] : (i == j ? 1.0 : 0.0);
-    Li[i][j] = 0.0;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int rr = min(lane, kb - 1);
+    double a[NB], y[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) a[t] = Fa[(k0 + rr) + (int64_t)(k0 + min(t, rr)) * f.ld];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) a[t] = (lane < kb && t <= lane) ? a[t] : (t == lane ? 1.0 : 0.0);
+    if (!diag_inverse(a, lane, y) && lane == 0) atomicOr(status, 1);
+    if (lane < NB)
+#pragma unroll
+      for (int i = 0; i < NB; ++i) Li[i][lane] = y[i];
   }
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const double d = D[j][j];
-    const bool bad = !(d > 0.0) || !__builtin_isfinite(d);
-    const double sd = bad ? 1.0 : sqrt(d);
-    if (bad && threadIdx.x == 0) atomicOr(status, 1);
-    __syncthreads();
-    for (int i = j + threadIdx.x; i < kb; i += kThreads) D[i][j] = (i == j) ? sd : D[i][j] / sd;
-    __syncthreads();
-    const int w = kb - j - 1;
-    for (int idx = threadIdx.x; idx < w * w; idx += kThreads) {
-      const int i = j + 1 + idx % w, t = j + 1 + idx / w;
-      if (i >= t) D[i][t] -= D[i][j] * D[t][j];
-    }
-    __syncthreads();
-  }
-  // column j of L_kk^{-1} by forward substitution on e_j, one lane per column
-  if (threadIdx.x < kb) {
-    const int j = threadIdx.x;
-    Li[j][j] = 1.0 / D[j][j];
-    for (int i = j + 1; i < kb; ++i) {
-      double v = 0.0;
-      for (int t = j; t < i; ++t) v += D[i][t] * Li[t][j];
-      Li[i][j] = -v / D[i][i];
-    }
-  }
-  __syncthreads();
-  double x[NB];
+  const int sub = threadIdx.x & 3, slot = threadIdx.x >> 2;
   double* __restrict__ v;
   int64_t stride;
   if (local < rows_chunks) {
-    const int i = k1 + local * kThreads + threadIdx.x;
+    const int i = k1 + local * kPanelRows + slot;
     if (i >= f.ld) return;
     v = Fa + i + (int64_t)k0 * f.ld;
     stride = f.ld;
   } else {
-    const int c = (local - rows_chunks) * kThreads + threadIdx.x;
+    const int c = (local - rows_chunks) * kPanelRows + slot;
     if (c >= k1) return;
     v = P + f.panel_off + (int64_t)c * f.ld + k0;
     stride = 1;
   }
+  double x[NB];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) x[t] = t < kb ? v[t * stride] : 0.0;
-#pragma unroll 2
-  for (int j = 0; j < kb; ++j) {
-    double s = 0.0;
+  for (int t = 0; t < NB; ++t) x[t] = v[min(t, kb - 1) * stride];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) s += Li[j][t] * x[t];
-    v[j * stride] = s;
+  for (int t = 0; t < NB; ++t) x[t] = t < kb ? x[t] : 0.0;
+  constexpr int kOut = NB / 4;
+#pragma unroll 1
+  for (int q = 0; q < kOut; ++q) {
+    const int jrow = sub * kOut + q;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; t += 2) {
+      s0 += Li[jrow][t] * x[t];
+      s1 += Li[jrow][t + 1] * x[t + 1];
+    }
+    if (jrow < kb) v[jrow * stride] = s0 + s1;
   }
 }
 
@@ -163,7 +210,7 @@ __global__ void __launch_bounds__(kThreads) k_factor_update(const FrontDesc* __r
   __shared__ double Xs[NB][TT + 1];   // Xs[t][p] = X[p][t]
   __shared__ double Ys[NB][TT + 1];   // Ys[t][q] = Y[t][q]
   const int32_t* pre = items + n;
-  const int it = find_item(pre, n, blockIdx.x);
+  const int it = item_of(items, n);
   const FrontDesc f = fd[items[it]];
   const int kb = min(NB, f.nc - k0), k1 = k0 + kb, m = f.ld - k1;
   const int T = (m + TT - 1) / TT;
@@ -185,28 +232,66 @@ __global__ void __launch_bounds__(kThreads) k_factor_update(const FrontDesc* __r
   double* __restrict__ Fa = F + f.front_off;
   double* __restrict__ Pa = P + f.panel_off;
   const double* __restrict__ Lp = Fa + k1 + (int64_t)k0 * ld;   // L_{>k,k}: row p, column t at p + t ld
-  for (int idx = threadIdx.x; idx < NB * TT; idx += kThreads) {
-    const int p = idx % TT, t = idx / TT;
-    const int gp = ti * TT + p;
-    Xs[t][p] = (t < kb && gp < m) ? Lp[gp + (int64_t)t * ld] : 0.0;
-  }
-  if (syrk) {
-    for (int idx = threadIdx.x; idx < NB * TT; idx += kThreads) {
-      const int q = idx % TT, t = idx / TT;
-      const int gq = tj * TT + q;
-      Ys[t][q] = (t < kb && gq < m) ? Lp[gq + (int64_t)t * ld] : 0.0;
-    }
-  } else {
-    for (int idx = threadIdx.x; idx < NB * TT; idx += kThreads) {
-      const int t = idx % NB, q = idx / NB;
-      const int gq = tj * TT + q;
-      Ys[t][q] = (t < kb && gq < k1) ? Pa[(k0 + t) + (int64_t)gq * ld] : 0.0;
-    }
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pr = (w >> 1) * 32, qc = (w & 1) * 32;
   const int kl = lane >> 4, il = lane & 15;
+  // the tile's current values first (clamped in-range addresses, so the loads
+  // issue together and overlap the operand staging and the products)
+  int64_t dst[2][2][4];
+  bool keep[2][2][4];
+  double old[2][2][4];
+#pragma unroll
+  for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gp = ti * TT + pr + pb * 16 + il;
+        const int gq = tj * TT + qc + qb * 16 + 4 * e + kl;
+        if (syrk) {
+          keep[qb][pb][e] = gp < m && gq <= gp;
+          dst[qb][pb][e] = f.front_off + (k1 + min(gp, m - 1)) + (int64_t)(k1 + min(gq, m - 1)) * ld;
+        } else {
+          keep[qb][pb][e] = gp < m && gq < k1;
+          dst[qb][pb][e] = f.panel_off + (k1 + min(gp, m - 1)) + (int64_t)min(gq, k1 - 1) * ld;
+        }
+      }
+  double* __restrict__ out = syrk ? F : P;
+#pragma unroll
+  for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) old[qb][pb][e] = out[dst[qb][pb][e]];
+  constexpr int kPer = NB * TT / kThreads;
+#pragma unroll
+  for (int s2 = 0; s2 < kPer; ++s2) {
+    const int idx = threadIdx.x + kThreads * s2;
+    const int p = idx % TT, t = idx / TT;
+    const int gp = ti * TT + p;
+    const double v = Lp[min(gp, m - 1) + (int64_t)min(t, kb - 1) * ld];
+    Xs[t][p] = (t < kb && gp < m) ? v : 0.0;
+  }
+  if (syrk) {
+#pragma unroll
+    for (int s2 = 0; s2 < kPer; ++s2) {
+      const int idx = threadIdx.x + kThreads * s2;
+      const int q = idx % TT, t = idx / TT;
+      const int gq = tj * TT + q;
+      const double v = Lp[min(gq, m - 1) + (int64_t)min(t, kb - 1) * ld];
+      Ys[t][q] = (t < kb && gq < m) ? v : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int s2 = 0; s2 < kPer; ++s2) {
+      const int idx = threadIdx.x + kThreads * s2;
+      const int t = idx % NB, q = idx / NB;
+      const int gq = tj * TT + q;
+      const double v = Pa[(k0 + min(t, kb - 1)) + (int64_t)min(gq, k1 - 1) * ld];
+      Ys[t][q] = (t < kb && gq < k1) ? v : 0.0;
+    }
+  }
+  __syncthreads();
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -227,40 +312,34 @@ __global__ void __launch_bounds__(kThreads) k_factor_update(const FrontDesc* __r
 #pragma unroll
   for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb) {
-      const int gp = ti * TT + pr + pb * 16 + il;
-      if (gp >= m) continue;
+    for (int pb = 0; pb < 2; ++pb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gq = tj * TT + qc + qb * 16 + 4 * e + kl;
-        const double v = acc[qb][pb][e];
-        if (syrk) {
-          if (gq <= gp) Fa[(k1 + gp) + (int64_t)(k1 + gq) * ld] -= v;
-        } else if (gq < k1) {
-          Pa[(k1 + gp) + (int64_t)gq * ld] -= v;
-        }
-      }
-    }
+      for (int e = 0; e < 4; ++e)
+        if (keep[qb][pb][e]) out[dst[qb][pb][e]] = old[qb][pb][e] - acc[qb][pb][e];
 }
 
 // Row-major copy of every panel: element (r, c) of a supernode at
-// panel_off + r * nc + c.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_factor_transpose(const FrontDesc* __restrict__ fd, int ns,
-                                                               int64_t total, const double* __restrict__ P,
-                                                               T* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  int lo = 0, hi = ns - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (fd[mid].panel_off <= e) lo = mid;
-    else hi = mid - 1;
+// panel_off + r * nc + c; a workgroup copies kFactorTransposeChunk entries
+// of one supernode, four per lane (loads issued together, stores masked).
+__global__ void __launch_bounds__(kThreads) k_factor_transpose(const FrontDesc* __restrict__ fd,
+                                                               const int32_t* __restrict__ items, int n,
+                                                               const double* __restrict__ P,
+                                                               double* __restrict__ out) {
+  const int32_t* pre = items + n;
+  const int it = item_of(items, n);
+  const FrontDesc f = fd[items[it]];
+  const int64_t total = (int64_t)f.ld * f.nc;
+  const int64_t e0 = (int64_t)(blockIdx.x - pre[it]) * kFactorTransposeChunk + threadIdx.x;
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t e = min(e0 + k * kThreads, total - 1);
+    const int64_t r = e / f.nc, c = e - r * f.nc;
+    v[k] = P[f.panel_off + c * f.ld + r];
   }
-  const FrontDesc f = fd[lo];
-  const int64_t local = e - f.panel_off;
-  const int64_t r = local / f.nc, c = local % f.nc;
-  out[e] = (T)P[f.panel_off + c * f.ld + r];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (e0 + k * kThreads < total) out[f.panel_off + e0 + k * kThreads] = v[k];
 }
 
 int grid_of(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
@@ -293,10 +372,10 @@ void launch_factor_op(hipStream_t s, const FactorOp& op, const FrontDesc* fd, co
   }
 }
 
-void launch_factor_transpose(hipStream_t s, const FrontDesc* fd, int ns, int64_t total, const double* P,
-                             double* out) {
-  if (total > 0)
-    hipLaunchKernelGGL(k_factor_transpose<double>, dim3(grid_of(total)), dim3(kThreads), 0, s, fd, ns, total, P,
+void launch_factor_transpose(hipStream_t s, const FactorOp& op, const FrontDesc* fd, const int32_t* ints,
+                             const double* P, double* out) {
+  if (op.blocks > 0)
+    hipLaunchKernelGGL(k_factor_transpose, dim3(op.blocks), dim3(kThreads), 0, s, fd, ints + op.list_off, op.n, P,
                        out);
 }
 

@@ -207,6 +207,7 @@ void build_plan(const Symbolic& S, LevelPlan& P);
 // of the sweeps, and F_s's trailing block the update for the parent.
 constexpr int kFactorNB = 32;     // block-column width
 constexpr int kFactorTile = 64;   // output tile of the update op
+constexpr int kFactorTransposeChunk = 1024;
 struct FrontDesc {
   int64_t front_off;   // into the front workspace (doubles)
   int64_t panel_off;   // into the panel array
@@ -214,10 +215,11 @@ struct FrontDesc {
   int32_t ld, nc, nrows, parent, col0, pad;
 };
 static_assert(sizeof(FrontDesc) == 48, "device layout");
-enum FactorOpKind : int32_t { kFactorExtend = 0, kFactorPanel = 1, kFactorUpdate = 2 };
+enum FactorOpKind : int32_t { kFactorExtend = 0, kFactorPanel = 1, kFactorUpdate = 2, kFactorTranspose = 3 };
 // One launch: n items (supernodes; for extend-add the children of the level's
 // fronts with a given sibling rank) at ints[list_off ...], then their
-// workgroup prefix sums (n + 1 entries, the last = blocks).
+// workgroup prefix sums (n + 1 entries, the last = blocks), then each
+// workgroup's item index (blocks entries).
 struct FactorOp {
   int32_t kind, k0, n, list_off, blocks, level;
 };
@@ -229,6 +231,8 @@ struct FactorPlan {
   std::vector<int32_t> relmap;         // per Symbolic::rows entry: its position in the parent's front
   std::vector<int32_t> ints;           // item lists and prefix sums of the ops
   std::vector<FactorOp> ops;           // in launch order
+  FactorOp transpose{};                // the row-major panel copy: every supernode,
+                                       // kFactorTransposeChunk panel entries per workgroup
   double flops = 0.0;                  // of the dense work (Cholesky, updates, panel)
 };
 // Builds the plan and checks every index it holds against its buffer; returns

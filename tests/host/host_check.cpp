@@ -84,12 +84,13 @@ static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A,
     return i;
   };
   for (const FactorOp& op : FP.ops) {
-    CHECK(op.n > 0 && op.list_off >= 0 && (size_t)op.list_off + 2 * op.n + 1 <= FP.ints.size());
+    CHECK(op.n > 0 && op.list_off >= 0 && (size_t)op.list_off + 2 * op.n + 1 + op.blocks <= FP.ints.size());
     const int32_t* items = &FP.ints[op.list_off];
     const int32_t* pre = items + op.n;
     CHECK(pre[0] == 0 && pre[op.n] == op.blocks);
     for (int b = 0; b < op.blocks; ++b) {
-      const int it = find_item_h(pre, op.n, b);
+      const int it = items[2 * op.n + 1 + b];
+      CHECK(it == find_item_h(pre, op.n, b));
       CHECK(pre[it] <= b && b < pre[it + 1]);
       CHECK(items[it] >= 0 && items[it] < ns);
       const FrontDesc f = FP.fronts[items[it]];
@@ -102,16 +103,24 @@ static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A,
           if (q >= f.nrows) continue;
           CHECK(f.rows_off + q < (int64_t)FP.relmap.size());
           const int rq = FP.relmap[f.rows_off + q];
-          for (int p = q; p < f.nrows; ++p) {
-            const int rp = FP.relmap[f.rows_off + p];
-            CHECK(rp >= rq);
-            F[fidx(pa, rp, rq)] += F[fidx(f, f.nc + p, f.nc + q)];
-          }
+          for (int lane = 0; lane < 64; ++lane)
+            for (int p0 = q + lane; p0 < f.nrows; p0 += 256)
+              for (int k = 0; k < 4; ++k) {
+                const int pc = std::min(p0 + 64 * k, f.nrows - 1);   // clamped load index
+                CHECK(f.rows_off + pc < (int64_t)FP.relmap.size());
+                const int rp = FP.relmap[f.rows_off + pc];
+                (void)F[fidx(pa, rp, rq)];
+                (void)F[fidx(f, f.nc + pc, f.nc + q)];
+                if (p0 + 64 * k >= f.nrows) continue;
+                CHECK(rp >= rq);
+                F[fidx(pa, rp, rq)] += F[fidx(f, f.nc + pc, f.nc + q)];
+              }
         }
       } else if (op.kind == kFactorPanel) {
         const int kb = std::min(NB, f.nc - op.k0), k0 = op.k0, k1 = k0 + kb;
         CHECK(kb > 0);
-        const int rows_chunks = (f.ld - k1 + TH - 1) / TH;
+        const int PR = TH / 4;   // rows (or panel columns) per workgroup, four lanes each
+        const int rows_chunks = (f.ld - k1 + PR - 1) / PR;
         double D[32][33], Li[32][33];
         for (int i = 0; i < NB; ++i)
           for (int j = 0; j < NB; ++j) {
@@ -133,11 +142,12 @@ static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A,
             Li[i][j] = -v / D[i][i];
           }
         }
-        for (int tid = 0; tid < TH; ++tid) {
+        CHECK(local < rows_chunks + (k1 + PR - 1) / PR);
+        for (int slot = 0; slot < PR; ++slot) {
           double x[32];
           std::vector<int64_t> at(kb);
           if (local < rows_chunks) {
-            const int i = k1 + local * TH + tid;
+            const int i = k1 + local * PR + slot;
             if (i >= f.ld) continue;
             for (int t = 0; t < kb; ++t) at[t] = fidx(f, i, k0 + t);
             for (int t = 0; t < NB; ++t) x[t] = t < kb ? F[at[t]] : 0.0;
@@ -147,8 +157,7 @@ static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A,
               F[at[j]] = sum;
             }
           } else {
-            const int c = (local - rows_chunks) * TH + tid;
-            CHECK(local - rows_chunks < (k1 + TH - 1) / TH);
+            const int c = (local - rows_chunks) * PR + slot;
             if (c >= k1) continue;
             for (int t = 0; t < kb; ++t) at[t] = pidx(f, k0 + t, c);
             for (int t = 0; t < NB; ++t) x[t] = t < kb ? P[at[t]] : 0.0;
@@ -194,6 +203,35 @@ static std::vector<double> replay_device_factor(const Symbolic& S, const Csr& A,
           }
       }
     }
+  }
+  // row-major copy: the transpose launch's table and indices
+  {
+    const FactorOp& op = FP.transpose;
+    CHECK(op.kind == kFactorTranspose && op.n == ns);
+    CHECK((size_t)op.list_off + 2 * op.n + 1 + op.blocks <= FP.ints.size());
+    const int32_t* items = &FP.ints[op.list_off];
+    const int32_t* pre = items + op.n;
+    std::vector<double> T(S.panel_size, -1.0);
+    for (int b = 0; b < op.blocks; ++b) {
+      const int it = items[2 * op.n + 1 + b];
+      CHECK(it == find_item_h(pre, op.n, b));
+      const FrontDesc f = FP.fronts[items[it]];
+      const int64_t total = (int64_t)f.ld * f.nc;
+      for (int tid = 0; tid < TH; ++tid)
+        for (int k = 0; k < 4; ++k) {
+          const int64_t e = (int64_t)(b - pre[it]) * kFactorTransposeChunk + tid + k * TH;
+          const int64_t ec = std::min(e, total - 1);
+          const int64_t r = ec / f.nc, c = ec - r * f.nc;
+          const int64_t src = f.panel_off + c * f.ld + r;
+          CHECK(src >= 0 && src < S.panel_size);
+          if (e < total) {
+            CHECK(f.panel_off + e < S.panel_size);
+            T[f.panel_off + e] = P[src];
+          }
+        }
+    }
+    const std::vector<double> ref = transpose_panels<double>(S, P);
+    for (int64_t i = 0; i < S.panel_size; ++i) CHECK(T[i] == ref[i]);
   }
   return P;
 }
