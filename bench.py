@@ -89,6 +89,9 @@ def parse(argv=None):
                          "tree level (default: the library's)")
     ap.add_argument("--leaf-nodes", type=int, default=0,
                     help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
+    ap.add_argument("--bwd-warm-start", type=int, default=2,
+                    help="adjoint CG start: 2 = linear extrapolation of the two previous backward steps' "
+                         "solutions, 1 = the previous solution, 0 = zero")
     ap.add_argument("--factorize-only", type=int, default=0,
                     help="time this many numeric factorizations of the workload's A and report them "
                          "(no rollouts)")
@@ -166,6 +169,8 @@ def solver_options(args) -> dict:
         opts["leaf_nodes"] = args.leaf_nodes
     if getattr(args, "factor_on_host", False):
         opts["factor_on_host"] = 1
+    if getattr(args, "bwd_warm_start", 0):
+        opts["bwd_warm_start"] = args.bwd_warm_start
     if args.deflation:
         opts["deflation"] = args.deflation
         opts["deflation_refresh"] = args.deflation_refresh
@@ -742,7 +747,8 @@ def main():
                    "fwd_rel_tol": args.fwd_tol, "bwd_rel_tol": args.bwd_tol,
                    "fwd_inner_tol": args.fwd_inner_tol,
                    "precision": args.precision, "fused_cg_workgroups": mesh.info["fused_blocks"],
-                   "deflation": args.deflation, "deflation_refresh": args.deflation_refresh if args.deflation else None},
+                   "deflation": args.deflation, "deflation_refresh": args.deflation_refresh if args.deflation else None,
+                   "bwd_warm_start": args.bwd_warm_start},
         "fwd_iters_per_step": fi / T,
         "bwd_iters_per_step": bi / T,
         "grad_rel_err_vs_oracle": err,

@@ -143,6 +143,17 @@ typedef struct {
                               over the supernodes is allocated and freed by the
                               call); 1: on the host (C++ with OpenMP), the
                               panels then uploaded.  Same factor to rounding   */
+  int32_t bwd_warm_start;  /* adjoint CG of the multi-launch path (not in the
+                              batch engine, not deflated): 1 = start from the
+                              previous backward step's solution z (the adjoint
+                              of the step after this one), 2 = from the linear
+                              extrapolation 2 z_{t+1} - z_{t+2} of the previous
+                              two; a start is kept only if its residual is
+                              smaller than the right-hand side, else zero.
+                              0 (default) = from zero.  Same stopping test
+                              (relative to the right-hand side); the handle
+                              keeps the last two solutions across calls       */
+  int32_t pad_opt;
 } dpd_options;
 
 typedef struct {

@@ -36,6 +36,7 @@ class Options(C.Structure):
         ("fused_cg", C.c_int32), ("contact_fused", C.c_int32), ("sweep_launch", C.c_int32),
         ("volume_scale", C.c_double), ("leaf_nodes", C.c_int32), ("deflation", C.c_int32),
         ("deflation_refresh", C.c_int32), ("factor_on_host", C.c_int32),
+        ("bwd_warm_start", C.c_int32), ("pad_opt", C.c_int32),
     ]
 
 

@@ -486,7 +486,7 @@ dpd_status setup_dense(dpd_mesh* m, hipStream_t s) {
 
 namespace {
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
-                              int max_it, int check_every);
+                              int max_it, int check_every, const double* z0 = nullptr);
 dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
                           bool fp32, bool pd_fallback);
 dpd_status check_aborted(dpd_mesh* m, int st_idx);
@@ -1516,7 +1516,7 @@ dpd_status deflated_start(dpd_mesh* m, hipStream_t s, const double* rhs) {
 }
 
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
-                              int max_it, int check_every) {
+                              int max_it, int check_every, const double* z0) {
   if (m->dense_blocks > 0 && m->opt.fused_cg) return cg_dense(m, s, st, rhs, fp32);
   dpd_status rc;
   const int64_t n3 = 3 * (int64_t)m->dm.N;
@@ -1526,6 +1526,21 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
+  if (z0 && st == m->st && !m->defl_active && !m->batcher) {
+    // warm start: z = z0, r = rhs - H z0, kept only if |r| < |rhs| (the
+    // stopping test stays relative to |rhs|)
+    IterState* aux = m->st + 1;
+    launch_lincomb(s, n3, m->z, 1.0, z0, 0.0, nullptr);
+    defl_hessian(m, s, m->z, m->q);
+    launch_lincomb(s, n3, m->cg_r, 1.0, rhs, -1.0, m->q);
+    launch_fill(s, n3, m->q, 0.0);
+    launch_dot(m->dm, s, m->cg_r, m->cg_r, aux, m->partials, 0);
+    if ((rc = read_state(m, s)) != DPD_OK) return rc;
+    if (!(m->h_st[1].nb2 < m->h_st[0].nb2)) {
+      launch_fill(s, n3, m->z, 0.0);
+      launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
+    }
+  }
   if (st == m->st && m->defl_active && !m->batcher) {
     // start from the solution's component in W: z0 = W E^{-1} W^T rhs, r0 = rhs - HW E^{-1} W^T rhs
     // (r0 is then orthogonal to W, and stays so)
@@ -1612,7 +1627,17 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   } else if (o.bwd_solver == DPD_BWD_PCG) {
     m->defl_active = false;
     if (o.deflation > 0 && !m->batcher && (rc = defl_prepare(m, s, fp32)) != DPD_OK) return rc;
-    rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every);
+    const bool warm = o.bwd_warm_start && !m->batcher && !m->defl_active;
+    if (warm && !m->z_warm && (rc = dev_alloc(m, &m->z_warm, n3)) != DPD_OK) return rc;
+    if (warm && !m->z_warm2 && (rc = dev_alloc(m, &m->z_warm2, n3)) != DPD_OK) return rc;
+    const double* z0 = nullptr;
+    if (warm && m->z_warm_n >= 1) z0 = m->z_warm;
+    if (warm && o.bwd_warm_start == 2 && m->z_warm_n >= 2) {
+      // linear extrapolation 2 z_{t+1} - z_{t+2}, staged in the older buffer
+      launch_lincomb(s, n3, m->z_warm2, 2.0, m->z_warm, -1.0, m->z_warm2);
+      z0 = m->z_warm2;
+    }
+    rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every, z0);
     m->defl_active = false;
     if (rc != DPD_OK) return rc;
     if ((rc = read_state(m, s)) != DPD_OK) return rc;
@@ -1623,6 +1648,13 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
       launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
       if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
+    }
+    if (warm) {
+      // keep the last two solutions (z_warm the newest); with extrapolation the
+      // older buffer held the guess, so it is rebuilt from z_warm
+      launch_lincomb(s, n3, m->z_warm2, 1.0, m->z_warm, 0.0, nullptr);
+      launch_lincomb(s, n3, m->z_warm, 1.0, m->z, 0.0, nullptr);
+      m->z_warm_n = std::min(2, m->z_warm_n + 1);
     }
   } else {
     launch_fill(s, n3, m->z, 0.0);
