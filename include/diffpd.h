@@ -148,11 +148,13 @@ typedef struct {
                               previous backward step's solution z (the adjoint
                               of the step after this one), 2 = from the linear
                               extrapolation 2 z_{t+1} - z_{t+2} of the previous
-                              two; a start is kept only if its residual is
-                              smaller than the right-hand side, else zero.
-                              0 (default) = from zero.  Same stopping test
-                              (relative to the right-hand side); the handle
-                              keeps the last two solutions across calls       */
+                              two, 3 = from the quadratic one 3 z_{t+1} -
+                              3 z_{t+2} + z_{t+3}; a start is kept only if its
+                              residual is smaller than the right-hand side,
+                              else zero.  0 (default) = from zero.  Same
+                              stopping test (relative to the right-hand side);
+                              the handle keeps the last three solutions across
+                              calls                                            */
   int32_t pad_opt;
 } dpd_options;
 

@@ -1627,15 +1627,26 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   } else if (o.bwd_solver == DPD_BWD_PCG) {
     m->defl_active = false;
     if (o.deflation > 0 && !m->batcher && (rc = defl_prepare(m, s, fp32)) != DPD_OK) return rc;
-    const bool warm = o.bwd_warm_start && !m->batcher && !m->defl_active;
-    if (warm && !m->z_warm && (rc = dev_alloc(m, &m->z_warm, n3)) != DPD_OK) return rc;
-    if (warm && !m->z_warm2 && (rc = dev_alloc(m, &m->z_warm2, n3)) != DPD_OK) return rc;
+    const bool warm = o.bwd_warm_start > 0 && !m->batcher && !m->defl_active;
+    if (warm && !m->z_start) {
+      for (double*& b : m->z_hist)
+        if ((rc = dev_alloc(m, &b, n3)) != DPD_OK) return rc;
+      if ((rc = dev_alloc(m, &m->z_start, n3)) != DPD_OK) return rc;
+    }
+    // polynomial extrapolation in t of the last solutions: order 0 (z_{t+1}),
+    // 1 (2 z_{t+1} - z_{t+2}) or 2 (3 z_{t+1} - 3 z_{t+2} + z_{t+3}), as many
+    // as are held
     const double* z0 = nullptr;
-    if (warm && m->z_warm_n >= 1) z0 = m->z_warm;
-    if (warm && o.bwd_warm_start == 2 && m->z_warm_n >= 2) {
-      // linear extrapolation 2 z_{t+1} - z_{t+2}, staged in the older buffer
-      launch_lincomb(s, n3, m->z_warm2, 2.0, m->z_warm, -1.0, m->z_warm2);
-      z0 = m->z_warm2;
+    const int order = warm ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
+    if (order == 0) {
+      z0 = m->z_hist[0];
+    } else if (order == 1) {
+      launch_lincomb(s, n3, m->z_start, 2.0, m->z_hist[0], -1.0, m->z_hist[1]);
+      z0 = m->z_start;
+    } else if (order == 2) {
+      launch_lincomb(s, n3, m->z_start, 3.0, m->z_hist[0], -3.0, m->z_hist[1]);
+      launch_lincomb(s, n3, m->z_start, 1.0, m->z_start, 1.0, m->z_hist[2]);
+      z0 = m->z_start;
     }
     rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every, z0);
     m->defl_active = false;
@@ -1650,11 +1661,10 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
     }
     if (warm) {
-      // keep the last two solutions (z_warm the newest); with extrapolation the
-      // older buffer held the guess, so it is rebuilt from z_warm
-      launch_lincomb(s, n3, m->z_warm2, 1.0, m->z_warm, 0.0, nullptr);
-      launch_lincomb(s, n3, m->z_warm, 1.0, m->z, 0.0, nullptr);
-      m->z_warm_n = std::min(2, m->z_warm_n + 1);
+      std::swap(m->z_hist[2], m->z_hist[1]);
+      std::swap(m->z_hist[1], m->z_hist[0]);   // the oldest buffer takes the new solution
+      launch_lincomb(s, n3, m->z_hist[0], 1.0, m->z, 0.0, nullptr);
+      m->z_hist_n = std::min(3, m->z_hist_n + 1);
     }
   } else {
     launch_fill(s, n3, m->z, 0.0);

@@ -82,9 +82,11 @@ struct dpd_mesh {
   double *fe = nullptr, *r = nullptr, *y = nullptr, *partials = nullptr, *cache = nullptr;
   double *z = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *xbar = nullptr, *cg_r = nullptr;
   double* xbar_w = nullptr;   // H s of the conjugate-gradient iteration
-  double* z_warm = nullptr;   // the last backward step's adjoint solution (dpd_options.bwd_warm_start)
-  double* z_warm2 = nullptr;  // the one before it (linear extrapolation, bwd_warm_start = 2)
-  int z_warm_n = 0;           // solutions held (0..2)
+  // the last three backward steps' adjoint solutions, newest first, and the
+  // start built from them (dpd_options.bwd_warm_start)
+  double* z_hist[3] = {nullptr, nullptr, nullptr};
+  double* z_start = nullptr;
+  int z_hist_n = 0;           // solutions held (0..3)
   dpd::IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   dpd::IterState* h_st = nullptr;   // pinned host mirror [2]
   // kernel timing (dpd_profile_start / dpd_profile_read)

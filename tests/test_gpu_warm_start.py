@@ -1,6 +1,6 @@
 """Warm-started adjoint conjugate gradients (dpd_options.bwd_warm_start): the
 backward steps of a rollout start from the previous step's adjoint solution
-or from the linear extrapolation of the previous two.  The adjoint system and
+or from the linear or quadratic extrapolation of the previous two or three.  The adjoint system and
 its stopping test (relative to the right-hand side) are unchanged, so the
 rollout gradients equal the cold-started ones to the solver tolerance, with
 fewer iterations; the rollouts' gradients against the oracle at the
@@ -31,7 +31,7 @@ def _rollout(sc, warm, T, tol=1e-10):
     return out
 
 
-@pytest.mark.parametrize("warm", [1, 2])
+@pytest.mark.parametrize("warm", [1, 2, 3])
 def test_warm_start_same_gradients_fewer_iterations(warm):
     sc = W.dropped_block(16, 10, 8, steps=16, drop=0.002)
     T = 16
