@@ -488,7 +488,7 @@ namespace {
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
                               int max_it, int check_every, const double* z0 = nullptr);
 dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
-                          bool fp32, bool pd_fallback);
+                          bool fp32, bool pd_fallback, const double* nb2_ref = nullptr);
 dpd_status check_aborted(dpd_mesh* m, int st_idx);
 }  // namespace
 
@@ -1253,14 +1253,14 @@ double dense_iter_bytes(const dpd_mesh* m, bool fp32) {
 // its next synchronisation.  With pd_fallback a non-positive curvature leaves
 // z = A^{-1} rhs, the plain PD step.
 dpd_status cg_dense_async(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, double rhs_scale,
-                          bool fp32, bool pd_fallback) {
+                          bool fp32, bool pd_fallback, const double* nb2_ref) {
   if (fp32 && !m->ainv32) return fail(m, DPD_ESTATE, "no FP32 copy of the dense inverse");
   // while timed, every launch adds its own device-clock duration, iterations
   // and itself to m->prof_acc (HIP events around a cooperative launch would
   // also bracket the host's enqueue time)
   ProfAcc* acc = m->prof_class == DPD_PROF_CG_DENSE && !m->capturing ? m->prof_acc : nullptr;
   HIPCHECK(m, launch_cg_dense(m->dm, m->dcg, s, m->dense_blocks, fp32, m->cache, rhs, rhs_scale,
-                              pd_fallback ? 1 : 0, m->z, st, acc));
+                              pd_fallback ? 1 : 0, m->z, st, acc, nb2_ref));
   return DPD_OK;
 }
 
@@ -1622,32 +1622,45 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   // on the device: it does nothing if the solve met non-positive curvature,
   // in which case the fallback below finishes the adjoint and runs it again.
   const bool gated = o.bwd_solver == DPD_BWD_PCG && m->dense_blocks > 0 && o.fused_cg;
+  // warm start (dpd_options.bwd_warm_start): polynomial extrapolation in t of
+  // the last adjoint solutions, order 0 (z_{t+1}), 1 (2 z_{t+1} - z_{t+2}) or
+  // 2 (3 z_{t+1} - 3 z_{t+2} + z_{t+3}), as many as are held, built in z_start
+  const bool warm = o.bwd_solver == DPD_BWD_PCG && o.bwd_warm_start > 0 && !m->batcher && o.deflation <= 0;
+  if (warm && !m->z_start) {
+    for (double*& b : m->z_hist)
+      if ((rc = dev_alloc(m, &b, n3)) != DPD_OK) return rc;
+    if ((rc = dev_alloc(m, &m->z_start, n3)) != DPD_OK) return rc;
+    if ((rc = dev_alloc(m, &m->warm_st, 2)) != DPD_OK) return rc;
+    HIPCHECK(m, hipMemset(m->warm_st, 0, 2 * sizeof(IterState)));   // reduction tickets start at zero
+  }
+  const int order = warm ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
+  if (order == 0) {
+    launch_lincomb(s, n3, m->z_start, 1.0, m->z_hist[0], 0.0, nullptr);
+  } else if (order == 1) {
+    launch_lincomb(s, n3, m->z_start, 2.0, m->z_hist[0], -1.0, m->z_hist[1]);
+  } else if (order == 2) {
+    launch_lincomb(s, n3, m->z_start, 3.0, m->z_hist[0], -3.0, m->z_hist[1]);
+    launch_lincomb(s, n3, m->z_start, 1.0, m->z_start, 1.0, m->z_hist[2]);
+  }
+  const double* z0 = order >= 0 ? m->z_start : nullptr;
   if (gated) {
-    if ((rc = cg_dense_async(m, s, m->st, m->xbar, 1.0, fp32, false)) != DPD_OK) return rc;
+    if (z0) {
+      // the fused solver solves H d = xbar - H z0 (start and safeguard decided
+      // on the device), its stopping test relative to |xbar|; z = z0 + d
+      defl_hessian(m, s, m->z_start, m->q);
+      launch_lincomb(s, n3, m->cg_r, 1.0, m->xbar, -1.0, m->q);
+      launch_dot(m->dm, s, m->xbar, m->xbar, m->warm_st, m->partials, 0);
+      launch_dot(m->dm, s, m->cg_r, m->cg_r, m->warm_st + 1, m->partials, 0);
+      launch_warm_select(s, n3, m->z_start, m->cg_r, m->xbar, m->warm_st);
+      if ((rc = cg_dense_async(m, s, m->st, m->cg_r, 1.0, fp32, false, &m->warm_st[0].nb2)) != DPD_OK) return rc;
+      launch_lincomb(s, n3, m->z, 1.0, m->z, 1.0, m->z_start);
+      launch_zero_fixed(m->dm, s, m->z);
+    } else if ((rc = cg_dense_async(m, s, m->st, m->xbar, 1.0, fp32, false)) != DPD_OK) {
+      return rc;
+    }
   } else if (o.bwd_solver == DPD_BWD_PCG) {
     m->defl_active = false;
     if (o.deflation > 0 && !m->batcher && (rc = defl_prepare(m, s, fp32)) != DPD_OK) return rc;
-    const bool warm = o.bwd_warm_start > 0 && !m->batcher && !m->defl_active;
-    if (warm && !m->z_start) {
-      for (double*& b : m->z_hist)
-        if ((rc = dev_alloc(m, &b, n3)) != DPD_OK) return rc;
-      if ((rc = dev_alloc(m, &m->z_start, n3)) != DPD_OK) return rc;
-    }
-    // polynomial extrapolation in t of the last solutions: order 0 (z_{t+1}),
-    // 1 (2 z_{t+1} - z_{t+2}) or 2 (3 z_{t+1} - 3 z_{t+2} + z_{t+3}), as many
-    // as are held
-    const double* z0 = nullptr;
-    const int order = warm ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
-    if (order == 0) {
-      z0 = m->z_hist[0];
-    } else if (order == 1) {
-      launch_lincomb(s, n3, m->z_start, 2.0, m->z_hist[0], -1.0, m->z_hist[1]);
-      z0 = m->z_start;
-    } else if (order == 2) {
-      launch_lincomb(s, n3, m->z_start, 3.0, m->z_hist[0], -3.0, m->z_hist[1]);
-      launch_lincomb(s, n3, m->z_start, 1.0, m->z_start, 1.0, m->z_hist[2]);
-      z0 = m->z_start;
-    }
     rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every, z0);
     m->defl_active = false;
     if (rc != DPD_OK) return rc;
@@ -1659,12 +1672,6 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       launch_reset(s, m->st, o.bwd_rel_tol * o.bwd_rel_tol, max_it);
       launch_dot(m->dm, s, m->xbar, m->xbar, m->st, m->partials, 0);
       if ((rc = fixed_point(m, s, xn, fp32, max_it)) != DPD_OK) return rc;
-    }
-    if (warm) {
-      std::swap(m->z_hist[2], m->z_hist[1]);
-      std::swap(m->z_hist[1], m->z_hist[0]);   // the oldest buffer takes the new solution
-      launch_lincomb(s, n3, m->z_hist[0], 1.0, m->z, 0.0, nullptr);
-      m->z_hist_n = std::min(3, m->z_hist_n + 1);
     }
   } else {
     launch_fill(s, n3, m->z, 0.0);
@@ -1689,6 +1696,12 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       HIPCHECK(m, hipGetLastError());
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
     }
+  }
+  if (warm) {
+    std::swap(m->z_hist[2], m->z_hist[1]);
+    std::swap(m->z_hist[1], m->z_hist[0]);   // the oldest buffer takes the new solution
+    launch_lincomb(s, n3, m->z_hist[0], 1.0, m->z, 0.0, nullptr);
+    m->z_hist_n = std::min(3, m->z_hist_n + 1);
   }
   const IterState& h = *m->h_st;
   if (stats) {

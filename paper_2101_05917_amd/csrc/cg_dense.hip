@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(kDenseBlock) k_cg_dense(DevMesh M, DenseCG D, 
       }
     }
     rsq = rsq_next;
-    if (k == 0) nb2 = rsq;
+    if (k == 0) nb2 = D.nb2_ref ? *D.nb2_ref : rsq;
     if (!isfinite(rsq)) {
       nonfinite = 1;
       break;
@@ -645,12 +645,13 @@ int cg_dense_max_blocks(int n, int rows, int mode, bool fp32) {
 
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
-                           double* z_out, IterState* st, ProfAcc* prof) {
+                           double* z_out, IterState* st, ProfAcc* prof, const double* nb2_ref) {
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, D.bar, D.ready, blocks);
   const int mode = fp32 ? D.mode32 : D.mode64;
   const size_t lds = cg_dense_lds_bytes(D.n, D.rows, mode, fp32);
   DevMesh m = M;
   DenseCG d = D;
+  d.nb2_ref = nb2_ref;
   IterState* stp = st;
   const double* cp = cache;
   const double* rp = rhs;

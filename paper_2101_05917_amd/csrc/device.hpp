@@ -110,6 +110,7 @@ struct DenseCG {
   uint32_t* ready;            // [G] how many s vectors workgroup b has published in this launch
   const int32_t* nbr_off;     // [G + 1] ranges of nbr
   const int32_t* nbr;         // workgroups owning rows at workgroup b's element corners (b excluded)
+  const double* nb2_ref;      // set for a warm-started solve: |b|^2 of the stopping test (else |r_0|^2)
 };
 
 void launch_hold(hipStream_t s, int periods);
@@ -273,6 +274,9 @@ void launch_node_residual(const DevMesh& M, hipStream_t s, const double* x, cons
                           int max_iter, int fixed_iters);
 void launch_velocity(const DevMesh& M, hipStream_t s, const double* x, const double* xn, double* vn);
 void launch_zero_fixed(const DevMesh& M, hipStream_t s, double* v);
+// Warm start safeguard on the device: where |r_0|^2 (w[1].nb2) is not below
+// |b|^2 (w[0].nb2), z0 := 0 and r := b.
+void launch_warm_select(hipStream_t s, int64_t n, double* z0, double* r, const double* b, const IterState* w);
 void launch_solve_dag(const DevSolve& S, const DevDag& D, hipStream_t s, bool fp32, const double* b, double* out,
                       int N, double alpha, int accumulate, const IterState* st);
 const void* solve_dag_kernel(bool fp32);
@@ -322,7 +326,8 @@ size_t cg_dense_lds_bytes(int n, int rows, int mode, bool fp32);
 int cg_dense_max_blocks(int n, int rows, int mode, bool fp32);
 hipError_t launch_cg_dense(const DevMesh& M, const DenseCG& D, hipStream_t s, int blocks, bool fp32,
                            const double* cache, const double* rhs, double rhs_scale, int pd_fallback,
-                           double* z_out, IterState* st, ProfAcc* prof);
+                           double* z_out, IterState* st, ProfAcc* prof,
+                           const double* nb2_ref = nullptr);
 void launch_unit_rhs(hipStream_t s, int N, int n, const int32_t* perm, int j0, double* b);
 void launch_collect_rows(hipStream_t s, int N, int n, const int32_t* perm, int j0, const double* x,
                          double* ainv);

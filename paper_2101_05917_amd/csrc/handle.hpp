@@ -87,6 +87,7 @@ struct dpd_mesh {
   double* z_hist[3] = {nullptr, nullptr, nullptr};
   double* z_start = nullptr;
   int z_hist_n = 0;           // solutions held (0..3)
+  dpd::IterState* warm_st = nullptr;   // [2] |b|^2 and |r_0|^2 of a warm-started fused solve
   dpd::IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   dpd::IterState* h_st = nullptr;   // pinned host mirror [2]
   // kernel timing (dpd_profile_start / dpd_profile_read)

@@ -864,6 +864,14 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(int64_t n, double* out, doub
   if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
+__global__ void __launch_bounds__(kBlock) k_warm_select(int64_t n, double* __restrict__ z0, double* __restrict__ r,
+                                                        const double* __restrict__ b, const IterState* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || w[1].nb2 < w[0].nb2) return;
+  z0[i] = 0.0;
+  r[i] = b[i];
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill(int64_t n, double* __restrict__ out, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = v;
@@ -891,6 +899,10 @@ void launch_hold(hipStream_t s, int periods) {
 
 void launch_fill(hipStream_t s, int64_t n, double* out, double v) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, out, v);
+}
+
+void launch_warm_select(hipStream_t s, int64_t n, double* z0, double* r, const double* b, const IterState* w) {
+  hipLaunchKernelGGL(k_warm_select, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, z0, r, b, w);
 }
 
 void launch_reset(hipStream_t s, IterState* st, double tolsq, int max_iter) {

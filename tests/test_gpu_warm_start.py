@@ -16,11 +16,11 @@ from parity_helpers import rel
 pytestmark = pytest.mark.gpu
 
 
-def _rollout(sc, warm, T, tol=1e-10):
+def _rollout(sc, warm, T, fused, tol=1e-10):
     from paper_2101_05917_amd.mesh import Mesh
     args = bench.parse(["--config", "c5", "--bwd-warm-start", str(warm)])
     opts = bench.solver_options(args)
-    opts.update(bwd_rel_tol=tol, fwd_rel_tol=1e-11, fused_cg=0)   # the multi-launch path (the warm start's)
+    opts.update(bwd_rel_tol=tol, fwd_rel_tol=1e-11, fused_cg=fused)
     g = Mesh.from_scene(sc, **opts)
     X = g.rest_positions()
     N = g.n_nodes
@@ -32,12 +32,15 @@ def _rollout(sc, warm, T, tol=1e-10):
 
 
 @pytest.mark.parametrize("warm", [1, 2, 3])
-def test_warm_start_same_gradients_fewer_iterations(warm):
+@pytest.mark.parametrize("fused", [0, 1])
+def test_warm_start_same_gradients_fewer_iterations(fused, warm):
+    """fused = 1: the mesh (1,683 nodes) takes the fused dense solver, which
+    solves for the correction from the start; 0: the multi-launch solver."""
     sc = W.dropped_block(16, 10, 8, steps=16, drop=0.002)
     T = 16
-    xc, gxc, gvc, gEc, _, _, bic = _rollout(sc, 0, T)
-    xw, gxw, gvw, gEw, _, _, biw = _rollout(sc, warm, T)
-    print("warm", warm, "adjoint iterations", bic, "->", biw,
+    xc, gxc, gvc, gEc, _, _, bic = _rollout(sc, 0, T, fused)
+    xw, gxw, gvw, gEw, _, _, biw = _rollout(sc, warm, T, fused)
+    print("fused", fused, "warm", warm, "adjoint iterations", bic, "->", biw,
           "dx0", rel(gxw.cpu().numpy(), gxc.cpu().numpy()), "dE", rel(gEw.cpu().numpy(), gEc.cpu().numpy()),
           flush=True)
     assert torch.equal(xw, xc)   # the forward pass is untouched
