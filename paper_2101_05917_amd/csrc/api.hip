@@ -1557,10 +1557,14 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   const int chunk = std::max(kGraphIters, check_every / kGraphIters * kGraphIters);
   // Iterations are enqueued in chunks between host checks; every kernel of an
   // iteration enqueued past convergence exits at once, but still costs a
-  // launch.  The first chunk has check_every iterations; later ones are sized
-  // from the residual reduction over the previous chunk: the iterations still
-  // needed at that rate, rounded up to whole graphs (at most 4 chunks).
+  // launch.  The first chunk has check_every iterations, or, after a solve on
+  // the same state, one more than that solve took (rounded up to whole
+  // graphs, at most check_every); later ones are sized from the residual
+  // reduction over the previous chunk: the iterations still needed at that
+  // rate, rounded up to whole graphs (at most 4 chunks).
   int chunks = 0, next = chunk, k_prev = 0;
+  if (m->cg_last[st_idx] > 0)
+    next = std::min(chunk, (m->cg_last[st_idx] + 1 + kGraphIters - 1) / kGraphIters * kGraphIters);
   double rsq_prev = 0.0;
   for (int k = 0; k < max_it;) {
     const bool direct = !m->opt.use_graphs || (m->prof_class != DPD_PROF_OFF && chunks % kProfStride == 0);
@@ -1590,6 +1594,7 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
     rsq_prev = h.rsq;
     k_prev = h.iter;
   }
+  m->cg_last[st_idx] = m->h_st[st_idx].iter;
   return DPD_OK;
 }
 

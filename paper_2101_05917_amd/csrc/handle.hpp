@@ -53,6 +53,7 @@ struct dpd_mesh {
   uint8_t* cmask = nullptr;                       // [N] contact active at the linearisation point
   hipGraphExec_t cg_exec[2][2][2] = {};           // captured CG iterations [state][fp32][deflated]
   bool graphs_failed = false;                     // a capture failed: direct launches only
+  int32_t cg_last[2] = {0, 0};                    // iterations of the last multi-launch solve per state
   // fused dense conjugate gradients (meshes with few free nodes)
   dpd::DenseCG dcg{};
   int dense_blocks = 0;                           // workgroups of its launch; 0: not available
