@@ -1074,10 +1074,10 @@ dpd_status dpd_forward_step(dpd_mesh* m, void* stream, const double* x, const do
         const int inner_max = std::max(1, std::min(o.fwd_inner_max_iter, max_it - solves));
         launch_reset(s, inner, eta * eta, inner_max);
         launch_lincomb(s, n3, m->xbar, -1.0, m->r, 0.0, nullptr);
+        // the solve returns with the host mirror of its final state current
         if ((rc = conjugate_gradient(m, s, inner, m->xbar, fp32, inner_max, o.check_every)) !=
             DPD_OK)
           return rc;
-        if ((rc = read_state(m, s)) != DPD_OK) return rc;
         solves += std::max(1, m->h_st[1].iter);
         if (m->h_st[1].curvature) {
           // not a descent direction: take one plain PD step instead
@@ -1526,20 +1526,16 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
-  if (z0 && st == m->st && !m->defl_active && !m->batcher) {
-    // warm start: z = z0, r = rhs - H z0, kept only if |r| < |rhs| (the
-    // stopping test stays relative to |rhs|)
-    IterState* aux = m->st + 1;
+  if (z0 && st == m->st && !m->defl_active && !m->batcher && m->warm_st) {
+    // warm start: z = z0, r = rhs - H z0, kept only if |r| < |rhs| (decided
+    // on the device; the stopping test stays relative to |rhs|)
     launch_lincomb(s, n3, m->z, 1.0, z0, 0.0, nullptr);
     defl_hessian(m, s, m->z, m->q);
     launch_lincomb(s, n3, m->cg_r, 1.0, rhs, -1.0, m->q);
     launch_fill(s, n3, m->q, 0.0);
-    launch_dot(m->dm, s, m->cg_r, m->cg_r, aux, m->partials, 0);
-    if ((rc = read_state(m, s)) != DPD_OK) return rc;
-    if (!(m->h_st[1].nb2 < m->h_st[0].nb2)) {
-      launch_fill(s, n3, m->z, 0.0);
-      launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
-    }
+    launch_dot(m->dm, s, rhs, rhs, m->warm_st, m->partials, 0);
+    launch_dot(m->dm, s, m->cg_r, m->cg_r, m->warm_st + 1, m->partials, 0);
+    launch_warm_select(s, n3, m->z, m->cg_r, rhs, m->warm_st);
   }
   if (st == m->st && m->defl_active && !m->batcher) {
     // start from the solution's component in W: z0 = W E^{-1} W^T rhs, r0 = rhs - HW E^{-1} W^T rhs
@@ -1552,7 +1548,7 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
     HIPCHECK(m, hipStreamSynchronize(s));
     if ((rc = m->batcher->solve(m, st, fp32, max_it)) != DPD_OK)
       return fail(m, rc, "batched conjugate-gradient iterations failed");
-    return DPD_OK;
+    return read_state(m, s);   // callers read the final state from the host mirror
   }
   const int chunk = std::max(kGraphIters, check_every / kGraphIters * kGraphIters);
   // Iterations are enqueued in chunks between host checks; every kernel of an
@@ -1594,6 +1590,7 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
     rsq_prev = h.rsq;
     k_prev = h.iter;
   }
+  if (chunks == 0 && (rc = read_state(m, s)) != DPD_OK) return rc;   // no iteration allowed
   m->cg_last[st_idx] = m->h_st[st_idx].iter;
   return DPD_OK;
 }
@@ -1666,10 +1663,9 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   } else if (o.bwd_solver == DPD_BWD_PCG) {
     m->defl_active = false;
     if (o.deflation > 0 && !m->batcher && (rc = defl_prepare(m, s, fp32)) != DPD_OK) return rc;
-    rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every, z0);
+    rc = conjugate_gradient(m, s, m->st, m->xbar, fp32, max_it, o.check_every, z0);   // leaves h_st current
     m->defl_active = false;
     if (rc != DPD_OK) return rc;
-    if ((rc = read_state(m, s)) != DPD_OK) return rc;
     if (m->h_st->curvature) {
       // the paper's safeguard when the quasi-Newton step is not a descent:
       // continue with the plain fixed-point iteration from the current z
