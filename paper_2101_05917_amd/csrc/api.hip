@@ -31,7 +31,7 @@ constexpr double kSweepBandwidth = 1.5e12;    // measured effective bytes/s of t
 constexpr int32_t kSepMax = 2048;
 constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
 constexpr int kHoldPeriodsAround = 40;  // about 130 us of s_sleep ahead of a timed multi-launch solve
-constexpr int kGraphIters = 4;   // conjugate-gradient iterations per captured graph
+constexpr int kGraphIters = 2;   // conjugate-gradient iterations per captured graph
 constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before the first check
 constexpr int kNewtonMore = 2;   // ... and per later check
 
