@@ -16,7 +16,7 @@ from parity_helpers import rel
 pytestmark = pytest.mark.gpu
 
 
-def _rollout(sc, warm, T, fused, tol=1e-10):
+def _rollout(sc, warm, T, fused, tol=1e-10, checkpoint_every=1):
     from paper_2101_05917_amd.mesh import Mesh
     args = bench.parse(["--config", "c5", "--bwd-warm-start", str(warm)])
     opts = bench.solver_options(args)
@@ -26,7 +26,7 @@ def _rollout(sc, warm, T, fused, tol=1e-10):
     N = g.n_nodes
     c = W.loss_vector(N, 0)
     c_dev = torch.from_numpy(np.ascontiguousarray(c.reshape(N, 3).T)).to(X.device)
-    out = bench.rollout(g, X, c_dev, T, torch)
+    out = bench.rollout(g, X, c_dev, T, torch, None, checkpoint_every)
     g.close()
     return out
 
@@ -44,6 +44,20 @@ def test_warm_start_same_gradients_fewer_iterations(fused, warm):
           "dx0", rel(gxw.cpu().numpy(), gxc.cpu().numpy()), "dE", rel(gEw.cpu().numpy(), gEc.cpu().numpy()),
           flush=True)
     assert torch.equal(xw, xc)   # the forward pass is untouched
+    assert rel(gxw.cpu().numpy(), gxc.cpu().numpy()) <= 1e-8
+    assert rel(gvw.cpu().numpy(), gvc.cpu().numpy()) <= 1e-8
+    assert rel(gEw.cpu().numpy(), gEc.cpu().numpy()) <= 1e-8
+    assert biw < bic
+
+
+def test_warm_start_with_checkpoint_segments():
+    """Checkpointed rollouts recompute each segment's forward states between
+    backward steps; the adjoint history is untouched by them."""
+    sc = W.dropped_block(16, 10, 8, steps=16, drop=0.002)
+    T = 16
+    _, gxc, gvc, gEc, _, _, bic = _rollout(sc, 0, T, 0, checkpoint_every=4)
+    _, gxw, gvw, gEw, _, _, biw = _rollout(sc, 2, T, 0, checkpoint_every=4)
+    print("checkpoint 4: adjoint iterations", bic, "->", biw, flush=True)
     assert rel(gxw.cpu().numpy(), gxc.cpu().numpy()) <= 1e-8
     assert rel(gvw.cpu().numpy(), gvc.cpu().numpy()) <= 1e-8
     assert rel(gEw.cpu().numpy(), gEc.cpu().numpy()) <= 1e-8
