@@ -90,9 +90,9 @@ def parse(argv=None):
     ap.add_argument("--leaf-nodes", type=int, default=0,
                     help="nested-dissection leaf size of the factor (0: chosen by the solve-time estimate)")
     ap.add_argument("--bwd-warm-start", type=int, default=None,
-                    help="adjoint CG start: 2 = linear extrapolation of the two previous backward steps' "
-                         "solutions, 1 = the previous solution, 0 = zero (default: 2 on c5, where it cuts "
-                         "the adjoint iterations 6x; 0 elsewhere, where it was measured not to help)")
+                    help="adjoint CG start: 4 = Galerkin combination of the previous backward steps' "
+                         "solutions, 2 = their linear extrapolation, 1 = the previous solution, 0 = zero "
+                         "(default: per workload, WARM_START)")
     ap.add_argument("--factorize-only", type=int, default=0,
                     help="time this many numeric factorizations of the workload's A and report them "
                          "(no rollouts)")
@@ -159,9 +159,11 @@ def parse(argv=None):
     return args
 
 
-# adjoint warm start per workload (measured: on the settling block 77.3 -> 12.8 adjoint iterations per
-# step; on the cantilever, the legged body and the bouncing ball no change)
-WARM_START = {"c5": 2}
+# adjoint warm start per workload: the Galerkin combination of the last five adjoint solutions
+# (measured adjoint iterations per step, cold -> start: block 77.3 -> 10.9, cantilever 53.9 -> 13.0,
+# tetrahedral ball 40.0 -> 33.8; the legged body 106.2 -> 104.1 did not pay for the extra Hessian
+# products, so it starts from zero)
+WARM_START = {"c1": 4, "c2": 4, "c5": 4, "tet": 4}
 
 
 def solver_options(args) -> dict:

@@ -149,12 +149,15 @@ typedef struct {
                               of the step after this one), 2 = from the linear
                               extrapolation 2 z_{t+1} - z_{t+2} of the previous
                               two, 3 = from the quadratic one 3 z_{t+1} -
-                              3 z_{t+2} + z_{t+3}; a start is kept only if its
+                              3 z_{t+2} + z_{t+3}, 4 = the Galerkin (H-norm best)
+                              combination of the last five, Z c with
+                              (Z^T H Z) c = Z^T xbar; a start is kept only if its
                               residual is smaller than the right-hand side,
                               else zero.  0 (default) = from zero.  Same
                               stopping test (relative to the right-hand side);
-                              the handle keeps the last three solutions across
-                              calls                                            */
+                              the handle keeps the last solutions across calls
+                              (one extra Hessian product per kept solution and
+                              a host round trip with mode 4)                   */
   int32_t pad_opt;
 } dpd_options;
 

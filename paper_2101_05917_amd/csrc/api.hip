@@ -32,6 +32,8 @@ constexpr int32_t kSepMax = 2048;
 constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
 constexpr int kHoldPeriodsAround = 40;  // about 130 us of s_sleep ahead of a timed multi-launch solve
 constexpr int kGraphIters = 2;   // conjugate-gradient iterations per captured graph
+constexpr int kGalMax = 5;       // stored adjoint solutions of the Galerkin start
+static_assert(kGalMax <= 64, "multi-dot and multi-axpy take at most 64 vectors");
 constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before the first check
 constexpr int kNewtonMore = 2;   // ... and per later check
 
@@ -834,6 +836,7 @@ void destroy_synced(dpd_mesh* m) {
       for (auto& ex : row)
         if (ex) (void)hipGraphExecDestroy(ex);
   if (m->h_defl) (void)hipHostFree(m->h_defl);
+  if (m->h_gal) (void)hipHostFree(m->h_gal);
   if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
   for (void* p : m->allocs) (void)hipFree(p);
   for (auto& e : m->ev_free) {
@@ -1515,6 +1518,54 @@ dpd_status deflated_start(dpd_mesh* m, hipStream_t s, const double* rhs) {
   return DPD_OK;
 }
 
+// Galerkin start of the adjoint solve: z_start = Z c with (Z^T H Z) c = Z^T xbar
+// over the stored solutions Z (the H-norm best approximation of the solution
+// in their span; eigenvalues of Z^T H Z below 1e-12 of the largest dropped).
+// Needs the adjoint cache at the current point.  Leaves z_start unset when
+// no solution is stored.
+dpd_status galerkin_start(dpd_mesh* m, hipStream_t s) {
+  const int64_t n3 = 3 * (int64_t)m->dm.N;
+  dpd_status rc;
+  if (!m->gal_Z) {
+    if ((rc = dev_alloc(m, &m->gal_Z, kGalMax * n3)) != DPD_OK) return rc;
+    if ((rc = dev_alloc(m, &m->gal_HZ, kGalMax * n3)) != DPD_OK) return rc;
+    // multi-dot partials: at most 256 chunks per vector; the small system: kGalMax
+    // columns of G and Z^T xbar
+    if ((rc = dev_alloc(m, &m->gal_part, 256 * kGalMax)) != DPD_OK) return rc;
+    if ((rc = dev_alloc(m, &m->gal_dots, (kGalMax + 1) * kGalMax)) != DPD_OK) return rc;
+    if ((rc = dev_alloc(m, &m->gal_coef, kGalMax)) != DPD_OK) return rc;
+    HIPCHECK(m, hipHostMalloc((void**)&m->h_gal, (kGalMax + 1) * kGalMax * sizeof(double), hipHostMallocDefault));
+  }
+  const int k = m->gal_n;
+  if (k == 0) return DPD_OK;
+  for (int j = 0; j < k; ++j) defl_hessian(m, s, m->gal_Z + j * n3, m->gal_HZ + j * n3);
+  for (int j = 0; j < k; ++j)
+    launch_multi_dot(s, m->gal_Z, k, m->gal_HZ + j * n3, n3, m->gal_part, m->gal_dots + j * kGalMax);
+  launch_multi_dot(s, m->gal_Z, k, m->xbar, n3, m->gal_part, m->gal_dots + kGalMax * kGalMax);
+  HIPCHECK(m, hipMemcpyAsync(m->h_gal, m->gal_dots, (kGalMax + 1) * kGalMax * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  std::vector<double> G((size_t)k * k), w, V, c(k, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j)
+      G[(size_t)i * k + j] = 0.5 * (m->h_gal[j * kGalMax + i] + m->h_gal[i * kGalMax + j]);
+  const double* b = m->h_gal + kGalMax * kGalMax;
+  sym_eig_jacobi(k, G, w, V);
+  double wmax = 0.0;
+  for (double x : w) wmax = std::max(wmax, x);
+  for (int e = 0; e < k; ++e) {
+    if (!(w[e] > 1e-12 * wmax)) continue;
+    double vb = 0.0;
+    for (int i = 0; i < k; ++i) vb += V[(size_t)i * k + e] * b[i];
+    for (int i = 0; i < k; ++i) c[i] += V[(size_t)i * k + e] * vb / w[e];
+  }
+  std::memcpy(m->h_gal, c.data(), k * sizeof(double));
+  HIPCHECK(m, hipMemcpyAsync(m->gal_coef, m->h_gal, k * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_fill(s, n3, m->z_start, 0.0);
+  launch_multi_axpy(s, m->z_start, m->gal_Z, k, m->gal_coef, n3, 1.0);
+  return DPD_OK;
+}
+
 dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const double* rhs, bool fp32,
                               int max_it, int check_every, const double* z0) {
   if (m->dense_blocks > 0 && m->opt.fused_cg) return cg_dense(m, s, st, rhs, fp32);
@@ -1635,7 +1686,13 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
     if ((rc = dev_alloc(m, &m->warm_st, 2)) != DPD_OK) return rc;
     HIPCHECK(m, hipMemset(m->warm_st, 0, 2 * sizeof(IterState)));   // reduction tickets start at zero
   }
-  const int order = warm ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
+  const bool galerkin = warm && o.bwd_warm_start == 4;
+  const int order = warm && !galerkin ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
+  bool have_start = order >= 0;
+  if (galerkin) {
+    if ((rc = galerkin_start(m, s)) != DPD_OK) return rc;
+    have_start = m->gal_n > 0;
+  }
   if (order == 0) {
     launch_lincomb(s, n3, m->z_start, 1.0, m->z_hist[0], 0.0, nullptr);
   } else if (order == 1) {
@@ -1644,7 +1701,7 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
     launch_lincomb(s, n3, m->z_start, 3.0, m->z_hist[0], -3.0, m->z_hist[1]);
     launch_lincomb(s, n3, m->z_start, 1.0, m->z_start, 1.0, m->z_hist[2]);
   }
-  const double* z0 = order >= 0 ? m->z_start : nullptr;
+  const double* z0 = have_start ? m->z_start : nullptr;
   if (gated) {
     if (z0) {
       // the fused solver solves H d = xbar - H z0 (start and safeguard decided
@@ -1698,11 +1755,15 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
       if ((rc = read_state(m, s)) != DPD_OK) return rc;
     }
   }
-  if (warm) {
+  if (warm && !galerkin) {
     std::swap(m->z_hist[2], m->z_hist[1]);
     std::swap(m->z_hist[1], m->z_hist[0]);   // the oldest buffer takes the new solution
     launch_lincomb(s, n3, m->z_hist[0], 1.0, m->z, 0.0, nullptr);
     m->z_hist_n = std::min(3, m->z_hist_n + 1);
+  } else if (galerkin) {
+    launch_lincomb(s, n3, m->gal_Z + (int64_t)m->gal_next * n3, 1.0, m->z, 0.0, nullptr);
+    m->gal_next = (m->gal_next + 1) % kGalMax;
+    m->gal_n = std::min(kGalMax, m->gal_n + 1);
   }
   const IterState& h = *m->h_st;
   if (stats) {

@@ -89,6 +89,15 @@ struct dpd_mesh {
   double* z_start = nullptr;
   int z_hist_n = 0;           // solutions held (0..3)
   dpd::IterState* warm_st = nullptr;   // [2] |b|^2 and |r_0|^2 of a warm-started fused solve
+  // Galerkin start (bwd_warm_start = 4): the last kGalMax solutions in slots of one
+  // block, their Hessian products, reduction scratch and the small system
+  double* gal_Z = nullptr;             // [kGalMax][3N]
+  double* gal_HZ = nullptr;            // [kGalMax][3N]
+  double* gal_part = nullptr;          // multi-dot partial sums
+  double* gal_dots = nullptr;          // [kGalMax + 1][kGalMax] G columns, then Z^T xbar
+  double* gal_coef = nullptr;          // [kGalMax]
+  double* h_gal = nullptr;             // pinned host mirror
+  int gal_n = 0, gal_next = 0;
   dpd::IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   dpd::IterState* h_st = nullptr;   // pinned host mirror [2]
   // kernel timing (dpd_profile_start / dpd_profile_read)

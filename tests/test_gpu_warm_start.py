@@ -1,6 +1,7 @@
 """Warm-started adjoint conjugate gradients (dpd_options.bwd_warm_start): the
-backward steps of a rollout start from the previous step's adjoint solution
-or from the linear or quadratic extrapolation of the previous two or three.  The adjoint system and
+backward steps of a rollout start from the previous step's adjoint solution,
+from the linear or quadratic extrapolation of the previous two or three, or
+from the Galerkin (H-norm best) combination of the previous five.  The adjoint system and
 its stopping test (relative to the right-hand side) are unchanged, so the
 rollout gradients equal the cold-started ones to the solver tolerance, with
 fewer iterations; the rollouts' gradients against the oracle at the
@@ -31,7 +32,7 @@ def _rollout(sc, warm, T, fused, tol=1e-10, checkpoint_every=1):
     return out
 
 
-@pytest.mark.parametrize("warm", [1, 2, 3])
+@pytest.mark.parametrize("warm", [1, 2, 3, 4])
 @pytest.mark.parametrize("fused", [0, 1])
 def test_warm_start_same_gradients_fewer_iterations(fused, warm):
     """fused = 1: the mesh (1,683 nodes) takes the fused dense solver, which
@@ -56,7 +57,7 @@ def test_warm_start_with_checkpoint_segments():
     sc = W.dropped_block(16, 10, 8, steps=16, drop=0.002)
     T = 16
     _, gxc, gvc, gEc, _, _, bic = _rollout(sc, 0, T, 0, checkpoint_every=4)
-    _, gxw, gvw, gEw, _, _, biw = _rollout(sc, 2, T, 0, checkpoint_every=4)
+    _, gxw, gvw, gEw, _, _, biw = _rollout(sc, 4, T, 0, checkpoint_every=4)
     print("checkpoint 4: adjoint iterations", bic, "->", biw, flush=True)
     assert rel(gxw.cpu().numpy(), gxc.cpu().numpy()) <= 1e-8
     assert rel(gvw.cpu().numpy(), gvc.cpu().numpy()) <= 1e-8
