@@ -159,11 +159,11 @@ def parse(argv=None):
     return args
 
 
-# adjoint warm start per workload: the Galerkin combination of the last five adjoint solutions
-# (measured adjoint iterations per step, cold -> start: block 77.3 -> 10.9, cantilever 53.9 -> 13.0,
-# tetrahedral ball 40.0 -> 33.8; the legged body 106.2 -> 104.1 did not pay for the extra Hessian
-# products, so it starts from zero)
-WARM_START = {"c1": 4, "c2": 4, "c5": 4, "tet": 4}
+# adjoint warm start per workload: the Galerkin combination of the last adjoint solutions, five
+# (mode 4) or ten on the block (measured adjoint iterations per step, cold -> start: block 77.3 ->
+# 10.9 with five, 10.0 with ten; cantilever 53.9 -> 13.0, tetrahedral ball 40.0 -> 33.8; the legged
+# body 106.2 -> 104.1 did not pay for the extra Hessian products, so it starts from zero)
+WARM_START = {"c1": 4, "c2": 4, "c5": 10, "tet": 4}
 
 
 def solver_options(args) -> dict:

@@ -151,7 +151,8 @@ typedef struct {
                               two, 3 = from the quadratic one 3 z_{t+1} -
                               3 z_{t+2} + z_{t+3}, 4 = the Galerkin (H-norm best)
                               combination of the last five, Z c with
-                              (Z^T H Z) c = Z^T xbar; a start is kept only if its
+                              (Z^T H Z) c = Z^T xbar, 5..12 = the same over the
+                              last that many; a start is kept only if its
                               residual is smaller than the right-hand side,
                               else zero.  0 (default) = from zero.  Same
                               stopping test (relative to the right-hand side);

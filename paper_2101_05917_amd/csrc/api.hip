@@ -32,7 +32,8 @@ constexpr int32_t kSepMax = 2048;
 constexpr int64_t kProfStride = 17;   // prime: no lock-step with the launch pattern of a solve
 constexpr int kHoldPeriodsAround = 40;  // about 130 us of s_sleep ahead of a timed multi-launch solve
 constexpr int kGraphIters = 2;   // conjugate-gradient iterations per captured graph
-constexpr int kGalMax = 5;       // stored adjoint solutions of the Galerkin start
+constexpr int kGalMax = 12;      // most stored adjoint solutions of the Galerkin start (buffer capacity)
+constexpr int kGalDefault = 5;   // solutions kept with bwd_warm_start = 4
 static_assert(kGalMax <= 64, "multi-dot and multi-axpy take at most 64 vectors");
 constexpr int kNewtonAhead = 4;  // fused Newton forward: steps enqueued before the first check
 constexpr int kNewtonMore = 2;   // ... and per later check
@@ -1686,10 +1687,15 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
     if ((rc = dev_alloc(m, &m->warm_st, 2)) != DPD_OK) return rc;
     HIPCHECK(m, hipMemset(m->warm_st, 0, 2 * sizeof(IterState)));   // reduction tickets start at zero
   }
-  const bool galerkin = warm && o.bwd_warm_start == 4;
+  const bool galerkin = warm && o.bwd_warm_start >= 4;
   const int order = warm && !galerkin ? std::min(std::min(o.bwd_warm_start, 3) - 1, m->z_hist_n - 1) : -1;
   bool have_start = order >= 0;
   if (galerkin) {
+    const int cap = o.bwd_warm_start == 4 ? kGalDefault : std::min(o.bwd_warm_start, kGalMax);
+    if (m->gal_cap != cap) {   // another number of kept solutions: start the history over
+      m->gal_cap = cap;
+      m->gal_n = m->gal_next = 0;
+    }
     if ((rc = galerkin_start(m, s)) != DPD_OK) return rc;
     have_start = m->gal_n > 0;
   }
@@ -1762,8 +1768,8 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
     m->z_hist_n = std::min(3, m->z_hist_n + 1);
   } else if (galerkin) {
     launch_lincomb(s, n3, m->gal_Z + (int64_t)m->gal_next * n3, 1.0, m->z, 0.0, nullptr);
-    m->gal_next = (m->gal_next + 1) % kGalMax;
-    m->gal_n = std::min(kGalMax, m->gal_n + 1);
+    m->gal_next = (m->gal_next + 1) % m->gal_cap;
+    m->gal_n = std::min(m->gal_cap, m->gal_n + 1);
   }
   const IterState& h = *m->h_st;
   if (stats) {

@@ -97,7 +97,7 @@ struct dpd_mesh {
   double* gal_dots = nullptr;          // [kGalMax + 1][kGalMax] G columns, then Z^T xbar
   double* gal_coef = nullptr;          // [kGalMax]
   double* h_gal = nullptr;             // pinned host mirror
-  int gal_n = 0, gal_next = 0;
+  int gal_n = 0, gal_next = 0, gal_cap = 0;   // held, next slot, slots in use
   dpd::IterState* st = nullptr;     // [2]: outer iteration, inner conjugate gradients
   dpd::IterState* h_st = nullptr;   // pinned host mirror [2]
   // kernel timing (dpd_profile_start / dpd_profile_read)

@@ -32,7 +32,7 @@ def _rollout(sc, warm, T, fused, tol=1e-10, checkpoint_every=1):
     return out
 
 
-@pytest.mark.parametrize("warm", [1, 2, 3, 4])
+@pytest.mark.parametrize("warm", [1, 2, 3, 4, 8])
 @pytest.mark.parametrize("fused", [0, 1])
 def test_warm_start_same_gradients_fewer_iterations(fused, warm):
     """fused = 1: the mesh (1,683 nodes) takes the fused dense solver, which
