@@ -160,10 +160,11 @@ def parse(argv=None):
 
 
 # adjoint warm start per workload: the Galerkin combination of the last adjoint solutions, five
-# (mode 4) or ten on the block (measured adjoint iterations per step, cold -> start: block 77.3 ->
-# 10.9 with five, 10.0 with ten; cantilever 53.9 -> 13.0, tetrahedral ball 40.0 -> 33.8; the legged
-# body 106.2 -> 104.1 did not pay for the extra Hessian products, so it starts from zero)
-WARM_START = {"c1": 4, "c2": 4, "c5": 10, "tet": 4}
+# (mode 4) or ten (measured adjoint iterations per step, cold -> start: block 77.3 -> 10.9 with five,
+# 10.0 with ten; tetrahedral ball 40.0 -> 33.8 with five, 30.0 with ten; cantilever 53.9 -> 13.0
+# with five, where eight cost more than they saved; the legged body 106.2 -> 104.1 did not pay for
+# the extra Hessian products, so it starts from zero)
+WARM_START = {"c1": 4, "c2": 4, "c5": 10, "tet": 10}
 
 
 def solver_options(args) -> dict:
