@@ -490,7 +490,9 @@ def serve_bench(args):
     srv = Server(int(args.hbm_budget_gb * (1 << 30)), max_slots=args.slots, batched=bool(args.batched))
     solve = dict(fwd_solver=args.fwd_solver, fwd_rel_tol=args.fwd_tol, fwd_max_iter=200000,
                  bwd_solver=args.bwd_solver, bwd_rel_tol=args.bwd_tol, bwd_max_iter=200000,
-                 precision=args.precision, check_every=16)
+                 precision=args.precision, check_every=16,
+                 # the cantilevers' adjoint starts from the Galerkin combination of the last five
+                 bwd_warm_start=4 if args.bwd_warm_start is None else args.bwd_warm_start)
     t0 = time.perf_counter()
     tickets = []
     for r in reqs:

@@ -143,8 +143,8 @@ typedef struct {
                               over the supernodes is allocated and freed by the
                               call); 1: on the host (C++ with OpenMP), the
                               panels then uploaded.  Same factor to rounding   */
-  int32_t bwd_warm_start;  /* adjoint CG (multi-launch or fused; not in the
-                              batch engine, not deflated): 1 = start from the
+  int32_t bwd_warm_start;  /* adjoint CG (multi-launch, fused or in the batch
+                              engine; not deflated): 1 = start from the
                               previous backward step's solution z (the adjoint
                               of the step after this one), 2 = from the linear
                               extrapolation 2 z_{t+1} - z_{t+2} of the previous

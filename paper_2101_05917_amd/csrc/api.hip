@@ -1578,7 +1578,7 @@ dpd_status conjugate_gradient(dpd_mesh* m, hipStream_t s, IterState* st, const d
   launch_fill(s, n3, m->q, 0.0);
   launch_lincomb(s, n3, m->cg_r, 1.0, rhs, 0.0, nullptr);
   launch_dot(m->dm, s, rhs, rhs, st, m->partials, 0);
-  if (z0 && st == m->st && !m->defl_active && !m->batcher && m->warm_st) {
+  if (z0 && st == m->st && !m->defl_active && m->warm_st) {
     // warm start: z = z0, r = rhs - H z0, kept only if |r| < |rhs| (decided
     // on the device; the stopping test stays relative to |rhs|)
     launch_lincomb(s, n3, m->z, 1.0, z0, 0.0, nullptr);
@@ -1679,7 +1679,7 @@ dpd_status dpd_backward_step(dpd_mesh* m, void* stream, const double* x, const d
   // warm start (dpd_options.bwd_warm_start): polynomial extrapolation in t of
   // the last adjoint solutions, order 0 (z_{t+1}), 1 (2 z_{t+1} - z_{t+2}) or
   // 2 (3 z_{t+1} - 3 z_{t+2} + z_{t+3}), as many as are held, built in z_start
-  const bool warm = o.bwd_solver == DPD_BWD_PCG && o.bwd_warm_start > 0 && !m->batcher && o.deflation <= 0;
+  const bool warm = o.bwd_solver == DPD_BWD_PCG && o.bwd_warm_start > 0 && o.deflation <= 0;
   if (warm && !m->z_start) {
     for (double*& b : m->z_hist)
       if ((rc = dev_alloc(m, &b, n3)) != DPD_OK) return rc;

@@ -135,6 +135,24 @@ def test_batch_engine_shares_launches():
         assert np.array_equal(a.g_youngs, gE)
 
 
+def test_batch_engine_with_galerkin_start():
+    """Requests whose adjoint starts from the Galerkin combination of their own
+    last solutions (bwd_warm_start = 4): each request's history lives in its
+    handle, so the batch engine's results are still bitwise the request's own
+    rollout through the mesh API with the same options."""
+    from paper_2101_05917_amd.serve import Server
+    reqs = _requests()[:3]
+    s = Server(8 << 30, max_slots=3, batched=True)
+    mix = _run(s, reqs, bwd_warm_start=4)
+    s.close()
+    for (sc, c), a in zip(reqs, mix):
+        assert a.state == "done" and a.status == 0, a
+        gx, gv, gE = _direct(sc, c, fused_cg=0, use_graphs=0, bwd_warm_start=4)
+        assert np.array_equal(a.g_x0, gx)
+        assert np.array_equal(a.g_v0, gv)
+        assert np.array_equal(a.g_youngs, gE)
+
+
 def test_admission_respects_budget_and_rejects_oversized():
     from paper_2101_05917_amd.serve import Server
     reqs = _requests()
